@@ -1,0 +1,222 @@
+/*
+ * sps.h - C ABI of the MI355X (gfx950) batched stellar-population forward model.
+ *
+ * The library evaluates, for a batch of B parameter vectors theta[B, P] (the
+ * live points of a nested sampler), the forward model of the paper "Ceridwen:
+ * Fast and Flexible GPU-Accelerated Stellar Population Inference":
+ *   SFH x enrichment weights W_ma (Sec. 2.2, App. B), contraction with the SSP
+ *   grid (eq. 1), nebular lines (Sec. 2.3, App. C), two-component dust
+ *   (Sec. 2.4, eq. D2), observer-frame conversion (Sec. 2.6), projection onto
+ *   photometry (App. E) or a spectrum (App. F), and the diagonal Gaussian
+ *   log-likelihood with the noise floor (eq. 6, eq. G1),
+ * plus its exact gradient and a continuous-batching request server.
+ *
+ * Conventions
+ *   - Every call returns sps_status: SPS_OK (0), SPS_PENDING (1) or a negative
+ *     error.  sps_last_error() returns a thread-local message for the last error
+ *     of the calling thread.  No call throws across the ABI.
+ *   - Host arrays passed to *_load / *_create / sps_submit are copied; the
+ *     caller keeps ownership and may free them after the call returns.
+ *   - theta, model, logl and grad pointers of the hot calls are device pointers
+ *     on the library's device, owned by the caller, contiguous, row-major.
+ *   - Hot calls (sps_forward, sps_logl, sps_logl_grad) validate arguments
+ *     synchronously, enqueue their kernels on the caller's HIP stream and return
+ *     without synchronising; they never allocate.  A device fault surfaces as
+ *     SPS_E_HIP on a later call.  Calls that share one sps_obs use its
+ *     workspace: serialise them on one stream.
+ */
+#ifndef SPS_H
+#define SPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sps_status;
+enum {
+  SPS_OK = 0,
+  SPS_PENDING = 1,
+  SPS_E_INVAL = -1,     /* bad argument (NULL, non-finite, out of range, bare R) */
+  SPS_E_SHAPE = -2,     /* size mismatch, B > max_batch, unsupported size */
+  SPS_E_NOMEM = -3,     /* device or host allocation failed (load/create only) */
+  SPS_E_BUDGET = -4,    /* request can never fit the server's HBM budget */
+  SPS_E_HIP = -5,       /* HIP runtime error (message names the call) */
+  SPS_E_STATE = -6,     /* object in the wrong state (destroyed, shut down) */
+  SPS_E_TIMEOUT = -7,   /* sps_wait timed out */
+  SPS_E_CANCELLED = -8, /* request was cancelled */
+  SPS_E_NOTFOUND = -9   /* unknown ticket */
+};
+
+/* Arithmetic of the library contraction (eq. 1).  The luminosity distance and
+ * the chi-squared accumulation are always FP64.
+ *   SPS_FP64   : everything in FP64 (parity instance).
+ *   SPS_FP32   : FP32 MFMA contraction, FP32 epilogue and projection.
+ *   SPS_BF16/SPS_FP16 : library stored as 2^e (H + R) per row with 16-bit hi H
+ *     and 16-bit residual R, weights as 2^e (W_h + W_l) per point; MFMA passes
+ *     W_h.H + W_h.R + W_l.H accumulated in FP32 (one refinement pass over the
+ *     residual terms).
+ *   *_1PASS    : W_h.H only.   *_HR : W_h.H + W_h.R only. */
+typedef enum {
+  SPS_FP64 = 0,
+  SPS_FP32 = 1,
+  SPS_BF16 = 2,
+  SPS_FP16 = 3,
+  SPS_BF16_1PASS = 4,
+  SPS_FP16_1PASS = 5,
+  SPS_BF16_HR = 6,
+  SPS_FP16_HR = 7
+} sps_precision;
+
+typedef struct sps_library sps_library;
+typedef struct sps_obs sps_obs;
+typedef struct sps_server sps_server;
+
+/* ------------------------------------------------------------------------- */
+/* Library: SSP grid + model configuration (Sec. 2.1-2.6)                     */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_age, n_z, n_afe, n_wave;
+  const double *ages;   /* [n_age] yr, strictly increasing, > 0 */
+  const double *logz;   /* [n_z] log10(Z/Zsun), strictly increasing */
+  const double *afe;    /* [n_afe] [alpha/Fe] nodes; may be NULL when n_afe == 1 */
+  const double *wave;   /* [n_wave] rest wavelength, Angstrom, strictly increasing */
+  const double *flux;   /* [n_afe][n_z][n_age][n_wave] Lsun/A per Msun formed, >= 0 */
+  double t_young;       /* birth-cloud edge in yr: ages < t_young see tau_BC (Sec. 2.4) */
+  /* star-formation history (Sec. 2.2, App. B): n_sfh lookback bins with edges
+   * 0, then log-uniform from T1 to t_univ(z); n_zh enrichment nodes (0 =
+   * constant-metallicity mode using theta[logzsol]). */
+  int32_t n_sfh;
+  double T1;
+  int32_t n_zh;
+  double H0, Om;        /* flat LambdaCDM (Sec. 2.6): km/s/Mpc, Omega_m */
+  const double *dust_a; /* [n_wave] diffuse-law shape a(lambda); NULL = zeros */
+  const double *dust_d; /* [n_wave] bump shape d(lambda); NULL = zeros */
+  /* nebular lines (App. C); n_line = 0 disables nebular emission.  The line
+   * table's age axis must be exactly the SSP ages younger than t_young. */
+  int32_t n_line, n_zg, n_u;
+  const double *line_wave;  /* [n_line] rest Angstrom */
+  const double *line_table; /* [n_line][n_young][n_zg][n_u] log10(L_line/Q), erg */
+  const double *zg_nodes;   /* [n_zg] gas log10(Z/Zsun) */
+  const double *u_nodes;    /* [n_u] log10 U */
+  uint32_t precisions;  /* bitmask of (1u << sps_precision) copies to build;
+                           FP32 is always built */
+  int32_t device;       /* HIP device ordinal */
+} sps_library_desc;
+
+typedef struct {
+  int32_t K, K_pad, K_young_pad, N, N_pad, n_young, n_line;
+  int64_t device_bytes; /* device memory held by the library */
+} sps_library_info;
+
+/* Copies the grid to the device, packs it in young-first K order (young SSP
+ * rows, then the line-profile rows, then old rows, each padded), removes the
+ * ionising continuum of nebular-covered ages (f_ob = 0, Fig. A1), computes Q_ma
+ * (eq. C1) and builds the requested precision copies (per-row 2^e scaling and
+ * 16-bit hi/residual split), plus an N-major FP32 copy for the adjoint.
+ * Errors: SPS_E_INVAL (bad values), SPS_E_NOMEM, SPS_E_HIP. */
+sps_status sps_library_load(const sps_library_desc *desc, sps_library **out);
+sps_status sps_library_info_get(const sps_library *lib, sps_library_info *out);
+void sps_library_destroy(sps_library *lib);
+
+/* Column layout of theta[B, P] (FP64, row-major), shared by every observation:
+ * 14 scalar columns (in this order: logmass, zred, tau_bc, alpha_bc, tau_diff,
+ * delta, logzsol, gas_logz, gas_logu, afe, log_err_scale, log_f_calib,
+ * log_f_data, log_jitter), then sfh[n_sfh] bin masses (Msun formed per unit of
+ * 10^logmass), then zh[n_zh] enrichment nodes.  Unused columns are ignored. */
+typedef struct {
+  int32_t P, n_scalar, sfh, n_sfh, zh, n_zh;
+  int32_t logmass, zred, tau_bc, alpha_bc, tau_diff, delta, logzsol, gas_logz, gas_logu, afe;
+  int32_t log_err_scale, log_f_calib, log_f_data, log_jitter;
+} sps_layout;
+sps_status sps_theta_layout(const sps_library *lib, sps_layout *out);
+
+/* ------------------------------------------------------------------------- */
+/* Observations (Sec. 3): photometry (App. E) or a spectrum (App. F)          */
+/* ------------------------------------------------------------------------- */
+enum { SPS_OBS_PHOT = 0, SPS_OBS_SPEC = 1 };
+/* LSF unit conventions of eq. F2.  SPS_LSF_BARE_R is rejected (SPS_E_INVAL):
+ * a resolving power must state whether it is lambda/FWHM or lambda/sigma. */
+enum {
+  SPS_LSF_R_FWHM = 0, SPS_LSF_R_SIGMA = 1, SPS_LSF_FWHM_AA = 2, SPS_LSF_SIGMA_AA = 3,
+  SPS_LSF_SIGMA_KMS = 4, SPS_LSF_FWHM_KMS = 5, SPS_LSF_BARE_R = 6
+};
+/* noise-floor switches of eq. G1 (parameters read from theta in ln space) */
+enum { SPS_NOISE_ERR_SCALE = 1, SPS_NOISE_F_CALIB = 2, SPS_NOISE_F_DATA = 4, SPS_NOISE_JITTER = 8 };
+/* warning flags returned by sps_obs_create */
+enum { SPS_WARN_LSF_FINER_THAN_LIBRARY = 1 };
+
+typedef struct {
+  int32_t kind;               /* SPS_OBS_PHOT or SPS_OBS_SPEC */
+  /* photometry: n_band filter curves concatenated; filter_len[b] nodes each,
+   * observer-frame Angstrom, strictly increasing within a curve */
+  int32_t n_band;
+  const int32_t *filter_len;
+  const double *filter_wave;
+  const double *filter_trans;
+  /* spectrum: detector pixel centres (observer Angstrom, increasing) */
+  int32_t n_pix;
+  const double *pix_wave;
+  int32_t lsf_mode;           /* SPS_LSF_* */
+  double lsf_value;           /* constant R / width, used when lsf_curve == NULL */
+  const double *lsf_curve;    /* [n_pix] or NULL */
+  double z_ref;               /* reference redshift of the fixed kernel (eq. F4) */
+  double sigma_gal_kms;       /* fixed stellar dispersion folded into the kernel */
+  double sigma_gas_kms;       /* gas dispersion of the line profiles (eq. F6) */
+  /* data [n_data] with n_data = n_band or n_pix: maggies (F_nu / 3631 Jy) */
+  const double *data;
+  const double *sigma;
+  const uint8_t *mask;        /* NULL = all included; ANDed with finite(data),
+                                 finite(sigma), sigma > 0 (App. H.1) */
+  uint32_t noise_flags;       /* SPS_NOISE_* */
+  int32_t max_batch;          /* workspace is sized for B <= max_batch */
+} sps_obs_desc;
+
+/* Builds the observation's fixed operators (filter rows of eq. E1, kernel
+ * widths of eq. F4, line-width table) and its workspace.  *warnings (may be
+ * NULL) receives SPS_WARN_* flags.  Errors: SPS_E_INVAL, SPS_E_SHAPE,
+ * SPS_E_NOMEM, SPS_E_HIP. */
+sps_status sps_obs_create(const sps_library *lib, const sps_obs_desc *desc, sps_obs **out,
+                          uint32_t *warnings);
+/* Replaces data/sigma/mask of an existing observation (same n_data). */
+sps_status sps_obs_set_data(sps_obs *obs, const double *data, const double *sigma,
+                            const uint8_t *mask);
+int32_t sps_obs_n_data(const sps_obs *obs);
+void sps_obs_destroy(sps_obs *obs);
+
+/* ------------------------------------------------------------------------- */
+/* Hot calls                                                                  */
+/* ------------------------------------------------------------------------- */
+/* model_dev [B, n_data] FP64: photometry in maggies, spectra in maggies per
+ * pixel (F_nu / 3631 Jy).  Errors: SPS_E_INVAL, SPS_E_SHAPE (B < 1 or
+ * B > max_batch), SPS_E_HIP. */
+sps_status sps_forward(const sps_library *lib, sps_obs *obs, const double *theta_dev, int32_t B,
+                       int32_t precision, double *model_dev, void *hip_stream);
+/* logl_dev [B] FP64: eq. (6) with eq. G1 over the inclusion mask.
+ * model_dev may be NULL; when given it also receives the model. */
+sps_status sps_logl(const sps_library *lib, sps_obs *obs, const double *theta_dev, int32_t B,
+                    int32_t precision, double *logl_dev, double *model_dev, void *hip_stream);
+/* logl_dev [B] and grad_dev [B, P] = d logL / d theta (FP64; columns the
+ * model does not use are zero).  Hand-written reverse pass.  Supported for
+ * SPS_FP64 and SPS_FP32. */
+sps_status sps_logl_grad(const sps_library *lib, sps_obs *obs, const double *theta_dev, int32_t B,
+                         int32_t precision, double *logl_dev, double *grad_dev, void *hip_stream);
+
+/* Timing of the library-contraction kernel.  When enabled, every hot call on
+ * this observation brackets its contraction kernel with HIP events on the
+ * caller's stream; sps_obs_contract_timing synchronises those events and
+ * returns the summed milliseconds, the number of launches and the executed
+ * K-tile count (for executed-flop accounting), then resets the counters. */
+sps_status sps_obs_enable_timing(sps_obs *obs, int32_t enable);
+sps_status sps_obs_contract_timing(sps_obs *obs, double *ms_total, int64_t *launches,
+                                   int64_t *executed_k_tiles, int64_t *dense_k_tiles);
+
+const char *sps_last_error(void);
+const char *sps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPS_H */

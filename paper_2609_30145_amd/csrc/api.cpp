@@ -1,0 +1,684 @@
+// Host runtime and C ABI of the batched SPS forward model (include/sps.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sps.h"
+#include "common.h"
+#include "kernels.h"
+#include "runtime.h"
+
+namespace sps {
+
+thread_local std::string g_last_error;
+
+sps_status fail(sps_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+static int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+DeviceBuffers::~DeviceBuffers() { release(); }
+void DeviceBuffers::release() {
+  for (void *p : ptrs) (void)hipFree(p);
+  ptrs.clear();
+  bytes = 0;
+}
+void *DeviceBuffers::alloc(size_t n) {
+  if (n == 0) n = 16;
+  void *p = nullptr;
+  if (hipMalloc(&p, n) != hipSuccess) return nullptr;
+  ptrs.push_back(p);
+  bytes += (int64_t)n;
+  return p;
+}
+void *DeviceBuffers::upload(const void *h, size_t n) {
+  void *p = alloc(n);
+  if (p && h && hipMemcpy(p, h, n, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  return p;
+}
+
+// Gauss-Legendre nodes on [-1, 1] by Newton iteration on P_n (n = 16).
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), pp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p1 = 1.0, p2 = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        const double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+      }
+      pp = n * (z * p1 - p2) / (z * z - 1.0);
+      const double dz = p1 / pp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = -z;
+    w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+}
+
+static bool finite_all(const double *p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+static bool increasing(const double *p, size_t n) {
+  for (size_t i = 1; i < n; ++i)
+    if (!(p[i] > p[i - 1])) return false;
+  return true;
+}
+
+}  // namespace sps
+
+using namespace sps;
+
+// =====================================================================================
+// Library
+// =====================================================================================
+extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **out) {
+  if (!d || !out) return fail(SPS_E_INVAL, "sps_library_load: NULL argument");
+  *out = nullptr;
+  const int na = d->n_age, nz = d->n_z, nf = d->n_afe, N = d->n_wave;
+  if (na < 2 || nz < 1 || nf < 1 || N < 2) return fail(SPS_E_SHAPE, "library needs n_age>=2, n_z>=1, n_afe>=1, n_wave>=2");
+  if (!d->ages || !d->logz || !d->wave || !d->flux) return fail(SPS_E_INVAL, "library arrays must not be NULL");
+  if (nf > 1 && !d->afe) return fail(SPS_E_INVAL, "afe nodes required when n_afe > 1");
+  if (!finite_all(d->ages, na) || !increasing(d->ages, na) || d->ages[0] <= 0)
+    return fail(SPS_E_INVAL, "ages must be finite, positive and strictly increasing");
+  if (!finite_all(d->logz, nz) || !increasing(d->logz, nz)) return fail(SPS_E_INVAL, "logz must be strictly increasing");
+  if (nf > 1 && (!finite_all(d->afe, nf) || !increasing(d->afe, nf)))
+    return fail(SPS_E_INVAL, "afe must be strictly increasing");
+  if (!finite_all(d->wave, N) || !increasing(d->wave, N) || d->wave[0] <= 0)
+    return fail(SPS_E_INVAL, "wave must be positive and strictly increasing");
+  const size_t nflux = (size_t)nf * nz * na * N;
+  for (size_t i = 0; i < nflux; ++i)
+    if (!std::isfinite(d->flux[i]) || d->flux[i] < 0) return fail(SPS_E_INVAL, "flux must be finite and >= 0");
+  if (d->n_sfh < 2 || d->n_sfh > 1024) return fail(SPS_E_SHAPE, "n_sfh must be in [2, 1024]");
+  if (d->n_zh < 0 || d->n_zh == 1 || d->n_zh > 1024) return fail(SPS_E_SHAPE, "n_zh must be 0 or in [2, 1024]");
+  if (!(d->T1 > 0) || !(d->H0 > 0) || !(d->Om > 0 && d->Om < 1) || !(d->t_young > 0))
+    return fail(SPS_E_INVAL, "T1, H0, t_young must be > 0 and 0 < Om < 1");
+  int ny = 0;
+  while (ny < na && d->ages[ny] < d->t_young) ++ny;
+  const int nl = d->n_line;
+  if (nl < 0 || nl > 512) return fail(SPS_E_SHAPE, "n_line must be in [0, 512]");
+  if (nl > 0) {
+    if (!d->line_wave || !d->line_table || !d->zg_nodes || !d->u_nodes || d->n_zg < 2 || d->n_u < 2)
+      return fail(SPS_E_INVAL, "line tables incomplete");
+    if (ny == 0) return fail(SPS_E_INVAL, "nebular lines need SSP ages younger than t_young");
+    if (!increasing(d->line_wave, nl) || !increasing(d->zg_nodes, d->n_zg) || !increasing(d->u_nodes, d->n_u))
+      return fail(SPS_E_INVAL, "line wavelengths and table axes must be strictly increasing");
+    if (!finite_all(d->line_table, (size_t)nl * ny * d->n_zg * d->n_u)) return fail(SPS_E_INVAL, "line table not finite");
+  }
+  int dev_count = 0;
+  if (hipGetDeviceCount(&dev_count) != hipSuccess || d->device < 0 || d->device >= dev_count)
+    return fail(SPS_E_HIP, "no HIP device %d", d->device);
+  if (hipSetDevice(d->device) != hipSuccess) return fail(SPS_E_HIP, "hipSetDevice(%d) failed", d->device);
+
+  auto *L = new sps_library();
+  L->device = d->device;
+  L->n_age = na;
+  L->n_z = nz;
+  L->n_afe = nf;
+  L->N = N;
+  L->n_young = ny;
+  L->n_line = nl;
+  L->n_sfh = d->n_sfh;
+  L->n_zh = d->n_zh;
+  L->precisions = d->precisions | (1u << SPS_FP32);
+  DevLib &g = L->dev;
+  memset(&g, 0, sizeof g);
+  g.n_age = na;
+  g.n_z = nz;
+  g.n_afe = nf;
+  g.N = N;
+  g.N_pad = round_up(N, kNAlign);
+  g.n_young = ny;
+  g.n_line = nl;
+  g.n_zg = nl ? d->n_zg : 0;
+  g.n_u = nl ? d->n_u : 0;
+  g.n_sfh = d->n_sfh;
+  g.n_zh = d->n_zh;
+  g.P = TH_NSCALAR + d->n_sfh + d->n_zh;
+  g.T1 = d->T1;
+  g.H0 = d->H0;
+  g.Om = d->Om;
+  g.t_young = d->t_young;
+
+  // ---- young-first K order.  Time-varying enrichment: age-major (old ages beyond
+  //      t_univ(z) form whole zero tiles); constant metallicity: metallicity-major
+  //      (rows of one metallicity/alpha bracket share a few (Z, alpha) blocks).
+  const int kyo = ny * nz * nf;
+  const int K_young_pad = round_up(kyo + nl, kKAlign);
+  const int kold = (na - ny) * nz * nf;
+  const int K_pad = K_young_pad + round_up(kold, kKAlign);
+  g.K = nf * nz * na + nl;
+  g.K_pad = K_pad;
+  g.K_young_pad = K_young_pad;
+  std::vector<int> kpos((size_t)nf * nz * na), ksrc(K_pad, INT_MIN);
+  auto place = [&](int a0, int a1, int kbase) {
+    int k = kbase;
+    if (d->n_zh > 0) {
+      for (int a = a0; a < a1; ++a)
+        for (int m = 0; m < nz; ++m)
+          for (int ia = 0; ia < nf; ++ia) kpos[(ia * nz + m) * na + a] = k++;
+    } else {
+      for (int m = 0; m < nz; ++m)
+        for (int ia = 0; ia < nf; ++ia)
+          for (int a = a0; a < a1; ++a) kpos[(ia * nz + m) * na + a] = k++;
+    }
+  };
+  place(0, ny, 0);
+  place(ny, na, K_young_pad);
+  for (int s = 0; s < nf * nz * na; ++s) ksrc[kpos[s]] = s;
+  L->line_k0 = kyo;
+  for (int l = 0; l < nl; ++l) ksrc[kyo + l] = -1 - l;
+
+  // ---- static per-wavelength tables
+  const int Np = g.N_pad;
+  std::vector<double> wave(Np), lnw(Np), lnlv(Np, 0.0), da(Np, 0.0), dd(Np, 0.0), lam2(Np, 0.0);
+  std::vector<float> wave_f(Np), lnlv_f(Np, 0.f), da_f(Np, 0.f), dd_f(Np, 0.f);
+  for (int n = 0; n < Np; ++n) {
+    const bool in = n < N;
+    wave[n] = in ? d->wave[n] : d->wave[N - 1] * (1.0 + 1e-3 * (n - N + 1));
+    lnw[n] = std::log(wave[n]);
+    if (in) {
+      lnlv[n] = std::log(d->wave[n] / kLamV);
+      da[n] = d->dust_a ? d->dust_a[n] : 0.0;
+      dd[n] = d->dust_d ? d->dust_d[n] : 0.0;
+      lam2[n] = d->wave[n] * d->wave[n];
+    }
+    wave_f[n] = (float)wave[n];
+    lnlv_f[n] = (float)lnlv[n];
+    da_f[n] = (float)da[n];
+    dd_f[n] = (float)dd[n];
+  }
+  // Voronoi cells of the age nodes (App. B): first from 0, last to +inf
+  std::vector<double> lo(na), hi(na);
+  for (int a = 0; a < na; ++a) {
+    lo[a] = a == 0 ? 0.0 : 0.5 * (d->ages[a - 1] + d->ages[a]);
+    hi[a] = a == na - 1 ? HUGE_VAL : 0.5 * (d->ages[a] + d->ages[a + 1]);
+  }
+  // composite Gauss-Legendre on [0, 1]: 8 panels x 16 nodes
+  std::vector<double> gx, gw, glu, glw;
+  gauss_legendre(16, gx, gw);
+  const int panels = 8;
+  for (int p = 0; p < panels; ++p)
+    for (int i = 0; i < 16; ++i) {
+      glu.push_back((p + 0.5 * (gx[i] + 1.0)) / panels);
+      glw.push_back(0.5 * gw[i] / panels);
+    }
+  g.n_gl = (int)glu.size();
+  // line profiles on the model grid: Gaussian of sigma = 2 local pixels, truncated at
+  // 5 sigma, unit trapezoid integral (Sec. 2.3.1, App. C)
+  std::vector<double> lineprof, line_a(std::max(nl, 1)), line_d(std::max(nl, 1));
+  if (nl > 0) {
+    lineprof.assign((size_t)nl * N, 0.0);
+    std::vector<double> tw(N, 0.0);
+    for (int n = 0; n + 1 < N; ++n) {
+      const double h = 0.5 * (d->wave[n + 1] - d->wave[n]);
+      tw[n] += h;
+      tw[n + 1] += h;
+    }
+    for (int l = 0; l < nl; ++l) {
+      const double lw = d->line_wave[l];
+      int k = (int)(std::upper_bound(d->wave, d->wave + N, lw) - d->wave) - 1;
+      k = std::min(std::max(k, 0), N - 2);
+      const double sg = 2.0 * (d->wave[k + 1] - d->wave[k]);
+      double norm = 0.0;
+      double *row = lineprof.data() + (size_t)l * N;
+      for (int n = 0; n < N; ++n) {
+        const double x = d->wave[n] - lw;
+        if (std::fabs(x) <= 5.0 * sg) {
+          row[n] = std::exp(-0.5 * (x / sg) * (x / sg));
+          norm += row[n] * tw[n];
+        }
+      }
+      for (int n = 0; n < N; ++n) row[n] /= norm;
+      // dust shape tables at the line wavelength (linear in lambda, clamped)
+      auto interp = [&](const double *tab) {
+        if (!tab) return 0.0;
+        if (lw <= d->wave[0]) return tab[0];
+        if (lw >= d->wave[N - 1]) return tab[N - 1];
+        const int j = (int)(std::upper_bound(d->wave, d->wave + N, lw) - d->wave) - 1;
+        const double t = (lw - d->wave[j]) / (d->wave[j + 1] - d->wave[j]);
+        return tab[j] + t * (tab[j + 1] - tab[j]);
+      };
+      line_a[l] = interp(d->dust_a);
+      line_d[l] = interp(d->dust_d);
+    }
+  }
+
+  // ---- device copies
+  DeviceBuffers &mem = L->mem;
+  bool ok = true;
+  auto up = [&](const void *h, size_t n) {
+    void *p = mem.upload(h, n);
+    ok = ok && p;
+    return p;
+  };
+  auto al = [&](size_t n) {
+    void *p = mem.alloc(n);
+    ok = ok && p;
+    return p;
+  };
+  g.cell_lo = (const double *)up(lo.data(), na * 8);
+  g.cell_hi = (const double *)up(hi.data(), na * 8);
+  g.logz = (const double *)up(d->logz, nz * 8);
+  std::vector<double> afe(nf, 0.0);
+  if (nf > 1) std::copy(d->afe, d->afe + nf, afe.begin());
+  g.afe = (const double *)up(afe.data(), nf * 8);
+  g.wave_d = (const double *)up(wave.data(), Np * 8);
+  g.lnwave_d = (const double *)up(lnw.data(), Np * 8);
+  g.wave_f = (const float *)up(wave_f.data(), Np * 4);
+  g.lnlv_d = (const double *)up(lnlv.data(), Np * 8);
+  g.lnlv_f = (const float *)up(lnlv_f.data(), Np * 4);
+  g.dust_a_d = (const double *)up(da.data(), Np * 8);
+  g.dust_d_d = (const double *)up(dd.data(), Np * 8);
+  g.dust_a_f = (const float *)up(da_f.data(), Np * 4);
+  g.dust_d_f = (const float *)up(dd_f.data(), Np * 4);
+  g.lam2_d = (const double *)up(lam2.data(), Np * 8);
+  g.gl_u = (const double *)up(glu.data(), glu.size() * 8);
+  g.gl_w = (const double *)up(glw.data(), glw.size() * 8);
+  L->kpos_d = (int *)up(kpos.data(), kpos.size() * 4);
+  int *ksrc_d = (int *)up(ksrc.data(), ksrc.size() * 4);
+  double *Q = (double *)al((size_t)std::max(1, nf * nz * ny) * 8);
+  g.Q = Q;
+  if (nl > 0) {
+    g.line_table = (const double *)up(d->line_table, (size_t)nl * ny * d->n_zg * d->n_u * 8);
+    g.zg = (const double *)up(d->zg_nodes, d->n_zg * 8);
+    g.un = (const double *)up(d->u_nodes, d->n_u * 8);
+    g.line_wave = (const double *)up(d->line_wave, nl * 8);
+    g.line_a = (const double *)up(line_a.data(), nl * 8);
+    g.line_d = (const double *)up(line_d.data(), nl * 8);
+  }
+  int *kexp = (int *)al((size_t)K_pad * 4);
+  g.kexp = kexp;
+  const size_t KN = (size_t)K_pad * Np;
+  PackLaunch pk;
+  memset(&pk, 0, sizeof pk);
+  pk.LT32 = (float *)al(KN * 4);
+  pk.L32n = (float *)al(KN * 4);
+  if (L->precisions & (1u << SPS_FP64)) pk.LT64 = (double *)al(KN * 8);
+  const bool want_bf = L->precisions & ((1u << SPS_BF16) | (1u << SPS_BF16_1PASS) | (1u << SPS_BF16_HR));
+  const bool want_h = L->precisions & ((1u << SPS_FP16) | (1u << SPS_FP16_1PASS) | (1u << SPS_FP16_HR));
+  if (want_bf) {
+    pk.Hb = (uint16_t *)al(KN * 2);
+    pk.Rb = (uint16_t *)al(KN * 2);
+    L->precisions |= (1u << SPS_BF16) | (1u << SPS_BF16_1PASS) | (1u << SPS_BF16_HR);
+  }
+  if (want_h) {
+    pk.Hh = (uint16_t *)al(KN * 2);
+    pk.Rh = (uint16_t *)al(KN * 2);
+    L->precisions |= (1u << SPS_FP16) | (1u << SPS_FP16_1PASS) | (1u << SPS_FP16_HR);
+  }
+  if (!ok) {
+    delete L;
+    return fail(SPS_E_NOMEM, "sps_library_load: device allocation failed");
+  }
+  g.LT64 = pk.LT64;
+  g.LT32 = pk.LT32;
+  g.L32n = pk.L32n;
+  g.Hb = pk.Hb;
+  g.Rb = pk.Rb;
+  g.Hh = pk.Hh;
+  g.Rh = pk.Rh;
+  // temporary uploads of the raw grid and the line profiles
+  DeviceBuffers tmp;
+  pk.flux = (const double *)tmp.upload(d->flux, nflux * 8);
+  pk.lineprof = nl ? (const double *)tmp.upload(lineprof.data(), lineprof.size() * 8) : nullptr;
+  if (!pk.flux || (nl && !pk.lineprof)) {
+    delete L;
+    return fail(SPS_E_NOMEM, "sps_library_load: staging allocation failed");
+  }
+  pk.ksrc = ksrc_d;
+  pk.neb_mask = nl > 0;
+  pk.kexp = kexp;
+  pk.Q = Q;
+  pk.wave = g.wave_d;
+  hipError_t e = launch_pack(g, pk, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    delete L;
+    return fail(SPS_E_HIP, "library packing failed: %s", hipGetErrorString(e));
+  }
+  tmp.release();
+  *out = L;
+  return SPS_OK;
+}
+
+extern "C" sps_status sps_library_info_get(const sps_library *L, sps_library_info *o) {
+  if (!L || !o) return fail(SPS_E_INVAL, "NULL argument");
+  o->K = L->dev.K;
+  o->K_pad = L->dev.K_pad;
+  o->K_young_pad = L->dev.K_young_pad;
+  o->N = L->dev.N;
+  o->N_pad = L->dev.N_pad;
+  o->n_young = L->n_young;
+  o->n_line = L->n_line;
+  o->device_bytes = L->mem.bytes;
+  return SPS_OK;
+}
+
+extern "C" void sps_library_destroy(sps_library *L) {
+  if (!L) return;
+  (void)hipSetDevice(L->device);
+  delete L;
+}
+
+extern "C" sps_status sps_theta_layout(const sps_library *L, sps_layout *o) {
+  if (!L || !o) return fail(SPS_E_INVAL, "NULL argument");
+  o->n_scalar = TH_NSCALAR;
+  o->sfh = TH_NSCALAR;
+  o->n_sfh = L->n_sfh;
+  o->zh = TH_NSCALAR + L->n_sfh;
+  o->n_zh = L->n_zh;
+  o->P = L->dev.P;
+  o->logmass = TH_LOGMASS;
+  o->zred = TH_ZRED;
+  o->tau_bc = TH_TAU_BC;
+  o->alpha_bc = TH_ALPHA_BC;
+  o->tau_diff = TH_TAU_DIFF;
+  o->delta = TH_DELTA;
+  o->logzsol = TH_LOGZSOL;
+  o->gas_logz = TH_GAS_LOGZ;
+  o->gas_logu = TH_GAS_LOGU;
+  o->afe = TH_AFE;
+  o->log_err_scale = TH_LOG_ERR_SCALE;
+  o->log_f_calib = TH_LOG_F_CALIB;
+  o->log_f_data = TH_LOG_F_DATA;
+  o->log_jitter = TH_LOG_JITTER;
+  return SPS_OK;
+}
+
+// =====================================================================================
+// Observations
+// =====================================================================================
+namespace sps {
+
+static double sigma_inst_host(int mode, double v, double lam) {
+  const double f = 2.3548200450309493;
+  switch (mode) {
+    case SPS_LSF_R_FWHM: return kC_kms / (f * v);
+    case SPS_LSF_R_SIGMA: return kC_kms / v;
+    case SPS_LSF_FWHM_AA: return kC_kms * v / (f * lam);
+    case SPS_LSF_SIGMA_AA: return kC_kms * v / lam;
+    case SPS_LSF_SIGMA_KMS: return v;
+    default: return v / f;
+  }
+}
+
+sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsHost &h, uint32_t *warnings) {
+  if (warnings) *warnings = 0;
+  h.kind = d->kind;
+  if (d->kind == SPS_OBS_PHOT) {
+    if (d->n_band < 1 || d->n_band > 256) return fail(SPS_E_SHAPE, "n_band must be in [1, 256]");
+    if (!d->filter_len || !d->filter_wave || !d->filter_trans) return fail(SPS_E_INVAL, "filter arrays are NULL");
+    h.n_data = d->n_band;
+    h.band_off.assign(1, 0);
+    size_t off = 0;
+    for (int b = 0; b < d->n_band; ++b) {
+      const int n = d->filter_len[b];
+      if (n < 2) return fail(SPS_E_SHAPE, "filter %d has fewer than 2 nodes", b);
+      const double *lam = d->filter_wave + off, *R = d->filter_trans + off;
+      if (!finite_all(lam, n) || !increasing(lam, n) || lam[0] <= 0)
+        return fail(SPS_E_INVAL, "filter %d wavelengths must be positive and increasing", b);
+      for (int j = 0; j < n; ++j)
+        if (!std::isfinite(R[j]) || R[j] < 0) return fail(SPS_E_INVAL, "filter %d transmission invalid", b);
+      // eq. E1: numerator R lambda dlambda (central differences, one-sided ends);
+      // zero point: trapezoid of R lambda f_lambda^AB
+      double zp = 0.0;
+      std::vector<double> num(n);
+      for (int j = 0; j < n; ++j) {
+        const double dl = j == 0 ? lam[1] - lam[0] : j == n - 1 ? lam[n - 1] - lam[n - 2] : 0.5 * (lam[j + 1] - lam[j - 1]);
+        const double tw = j == 0 ? 0.5 * (lam[1] - lam[0]) : j == n - 1 ? 0.5 * (lam[n - 1] - lam[n - 2])
+                                                                         : 0.5 * (lam[j + 1] - lam[j - 1]);
+        const double fab = kFnuAB * kC_cms / ((lam[j] * kAng_cm) * (lam[j] * kAng_cm));
+        zp += R[j] * lam[j] * tw * fab;
+        num[j] = R[j] * lam[j] * dl;
+      }
+      if (!(zp > 0)) return fail(SPS_E_INVAL, "filter %d has zero transmission", b);
+      for (int j = 0; j < n; ++j) {
+        h.fw.push_back(lam[j]);
+        h.fr.push_back(num[j] / zp);
+      }
+      off += n;
+      h.band_off.push_back((int)off);
+    }
+  } else if (d->kind == SPS_OBS_SPEC) {
+    const int np = d->n_pix;
+    if (np < 2) return fail(SPS_E_SHAPE, "n_pix must be >= 2");
+    if (!d->pix_wave || !finite_all(d->pix_wave, np) || !increasing(d->pix_wave, np) || d->pix_wave[0] <= 0)
+      return fail(SPS_E_INVAL, "pixel wavelengths must be positive and increasing");
+    if (d->lsf_mode == SPS_LSF_BARE_R)
+      return fail(SPS_E_INVAL, "a bare resolving power is ambiguous: state R_fwhm or R_sigma (App. F)");
+    if (d->lsf_mode < 0 || d->lsf_mode > SPS_LSF_FWHM_KMS) return fail(SPS_E_INVAL, "unknown LSF mode %d", d->lsf_mode);
+    if (!d->lsf_curve && !(d->lsf_value > 0)) return fail(SPS_E_INVAL, "LSF value must be > 0");
+    if (d->lsf_curve)
+      for (int i = 0; i < np; ++i)
+        if (!(d->lsf_curve[i] > 0) || !std::isfinite(d->lsf_curve[i])) return fail(SPS_E_INVAL, "LSF curve must be > 0");
+    if (!(d->z_ref >= 0) || !(d->sigma_gal_kms >= 0) || !(d->sigma_gas_kms >= 0))
+      return fail(SPS_E_INVAL, "z_ref and dispersions must be >= 0");
+    h.n_data = np;
+    h.pix.assign(d->pix_wave, d->pix_wave + np);
+    h.lnpix.resize(np);
+    h.ksig.resize(np);
+    // library resolution floor (eq. F3): (c / 2.3548) * 2 dlambda / lambda on the stored grid
+    const int N = L->dev.N;
+    std::vector<double> lw(N), slib(N);
+    L->host_wave(lw);
+    for (int n = 0; n < N; ++n) {
+      const double dl = n == 0 ? lw[1] - lw[0] : n == N - 1 ? lw[N - 1] - lw[N - 2] : 0.5 * (lw[n + 1] - lw[n - 1]);
+      slib[n] = kC_kms / 2.3548200450309493 * 2.0 * dl / lw[n];
+    }
+    int finer = 0;
+    for (int i = 0; i < np; ++i) {
+      const double lam = d->pix_wave[i];
+      h.lnpix[i] = std::log(lam);
+      const double v = d->lsf_curve ? d->lsf_curve[i] : d->lsf_value;
+      const double si = sigma_inst_host(d->lsf_mode, v, lam);
+      const double lr = lam / (1.0 + d->z_ref);
+      double sl;
+      if (lr <= lw[0]) sl = slib[0];
+      else if (lr >= lw[N - 1]) sl = slib[N - 1];
+      else {
+        const int j = (int)(std::upper_bound(lw.begin(), lw.end(), lr) - lw.begin()) - 1;
+        sl = slib[j] + (lr - lw[j]) / (lw[j + 1] - lw[j]) * (slib[j + 1] - slib[j]);
+      }
+      if (si < sl) ++finer;
+      const double sfix2 = std::max(si * si - sl * sl, 0.0);
+      h.ksig[i] = std::sqrt(sfix2 + d->sigma_gal_kms * d->sigma_gal_kms) / kC_kms;
+    }
+    if (finer && warnings) *warnings |= SPS_WARN_LSF_FINER_THAN_LIBRARY;
+    h.lsf_mode = d->lsf_mode;
+    h.lsf_value = d->lsf_value;
+    if (d->lsf_curve) h.lsf_vals.assign(d->lsf_curve, d->lsf_curve + np);
+    h.sigma_gas = d->sigma_gas_kms;
+  } else {
+    return fail(SPS_E_INVAL, "unknown observation kind %d", d->kind);
+  }
+  h.noise_flags = d->noise_flags & 15u;
+  return SPS_OK;
+}
+
+sps_status set_obs_data(ObsHost &h, const double *data, const double *sigma, const uint8_t *mask) {
+  const int n = h.n_data;
+  h.data.assign(n, 0.0);
+  h.sigma.assign(n, 1.0);
+  h.mask.assign(n, 0);
+  if (!data || !sigma) return SPS_OK;   // no data: logL over an empty mask is 0
+  for (int i = 0; i < n; ++i) {
+    const bool ok = std::isfinite(data[i]) && std::isfinite(sigma[i]) && sigma[i] > 0 && (!mask || mask[i]);
+    h.mask[i] = ok ? 1 : 0;
+    if (ok) {
+      h.data[i] = data[i];
+      h.sigma[i] = sigma[i];
+    }
+  }
+  return SPS_OK;
+}
+
+}  // namespace sps
+
+extern "C" sps_status sps_obs_create(const sps_library *L, const sps_obs_desc *d, sps_obs **out, uint32_t *warnings) {
+  if (!L || !d || !out) return fail(SPS_E_INVAL, "sps_obs_create: NULL argument");
+  *out = nullptr;
+  if (d->max_batch < 1 || d->max_batch > (1 << 20)) return fail(SPS_E_SHAPE, "max_batch must be in [1, 2^20]");
+  if (hipSetDevice(L->device) != hipSuccess) return fail(SPS_E_HIP, "hipSetDevice failed");
+  auto *o = new sps_obs();
+  o->lib = L;
+  sps_status st = build_obs_operators(L, d, o->host, warnings);
+  if (st == SPS_OK) st = set_obs_data(o->host, d->data, d->sigma, d->mask);
+  if (st == SPS_OK) st = o->upload_operators();
+  if (st == SPS_OK) st = o->ws.create(L, d->max_batch, o->host.n_data);
+  if (st != SPS_OK) {
+    delete o;
+    return st;
+  }
+  *out = o;
+  return SPS_OK;
+}
+
+extern "C" sps_status sps_obs_set_data(sps_obs *o, const double *data, const double *sigma, const uint8_t *mask) {
+  if (!o) return fail(SPS_E_INVAL, "NULL observation");
+  if (hipSetDevice(o->lib->device) != hipSuccess) return fail(SPS_E_HIP, "hipSetDevice failed");
+  sps_status st = set_obs_data(o->host, data, sigma, mask);
+  if (st != SPS_OK) return st;
+  return o->upload_data();
+}
+
+extern "C" int32_t sps_obs_n_data(const sps_obs *o) { return o ? o->host.n_data : -1; }
+
+extern "C" void sps_obs_destroy(sps_obs *o) {
+  if (!o) return;
+  (void)hipSetDevice(o->lib->device);
+  delete o;
+}
+
+// =====================================================================================
+// Hot calls
+// =====================================================================================
+namespace sps {
+
+static bool precision_built(const sps_library *L, int p) { return p >= 0 && p <= 7 && (L->precisions >> p) & 1u; }
+
+sps_status run_forward(const sps_library *L, sps_obs *o, const double *theta, int B, int prec, double *logl,
+                       double *model, bool want_grad_buffers, hipStream_t s) {
+  if (!L || !o || !theta) return fail(SPS_E_INVAL, "NULL argument");
+  if (o->lib != L) return fail(SPS_E_INVAL, "observation belongs to another library");
+  if (B < 1 || B > o->ws.max_batch) return fail(SPS_E_SHAPE, "B=%d outside [1, max_batch=%d]", B, o->ws.max_batch);
+  if (!precision_built(L, prec)) return fail(SPS_E_INVAL, "precision %d not built into this library", prec);
+  Workspace &w = o->ws;
+  const DevLib &g = L->dev;
+  const int B_pad = (B + kMAlign - 1) / kMAlign * kMAlign;
+  const int mode = prec == 0 ? 0 : prec == 1 ? 1 : (prec == 2 || prec == 4 || prec == 6) ? 2 : 3;
+  hipError_t e = launch_sort(g, theta, g.P, B, w.perm, s);
+  PrepLaunch pl;
+  pl.theta = theta;
+  pl.P = g.P;
+  pl.B = B;
+  pl.B_pad = B_pad;
+  pl.perm = w.perm;
+  pl.obs_table = o->dev_obs;
+  pl.point_obs = nullptr;
+  pl.W = w.W;
+  pl.Wlo = (char *)w.W + (size_t)B_pad * g.K_pad * 2;
+  pl.rowmask = w.rowmask;
+  pl.mask_words = w.mask_words;
+  pl.rows = w.rows;
+  pl.Lline = w.Lline;
+  pl.kpos = L->kpos_d;
+  pl.line_k0 = L->line_k0;
+  pl.mode = mode;
+  if (e == hipSuccess) e = launch_prep(g, pl, s);
+  const int MT = contract_mtile(prec);
+  const int tf = contract_ktile_factor(prec);
+  if (e == hipSuccess)
+    e = launch_tiles(w.rowmask, w.mask_words, B_pad, MT, g.K_pad / kKTile, g.K_young_pad / kKTile, tf, w.tiles,
+                     w.n_young, w.n_act, w.counter, s);
+  ContractLaunch cl;
+  cl.W = pl.W;
+  cl.Wlo = pl.Wlo;
+  cl.B_pad = B_pad;
+  cl.tiles = w.tiles;
+  cl.n_young = w.n_young;
+  cl.n_act = w.n_act;
+  cl.rows = w.rows;
+  cl.F = w.F;
+  cl.Yatt = want_grad_buffers ? w.Yatt : nullptr;
+  cl.precision = prec;
+  if (e == hipSuccess) e = o->timing_begin(s, B_pad / MT, g.K_pad / (kKTile * tf));
+  if (e == hipSuccess) e = launch_contract(g, cl, s);
+  if (e == hipSuccess) e = o->timing_end(s);
+  ProjectLaunch pj;
+  pj.obs_table = o->dev_obs;
+  pj.rows = w.rows;
+  pj.F = w.F;
+  pj.f64 = prec == 0;
+  pj.theta = theta;
+  pj.P = g.P;
+  pj.B = B;
+  pj.Lline = w.Lline;
+  pj.model = model;
+  pj.logl = logl;
+  pj.gvec = want_grad_buffers ? w.gvec : nullptr;
+  pj.gnoise = want_grad_buffers ? w.gnoise : nullptr;
+  pj.ld_model = o->host.n_data;
+  pj.ld_g = o->host.n_data;
+  if (e == hipSuccess) e = launch_project(g, pj, s);
+  if (e != hipSuccess) return fail(SPS_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return SPS_OK;
+}
+
+}  // namespace sps
+
+extern "C" sps_status sps_forward(const sps_library *L, sps_obs *o, const double *theta, int32_t B, int32_t prec,
+                                  double *model, void *stream) {
+  if (!model) return fail(SPS_E_INVAL, "model_dev is NULL");
+  return run_forward(L, o, theta, B, prec, nullptr, model, false, (hipStream_t)stream);
+}
+
+extern "C" sps_status sps_logl(const sps_library *L, sps_obs *o, const double *theta, int32_t B, int32_t prec,
+                               double *logl, double *model, void *stream) {
+  if (!logl) return fail(SPS_E_INVAL, "logl_dev is NULL");
+  return run_forward(L, o, theta, B, prec, logl, model, false, (hipStream_t)stream);
+}
+
+extern "C" sps_status sps_logl_grad(const sps_library *L, sps_obs *o, const double *theta, int32_t B, int32_t prec,
+                                    double *logl, double *grad, void *stream) {
+  if (!logl || !grad) return fail(SPS_E_INVAL, "logl_dev / grad_dev is NULL");
+  if (prec != SPS_FP64 && prec != SPS_FP32) return fail(SPS_E_INVAL, "gradients are available for FP64 and FP32");
+  sps_status st = run_forward(L, o, theta, B, prec, logl, nullptr, true, (hipStream_t)stream);
+  if (st != SPS_OK) return st;
+  return run_adjoint(L, o, theta, B, prec, grad, (hipStream_t)stream);
+}
+
+extern "C" sps_status sps_obs_enable_timing(sps_obs *o, int32_t enable) {
+  if (!o) return fail(SPS_E_INVAL, "NULL observation");
+  return o->enable_timing(enable != 0);
+}
+
+extern "C" sps_status sps_obs_contract_timing(sps_obs *o, double *ms, int64_t *launches, int64_t *exec_tiles,
+                                              int64_t *dense_tiles) {
+  if (!o) return fail(SPS_E_INVAL, "NULL observation");
+  return o->read_timing(ms, launches, exec_tiles, dense_tiles);
+}
+
+extern "C" const char *sps_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *sps_version(void) { return "sps-gfx950 0.1"; }

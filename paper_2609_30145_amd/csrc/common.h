@@ -1,0 +1,130 @@
+// Internal definitions shared by the host runtime (api.cpp) and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sps {
+
+// ---------------------------------------------------------------- constants (cgs)
+constexpr double kC_cms = 2.99792458e10;
+constexpr double kC_kms = 2.99792458e5;
+constexpr double kHplanck = 6.62607015e-27;
+constexpr double kLsun = 3.839e33;            // FSPS value (Sec. 2.6)
+constexpr double kPc_cm = 3.0856775814913673e18;
+constexpr double kMpc_cm = 1e6 * kPc_cm;
+constexpr double kMpc_km = kMpc_cm / 1e5;
+constexpr double kYr_s = 3.15576e7;
+constexpr double kFnuAB = 3.631e-20;          // 3631 Jy (App. E)
+constexpr double kAng_cm = 1e-8;
+constexpr double kLamV = 5500.0;              // attenuation reference (Sec. 2.4)
+constexpr double kLamLyman = 912.0;           // eq. C1 upper limit
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------- tiling
+constexpr int kKAlign = 64;     // K segments (young, old) padded to this
+constexpr int kNAlign = 128;    // wavelength axis padded to this
+constexpr int kMAlign = 128;    // batch rows padded to this (contraction M tile)
+constexpr int kKTile = 32;      // K tile of the occupancy bitmask (FP32 / FP64 kernels)
+
+// theta scalar columns (see include/sps.h)
+enum ThetaCol {
+  TH_LOGMASS = 0, TH_ZRED, TH_TAU_BC, TH_ALPHA_BC, TH_TAU_DIFF, TH_DELTA, TH_LOGZSOL,
+  TH_GAS_LOGZ, TH_GAS_LOGU, TH_AFE, TH_LOG_ERR_SCALE, TH_LOG_F_CALIB, TH_LOG_F_DATA,
+  TH_LOG_JITTER, TH_NSCALAR
+};
+
+// Device-resident library (all pointers are device pointers).
+struct DevLib {
+  int n_age, n_z, n_afe, N, N_pad, K, K_pad, K_young_pad, n_young, n_line, n_zg, n_u;
+  int n_sfh, n_zh, P, n_gl;
+  double T1, H0, Om, t_young;
+  const double *cell_lo, *cell_hi;   // [n_age] linear-time Voronoi cells
+  const double *logz, *afe;          // nodes
+  const double *Q;                   // [n_afe][n_z][n_young] photons/s/Msun
+  const double *line_table;          // [n_line][n_young][n_zg][n_u]
+  const double *zg, *un;             // nebular table axes
+  const double *line_wave;           // [n_line] rest A
+  const double *line_a, *line_d;     // dust shape tables at the line wavelengths
+  const double *wave_d, *lnwave_d;   // [N_pad] rest wavelength (padding: +inf-ish)
+  const float *wave_f;
+  const double *lnlv_d;              // [N_pad] ln(lambda/5500)
+  const float *lnlv_f;
+  const double *dust_a_d, *dust_d_d; // [N_pad]
+  const float *dust_a_f, *dust_d_f;
+  const double *lam2_d;              // [N_pad] lambda^2 (A^2)
+  const double *LT64;                // [N_pad][K_pad] FP64, K contiguous
+  const float *LT32;                 // [N_pad][K_pad] FP32
+  const float *L32n;                 // [K_pad][N_pad] FP32, N contiguous (adjoint)
+  const uint16_t *Hb, *Rb;           // [N_pad][K_pad] bf16 hi / residual
+  const uint16_t *Hh, *Rh;           // [N_pad][K_pad] fp16 hi / residual
+  const int *kexp;                   // [K_pad] row exponent e_k of the 16-bit copies
+  const double *gl_u, *gl_w;         // [n_gl] composite Gauss-Legendre on [0,1]
+};
+
+// Observation descriptor in device memory.
+struct DevObs {
+  int kind, n_data, n_band, n_fnodes, noise_flags, lsf_mode, has_curve, pad;
+  const int *band_off;               // [n_band+1]
+  const double *fw;                  // [n_fnodes] filter node wavelengths (observer A)
+  const double *fr_d;                // R_j lambda_j dlambda_j / zero point  (eq. E1)
+  const float *fr_f;
+  const double *pix, *lnpix;         // [n_pix]
+  const double *ksig;                // [n_pix] continuum kernel dispersion in ln(lambda)
+  const double *lsf_vals;            // [n_pix] LSF parameter curve (eq. F2 units) or NULL
+  double sigma_gas_kms, lsf_value;   // gas dispersion; constant LSF parameter
+  const double *data, *sigma;        // [n_data]
+  const uint8_t *mask;               // [n_data] final inclusion mask
+};
+
+// Per-point quantities, stored at the point's sorted row.
+struct PointRow {
+  double z, t_univ, dl, dc, scale_fnu, mass10, wscale;
+  double tau_bc, alpha_bc, tau_diff, delta;
+  int b;        // original batch index
+  int obs;      // observation slot
+  int kind;     // observation kind
+  int pad;
+};
+
+// ---------------------------------------------------------------- device helpers
+// index j with x[j] <= v < x[j+1], limited to [0, n-2]
+template <typename T>
+__device__ __forceinline__ int bracket(const T *x, int n, T v) {
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (x[mid] <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// first index j with x[j] >= v (n if none)
+template <typename T>
+__device__ __forceinline__ int lower_bound_dev(const T *x, int n, T v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (x[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// bracketing node j and fraction t of x on a 1-D grid, clamped (metallicity split of App. B)
+__device__ __forceinline__ void grid_split_dev(const double *nodes, int n, double x, int &j, double &t,
+                                               bool &inside) {
+  double xc = x;
+  inside = true;
+  if (xc < nodes[0]) { xc = nodes[0]; inside = false; }
+  if (xc > nodes[n - 1]) { xc = nodes[n - 1]; inside = false; }
+  int jj = 0;
+  while (jj + 1 < n - 1 && nodes[jj + 1] <= xc) ++jj;
+  j = jj;
+  t = (xc - nodes[jj]) / (nodes[jj + 1] - nodes[jj]);
+}
+
+}  // namespace sps
+
+// ---------------------------------------------------------------- host launchers
+namespace sps {
+struct Workspace;
+}

@@ -1,0 +1,302 @@
+// Library contraction F = T_d (T_BC * sum_young W L + sum_old W L) (eq. 1, eq. D2),
+// fused with both attenuation factors.  The weight matrix is in young-first K order,
+// so the birth-cloud transmission is applied to the accumulator once, between the
+// young and the old K tiles; K tiles that are zero for every row of an M tile are
+// skipped through the per-M-tile active list.
+#include "common.h"
+#include "kernels.h"
+
+namespace sps {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+struct ContractArgs {
+  const void *W, *Wlo;
+  const void *LTa, *LTb;   // FP32/FP64: LTa; 16-bit: hi (LTa) and residual (LTb) planes
+  int K_pad, N_pad, B_pad, n_tiles;
+  const int *tiles, *n_young, *n_act;
+  const PointRow *rows;
+  const float *lnlv, *da, *dd;
+  const double *lnlv_d, *da_d, *dd_d;
+  void *F, *Yatt;
+};
+
+// blockIdx -> (m tile, n tile).  Workgroups are dispatched round-robin over the 8 XCDs;
+// the remap gives each XCD a contiguous range of (m, n) tiles with n fastest, so one
+// XCD keeps a single M tile of the weights in its L2 while the library streams past.
+__device__ __forceinline__ void tile_of_block(int n_ntiles, int &mt, int &nt) {
+  const int nblk = gridDim.x, bid = blockIdx.x;
+  int logical = bid;
+  if ((nblk & 7) == 0) logical = (bid & 7) * (nblk >> 3) + (bid >> 3);
+  mt = logical / n_ntiles;
+  nt = logical - mt * n_ntiles;
+}
+
+// ---------------------------------------------------------------------------------
+// FP32: v_mfma_f32_32x32x2f32.  Lane (i = l & 31, h = l >> 5) feeds A[i][k] and
+// B[k][i] with k = h*16 + s at MFMA step s, so each lane reads 16 contiguous
+// floats of its LDS row per 32-wide K tile.
+// ---------------------------------------------------------------------------------
+template <int MT, int NT, int WM, int WN>
+__global__ void __launch_bounds__(256) k_contract_f32(ContractArgs a) {
+  constexpr int KT = 32, LDSK = KT + 4;
+  constexpr int WTM = MT / WM, WTN = NT / WN, BM = WTM / 32, BN = WTN / 32;
+  static_assert(WM * WN == 4, "4 waves");
+  constexpr int A4 = MT * KT / 4 / 256, B4 = NT * KT / 4 / 256;
+  __shared__ __attribute__((aligned(16))) float As[MT * LDSK];
+  __shared__ __attribute__((aligned(16))) float Bs[NT * LDSK];
+  __shared__ float sp[MT][5];
+
+  int mt, nt;
+  tile_of_block(a.N_pad / NT, mt, nt);
+  const int m0 = mt * MT, n0 = nt * NT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int li = lane & 31, lh = lane >> 5;
+  const float *W = (const float *)a.W;
+  const float *LT = (const float *)a.LTa;
+  const int K_pad = a.K_pad;
+
+  for (int r = tid; r < MT; r += 256) {
+    const PointRow &pr = a.rows[m0 + r];
+    sp[r][0] = (float)pr.tau_bc;
+    sp[r][1] = (float)pr.alpha_bc;
+    sp[r][2] = (float)pr.tau_diff;
+    sp[r][3] = (float)pr.delta;
+    sp[r][4] = (float)(0.85 - 1.9 * pr.delta);
+  }
+
+  v16f acc[BM][BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int nact = a.n_act[mt], ny = a.n_young[mt];
+  const int *tl = a.tiles + (size_t)mt * a.n_tiles;
+
+  float4 ra[A4], rb[B4];
+  auto gload = [&](int t) {
+    const int k0 = tl[t] * KT;
+#pragma unroll
+    for (int q = 0; q < A4; ++q) {
+      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
+      ra[q] = *(const float4 *)(W + (size_t)(m0 + row) * K_pad + k0 + c4 * 4);
+    }
+#pragma unroll
+    for (int q = 0; q < B4; ++q) {
+      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
+      rb[q] = *(const float4 *)(LT + (size_t)(n0 + row) * K_pad + k0 + c4 * 4);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int q = 0; q < A4; ++q) {
+      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
+      *(float4 *)(As + row * LDSK + c4 * 4) = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < B4; ++q) {
+      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
+      *(float4 *)(Bs + row * LDSK + c4 * 4) = rb[q];
+    }
+  };
+
+  // per-lane columns and their static factors
+  float c_lnlv[BN], c_a[BN], c_d[BN];
+#pragma unroll
+  for (int j = 0; j < BN; ++j) {
+    const int col = n0 + wn * WTN + j * 32 + li;
+    c_lnlv[j] = a.lnlv[col];
+    c_a[j] = a.da[col];
+    c_d[j] = a.dd[col];
+  }
+
+  auto apply_bc = [&]() {
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+        const float tbc = sp[rl][0], abc = sp[rl][1];
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          const float T = __expf(-tbc * __expf(abc * c_lnlv[j]));
+          acc[i][j][e] *= T;
+          if (a.Yatt) {
+            const float Td = __expf(-sp[rl][2] * __expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+            const int col = n0 + wn * WTN + j * 32 + li;
+            ((float *)a.Yatt)[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j][e] * Td;
+          }
+        }
+      }
+  };
+
+  __syncthreads();
+  if (nact > 0) gload(0);
+  for (int t = 0; t < nact; ++t) {
+    __syncthreads();
+    sstore();
+    __syncthreads();
+    if (t + 1 < nact) gload(t + 1);
+    if (t == ny) apply_bc();
+    float af[BM][16], bf[BN][16];
+#pragma unroll
+    for (int i = 0; i < BM; ++i) {
+      const float *p = As + (wm * WTM + i * 32 + li) * LDSK + lh * 16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = *(const float4 *)(p + 4 * q);
+        af[i][4 * q] = v.x; af[i][4 * q + 1] = v.y; af[i][4 * q + 2] = v.z; af[i][4 * q + 3] = v.w;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < BN; ++j) {
+      const float *p = Bs + (wn * WTN + j * 32 + li) * LDSK + lh * 16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = *(const float4 *)(p + 4 * q);
+        bf[j][4 * q] = v.x; bf[j][4 * q + 1] = v.y; bf[j][4 * q + 2] = v.z; bf[j][4 * q + 3] = v.w;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+  }
+  if (ny == nact) {
+    __syncthreads();
+    apply_bc();
+  }
+
+  // diffuse screen on everything and store
+  float *F = (float *)a.F;
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        const int col = n0 + wn * WTN + j * 32 + li;
+        const float Td = __expf(-sp[rl][2] * __expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+        F[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j][e] * Td;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// FP64 parity instance: LDS-tiled FMA, 64x64 tile, 4x4 outputs per thread.
+// ---------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_contract_f64(ContractArgs a) {
+  constexpr int MT = 64, NT = 64, KT = 32, LDSK = KT + 1;
+  __shared__ double As[MT * LDSK];
+  __shared__ double Bs[NT * LDSK];
+  __shared__ double sp[MT][5];
+  int mt, nt;
+  tile_of_block(a.N_pad / NT, mt, nt);
+  const int m0 = mt * MT, n0 = nt * NT;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const double *W = (const double *)a.W;
+  const double *LT = (const double *)a.LTa;
+  for (int r = tid; r < MT; r += 256) {
+    const PointRow &pr = a.rows[m0 + r];
+    sp[r][0] = pr.tau_bc;
+    sp[r][1] = pr.alpha_bc;
+    sp[r][2] = pr.tau_diff;
+    sp[r][3] = pr.delta;
+    sp[r][4] = 0.85 - 1.9 * pr.delta;
+  }
+  double acc[4][4] = {};
+  const int nact = a.n_act[mt], ny = a.n_young[mt];
+  const int *tl = a.tiles + (size_t)mt * a.n_tiles;
+  auto apply_bc = [&]() {
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        const int rl = ty + 16 * i, col = n0 + tx + 16 * j;
+        const double T = exp(-sp[rl][0] * exp(sp[rl][1] * a.lnlv_d[col]));
+        acc[i][j] *= T;
+        if (a.Yatt) {
+          const double Td = exp(-sp[rl][2] * exp(sp[rl][3] * a.lnlv_d[col]) * (a.da_d[col] + sp[rl][4] * a.dd_d[col]));
+          ((double *)a.Yatt)[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j] * Td;
+        }
+      }
+  };
+  for (int t = 0; t < nact; ++t) {
+    const int k0 = tl[t] * KT;
+    __syncthreads();
+    for (int idx = tid; idx < MT * KT; idx += 256) {
+      const int row = idx / KT, c = idx % KT;
+      As[row * LDSK + c] = W[(size_t)(m0 + row) * a.K_pad + k0 + c];
+      Bs[row * LDSK + c] = LT[(size_t)(n0 + row) * a.K_pad + k0 + c];
+    }
+    __syncthreads();
+    if (t == ny) apply_bc();
+    for (int kk = 0; kk < KT; ++kk) {
+      double av[4], bv[4];
+      for (int i = 0; i < 4; ++i) av[i] = As[(ty + 16 * i) * LDSK + kk];
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[(tx + 16 * j) * LDSK + kk];
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+  }
+  __syncthreads();
+  if (ny == nact) apply_bc();
+  double *F = (double *)a.F;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      const int rl = ty + 16 * i, col = n0 + tx + 16 * j;
+      const double Td = exp(-sp[rl][2] * exp(sp[rl][3] * a.lnlv_d[col]) * (a.da_d[col] + sp[rl][4] * a.dd_d[col]));
+      F[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j] * Td;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+int contract_mtile(int precision) { return precision == 0 ? 64 : 128; }
+int contract_ktile_factor(int precision) { return precision >= 2 ? 2 : 1; }
+
+hipError_t launch_contract16_impl(const DevLib &lib, const void *W, const void *Wlo, const int *tiles,
+                                  const int *n_young, const int *n_act, const PointRow *rows, void *F, void *Yatt,
+                                  int precision, int n_mt, hipStream_t s);
+
+hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStream_t s) {
+  ContractArgs a;
+  a.W = cl.W;
+  a.Wlo = cl.Wlo;
+  a.K_pad = lib.K_pad;
+  a.N_pad = lib.N_pad;
+  a.B_pad = cl.B_pad;
+  a.tiles = cl.tiles;
+  a.n_young = cl.n_young;
+  a.n_act = cl.n_act;
+  a.rows = cl.rows;
+  a.lnlv = lib.lnlv_f;
+  a.da = lib.dust_a_f;
+  a.dd = lib.dust_d_f;
+  a.lnlv_d = lib.lnlv_d;
+  a.da_d = lib.dust_a_d;
+  a.dd_d = lib.dust_d_d;
+  a.F = cl.F;
+  a.Yatt = cl.Yatt;
+  const int MT = contract_mtile(cl.precision);
+  const int n_mt = cl.B_pad / MT;
+  a.n_tiles = lib.K_pad / (kKTile * contract_ktile_factor(cl.precision));
+  if (cl.precision == 0) {
+    a.LTa = lib.LT64;
+    hipLaunchKernelGGL(k_contract_f64, dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
+  } else if (cl.precision == 1) {
+    a.LTa = lib.LT32;
+    hipLaunchKernelGGL((k_contract_f32<128, 64, 2, 2>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
+  } else {
+    return launch_contract16_impl(lib, cl.W, cl.Wlo, cl.tiles, cl.n_young, cl.n_act, cl.rows, cl.F, cl.Yatt,
+                                  cl.precision, n_mt, s);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sps

@@ -1,0 +1,234 @@
+// 16-bit library contraction with FP32 accumulation (BF16 or FP16 MFMA).
+// The library row k is stored as 2^{e_k} (H_k + R_k) and the weight row of point b
+// as 2^{e_b} 2^{-e_k} (W_h + W_l), both 16-bit hi + residual pairs.  The products
+// W_h H (main pass), W_h R and W_l H (one refinement pass over the residual terms)
+// accumulate into one FP32 accumulator; the dropped W_l R term is second order.
+#include "common.h"
+#include "kernels.h"
+
+namespace sps {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+struct ContractArgs16 {
+  const uint16_t *Wh, *Wl, *H, *R;
+  int K_pad, N_pad, n_tiles;
+  const int *tiles, *n_young, *n_act;
+  const PointRow *rows;
+  const float *lnlv, *da, *dd;
+  float *F, *Yatt;
+};
+
+__device__ __forceinline__ void tile_of_block16(int n_ntiles, int &mt, int &nt) {
+  const int nblk = gridDim.x, bid = blockIdx.x;
+  int logical = bid;
+  if ((nblk & 7) == 0) logical = (bid & 7) * (nblk >> 3) + (bid >> 3);
+  mt = logical / n_ntiles;
+  nt = logical - mt * n_ntiles;
+}
+
+template <bool BF, int PASSES>
+__device__ __forceinline__ v16f mfma16(const uint4 &a, const uint4 &b, v16f c) {
+  if constexpr (BF) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a), __builtin_bit_cast(v8h, b), c, 0, 0, 0);
+  }
+}
+
+// PASSES: 1 = W_h H; 2 = W_h H + W_h R; 3 = W_h H + W_h R + W_l H
+template <bool BF, int PASSES, int MT, int NT, int WM, int WN>
+__global__ void __launch_bounds__(256) k_contract_16(ContractArgs16 a) {
+  constexpr int KT = 64, LDSK = KT + 8;   // 16-bit elements per LDS row
+  constexpr int WTM = MT / WM, WTN = NT / WN, BM = WTM / 32, BN = WTN / 32;
+  constexpr bool USE_WL = PASSES >= 3, USE_R = PASSES >= 2;
+  constexpr int A8 = MT * KT / 8 / 256, B8 = NT * KT / 8 / 256;   // 16-byte chunks per thread
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[MT * LDSK];
+  __shared__ __attribute__((aligned(16))) uint16_t Al[USE_WL ? MT * LDSK : 8];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[NT * LDSK];
+  __shared__ __attribute__((aligned(16))) uint16_t Br[USE_R ? NT * LDSK : 8];
+  __shared__ float sp[MT][6];
+
+  int mt, nt;
+  tile_of_block16(a.N_pad / NT, mt, nt);
+  const int m0 = mt * MT, n0 = nt * NT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int li = lane & 31, lh = lane >> 5;
+  const int K_pad = a.K_pad;
+
+  for (int r = tid; r < MT; r += 256) {
+    const PointRow &pr = a.rows[m0 + r];
+    sp[r][0] = (float)pr.tau_bc;
+    sp[r][1] = (float)pr.alpha_bc;
+    sp[r][2] = (float)pr.tau_diff;
+    sp[r][3] = (float)pr.delta;
+    sp[r][4] = (float)(0.85 - 1.9 * pr.delta);
+    sp[r][5] = (float)pr.wscale;
+  }
+  v16f acc[BM][BN];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int nact = a.n_act[mt], ny = a.n_young[mt];
+  const int *tl = a.tiles + (size_t)mt * a.n_tiles;
+
+  uint4 rah[A8], ral[USE_WL ? A8 : 1], rbh[B8], rbr[USE_R ? B8 : 1];
+  auto gload = [&](int t) {
+    const int k0 = tl[t] * KT;
+#pragma unroll
+    for (int q = 0; q < A8; ++q) {
+      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;
+      const size_t o = (size_t)(m0 + row) * K_pad + k0 + c8 * 8;
+      rah[q] = *(const uint4 *)(a.Wh + o);
+      if constexpr (USE_WL) ral[q] = *(const uint4 *)(a.Wl + o);
+    }
+#pragma unroll
+    for (int q = 0; q < B8; ++q) {
+      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;
+      const size_t o = (size_t)(n0 + row) * K_pad + k0 + c8 * 8;
+      rbh[q] = *(const uint4 *)(a.H + o);
+      if constexpr (USE_R) rbr[q] = *(const uint4 *)(a.R + o);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int q = 0; q < A8; ++q) {
+      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;
+      *(uint4 *)(Ah + row * LDSK + c8 * 8) = rah[q];
+      if constexpr (USE_WL) *(uint4 *)(Al + row * LDSK + c8 * 8) = ral[q];
+    }
+#pragma unroll
+    for (int q = 0; q < B8; ++q) {
+      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;
+      *(uint4 *)(Bh + row * LDSK + c8 * 8) = rbh[q];
+      if constexpr (USE_R) *(uint4 *)(Br + row * LDSK + c8 * 8) = rbr[q];
+    }
+  };
+
+  float c_lnlv[BN], c_a[BN], c_d[BN];
+#pragma unroll
+  for (int j = 0; j < BN; ++j) {
+    const int col = n0 + wn * WTN + j * 32 + li;
+    c_lnlv[j] = a.lnlv[col];
+    c_a[j] = a.da[col];
+    c_d[j] = a.dd[col];
+  }
+  auto apply_bc = [&]() {
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          acc[i][j][e] *= __expf(-sp[rl][0] * __expf(sp[rl][1] * c_lnlv[j]));
+          if (a.Yatt) {
+            const float Td = __expf(-sp[rl][2] * __expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+            const int col = n0 + wn * WTN + j * 32 + li;
+            a.Yatt[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j][e] * Td * sp[rl][5];
+          }
+        }
+      }
+  };
+
+  __syncthreads();
+  if (nact > 0) gload(0);
+  for (int t = 0; t < nact; ++t) {
+    __syncthreads();
+    sstore();
+    __syncthreads();
+    if (t + 1 < nact) gload(t + 1);
+    if (t == ny) apply_bc();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kofs = lh * 32 + s * 8;
+      uint4 fa[BM], fl[BM], fb[BN], fr[BN];
+#pragma unroll
+      for (int i = 0; i < BM; ++i) {
+        const int row = wm * WTM + i * 32 + li;
+        fa[i] = *(const uint4 *)(Ah + row * LDSK + kofs);
+        if constexpr (USE_WL) fl[i] = *(const uint4 *)(Al + row * LDSK + kofs);
+      }
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        const int col = wn * WTN + j * 32 + li;
+        fb[j] = *(const uint4 *)(Bh + col * LDSK + kofs);
+        if constexpr (USE_R) fr[j] = *(const uint4 *)(Br + col * LDSK + kofs);
+      }
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          acc[i][j] = mfma16<BF, PASSES>(fa[i], fb[j], acc[i][j]);
+          if constexpr (USE_R) acc[i][j] = mfma16<BF, PASSES>(fa[i], fr[j], acc[i][j]);
+          if constexpr (USE_WL) acc[i][j] = mfma16<BF, PASSES>(fl[i], fb[j], acc[i][j]);
+        }
+    }
+  }
+  if (ny == nact) {
+    __syncthreads();
+    apply_bc();
+  }
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        const int col = n0 + wn * WTN + j * 32 + li;
+        const float Td = __expf(-sp[rl][2] * __expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+        a.F[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j][e] * Td * sp[rl][5];
+      }
+    }
+}
+
+struct ContractArgs;   // FP32/FP64 argument block (contract.hip)
+
+template <bool BF, int PASSES>
+static void launch16(const ContractArgs16 &a, int n_mt, int N_pad, hipStream_t s) {
+  hipLaunchKernelGGL((k_contract_16<BF, PASSES, 128, 128, 2, 2>), dim3(n_mt * (N_pad / 128)), dim3(256), 0, s, a);
+}
+
+hipError_t launch_contract16_impl(const DevLib &lib, const void *W, const void *Wlo, const int *tiles,
+                                  const int *n_young, const int *n_act, const PointRow *rows, void *F, void *Yatt,
+                                  int precision, int n_mt, hipStream_t s) {
+  ContractArgs16 a;
+  const bool bf = precision == 2 || precision == 4 || precision == 6;
+  a.Wh = (const uint16_t *)W;
+  a.Wl = (const uint16_t *)Wlo;
+  a.H = bf ? lib.Hb : lib.Hh;
+  a.R = bf ? lib.Rb : lib.Rh;
+  a.K_pad = lib.K_pad;
+  a.N_pad = lib.N_pad;
+  a.n_tiles = lib.K_pad / (kKTile * 2);
+  a.tiles = tiles;
+  a.n_young = n_young;
+  a.n_act = n_act;
+  a.rows = rows;
+  a.lnlv = lib.lnlv_f;
+  a.da = lib.dust_a_f;
+  a.dd = lib.dust_d_f;
+  a.F = (float *)F;
+  a.Yatt = (float *)Yatt;
+  if (!a.H || !a.R) return hipErrorInvalidValue;
+  switch (precision) {
+    case 2: launch16<true, 3>(a, n_mt, lib.N_pad, s); break;
+    case 3: launch16<false, 3>(a, n_mt, lib.N_pad, s); break;
+    case 4: launch16<true, 1>(a, n_mt, lib.N_pad, s); break;
+    case 5: launch16<false, 1>(a, n_mt, lib.N_pad, s); break;
+    case 6: launch16<true, 2>(a, n_mt, lib.N_pad, s); break;
+    case 7: launch16<false, 2>(a, n_mt, lib.N_pad, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sps

@@ -1,0 +1,75 @@
+// Host-side launchers of the gfx950 kernels (one declaration per kernel family).
+#pragma once
+#include "common.h"
+
+namespace sps {
+
+struct PrepLaunch {
+  const double *theta;
+  int P, B, B_pad;
+  const int *perm;
+  const DevObs *obs_table;
+  const int *point_obs;
+  void *W, *Wlo;
+  uint32_t *rowmask;
+  int mask_words;
+  PointRow *rows;
+  double *Lline;
+  const int *kpos;
+  int line_k0;
+  int mode;   // 0 f64, 1 f32, 2 bf16, 3 f16
+};
+
+size_t prep_smem_bytes(const DevLib &lib);
+hipError_t launch_sort(const DevLib &lib, const double *theta, int P, int B, int *perm, hipStream_t s);
+hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s);
+hipError_t launch_tiles(const uint32_t *rowmask, int mask_words, int B_pad, int MT, int n_tiles32, int young_tiles32,
+                        int tf, int *tiles, int *n_young, int *n_act, unsigned long long *counter, hipStream_t s);
+
+struct ContractLaunch {
+  const void *W, *Wlo;       // weights (hi/lo planes for 16-bit)
+  int B_pad;
+  const int *tiles, *n_young, *n_act;
+  const PointRow *rows;
+  void *F;                   // [B_pad][N_pad] attenuated rest-frame spectrum (float or double)
+  void *Yatt;                // optional [B_pad][N_pad]: young part after both attenuations
+  int precision;             // sps_precision value
+};
+// M tile used by the contraction of a precision (the occupancy list granularity)
+int contract_mtile(int precision);
+int contract_ktile_factor(int precision);   // K tile in units of kKTile
+hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStream_t s);
+
+struct ProjectLaunch {
+  const DevObs *obs_table;
+  const PointRow *rows;
+  const void *F;             // float or double [B_pad][N_pad]
+  int f64;
+  const double *theta;
+  int P, B;
+  const double *Lline;       // [B_pad][n_line]
+  double *model;             // [B][n_data] or NULL
+  double *logl;              // [B] or NULL
+  double *gvec;              // [B_pad][n_data_max] dlogL/dm (adjoint) or NULL
+  double *gnoise;            // [B][4] dlogL/d(noise params) or NULL
+  int ld_model;              // row stride of model
+  int ld_g;
+};
+hipError_t launch_project(const DevLib &lib, const ProjectLaunch &pl, hipStream_t s);
+
+// library packing
+struct PackLaunch {
+  const double *flux;        // [n_afe][n_z][n_age][N] raw
+  const double *lineprof;    // [n_line][N] per-A line profiles on the model grid
+  const int *ksrc;           // [K_pad]: >= 0 SSP flat index (ia*n_z + m)*n_age + a; -1-l line l; INT_MIN pad
+  int neb_mask;              // remove lambda < 912 A from nebular-covered ages
+  double *LT64;
+  float *LT32, *L32n;
+  uint16_t *Hb, *Rb, *Hh, *Rh;
+  int *kexp;
+  double *Q;                 // [n_afe][n_z][n_young]
+  const double *wave;        // [N]
+};
+hipError_t launch_pack(const DevLib &lib, const PackLaunch &pk, hipStream_t s);
+
+}  // namespace sps

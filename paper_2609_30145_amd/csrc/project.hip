@@ -1,0 +1,216 @@
+// Observer-frame projection (Sec. 2.6, App. E, App. F) and the diagonal Gaussian
+// log-likelihood with the noise floor (eq. 6, eq. G1).  One workgroup per sorted
+// row; the chi-squared sum is accumulated in FP64 and reduced in a fixed order.
+#include "common.h"
+#include "kernels.h"
+
+namespace sps {
+
+constexpr int kLineCut = 10;   // analytic line profiles evaluated within 10 sigma
+
+template <typename T>
+struct ProjArgs {
+  const DevObs *obs_table;
+  const PointRow *rows;
+  const T *F;
+  int N_pad, n_line;
+  const double *theta;
+  int P, B;
+  const double *Lline;
+  double *model, *logl, *gvec, *gnoise;
+  int ld_model, ld_g;
+};
+
+__device__ __forceinline__ double wave_reduce_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// sigma_inst(lambda_obs) in km/s for an LSF mode (eq. F2); `v` is the constant
+// or the curve value interpolated at lambda.
+__device__ double sigma_inst_mode(int mode, double v, double lam) {
+  switch (mode) {
+    case 0: return kC_kms / (2.3548200450309493 * v);   // R_fwhm
+    case 1: return kC_kms / v;                          // R_sigma
+    case 2: return kC_kms * v / (2.3548200450309493 * lam);
+    case 3: return kC_kms * v / lam;
+    case 4: return v;
+    default: return v / 2.3548200450309493;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
+  __shared__ double red[256];
+  __shared__ double s_lnl[512], s_sl[512], s_amp[512];   // per-line (spectra)
+  __shared__ double s_noise[4];
+  const int r = blockIdx.x;
+  const PointRow pr = a.rows[r];
+  if (pr.b < 0) return;
+  const DevObs ob = a.obs_table[pr.obs];
+  const int tid = threadIdx.x;
+  const double *th = a.theta + (size_t)pr.b * a.P;
+  const double z = pr.z, opz = 1.0 + z;
+  const T *Fr = a.F + (size_t)r * a.N_pad;
+  const int N = lib.N;
+
+  // noise-floor parameters (ln space)
+  if (tid == 0) {
+    s_noise[0] = (ob.noise_flags & 1) ? exp(th[TH_LOG_ERR_SCALE]) : 1.0;
+    s_noise[1] = (ob.noise_flags & 2) ? exp(th[TH_LOG_F_CALIB]) : 0.0;
+    s_noise[2] = (ob.noise_flags & 4) ? exp(th[TH_LOG_F_DATA]) : 0.0;
+    s_noise[3] = (ob.noise_flags & 8) ? exp(th[TH_LOG_JITTER]) : 0.0;
+  }
+  __syncthreads();
+  const double ns = s_noise[0], fc = s_noise[1], fd = s_noise[2], jt = s_noise[3];
+  double lsum = 0.0;
+  double gs[4] = {0.0, 0.0, 0.0, 0.0};
+
+  auto datum = [&](int i, double m) {
+    if (a.model) a.model[(size_t)pr.b * a.ld_model + i] = m;
+    double g = 0.0;
+    if (ob.mask[i]) {
+      const double d = ob.data[i], sg = ob.sigma[i];
+      const double v = ns * ns * sg * sg + fc * fc * m * m + fd * fd * d * d + jt * jt;
+      const double res = d - m;
+      lsum += -0.5 * res * res / v - 0.5 * log(2.0 * kPi * v);
+      // d logL / d v and d logL / d m (App. G terms)
+      const double dv = 0.5 * res * res / (v * v) - 0.5 / v;
+      g = res / v + dv * 2.0 * fc * fc * m;
+      gs[0] += dv * 2.0 * ns * ns * sg * sg;   // d/d ln s
+      gs[1] += dv * 2.0 * fc * fc * m * m;     // d/d ln f_calib
+      gs[2] += dv * 2.0 * fd * fd * d * d;     // d/d ln f_data
+      gs[3] += dv * 2.0 * jt * jt;             // d/d ln j
+    }
+    if (a.gvec) a.gvec[(size_t)r * a.ld_g + i] = g;
+  };
+
+  if (ob.kind == 0) {
+    // ---------------- photometry (eq. E1-E2): f_lambda^obs(lambda_j) = fac * F(lambda_j/(1+z))
+    const double fac = kC_cms * pr.scale_fnu / (opz * opz * kAng_cm * kAng_cm);
+    const int wave_id = tid >> 6, lane = tid & 63;
+    for (int band = wave_id; band < ob.n_band; band += 4) {
+      const int j0 = ob.band_off[band], j1 = ob.band_off[band + 1];
+      T part = (T)0;
+      for (int j = j0 + lane; j < j1; j += 64) {
+        const double lr = ob.fw[j] / opz;
+        if (lr < lib.wave_d[0] || lr > lib.wave_d[N - 1]) continue;
+        const int k = bracket(lib.wave_d, N, lr);
+        const T t = (T)((lr - lib.wave_d[k]) / (lib.wave_d[k + 1] - lib.wave_d[k]));
+        const T f = Fr[k] + t * (Fr[k + 1] - Fr[k]);
+        const T w = sizeof(T) == 8 ? (T)ob.fr_d[j] : (T)ob.fr_f[j];
+        part += w * f;
+      }
+      double s = wave_reduce_sum((double)part);
+      if (lane == 0) red[band] = s;
+    }
+    __syncthreads();
+    for (int band = tid; band < ob.n_band; band += 256) datum(band, fac * red[band]);
+  } else {
+    // ---------------- spectrum (eq. F5-F6)
+    const double lnopz = log1p(z);
+    const int nl = a.n_line;
+    if (nl > 0) {
+      const double Tfac = pr.mass10 / (4.0 * kPi * pr.dl * pr.dl);
+      for (int l = tid; l < nl; l += 256) {
+        const double lw = lib.line_wave[l];
+        const double lnlv = log(lw / kLamV);
+        const double tau = pr.tau_bc * exp(pr.alpha_bc * lnlv) +
+                           pr.tau_diff * exp(pr.delta * lnlv) * (lib.line_a[l] + (0.85 - 1.9 * pr.delta) * lib.line_d[l]);
+        const double Fl = a.Lline[(size_t)r * nl + l] * exp(-tau) * Tfac;
+        const double lobs = opz * lw;
+        double v = ob.lsf_value;
+        if (ob.has_curve) {
+          const int np = ob.n_data;
+          const double lc = fmin(fmax(lobs, ob.pix[0]), ob.pix[np - 1]);
+          const int k = bracket(ob.pix, np, lc);
+          const double t = (lc - ob.pix[k]) / (ob.pix[k + 1] - ob.pix[k]);
+          v = ob.lsf_vals[k] + t * (ob.lsf_vals[k + 1] - ob.lsf_vals[k]);
+        }
+        const double si = sigma_inst_mode(ob.lsf_mode, v, lobs);
+        const double sl = sqrt(ob.sigma_gas_kms * ob.sigma_gas_kms + si * si) / kC_kms;
+        s_lnl[l] = log(lobs);
+        s_sl[l] = sl;
+        s_amp[l] = Fl / (2.5066282746310002 * sl);
+      }
+      __syncthreads();
+    }
+    double slmax = 0.0;
+    for (int l = 0; l < nl; ++l) slmax = fmax(slmax, s_sl[l]);
+    const double lnw0 = lib.lnwave_d[0], lnw1 = lib.lnwave_d[N - 1];
+    for (int i = tid; i < ob.n_data; i += 256) {
+      const double x = ob.lnpix[i] - lnopz;
+      T cont = (T)0;
+      if (x >= lnw0 && x <= lnw1) {
+        const double s = ob.ksig[i];
+        const int k = bracket(lib.lnwave_d, N, x);
+        const double dk = lib.lnwave_d[k + 1] - lib.lnwave_d[k];
+        if (s < 0.5 * dk) {
+          const T t = (T)((x - lib.lnwave_d[k]) / dk);
+          const T fk = Fr[k] * (T)lib.lam2_d[k], fk1 = Fr[k + 1] * (T)lib.lam2_d[k + 1];
+          cont = fk + t * (fk1 - fk);
+        } else {
+          int j = lower_bound_dev(lib.lnwave_d, N, x - 5.0 * s);
+          const double inv = 1.0 / s;
+          T num = (T)0, den = (T)0;
+          for (; j < N; ++j) {
+            const double u = (lib.lnwave_d[j] - x) * inv;
+            if (u > 5.0) break;
+            const T w = sizeof(T) == 8 ? (T)exp(-0.5 * u * u) : (T)__expf((float)(-0.5 * u * u));
+            num += w * (Fr[j] * (T)lib.lam2_d[j]);
+            den += w;
+          }
+          cont = num / den;
+        }
+      }
+      double m = pr.scale_fnu * (double)cont;
+      if (nl > 0) {
+        const double lp = ob.lnpix[i];
+        // lines sorted by wavelength: window of ln(lambda_obs) within kLineCut * s_max
+        int l = lower_bound_dev(s_lnl, nl, lp - kLineCut * slmax);
+        double lines = 0.0;
+        for (; l < nl && s_lnl[l] <= lp + kLineCut * slmax; ++l) {
+          const double u = (lp - s_lnl[l]) / s_sl[l];
+          lines += s_amp[l] * exp(-0.5 * u * u);
+        }
+        m += lines * ob.pix[i] * kAng_cm / kC_cms;
+      }
+      datum(i, m / kFnuAB);
+    }
+  }
+  // fixed-order block reduction of logL (and the noise-parameter gradients)
+  red[tid] = lsum;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0 && a.logl) a.logl[pr.b] = red[0];
+  if (a.gnoise) {
+    for (int q = 0; q < 4; ++q) {
+      __syncthreads();
+      red[tid] = gs[q];
+      __syncthreads();
+      for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+      }
+      if (tid == 0) a.gnoise[(size_t)pr.b * 4 + q] = red[0];
+    }
+  }
+}
+
+hipError_t launch_project(const DevLib &lib, const ProjectLaunch &pl, hipStream_t s) {
+  if (pl.f64) {
+    ProjArgs<double> a{pl.obs_table, pl.rows, (const double *)pl.F, lib.N_pad, lib.n_line, pl.theta, pl.P, pl.B,
+                       pl.Lline, pl.model, pl.logl, pl.gvec, pl.gnoise, pl.ld_model, pl.ld_g};
+    hipLaunchKernelGGL(k_project<double>, dim3(pl.B), dim3(256), 0, s, lib, a);
+  } else {
+    ProjArgs<float> a{pl.obs_table, pl.rows, (const float *)pl.F, lib.N_pad, lib.n_line, pl.theta, pl.P, pl.B,
+                      pl.Lline, pl.model, pl.logl, pl.gvec, pl.gnoise, pl.ld_model, pl.ld_g};
+    hipLaunchKernelGGL(k_project<float>, dim3(pl.B), dim3(256), 0, s, lib, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sps

@@ -1,0 +1,171 @@
+// Observation operators, workspaces and contraction timing.
+#include "runtime.h"
+
+#include <cstring>
+
+#include "kernels.h"
+
+using namespace sps;
+
+void sps_library::host_wave(std::vector<double> &w) const {
+  w.resize(N);
+  (void)hipMemcpy(w.data(), dev.wave_d, (size_t)N * 8, hipMemcpyDeviceToHost);
+}
+
+sps_status Workspace::create(const sps_library *L, int mb, int n_data) {
+  const DevLib &g = L->dev;
+  max_batch = mb;
+  B_pad_max = (mb + kMAlign - 1) / kMAlign * kMAlign;
+  const size_t Bp = B_pad_max;
+  mask_words = (g.K_pad / kKTile + 31) / 32;
+  bool ok = true;
+  auto al = [&](size_t n) {
+    void *p = mem.alloc(n);
+    ok = ok && p;
+    return p;
+  };
+  perm = (int *)al(Bp * 4);
+  W = al(Bp * g.K_pad * 8);
+  rowmask = (uint32_t *)al(Bp * mask_words * 4);
+  const size_t n_mt = Bp / 64, n_kt = g.K_pad / kKTile;
+  tiles = (int *)al(n_mt * n_kt * 4);
+  n_young = (int *)al(n_mt * 4);
+  n_act = (int *)al(n_mt * 4);
+  rows = (PointRow *)al(Bp * sizeof(PointRow));
+  F = al(Bp * g.N_pad * 8);
+  Yatt = al(Bp * g.N_pad * 8);
+  Lline = (double *)al(Bp * (size_t)std::max(1, g.n_line) * 8);
+  gvec = (double *)al(Bp * (size_t)std::max(1, n_data) * 8);
+  gnoise = (double *)al(Bp * 4 * 8);
+  gbuf = (double *)al(Bp * 64 * 8);
+  G = al(Bp * g.N_pad * 8 * 2);
+  dW = al(Bp * g.K_pad * 8);
+  counter = (unsigned long long *)al(8);
+  if (!ok) return fail(SPS_E_NOMEM, "workspace allocation failed (max_batch=%d)", mb);
+  if (hipMemset(counter, 0, 8) != hipSuccess) return fail(SPS_E_HIP, "hipMemset failed");
+  return SPS_OK;
+}
+
+sps_obs::~sps_obs() {
+  for (auto e : ev_start) (void)hipEventDestroy(e);
+  for (auto e : ev_stop) (void)hipEventDestroy(e);
+}
+
+sps_status sps_obs::upload_operators() {
+  DevObs &o = dobs;
+  memset(&o, 0, sizeof o);
+  o.kind = host.kind;
+  o.n_data = host.n_data;
+  o.noise_flags = host.noise_flags;
+  bool ok = true;
+  auto up = [&](const void *h, size_t n) {
+    void *p = opmem.upload(h, n);
+    ok = ok && p;
+    return p;
+  };
+  if (host.kind == SPS_OBS_PHOT) {
+    o.n_band = host.n_data;
+    o.n_fnodes = (int)host.fw.size();
+    o.band_off = (const int *)up(host.band_off.data(), host.band_off.size() * 4);
+    o.fw = (const double *)up(host.fw.data(), host.fw.size() * 8);
+    o.fr_d = (const double *)up(host.fr.data(), host.fr.size() * 8);
+    std::vector<float> frf(host.fr.begin(), host.fr.end());
+    o.fr_f = (const float *)up(frf.data(), frf.size() * 4);
+  } else {
+    o.pix = (const double *)up(host.pix.data(), host.pix.size() * 8);
+    o.lnpix = (const double *)up(host.lnpix.data(), host.lnpix.size() * 8);
+    o.ksig = (const double *)up(host.ksig.data(), host.ksig.size() * 8);
+    o.lsf_mode = host.lsf_mode;
+    o.lsf_value = host.lsf_value;
+    o.has_curve = host.lsf_vals.empty() ? 0 : 1;
+    if (o.has_curve) o.lsf_vals = (const double *)up(host.lsf_vals.data(), host.lsf_vals.size() * 8);
+    o.sigma_gas_kms = host.sigma_gas;
+  }
+  if (!ok) return fail(SPS_E_NOMEM, "observation upload failed");
+  // data buffers are allocated once; later updates copy into them
+  o.data = (const double *)datamem.alloc((size_t)host.n_data * 8);
+  o.sigma = (const double *)datamem.alloc((size_t)host.n_data * 8);
+  o.mask = (const uint8_t *)datamem.alloc((size_t)host.n_data);
+  dev_obs = (DevObs *)opmem.alloc(sizeof(DevObs));
+  if (!o.data || !o.sigma || !o.mask || !dev_obs) return fail(SPS_E_NOMEM, "observation upload failed");
+  return upload_data();
+}
+
+sps_status sps_obs::upload_data() {
+  const size_t n = host.n_data;
+  hipError_t e = hipMemcpy((void *)dobs.data, host.data.data(), n * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy((void *)dobs.sigma, host.sigma.data(), n * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy((void *)dobs.mask, host.mask.data(), n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dev_obs, &dobs, sizeof(DevObs), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(SPS_E_HIP, "observation data upload failed: %s", hipGetErrorString(e));
+  return SPS_OK;
+}
+
+// ---------------------------------------------------------------- timing
+static constexpr size_t kEvents = 64;
+
+sps_status sps_obs::enable_timing(bool on) {
+  if (on && ev_start.empty()) {
+    ev_start.resize(kEvents);
+    ev_stop.resize(kEvents);
+    for (size_t i = 0; i < kEvents; ++i) {
+      if (hipEventCreate(&ev_start[i]) != hipSuccess || hipEventCreate(&ev_stop[i]) != hipSuccess)
+        return fail(SPS_E_HIP, "hipEventCreate failed");
+    }
+  }
+  timing = on;
+  ev_next = ev_pending = 0;
+  ms_total = 0;
+  launches = dense_tiles = 0;
+  if (hipMemset(ws.counter, 0, 8) != hipSuccess) return fail(SPS_E_HIP, "hipMemset failed");
+  return SPS_OK;
+}
+
+hipError_t sps_obs::timing_begin(hipStream_t s, int n_mtiles, int n_ktiles) {
+  if (!timing) return hipSuccess;
+  const size_t i = ev_next % kEvents;
+  if (ev_pending >= kEvents) {   // reuse the oldest pair: fold its time in first
+    float ms = 0;
+    hipError_t e = hipEventSynchronize(ev_stop[i]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev_start[i], ev_stop[i]);
+    if (e != hipSuccess) return e;
+    ms_total += ms;
+    --ev_pending;
+  }
+  dense_tiles += (int64_t)n_mtiles * n_ktiles;
+  return hipEventRecord(ev_start[i], s);
+}
+
+hipError_t sps_obs::timing_end(hipStream_t s) {
+  if (!timing) return hipSuccess;
+  const size_t i = ev_next % kEvents;
+  hipError_t e = hipEventRecord(ev_stop[i], s);
+  ++ev_next;
+  ++ev_pending;
+  ++launches;
+  return e;
+}
+
+sps_status sps_obs::read_timing(double *ms, int64_t *nl, int64_t *exec_tiles, int64_t *dense) {
+  if (!timing) return fail(SPS_E_STATE, "timing is not enabled on this observation");
+  while (ev_pending > 0) {
+    const size_t i = (ev_next - ev_pending) % kEvents;
+    float t = 0;
+    hipError_t e = hipEventSynchronize(ev_stop[i]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, ev_start[i], ev_stop[i]);
+    if (e != hipSuccess) return fail(SPS_E_HIP, "event timing failed: %s", hipGetErrorString(e));
+    ms_total += t;
+    --ev_pending;
+  }
+  unsigned long long c = 0;
+  if (hipMemcpy(&c, ws.counter, 8, hipMemcpyDeviceToHost) != hipSuccess) return fail(SPS_E_HIP, "counter read failed");
+  if (ms) *ms = ms_total;
+  if (nl) *nl = launches;
+  if (exec_tiles) *exec_tiles = (int64_t)c;
+  if (dense) *dense = dense_tiles;
+  ms_total = 0;
+  launches = dense_tiles = 0;
+  ev_next = ev_pending = 0;
+  if (hipMemset(ws.counter, 0, 8) != hipSuccess) return fail(SPS_E_HIP, "hipMemset failed");
+  return SPS_OK;
+}

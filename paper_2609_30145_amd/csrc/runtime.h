@@ -1,0 +1,99 @@
+// Host-side objects behind the C ABI handles.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sps.h"
+#include "common.h"
+
+namespace sps {
+
+sps_status fail(sps_status code, const char *fmt, ...);
+
+// Owns a set of device allocations.
+struct DeviceBuffers {
+  std::vector<void *> ptrs;
+  int64_t bytes = 0;
+  ~DeviceBuffers();
+  void release();
+  void *alloc(size_t n);
+  void *upload(const void *h, size_t n);
+};
+
+// Per-observation workspace, sized once for max_batch rows.
+struct Workspace {
+  DeviceBuffers mem;
+  int max_batch = 0, B_pad_max = 0, mask_words = 0;
+  int *perm = nullptr;
+  void *W = nullptr;             // B_pad * K_pad * 8 bytes
+  uint32_t *rowmask = nullptr;
+  int *tiles = nullptr, *n_young = nullptr, *n_act = nullptr;
+  PointRow *rows = nullptr;
+  void *F = nullptr, *Yatt = nullptr;   // B_pad * N_pad * 8 bytes each
+  double *Lline = nullptr;
+  double *gvec = nullptr, *gnoise = nullptr;
+  double *gbuf = nullptr;        // adjoint scratch (see adjoint.hip)
+  void *G = nullptr;             // adjoint [B_pad][N_pad] float/double
+  void *dW = nullptr;            // adjoint [B_pad][K_pad] float/double
+  unsigned long long *counter = nullptr;
+  sps_status create(const sps_library *L, int max_batch, int n_data);
+};
+
+// Host copy of an observation's fixed operators and data.
+struct ObsHost {
+  int kind = 0, n_data = 0, noise_flags = 0, lsf_mode = 0;
+  std::vector<int> band_off;
+  std::vector<double> fw, fr;
+  std::vector<double> pix, lnpix, ksig, lsf_vals;
+  double lsf_value = 0, sigma_gas = 0;
+  std::vector<double> data, sigma;
+  std::vector<uint8_t> mask;
+};
+
+sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsHost &h, uint32_t *warnings);
+sps_status set_obs_data(ObsHost &h, const double *data, const double *sigma, const uint8_t *mask);
+
+}  // namespace sps
+
+struct sps_library {
+  int device = 0;
+  int n_age = 0, n_z = 0, n_afe = 0, N = 0, n_young = 0, n_line = 0, n_sfh = 0, n_zh = 0;
+  int line_k0 = 0;
+  uint32_t precisions = 0;
+  sps::DevLib dev;
+  int *kpos_d = nullptr;
+  sps::DeviceBuffers mem;
+  void host_wave(std::vector<double> &w) const;   // copies wave[N] from the device
+};
+
+struct sps_obs {
+  const sps_library *lib = nullptr;
+  sps::ObsHost host;
+  sps::DevObs dobs;
+  sps::DevObs *dev_obs = nullptr;
+  sps::DeviceBuffers opmem;        // operators
+  sps::DeviceBuffers datamem;      // data, sigma, mask
+  sps::Workspace ws;
+  // contraction timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  size_t ev_next = 0, ev_pending = 0;
+  double ms_total = 0;
+  int64_t launches = 0, dense_tiles = 0, dense_per_launch = 0;
+  ~sps_obs();
+  sps_status upload_operators();
+  sps_status upload_data();
+  sps_status enable_timing(bool on);
+  hipError_t timing_begin(hipStream_t s, int n_mtiles, int n_ktiles);
+  hipError_t timing_end(hipStream_t s);
+  sps_status read_timing(double *ms, int64_t *launches, int64_t *exec_tiles, int64_t *dense_tiles);
+};
+
+namespace sps {
+sps_status run_forward(const sps_library *L, sps_obs *o, const double *theta, int B, int prec, double *logl,
+                       double *model, bool want_grad_buffers, hipStream_t s);
+sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, int B, int prec, double *grad,
+                       hipStream_t s);
+}  // namespace sps

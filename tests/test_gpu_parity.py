@@ -1,0 +1,201 @@
+"""GPU parity: the HIP path against the FP64 oracle on the same seeded inputs.
+
+Tolerances (per output, relative to |ref| + 1e-3 max|ref| of the row):
+  FP64 instance 1e-12; FP32 path 1e-5; BF16/FP16 + residual pass 2e-3 per band.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import gpu_objects, make_case, rel_err
+from oracle import model as om
+from synth import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2609_30145_amd as sps  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(L, O, theta, precision):
+    th = torch.tensor(theta, dtype=torch.float64, device="cuda")
+    ll, m = sps.logl(L, O, th, precision, return_model=True)
+    torch.cuda.synchronize()
+    return ll.cpu().numpy(), m.cpu().numpy()
+
+
+def oracle_run(case, idx=None):
+    th = case["theta"] if idx is None else case["theta"][idx]
+    m = om.predict(case["olib"], case["obs"], th)
+    return om.logl(case["olib"], case["obs"], th, model=m), m
+
+
+# ------------------------------------------------------------------------------ c0
+@pytest.fixture(scope="module")
+def c0():
+    case = make_case(wl.CONFIGS["c0"])
+    L, O = gpu_objects(case, precisions=("fp64", "fp32", "bf16", "fp16"))
+    ll, m = oracle_run(case)
+    return case, L, O, ll, m
+
+
+def test_c0_fp64_matches_oracle_to_1e12(c0):
+    case, L, O, ll_ref, m_ref = c0
+    say("c0 fp64 B=64")
+    ll, m = gpu_run(L, O, case["theta"], "fp64")
+    assert rel_err(m, m_ref).max() < 1e-12
+    assert np.all(np.abs(ll - ll_ref) <= 1e-10 * np.maximum(1.0, np.abs(ll_ref)))
+
+
+def test_c0_fp32_matches_oracle_to_1e5(c0):
+    case, L, O, ll_ref, m_ref = c0
+    say("c0 fp32 B=64")
+    ll, m = gpu_run(L, O, case["theta"], "fp32")
+    e = rel_err(m, m_ref)
+    say(f"  max rel err {e.max():.3e}")
+    assert e.max() < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16_hr", "fp16_hr"])
+def test_c0_low_precision_within_2e3(c0, prec):
+    case, L, O, ll_ref, m_ref = c0
+    say(f"c0 {prec} B=64")
+    ll, m = gpu_run(L, O, case["theta"], prec)
+    e = rel_err(m, m_ref)
+    say(f"  max rel err {e.max():.3e}")
+    assert e.max() < 2e-3
+
+
+# ------------------------------------------------------------------------------ c1 (reduced grid)
+@pytest.fixture(scope="module")
+def c1s():
+    cfg = wl.reduced(wl.CONFIGS["c1"], n_age=40, logz=tuple(np.linspace(-2.5, 0.5, 8)), n_wave=1500,
+                     n_sfh=30, n_zh=6, n_lines=24)
+    case = make_case(cfg, B=200)
+    L, O = gpu_objects(case, precisions=("fp64", "fp32", "bf16", "fp16"), max_batch=256)
+    ll, m = oracle_run(case)
+    return case, L, O, ll, m
+
+
+def test_c1_reduced_fp64_ragged_batch(c1s):
+    case, L, O, ll_ref, m_ref = c1s
+    say("c1-reduced fp64 B=200")
+    ll, m = gpu_run(L, O, case["theta"], "fp64")
+    assert rel_err(m, m_ref).max() < 1e-12
+    assert np.all(np.abs(ll - ll_ref) <= 1e-10 * np.maximum(1.0, np.abs(ll_ref)))
+
+
+def test_c1_reduced_fp32(c1s):
+    case, L, O, ll_ref, m_ref = c1s
+    say("c1-reduced fp32 B=200")
+    ll, m = gpu_run(L, O, case["theta"], "fp32")
+    e = rel_err(m, m_ref)
+    say(f"  max rel err {e.max():.3e}")
+    assert e.max() < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_c1_reduced_low_precision(c1s, prec):
+    case, L, O, ll_ref, m_ref = c1s
+    say(f"c1-reduced {prec} B=200")
+    ll, m = gpu_run(L, O, case["theta"], prec)
+    e = rel_err(m, m_ref)
+    say(f"  max rel err {e.max():.3e}")
+    assert e.max() < 2e-3
+
+
+def test_batch_edges_single_point_and_composition(c1s):
+    case, L, O, ll_ref, m_ref = c1s
+    say("c1-reduced fp32 B=1 and a permuted batch")
+    ll_all, m_all = gpu_run(L, O, case["theta"], "fp32")
+    ll1, m1 = gpu_run(L, O, case["theta"][7:8], "fp32")
+    assert rel_err(m1, m_ref[7:8]).max() < 1e-5
+    perm = np.random.default_rng(0).permutation(200)
+    llp, mp = gpu_run(L, O, case["theta"][perm], "fp32")
+    # the row result does not depend on the batch it is in (skipped tiles add exact zeros)
+    assert np.array_equal(mp, m_all[perm])
+    assert np.array_equal(llp, ll_all[perm])
+    ll2, m2 = gpu_run(L, O, case["theta"], "fp32")
+    assert np.array_equal(m2, m_all) and np.array_equal(ll2, ll_all)
+
+
+def test_batch_larger_than_workspace_is_rejected(c1s):
+    case, L, O, _, _ = c1s
+    th = torch.zeros((257, L.P), dtype=torch.float64, device="cuda")
+    with pytest.raises(sps.SpsError) as ei:
+        sps.logl(L, O, th, "fp32")
+    assert ei.value.code == -2
+
+
+# ------------------------------------------------------------------------------ spectra (reduced)
+@pytest.fixture(scope="module")
+def specs():
+    cfg = wl.reduced(wl.CONFIGS["c3"], n_age=40, logz=tuple(np.linspace(-2.5, 0.5, 8)), n_wave=1500,
+                     n_sfh=30, n_zh=6, n_lines=24, n_pix=400)
+    case = make_case(cfg, B=40)
+    L, O = gpu_objects(case, precisions=("fp64", "fp32"))
+    ll, m = oracle_run(case)
+    return case, L, O, ll, m
+
+
+def test_spectrum_fp64(specs):
+    case, L, O, ll_ref, m_ref = specs
+    say("spec-reduced fp64 B=40")
+    ll, m = gpu_run(L, O, case["theta"], "fp64")
+    e = rel_err(m, m_ref)
+    say(f"  max rel err {e.max():.3e}")
+    assert e.max() < 1e-11
+    assert np.all(np.abs(ll - ll_ref) <= 1e-9 * np.maximum(1.0, np.abs(ll_ref)))
+
+
+def test_spectrum_fp32(specs):
+    case, L, O, ll_ref, m_ref = specs
+    say("spec-reduced fp32 B=40")
+    ll, m = gpu_run(L, O, case["theta"], "fp32")
+    e = rel_err(m, m_ref)
+    say(f"  max rel err {e.max():.3e}")
+    assert e.max() < 1e-5
+
+
+def test_bare_resolving_power_rejected(specs):
+    case, L, O, _, _ = specs
+    with pytest.raises(sps.SpsError) as ei:
+        sps.Observation(L, "spec", 4, pix_wave=case["obs"].pix_wave, lsf_mode="R", lsf_value=100.0)
+    assert ei.value.code == -1
+
+
+# ------------------------------------------------------------------------------ full-size c1
+@pytest.fixture(scope="module")
+def c1full():
+    case = make_case(wl.CONFIGS["c1"])
+    L, O = gpu_objects(case, precisions=("fp32", "bf16", "fp16"))
+    ll, m = oracle_run(case)
+    return case, L, O, ll, m
+
+
+def test_c1_full_fp32(c1full):
+    case, L, O, ll_ref, m_ref = c1full
+    say("c1 fp32 B=1024 full size")
+    ll, m = gpu_run(L, O, case["theta"], "fp32")
+    e = rel_err(m, m_ref)
+    say(f"  max rel err {e.max():.3e}  max |dlogL|/|logL| {np.max(np.abs(ll - ll_ref) / np.abs(ll_ref)):.3e}")
+    assert e.max() < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_c1_full_low_precision(c1full, prec):
+    case, L, O, ll_ref, m_ref = c1full
+    say(f"c1 {prec} B=1024 full size")
+    ll, m = gpu_run(L, O, case["theta"], prec)
+    e = rel_err(m, m_ref)
+    say(f"  max rel err {e.max():.3e}")
+    assert e.max() < 2e-3
