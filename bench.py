@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched SPS forward model + logL on one MI355X.
+
+A step is one sps_logl call over a batch of 1024 live points of the full-size
+photometric workload (library 107 ages x 22 metallicities x 5994 wavelengths,
+120-bin SFH with a 24-node enrichment history, two-component dust, 128 nebular
+lines, 20 filters): sort + weights + K-tile lists + library contraction (fused
+attenuation) + projection + FP64 chi-squared.  Inputs are resident in HBM.
+
+Prints one JSON line.  The roofline entry is for the library contraction, timed
+with HIP events recorded around that kernel on the stream it runs on.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16_hr": 2500.0,
+               "fp16_hr": 2500.0, "bf16_1pass": 2500.0, "fp16_1pass": 2500.0}
+MFMA_PASSES = {"fp32": 1, "fp64": 1, "bf16": 3, "fp16": 3, "bf16_hr": 2, "fp16_hr": 2, "bf16_1pass": 1,
+               "fp16_1pass": 1}
+DTYPE = {"fp32": "f32", "fp64": "f64", "bf16": "bf16 (f32 accumulate, residual pass)",
+         "fp16": "f16 (f32 accumulate, residual pass)", "bf16_hr": "bf16", "fp16_hr": "f16",
+         "bf16_1pass": "bf16", "fp16_1pass": "f16"}
+
+
+def build_workload(cfg_name, precisions, seed=0):
+    import torch
+
+    import paper_2609_30145_amd as sps
+    from synth import workloads as wl
+    cfg = wl.CONFIGS[cfg_name]
+    lib = wl.make_library(cfg, seed)
+    lines = wl.make_lines(cfg, lib, seed + 1)
+    dust = wl.make_dust_tables(cfg, lib["wave"])
+    L = sps.Library(lib, n_sfh=cfg.n_sfh, T1=cfg.T1, n_zh=cfg.n_zh, cosmo=cfg.cosmo, dust=dust, lines=lines,
+                    precisions=precisions)
+    filters = wl.make_filters(cfg.filters)
+    O = sps.Observation(L, "phot", cfg.batch, filters=filters)
+    # data: the GPU model at a reference point plus 5 % noise
+    th_true = torch.tensor(wl.make_theta(cfg, 1, seed=seed + 1002), device="cuda")
+    m_true = sps.forward(L, O, th_true, "fp32")[0].cpu().numpy()
+    d, s = wl.noisy_photometry(m_true, seed + 5)
+    O.set_data(d, s)
+    theta = torch.tensor(wl.make_theta(cfg, cfg.batch, seed=seed + 2), device="cuda")
+    return cfg, lib, lines, dust, L, O, theta
+
+
+def time_precision(L, O, theta, prec, steps, warmup):
+    import torch
+
+    import paper_2609_30145_amd as sps
+    for _ in range(warmup):
+        sps.logl(L, O, theta, prec)
+    torch.cuda.synchronize()
+    O.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sps.logl(L, O, theta, prec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tim = O.contract_timing()
+    O.enable_timing(False)
+    return (t1 - t0), tim
+
+
+def cpu_baseline(cfg_name, budget_s=12.0, seed=0):
+    """The FP64 oracle (as it stands) on the host cores over a bounded sample."""
+    from oracle import model as om
+    from synth import workloads as wl
+    cfg = wl.CONFIGS[cfg_name]
+    lib = wl.make_library(cfg, seed)
+    lines = wl.make_lines(cfg, lib, seed + 1)
+    dust = wl.make_dust_tables(cfg, lib["wave"])
+    olib = om.build_library(cfg, lib, lines, dust)
+    obs = om.Photometry(filters=wl.make_filters(cfg.filters))
+    th_true = wl.make_theta(cfg, 1, seed=seed + 1002)
+    obs.data, obs.sigma = wl.noisy_photometry(om.predict(olib, obs, th_true)[0], seed + 5)
+    theta = wl.make_theta(cfg, cfg.batch, seed=seed + 2)
+    sample = 256
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        th = theta[(n % cfg.batch):(n % cfg.batch) + sample]
+        om.logl(olib, obs, th)
+        n += len(th)
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    return dict(value=n / dt, unit="evals/s", cores=int(cores), kind="oracle",
+                sample=f"{n} parameter vectors of the same workload in batches of {sample} "
+                       f"(FP64 NumPy, BLAS dgemm contraction), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp16")
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--also", default="fp32,bf16", help="other precisions timed for the record")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    precs = [args.precision] + [p for p in args.also.split(",") if p and p != args.precision]
+    cfg, lib, lines, dust, L, O, theta = build_workload(args.workload, tuple(precs))
+    B = theta.shape[0]
+    K_dense = cfg.n_age * len(cfg.logz) * len(cfg.afe)
+    N = cfg.n_wave
+    flop_per_eval = 2.0 * K_dense * N          # dense sum over the SSP grid (eq. 1)
+    results = {}
+    for p in precs:
+        steps = args.steps if p == args.precision else max(10, args.steps // 5)
+        dt, tim = time_precision(L, O, theta, p, steps, args.warmup)
+        avg_ms = tim["ms_total"] / max(1, tim["launches"])
+        frac_exec = tim["executed_k_tiles"] / max(1, tim["dense_k_tiles"])
+        K_pad = L.info["K_pad"]
+        exec_flops = 2.0 * B_pad(B) * K_pad * L.info["N_pad"] * frac_exec * MFMA_PASSES[p]
+        results[p] = dict(ms_per_step=1e3 * dt / steps, evals_per_s=B * steps / dt, contract_ms=avg_ms,
+                          contract_alg_tflops=flop_per_eval * B / (avg_ms * 1e-3) / 1e12,
+                          contract_exec_tflops=exec_flops / (avg_ms * 1e-3) / 1e12,
+                          active_k_tile_frac=frac_exec, steps=steps)
+    main_r = results[args.precision]
+    peak = PEAK_TFLOPS[args.precision]
+    roof = {"bound": "mfma", "achieved": round(main_r["contract_alg_tflops"], 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(main_r["contract_alg_tflops"] / peak, 4), "traffic": None,
+            "executed_mfma_tflops": round(main_r["contract_exec_tflops"], 3),
+            "executed_frac": round(main_r["contract_exec_tflops"] / peak, 4),
+            "kernel": "library contraction (k_contract)", "contract_ms": round(main_r["contract_ms"], 4),
+            "alg_flop_per_eval": flop_per_eval, "active_k_tile_frac": round(main_r["active_k_tile_frac"], 4)}
+    out = {
+        "metric": "forward-model evals/s at 1024 live pts (low-prec vs FP32 plain); served p50/p99",
+        "value": round(main_r["evals_per_s"], 1),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": main_r["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": round(main_r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.precision],
+        "data": "synthetic (seeded SSP library, filters, line tables and parameter draws)",
+        "config": {"workload": f"{args.workload}: {B} live points, library {cfg.n_age} ages x {len(cfg.logz)} Z x "
+                               f"{len(cfg.afe)} afe x {N} wavelengths, {cfg.n_sfh}-bin SFH, {cfg.n_zh}-node ZH, "
+                               f"two-component dust, {cfg.n_lines} lines, photometry ({cfg.filters})",
+                   "batch": B, "precision": args.precision},
+        "roofline": roof,
+        "by_precision": {p: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+                         for p, r in results.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+def B_pad(B):
+    return (B + 127) // 128 * 128
+
+
+if __name__ == "__main__":
+    main()

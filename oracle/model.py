@@ -185,7 +185,7 @@ def line_fluxes(L: Library, th, cols, Lline, dl):
     return Lline * T * 10.0 ** th[cols["logmass"]] / (4.0 * math.pi * dl * dl)
 
 
-def predict(L: Library, obs, theta, rf=None):
+def predict(L: Library, obs, theta, rf=None, trunc=5.0):
     """Model observables [B, n] (maggies) for photometry or a spectrum."""
     theta = np.atleast_2d(theta)
     spec = obs.kind == "spec"
@@ -204,7 +204,7 @@ def predict(L: Library, obs, theta, rf=None):
         if not spec:
             out.append(projection.band_maggies(L.wave, fnu, z, obs.filters))
             continue
-        cont = projection.spectrum_continuum(obs.pix_wave, sig_k, L.wave, fnu, z)
+        cont = projection.spectrum_continuum(obs.pix_wave, sig_k, L.wave, fnu, z, trunc)
         if L.lines is not None:
             Fl = line_fluxes(L, th, cols, rf["Lline"][b], dl)
             lobs = (1.0 + z) * L.lines["line_wave"]
@@ -233,11 +233,11 @@ def noise_terms(obs, th, cols):
     return s, fc, fd, j
 
 
-def logl(L: Library, obs, theta, model=None):
+def logl(L: Library, obs, theta, model=None, trunc=5.0):
     """logL[B] of eq. (6) with the noise floor of eq. G1."""
     theta = np.atleast_2d(theta)
     if model is None:
-        model = predict(L, obs, theta)
+        model = predict(L, obs, theta, trunc=trunc)
     cols = columns(L.n_sfh, L.n_zh)
     mask = likelihood.inclusion_mask(obs.data, obs.sigma, obs.mask)
     out = np.empty(theta.shape[0])

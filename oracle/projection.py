@@ -91,8 +91,12 @@ def kernel_sigma_kms(pix_wave, lsf_mode, lsf_value, rest_wave, z_ref, sigma_gal_
     return np.sqrt(s_fix2 + sigma_gal_kms ** 2)
 
 
-def lsf_row(pix_lam, sigma_kms, ln_rest, z):
-    """(indices, weights) of one row of the banded response W_ij (eq. F5)."""
+def lsf_row(pix_lam, sigma_kms, ln_rest, z, trunc=5.0):
+    """(indices, weights) of one row of the banded response W_ij (eq. F5).
+
+    ``trunc`` is the truncation in dispersions (five in the paper); tests of the
+    redshift gradient widen it so that no node enters or leaves the window.
+    """
     x = math.log(pix_lam) - math.log1p(z)
     n = len(ln_rest)
     if x < ln_rest[0] or x > ln_rest[-1]:
@@ -103,17 +107,17 @@ def lsf_row(pix_lam, sigma_kms, ln_rest, z):
     if s < 0.5 * (ln_rest[k + 1] - ln_rest[k]):
         t = (x - ln_rest[k]) / (ln_rest[k + 1] - ln_rest[k])
         return np.array([k, k + 1]), np.array([1.0 - t, t])
-    idx = np.nonzero(np.abs(ln_rest - x) <= 5.0 * s)[0]
+    idx = np.nonzero(np.abs(ln_rest - x) <= trunc * s)[0]
     w = np.exp(-0.5 * ((ln_rest[idx] - x) / s) ** 2)
     return idx, w / w.sum()
 
 
-def spectrum_continuum(pix_wave, sigma_kms, rest_wave, fnu_obs, z):
+def spectrum_continuum(pix_wave, sigma_kms, rest_wave, fnu_obs, z, trunc=5.0):
     """F_nu(lambda_i) = sum_j W_ij F_nu^obs(lambda_j) for every detector pixel."""
     ln_rest = np.log(rest_wave)
     out = np.zeros(len(pix_wave))
     for i, (lam, s) in enumerate(zip(pix_wave, sigma_kms)):
-        idx, w = lsf_row(lam, s, ln_rest, z)
+        idx, w = lsf_row(lam, s, ln_rest, z, trunc)
         out[i] = np.dot(w, fnu_obs[idx])
     return out
 

@@ -209,6 +209,15 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
     da_f[n] = (float)da[n];
     dd_f[n] = (float)dd[n];
   }
+  {
+    const double dl = (std::log(d->wave[N - 1]) - std::log(d->wave[0])) / (N - 1);
+    double dev = 0.0;
+    for (int n = 0; n + 1 < N; ++n)
+      dev = std::max(dev, std::fabs((std::log(d->wave[n + 1]) - std::log(d->wave[n])) / dl - 1.0));
+    g.log_uniform = dev < 1e-6 ? 1 : 0;
+    g.lnw0 = std::log(d->wave[0]);
+    g.inv_dlnw = 1.0 / dl;
+  }
   // Voronoi cells of the age nodes (App. B): first from 0, last to +inf
   std::vector<double> lo(na), hi(na);
   for (int a = 0; a < na; ++a) {

@@ -37,7 +37,9 @@ enum ThetaCol {
 struct DevLib {
   int n_age, n_z, n_afe, N, N_pad, K, K_pad, K_young_pad, n_young, n_line, n_zg, n_u;
   int n_sfh, n_zh, P, n_gl;
+  int log_uniform;                   // wave grid uniform in ln(lambda) (direct indexing)
   double T1, H0, Om, t_young;
+  double lnw0, inv_dlnw;             // ln(lambda_0) and 1/dln(lambda) when log_uniform
   const double *cell_lo, *cell_hi;   // [n_age] linear-time Voronoi cells
   const double *logz, *afe;          // nodes
   const double *Q;                   // [n_afe][n_z][n_young] photons/s/Msun
@@ -107,6 +109,42 @@ __device__ __forceinline__ int lower_bound_dev(const T *x, int n, T v) {
     if (x[mid] < v) lo = mid + 1; else hi = mid;
   }
   return lo;
+}
+
+// k with wave[k] <= lr < wave[k+1] (lr inside the grid), limited to [0, N-2]
+__device__ __forceinline__ int wave_bracket(const DevLib &lib, double lr) {
+  if (lib.log_uniform) {
+    int k = (int)floor((log(lr) - lib.lnw0) * lib.inv_dlnw);
+    k = min(max(k, 0), lib.N - 2);
+    while (k > 0 && lib.wave_d[k] > lr) --k;
+    while (k < lib.N - 2 && lib.wave_d[k + 1] <= lr) ++k;
+    return k;
+  }
+  return bracket(lib.wave_d, lib.N, lr);
+}
+
+// same in ln(lambda): k with lnwave[k] <= x < lnwave[k+1]
+__device__ __forceinline__ int lnwave_bracket(const DevLib &lib, double x) {
+  if (lib.log_uniform) {
+    int k = (int)floor((x - lib.lnw0) * lib.inv_dlnw);
+    k = min(max(k, 0), lib.N - 2);
+    while (k > 0 && lib.lnwave_d[k] > x) --k;
+    while (k < lib.N - 2 && lib.lnwave_d[k + 1] <= x) ++k;
+    return k;
+  }
+  return bracket(lib.lnwave_d, lib.N, x);
+}
+
+// first j with lnwave[j] >= x
+__device__ __forceinline__ int lnwave_lower_bound(const DevLib &lib, double x) {
+  if (lib.log_uniform) {
+    int j = (int)ceil((x - lib.lnw0) * lib.inv_dlnw);
+    j = min(max(j, 0), lib.N);
+    while (j > 0 && lib.lnwave_d[j - 1] >= x) --j;
+    while (j < lib.N && lib.lnwave_d[j] < x) ++j;
+    return j;
+  }
+  return lower_bound_dev(lib.lnwave_d, lib.N, x);
 }
 
 // bracketing node j and fraction t of x on a 1-D grid, clamped (metallicity split of App. B)

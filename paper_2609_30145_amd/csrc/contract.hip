@@ -9,6 +9,7 @@
 namespace sps {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct ContractArgs {
   const void *W, *Wlo;
@@ -37,6 +38,27 @@ __device__ __forceinline__ void tile_of_block(int n_ntiles, int &mt, int &nt) {
 // B[k][i] with k = h*16 + s at MFMA step s, so each lane reads 16 contiguous
 // floats of its LDS row per 32-wide K tile.
 // ---------------------------------------------------------------------------------
+template <int BM, int BN, int WTM, int WTN>
+__device__ __forceinline__ void bc32(v16f (&acc)[BM][BN], const float (*sp)[5], const float *c_lnlv, const float *c_a,
+                                     const float *c_d, float *Yatt, int N_pad, int m0, int n0, int wm, int wn, int li,
+                                     int lh) {
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        acc[i][j][e] *= __expf(-sp[rl][0] * __expf(sp[rl][1] * c_lnlv[j]));
+        if (Yatt) {
+          const float Td = __expf(-sp[rl][2] * __expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+          const int col = n0 + wn * WTN + j * 32 + li;
+          Yatt[(size_t)(m0 + rl) * N_pad + col] = acc[i][j][e] * Td;
+        }
+      }
+    }
+}
+
 template <int MT, int NT, int WM, int WN>
 __global__ void __launch_bounds__(256) k_contract_f32(ContractArgs a) {
   constexpr int KT = 32, LDSK = KT + 4;
@@ -77,32 +99,19 @@ __global__ void __launch_bounds__(256) k_contract_f32(ContractArgs a) {
   const int nact = a.n_act[mt], ny = a.n_young[mt];
   const int *tl = a.tiles + (size_t)mt * a.n_tiles;
 
-  float4 ra[A4], rb[B4];
-  auto gload = [&](int t) {
-    const int k0 = tl[t] * KT;
-#pragma unroll
-    for (int q = 0; q < A4; ++q) {
-      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
-      ra[q] = *(const float4 *)(W + (size_t)(m0 + row) * K_pad + k0 + c4 * 4);
-    }
-#pragma unroll
-    for (int q = 0; q < B4; ++q) {
-      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
-      rb[q] = *(const float4 *)(LT + (size_t)(n0 + row) * K_pad + k0 + c4 * 4);
-    }
-  };
-  auto sstore = [&]() {
-#pragma unroll
-    for (int q = 0; q < A4; ++q) {
-      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
-      *(float4 *)(As + row * LDSK + c4 * 4) = ra[q];
-    }
-#pragma unroll
-    for (int q = 0; q < B4; ++q) {
-      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
-      *(float4 *)(Bs + row * LDSK + c4 * 4) = rb[q];
-    }
-  };
+  f32x4 ra[A4], rb[B4];
+#define SPS_GLOAD32(t_)                                                              \
+  {                                                                                  \
+    const int k0_ = tl[t_] * KT;                                                     \
+    _Pragma("unroll") for (int q = 0; q < A4; ++q) {                                 \
+      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;                   \
+      ra[q] = *(const f32x4 *)(W + (size_t)(m0 + row) * K_pad + k0_ + c4 * 4);      \
+    }                                                                                \
+    _Pragma("unroll") for (int q = 0; q < B4; ++q) {                                 \
+      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;                   \
+      rb[q] = *(const f32x4 *)(LT + (size_t)(n0 + row) * K_pad + k0_ + c4 * 4);     \
+    }                                                                                \
+  }
 
   // per-lane columns and their static factors
   float c_lnlv[BN], c_a[BN], c_d[BN];
@@ -114,42 +123,31 @@ __global__ void __launch_bounds__(256) k_contract_f32(ContractArgs a) {
     c_d[j] = a.dd[col];
   }
 
-  auto apply_bc = [&]() {
-#pragma unroll
-    for (int i = 0; i < BM; ++i)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
-        const float tbc = sp[rl][0], abc = sp[rl][1];
-#pragma unroll
-        for (int j = 0; j < BN; ++j) {
-          const float T = __expf(-tbc * __expf(abc * c_lnlv[j]));
-          acc[i][j][e] *= T;
-          if (a.Yatt) {
-            const float Td = __expf(-sp[rl][2] * __expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
-            const int col = n0 + wn * WTN + j * 32 + li;
-            ((float *)a.Yatt)[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j][e] * Td;
-          }
-        }
-      }
-  };
-
   __syncthreads();
-  if (nact > 0) gload(0);
+  if (nact > 0) SPS_GLOAD32(0);
   for (int t = 0; t < nact; ++t) {
     __syncthreads();
-    sstore();
+#pragma unroll
+    for (int q = 0; q < A4; ++q) {
+      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
+      *(f32x4 *)(As + row * LDSK + c4 * 4) = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < B4; ++q) {
+      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
+      *(f32x4 *)(Bs + row * LDSK + c4 * 4) = rb[q];
+    }
     __syncthreads();
-    if (t + 1 < nact) gload(t + 1);
-    if (t == ny) apply_bc();
+    if (t + 1 < nact) SPS_GLOAD32(t + 1);
+    if (t == ny) bc32<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
     float af[BM][16], bf[BN][16];
 #pragma unroll
     for (int i = 0; i < BM; ++i) {
       const float *p = As + (wm * WTM + i * 32 + li) * LDSK + lh * 16;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float4 v = *(const float4 *)(p + 4 * q);
-        af[i][4 * q] = v.x; af[i][4 * q + 1] = v.y; af[i][4 * q + 2] = v.z; af[i][4 * q + 3] = v.w;
+        const f32x4 v = *(const f32x4 *)(p + 4 * q);
+        af[i][4 * q] = v[0]; af[i][4 * q + 1] = v[1]; af[i][4 * q + 2] = v[2]; af[i][4 * q + 3] = v[3];
       }
     }
 #pragma unroll
@@ -157,8 +155,8 @@ __global__ void __launch_bounds__(256) k_contract_f32(ContractArgs a) {
       const float *p = Bs + (wn * WTN + j * 32 + li) * LDSK + lh * 16;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float4 v = *(const float4 *)(p + 4 * q);
-        bf[j][4 * q] = v.x; bf[j][4 * q + 1] = v.y; bf[j][4 * q + 2] = v.z; bf[j][4 * q + 3] = v.w;
+        const f32x4 v = *(const f32x4 *)(p + 4 * q);
+        bf[j][4 * q] = v[0]; bf[j][4 * q + 1] = v[1]; bf[j][4 * q + 2] = v[2]; bf[j][4 * q + 3] = v[3];
       }
     }
 #pragma unroll
@@ -171,8 +169,9 @@ __global__ void __launch_bounds__(256) k_contract_f32(ContractArgs a) {
   }
   if (ny == nact) {
     __syncthreads();
-    apply_bc();
+    bc32<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
   }
+#undef SPS_GLOAD32
 
   // diffuse screen on everything and store
   float *F = (float *)a.F;

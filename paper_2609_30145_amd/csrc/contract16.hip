@@ -11,6 +11,7 @@ namespace sps {
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 struct ContractArgs16 {
   const uint16_t *Wh, *Wl, *H, *R;
@@ -30,12 +31,35 @@ __device__ __forceinline__ void tile_of_block16(int n_ntiles, int &mt, int &nt) 
 }
 
 template <bool BF, int PASSES>
-__device__ __forceinline__ v16f mfma16(const uint4 &a, const uint4 &b, v16f c) {
+__device__ __forceinline__ v16f mfma16(const u32x4 &a, const u32x4 &b, v16f c) {
   if constexpr (BF) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
   } else {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a), __builtin_bit_cast(v8h, b), c, 0, 0, 0);
   }
+}
+
+// Birth-cloud transmission applied to the young-part accumulator (and, for the
+// gradient, the young spectrum after both screens stored to Yatt).
+template <int BM, int BN, int WTM, int WTN>
+__device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[6], const float *c_lnlv, const float *c_a,
+                                     const float *c_d, float *Yatt, int N_pad, int m0, int n0, int wm, int wn, int li,
+                                     int lh) {
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        acc[i][j][e] *= __expf(-sp[rl][0] * __expf(sp[rl][1] * c_lnlv[j]));
+        if (Yatt) {
+          const float Td = __expf(-sp[rl][2] * __expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+          const int col = n0 + wn * WTN + j * 32 + li;
+          Yatt[(size_t)(m0 + rl) * N_pad + col] = acc[i][j][e] * Td * sp[rl][5];
+        }
+      }
+    }
 }
 
 // PASSES: 1 = W_h H; 2 = W_h H + W_h R; 3 = W_h H + W_h R + W_l H
@@ -79,38 +103,23 @@ __global__ void __launch_bounds__(256) k_contract_16(ContractArgs16 a) {
   const int nact = a.n_act[mt], ny = a.n_young[mt];
   const int *tl = a.tiles + (size_t)mt * a.n_tiles;
 
-  uint4 rah[A8], ral[USE_WL ? A8 : 1], rbh[B8], rbr[USE_R ? B8 : 1];
-  auto gload = [&](int t) {
-    const int k0 = tl[t] * KT;
-#pragma unroll
-    for (int q = 0; q < A8; ++q) {
-      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;
-      const size_t o = (size_t)(m0 + row) * K_pad + k0 + c8 * 8;
-      rah[q] = *(const uint4 *)(a.Wh + o);
-      if constexpr (USE_WL) ral[q] = *(const uint4 *)(a.Wl + o);
-    }
-#pragma unroll
-    for (int q = 0; q < B8; ++q) {
-      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;
-      const size_t o = (size_t)(n0 + row) * K_pad + k0 + c8 * 8;
-      rbh[q] = *(const uint4 *)(a.H + o);
-      if constexpr (USE_R) rbr[q] = *(const uint4 *)(a.R + o);
-    }
-  };
-  auto sstore = [&]() {
-#pragma unroll
-    for (int q = 0; q < A8; ++q) {
-      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;
-      *(uint4 *)(Ah + row * LDSK + c8 * 8) = rah[q];
-      if constexpr (USE_WL) *(uint4 *)(Al + row * LDSK + c8 * 8) = ral[q];
-    }
-#pragma unroll
-    for (int q = 0; q < B8; ++q) {
-      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;
-      *(uint4 *)(Bh + row * LDSK + c8 * 8) = rbh[q];
-      if constexpr (USE_R) *(uint4 *)(Br + row * LDSK + c8 * 8) = rbr[q];
-    }
-  };
+  u32x4 rah[A8], ral[USE_WL ? A8 : 1], rbh[B8], rbr[USE_R ? B8 : 1];
+#define SPS_GLOAD16(t_)                                                        \
+  {                                                                            \
+    const int k0_ = tl[t_] * KT;                                               \
+    _Pragma("unroll") for (int q = 0; q < A8; ++q) {                           \
+      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;             \
+      const size_t o = (size_t)(m0 + row) * K_pad + k0_ + c8 * 8;              \
+      rah[q] = *(const u32x4 *)(a.Wh + o);                                     \
+      if constexpr (USE_WL) ral[q] = *(const u32x4 *)(a.Wl + o);               \
+    }                                                                          \
+    _Pragma("unroll") for (int q = 0; q < B8; ++q) {                           \
+      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;             \
+      const size_t o = (size_t)(n0 + row) * K_pad + k0_ + c8 * 8;              \
+      rbh[q] = *(const u32x4 *)(a.H + o);                                      \
+      if constexpr (USE_R) rbr[q] = *(const u32x4 *)(a.R + o);                 \
+    }                                                                          \
+  }
 
   float c_lnlv[BN], c_a[BN], c_d[BN];
 #pragma unroll
@@ -120,62 +129,65 @@ __global__ void __launch_bounds__(256) k_contract_16(ContractArgs16 a) {
     c_a[j] = a.da[col];
     c_d[j] = a.dd[col];
   }
-  auto apply_bc = [&]() {
-#pragma unroll
-    for (int i = 0; i < BM; ++i)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
-#pragma unroll
-        for (int j = 0; j < BN; ++j) {
-          acc[i][j][e] *= __expf(-sp[rl][0] * __expf(sp[rl][1] * c_lnlv[j]));
-          if (a.Yatt) {
-            const float Td = __expf(-sp[rl][2] * __expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
-            const int col = n0 + wn * WTN + j * 32 + li;
-            a.Yatt[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j][e] * Td * sp[rl][5];
-          }
-        }
-      }
-  };
-
   __syncthreads();
-  if (nact > 0) gload(0);
+  if (nact > 0) SPS_GLOAD16(0);
   for (int t = 0; t < nact; ++t) {
     __syncthreads();
-    sstore();
+#pragma unroll
+    for (int q = 0; q < A8; ++q) {
+      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;
+      *(u32x4 *)(Ah + row * LDSK + c8 * 8) = rah[q];
+      if constexpr (USE_WL) *(u32x4 *)(Al + row * LDSK + c8 * 8) = ral[q];
+    }
+#pragma unroll
+    for (int q = 0; q < B8; ++q) {
+      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;
+      *(u32x4 *)(Bh + row * LDSK + c8 * 8) = rbh[q];
+      if constexpr (USE_R) *(u32x4 *)(Br + row * LDSK + c8 * 8) = rbr[q];
+    }
     __syncthreads();
-    if (t + 1 < nact) gload(t + 1);
-    if (t == ny) apply_bc();
+    if (t + 1 < nact) SPS_GLOAD16(t + 1);
+    if (t == ny) bc16<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int kofs = lh * 32 + s * 8;
-      uint4 fa[BM], fl[BM], fb[BN], fr[BN];
+      u32x4 fa[BM], fl[BM], fb[BN], fr[BN];
 #pragma unroll
       for (int i = 0; i < BM; ++i) {
         const int row = wm * WTM + i * 32 + li;
-        fa[i] = *(const uint4 *)(Ah + row * LDSK + kofs);
-        if constexpr (USE_WL) fl[i] = *(const uint4 *)(Al + row * LDSK + kofs);
+        fa[i] = *(const u32x4 *)(Ah + row * LDSK + kofs);
+        if constexpr (USE_WL) fl[i] = *(const u32x4 *)(Al + row * LDSK + kofs);
       }
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
         const int col = wn * WTN + j * 32 + li;
-        fb[j] = *(const uint4 *)(Bh + col * LDSK + kofs);
-        if constexpr (USE_R) fr[j] = *(const uint4 *)(Br + col * LDSK + kofs);
+        fb[j] = *(const u32x4 *)(Bh + col * LDSK + kofs);
+        if constexpr (USE_R) fr[j] = *(const u32x4 *)(Br + col * LDSK + kofs);
       }
+      // the passes are interleaved over the independent accumulators
 #pragma unroll
       for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < BN; ++j) {
-          acc[i][j] = mfma16<BF, PASSES>(fa[i], fb[j], acc[i][j]);
-          if constexpr (USE_R) acc[i][j] = mfma16<BF, PASSES>(fa[i], fr[j], acc[i][j]);
-          if constexpr (USE_WL) acc[i][j] = mfma16<BF, PASSES>(fl[i], fb[j], acc[i][j]);
-        }
+        for (int j = 0; j < BN; ++j) acc[i][j] = mfma16<BF, PASSES>(fa[i], fb[j], acc[i][j]);
+      if constexpr (USE_R) {
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+#pragma unroll
+          for (int j = 0; j < BN; ++j) acc[i][j] = mfma16<BF, PASSES>(fa[i], fr[j], acc[i][j]);
+      }
+      if constexpr (USE_WL) {
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+#pragma unroll
+          for (int j = 0; j < BN; ++j) acc[i][j] = mfma16<BF, PASSES>(fl[i], fb[j], acc[i][j]);
+      }
     }
   }
   if (ny == nact) {
     __syncthreads();
-    apply_bc();
+    bc16<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
   }
+#undef SPS_GLOAD16
 #pragma unroll
   for (int i = 0; i < BM; ++i)
 #pragma unroll

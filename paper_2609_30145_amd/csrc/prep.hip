@@ -22,25 +22,27 @@ __device__ double sort_key(const DevLib &lib, const double *th) {
   return (double)jz * 1.0e6 + (double)ja * 1.0e4 + fmin(fmax(z, 0.0), 9.0e3);
 }
 
+// One workgroup per point: rank = number of points with a smaller (key, index).
 __global__ void __launch_bounds__(256) k_sort(DevLib lib, const double *__restrict__ theta, int P, int B,
                                               int *__restrict__ perm) {
-  __shared__ double keys[256];
-  const int b = blockIdx.x * 256 + threadIdx.x;
-  const double my = b < B ? sort_key(lib, theta + (size_t)b * P) : 0.0;
-  int rank = 0;
-  for (int base = 0; base < B; base += 256) {
-    const int j = base + threadIdx.x;
-    keys[threadIdx.x] = j < B ? sort_key(lib, theta + (size_t)j * P) : 0.0;
-    __syncthreads();
-    const int n = min(256, B - base);
-    for (int q = 0; q < n; ++q) {
-      const double kq = keys[q];
-      const int jq = base + q;
-      rank += (kq < my) || (kq == my && jq < b);
-    }
+  __shared__ int cnt[256];
+  __shared__ double s_my;
+  const int b = blockIdx.x;
+  if (threadIdx.x == 0) s_my = sort_key(lib, theta + (size_t)b * P);
+  __syncthreads();
+  const double my = s_my;
+  int c = 0;
+  for (int j = threadIdx.x; j < B; j += 256) {
+    const double kj = sort_key(lib, theta + (size_t)j * P);
+    c += (kj < my) || (kj == my && j < b);
+  }
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
     __syncthreads();
   }
-  if (b < B) perm[rank] = b;
+  if (threadIdx.x == 0) perm[cnt[0]] = b;
 }
 
 // ---------------------------------------------------------------------------------
@@ -272,14 +274,18 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     grid_split_dev(lib.zg, lib.n_zg, s_th[TH_GAS_LOGZ], jg, tg, in);
     grid_split_dev(lib.un, lib.n_u, s_th[TH_GAS_LOGU], ju, tu, in);
     const int nzg = lib.n_zg, nu = lib.n_u;
+    double *lt = wq + ny;   // [n_line * n_young] per (line, age) luminosity terms
+    for (int q = tid; q < lib.n_line * ny; q += 256) {
+      const int l = q / ny, ag = q - l * ny;
+      const double *tb = lib.line_table + ((size_t)l * ny + ag) * nzg * nu;
+      const double lh = (1.0 - tg) * (1.0 - tu) * tb[jg * nu + ju] + (1.0 - tg) * tu * tb[jg * nu + ju + 1] +
+                        tg * (1.0 - tu) * tb[(jg + 1) * nu + ju] + tg * tu * tb[(jg + 1) * nu + ju + 1];
+      lt[q] = exp10(lh) * wq[ag];
+    }
+    __syncthreads();
     for (int l = tid; l < lib.n_line; l += 256) {
       double Ll = 0.0;
-      for (int ag = 0; ag < ny; ++ag) {
-        const double *tb = lib.line_table + ((size_t)l * ny + ag) * nzg * nu;
-        const double lh = (1.0 - tg) * (1.0 - tu) * tb[jg * nu + ju] + (1.0 - tg) * tu * tb[jg * nu + ju + 1] +
-                          tg * (1.0 - tu) * tb[(jg + 1) * nu + ju] + tg * tu * tb[(jg + 1) * nu + ju + 1];
-        Ll += exp10(lh) * wq[ag];
-      }
+      for (int ag = 0; ag < ny; ++ag) Ll += lt[l * ny + ag];
       if (kind == 0) wacc[a.line_k0 + l] = Ll / kLsun;        // photometry: lines on the model grid
       else a.Lline[(size_t)r * lib.n_line + l] = Ll;           // spectra: lines on the detector pixels
     }
@@ -318,16 +324,18 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     }
   }
   __syncthreads();
-  for (int w = tid; w < a.mask_words; w += 256) {
-    uint32_t bits = 0u;
-    for (int q = 0; q < 32; ++q) {
-      const int k0 = (w * 32 + q) * kKTile;
-      if (k0 >= K_pad) break;
-      bool nz_tile = false;
-      for (int k = k0; k < k0 + kKTile; ++k) nz_tile |= (wacc[k] != 0.0);
-      bits |= (nz_tile ? 1u : 0u) << q;
+  {
+    uint32_t *tbits = (uint32_t *)red;   // reuse: one word per 32 K tiles
+    for (int w = tid; w < a.mask_words; w += 256) tbits[w] = 0u;
+    __syncthreads();
+    const int n_kt = K_pad / kKTile;
+    for (int t = tid; t < n_kt; t += 256) {
+      bool on = false;
+      for (int k = t * kKTile; k < (t + 1) * kKTile; ++k) on |= (wacc[k] != 0.0);
+      if (on) atomicOr(&tbits[t >> 5], 1u << (t & 31));
     }
-    a.rowmask[(size_t)r * a.mask_words + w] = bits;
+    __syncthreads();
+    for (int w = tid; w < a.mask_words; w += 256) a.rowmask[(size_t)r * a.mask_words + w] = tbits[w];
   }
 
   if (tid == 0) {
@@ -359,32 +367,55 @@ __global__ void __launch_bounds__(256) k_tiles(const uint32_t *__restrict__ rowm
                                                int *__restrict__ n_young, int *__restrict__ n_act,
                                                unsigned long long *__restrict__ counter) {
   __shared__ uint32_t acc[64];
-  const int mt = blockIdx.x;
-  for (int w = threadIdx.x; w < mask_words; w += 256) {
-    uint32_t v = 0u;
-    for (int r = 0; r < MT; ++r) v |= rowmask[(size_t)(mt * MT + r) * mask_words + w];
-    acc[w] = v;
+  __shared__ int cnt[256], cy[256];
+  const int mt = blockIdx.x, tid = threadIdx.x;
+  if (tid < 64) acc[tid] = 0u;
+  __syncthreads();
+  for (int idx = tid; idx < MT * mask_words; idx += 256) {
+    const int r = idx / mask_words, w = idx - r * mask_words;
+    const uint32_t v = rowmask[(size_t)(mt * MT + r) * mask_words + w];
+    if (v) atomicOr(&acc[w], v);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int n_tiles = (n_tiles32 + tf - 1) / tf;
-    const int y_tiles = young_tiles32 / tf;
-    int n = 0, ny = 0;
-    for (int t = 0; t < n_tiles; ++t) {
-      bool on = false;
-      for (int q = 0; q < tf; ++q) {
-        const int t32 = t * tf + q;
-        if (t32 < n_tiles32) on |= (acc[t32 >> 5] >> (t32 & 31)) & 1u;
-      }
-      if (on) {
-        tiles[mt * n_tiles + n] = t;
-        ++n;
-        if (t < y_tiles) ++ny;
-      }
+  const int n_tiles = (n_tiles32 + tf - 1) / tf;
+  const int y_tiles = young_tiles32 / tf;
+  const int chunk = (n_tiles + 255) / 256;
+  const int t0 = min(tid * chunk, n_tiles), t1 = min(t0 + chunk, n_tiles);
+  auto on_tile = [&](int t) {
+    bool on = false;
+    for (int q = 0; q < tf; ++q) {
+      const int t32 = t * tf + q;
+      if (t32 < n_tiles32) on |= (acc[t32 >> 5] >> (t32 & 31)) & 1u;
     }
-    n_young[mt] = ny;
-    n_act[mt] = n;
-    if (counter) atomicAdd(counter, (unsigned long long)n);
+    return on;
+  };
+  int c = 0, y = 0;
+  for (int t = t0; t < t1; ++t)
+    if (on_tile(t)) {
+      ++c;
+      y += t < y_tiles;
+    }
+  cnt[tid] = c;
+  cy[tid] = y;
+  __syncthreads();
+  // inclusive scan of cnt (Hillis-Steele), sum of cy
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = tid >= off ? cnt[tid - off] : 0;
+    __syncthreads();
+    cnt[tid] += v;
+    __syncthreads();
+  }
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (tid < s2) cy[tid] += cy[tid + s2];
+    __syncthreads();
+  }
+  int pos = cnt[tid] - c;
+  for (int t = t0; t < t1; ++t)
+    if (on_tile(t)) tiles[mt * n_tiles + pos++] = t;
+  if (tid == 0) {
+    n_act[mt] = cnt[255];
+    n_young[mt] = cy[0];
+    if (counter) atomicAdd(counter, (unsigned long long)cnt[255]);
   }
 }
 
@@ -392,12 +423,13 @@ __global__ void __launch_bounds__(256) k_tiles(const uint32_t *__restrict__ rowm
 // Host launchers
 // ---------------------------------------------------------------------------------
 size_t prep_smem_bytes(const DevLib &lib) {
-  return sizeof(double) * ((size_t)lib.K_pad + lib.n_sfh + 1 + lib.n_sfh + 256 + lib.n_young + 8) +
+  return sizeof(double) * ((size_t)lib.K_pad + lib.n_sfh + 1 + lib.n_sfh + 256 + lib.n_young +
+                           (size_t)lib.n_line * lib.n_young + 8) +
          sizeof(int) * ((size_t)lib.n_sfh + 2);
 }
 
 hipError_t launch_sort(const DevLib &lib, const double *theta, int P, int B, int *perm, hipStream_t s) {
-  hipLaunchKernelGGL(k_sort, dim3((B + 255) / 256), dim3(256), 0, s, lib, theta, P, B, perm);
+  hipLaunchKernelGGL(k_sort, dim3(B), dim3(256), 0, s, lib, theta, P, B, perm);
   return hipGetLastError();
 }
 

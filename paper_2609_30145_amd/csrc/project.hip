@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
       for (int j = j0 + lane; j < j1; j += 64) {
         const double lr = ob.fw[j] / opz;
         if (lr < lib.wave_d[0] || lr > lib.wave_d[N - 1]) continue;
-        const int k = bracket(lib.wave_d, N, lr);
+        const int k = wave_bracket(lib, lr);
         const T t = (T)((lr - lib.wave_d[k]) / (lib.wave_d[k + 1] - lib.wave_d[k]));
         const T f = Fr[k] + t * (Fr[k + 1] - Fr[k]);
         const T w = sizeof(T) == 8 ? (T)ob.fr_d[j] : (T)ob.fr_f[j];
@@ -143,14 +143,14 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
       T cont = (T)0;
       if (x >= lnw0 && x <= lnw1) {
         const double s = ob.ksig[i];
-        const int k = bracket(lib.lnwave_d, N, x);
+        const int k = lnwave_bracket(lib, x);
         const double dk = lib.lnwave_d[k + 1] - lib.lnwave_d[k];
         if (s < 0.5 * dk) {
           const T t = (T)((x - lib.lnwave_d[k]) / dk);
           const T fk = Fr[k] * (T)lib.lam2_d[k], fk1 = Fr[k + 1] * (T)lib.lam2_d[k + 1];
           cont = fk + t * (fk1 - fk);
         } else {
-          int j = lower_bound_dev(lib.lnwave_d, N, x - 5.0 * s);
+          int j = lnwave_lower_bound(lib, x - 5.0 * s);
           const double inv = 1.0 / s;
           T num = (T)0, den = (T)0;
           for (; j < N; ++j) {

@@ -135,8 +135,12 @@ def _planck_shape(wave, T):
     return val / peak
 
 
-def make_library(cfg: Config, seed: int = 0) -> dict:
-    """SSP grid flux[n_afe, n_z, n_age, n_wave] in Lsun/A/Msun on a log-uniform grid."""
+def make_library(cfg: Config, seed: int = 0, noise: float = 0.1) -> dict:
+    """SSP grid flux[n_afe, n_z, n_age, n_wave] in Lsun/A/Msun on a log-uniform grid.
+
+    ``noise`` is the dispersion of the iid lognormal factor per element (0.1 for the
+    workloads; 0 gives smooth spectra for finite-difference tests).
+    """
     rng = np.random.default_rng(seed)
     ages = np.geomspace(cfg.age_min, cfg.age_max, cfg.n_age)
     wave = np.geomspace(cfg.lam_min, cfg.lam_max, cfg.n_wave)
@@ -156,7 +160,7 @@ def make_library(cfg: Config, seed: int = 0) -> dict:
             flux[ia, iz] = (A1[:, None] * _planck_shape(wave, T1)
                             + A2[:, None] * _planck_shape(wave, T2)
                             + A3[:, None] * _planck_shape(wave, T3))
-    flux *= np.exp(rng.normal(0.0, 0.1, size=flux.shape))
+    flux *= np.exp(rng.normal(0.0, noise, size=flux.shape))
     flux *= 1e2 / flux.max()
     np.maximum(flux, 1e-8, out=flux)
     return dict(ages=ages, logz=logz, afe=afe, wave=wave, flux=flux, t_young=cfg.t_young)
