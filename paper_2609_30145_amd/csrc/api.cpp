@@ -555,7 +555,7 @@ extern "C" sps_status sps_obs_create(const sps_library *L, const sps_obs_desc *d
   sps_status st = build_obs_operators(L, d, o->host, warnings);
   if (st == SPS_OK) st = set_obs_data(o->host, d->data, d->sigma, d->mask);
   if (st == SPS_OK) st = o->upload_operators();
-  if (st == SPS_OK) st = o->ws.create(L, d->max_batch, o->host.n_data);
+  if (st == SPS_OK) st = o->ws.create(L, d->max_batch, o->host.n_data, (int)o->host.fw.size());
   if (st != SPS_OK) {
     delete o;
     return st;
@@ -596,6 +596,9 @@ sps_status run_forward(const sps_library *L, sps_obs *o, const double *theta, in
   Workspace &w = o->ws;
   const DevLib &g = L->dev;
   const int B_pad = (B + kMAlign - 1) / kMAlign * kMAlign;
+  // the thread's HIP last-error slot may hold a stale code set by another library's
+  // call; clear it so that only this call's own launches are checked below
+  (void)hipGetLastError();
   const int mode = prec == 0 ? 0 : prec == 1 ? 1 : (prec == 2 || prec == 4 || prec == 6) ? 2 : 3;
   hipError_t e = launch_sort(g, theta, g.P, B, w.perm, s);
   PrepLaunch pl;
@@ -648,6 +651,7 @@ sps_status run_forward(const sps_library *L, sps_obs *o, const double *theta, in
   pj.logl = logl;
   pj.gvec = want_grad_buffers ? w.gvec : nullptr;
   pj.gnoise = want_grad_buffers ? w.gnoise : nullptr;
+  pj.msorted = want_grad_buffers ? w.mbuf : nullptr;
   pj.ld_model = o->host.n_data;
   pj.ld_g = o->host.n_data;
   if (e == hipSuccess) e = launch_project(g, pj, s);

@@ -49,9 +49,9 @@ __device__ __forceinline__ void bc32(v16f (&acc)[BM][BN], const float (*sp)[5], 
       const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
-        acc[i][j][e] *= __expf(-sp[rl][0] * __expf(sp[rl][1] * c_lnlv[j]));
+        acc[i][j][e] *= expf(-sp[rl][0] * expf(sp[rl][1] * c_lnlv[j]));
         if (Yatt) {
-          const float Td = __expf(-sp[rl][2] * __expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+          const float Td = expf(-sp[rl][2] * expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
           const int col = n0 + wn * WTN + j * 32 + li;
           Yatt[(size_t)(m0 + rl) * N_pad + col] = acc[i][j][e] * Td;
         }
@@ -59,7 +59,30 @@ __device__ __forceinline__ void bc32(v16f (&acc)[BM][BN], const float (*sp)[5], 
     }
 }
 
-template <int MT, int NT, int WM, int WN>
+template <int BM, int BN, int WTM, int WTN>
+__device__ __forceinline__ void bc32p(double (&acc)[BM][BN][16], const float (*sp)[5], const float *c_lnlv, const float *c_a,
+                                     const float *c_d, float *Yatt, int N_pad, int m0, int n0, int wm, int wn, int li,
+                                     int lh) {
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        acc[i][j][e] *= (double)expf(-sp[rl][0] * expf(sp[rl][1] * c_lnlv[j]));
+        if (Yatt) {
+          const float Td = expf(-sp[rl][2] * expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+          const int col = n0 + wn * WTN + j * 32 + li;
+          Yatt[(size_t)(m0 + rl) * N_pad + col] = (float)(acc[i][j][e] * (double)Td);
+        }
+      }
+    }
+}
+
+// PRECISE (gradient pass): each 32-wide K tile is accumulated in FP32 and the tile
+// partials are summed in FP64.
+template <int MT, int NT, int WM, int WN, bool PRECISE>
 __global__ void __launch_bounds__(256) k_contract_f32(ContractArgs a) {
   constexpr int KT = 32, LDSK = KT + 4;
   constexpr int WTM = MT / WM, WTN = NT / WN, BM = WTM / 32, BN = WTN / 32;
@@ -89,12 +112,16 @@ __global__ void __launch_bounds__(256) k_contract_f32(ContractArgs a) {
   }
 
   v16f acc[BM][BN];
+  double dacc[PRECISE ? BM : 1][PRECISE ? BN : 1][PRECISE ? 16 : 1];
 #pragma unroll
   for (int i = 0; i < BM; ++i)
 #pragma unroll
     for (int j = 0; j < BN; ++j)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+      for (int e = 0; e < 16; ++e) {
+        acc[i][j][e] = 0.f;
+        if constexpr (PRECISE) dacc[i][j][e] = 0.0;
+      }
 
   const int nact = a.n_act[mt], ny = a.n_young[mt];
   const int *tl = a.tiles + (size_t)mt * a.n_tiles;
@@ -139,7 +166,13 @@ __global__ void __launch_bounds__(256) k_contract_f32(ContractArgs a) {
     }
     __syncthreads();
     if (t + 1 < nact) SPS_GLOAD32(t + 1);
-    if (t == ny) bc32<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
+    if (t == ny) {
+      if constexpr (PRECISE) {
+        bc32p<BM, BN, WTM, WTN>(dacc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
+      } else {
+        bc32<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
+      }
+    }
     float af[BM][16], bf[BN][16];
 #pragma unroll
     for (int i = 0; i < BM; ++i) {
@@ -166,10 +199,25 @@ __global__ void __launch_bounds__(256) k_contract_f32(ContractArgs a) {
 #pragma unroll
         for (int j = 0; j < BN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+    if constexpr (PRECISE) {
+#pragma unroll
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BN; ++j)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            dacc[i][j][e] += (double)acc[i][j][e];
+            acc[i][j][e] = 0.f;
+          }
+    }
   }
   if (ny == nact) {
     __syncthreads();
-    bc32<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
+    if constexpr (PRECISE) {
+      bc32p<BM, BN, WTM, WTN>(dacc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
+    } else {
+      bc32<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
+    }
   }
 #undef SPS_GLOAD32
 
@@ -183,8 +231,9 @@ __global__ void __launch_bounds__(256) k_contract_f32(ContractArgs a) {
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
         const int col = n0 + wn * WTN + j * 32 + li;
-        const float Td = __expf(-sp[rl][2] * __expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
-        F[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j][e] * Td;
+        const float Td = expf(-sp[rl][2] * expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+        if constexpr (PRECISE) F[(size_t)(m0 + rl) * a.N_pad + col] = (float)(dacc[i][j][e] * (double)Td);
+        else F[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j][e] * Td;
       }
     }
 }
@@ -290,7 +339,10 @@ hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStrea
     hipLaunchKernelGGL(k_contract_f64, dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
   } else if (cl.precision == 1) {
     a.LTa = lib.LT32;
-    hipLaunchKernelGGL((k_contract_f32<128, 64, 2, 2>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
+    if (cl.Yatt)
+      hipLaunchKernelGGL((k_contract_f32<128, 64, 2, 2, true>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_contract_f32<128, 64, 2, 2, false>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
   } else {
     return launch_contract16_impl(lib, cl.W, cl.Wlo, cl.tiles, cl.n_young, cl.n_act, cl.rows, cl.F, cl.Yatt,
                                   cl.precision, n_mt, s);

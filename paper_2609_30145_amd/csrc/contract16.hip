@@ -52,9 +52,9 @@ __device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[6], 
       const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
-        acc[i][j][e] *= __expf(-sp[rl][0] * __expf(sp[rl][1] * c_lnlv[j]));
+        acc[i][j][e] *= expf(-sp[rl][0] * expf(sp[rl][1] * c_lnlv[j]));
         if (Yatt) {
-          const float Td = __expf(-sp[rl][2] * __expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+          const float Td = expf(-sp[rl][2] * expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
           const int col = n0 + wn * WTN + j * 32 + li;
           Yatt[(size_t)(m0 + rl) * N_pad + col] = acc[i][j][e] * Td * sp[rl][5];
         }
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(256) k_contract_16(ContractArgs16 a) {
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
         const int col = n0 + wn * WTN + j * 32 + li;
-        const float Td = __expf(-sp[rl][2] * __expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+        const float Td = expf(-sp[rl][2] * expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
         a.F[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j][e] * Td * sp[rl][5];
       }
     }

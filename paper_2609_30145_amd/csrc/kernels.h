@@ -52,6 +52,7 @@ struct ProjectLaunch {
   double *logl;              // [B] or NULL
   double *gvec;              // [B_pad][n_data_max] dlogL/dm (adjoint) or NULL
   double *gnoise;            // [B][4] dlogL/d(noise params) or NULL
+  double *msorted;           // [B_pad][ld_g] model at sorted rows or NULL
   int ld_model;              // row stride of model
   int ld_g;
 };

@@ -452,14 +452,14 @@ hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s) {
   a.line_k0 = pl.line_k0;
   const size_t sm = prep_smem_bytes(lib);
   if (sm > 160 * 1024) return hipErrorInvalidValue;
-  static bool attr_set[4] = {false, false, false, false};
+  static size_t attr_set[4] = {0, 0, 0, 0};
   const void *fn[4] = {(const void *)k_prep<W_F64>, (const void *)k_prep<W_F32>, (const void *)k_prep<W_BF16>,
                        (const void *)k_prep<W_F16>};
   const int md = pl.mode & 3;
-  if (!attr_set[md] && sm > 48 * 1024) {
-    hipError_t e = hipFuncSetAttribute(fn[md], hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (sm > 48 * 1024 && sm > attr_set[md]) {
+    hipError_t e = hipFuncSetAttribute(fn[md], hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
-    attr_set[md] = true;
+    attr_set[md] = sm;
   }
   const dim3 g(pl.B_pad), blk(256);
   switch (pl.mode) {

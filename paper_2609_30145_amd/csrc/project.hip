@@ -17,7 +17,7 @@ struct ProjArgs {
   const double *theta;
   int P, B;
   const double *Lline;
-  double *model, *logl, *gvec, *gnoise;
+  double *model, *logl, *gvec, *gnoise, *msorted;
   int ld_model, ld_g;
 };
 
@@ -68,6 +68,7 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
 
   auto datum = [&](int i, double m) {
     if (a.model) a.model[(size_t)pr.b * a.ld_model + i] = m;
+    if (a.msorted) a.msorted[(size_t)r * a.ld_g + i] = m;
     double g = 0.0;
     if (ob.mask[i]) {
       const double d = ob.data[i], sg = ob.sigma[i];
@@ -77,7 +78,7 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
       // d logL / d v and d logL / d m (App. G terms)
       const double dv = 0.5 * res * res / (v * v) - 0.5 / v;
       g = res / v + dv * 2.0 * fc * fc * m;
-      gs[0] += dv * 2.0 * ns * ns * sg * sg;   // d/d ln s
+      if (ob.noise_flags & 1) gs[0] += dv * 2.0 * ns * ns * sg * sg;   // d/d ln s
       gs[1] += dv * 2.0 * fc * fc * m * m;     // d/d ln f_calib
       gs[2] += dv * 2.0 * fd * fd * d * d;     // d/d ln f_data
       gs[3] += dv * 2.0 * jt * jt;             // d/d ln j
@@ -91,7 +92,7 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
     const int wave_id = tid >> 6, lane = tid & 63;
     for (int band = wave_id; band < ob.n_band; band += 4) {
       const int j0 = ob.band_off[band], j1 = ob.band_off[band + 1];
-      T part = (T)0;
+      double part = 0.0;
       for (int j = j0 + lane; j < j1; j += 64) {
         const double lr = ob.fw[j] / opz;
         if (lr < lib.wave_d[0] || lr > lib.wave_d[N - 1]) continue;
@@ -99,9 +100,9 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
         const T t = (T)((lr - lib.wave_d[k]) / (lib.wave_d[k + 1] - lib.wave_d[k]));
         const T f = Fr[k] + t * (Fr[k + 1] - Fr[k]);
         const T w = sizeof(T) == 8 ? (T)ob.fr_d[j] : (T)ob.fr_f[j];
-        part += w * f;
+        part += (double)(w * f);
       }
-      double s = wave_reduce_sum((double)part);
+      double s = wave_reduce_sum(part);
       if (lane == 0) red[band] = s;
     }
     __syncthreads();
@@ -152,15 +153,15 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
         } else {
           int j = lnwave_lower_bound(lib, x - 5.0 * s);
           const double inv = 1.0 / s;
-          T num = (T)0, den = (T)0;
+          double num = 0.0, den = 0.0;
           for (; j < N; ++j) {
             const double u = (lib.lnwave_d[j] - x) * inv;
             if (u > 5.0) break;
-            const T w = sizeof(T) == 8 ? (T)exp(-0.5 * u * u) : (T)__expf((float)(-0.5 * u * u));
-            num += w * (Fr[j] * (T)lib.lam2_d[j]);
-            den += w;
+            const T w = sizeof(T) == 8 ? (T)exp(-0.5 * u * u) : (T)expf((float)(-0.5 * u * u));
+            num += (double)(w * (Fr[j] * (T)lib.lam2_d[j]));
+            den += (double)w;
           }
-          cont = num / den;
+          cont = (T)(num / den);
         }
       }
       double m = pr.scale_fnu * (double)cont;
@@ -203,11 +204,11 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
 hipError_t launch_project(const DevLib &lib, const ProjectLaunch &pl, hipStream_t s) {
   if (pl.f64) {
     ProjArgs<double> a{pl.obs_table, pl.rows, (const double *)pl.F, lib.N_pad, lib.n_line, pl.theta, pl.P, pl.B,
-                       pl.Lline, pl.model, pl.logl, pl.gvec, pl.gnoise, pl.ld_model, pl.ld_g};
+                       pl.Lline, pl.model, pl.logl, pl.gvec, pl.gnoise, pl.msorted, pl.ld_model, pl.ld_g};
     hipLaunchKernelGGL(k_project<double>, dim3(pl.B), dim3(256), 0, s, lib, a);
   } else {
     ProjArgs<float> a{pl.obs_table, pl.rows, (const float *)pl.F, lib.N_pad, lib.n_line, pl.theta, pl.P, pl.B,
-                      pl.Lline, pl.model, pl.logl, pl.gvec, pl.gnoise, pl.ld_model, pl.ld_g};
+                      pl.Lline, pl.model, pl.logl, pl.gvec, pl.gnoise, pl.msorted, pl.ld_model, pl.ld_g};
     hipLaunchKernelGGL(k_project<float>, dim3(pl.B), dim3(256), 0, s, lib, a);
   }
   return hipGetLastError();

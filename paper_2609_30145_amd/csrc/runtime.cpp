@@ -1,6 +1,7 @@
 // Observation operators, workspaces and contraction timing.
 #include "runtime.h"
 
+#include <algorithm>
 #include <cstring>
 
 #include "kernels.h"
@@ -12,7 +13,7 @@ void sps_library::host_wave(std::vector<double> &w) const {
   (void)hipMemcpy(w.data(), dev.wave_d, (size_t)N * 8, hipMemcpyDeviceToHost);
 }
 
-sps_status Workspace::create(const sps_library *L, int mb, int n_data) {
+sps_status Workspace::create(const sps_library *L, int mb, int n_data, int n_fnodes) {
   const DevLib &g = L->dev;
   max_batch = mb;
   B_pad_max = (mb + kMAlign - 1) / kMAlign * kMAlign;
@@ -37,7 +38,11 @@ sps_status Workspace::create(const sps_library *L, int mb, int n_data) {
   Lline = (double *)al(Bp * (size_t)std::max(1, g.n_line) * 8);
   gvec = (double *)al(Bp * (size_t)std::max(1, n_data) * 8);
   gnoise = (double *)al(Bp * 4 * 8);
-  gbuf = (double *)al(Bp * 64 * 8);
+  gbuf = (double *)al(Bp * 16 * 8);
+  mbuf = (double *)al(Bp * (size_t)std::max(1, n_data) * 8);
+  ld_scr = std::max(3 * n_fnodes, 8 * n_data);
+  scr = (double *)al(Bp * (size_t)ld_scr * 8);
+  dLl = (double *)al(Bp * (size_t)std::max(1, g.n_line) * 8);
   G = al(Bp * g.N_pad * 8 * 2);
   dW = al(Bp * g.K_pad * 8);
   counter = (unsigned long long *)al(8);

@@ -34,11 +34,15 @@ struct Workspace {
   void *F = nullptr, *Yatt = nullptr;   // B_pad * N_pad * 8 bytes each
   double *Lline = nullptr;
   double *gvec = nullptr, *gnoise = nullptr;
-  double *gbuf = nullptr;        // adjoint scratch (see adjoint.hip)
+  double *gbuf = nullptr;        // adjoint per-point sums [B_pad][16]
+  double *mbuf = nullptr;        // model at sorted rows [B_pad][n_data] (gradient pass)
+  double *scr = nullptr;         // adjoint per-node / per-pixel scratch [B_pad][ld_scr]
+  int ld_scr = 0;
+  double *dLl = nullptr;         // adjoint d logL / d L_line [B_pad][n_line]
   void *G = nullptr;             // adjoint [B_pad][N_pad] float/double
   void *dW = nullptr;            // adjoint [B_pad][K_pad] float/double
   unsigned long long *counter = nullptr;
-  sps_status create(const sps_library *L, int max_batch, int n_data);
+  sps_status create(const sps_library *L, int max_batch, int n_data, int n_fnodes);
 };
 
 // Host copy of an observation's fixed operators and data.
