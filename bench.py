@@ -104,6 +104,80 @@ def cpu_baseline(cfg_name, budget_s=12.0, seed=0):
                        f"(FP64 NumPy, BLAS dgemm contraction), {dt:.1f} s")
 
 
+def serve_leg(seconds, rate_hz=50.0, target_load=0.5, seed=0, log=None):
+    """Poisson stream of photometry / prism-spectrum fit requests served by sps_server on
+    the alpha-enhanced library in FP16.  Capacity is measured first with a saturating
+    burst; n_iter is then chosen so that the offered load is ``target_load`` of it."""
+    import paper_2609_30145_amd as sps
+    from synth import workloads as wl
+    log = log or (lambda m: None)
+    cfg = wl.CONFIGS["c4"]
+    lib = wl.make_library(cfg, seed + 40)
+    dust = wl.make_dust_tables(cfg, lib["wave"])
+    L = sps.Library(lib, n_sfh=cfg.n_sfh, T1=cfg.T1, n_zh=cfg.n_zh, cosmo=cfg.cosmo, dust=dust,
+                    precisions=("fp16",))
+    del lib
+    pool = [wl.make_theta(cfg, 1024, seed=seed + 300 + i) for i in range(8)]
+    rng = np.random.default_rng(seed + 9)
+
+    def obs_of(q):
+        d = 1e-9 * np.exp(rng.normal(0.0, 0.3, q["size"]))
+        if q["kind"] == "phot":
+            return dict(filters=wl.make_filters("gaussN", q["size"]), data=d, sigma=0.05 * d)
+        g = wl.make_spectrum_grid(q["size"])
+        return dict(pix_wave=g["pix_wave"], lsf_mode="R_fwhm", lsf_value=100.0, z_ref=float(rng.uniform(0.5, 12)),
+                    sigma_gas_kms=100.0, data=d, sigma=0.05 * d)
+
+    def run(reqs, n_iter, paced):
+        S = sps.Server(L, precision="fp16", max_points=16384, max_active=256, hbm_budget_bytes=8 << 30)
+        tickets, t0, last = [], time.perf_counter(), time.perf_counter()
+        for q in reqs:
+            if paced:
+                dt = q["arrival_s"] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+            th = pool[q["id"] % len(pool)][:q["B"]]
+            tickets.append(S.submit(q["kind"], th, n_iter=n_iter, seed=q["seed"], **obs_of(q)))
+            if time.perf_counter() - last > 5.0:
+                last = time.perf_counter()
+                log(f"serve: submitted {len(tickets)}/{len(reqs)}")
+        states = []
+        for t in tickets:
+            states.append(S.wait(t, timeout_s=600)["state"])
+            S.release(t)
+        st = S.stats()
+        S.close()
+        st["wall_s"] = time.perf_counter() - t0
+        st["failed"] = sum(s != "done" for s in states)
+        return st
+
+    burst = wl.make_requests(48, rate_hz=1e6, seed=seed + 11)
+    cap = run(burst, 8, False)
+    log(f"serve: capacity {cap['evals_per_s']:.3g} evals/s ({cap['mean_points_per_tick']:.0f} points/tick)")
+    n_req = max(1, int(round(seconds * rate_hz)))
+    reqs = wl.make_requests(n_req, rate_hz=rate_hz, seed=seed + 12)
+    mean_B = float(np.mean([q["B"] for q in reqs]))
+    n_iter = int(max(1, round(target_load * cap["evals_per_s"] / (rate_hz * mean_B) - 1)))
+    st = run(reqs, n_iter, True)
+    offered = rate_hz * mean_B * (n_iter + 1)
+    log(f"serve: {n_req} requests, n_iter {n_iter}, p50/p99 phot {st['p50_latency_s'][0]:.3f}/"
+        f"{st['p99_latency_s'][0]:.3f} s spec {st['p50_latency_s'][1]:.3f}/{st['p99_latency_s'][1]:.3f} s")
+    r = lambda v: round(float(v), 4)
+    return {"workload": f"c4: library {cfg.n_age} ages x {len(cfg.logz)} Z x {len(cfg.afe)} afe x {cfg.n_wave} "
+                        f"wavelengths in fp16 (+residual); Poisson {rate_hz:g} req/s for {seconds:g} s; 50/50 "
+                        f"photometry (8-25 bands) / prism (400-3000 px); B_r in 64..1024",
+            "requests": n_req, "n_iter": n_iter, "evals_per_request_mean": r(mean_B * (n_iter + 1)),
+            "capacity_evals_per_s": r(cap["evals_per_s"]), "offered_evals_per_s": r(offered),
+            "offered_load": r(offered / cap["evals_per_s"]),
+            "evals_per_s_busy": r(st["evals_per_s"]), "evals_per_s_wall": r(st["evals"] / st["wall_s"]),
+            "p50_latency_s": {"phot": r(st["p50_latency_s"][0]), "spec": r(st["p50_latency_s"][1])},
+            "p99_latency_s": {"phot": r(st["p99_latency_s"][0]), "spec": r(st["p99_latency_s"][1])},
+            "completed": {"phot": st["completed_by_kind"][0], "spec": st["completed_by_kind"][1]},
+            "failed": st["failed"], "rejected": st["rejected"], "mean_points_per_tick": r(st["mean_points_per_tick"]),
+            "mean_admission_wait_s": r(st["mean_queue_s"]), "max_admission_wait_s": r(st["max_queue_s"]),
+            "hbm_peak_bytes": st["hbm_peak"], "hbm_budget_bytes": st["hbm_budget"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +187,10 @@ def main():
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--also", default="fp32,bf16", help="other precisions timed for the record")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the Poisson request stream of the serving leg (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build",
@@ -122,6 +200,15 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib << 18
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}))
+        return
     precs = [args.precision] + [p for p in args.also.split(",") if p and p != args.precision]
     cfg, lib, lines, dust, L, O, theta = build_workload(args.workload, tuple(precs))
     B = theta.shape[0]
@@ -169,6 +256,8 @@ def main():
         "by_precision": {p: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                          for p, r in results.items()},
     }
+    if args.serve_seconds > 0:
+        out["serving"] = serve_leg(args.serve_seconds, log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

@@ -4,7 +4,7 @@ The compute path is the HIP library libsps.so (C ABI in include/sps.h); this
 package holds its build script and a thin ctypes binding.  Importing the
 binding does not require a GPU; calling it does.
 """
-from .sps import (PRECISIONS, Library, Observation, SpsError, forward, lib, logl,  # noqa: F401
+from .sps import (PRECISIONS, Library, Observation, Server, SpsError, forward, lib, logl,  # noqa: F401
                   logl_grad)
 
-__all__ = ["Library", "Observation", "SpsError", "forward", "logl", "logl_grad", "lib", "PRECISIONS"]
+__all__ = ["Library", "Observation", "Server", "SpsError", "forward", "logl", "logl_grad", "lib", "PRECISIONS"]

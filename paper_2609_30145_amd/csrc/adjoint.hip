@@ -583,16 +583,16 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
           const int ia = nf > 1 ? ja + q : 0;
           const double fa = nf > 1 ? (q == 0 ? 1.0 - ta : ta) : 1.0;
           if (nz > 1) {
-            wrow[a.kpos[(ia * nz + zj[i]) * na + ag]] += fa * (1.0 - zt[i]) * w;
-            wrow[a.kpos[(ia * nz + zj[i] + 1) * na + ag]] += fa * zt[i] * w;
+            wrow[kpos_of(lib, ia, zj[i], ag)] += fa * (1.0 - zt[i]) * w;
+            wrow[kpos_of(lib, ia, zj[i] + 1, ag)] += fa * zt[i] * w;
           } else {
-            wrow[a.kpos[ia * nz * na + ag]] += fa * w;
+            wrow[kpos_of(lib, ia, 0, ag)] += fa * w;
           }
         }
       }
       double s = 0.0;
       for (int ia = 0; ia < nf; ++ia)
-        for (int m = 0; m < nz; ++m) s += wrow[a.kpos[(ia * nz + m) * na + ag]] * lib.Q[(ia * nz + m) * ny + ag];
+        for (int m = 0; m < nz; ++m) s += wrow[kpos_of(lib, ia, m, ag)] * lib.Q[(ia * nz + m) * ny + ag];
       wq[ag] = s;
       gwq[ag] = 0.0;
     }
@@ -604,15 +604,16 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
     grid_split_dev(lib.un, lib.n_u, th[TH_GAS_LOGU], ju, tu, iu);
     const double dtg = ig ? 1.0 / (lib.zg[jg + 1] - lib.zg[jg]) : 0.0;
     const double dtu = iu ? 1.0 / (lib.un[ju + 1] - lib.un[ju]) : 0.0;
-    const int nzg = lib.n_zg, nu = lib.n_u;
+    const int nu = lib.n_u;
     // thread per age: sum over lines in a fixed order
     for (int ag = tid; ag < ny; ag += 256) {
       double gs = 0.0, gzg = 0.0, gu = 0.0;
       for (int l = 0; l < lib.n_line; ++l) {
         const double gL = pr.kind == 0 ? gacc[a.line_k0 + l] / kLsun : a.dLl[(size_t)r * lib.n_line + l];
-        const double *tb = lib.line_table + ((size_t)l * ny + ag) * nzg * nu;
-        const double t00 = tb[jg * nu + ju], t01 = tb[jg * nu + ju + 1];
-        const double t10 = tb[(jg + 1) * nu + ju], t11 = tb[(jg + 1) * nu + ju + 1];
+        const size_t slab = (size_t)lib.n_line * ny;
+        const double *tb = lib.line_table + (size_t)l * ny + ag;
+        const double t00 = tb[(jg * nu + ju) * slab], t01 = tb[(jg * nu + ju + 1) * slab];
+        const double t10 = tb[((jg + 1) * nu + ju) * slab], t11 = tb[((jg + 1) * nu + ju + 1) * slab];
         const double lh = (1 - tg) * (1 - tu) * t00 + (1 - tg) * tu * t01 + tg * (1 - tu) * t10 + tg * tu * t11;
         const double E = exp10(lh);
         gs += gL * E;
@@ -627,7 +628,7 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
     __syncthreads();
     for (int ag = tid; ag < ny; ag += 256)
       for (int ia = 0; ia < nf; ++ia)
-        for (int m = 0; m < nz; ++m) gacc[a.kpos[(ia * nz + m) * na + ag]] += gwq[ag] * lib.Q[(ia * nz + m) * ny + ag];
+        for (int m = 0; m < nz; ++m) gacc[kpos_of(lib, ia, m, ag)] += gwq[ag] * lib.Q[(ia * nz + m) * ny + ag];
     __syncthreads();
   }
 
@@ -658,12 +659,12 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
         const double dfa = nf > 1 ? (q == 0 ? -dta : dta) : 0.0;
         double gA;
         if (nz > 1) {
-          const double g0 = gacc[a.kpos[(ia * nz + zj[i]) * na + ag]];
-          const double g1 = gacc[a.kpos[(ia * nz + zj[i] + 1) * na + ag]];
+          const double g0 = gacc[kpos_of(lib, ia, zj[i], ag)];
+          const double g1 = gacc[kpos_of(lib, ia, zj[i] + 1, ag)];
           gA = (1.0 - zt[i]) * g0 + zt[i] * g1;
           gzi += fa * zd[i] * w * (g1 - g0);
         } else {
-          gA = gacc[a.kpos[ia * nz * na + ag]];
+          gA = gacc[kpos_of(lib, ia, 0, ag)];
         }
         gw += fa * gA;
         gafe += dfa * w * gA;

@@ -126,10 +126,12 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
       return fail(SPS_E_INVAL, "line wavelengths and table axes must be strictly increasing");
     if (!finite_all(d->line_table, (size_t)nl * ny * d->n_zg * d->n_u)) return fail(SPS_E_INVAL, "line table not finite");
   }
-  int dev_count = 0;
-  if (hipGetDeviceCount(&dev_count) != hipSuccess || d->device < 0 || d->device >= dev_count)
-    return fail(SPS_E_HIP, "no HIP device %d", d->device);
-  if (hipSetDevice(d->device) != hipSuccess) return fail(SPS_E_HIP, "hipSetDevice(%d) failed", d->device);
+  if (d->device >= 0) {
+    int dev_count = 0;
+    if (hipGetDeviceCount(&dev_count) != hipSuccess || d->device >= dev_count)
+      return fail(SPS_E_HIP, "no HIP device %d", d->device);
+    if (hipSetDevice(d->device) != hipSuccess) return fail(SPS_E_HIP, "hipSetDevice(%d) failed", d->device);
+  }
 
   auto *L = new sps_library();
   L->device = d->device;
@@ -142,6 +144,11 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   L->n_sfh = d->n_sfh;
   L->n_zh = d->n_zh;
   L->precisions = d->precisions | (1u << SPS_FP32);
+  L->wave_h.assign(d->wave, d->wave + N);
+  L->logz_lo = d->logz[0];
+  L->logz_hi = d->logz[nz - 1];
+  L->afe_lo = nf > 1 ? d->afe[0] : 0.0;
+  L->afe_hi = nf > 1 ? d->afe[nf - 1] : 0.0;
   DevLib &g = L->dev;
   memset(&g, 0, sizeof g);
   g.n_age = na;
@@ -172,6 +179,7 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   g.K_pad = K_pad;
   g.K_young_pad = K_young_pad;
   std::vector<int> kpos((size_t)nf * nz * na), ksrc(K_pad, INT_MIN);
+  g.zmajor = d->n_zh > 0 ? 0 : 1;
   auto place = [&](int a0, int a1, int kbase) {
     int k = kbase;
     if (d->n_zh > 0) {
@@ -189,6 +197,12 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   for (int s = 0; s < nf * nz * na; ++s) ksrc[kpos[s]] = s;
   L->line_k0 = kyo;
   for (int l = 0; l < nl; ++l) ksrc[kyo + l] = -1 - l;
+
+  if (d->device < 0) {   // host-only library: layout and observation operators only
+    L->precisions = 0;
+    *out = L;
+    return SPS_OK;
+  }
 
   // ---- static per-wavelength tables
   const int Np = g.N_pad;
@@ -310,7 +324,15 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   double *Q = (double *)al((size_t)std::max(1, nf * nz * ny) * 8);
   g.Q = Q;
   if (nl > 0) {
-    g.line_table = (const double *)up(d->line_table, (size_t)nl * ny * d->n_zg * d->n_u * 8);
+    // stored as [zg][u][line][age]: for one (Z_gas, U) corner the (line, age) slab is contiguous
+    std::vector<double> ltT((size_t)nl * ny * d->n_zg * d->n_u);
+    for (int l = 0; l < nl; ++l)
+      for (int a = 0; a < ny; ++a)
+        for (int ig = 0; ig < d->n_zg; ++ig)
+          for (int iu = 0; iu < d->n_u; ++iu)
+            ltT[(((size_t)ig * d->n_u + iu) * nl + l) * ny + a] =
+                d->line_table[(((size_t)l * ny + a) * d->n_zg + ig) * d->n_u + iu];
+    g.line_table = (const double *)up(ltT.data(), ltT.size() * 8);
     g.zg = (const double *)up(d->zg_nodes, d->n_zg * 8);
     g.un = (const double *)up(d->u_nodes, d->n_u * 8);
     g.line_wave = (const double *)up(d->line_wave, nl * 8);
@@ -387,7 +409,7 @@ extern "C" sps_status sps_library_info_get(const sps_library *L, sps_library_inf
 
 extern "C" void sps_library_destroy(sps_library *L) {
   if (!L) return;
-  (void)hipSetDevice(L->device);
+  if (L->device >= 0) (void)hipSetDevice(L->device);
   delete L;
 }
 
@@ -438,6 +460,11 @@ sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsH
   h.kind = d->kind;
   if (d->kind == SPS_OBS_PHOT) {
     if (d->n_band < 1 || d->n_band > 256) return fail(SPS_E_SHAPE, "n_band must be in [1, 256]");
+    {
+      long tot = 0;
+      for (int b = 0; d->filter_len && b < d->n_band; ++b) tot += d->filter_len[b];
+      if (tot > 4096) return fail(SPS_E_SHAPE, "at most 4096 filter nodes per observation");
+    }
     if (!d->filter_len || !d->filter_wave || !d->filter_trans) return fail(SPS_E_INVAL, "filter arrays are NULL");
     h.n_data = d->n_band;
     h.band_off.assign(1, 0);
@@ -465,7 +492,9 @@ sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsH
       if (!(zp > 0)) return fail(SPS_E_INVAL, "filter %d has zero transmission", b);
       for (int j = 0; j < n; ++j) {
         h.fw.push_back(lam[j]);
+        h.fwln.push_back(std::log(lam[j]));
         h.fr.push_back(num[j] / zp);
+        h.fr_f.push_back((float)(num[j] / zp));
       }
       off += n;
       h.band_off.push_back((int)off);
@@ -548,6 +577,7 @@ sps_status set_obs_data(ObsHost &h, const double *data, const double *sigma, con
 extern "C" sps_status sps_obs_create(const sps_library *L, const sps_obs_desc *d, sps_obs **out, uint32_t *warnings) {
   if (!L || !d || !out) return fail(SPS_E_INVAL, "sps_obs_create: NULL argument");
   *out = nullptr;
+  if (L->device < 0) return fail(SPS_E_STATE, "host-only library: observations need a device library");
   if (d->max_batch < 1 || d->max_batch > (1 << 20)) return fail(SPS_E_SHAPE, "max_batch must be in [1, 2^20]");
   if (hipSetDevice(L->device) != hipSuccess) return fail(SPS_E_HIP, "hipSetDevice failed");
   auto *o = new sps_obs();
@@ -585,30 +615,28 @@ extern "C" void sps_obs_destroy(sps_obs *o) {
 // =====================================================================================
 namespace sps {
 
-static bool precision_built(const sps_library *L, int p) { return p >= 0 && p <= 7 && (L->precisions >> p) & 1u; }
+bool precision_built(const sps_library *L, int p) { return p >= 0 && p <= 7 && (L->precisions >> p) & 1u; }
 
-sps_status run_forward(const sps_library *L, sps_obs *o, const double *theta, int B, int prec, double *logl,
-                       double *model, bool want_grad_buffers, hipStream_t s) {
-  if (!L || !o || !theta) return fail(SPS_E_INVAL, "NULL argument");
-  if (o->lib != L) return fail(SPS_E_INVAL, "observation belongs to another library");
-  if (B < 1 || B > o->ws.max_batch) return fail(SPS_E_SHAPE, "B=%d outside [1, max_batch=%d]", B, o->ws.max_batch);
+sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_table, const int *point_obs,
+                          const double *theta, int B, int prec, double *logl, double *model, int ld_model,
+                          bool grad, int ld_g, sps_obs *timing_obs, hipStream_t s) {
+  if (B < 1 || B > w.max_batch) return fail(SPS_E_SHAPE, "B=%d outside [1, max_batch=%d]", B, w.max_batch);
   if (!precision_built(L, prec)) return fail(SPS_E_INVAL, "precision %d not built into this library", prec);
-  Workspace &w = o->ws;
   const DevLib &g = L->dev;
   const int B_pad = (B + kMAlign - 1) / kMAlign * kMAlign;
   // the thread's HIP last-error slot may hold a stale code set by another library's
   // call; clear it so that only this call's own launches are checked below
   (void)hipGetLastError();
   const int mode = prec == 0 ? 0 : prec == 1 ? 1 : (prec == 2 || prec == 4 || prec == 6) ? 2 : 3;
-  hipError_t e = launch_sort(g, theta, g.P, B, w.perm, s);
+  hipError_t e = launch_sort(g, theta, g.P, B, w.keys, w.perm, s);
   PrepLaunch pl;
   pl.theta = theta;
   pl.P = g.P;
   pl.B = B;
   pl.B_pad = B_pad;
   pl.perm = w.perm;
-  pl.obs_table = o->dev_obs;
-  pl.point_obs = nullptr;
+  pl.obs_table = obs_table;
+  pl.point_obs = point_obs;
   pl.W = w.W;
   pl.Wlo = (char *)w.W + (size_t)B_pad * g.K_pad * 2;
   pl.rowmask = w.rowmask;
@@ -633,13 +661,13 @@ sps_status run_forward(const sps_library *L, sps_obs *o, const double *theta, in
   cl.n_act = w.n_act;
   cl.rows = w.rows;
   cl.F = w.F;
-  cl.Yatt = want_grad_buffers ? w.Yatt : nullptr;
+  cl.Yatt = grad ? w.Yatt : nullptr;
   cl.precision = prec;
-  if (e == hipSuccess) e = o->timing_begin(s, B_pad / MT, g.K_pad / (kKTile * tf));
+  if (e == hipSuccess && timing_obs) e = timing_obs->timing_begin(s, B_pad / MT, g.K_pad / (kKTile * tf));
   if (e == hipSuccess) e = launch_contract(g, cl, s);
-  if (e == hipSuccess) e = o->timing_end(s);
+  if (e == hipSuccess && timing_obs) e = timing_obs->timing_end(s);
   ProjectLaunch pj;
-  pj.obs_table = o->dev_obs;
+  pj.obs_table = obs_table;
   pj.rows = w.rows;
   pj.F = w.F;
   pj.f64 = prec == 0;
@@ -649,14 +677,22 @@ sps_status run_forward(const sps_library *L, sps_obs *o, const double *theta, in
   pj.Lline = w.Lline;
   pj.model = model;
   pj.logl = logl;
-  pj.gvec = want_grad_buffers ? w.gvec : nullptr;
-  pj.gnoise = want_grad_buffers ? w.gnoise : nullptr;
-  pj.msorted = want_grad_buffers ? w.mbuf : nullptr;
-  pj.ld_model = o->host.n_data;
-  pj.ld_g = o->host.n_data;
+  pj.gvec = grad ? w.gvec : nullptr;
+  pj.gnoise = grad ? w.gnoise : nullptr;
+  pj.msorted = grad ? w.mbuf : nullptr;
+  pj.ld_model = ld_model;
+  pj.ld_g = ld_g;
   if (e == hipSuccess) e = launch_project(g, pj, s);
   if (e != hipSuccess) return fail(SPS_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
   return SPS_OK;
+}
+
+sps_status run_forward(const sps_library *L, sps_obs *o, const double *theta, int B, int prec, double *logl,
+                       double *model, bool want_grad_buffers, hipStream_t s) {
+  if (!L || !o || !theta) return fail(SPS_E_INVAL, "NULL argument");
+  if (o->lib != L) return fail(SPS_E_INVAL, "observation belongs to another library");
+  return launch_forward(L, o->ws, o->dev_obs, nullptr, theta, B, prec, logl, model, o->host.n_data,
+                        want_grad_buffers, o->host.n_data, o, s);
 }
 
 }  // namespace sps

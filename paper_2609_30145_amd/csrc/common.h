@@ -38,12 +38,13 @@ struct DevLib {
   int n_age, n_z, n_afe, N, N_pad, K, K_pad, K_young_pad, n_young, n_line, n_zg, n_u;
   int n_sfh, n_zh, P, n_gl;
   int log_uniform;                   // wave grid uniform in ln(lambda) (direct indexing)
+  int zmajor;                        // K order: 0 age-major, 1 metallicity-major (see kpos_of)
   double T1, H0, Om, t_young;
   double lnw0, inv_dlnw;             // ln(lambda_0) and 1/dln(lambda) when log_uniform
   const double *cell_lo, *cell_hi;   // [n_age] linear-time Voronoi cells
   const double *logz, *afe;          // nodes
   const double *Q;                   // [n_afe][n_z][n_young] photons/s/Msun
-  const double *line_table;          // [n_line][n_young][n_zg][n_u]
+  const double *line_table;          // [n_zg][n_u][n_line][n_young]
   const double *zg, *un;             // nebular table axes
   const double *line_wave;           // [n_line] rest A
   const double *line_a, *line_d;     // dust shape tables at the line wavelengths
@@ -68,6 +69,7 @@ struct DevObs {
   int kind, n_data, n_band, n_fnodes, noise_flags, lsf_mode, has_curve, pad;
   const int *band_off;               // [n_band+1]
   const double *fw;                  // [n_fnodes] filter node wavelengths (observer A)
+  const double *fwln;                // [n_fnodes] their natural logarithms
   const double *fr_d;                // R_j lambda_j dlambda_j / zero point  (eq. E1)
   const float *fr_f;
   const double *pix, *lnpix;         // [n_pix]
@@ -111,10 +113,32 @@ __device__ __forceinline__ int lower_bound_dev(const T *x, int n, T v) {
   return lo;
 }
 
+// K position of SSP node (alpha ia, metallicity m, age a) in the young-first order:
+// young ages (a < n_young) first, then the line rows, then old ages, each segment
+// padded; inside a segment age-major (a, m, ia) or metallicity-major (m, ia, a).
+__device__ __forceinline__ int kpos_of(const DevLib &lib, int ia, int m, int a) {
+  const int nz = lib.n_z, nf = lib.n_afe, ny = lib.n_young;
+  if (a < ny) return lib.zmajor ? (m * nf + ia) * ny + a : (a * nz + m) * nf + ia;
+  const int no = lib.n_age - ny, ao = a - ny;
+  return lib.K_young_pad + (lib.zmajor ? (m * nf + ia) * no + ao : (ao * nz + m) * nf + ia);
+}
+
 // k with wave[k] <= lr < wave[k+1] (lr inside the grid), limited to [0, N-2]
 __device__ __forceinline__ int wave_bracket(const DevLib &lib, double lr) {
   if (lib.log_uniform) {
     int k = (int)floor((log(lr) - lib.lnw0) * lib.inv_dlnw);
+    k = min(max(k, 0), lib.N - 2);
+    while (k > 0 && lib.wave_d[k] > lr) --k;
+    while (k < lib.N - 2 && lib.wave_d[k + 1] <= lr) ++k;
+    return k;
+  }
+  return bracket(lib.wave_d, lib.N, lr);
+}
+
+// as wave_bracket with ln(lr) supplied by the caller
+__device__ __forceinline__ int wave_bracket_ln(const DevLib &lib, double lr, double lnlr) {
+  if (lib.log_uniform) {
+    int k = (int)floor((lnlr - lib.lnw0) * lib.inv_dlnw);
     k = min(max(k, 0), lib.N - 2);
     while (k > 0 && lib.wave_d[k] > lr) --k;
     while (k < lib.N - 2 && lib.wave_d[k + 1] <= lr) ++k;

@@ -82,8 +82,8 @@ __device__ __forceinline__ void bc32p(double (&acc)[BM][BN][16], const float (*s
 
 // PRECISE (gradient pass): each 32-wide K tile is accumulated in FP32 and the tile
 // partials are summed in FP64.
-template <int MT, int NT, int WM, int WN, bool PRECISE>
-__global__ void __launch_bounds__(256) k_contract_f32(ContractArgs a) {
+template <int MT, int NT, int WM, int WN, bool PRECISE, int MINW = 1>
+__global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
   constexpr int KT = 32, LDSK = KT + 4;
   constexpr int WTM = MT / WM, WTN = NT / WN, BM = WTM / 32, BN = WTN / 32;
   static_assert(WM * WN == 4, "4 waves");
@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(256) k_contract_f64(ContractArgs a) {
 }
 
 // ---------------------------------------------------------------------------------
-int contract_mtile(int precision) { return precision == 0 ? 64 : 128; }
+int contract_mtile(int precision) { return precision <= 1 ? 64 : 128; }
 int contract_ktile_factor(int precision) { return precision >= 2 ? 2 : 1; }
 
 hipError_t launch_contract16_impl(const DevLib &lib, const void *W, const void *Wlo, const int *tiles,
@@ -340,9 +340,9 @@ hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStrea
   } else if (cl.precision == 1) {
     a.LTa = lib.LT32;
     if (cl.Yatt)
-      hipLaunchKernelGGL((k_contract_f32<128, 64, 2, 2, true>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, true, 2>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
     else
-      hipLaunchKernelGGL((k_contract_f32<128, 64, 2, 2, false>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, false, 2>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
   } else {
     return launch_contract16_impl(lib, cl.W, cl.Wlo, cl.tiles, cl.n_young, cl.n_act, cl.rows, cl.F, cl.Yatt,
                                   cl.precision, n_mt, s);

@@ -63,8 +63,8 @@ __device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[6], 
 }
 
 // PASSES: 1 = W_h H; 2 = W_h H + W_h R; 3 = W_h H + W_h R + W_l H
-template <bool BF, int PASSES, int MT, int NT, int WM, int WN>
-__global__ void __launch_bounds__(256) k_contract_16(ContractArgs16 a) {
+template <bool BF, int PASSES, int MT, int NT, int WM, int WN, int MINW = 1>
+__global__ void __launch_bounds__(256, MINW) k_contract_16(ContractArgs16 a) {
   constexpr int KT = 64, LDSK = KT + 8;   // 16-bit elements per LDS row
   constexpr int WTM = MT / WM, WTN = NT / WN, BM = WTM / 32, BN = WTN / 32;
   constexpr bool USE_WL = PASSES >= 3, USE_R = PASSES >= 2;
@@ -206,7 +206,7 @@ struct ContractArgs;   // FP32/FP64 argument block (contract.hip)
 
 template <bool BF, int PASSES>
 static void launch16(const ContractArgs16 &a, int n_mt, int N_pad, hipStream_t s) {
-  hipLaunchKernelGGL((k_contract_16<BF, PASSES, 128, 128, 2, 2>), dim3(n_mt * (N_pad / 128)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_contract_16<BF, PASSES, 128, 64, 4, 1, 2>), dim3(n_mt * (N_pad / 64)), dim3(256), 0, s, a);
 }
 
 hipError_t launch_contract16_impl(const DevLib &lib, const void *W, const void *Wlo, const int *tiles,

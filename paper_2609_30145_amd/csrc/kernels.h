@@ -21,7 +21,7 @@ struct PrepLaunch {
 };
 
 size_t prep_smem_bytes(const DevLib &lib);
-hipError_t launch_sort(const DevLib &lib, const double *theta, int P, int B, int *perm, hipStream_t s);
+hipError_t launch_sort(const DevLib &lib, const double *theta, int P, int B, double *keys, int *perm, hipStream_t s);
 hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s);
 hipError_t launch_tiles(const uint32_t *rowmask, int mask_words, int B_pad, int MT, int n_tiles32, int young_tiles32,
                         int tf, int *tiles, int *n_young, int *n_act, unsigned long long *counter, hipStream_t s);

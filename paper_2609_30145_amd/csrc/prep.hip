@@ -22,18 +22,20 @@ __device__ double sort_key(const DevLib &lib, const double *th) {
   return (double)jz * 1.0e6 + (double)ja * 1.0e4 + fmin(fmax(z, 0.0), 9.0e3);
 }
 
+__global__ void __launch_bounds__(256) k_keys(DevLib lib, const double *__restrict__ theta, int P, int B,
+                                              double *__restrict__ keys) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b < B) keys[b] = sort_key(lib, theta + (size_t)b * P);
+}
+
 // One workgroup per point: rank = number of points with a smaller (key, index).
-__global__ void __launch_bounds__(256) k_sort(DevLib lib, const double *__restrict__ theta, int P, int B,
-                                              int *__restrict__ perm) {
+__global__ void __launch_bounds__(256) k_sort(const double *__restrict__ keys, int B, int *__restrict__ perm) {
   __shared__ int cnt[256];
-  __shared__ double s_my;
   const int b = blockIdx.x;
-  if (threadIdx.x == 0) s_my = sort_key(lib, theta + (size_t)b * P);
-  __syncthreads();
-  const double my = s_my;
+  const double my = keys[b];
   int c = 0;
   for (int j = threadIdx.x; j < B; j += 256) {
-    const double kj = sort_key(lib, theta + (size_t)j * P);
+    const double kj = keys[j];
     c += (kj < my) || (kj == my && j < b);
   }
   cnt[threadIdx.x] = c;
@@ -245,10 +247,10 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
         const double fa = nf > 1 ? (q == 0 ? 1.0 - ta : ta) : 1.0;
         const int base = ia * nz;
         if (nz > 1) {
-          wacc[a.kpos[(base + j) * na + ag]] += fa * (1.0 - t) * w;
-          wacc[a.kpos[(base + j + 1) * na + ag]] += fa * t * w;
+          wacc[kpos_of(lib, ia, j, ag)] += fa * (1.0 - t) * w;
+          wacc[kpos_of(lib, ia, j + 1, ag)] += fa * t * w;
         } else {
-          wacc[a.kpos[base * na + ag]] += fa * w;
+          wacc[kpos_of(lib, ia, 0, ag)] += fa * w;
         }
       }
     }
@@ -264,7 +266,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       double s = 0.0;
       for (int ia = 0; ia < nf; ++ia)
         for (int m = 0; m < nz; ++m)
-          s += wacc[a.kpos[(ia * nz + m) * na + ag]] * lib.Q[(ia * nz + m) * ny + ag];
+          s += wacc[kpos_of(lib, ia, m, ag)] * lib.Q[(ia * nz + m) * ny + ag];
       wq[ag] = s;
     }
     __syncthreads();
@@ -273,13 +275,15 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     bool in;
     grid_split_dev(lib.zg, lib.n_zg, s_th[TH_GAS_LOGZ], jg, tg, in);
     grid_split_dev(lib.un, lib.n_u, s_th[TH_GAS_LOGU], ju, tu, in);
-    const int nzg = lib.n_zg, nu = lib.n_u;
+    const int nu = lib.n_u;
     double *lt = wq + ny;   // [n_line * n_young] per (line, age) luminosity terms
     for (int q = tid; q < lib.n_line * ny; q += 256) {
       const int l = q / ny, ag = q - l * ny;
-      const double *tb = lib.line_table + ((size_t)l * ny + ag) * nzg * nu;
-      const double lh = (1.0 - tg) * (1.0 - tu) * tb[jg * nu + ju] + (1.0 - tg) * tu * tb[jg * nu + ju + 1] +
-                        tg * (1.0 - tu) * tb[(jg + 1) * nu + ju] + tg * tu * tb[(jg + 1) * nu + ju + 1];
+      const size_t slab = (size_t)lib.n_line * ny;
+      const double *tb = lib.line_table + q;
+      const double lh = (1.0 - tg) * (1.0 - tu) * tb[(jg * nu + ju) * slab] +
+                        (1.0 - tg) * tu * tb[(jg * nu + ju + 1) * slab] +
+                        tg * (1.0 - tu) * tb[((jg + 1) * nu + ju) * slab] + tg * tu * tb[((jg + 1) * nu + ju + 1) * slab];
       lt[q] = exp10(lh) * wq[ag];
     }
     __syncthreads();
@@ -428,8 +432,9 @@ size_t prep_smem_bytes(const DevLib &lib) {
          sizeof(int) * ((size_t)lib.n_sfh + 2);
 }
 
-hipError_t launch_sort(const DevLib &lib, const double *theta, int P, int B, int *perm, hipStream_t s) {
-  hipLaunchKernelGGL(k_sort, dim3(B), dim3(256), 0, s, lib, theta, P, B, perm);
+hipError_t launch_sort(const DevLib &lib, const double *theta, int P, int B, double *keys, int *perm, hipStream_t s) {
+  hipLaunchKernelGGL(k_keys, dim3((B + 255) / 256), dim3(256), 0, s, lib, theta, P, B, keys);
+  hipLaunchKernelGGL(k_sort, dim3(B), dim3(256), 0, s, keys, B, perm);
   return hipGetLastError();
 }
 

@@ -42,7 +42,8 @@ __device__ double sigma_inst_mode(int mode, double v, double lam) {
 template <typename T>
 __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
   __shared__ double red[256];
-  __shared__ double s_lnl[512], s_sl[512], s_amp[512];   // per-line (spectra)
+  __shared__ double sbuf[4096];   // photometry: per-node terms; spectra: per-line tables
+  double *s_lnl = sbuf, *s_sl = sbuf + 512, *s_amp = sbuf + 1024;
   __shared__ double s_noise[4];
   const int r = blockIdx.x;
   const PointRow pr = a.rows[r];
@@ -89,20 +90,48 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
   if (ob.kind == 0) {
     // ---------------- photometry (eq. E1-E2): f_lambda^obs(lambda_j) = fac * F(lambda_j/(1+z))
     const double fac = kC_cms * pr.scale_fnu / (opz * opz * kAng_cm * kAng_cm);
+    const double lnopz = log1p(z);
+    const double wlo = lib.wave_d[0], whi = lib.wave_d[N - 1];
+    // one pass over all filter nodes, four per thread in flight, terms kept in LDS
+    for (int j0 = tid; j0 < ob.n_fnodes; j0 += 1024) {
+      int kq[4];
+      double lrq[4];
+      bool in[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + 256 * q;
+        in[q] = false;
+        kq[q] = 0;
+        lrq[q] = 0.0;
+        if (j < ob.n_fnodes) {
+          lrq[q] = ob.fw[j] / opz;
+          in[q] = lrq[q] >= wlo && lrq[q] <= whi;
+          if (in[q]) kq[q] = wave_bracket_ln(lib, lrq[q], ob.fwln[j] - lnopz);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + 256 * q;
+        if (j >= ob.n_fnodes) break;
+        double term = 0.0;
+        if (in[q]) {
+          const int k = kq[q];
+          const T t = (T)((lrq[q] - lib.wave_d[k]) / (lib.wave_d[k + 1] - lib.wave_d[k]));
+          const T f = Fr[k] + t * (Fr[k + 1] - Fr[k]);
+          const T w = sizeof(T) == 8 ? (T)ob.fr_d[j] : (T)ob.fr_f[j];
+          term = (double)(w * f);
+        }
+        sbuf[j] = term;
+      }
+    }
+    __syncthreads();
+    // fixed-order band sums: one wave per band
     const int wave_id = tid >> 6, lane = tid & 63;
     for (int band = wave_id; band < ob.n_band; band += 4) {
       const int j0 = ob.band_off[band], j1 = ob.band_off[band + 1];
       double part = 0.0;
-      for (int j = j0 + lane; j < j1; j += 64) {
-        const double lr = ob.fw[j] / opz;
-        if (lr < lib.wave_d[0] || lr > lib.wave_d[N - 1]) continue;
-        const int k = wave_bracket(lib, lr);
-        const T t = (T)((lr - lib.wave_d[k]) / (lib.wave_d[k + 1] - lib.wave_d[k]));
-        const T f = Fr[k] + t * (Fr[k + 1] - Fr[k]);
-        const T w = sizeof(T) == 8 ? (T)ob.fr_d[j] : (T)ob.fr_f[j];
-        part += (double)(w * f);
-      }
-      double s = wave_reduce_sum(part);
+      for (int j = j0 + lane; j < j1; j += 64) part += sbuf[j];
+      const double s = wave_reduce_sum(part);
       if (lane == 0) red[band] = s;
     }
     __syncthreads();

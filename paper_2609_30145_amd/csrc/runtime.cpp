@@ -2,18 +2,16 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "kernels.h"
 
 using namespace sps;
 
-void sps_library::host_wave(std::vector<double> &w) const {
-  w.resize(N);
-  (void)hipMemcpy(w.data(), dev.wave_d, (size_t)N * 8, hipMemcpyDeviceToHost);
-}
+void sps_library::host_wave(std::vector<double> &w) const { w = wave_h; }
 
-sps_status Workspace::create(const sps_library *L, int mb, int n_data, int n_fnodes) {
+sps_status Workspace::create(const sps_library *L, int mb, int n_data, int n_fnodes, bool forward_only) {
   const DevLib &g = L->dev;
   max_batch = mb;
   B_pad_max = (mb + kMAlign - 1) / kMAlign * kMAlign;
@@ -26,6 +24,7 @@ sps_status Workspace::create(const sps_library *L, int mb, int n_data, int n_fno
     return p;
   };
   perm = (int *)al(Bp * 4);
+  keys = (double *)al(Bp * 8);
   W = al(Bp * g.K_pad * 8);
   rowmask = (uint32_t *)al(Bp * mask_words * 4);
   const size_t n_mt = Bp / 64, n_kt = g.K_pad / kKTile;
@@ -34,17 +33,18 @@ sps_status Workspace::create(const sps_library *L, int mb, int n_data, int n_fno
   n_act = (int *)al(n_mt * 4);
   rows = (PointRow *)al(Bp * sizeof(PointRow));
   F = al(Bp * g.N_pad * 8);
-  Yatt = al(Bp * g.N_pad * 8);
+  const size_t gb = forward_only ? 1 : Bp;   // gradient-pass buffers
+  Yatt = al(gb * g.N_pad * 8);
   Lline = (double *)al(Bp * (size_t)std::max(1, g.n_line) * 8);
-  gvec = (double *)al(Bp * (size_t)std::max(1, n_data) * 8);
-  gnoise = (double *)al(Bp * 4 * 8);
-  gbuf = (double *)al(Bp * 16 * 8);
-  mbuf = (double *)al(Bp * (size_t)std::max(1, n_data) * 8);
+  gvec = (double *)al(gb * (size_t)std::max(1, n_data) * 8);
+  gnoise = (double *)al(gb * 4 * 8);
+  gbuf = (double *)al(gb * 16 * 8);
+  mbuf = (double *)al(gb * (size_t)std::max(1, n_data) * 8);
   ld_scr = std::max(3 * n_fnodes, 8 * n_data);
-  scr = (double *)al(Bp * (size_t)ld_scr * 8);
-  dLl = (double *)al(Bp * (size_t)std::max(1, g.n_line) * 8);
-  G = al(Bp * g.N_pad * 8 * 2);
-  dW = al(Bp * g.K_pad * 8);
+  scr = (double *)al(gb * (size_t)std::max(1, ld_scr) * 8);
+  dLl = (double *)al(gb * (size_t)std::max(1, g.n_line) * 8);
+  G = al(gb * g.N_pad * 8 * 2);
+  dW = al(gb * g.K_pad * 8);
   counter = (unsigned long long *)al(8);
   if (!ok) return fail(SPS_E_NOMEM, "workspace allocation failed (max_batch=%d)", mb);
   if (hipMemset(counter, 0, 8) != hipSuccess) return fail(SPS_E_HIP, "hipMemset failed");
@@ -56,44 +56,74 @@ sps_obs::~sps_obs() {
   for (auto e : ev_stop) (void)hipEventDestroy(e);
 }
 
-sps_status sps_obs::upload_operators() {
-  DevObs &o = dobs;
+namespace sps {
+
+static size_t r256(size_t n) { return (n + 255) / 256 * 256; }
+
+int64_t obs_device_bytes(const ObsHost &h) {
+  size_t b = 0;
+  if (h.kind == SPS_OBS_PHOT) {
+    b += r256(h.band_off.size() * 4) + 3 * r256(h.fw.size() * 8) + r256(h.fw.size() * 4);
+  } else {
+    b += 3 * r256(h.pix.size() * 8) + (h.lsf_vals.empty() ? 0 : r256(h.lsf_vals.size() * 8));
+  }
+  b += 2 * r256((size_t)h.n_data * 8) + r256((size_t)h.n_data);
+  return (int64_t)b;
+}
+
+// Uploads operators and data of an observation into `mem` (asynchronously on `s`;
+// the host vectors must stay alive until `s` has drained).
+sps_status upload_obs(const ObsHost &host, DevObs &o, DeviceBuffers &mem, hipStream_t s) {
   memset(&o, 0, sizeof o);
   o.kind = host.kind;
   o.n_data = host.n_data;
   o.noise_flags = host.noise_flags;
   bool ok = true;
-  auto up = [&](const void *h, size_t n) {
-    void *p = opmem.upload(h, n);
-    ok = ok && p;
+  auto put = [&](const void *h, size_t n) -> void * {
+    void *p = mem.alloc(n);
+    if (!p) {
+      ok = false;
+      return nullptr;
+    }
+    if (h && hipMemcpyAsync(p, h, n, hipMemcpyHostToDevice, s) != hipSuccess) ok = false;
     return p;
   };
   if (host.kind == SPS_OBS_PHOT) {
     o.n_band = host.n_data;
     o.n_fnodes = (int)host.fw.size();
-    o.band_off = (const int *)up(host.band_off.data(), host.band_off.size() * 4);
-    o.fw = (const double *)up(host.fw.data(), host.fw.size() * 8);
-    o.fr_d = (const double *)up(host.fr.data(), host.fr.size() * 8);
-    std::vector<float> frf(host.fr.begin(), host.fr.end());
-    o.fr_f = (const float *)up(frf.data(), frf.size() * 4);
+    o.band_off = (const int *)put(host.band_off.data(), host.band_off.size() * 4);
+    o.fw = (const double *)put(host.fw.data(), host.fw.size() * 8);
+    o.fwln = (const double *)put(host.fwln.data(), host.fwln.size() * 8);
+    o.fr_d = (const double *)put(host.fr.data(), host.fr.size() * 8);
+    o.fr_f = (const float *)put(host.fr_f.data(), host.fr_f.size() * 4);
   } else {
-    o.pix = (const double *)up(host.pix.data(), host.pix.size() * 8);
-    o.lnpix = (const double *)up(host.lnpix.data(), host.lnpix.size() * 8);
-    o.ksig = (const double *)up(host.ksig.data(), host.ksig.size() * 8);
+    o.pix = (const double *)put(host.pix.data(), host.pix.size() * 8);
+    o.lnpix = (const double *)put(host.lnpix.data(), host.lnpix.size() * 8);
+    o.ksig = (const double *)put(host.ksig.data(), host.ksig.size() * 8);
     o.lsf_mode = host.lsf_mode;
     o.lsf_value = host.lsf_value;
     o.has_curve = host.lsf_vals.empty() ? 0 : 1;
-    if (o.has_curve) o.lsf_vals = (const double *)up(host.lsf_vals.data(), host.lsf_vals.size() * 8);
+    if (o.has_curve) o.lsf_vals = (const double *)put(host.lsf_vals.data(), host.lsf_vals.size() * 8);
     o.sigma_gas_kms = host.sigma_gas;
   }
+  o.data = (const double *)put(host.data.data(), (size_t)host.n_data * 8);
+  o.sigma = (const double *)put(host.sigma.data(), (size_t)host.n_data * 8);
+  o.mask = (const uint8_t *)put(host.mask.data(), (size_t)host.n_data);
   if (!ok) return fail(SPS_E_NOMEM, "observation upload failed");
-  // data buffers are allocated once; later updates copy into them
-  o.data = (const double *)datamem.alloc((size_t)host.n_data * 8);
-  o.sigma = (const double *)datamem.alloc((size_t)host.n_data * 8);
-  o.mask = (const uint8_t *)datamem.alloc((size_t)host.n_data);
+  return SPS_OK;
+}
+
+}  // namespace sps
+
+sps_status sps_obs::upload_operators() {
+  sps_status st = upload_obs(host, dobs, opmem, nullptr);
+  if (st != SPS_OK) return st;
   dev_obs = (DevObs *)opmem.alloc(sizeof(DevObs));
-  if (!o.data || !o.sigma || !o.mask || !dev_obs) return fail(SPS_E_NOMEM, "observation upload failed");
-  return upload_data();
+  if (!dev_obs) return fail(SPS_E_NOMEM, "observation upload failed");
+  if (hipMemcpy(dev_obs, &dobs, sizeof(DevObs), hipMemcpyHostToDevice) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess)
+    return fail(SPS_E_HIP, "observation upload failed");
+  return SPS_OK;
 }
 
 sps_status sps_obs::upload_data() {
@@ -101,7 +131,6 @@ sps_status sps_obs::upload_data() {
   hipError_t e = hipMemcpy((void *)dobs.data, host.data.data(), n * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy((void *)dobs.sigma, host.sigma.data(), n * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy((void *)dobs.mask, host.mask.data(), n, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(dev_obs, &dobs, sizeof(DevObs), hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(SPS_E_HIP, "observation data upload failed: %s", hipGetErrorString(e));
   return SPS_OK;
 }

@@ -27,6 +27,7 @@ struct Workspace {
   DeviceBuffers mem;
   int max_batch = 0, B_pad_max = 0, mask_words = 0;
   int *perm = nullptr;
+  double *keys = nullptr;       // batch-ordering keys [B_pad]
   void *W = nullptr;             // B_pad * K_pad * 8 bytes
   uint32_t *rowmask = nullptr;
   int *tiles = nullptr, *n_young = nullptr, *n_act = nullptr;
@@ -42,14 +43,15 @@ struct Workspace {
   void *G = nullptr;             // adjoint [B_pad][N_pad] float/double
   void *dW = nullptr;            // adjoint [B_pad][K_pad] float/double
   unsigned long long *counter = nullptr;
-  sps_status create(const sps_library *L, int max_batch, int n_data, int n_fnodes);
+  sps_status create(const sps_library *L, int max_batch, int n_data, int n_fnodes, bool forward_only = false);
 };
 
 // Host copy of an observation's fixed operators and data.
 struct ObsHost {
   int kind = 0, n_data = 0, noise_flags = 0, lsf_mode = 0;
   std::vector<int> band_off;
-  std::vector<double> fw, fr;
+  std::vector<double> fw, fwln, fr;
+  std::vector<float> fr_f;
   std::vector<double> pix, lnpix, ksig, lsf_vals;
   double lsf_value = 0, sigma_gas = 0;
   std::vector<double> data, sigma;
@@ -62,7 +64,9 @@ sps_status set_obs_data(ObsHost &h, const double *data, const double *sigma, con
 }  // namespace sps
 
 struct sps_library {
-  int device = 0;
+  int device = 0;                  // -1: host-only (layout and operators, no device copies)
+  double logz_lo = 0, logz_hi = 0, afe_lo = 0, afe_hi = 0;
+  std::vector<double> wave_h;      // host copy of the wavelength grid
   int n_age = 0, n_z = 0, n_afe = 0, N = 0, n_young = 0, n_line = 0, n_sfh = 0, n_zh = 0;
   int line_k0 = 0;
   uint32_t precisions = 0;
@@ -77,8 +81,7 @@ struct sps_obs {
   sps::ObsHost host;
   sps::DevObs dobs;
   sps::DevObs *dev_obs = nullptr;
-  sps::DeviceBuffers opmem;        // operators
-  sps::DeviceBuffers datamem;      // data, sigma, mask
+  sps::DeviceBuffers opmem;        // operators and data
   sps::Workspace ws;
   // contraction timing
   bool timing = false;
@@ -100,4 +103,13 @@ sps_status run_forward(const sps_library *L, sps_obs *o, const double *theta, in
                        double *model, bool want_grad_buffers, hipStream_t s);
 sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, int B, int prec, double *grad,
                        hipStream_t s);
+// The forward launch sequence on an explicit workspace and observation table
+// (point_obs: observation slot per point, NULL = slot 0).
+sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_table, const int *point_obs,
+                          const double *theta, int B, int prec, double *logl, double *model, int ld_model,
+                          bool grad, int ld_g, sps_obs *timing_obs, hipStream_t s);
+bool precision_built(const sps_library *L, int p);
+// Device copies of an observation's operators and data (used by sps_obs and the server).
+sps_status upload_obs(const ObsHost &h, DevObs &o, DeviceBuffers &mem, hipStream_t s);
+int64_t obs_device_bytes(const ObsHost &h);
 }  // namespace sps

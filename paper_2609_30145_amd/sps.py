@@ -126,6 +126,8 @@ class Library:
 
     def __init__(self, lib_arrays: dict, n_sfh: int, T1: float, n_zh: int, cosmo=(70.0, 0.3),
                  dust: dict | None = None, lines: dict | None = None, precisions=("fp32",), device: int = 0):
+        """``device=-1`` loads a host-only library (layout and observation operators; used by
+        the mock server executor)."""
         L = lib()
         keep = []
         ages, logz, wave = _arr(lib_arrays["ages"]), _arr(lib_arrays["logz"]), _arr(lib_arrays["wave"])
@@ -301,3 +303,155 @@ def logl_grad(library, obs, theta, precision="fp32", stream=None):
                               PRECISIONS[precision], C.c_void_p(out.data_ptr()), C.c_void_p(grad.data_ptr()),
                               _stream_ptr(stream)))
     return out, grad
+
+
+# ---------------------------------------------------------------------------------
+# Request server (include/sps_server.h)
+# ---------------------------------------------------------------------------------
+class ServerDesc(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_points", C.c_int32), ("max_active", C.c_int32),
+                ("precision", C.c_int32), ("device", C.c_int32), ("mock_eval_ns", C.c_double)]
+
+
+class Request(C.Structure):
+    _fields_ = [("obs", ObsDesc), ("B", C.c_int32), ("theta0", _dp), ("n_iter", C.c_int32), ("seed", C.c_uint64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("state", C.c_int32), ("B", C.c_int32), ("P", C.c_int32), ("kind", C.c_int32),
+                ("theta", _dp), ("logl", _dp), ("queue_s", C.c_double), ("latency_s", C.c_double),
+                ("evals", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("cancelled", C.c_int64), ("active", C.c_int64), ("pending", C.c_int64), ("ticks", C.c_int64),
+                ("evals", C.c_int64), ("busy_s", C.c_double), ("evals_per_s", C.c_double),
+                ("mean_points_per_tick", C.c_double), ("p50_latency_s", C.c_double * 2),
+                ("p99_latency_s", C.c_double * 2), ("completed_by_kind", C.c_int64 * 2),
+                ("mean_queue_s", C.c_double), ("max_queue_s", C.c_double), ("hbm_in_use", C.c_int64),
+                ("hbm_peak", C.c_int64), ("hbm_budget", C.c_int64)]
+
+
+REQ_STATES = {0: "pending", 1: "active", 2: "done", 3: "cancelled", 4: "failed"}
+
+
+def _server_lib():
+    L = lib()
+    if not getattr(L, "_server_bound", False):
+        vp = C.c_void_p
+        L.sps_server_create.argtypes = [vp, C.POINTER(ServerDesc), C.POINTER(vp)]
+        L.sps_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
+        L.sps_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result)]
+        L.sps_wait.argtypes = [vp, C.c_uint64, C.c_int64, C.POINTER(Result)]
+        L.sps_cancel.argtypes = [vp, C.c_uint64]
+        L.sps_release.argtypes = [vp, C.c_uint64]
+        L.sps_server_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.sps_server_destroy.argtypes = [vp]
+        L.sps_server_destroy.restype = None
+        for n in ("sps_server_create", "sps_submit", "sps_poll", "sps_wait", "sps_cancel", "sps_release",
+                  "sps_server_stats"):
+            getattr(L, n).restype = C.c_int32
+        L._server_bound = True
+    return L
+
+
+def _obs_desc(kind, filters=None, pix_wave=None, lsf_mode="R_fwhm", lsf_value=100.0, z_ref=0.0,
+              sigma_gal_kms=0.0, sigma_gas_kms=0.0, data=None, sigma=None, noise=(), keep=None):
+    d = ObsDesc()
+    d.kind = OBS_PHOT if kind == "phot" else OBS_SPEC
+    if kind == "phot":
+        lens = _arr([len(f[0]) for f in filters], np.int32)
+        fw = _arr(np.concatenate([f[0] for f in filters]))
+        ft = _arr(np.concatenate([f[1] for f in filters]))
+        keep += [lens, fw, ft]
+        d.n_band, d.filter_len, d.filter_wave, d.filter_trans = len(filters), _ptr(lens, C.c_int32), _ptr(fw), \
+            _ptr(ft)
+    else:
+        pw = _arr(pix_wave)
+        keep.append(pw)
+        d.n_pix, d.pix_wave, d.lsf_mode, d.lsf_value = len(pw), _ptr(pw), LSF_MODES[lsf_mode], float(lsf_value)
+        d.z_ref, d.sigma_gal_kms, d.sigma_gas_kms = float(z_ref), float(sigma_gal_kms), float(sigma_gas_kms)
+    if data is not None:
+        da, sg = _arr(data), _arr(sigma)
+        keep += [da, sg]
+        d.data, d.sigma = _ptr(da), _ptr(sg)
+    flags = 0
+    for n in noise:
+        flags |= NOISE[n]
+    d.noise_flags = flags
+    return d
+
+
+class Server:
+    """Continuous-batching request server (sps_server_*).  ``device=-1`` selects the
+    host-only mock executor, which needs no GPU (scheduler tests)."""
+
+    def __init__(self, library, hbm_budget_bytes=8 << 30, max_points=16384, max_active=256, precision="fp16",
+                 device=0, mock_eval_ns=0.0):
+        L = _server_lib()
+        d = ServerDesc(int(hbm_budget_bytes), int(max_points), int(max_active), PRECISIONS[precision], int(device),
+                       float(mock_eval_ns))
+        h = C.c_void_p()
+        check(L.sps_server_create(library.handle, C.byref(d), C.byref(h)))
+        self.handle = h
+        self.library = library
+
+    def submit(self, kind, theta0, n_iter, seed, **obs):
+        keep = []
+        th = _arr(theta0)
+        keep.append(th)
+        q = Request()
+        q.obs = _obs_desc(kind, keep=keep, **obs)
+        q.B = th.shape[0]
+        q.theta0 = _ptr(th)
+        q.n_iter = int(n_iter)
+        q.seed = int(seed)
+        t = C.c_uint64()
+        check(_server_lib().sps_submit(self.handle, C.byref(q), C.byref(t)))
+        return t.value
+
+    @staticmethod
+    def _result(r):
+        out = dict(state=REQ_STATES[r.state], B=r.B, P=r.P, kind=("phot", "spec")[r.kind], queue_s=r.queue_s,
+                   latency_s=r.latency_s, evals=r.evals)
+        if r.state == 2:
+            out["theta"] = np.ctypeslib.as_array(r.theta, shape=(r.B * r.P,)).reshape(r.B, r.P).copy()
+            out["logl"] = np.ctypeslib.as_array(r.logl, shape=(r.B,)).copy()
+        return out
+
+    def poll(self, ticket):
+        r = Result()
+        code = check(_server_lib().sps_poll(self.handle, ticket, C.byref(r)))
+        return None if code == SPS_PENDING else self._result(r)
+
+    def wait(self, ticket, timeout_s=None):
+        r = Result()
+        us = -1 if timeout_s is None else int(timeout_s * 1e6)
+        check(_server_lib().sps_wait(self.handle, ticket, us, C.byref(r)))
+        return self._result(r)
+
+    def cancel(self, ticket):
+        check(_server_lib().sps_cancel(self.handle, ticket))
+
+    def release(self, ticket):
+        check(_server_lib().sps_release(self.handle, ticket))
+
+    def stats(self):
+        s = Stats()
+        check(_server_lib().sps_server_stats(self.handle, C.byref(s)))
+        out = {n: getattr(s, n) for n, _ in Stats._fields_}
+        for k in ("p50_latency_s", "p99_latency_s", "completed_by_kind"):
+            out[k] = list(out[k])
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _server_lib().sps_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

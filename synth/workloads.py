@@ -341,7 +341,10 @@ def perturb_theta(cfg: Config, theta: np.ndarray, scale: float, seed: int) -> np
     s0, n = cols["sfh"], cfg.n_sfh
     m = th[:, s0:s0 + n] * np.exp(scale * rng.normal(size=(B, n)))
     th[:, s0:s0 + n] = m / m.sum(axis=1, keepdims=True)
+    # metallicities stay strictly inside the grid (away from the clamp at its ends)
     zlo_g, zhi_g = min(cfg.logz), max(cfg.logz)
+    margin = 1e-3 * (zhi_g - zlo_g)
+    zlo_g, zhi_g = zlo_g + margin, zhi_g - margin
     if cfg.n_zh:
         z0 = cols["zh"]
         th[:, z0:z0 + cfg.n_zh] = np.clip(th[:, z0:z0 + cfg.n_zh]
@@ -349,6 +352,10 @@ def perturb_theta(cfg: Config, theta: np.ndarray, scale: float, seed: int) -> np
     else:
         th[:, cols["logzsol"]] = np.clip(th[:, cols["logzsol"]] + scale * rng.normal(size=B),
                                          zlo_g, zhi_g)
+    if len(cfg.afe) > 1:
+        alo, ahi = min(cfg.afe), max(cfg.afe)
+        am = 1e-3 * (ahi - alo)
+        th[:, cols["afe"]] = np.clip(th[:, cols["afe"]], alo + am, ahi - am)
     return th
 
 
