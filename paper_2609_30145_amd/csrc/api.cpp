@@ -177,6 +177,7 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   const int K_pad = K_young_pad + round_up(kold, kKAlign);
   g.K = nf * nz * na + nl;
   g.K_pad = K_pad;
+  if (K_pad > 65536) return fail(SPS_E_SHAPE, "library too large: %d weight rows after padding (at most 65536)", K_pad);
   g.K_young_pad = K_young_pad;
   std::vector<int> kpos((size_t)nf * nz * na), ksrc(K_pad, INT_MIN);
   g.zmajor = d->n_zh > 0 ? 0 : 1;
@@ -288,6 +289,8 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
     }
   }
 
+  if (prep_smem_bytes(g, 0) > 160 * 1024)
+    return fail(SPS_E_SHAPE, "library too large for the per-point weight builder (%zu bytes of LDS)", prep_smem_bytes(g, 0));
   // ---- device copies
   DeviceBuffers &mem = L->mem;
   bool ok = true;
@@ -333,6 +336,8 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
             ltT[(((size_t)ig * d->n_u + iu) * nl + l) * ny + a] =
                 d->line_table[(((size_t)l * ny + a) * d->n_zg + ig) * d->n_u + iu];
     g.line_table = (const double *)up(ltT.data(), ltT.size() * 8);
+    std::vector<float> ltF(ltT.begin(), ltT.end());
+    g.line_table_f = (const float *)up(ltF.data(), ltF.size() * 4);
     g.zg = (const double *)up(d->zg_nodes, d->n_zg * 8);
     g.un = (const double *)up(d->u_nodes, d->n_u * 8);
     g.line_wave = (const double *)up(d->line_wave, nl * 8);

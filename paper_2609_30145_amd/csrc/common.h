@@ -45,6 +45,7 @@ struct DevLib {
   const double *logz, *afe;          // nodes
   const double *Q;                   // [n_afe][n_z][n_young] photons/s/Msun
   const double *line_table;          // [n_zg][n_u][n_line][n_young]
+  const float *line_table_f;         // the same in FP32 (FP32 and 16-bit paths)
   const double *zg, *un;             // nebular table axes
   const double *line_wave;           // [n_line] rest A
   const double *line_a, *line_d;     // dust shape tables at the line wavelengths

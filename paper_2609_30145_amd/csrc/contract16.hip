@@ -22,12 +22,24 @@ struct ContractArgs16 {
   float *F, *Yatt;
 };
 
-__device__ __forceinline__ void tile_of_block16(int n_ntiles, int &mt, int &nt) {
+// Block -> (M tile, N tile).  The hardware deals consecutive blocks round-robin to the
+// 8 XCDs; XCD x takes the consecutive tiles [x*nblk/8, (x+1)*nblk/8) of the order
+// (N tile, then M tile), so the XCDs split the library columns and each holds a share
+// of every M tile (M tiles differ in their active K-tile counts).  The M tiles of N tile
+// n are rotated by 3*(n/4) so that the blocks l, l+32, l+64 of an XCD, which tend to
+// share a CU, come from different M tiles.
+__device__ __forceinline__ void tile_of_block16(int n_mt, int n_nt, int &mt, int &nt) {
   const int nblk = gridDim.x, bid = blockIdx.x;
-  int logical = bid;
-  if ((nblk & 7) == 0) logical = (bid & 7) * (nblk >> 3) + (bid >> 3);
-  mt = logical / n_ntiles;
-  nt = logical - mt * n_ntiles;
+  if ((nblk & 7) != 0) {
+    mt = bid / n_nt;
+    nt = bid - mt * n_nt;
+    return;
+  }
+  const int per = nblk >> 3, l = bid >> 3;
+  const int logical = (bid & 7) * per + l;
+  const int n = logical / n_mt, mm = logical - n * n_mt;
+  mt = (mm + 3 * (n >> 2)) % n_mt;
+  nt = n;
 }
 
 template <bool BF, int PASSES>
@@ -62,24 +74,28 @@ __device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[6], 
     }
 }
 
-// PASSES: 1 = W_h H; 2 = W_h H + W_h R; 3 = W_h H + W_h R + W_l H
-template <bool BF, int PASSES, int MT, int NT, int WM, int WN, int MINW = 1>
-__global__ void __launch_bounds__(256, MINW) k_contract_16(ContractArgs16 a) {
-  constexpr int KT = 64, LDSK = KT + 8;   // 16-bit elements per LDS row
-  constexpr int WTM = MT / WM, WTN = NT / WN, BM = WTM / 32, BN = WTN / 32;
+// PASSES: 1 = W_h H; 2 = W_h H + W_h R; 3 = W_h H + W_h R + W_l H.
+// Block tile 128 (points) x 64 (wavelengths), K tile 64; four waves stacked along M,
+// each 32 x 64 (two 32x32x16 MFMA accumulators).  The next K tile is prefetched into
+// registers while the current one is multiplied out of LDS.  LDS rows are unpadded with
+// the 16-byte chunks XOR-swizzled by the row, so three blocks fit a CU.
+template <bool BF, int PASSES>
+__global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
+  constexpr int MT = 128, NT = 64, KT = 64, NCH = KT / 8, WTM = 32, WTN = 64, BM = 1, BN = 2;
   constexpr bool USE_WL = PASSES >= 3, USE_R = PASSES >= 2;
   constexpr int A8 = MT * KT / 8 / 256, B8 = NT * KT / 8 / 256;   // 16-byte chunks per thread
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[MT * LDSK];
-  __shared__ __attribute__((aligned(16))) uint16_t Al[USE_WL ? MT * LDSK : 8];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[NT * LDSK];
-  __shared__ __attribute__((aligned(16))) uint16_t Br[USE_R ? NT * LDSK : 8];
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[MT * KT];
+  __shared__ __attribute__((aligned(16))) uint16_t Al[USE_WL ? MT * KT : 8];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[NT * KT];
+  __shared__ __attribute__((aligned(16))) uint16_t Br[USE_R ? NT * KT : 8];
   __shared__ float sp[MT][6];
+#define SPS_SW(r_, c_) ((r_) * KT + (((c_) ^ ((r_) & (NCH - 1))) << 3))
 
+  const int n_nt = a.N_pad / NT;
   int mt, nt;
-  tile_of_block16(a.N_pad / NT, mt, nt);
+  tile_of_block16(gridDim.x / n_nt, n_nt, mt, nt);
   const int m0 = mt * MT, n0 = nt * NT;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
+  const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6, wn = 0;
   const int li = lane & 31, lh = lane >> 5;
   const int K_pad = a.K_pad;
 
@@ -94,11 +110,9 @@ __global__ void __launch_bounds__(256, MINW) k_contract_16(ContractArgs16 a) {
   }
   v16f acc[BM][BN];
 #pragma unroll
-  for (int i = 0; i < BM; ++i)
+  for (int j = 0; j < BN; ++j)
 #pragma unroll
-    for (int j = 0; j < BN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+    for (int e = 0; e < 16; ++e) acc[0][j][e] = 0.f;
 
   const int nact = a.n_act[mt], ny = a.n_young[mt];
   const int *tl = a.tiles + (size_t)mt * a.n_tiles;
@@ -108,13 +122,13 @@ __global__ void __launch_bounds__(256, MINW) k_contract_16(ContractArgs16 a) {
   {                                                                            \
     const int k0_ = tl[t_] * KT;                                               \
     _Pragma("unroll") for (int q = 0; q < A8; ++q) {                           \
-      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;             \
+      const int idx = tid + 256 * q, row = idx / NCH, c8 = idx % NCH;          \
       const size_t o = (size_t)(m0 + row) * K_pad + k0_ + c8 * 8;              \
       rah[q] = *(const u32x4 *)(a.Wh + o);                                     \
       if constexpr (USE_WL) ral[q] = *(const u32x4 *)(a.Wl + o);               \
     }                                                                          \
     _Pragma("unroll") for (int q = 0; q < B8; ++q) {                           \
-      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;             \
+      const int idx = tid + 256 * q, row = idx / NCH, c8 = idx % NCH;          \
       const size_t o = (size_t)(n0 + row) * K_pad + k0_ + c8 * 8;              \
       rbh[q] = *(const u32x4 *)(a.H + o);                                      \
       if constexpr (USE_R) rbr[q] = *(const u32x4 *)(a.R + o);                 \
@@ -124,7 +138,7 @@ __global__ void __launch_bounds__(256, MINW) k_contract_16(ContractArgs16 a) {
   float c_lnlv[BN], c_a[BN], c_d[BN];
 #pragma unroll
   for (int j = 0; j < BN; ++j) {
-    const int col = n0 + wn * WTN + j * 32 + li;
+    const int col = n0 + j * 32 + li;
     c_lnlv[j] = a.lnlv[col];
     c_a[j] = a.da[col];
     c_d[j] = a.dd[col];
@@ -135,78 +149,68 @@ __global__ void __launch_bounds__(256, MINW) k_contract_16(ContractArgs16 a) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < A8; ++q) {
-      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;
-      *(u32x4 *)(Ah + row * LDSK + c8 * 8) = rah[q];
-      if constexpr (USE_WL) *(u32x4 *)(Al + row * LDSK + c8 * 8) = ral[q];
+      const int idx = tid + 256 * q, row = idx / NCH, c8 = idx % NCH;
+      *(u32x4 *)(Ah + SPS_SW(row, c8)) = rah[q];
+      if constexpr (USE_WL) *(u32x4 *)(Al + SPS_SW(row, c8)) = ral[q];
     }
 #pragma unroll
     for (int q = 0; q < B8; ++q) {
-      const int idx = tid + 256 * q, row = idx >> 3, c8 = idx & 7;
-      *(u32x4 *)(Bh + row * LDSK + c8 * 8) = rbh[q];
-      if constexpr (USE_R) *(u32x4 *)(Br + row * LDSK + c8 * 8) = rbr[q];
+      const int idx = tid + 256 * q, row = idx / NCH, c8 = idx % NCH;
+      *(u32x4 *)(Bh + SPS_SW(row, c8)) = rbh[q];
+      if constexpr (USE_R) *(u32x4 *)(Br + SPS_SW(row, c8)) = rbr[q];
     }
     __syncthreads();
     if (t + 1 < nact) SPS_GLOAD16(t + 1);
     if (t == ny) bc16<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
+    // lane half lh takes chunks lh*4 .. lh*4+3 of the K tile (the same permutation of
+    // K for both operands, so each MFMA still sums matching products)
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int kofs = lh * 32 + s * 8;
-      u32x4 fa[BM], fl[BM], fb[BN], fr[BN];
-#pragma unroll
-      for (int i = 0; i < BM; ++i) {
-        const int row = wm * WTM + i * 32 + li;
-        fa[i] = *(const u32x4 *)(Ah + row * LDSK + kofs);
-        if constexpr (USE_WL) fl[i] = *(const u32x4 *)(Al + row * LDSK + kofs);
-      }
+      const int ch = lh * 4 + s;
+      u32x4 fa, fl, fb[BN], fr[BN];
+      fa = *(const u32x4 *)(Ah + SPS_SW(wm * WTM + li, ch));
+      if constexpr (USE_WL) fl = *(const u32x4 *)(Al + SPS_SW(wm * WTM + li, ch));
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
-        const int col = wn * WTN + j * 32 + li;
-        fb[j] = *(const u32x4 *)(Bh + col * LDSK + kofs);
-        if constexpr (USE_R) fr[j] = *(const u32x4 *)(Br + col * LDSK + kofs);
+        fb[j] = *(const u32x4 *)(Bh + SPS_SW(j * 32 + li, ch));
+        if constexpr (USE_R) fr[j] = *(const u32x4 *)(Br + SPS_SW(j * 32 + li, ch));
       }
       // the passes are interleaved over the independent accumulators
 #pragma unroll
-      for (int i = 0; i < BM; ++i)
-#pragma unroll
-        for (int j = 0; j < BN; ++j) acc[i][j] = mfma16<BF, PASSES>(fa[i], fb[j], acc[i][j]);
+      for (int j = 0; j < BN; ++j) acc[0][j] = mfma16<BF, PASSES>(fa, fb[j], acc[0][j]);
       if constexpr (USE_R) {
 #pragma unroll
-        for (int i = 0; i < BM; ++i)
-#pragma unroll
-          for (int j = 0; j < BN; ++j) acc[i][j] = mfma16<BF, PASSES>(fa[i], fr[j], acc[i][j]);
+        for (int j = 0; j < BN; ++j) acc[0][j] = mfma16<BF, PASSES>(fa, fr[j], acc[0][j]);
       }
       if constexpr (USE_WL) {
 #pragma unroll
-        for (int i = 0; i < BM; ++i)
-#pragma unroll
-          for (int j = 0; j < BN; ++j) acc[i][j] = mfma16<BF, PASSES>(fl[i], fb[j], acc[i][j]);
+        for (int j = 0; j < BN; ++j) acc[0][j] = mfma16<BF, PASSES>(fl, fb[j], acc[0][j]);
       }
     }
   }
+#undef SPS_GLOAD16
+#undef SPS_SW
   if (ny == nact) {
     __syncthreads();
     bc16<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
   }
-#undef SPS_GLOAD16
 #pragma unroll
-  for (int i = 0; i < BM; ++i)
+  for (int e = 0; e < 16; ++e) {
+    const int rl = wm * WTM + 8 * (e >> 2) + 4 * lh + (e & 3);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
-#pragma unroll
-      for (int j = 0; j < BN; ++j) {
-        const int col = n0 + wn * WTN + j * 32 + li;
-        const float Td = expf(-sp[rl][2] * expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
-        a.F[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j][e] * Td * sp[rl][5];
-      }
+    for (int j = 0; j < BN; ++j) {
+      const int col = n0 + j * 32 + li;
+      const float Td = expf(-sp[rl][2] * expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+      a.F[(size_t)(m0 + rl) * a.N_pad + col] = acc[0][j][e] * Td * sp[rl][5];
     }
+  }
 }
 
 struct ContractArgs;   // FP32/FP64 argument block (contract.hip)
 
 template <bool BF, int PASSES>
 static void launch16(const ContractArgs16 &a, int n_mt, int N_pad, hipStream_t s) {
-  hipLaunchKernelGGL((k_contract_16<BF, PASSES, 128, 64, 4, 1, 2>), dim3(n_mt * (N_pad / 64)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_contract_16<BF, PASSES>), dim3(n_mt * (N_pad / 64)), dim3(256), 0, s, a);
 }
 
 hipError_t launch_contract16_impl(const DevLib &lib, const void *W, const void *Wlo, const int *tiles,

@@ -20,7 +20,7 @@ struct PrepLaunch {
   int mode;   // 0 f64, 1 f32, 2 bf16, 3 f16
 };
 
-size_t prep_smem_bytes(const DevLib &lib);
+size_t prep_smem_bytes(const DevLib &lib, int mode);   // mode as PrepLaunch::mode
 hipError_t launch_sort(const DevLib &lib, const double *theta, int P, int B, double *keys, int *perm, hipStream_t s);
 hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s);
 hipError_t launch_tiles(const uint32_t *rowmask, int mask_words, int B_pad, int MT, int n_tiles32, int young_tiles32,

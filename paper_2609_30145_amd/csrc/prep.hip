@@ -1,9 +1,12 @@
 // Per-point preparation: batch ordering, cosmology, SFH x ZH -> SSP weights, nebular
 // line luminosities and the K-tile occupancy of the contraction.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace sps {
+
 
 // ---------------------------------------------------------------------------------
 // Batch ordering.  Rows that share a redshift (time-varying enrichment) or a
@@ -111,30 +114,93 @@ struct PrepArgs {
   int line_k0;              // K position of line 0 (photometric path)
 };
 
+// bracketing node j and fraction t of x on a short grid held in LDS, clamped; the
+// same (j, t) as grid_split_dev by bisection
+__device__ __forceinline__ void split_lds(const double *nodes, int n, double x, int &j, double &t) {
+  const double xc = fmin(fmax(x, nodes[0]), nodes[n - 1]);
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (nodes[mid] <= xc) lo = mid; else hi = mid;
+  }
+  j = lo;
+  t = (xc - nodes[lo]) / (nodes[lo + 1] - nodes[lo]);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// LDS layout of k_prep, in 8-byte words (the weight row and the line terms are
+// FP64 for the FP64 path and FP32 otherwise).
+struct PrepSmem {
+  int th, logz, afe, clo, chi, zg, un, Q, edges, zt, zj, wq, wacc, lt, total;
+  __host__ __device__ PrepSmem(const DevLib &lib, bool f64) {
+    const int acc = f64 ? 8 : 4;
+    const int nq = lib.n_line > 0 ? lib.n_afe * lib.n_z * lib.n_young : 0;
+    int o = 0;
+    th = o;    o += lib.P;
+    logz = o;  o += lib.n_z;
+    afe = o;   o += lib.n_afe;
+    clo = o;   o += lib.n_age;
+    chi = o;   o += lib.n_age;
+    zg = o;    o += lib.n_zg;
+    un = o;    o += lib.n_u;
+    Q = o;     o += nq;
+    edges = o; o += lib.n_sfh + 1;
+    zt = o;    o += lib.n_sfh;
+    zj = o;    o += (lib.n_sfh + 1) / 2;                  // int
+    wq = o;    o += lib.n_line > 0 ? lib.n_young : 0;
+    wacc = o;  o += (lib.K_pad * acc + 7) / 8;
+    lt = o;    o += (lib.n_line * lib.n_young * acc + 7) / 8;
+    total = o;
+  }
+};
+
+// One workgroup (4 waves) per sorted row:
+//   A1  theta, node tables, cell bounds and photon rates to LDS; weight row cleared;
+//       Gauss-Legendre partial sums of D_C
+//   A2  wave 0: t_univ and the bin edges; the other waves: the bin metallicities and
+//       their bracketing nodes; all waves: the interpolated line terms 10^Lhat (they
+//       depend on the gas parameters only)
+//   B   step-scheme overlap weights, one thread per SSP age (single writer per slot)
+//   C   photon rate per young age, then the line luminosities
+//   D   the row in the contraction's format with its K-tile occupancy bits; the
+//       per-point row (redshift, distances, scales).
 template <int MODE>
 __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
+  using Acc = typename std::conditional<MODE == W_F64, double, float>::type;
   extern __shared__ double smem[];
-  const int K_pad = lib.K_pad;
-  double *wacc = smem;                        // [K_pad]
-  double *edges = wacc + K_pad;               // [n_sfh + 1]
-  double *zt = edges + lib.n_sfh + 1;         // [n_sfh] fraction t
-  int *zj = (int *)(zt + lib.n_sfh);          // [n_sfh] node j
-  double *red = (double *)(zj + ((lib.n_sfh + 1) & ~1));   // [256]
-  double *wq = red + 256;                     // [n_young]
-  __shared__ double s_th[TH_NSCALAR];
-  __shared__ double s_sc[4];
+  const PrepSmem L(lib, MODE == W_F64);
+  const int K_pad = lib.K_pad, na = lib.n_age, nz = lib.n_z, nf = lib.n_afe, ny = lib.n_young;
+  const int n_sfh = lib.n_sfh, nl = lib.n_line;
+  double *s_th = smem + L.th, *s_logz = smem + L.logz, *s_afe = smem + L.afe;
+  double *s_clo = smem + L.clo, *s_chi = smem + L.chi, *s_zg = smem + L.zg, *s_un = smem + L.un;
+  double *s_Q = smem + L.Q, *s_edges = smem + L.edges, *s_zt = smem + L.zt, *s_wq = smem + L.wq;
+  int *s_zj = (int *)(smem + L.zj);
+  Acc *wacc = (Acc *)(smem + L.wacc);
+  Acc *s_lt = (Acc *)(smem + L.lt);
+  __shared__ double s_part[4];
+  __shared__ double s_tu;
+  __shared__ uint32_t s_bits[64];
 
   const int r = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int b = r < a.B ? a.perm[r] : -1;
+  const size_t rowoff = (size_t)r * K_pad;
 
   if (b < 0) {   // padding row: zero weights
     for (int k = tid; k < K_pad; k += 256) {
-      if (MODE == W_F64) ((double *)a.W)[(size_t)r * K_pad + k] = 0.0;
-      else if (MODE == W_F32) ((float *)a.W)[(size_t)r * K_pad + k] = 0.f;
+      if (MODE == W_F64) ((double *)a.W)[rowoff + k] = 0.0;
+      else if (MODE == W_F32) ((float *)a.W)[rowoff + k] = 0.f;
       else {
-        ((uint16_t *)a.W)[(size_t)r * K_pad + k] = 0;
-        ((uint16_t *)a.Wlo)[(size_t)r * K_pad + k] = 0;
+        ((uint16_t *)a.W)[rowoff + k] = 0;
+        ((uint16_t *)a.Wlo)[rowoff + k] = 0;
       }
     }
     for (int w = tid; w < a.mask_words; w += 256) a.rowmask[(size_t)r * a.mask_words + w] = 0u;
@@ -145,211 +211,255 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     }
     return;
   }
+
+  // ---- A1
   const double *th = a.theta + (size_t)b * a.P;
-  if (tid < TH_NSCALAR) s_th[tid] = th[tid];
-  for (int k = tid; k < K_pad; k += 256) wacc[k] = 0.0;
-  __syncthreads();
-
-  // ---- cosmology (Sec. 2.6): t_univ closed form; D_C by composite Gauss-Legendre in
-  //      u = (1+z')^-1/2, where the integrand 2 / sqrt(Om + OL u^6) is smooth.
-  const double z = s_th[TH_ZRED];
+  for (int c = tid; c < a.P; c += 256) s_th[c] = th[c];
+  for (int m = tid; m < nz; m += 256) s_logz[m] = lib.logz[m];
+  for (int m = tid; m < nf; m += 256) s_afe[m] = nf > 1 ? lib.afe[m] : 0.0;
+  for (int g = tid; g < na; g += 256) {
+    s_clo[g] = lib.cell_lo[g];
+    s_chi[g] = lib.cell_hi[g];
+  }
+  if (nl > 0) {
+    for (int m = tid; m < lib.n_zg; m += 256) s_zg[m] = lib.zg[m];
+    for (int m = tid; m < lib.n_u; m += 256) s_un[m] = lib.un[m];
+    for (int q = tid; q < nf * nz * ny; q += 256) s_Q[q] = lib.Q[q];
+  }
+  for (int k = tid; k < K_pad; k += 256) wacc[k] = (Acc)0;
+  if (tid < 64) s_bits[tid] = 0u;
+  // cosmology (Sec. 2.6): D_C by composite Gauss-Legendre in u = (1+z')^-1/2, where
+  // the integrand 2 / sqrt(Om + OL u^6) is smooth
+  const double z = th[TH_ZRED];
   const double Om = lib.Om, OL = 1.0 - lib.Om;
-  const double tH_yr = kMpc_km / lib.H0 / kYr_s;
-  const double DH_mpc = kC_kms / lib.H0;
   const double u0 = 1.0 / sqrt(1.0 + z);
-  double part = 0.0;
-  for (int i = tid; i < lib.n_gl; i += 256) {
-    const double u = u0 + (1.0 - u0) * lib.gl_u[i];
-    const double u2 = u * u;
-    part += lib.gl_w[i] * 2.0 / sqrt(Om + OL * u2 * u2 * u2);
-  }
-  const double dc_int = block_sum<256>(part, red) * (1.0 - u0);
-  if (tid == 0) {
-    const double t_univ = tH_yr * 2.0 / (3.0 * sqrt(OL)) * asinh(sqrt(OL / Om) * pow(1.0 + z, -1.5));
-    s_sc[0] = t_univ;
-    s_sc[1] = DH_mpc * dc_int * kMpc_cm;    // D_C [cm]
-  }
-  __syncthreads();
-  const double t_univ = s_sc[0];
-  const double dc = s_sc[1];
-  const double dl = (1.0 + z) * dc;
-
-  // ---- SFH edges, rescaled to t_univ (App. B, Sec. 2.6)
-  const int n_sfh = lib.n_sfh;
-  const double lnR = log(t_univ / lib.T1);
-  for (int i = tid; i <= n_sfh; i += 256) {
-    double T;
-    if (i == 0) T = 0.0;
-    else if (i == 1) T = lib.T1;
-    else if (i == n_sfh) T = t_univ;
-    else T = lib.T1 * exp(lnR * (double)(i - 1) / (double)(n_sfh - 1));
-    edges[i] = T;
-  }
-  // ---- per-bin metallicity and its bracketing nodes (Sec. 2.2.2)
-  //      time-varying mode: nodes and bin centres are both log-uniform from T1 to
-  //      t_univ, so the interpolation weight in ln T is fixed in the normalised
-  //      coordinate: bin i >= 1 sits at (i - 1/2)/(n_sfh - 1), node k at k/(n_zh - 1);
-  //      the first bin (centre T1/2) is clamped to node 0.
-  const double *zh = th + TH_NSCALAR + n_sfh;
-  for (int i = tid; i < n_sfh; i += 256) {
-    double zeta;
-    if (lib.n_zh == 0) {
-      zeta = s_th[TH_LOGZSOL];
-    } else if (i == 0 || lib.n_zh == 1) {
-      zeta = zh[0];
-    } else {
-      const double x = ((double)i - 0.5) / (double)(n_sfh - 1) * (double)(lib.n_zh - 1);
-      int k = (int)floor(x);
-      if (k >= lib.n_zh - 1) k = lib.n_zh - 2;
-      const double f = x - (double)k;
-      zeta = zh[k] + f * (zh[k + 1] - zh[k]);
+  {
+    double part = 0.0;
+    for (int i = tid; i < lib.n_gl; i += 256) {
+      const double u = u0 + (1.0 - u0) * lib.gl_u[i];
+      const double u2 = u * u;
+      part += lib.gl_w[i] * 2.0 / sqrt(Om + OL * u2 * u2 * u2);
     }
-    int j = 0;
-    double t = 0.0;
-    bool in;
-    if (lib.n_z > 1) grid_split_dev(lib.logz, lib.n_z, zeta, j, t, in);
-    zj[i] = j;
-    zt[i] = t;
-  }
-  int ja = 0;
-  double ta = 0.0;
-  if (lib.n_afe > 1) {
-    bool in;
-    grid_split_dev(lib.afe, lib.n_afe, s_th[TH_AFE], ja, ta, in);
+    part = wave_sum(part);
+    if (lane == 0) s_part[wv] = part;
   }
   __syncthreads();
+  const double dc = kC_kms / lib.H0 * (1.0 - u0) * ((s_part[0] + s_part[1]) + (s_part[2] + s_part[3])) * kMpc_cm;
 
-  // ---- step-scheme overlap weights (App. B): thread per SSP age node, so every
-  //      (alpha, m, a) slot of the LDS row has a single writer.
-  const double *mass = th + TH_NSCALAR;
-  const int na = lib.n_age, nz = lib.n_z, nf = lib.n_afe;
-  for (int ag = tid; ag < na; ag += 256) {
-    const double lo = lib.cell_lo[ag], hi = lib.cell_hi[ag];
-    // first bin whose upper edge exceeds lo
-    int i = 0;
-    {
-      int l = 0, h = n_sfh;   // search over edges[1..n_sfh]
-      while (l < h) {
-        int mid = (l + h) >> 1;
-        if (edges[mid + 1] > lo) h = mid; else l = mid + 1;
+  // ---- A2
+  if (wv == 0) {
+    // t_univ in closed form; SFH edges rescaled to it (App. B, Sec. 2.6): T_0 = 0,
+    // T_1 = T1, T_n = t_univ, log-uniform in between
+    const double tH_yr = kMpc_km / lib.H0 / kYr_s;
+    const double tu = tH_yr * 2.0 / (3.0 * sqrt(OL)) * asinh(sqrt(OL / Om) * pow(1.0 + z, -1.5));
+    const double lnR = log(tu / lib.T1);
+    for (int i = lane; i <= n_sfh; i += 64) {
+      double T;
+      if (i == 0) T = 0.0;
+      else if (i == 1) T = lib.T1;
+      else if (i == n_sfh) T = tu;
+      else T = lib.T1 * exp(lnR * (double)(i - 1) / (double)(n_sfh - 1));
+      s_edges[i] = T;
+    }
+    if (lane == 0) s_tu = tu;
+  } else {
+    // bin metallicity from the enrichment history (Sec. 2.2.2): nodes and bin centres
+    // are both log-uniform from T1 to t_univ, so the interpolation weight in ln T is
+    // fixed in the normalised coordinate (bin i >= 1 at (i - 1/2)/(n_sfh - 1), node k at
+    // k/(n_zh - 1)); the first bin (centre T1/2) takes node 0
+    const double *zh = s_th + TH_NSCALAR + n_sfh;
+    for (int i = tid - 64; i < n_sfh; i += 192) {
+      double zeta;
+      if (lib.n_zh == 0) {
+        zeta = s_th[TH_LOGZSOL];
+      } else if (i == 0) {
+        zeta = zh[0];
+      } else {
+        const double x = ((double)i - 0.5) / (double)(n_sfh - 1) * (double)(lib.n_zh - 1);
+        int k = (int)floor(x);
+        if (k >= lib.n_zh - 1) k = lib.n_zh - 2;
+        const double f = x - (double)k;
+        zeta = zh[k] + f * (zh[k + 1] - zh[k]);
       }
-      i = l;
+      int j = 0;
+      double t = 0.0;
+      if (nz > 1) split_lds(s_logz, nz, zeta, j, t);
+      s_zj[i] = j;
+      s_zt[i] = t;
     }
-    for (; i < n_sfh && edges[i] < hi; ++i) {
-      const double Ti = edges[i], Tj = edges[i + 1];
-      const double ov = fmin(hi, Tj) - fmax(lo, Ti);
-      if (ov <= 0.0) continue;
-      const double w = mass[i] * ov / (Tj - Ti);
-      const int j = zj[i];
-      const double t = zt[i];
-      for (int q = 0; q < (nf > 1 ? 2 : 1); ++q) {
-        const int ia = nf > 1 ? ja + q : 0;
-        const double fa = nf > 1 ? (q == 0 ? 1.0 - ta : ta) : 1.0;
-        const int base = ia * nz;
-        if (nz > 1) {
-          wacc[kpos_of(lib, ia, j, ag)] += fa * (1.0 - t) * w;
-          wacc[kpos_of(lib, ia, j + 1, ag)] += fa * t * w;
+  }
+  if (nl > 0) {
+    // 10^Lhat_l(a): bilinear in (log Z_gas, log U) of the tabulated log values (App. C);
+    // entry q = l * n_young + a, consecutive threads on consecutive entries
+    int jg = 0, ju = 0;
+    double tg = 0.0, tu = 0.0;
+    split_lds(s_zg, lib.n_zg, s_th[TH_GAS_LOGZ], jg, tg);
+    split_lds(s_un, lib.n_u, s_th[TH_GAS_LOGU], ju, tu);
+    const int nu = lib.n_u;
+    const size_t slab = (size_t)nl * ny;
+    const size_t o00 = (size_t)(jg * nu + ju) * slab, o01 = (size_t)(jg * nu + ju + 1) * slab;
+    const size_t o10 = (size_t)((jg + 1) * nu + ju) * slab, o11 = (size_t)((jg + 1) * nu + ju + 1) * slab;
+    const double c00 = (1.0 - tg) * (1.0 - tu), c01 = (1.0 - tg) * tu, c10 = tg * (1.0 - tu), c11 = tg * tu;
+    const int nq = nl * ny;
+    if (wv > 0) {   // wave 0 is busy with t_univ and the edges
+      for (int q0 = tid - 64; q0 < nq; q0 += 192 * 8) {
+        if (MODE == W_F64) {
+          const double *tb = lib.line_table;
+          double lh[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int q = q0 + 192 * u;
+            lh[u] = q < nq ? c00 * tb[o00 + q] + c01 * tb[o01 + q] + c10 * tb[o10 + q] + c11 * tb[o11 + q] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int q = q0 + 192 * u;
+            if (q < nq) s_lt[q] = (Acc)exp10(lh[u]);
+          }
         } else {
-          wacc[kpos_of(lib, ia, 0, ag)] += fa * w;
+          const float *tb = lib.line_table_f;
+          const float f00 = (float)c00, f01 = (float)c01, f10 = (float)c10, f11 = (float)c11;
+          float lh[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int q = q0 + 192 * u;
+            lh[u] = q < nq ? f00 * tb[o00 + q] + f01 * tb[o01 + q] + f10 * tb[o10 + q] + f11 * tb[o11 + q] : 0.f;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int q = q0 + 192 * u;
+            if (q < nq) s_lt[q] = (Acc)exp10f(lh[u]);
+          }
         }
       }
     }
   }
   __syncthreads();
 
-  // ---- nebular lines (App. C): L_l = sum_a 10^Lhat_l(a) sum_{alpha,m} W Q
+  // ---- B: overlap of SFH bin i with the linear-time cell of age ag (App. B)
+  int ja = 0;
+  double ta = 0.0;
+  if (nf > 1) split_lds(s_afe, nf, s_th[TH_AFE], ja, ta);
+  for (int ag = tid; ag < na; ag += 256) {
+    const double lo = s_clo[ag], hi = s_chi[ag];
+    // first bin whose upper edge exceeds lo
+    int i = 0;
+    {
+      int l = 0, h = n_sfh;
+      while (l < h) {
+        const int mid = (l + h) >> 1;
+        if (s_edges[mid + 1] > lo) h = mid; else l = mid + 1;
+      }
+      i = l;
+    }
+    for (; i < n_sfh && s_edges[i] < hi; ++i) {
+      const double Ti = s_edges[i], Tj = s_edges[i + 1];
+      const double ov = fmin(hi, Tj) - fmax(lo, Ti);
+      if (ov <= 0.0) continue;
+      const double w = s_th[TH_NSCALAR + i] * ov / (Tj - Ti);
+      const int j = s_zj[i];
+      const double t = s_zt[i];
+      for (int q = 0; q < (nf > 1 ? 2 : 1); ++q) {
+        const int ia = nf > 1 ? ja + q : 0;
+        const double fa = nf > 1 ? (q == 0 ? 1.0 - ta : ta) : 1.0;
+        if (nz > 1) {
+          wacc[kpos_of(lib, ia, j, ag)] += (Acc)(fa * (1.0 - t) * w);
+          wacc[kpos_of(lib, ia, j + 1, ag)] += (Acc)(fa * t * w);
+        } else {
+          wacc[kpos_of(lib, ia, 0, ag)] += (Acc)(fa * w);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- C: nebular lines (App. C): L_l = sum_a 10^Lhat_l(a) sum_{alpha,m} W Q
   const int slot = a.point_obs ? a.point_obs[b] : 0;
   const int kind = a.obs_table[slot].kind;
-  const int ny = lib.n_young;
-  if (lib.n_line > 0) {
+  if (nl > 0) {
     for (int ag = tid; ag < ny; ag += 256) {
       double s = 0.0;
       for (int ia = 0; ia < nf; ++ia)
-        for (int m = 0; m < nz; ++m)
-          s += wacc[kpos_of(lib, ia, m, ag)] * lib.Q[(ia * nz + m) * ny + ag];
-      wq[ag] = s;
+        for (int m = 0; m < nz; ++m) s += (double)wacc[kpos_of(lib, ia, m, ag)] * s_Q[(ia * nz + m) * ny + ag];
+      s_wq[ag] = s;
     }
     __syncthreads();
-    int jg = 0, ju = 0;
-    double tg = 0.0, tu = 0.0;
-    bool in;
-    grid_split_dev(lib.zg, lib.n_zg, s_th[TH_GAS_LOGZ], jg, tg, in);
-    grid_split_dev(lib.un, lib.n_u, s_th[TH_GAS_LOGU], ju, tu, in);
-    const int nu = lib.n_u;
-    double *lt = wq + ny;   // [n_line * n_young] per (line, age) luminosity terms
-    for (int q = tid; q < lib.n_line * ny; q += 256) {
-      const int l = q / ny, ag = q - l * ny;
-      const size_t slab = (size_t)lib.n_line * ny;
-      const double *tb = lib.line_table + q;
-      const double lh = (1.0 - tg) * (1.0 - tu) * tb[(jg * nu + ju) * slab] +
-                        (1.0 - tg) * tu * tb[(jg * nu + ju + 1) * slab] +
-                        tg * (1.0 - tu) * tb[((jg + 1) * nu + ju) * slab] + tg * tu * tb[((jg + 1) * nu + ju + 1) * slab];
-      lt[q] = exp10(lh) * wq[ag];
-    }
-    __syncthreads();
-    for (int l = tid; l < lib.n_line; l += 256) {
+    for (int l = tid; l < nl; l += 256) {
       double Ll = 0.0;
-      for (int ag = 0; ag < ny; ++ag) Ll += lt[l * ny + ag];
-      if (kind == 0) wacc[a.line_k0 + l] = Ll / kLsun;        // photometry: lines on the model grid
-      else a.Lline[(size_t)r * lib.n_line + l] = Ll;           // spectra: lines on the detector pixels
+      for (int ag = 0; ag < ny; ++ag) Ll += (double)s_lt[l * ny + ag] * s_wq[ag];
+      if (kind == 0) wacc[a.line_k0 + l] = (Acc)(Ll / kLsun);     // photometry: lines on the model grid
+      else a.Lline[(size_t)r * nl + l] = Ll;                      // spectra: lines on the detector pixels
     }
     __syncthreads();
   }
 
-  // ---- write the row in the contraction's format and its K-tile occupancy bits
+  // ---- D: the row in the contraction's format (thread per K entry) and its K-tile
+  //      occupancy bits: a wave covers two 32-wide tiles per pass (ballot halves)
   double wscale = 1.0;
-  if (MODE == W_F64 || MODE == W_F32) {
+  int eb = 0;
+  if (MODE == W_BF16 || MODE == W_F16) {
+    // W'_k = W_k 2^{e_k} (exact in FP32), kept in the LDS row; the row scale 2^{e_b}
+    // puts max |W'| in [2^14, 2^15)
+    float mx = 0.f;
+#pragma unroll 4
     for (int k = tid; k < K_pad; k += 256) {
-      if (MODE == W_F64) ((double *)a.W)[(size_t)r * K_pad + k] = wacc[k];
-      else ((float *)a.W)[(size_t)r * K_pad + k] = (float)wacc[k];
+      const float x = ldexpf((float)wacc[k], lib.kexp[k]);
+      wacc[k] = (Acc)x;
+      mx = fmaxf(mx, fabsf(x));
     }
-  } else {
-    // W'_k = W_k 2^{e_k}; row scale 2^{e_b} puts max |W'| in [2^14, 2^15)
-    double mx = 0.0;
-    for (int k = tid; k < K_pad; k += 256) mx = fmax(mx, fabs(ldexp(wacc[k], lib.kexp[k])));
-    mx = block_max<256>(mx, red);
-    int eb = 0;
-    if (mx > 0.0) eb = ilogb(mx) - 14;
+    double m2 = wave_max((double)mx);
+    __syncthreads();   // every thread has read the D_C partials
+    if (lane == 0) s_part[wv] = m2;
+    __syncthreads();
+    m2 = fmax(fmax(s_part[0], s_part[1]), fmax(s_part[2], s_part[3]));
+    if (m2 > 0.0) eb = ilogb(m2) - 14;
     wscale = ldexp(1.0, eb);
-    uint16_t *hi = (uint16_t *)a.W, *lo = (uint16_t *)a.Wlo;
-    for (int k = tid; k < K_pad; k += 256) {
-      const double x = ldexp(wacc[k], lib.kexp[k] - eb);
+  }
+  for (int k = tid; k < K_pad; k += 256) {   // K_pad is a multiple of 64: no partial waves
+    bool on;
+    if (MODE == W_F64) {
+      const double x = (double)wacc[k];
+      ((double *)a.W)[rowoff + k] = x;
+      on = x != 0.0;
+    } else if (MODE == W_F32) {
+      const float x = (float)wacc[k];
+      ((float *)a.W)[rowoff + k] = x;
+      on = x != 0.f;
+    } else {
+      // hi + residual: x - hi is exact in FP32 (at most 13 significant bits)
+      const float x = ldexpf((float)wacc[k], -eb);
       uint16_t h, l;
       if (MODE == W_BF16) {
-        h = bf16_rne((float)x);
-        l = bf16_rne((float)(x - (double)bf16_to_f(h)));
+        h = bf16_rne(x);
+        l = bf16_rne(x - bf16_to_f(h));
       } else {
-        h = f16_rne((float)x);
-        l = f16_rne((float)(x - (double)f16_to_f(h)));
+        h = f16_rne(x);
+        l = f16_rne(x - f16_to_f(h));
       }
-      hi[(size_t)r * K_pad + k] = h;
-      lo[(size_t)r * K_pad + k] = l;
-      wacc[k] = (h != 0 || l != 0) ? 1.0 : 0.0;   // reuse the LDS row for the occupancy test
+      ((uint16_t *)a.W)[rowoff + k] = h;
+      ((uint16_t *)a.Wlo)[rowoff + k] = l;
+      on = (h != 0) || (l != 0);
+    }
+    const unsigned long long bal = __ballot(on);
+    if (lane == 0) {
+      const int t0 = (k - lane) / kKTile;   // first of the wave's two tiles
+      uint32_t bits = 0u;
+      if (bal & 0xffffffffull) bits |= 1u << (t0 & 31);
+      if (bal >> 32) bits |= 1u << ((t0 + 1) & 31);
+      if (bits) atomicOr(&s_bits[t0 >> 5], bits);   // t0 even: both tiles share a word
     }
   }
   __syncthreads();
-  {
-    uint32_t *tbits = (uint32_t *)red;   // reuse: one word per 32 K tiles
-    for (int w = tid; w < a.mask_words; w += 256) tbits[w] = 0u;
-    __syncthreads();
-    const int n_kt = K_pad / kKTile;
-    for (int t = tid; t < n_kt; t += 256) {
-      bool on = false;
-      for (int k = t * kKTile; k < (t + 1) * kKTile; ++k) on |= (wacc[k] != 0.0);
-      if (on) atomicOr(&tbits[t >> 5], 1u << (t & 31));
-    }
-    __syncthreads();
-    for (int w = tid; w < a.mask_words; w += 256) a.rowmask[(size_t)r * a.mask_words + w] = tbits[w];
-  }
+  for (int w = tid; w < a.mask_words; w += 256) a.rowmask[(size_t)r * a.mask_words + w] = s_bits[w];
 
   if (tid == 0) {
     PointRow pr;
     pr.z = z;
-    pr.t_univ = t_univ;
-    pr.dl = dl;
+    pr.t_univ = s_tu;
     pr.dc = dc;
+    pr.dl = (1.0 + z) * dc;
     pr.mass10 = exp10(s_th[TH_LOGMASS]);
-    pr.scale_fnu = pr.mass10 * (1.0 + z) / (4.0 * kPi * dl * dl) * kLsun * kAng_cm / kC_cms;
+    pr.scale_fnu = pr.mass10 * (1.0 + z) / (4.0 * kPi * pr.dl * pr.dl) * kLsun * kAng_cm / kC_cms;
     pr.wscale = wscale;
     pr.tau_bc = s_th[TH_TAU_BC];
     pr.alpha_bc = s_th[TH_ALPHA_BC];
@@ -426,10 +536,8 @@ __global__ void __launch_bounds__(256) k_tiles(const uint32_t *__restrict__ rowm
 // ---------------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------------
-size_t prep_smem_bytes(const DevLib &lib) {
-  return sizeof(double) * ((size_t)lib.K_pad + lib.n_sfh + 1 + lib.n_sfh + 256 + lib.n_young +
-                           (size_t)lib.n_line * lib.n_young + 8) +
-         sizeof(int) * ((size_t)lib.n_sfh + 2);
+size_t prep_smem_bytes(const DevLib &lib, int mode) {
+  return sizeof(double) * (size_t)PrepSmem(lib, mode == W_F64).total;
 }
 
 hipError_t launch_sort(const DevLib &lib, const double *theta, int P, int B, double *keys, int *perm, hipStream_t s) {
@@ -455,7 +563,7 @@ hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s) {
   a.Lline = pl.Lline;
   a.kpos = pl.kpos;
   a.line_k0 = pl.line_k0;
-  const size_t sm = prep_smem_bytes(lib);
+  const size_t sm = prep_smem_bytes(lib, pl.mode);
   if (sm > 160 * 1024) return hipErrorInvalidValue;
   static size_t attr_set[4] = {0, 0, 0, 0};
   const void *fn[4] = {(const void *)k_prep<W_F64>, (const void *)k_prep<W_F32>, (const void *)k_prep<W_BF16>,

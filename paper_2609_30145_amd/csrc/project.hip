@@ -92,13 +92,16 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
     const double fac = kC_cms * pr.scale_fnu / (opz * opz * kAng_cm * kAng_cm);
     const double lnopz = log1p(z);
     const double wlo = lib.wave_d[0], whi = lib.wave_d[N - 1];
-    // one pass over all filter nodes, four per thread in flight, terms kept in LDS
-    for (int j0 = tid; j0 < ob.n_fnodes; j0 += 1024) {
-      int kq[4];
-      double lrq[4];
-      bool in[4];
+    // one pass over all filter nodes, eight per thread in flight, terms kept in LDS.
+    // On a log-uniform rest grid the bracketing interval follows from ln(lambda)
+    // directly; a node within rounding of a grid point may take the neighbouring
+    // interval, where the interpolation weight is within rounding of 0 or 1.
+    for (int j0 = tid; j0 < ob.n_fnodes; j0 += 2048) {
+      int kq[8];
+      double lrq[8];
+      bool in[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 8; ++q) {
         const int j = j0 + 256 * q;
         in[q] = false;
         kq[q] = 0;
@@ -106,22 +109,31 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
         if (j < ob.n_fnodes) {
           lrq[q] = ob.fw[j] / opz;
           in[q] = lrq[q] >= wlo && lrq[q] <= whi;
-          if (in[q]) kq[q] = wave_bracket_ln(lib, lrq[q], ob.fwln[j] - lnopz);
+          if (in[q]) {
+            if (lib.log_uniform) {
+              const int k = (int)floor((ob.fwln[j] - lnopz - lib.lnw0) * lib.inv_dlnw);
+              kq[q] = min(max(k, 0), N - 2);
+            } else {
+              kq[q] = bracket(lib.wave_d, N, lrq[q]);
+            }
+          }
         }
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 8; ++q) {
         const int j = j0 + 256 * q;
-        if (j >= ob.n_fnodes) break;
-        double term = 0.0;
-        if (in[q]) {
-          const int k = kq[q];
-          const T t = (T)((lrq[q] - lib.wave_d[k]) / (lib.wave_d[k + 1] - lib.wave_d[k]));
-          const T f = Fr[k] + t * (Fr[k + 1] - Fr[k]);
-          const T w = sizeof(T) == 8 ? (T)ob.fr_d[j] : (T)ob.fr_f[j];
-          term = (double)(w * f);
+        if (j < ob.n_fnodes) {
+          double term = 0.0;
+          if (in[q]) {
+            const int k = kq[q];
+            const double w0 = lib.wave_d[k], w1 = lib.wave_d[k + 1];
+            const T f0 = Fr[k], f1 = Fr[k + 1];
+            const T w = sizeof(T) == 8 ? (T)ob.fr_d[j] : (T)ob.fr_f[j];
+            const T t = (T)((lrq[q] - w0) / (w1 - w0));
+            term = (double)(w * (f0 + t * (f1 - f0)));
+          }
+          sbuf[j] = term;
         }
-        sbuf[j] = term;
       }
     }
     __syncthreads();
@@ -208,24 +220,24 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
       datum(i, m / kFnuAB);
     }
   }
-  // fixed-order block reduction of logL (and the noise-parameter gradients)
-  red[tid] = lsum;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
+  // fixed-order reduction of logL (and the noise-parameter gradients): wave sums,
+  // then the four waves in order
+  {
+    const int wv = tid >> 6, lane = tid & 63;
+    const double ws = wave_reduce_sum(lsum);
+    double wg[4] = {0.0, 0.0, 0.0, 0.0};
+    if (a.gnoise)
+      for (int q = 0; q < 4; ++q) wg[q] = wave_reduce_sum(gs[q]);
+    __syncthreads();   // red[] may still be read by the band sums
+    if (lane == 0) {
+      red[wv] = ws;
+      for (int q = 0; q < 4; ++q) red[4 + 4 * q + wv] = wg[q];
+    }
     __syncthreads();
-  }
-  if (tid == 0 && a.logl) a.logl[pr.b] = red[0];
-  if (a.gnoise) {
-    for (int q = 0; q < 4; ++q) {
-      __syncthreads();
-      red[tid] = gs[q];
-      __syncthreads();
-      for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-      }
-      if (tid == 0) a.gnoise[(size_t)pr.b * 4 + q] = red[0];
+    if (tid == 0 && a.logl) a.logl[pr.b] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (a.gnoise && tid < 4) {
+      const double *g = red + 4 + 4 * tid;
+      a.gnoise[(size_t)pr.b * 4 + tid] = (g[0] + g[1]) + (g[2] + g[3]);
     }
   }
 }
