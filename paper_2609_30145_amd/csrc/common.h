@@ -91,6 +91,30 @@ struct PointRow {
   int pad;
 };
 
+// ---------------------------------------------------------------- contraction tiles
+// Block -> (M tile, N tile) for the library contractions.  The hardware deals
+// consecutive blocks round-robin to the 8 XCDs; XCD x takes the consecutive tiles
+// [x*nblk/8, (x+1)*nblk/8) of the order (N tile, then M tile), so the XCDs split the
+// library columns and each holds a share of every M tile (M tiles differ in their
+// active K-tile counts).  The M tiles of an N tile are rotated so that the blocks
+// l, l+32, l+64, ... of an XCD (32 CUs), which tend to share a CU, come from M tiles
+// spread over the batch; blocks_per_cu is the occupancy the kernel is built for.
+__device__ __forceinline__ void balanced_tile(int n_mt, int n_nt, int blocks_per_cu, int &mt, int &nt) {
+  const int nblk = gridDim.x, bid = blockIdx.x;
+  if ((nblk & 7) != 0) {
+    mt = bid / n_nt;
+    nt = bid - mt * n_nt;
+    return;
+  }
+  const int per = nblk >> 3, l = bid >> 3;
+  const int logical = (bid & 7) * per + l;
+  const int n = logical / n_mt, mm = logical - n * n_mt;
+  const int grp = n_mt < 32 ? 32 / n_mt : 1;                       // N tiles between blocks l and l+32
+  const int rot = n_mt > blocks_per_cu ? n_mt / blocks_per_cu : 1;
+  mt = (mm + rot * (n / grp)) % n_mt;
+  nt = n;
+}
+
 // ---------------------------------------------------------------- device helpers
 // index j with x[j] <= v < x[j+1], limited to [0, n-2]
 template <typename T>

@@ -22,9 +22,10 @@ struct ContractArgs {
   void *F, *Yatt;
 };
 
-// blockIdx -> (m tile, n tile).  Workgroups are dispatched round-robin over the 8 XCDs;
-// the remap gives each XCD a contiguous range of (m, n) tiles with n fastest, so one
-// XCD keeps a single M tile of the weights in its L2 while the library streams past.
+// blockIdx -> (m tile, n tile) for the FP32 / FP64 kernels: each XCD takes a contiguous
+// range of (m, n) tiles with n fastest, so an XCD keeps its few M tiles of the weights
+// in L2 while the library streams past (measured faster here than the column split
+// used by the 16-bit kernel, whose weight tiles are half the size).
 __device__ __forceinline__ void tile_of_block(int n_ntiles, int &mt, int &nt) {
   const int nblk = gridDim.x, bid = blockIdx.x;
   int logical = bid;

@@ -19,28 +19,8 @@ struct ContractArgs16 {
   const int *tiles, *n_young, *n_act;
   const PointRow *rows;
   const float *lnlv, *da, *dd;
-  float *F, *Yatt;
+  float *F;
 };
-
-// Block -> (M tile, N tile).  The hardware deals consecutive blocks round-robin to the
-// 8 XCDs; XCD x takes the consecutive tiles [x*nblk/8, (x+1)*nblk/8) of the order
-// (N tile, then M tile), so the XCDs split the library columns and each holds a share
-// of every M tile (M tiles differ in their active K-tile counts).  The M tiles of N tile
-// n are rotated by 3*(n/4) so that the blocks l, l+32, l+64 of an XCD, which tend to
-// share a CU, come from different M tiles.
-__device__ __forceinline__ void tile_of_block16(int n_mt, int n_nt, int &mt, int &nt) {
-  const int nblk = gridDim.x, bid = blockIdx.x;
-  if ((nblk & 7) != 0) {
-    mt = bid / n_nt;
-    nt = bid - mt * n_nt;
-    return;
-  }
-  const int per = nblk >> 3, l = bid >> 3;
-  const int logical = (bid & 7) * per + l;
-  const int n = logical / n_mt, mm = logical - n * n_mt;
-  mt = (mm + 3 * (n >> 2)) % n_mt;
-  nt = n;
-}
 
 template <bool BF, int PASSES>
 __device__ __forceinline__ v16f mfma16(const u32x4 &a, const u32x4 &b, v16f c) {
@@ -51,26 +31,16 @@ __device__ __forceinline__ v16f mfma16(const u32x4 &a, const u32x4 &b, v16f c) {
   }
 }
 
-// Birth-cloud transmission applied to the young-part accumulator (and, for the
-// gradient, the young spectrum after both screens stored to Yatt).
-template <int BM, int BN, int WTM, int WTN>
-__device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[6], const float *c_lnlv, const float *c_a,
-                                     const float *c_d, float *Yatt, int N_pad, int m0, int n0, int wm, int wn, int li,
-                                     int lh) {
+// Birth-cloud transmission applied to the young-part accumulator.
+template <int BM, int BN, int WTM>
+__device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[6], const float *c_lnlv, int wm, int lh) {
 #pragma unroll
   for (int i = 0; i < BM; ++i)
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
 #pragma unroll
-      for (int j = 0; j < BN; ++j) {
-        acc[i][j][e] *= expf(-sp[rl][0] * expf(sp[rl][1] * c_lnlv[j]));
-        if (Yatt) {
-          const float Td = expf(-sp[rl][2] * expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
-          const int col = n0 + wn * WTN + j * 32 + li;
-          Yatt[(size_t)(m0 + rl) * N_pad + col] = acc[i][j][e] * Td * sp[rl][5];
-        }
-      }
+      for (int j = 0; j < BN; ++j) acc[i][j][e] *= expf(-sp[rl][0] * expf(sp[rl][1] * c_lnlv[j]));
     }
 }
 
@@ -93,9 +63,9 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
 
   const int n_nt = a.N_pad / NT;
   int mt, nt;
-  tile_of_block16(gridDim.x / n_nt, n_nt, mt, nt);
+  balanced_tile(gridDim.x / n_nt, n_nt, 3, mt, nt);
   const int m0 = mt * MT, n0 = nt * NT;
-  const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6, wn = 0;
+  const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6;
   const int li = lane & 31, lh = lane >> 5;
   const int K_pad = a.K_pad;
 
@@ -117,21 +87,29 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
   const int nact = a.n_act[mt], ny = a.n_young[mt];
   const int *tl = a.tiles + (size_t)mt * a.n_tiles;
 
+  // 32-bit element offsets of this thread's 16-byte chunks (K tile added per tile)
+  int offA[A8], offB[B8];
+#pragma unroll
+  for (int q = 0; q < A8; ++q) {
+    const int idx = tid + 256 * q;
+    offA[q] = (m0 + idx / NCH) * K_pad + (idx % NCH) * 8;
+  }
+#pragma unroll
+  for (int q = 0; q < B8; ++q) {
+    const int idx = tid + 256 * q;
+    offB[q] = (n0 + idx / NCH) * K_pad + (idx % NCH) * 8;
+  }
   u32x4 rah[A8], ral[USE_WL ? A8 : 1], rbh[B8], rbr[USE_R ? B8 : 1];
 #define SPS_GLOAD16(t_)                                                        \
   {                                                                            \
     const int k0_ = tl[t_] * KT;                                               \
     _Pragma("unroll") for (int q = 0; q < A8; ++q) {                           \
-      const int idx = tid + 256 * q, row = idx / NCH, c8 = idx % NCH;          \
-      const size_t o = (size_t)(m0 + row) * K_pad + k0_ + c8 * 8;              \
-      rah[q] = *(const u32x4 *)(a.Wh + o);                                     \
-      if constexpr (USE_WL) ral[q] = *(const u32x4 *)(a.Wl + o);               \
+      rah[q] = *(const u32x4 *)(a.Wh + (offA[q] + k0_));                       \
+      if constexpr (USE_WL) ral[q] = *(const u32x4 *)(a.Wl + (offA[q] + k0_)); \
     }                                                                          \
     _Pragma("unroll") for (int q = 0; q < B8; ++q) {                           \
-      const int idx = tid + 256 * q, row = idx / NCH, c8 = idx % NCH;          \
-      const size_t o = (size_t)(n0 + row) * K_pad + k0_ + c8 * 8;              \
-      rbh[q] = *(const u32x4 *)(a.H + o);                                      \
-      if constexpr (USE_R) rbr[q] = *(const u32x4 *)(a.R + o);                 \
+      rbh[q] = *(const u32x4 *)(a.H + (offB[q] + k0_));                        \
+      if constexpr (USE_R) rbr[q] = *(const u32x4 *)(a.R + (offB[q] + k0_));   \
     }                                                                          \
   }
 
@@ -161,7 +139,7 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
     }
     __syncthreads();
     if (t + 1 < nact) SPS_GLOAD16(t + 1);
-    if (t == ny) bc16<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
+    if (t == ny) bc16<BM, BN, WTM>(acc, sp, c_lnlv, wm, lh);
     // lane half lh takes chunks lh*4 .. lh*4+3 of the K tile (the same permutation of
     // K for both operands, so each MFMA still sums matching products)
 #pragma unroll
@@ -192,7 +170,7 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
 #undef SPS_SW
   if (ny == nact) {
     __syncthreads();
-    bc16<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
+    bc16<BM, BN, WTM>(acc, sp, c_lnlv, wm, lh);
   }
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -233,8 +211,8 @@ hipError_t launch_contract16_impl(const DevLib &lib, const void *W, const void *
   a.da = lib.dust_a_f;
   a.dd = lib.dust_d_f;
   a.F = (float *)F;
-  a.Yatt = (float *)Yatt;
-  if (!a.H || !a.R) return hipErrorInvalidValue;
+  // the gradient pass (which needs the young part) runs on the FP32 / FP64 paths only
+  if (!a.H || !a.R || Yatt) return hipErrorInvalidValue;
   switch (precision) {
     case 2: launch16<true, 3>(a, n_mt, lib.N_pad, s); break;
     case 3: launch16<false, 3>(a, n_mt, lib.N_pad, s); break;
