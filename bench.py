@@ -32,6 +32,29 @@ DTYPE = {"fp32": "f32", "fp64": "f64", "bf16": "bf16 (f32 accumulate, residual p
          "bf16_1pass": "bf16", "fp16_1pass": "f16"}
 
 
+def traffic_record(precision):
+    """HBM bytes per launch of the contraction from the committed counter summary, or
+    None when there is none for this precision or the kernel sources changed since."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.md"))):
+        text = open(path).read()
+        for line in text.splitlines():
+            line = line.strip()
+            if not (line.startswith("{") and '"traffic_bytes_per_launch"' in line):
+                continue
+            rec = json.loads(line)
+            if rec.get("precision") != precision:
+                continue
+            h = hashlib.sha256()
+            for f in rec["sources"]:
+                h.update(open(os.path.join(ROOT, "paper_2609_30145_amd", "csrc", f), "rb").read())
+            if h.hexdigest() != rec["sources_sha256"]:
+                return None
+            return dict(bytes=rec["traffic_bytes_per_launch"], source=os.path.relpath(path, ROOT))
+    return None
+
+
 def build_workload(cfg_name, precisions, seed=0):
     import torch
 
@@ -229,8 +252,13 @@ def main():
                           active_k_tile_frac=frac_exec, steps=steps)
     main_r = results[args.precision]
     peak = PEAK_TFLOPS[args.precision]
+    tr = traffic_record(args.precision)
     roof = {"bound": "mfma", "achieved": round(main_r["contract_alg_tflops"], 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(main_r["contract_alg_tflops"] / peak, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(main_r["contract_alg_tflops"] / peak, 4),
+            "traffic": tr["bytes"] if tr else None,
+            "traffic_unit": "bytes per launch (HBM-side counters scaled by a copy probe)",
+            "traffic_source": tr["source"] if tr else None,
+            "alg_bytes_per_launch": alg_bytes(cfg, B, args.precision),
             "executed_mfma_tflops": round(main_r["contract_exec_tflops"], 3),
             "executed_frac": round(main_r["contract_exec_tflops"] / peak, 4),
             "kernel": "library contraction (k_contract)", "contract_ms": round(main_r["contract_ms"], 4),
@@ -261,6 +289,17 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
+
+
+def alg_bytes(cfg, B, precision):
+    """Minimum bytes of one contraction launch: the library once (both 16-bit planes, or
+    the FP32/FP64 copy), the weight rows and the rest-frame output."""
+    K = cfg.n_age * len(cfg.logz) * len(cfg.afe) + cfg.n_lines
+    N = cfg.n_wave
+    lib = {"fp64": 8, "fp32": 4}.get(precision, 4 if precision.endswith(("16", "_hr")) else 2)
+    w = {"fp64": 8, "fp32": 4}.get(precision, 2 if precision.endswith("1pass") or precision.endswith("_hr") else 4)
+    out = 8 if precision == "fp64" else 4
+    return int(K * N * lib + B * K * w + B * N * out)
 
 
 def B_pad(B):
