@@ -136,3 +136,54 @@ def test_autograd_function(gcase):
     with torch.no_grad():
         ll2 = sag.logl(L, O, th.detach(), "fp64")
     assert np.allclose(ll2.cpu().numpy(), ll_ref, rtol=1e-10)
+
+
+# ------------------------------------------------------------------ full-size spectroscopic case
+@pytest.fixture(scope="module")
+def c3full():
+    cfg = wl.CONFIGS["c3"]
+    case = make_case(cfg, kind="spec")
+    theta = near_truth(case, cfg.batch, scale=0.05, seed=33)
+    L, O = gpu_objects(case, precisions=("fp64", "fp32"), max_batch=1280)
+    idx = np.linspace(0, cfg.batch - 1, 12).astype(int)
+    ll_ref, g_ref = adjoint.logl_grad(case["olib"], case["obs"], theta[idx])
+    return case, theta, L, O, idx, ll_ref, g_ref
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
+def test_c3_full_size_gradient_sampled_against_oracle(c3full, prec, tol):
+    """B = 1024 live points of the 3000-pixel prism spectrum (P = 158), the gradient of
+    every point computed in one launch; twelve rows spread over the batch are checked
+    against the oracle adjoint."""
+    case, theta, L, O, idx, ll_ref, g_ref = c3full
+    say(f"c3 full size grad {prec} B={theta.shape[0]} P={theta.shape[1]}")
+    ll, g = gpu_grad(L, O, theta, prec)
+    assert np.all(np.isfinite(g)) and np.all(np.isfinite(ll))
+    e = rel_err(g[idx], g_ref)
+    lle = np.max(np.abs(ll[idx] - ll_ref) / np.abs(ll_ref))
+    say(f"  max rel err {e.max():.3e}; logL rel err {lle:.3e}")
+    assert e.max() < tol
+    assert lle < (1e-12 if prec == "fp64" else 1e-5)
+
+
+def test_c3_full_size_gradient_against_gpu_fd(c3full):
+    """Central differences (h = 1e-6) of the GPU FP64 forward model on four points and
+    every used column except z (the five-sigma LSF window makes FD in z discontinuous)."""
+    case, theta, L, O, idx, ll_ref, g_ref = c3full
+    cfg = case["cfg"]
+    th0 = theta[idx[:4]]
+    _, g = gpu_grad(L, O, th0, "fp64")
+    cols = [c for c in used_columns(cfg, True) if c != om.columns(cfg.n_sfh, cfg.n_zh)["zred"]]
+    h = 1e-6
+    rows_p, rows_m = [], []
+    for b in range(len(th0)):
+        for c in cols:
+            a = th0[b].copy(); a[c] += h; rows_p.append(a)
+            a = th0[b].copy(); a[c] -= h; rows_m.append(a)
+    say(f"c3 full size grad vs GPU FD: {len(th0)} points x {len(cols)} columns")
+    lp = sps.logl(L, O, torch.tensor(np.array(rows_p), device="cuda"), "fp64").cpu().numpy()
+    lm = sps.logl(L, O, torch.tensor(np.array(rows_m), device="cuda"), "fp64").cpu().numpy()
+    fd = ((lp - lm) / (2 * h)).reshape(len(th0), len(cols))
+    e = rel_err(g[:, cols], fd)
+    say(f"  max rel err vs FD {e.max():.3e}")
+    assert e.max() < 1e-4
