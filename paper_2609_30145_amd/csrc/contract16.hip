@@ -1,6 +1,7 @@
 // 16-bit library contraction with FP32 accumulation (BF16 or FP16 MFMA).
 // The library row k is stored as 2^{e_k} (H_k + R_k) and the weight row of point b
-// as 2^{e_b} 2^{-e_k} (W_h + W_l), both 16-bit hi + residual pairs.  The products
+// as 2^{e_b} 2^{-e_k} (W_h + W_l), both 16-bit hi + residual pairs (the weight planes
+// in the fragment-tiled layout written by the weight builder).  The products
 // W_h H (main pass), W_h R and W_l H (one refinement pass over the residual terms)
 // accumulate into one FP32 accumulator; the dropped W_l R term is second order.
 #include "common.h"
@@ -46,20 +47,23 @@ __device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[6], 
 
 // PASSES: 1 = W_h H; 2 = W_h H + W_h R; 3 = W_h H + W_h R + W_l H.
 // Block tile 128 (points) x 64 (wavelengths), K tile 64; four waves stacked along M,
-// each 32 x 64 (two 32x32x16 MFMA accumulators).  The next K tile is prefetched into
-// registers while the current one is multiplied out of LDS.  LDS rows are unpadded with
-// the 16-byte chunks XOR-swizzled by the row, so three blocks fit a CU.
+// each 32 x 64 (two 32x32x16 MFMA accumulators).  Each wave reads its own weight
+// fragments straight from global memory into registers (the weight planes are stored
+// fragment-tiled, so one wave load is two contiguous 512-byte runs) with two register
+// sets, the next K tile in flight while the current one is multiplied.  The library
+// tile is shared by the four waves through double-buffered LDS: one barrier per K tile.
+// LDS rows are unpadded with the 16-byte chunks XOR-swizzled: chunk c of row r sits at
+// c ^ (r & 7) ^ ((r >> 3) & 1), which keeps 16-byte reads of 8 consecutive rows, and of
+// the 8 rows of one parity among 16 consecutive rows, on distinct banks.
 template <bool BF, int PASSES>
 __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
-  constexpr int MT = 128, NT = 64, KT = 64, NCH = KT / 8, WTM = 32, WTN = 64, BM = 1, BN = 2;
+  constexpr int MT = 128, NT = 64, KT = 64, NCH = KT / 8, WTM = 32, BM = 1, BN = 2;
   constexpr bool USE_WL = PASSES >= 3, USE_R = PASSES >= 2;
-  constexpr int A8 = MT * KT / 8 / 256, B8 = NT * KT / 8 / 256;   // 16-byte chunks per thread
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[MT * KT];
-  __shared__ __attribute__((aligned(16))) uint16_t Al[USE_WL ? MT * KT : 8];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[NT * KT];
-  __shared__ __attribute__((aligned(16))) uint16_t Br[USE_R ? NT * KT : 8];
+  constexpr int B8 = NT * KT / 8 / 256;   // 16-byte library chunks per thread and K tile
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][NT * KT];
+  __shared__ __attribute__((aligned(16))) uint16_t Br[2][USE_R ? NT * KT : 8];
   __shared__ float sp[MT][6];
-#define SPS_SW(r_, c_) ((r_) * KT + (((c_) ^ ((r_) & (NCH - 1))) << 3))
+#define SPS_SW(r_, c_) ((r_) * KT + (((c_) ^ ((r_) & 7) ^ (((r_) >> 3) & 1)) << 3))
 
   const int n_nt = a.N_pad / NT;
   int mt, nt;
@@ -67,7 +71,7 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
   const int m0 = mt * MT, n0 = nt * NT;
   const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6;
   const int li = lane & 31, lh = lane >> 5;
-  const int K_pad = a.K_pad;
+  const int K_pad = a.K_pad, n_kt = K_pad / KT;
 
   for (int r = tid; r < MT; r += 256) {
     const PointRow &pr = a.rows[m0 + r];
@@ -86,31 +90,58 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
 
   const int nact = a.n_act[mt], ny = a.n_young[mt];
   const int *tl = a.tiles + (size_t)mt * a.n_tiles;
-
-  // 32-bit element offsets of this thread's 16-byte chunks (K tile added per tile)
-  int offA[A8], offB[B8];
-#pragma unroll
-  for (int q = 0; q < A8; ++q) {
-    const int idx = tid + 256 * q;
-    offA[q] = (m0 + idx / NCH) * K_pad + (idx % NCH) * 8;
-  }
+  // weight fragments of this wave's 32-row group: lane (li, lh) takes chunk lh*4 + s of
+  // row li at MFMA step s (the same permutation of K as the library fragments below)
+  const size_t wbase = (size_t)((m0 >> 5) + wm) * n_kt * (KT * 32) + (size_t)(lh * 4) * 256 + li * 8;
+  int offB[B8];
 #pragma unroll
   for (int q = 0; q < B8; ++q) {
     const int idx = tid + 256 * q;
     offB[q] = (n0 + idx / NCH) * K_pad + (idx % NCH) * 8;
   }
-  u32x4 rah[A8], ral[USE_WL ? A8 : 1], rbh[B8], rbr[USE_R ? B8 : 1];
-#define SPS_GLOAD16(t_)                                                        \
-  {                                                                            \
-    const int k0_ = tl[t_] * KT;                                               \
-    _Pragma("unroll") for (int q = 0; q < A8; ++q) {                           \
-      rah[q] = *(const u32x4 *)(a.Wh + (offA[q] + k0_));                       \
-      if constexpr (USE_WL) ral[q] = *(const u32x4 *)(a.Wl + (offA[q] + k0_)); \
-    }                                                                          \
-    _Pragma("unroll") for (int q = 0; q < B8; ++q) {                           \
-      rbh[q] = *(const u32x4 *)(a.H + (offB[q] + k0_));                        \
-      if constexpr (USE_R) rbr[q] = *(const u32x4 *)(a.R + (offB[q] + k0_));   \
-    }                                                                          \
+  u32x4 ah0[4], al0[USE_WL ? 4 : 1], ah1[4], al1[USE_WL ? 4 : 1], rbh[B8], rbr[USE_R ? B8 : 1];
+#define SPS_LOADA(t_, H_, L_)                                                      \
+  {                                                                                \
+    const size_t o_ = wbase + (size_t)tl[t_] * (KT * 32);                          \
+    _Pragma("unroll") for (int s = 0; s < 4; ++s) {                                \
+      H_[s] = *(const u32x4 *)(a.Wh + o_ + s * 256);                               \
+      if constexpr (USE_WL) L_[s] = *(const u32x4 *)(a.Wl + o_ + s * 256);         \
+    }                                                                              \
+  }
+#define SPS_LOADB(t_)                                                              \
+  {                                                                                \
+    const int k0_ = tl[t_] * KT;                                                   \
+    _Pragma("unroll") for (int q = 0; q < B8; ++q) {                               \
+      rbh[q] = *(const u32x4 *)(a.H + (offB[q] + k0_));                            \
+      if constexpr (USE_R) rbr[q] = *(const u32x4 *)(a.R + (offB[q] + k0_));       \
+    }                                                                              \
+  }
+#define SPS_STOREB(buf_)                                                           \
+  {                                                                                \
+    _Pragma("unroll") for (int q = 0; q < B8; ++q) {                               \
+      const int idx = tid + 256 * q, row = idx / NCH, c = idx % NCH;               \
+      *(u32x4 *)(&Bh[buf_][SPS_SW(row, c)]) = rbh[q];                              \
+      if constexpr (USE_R) *(u32x4 *)(&Br[buf_][SPS_SW(row, c)]) = rbr[q];         \
+    }                                                                              \
+  }
+  // the passes are interleaved over the two independent accumulators
+#define SPS_MMA(buf_, H_, L_)                                                      \
+  {                                                                                \
+    _Pragma("unroll") for (int s = 0; s < 4; ++s) {                                \
+      const int ch = lh * 4 + s;                                                   \
+      u32x4 fb[BN], fr[BN];                                                        \
+      _Pragma("unroll") for (int j = 0; j < BN; ++j) {                             \
+        fb[j] = *(const u32x4 *)(&Bh[buf_][SPS_SW(j * 32 + li, ch)]);              \
+        if constexpr (USE_R) fr[j] = *(const u32x4 *)(&Br[buf_][SPS_SW(j * 32 + li, ch)]); \
+      }                                                                            \
+      _Pragma("unroll") for (int j = 0; j < BN; ++j) acc[0][j] = mfma16<BF, PASSES>(H_[s], fb[j], acc[0][j]); \
+      if constexpr (USE_R) {                                                       \
+        _Pragma("unroll") for (int j = 0; j < BN; ++j) acc[0][j] = mfma16<BF, PASSES>(H_[s], fr[j], acc[0][j]); \
+      }                                                                            \
+      if constexpr (USE_WL) {                                                      \
+        _Pragma("unroll") for (int j = 0; j < BN; ++j) acc[0][j] = mfma16<BF, PASSES>(L_[s], fb[j], acc[0][j]); \
+      }                                                                            \
+    }                                                                              \
   }
 
   float c_lnlv[BN], c_a[BN], c_d[BN];
@@ -121,57 +152,37 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
     c_a[j] = a.da[col];
     c_d[j] = a.dd[col];
   }
+  if (nact > 0) {
+    SPS_LOADB(0);
+    SPS_LOADA(0, ah0, al0);
+    SPS_STOREB(0);
+    if (nact > 1) SPS_LOADB(1);
+  }
   __syncthreads();
-  if (nact > 0) SPS_GLOAD16(0);
-  for (int t = 0; t < nact; ++t) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < A8; ++q) {
-      const int idx = tid + 256 * q, row = idx / NCH, c8 = idx % NCH;
-      *(u32x4 *)(Ah + SPS_SW(row, c8)) = rah[q];
-      if constexpr (USE_WL) *(u32x4 *)(Al + SPS_SW(row, c8)) = ral[q];
-    }
-#pragma unroll
-    for (int q = 0; q < B8; ++q) {
-      const int idx = tid + 256 * q, row = idx / NCH, c8 = idx % NCH;
-      *(u32x4 *)(Bh + SPS_SW(row, c8)) = rbh[q];
-      if constexpr (USE_R) *(u32x4 *)(Br + SPS_SW(row, c8)) = rbr[q];
-    }
-    __syncthreads();
-    if (t + 1 < nact) SPS_GLOAD16(t + 1);
+  // two K tiles per trip, so the two weight register sets and LDS buffers alternate
+  // without copies; LDS buffer b is rewritten only after the barrier that follows its
+  // last read
+  for (int t = 0; t < nact; t += 2) {
+    if (t + 1 < nact) SPS_LOADA(t + 1, ah1, al1);
     if (t == ny) bc16<BM, BN, WTM>(acc, sp, c_lnlv, wm, lh);
-    // lane half lh takes chunks lh*4 .. lh*4+3 of the K tile (the same permutation of
-    // K for both operands, so each MFMA still sums matching products)
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int ch = lh * 4 + s;
-      u32x4 fa, fl, fb[BN], fr[BN];
-      fa = *(const u32x4 *)(Ah + SPS_SW(wm * WTM + li, ch));
-      if constexpr (USE_WL) fl = *(const u32x4 *)(Al + SPS_SW(wm * WTM + li, ch));
-#pragma unroll
-      for (int j = 0; j < BN; ++j) {
-        fb[j] = *(const u32x4 *)(Bh + SPS_SW(j * 32 + li, ch));
-        if constexpr (USE_R) fr[j] = *(const u32x4 *)(Br + SPS_SW(j * 32 + li, ch));
-      }
-      // the passes are interleaved over the independent accumulators
-#pragma unroll
-      for (int j = 0; j < BN; ++j) acc[0][j] = mfma16<BF, PASSES>(fa, fb[j], acc[0][j]);
-      if constexpr (USE_R) {
-#pragma unroll
-        for (int j = 0; j < BN; ++j) acc[0][j] = mfma16<BF, PASSES>(fa, fr[j], acc[0][j]);
-      }
-      if constexpr (USE_WL) {
-#pragma unroll
-        for (int j = 0; j < BN; ++j) acc[0][j] = mfma16<BF, PASSES>(fl, fb[j], acc[0][j]);
-      }
-    }
-  }
-#undef SPS_GLOAD16
-#undef SPS_SW
-  if (ny == nact) {
+    SPS_MMA(0, ah0, al0);
+    if (t + 1 < nact) SPS_STOREB(1);
+    if (t + 2 < nact) SPS_LOADB(t + 2);
     __syncthreads();
-    bc16<BM, BN, WTM>(acc, sp, c_lnlv, wm, lh);
+    if (t + 1 >= nact) break;
+    if (t + 2 < nact) SPS_LOADA(t + 2, ah0, al0);
+    if (t + 1 == ny) bc16<BM, BN, WTM>(acc, sp, c_lnlv, wm, lh);
+    SPS_MMA(1, ah1, al1);
+    if (t + 2 < nact) SPS_STOREB(0);
+    if (t + 3 < nact) SPS_LOADB(t + 3);
+    __syncthreads();
   }
+#undef SPS_LOADA
+#undef SPS_LOADB
+#undef SPS_STOREB
+#undef SPS_MMA
+#undef SPS_SW
+  if (ny == nact) bc16<BM, BN, WTM>(acc, sp, c_lnlv, wm, lh);
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int rl = wm * WTM + 8 * (e >> 2) + 4 * lh + (e & 3);

@@ -95,6 +95,14 @@ __device__ __forceinline__ float f16_to_f(uint16_t h) {
   return (float)v;
 }
 
+// Position of weight (row r, K entry k) in the 16-bit planes, which the contraction
+// reads straight into MFMA registers: blocks of 32 rows x 64 K entries (4 KB), inside a
+// block chunk-major ([8-entry chunk][row][8]), so one wave load of a chunk for its 32
+// rows is a single contiguous 512-byte run.
+__device__ __forceinline__ size_t w16_pos(int r, int k, int n_kt64) {
+  return ((size_t)(r >> 5) * n_kt64 + (k >> 6)) * 2048 + (size_t)((k >> 3) & 7) * 256 + (r & 31) * 8 + (k & 7);
+}
+
 // Output mode of the weight row.
 enum WMode { W_F64 = 0, W_F32 = 1, W_BF16 = 2, W_F16 = 3 };
 
@@ -199,8 +207,8 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       if (MODE == W_F64) ((double *)a.W)[rowoff + k] = 0.0;
       else if (MODE == W_F32) ((float *)a.W)[rowoff + k] = 0.f;
       else {
-        ((uint16_t *)a.W)[rowoff + k] = 0;
-        ((uint16_t *)a.Wlo)[rowoff + k] = 0;
+        ((uint16_t *)a.W)[w16_pos(r, k, K_pad >> 6)] = 0;
+        ((uint16_t *)a.Wlo)[w16_pos(r, k, K_pad >> 6)] = 0;
       }
     }
     for (int w = tid; w < a.mask_words; w += 256) a.rowmask[(size_t)r * a.mask_words + w] = 0u;
@@ -436,8 +444,8 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
         h = f16_rne(x);
         l = f16_rne(x - f16_to_f(h));
       }
-      ((uint16_t *)a.W)[rowoff + k] = h;
-      ((uint16_t *)a.Wlo)[rowoff + k] = l;
+      ((uint16_t *)a.W)[w16_pos(r, k, K_pad >> 6)] = h;
+      ((uint16_t *)a.Wlo)[w16_pos(r, k, K_pad >> 6)] = l;
       on = (h != 0) || (l != 0);
     }
     const unsigned long long bal = __ballot(on);
