@@ -177,7 +177,7 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   const int K_pad = K_young_pad + round_up(kold, kKAlign);
   g.K = nf * nz * na + nl;
   g.K_pad = K_pad;
-  if (K_pad > 65536) return fail(SPS_E_SHAPE, "library too large: %d weight rows after padding (at most 65536)", K_pad);
+  if (K_pad > kMaxKPad) return fail(SPS_E_SHAPE, "library too large: %d weight rows after padding (at most %d)", K_pad, kMaxKPad);
   g.K_young_pad = K_young_pad;
   std::vector<int> kpos((size_t)nf * nz * na), ksrc(K_pad, INT_MIN);
   g.zmajor = d->n_zh > 0 ? 0 : 1;
@@ -633,13 +633,15 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   // call; clear it so that only this call's own launches are checked below
   (void)hipGetLastError();
   const int mode = prec == 0 ? 0 : prec == 1 ? 1 : (prec == 2 || prec == 4 || prec == 6) ? 2 : 3;
-  hipError_t e = launch_sort(g, theta, g.P, B, w.keys, w.perm, s);
+  const int MT = contract_mtile(prec);
+  const int tf = contract_ktile_factor(prec);
+  hipError_t e = launch_keys(g, theta, g.P, B, w.keys, s);
   PrepLaunch pl;
   pl.theta = theta;
   pl.P = g.P;
   pl.B = B;
   pl.B_pad = B_pad;
-  pl.perm = w.perm;
+  pl.keys = w.keys;
   pl.obs_table = obs_table;
   pl.point_obs = point_obs;
   pl.W = w.W;
@@ -652,18 +654,13 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   pl.line_k0 = L->line_k0;
   pl.mode = mode;
   if (e == hipSuccess) e = launch_prep(g, pl, s);
-  const int MT = contract_mtile(prec);
-  const int tf = contract_ktile_factor(prec);
-  if (e == hipSuccess)
-    e = launch_tiles(w.rowmask, w.mask_words, B_pad, MT, g.K_pad / kKTile, g.K_young_pad / kKTile, tf, w.tiles,
-                     w.n_young, w.n_act, w.counter, s);
   ContractLaunch cl;
   cl.W = pl.W;
   cl.Wlo = pl.Wlo;
   cl.B_pad = B_pad;
-  cl.tiles = w.tiles;
-  cl.n_young = w.n_young;
-  cl.n_act = w.n_act;
+  cl.rowmask = w.rowmask;
+  cl.mask_words = w.mask_words;
+  cl.counter = w.counter;
   cl.rows = w.rows;
   cl.F = w.F;
   cl.Yatt = grad ? w.Yatt : nullptr;

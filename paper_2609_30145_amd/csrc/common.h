@@ -25,6 +25,8 @@ constexpr int kKAlign = 64;     // K segments (young, old) padded to this
 constexpr int kNAlign = 128;    // wavelength axis padded to this
 constexpr int kMAlign = 128;    // batch rows padded to this (contraction M tile)
 constexpr int kKTile = 32;      // K tile of the occupancy bitmask (FP32 / FP64 kernels)
+constexpr int kMaxKPad = 32768; // largest padded K (weight rows) a library may have
+constexpr int kMaxKTiles32 = kMaxKPad / kKTile;
 
 // theta scalar columns (see include/sps.h)
 enum ThetaCol {
@@ -113,6 +115,50 @@ __device__ __forceinline__ void balanced_tile(int n_mt, int n_nt, int blocks_per
   const int rot = n_mt > blocks_per_cu ? n_mt / blocks_per_cu : 1;
   mt = (mm + rot * (n / grp)) % n_mt;
   nt = n;
+}
+
+// Active K-tile list of the M tile whose rows start at m0: OR of the rows' occupancy
+// bits (one bit per 32-wide K tile, mask_words words per row), grouped into tiles of
+// 32*tf; the young tiles come first in the K order, so the list starts with them.
+// Run by the whole block; s_tl receives the tile ids in order, s_or is 64 words of
+// scratch, s_n two ints.  Returns the list length and the count of young tiles.
+__device__ __forceinline__ void block_tile_list(const uint32_t *__restrict__ rowmask, int mask_words, int m0, int MT,
+                                                int tf, int n_tiles32, int young_tiles32, int *s_tl, uint32_t *s_or,
+                                                int *s_n, int &n_act, int &n_young) {
+  const int tid = threadIdx.x;
+  if (tid < 64) s_or[tid] = 0u;
+  __syncthreads();
+  const uint32_t *rm = rowmask + (size_t)m0 * mask_words;
+  for (int idx = tid; idx < MT * mask_words; idx += blockDim.x) {
+    const uint32_t v = rm[idx];
+    if (v) atomicOr(&s_or[idx % mask_words], v);
+  }
+  __syncthreads();
+  if (tid < 64) {   // one wave: ballot over 64 tiles at a time, positions by prefix popcount
+    const int n_tiles = (n_tiles32 + tf - 1) / tf, y_tiles = young_tiles32 / tf;
+    int count = 0, ycount = 0;
+    for (int base = 0; base < n_tiles; base += 64) {
+      const int t = base + tid;
+      bool on = false;
+      if (t < n_tiles)
+        for (int q = 0; q < tf; ++q) {
+          const int t32 = t * tf + q;
+          if (t32 < n_tiles32) on |= ((s_or[t32 >> 5] >> (t32 & 31)) & 1u) != 0u;
+        }
+      const unsigned long long bal = __ballot(on);
+      if (on) s_tl[count + __popcll(bal & ((1ull << tid) - 1ull))] = t;
+      count += __popcll(bal);
+      const unsigned long long yb = __ballot(on && t < y_tiles);
+      ycount += __popcll(yb);
+    }
+    if (tid == 0) {
+      s_n[0] = count;
+      s_n[1] = ycount;
+    }
+  }
+  __syncthreads();
+  n_act = s_n[0];
+  n_young = s_n[1];
 }
 
 // ---------------------------------------------------------------- device helpers

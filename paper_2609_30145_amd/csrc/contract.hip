@@ -14,8 +14,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 struct ContractArgs {
   const void *W, *Wlo;
   const void *LTa, *LTb;   // FP32/FP64: LTa; 16-bit: hi (LTa) and residual (LTb) planes
-  int K_pad, N_pad, B_pad, n_tiles;
-  const int *tiles, *n_young, *n_act;
+  int K_pad, N_pad, B_pad;
+  const uint32_t *rowmask;   // [B_pad][mask_words] occupancy bits of 32-wide K tiles
+  int mask_words, n_tiles32, young_tiles32;
+  unsigned long long *counter;
   const PointRow *rows;
   const float *lnlv, *da, *dd;
   const double *lnlv_d, *da_d, *dd_d;
@@ -124,8 +126,12 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
         if constexpr (PRECISE) dacc[i][j][e] = 0.0;
       }
 
-  const int nact = a.n_act[mt], ny = a.n_young[mt];
-  const int *tl = a.tiles + (size_t)mt * a.n_tiles;
+  __shared__ int tl[kMaxKTiles32];
+  __shared__ uint32_t s_or[64];
+  __shared__ int s_n[2];
+  int nact, ny;
+  block_tile_list(a.rowmask, a.mask_words, m0, MT, 1, a.n_tiles32, a.young_tiles32, tl, s_or, s_n, nact, ny);
+  if (nt == 0 && threadIdx.x == 0 && a.counter) atomicAdd(a.counter, (unsigned long long)nact);
 
   f32x4 ra[A4], rb[B4];
 #define SPS_GLOAD32(t_)                                                              \
@@ -262,8 +268,12 @@ __global__ void __launch_bounds__(256) k_contract_f64(ContractArgs a) {
     sp[r][4] = 0.85 - 1.9 * pr.delta;
   }
   double acc[4][4] = {};
-  const int nact = a.n_act[mt], ny = a.n_young[mt];
-  const int *tl = a.tiles + (size_t)mt * a.n_tiles;
+  __shared__ int tl[kMaxKTiles32];
+  __shared__ uint32_t s_or[64];
+  __shared__ int s_n[2];
+  int nact, ny;
+  block_tile_list(a.rowmask, a.mask_words, m0, MT, 1, a.n_tiles32, a.young_tiles32, tl, s_or, s_n, nact, ny);
+  if (nt == 0 && threadIdx.x == 0 && a.counter) atomicAdd(a.counter, (unsigned long long)nact);
   auto apply_bc = [&]() {
     for (int i = 0; i < 4; ++i)
       for (int j = 0; j < 4; ++j) {
@@ -309,9 +319,7 @@ __global__ void __launch_bounds__(256) k_contract_f64(ContractArgs a) {
 int contract_mtile(int precision) { return precision <= 1 ? 64 : 128; }
 int contract_ktile_factor(int precision) { return precision >= 2 ? 2 : 1; }
 
-hipError_t launch_contract16_impl(const DevLib &lib, const void *W, const void *Wlo, const int *tiles,
-                                  const int *n_young, const int *n_act, const PointRow *rows, void *F, void *Yatt,
-                                  int precision, int n_mt, hipStream_t s);
+hipError_t launch_contract16_impl(const DevLib &lib, const ContractLaunch &cl, int n_mt, hipStream_t s);
 
 hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStream_t s) {
   ContractArgs a;
@@ -320,9 +328,11 @@ hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStrea
   a.K_pad = lib.K_pad;
   a.N_pad = lib.N_pad;
   a.B_pad = cl.B_pad;
-  a.tiles = cl.tiles;
-  a.n_young = cl.n_young;
-  a.n_act = cl.n_act;
+  a.rowmask = cl.rowmask;
+  a.mask_words = cl.mask_words;
+  a.n_tiles32 = lib.K_pad / kKTile;
+  a.young_tiles32 = lib.K_young_pad / kKTile;
+  a.counter = cl.counter;
   a.rows = cl.rows;
   a.lnlv = lib.lnlv_f;
   a.da = lib.dust_a_f;
@@ -334,7 +344,6 @@ hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStrea
   a.Yatt = cl.Yatt;
   const int MT = contract_mtile(cl.precision);
   const int n_mt = cl.B_pad / MT;
-  a.n_tiles = lib.K_pad / (kKTile * contract_ktile_factor(cl.precision));
   if (cl.precision == 0) {
     a.LTa = lib.LT64;
     hipLaunchKernelGGL(k_contract_f64, dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
@@ -345,8 +354,7 @@ hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStrea
     else
       hipLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, false, 2>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
   } else {
-    return launch_contract16_impl(lib, cl.W, cl.Wlo, cl.tiles, cl.n_young, cl.n_act, cl.rows, cl.F, cl.Yatt,
-                                  cl.precision, n_mt, s);
+    return launch_contract16_impl(lib, cl, n_mt, s);
   }
   return hipGetLastError();
 }

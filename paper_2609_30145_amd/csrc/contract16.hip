@@ -16,8 +16,10 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 struct ContractArgs16 {
   const uint16_t *Wh, *Wl, *H, *R;
-  int K_pad, N_pad, n_tiles;
-  const int *tiles, *n_young, *n_act;
+  int K_pad, N_pad;
+  const uint32_t *rowmask;   // [B_pad][mask_words] occupancy bits of 32-wide K tiles
+  int mask_words, n_tiles32, young_tiles32;
+  unsigned long long *counter;
   const PointRow *rows;
   const float *lnlv, *da, *dd;
   float *F;
@@ -88,8 +90,12 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[0][j][e] = 0.f;
 
-  const int nact = a.n_act[mt], ny = a.n_young[mt];
-  const int *tl = a.tiles + (size_t)mt * a.n_tiles;
+  __shared__ int tl[kMaxKTiles32 / 2];   // active 64-wide K tiles of this M tile
+  __shared__ uint32_t s_or[64];
+  __shared__ int s_n[2];
+  int nact, ny;
+  block_tile_list(a.rowmask, a.mask_words, m0, MT, 2, a.n_tiles32, a.young_tiles32, tl, s_or, s_n, nact, ny);
+  if (nt == 0 && tid == 0 && a.counter) atomicAdd(a.counter, (unsigned long long)nact);
   // weight fragments of this wave's 32-row group: lane (li, lh) takes chunk lh*4 + s of
   // row li at MFMA step s (the same permutation of K as the library fragments below)
   const size_t wbase = (size_t)((m0 >> 5) + wm) * n_kt * (KT * 32) + (size_t)(lh * 4) * 256 + li * 8;
@@ -195,33 +201,33 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
   }
 }
 
-struct ContractArgs;   // FP32/FP64 argument block (contract.hip)
 
 template <bool BF, int PASSES>
 static void launch16(const ContractArgs16 &a, int n_mt, int N_pad, hipStream_t s) {
   hipLaunchKernelGGL((k_contract_16<BF, PASSES>), dim3(n_mt * (N_pad / 64)), dim3(256), 0, s, a);
 }
 
-hipError_t launch_contract16_impl(const DevLib &lib, const void *W, const void *Wlo, const int *tiles,
-                                  const int *n_young, const int *n_act, const PointRow *rows, void *F, void *Yatt,
-                                  int precision, int n_mt, hipStream_t s) {
+hipError_t launch_contract16_impl(const DevLib &lib, const ContractLaunch &cl, int n_mt, hipStream_t s) {
   ContractArgs16 a;
+  const int precision = cl.precision;
   const bool bf = precision == 2 || precision == 4 || precision == 6;
-  a.Wh = (const uint16_t *)W;
-  a.Wl = (const uint16_t *)Wlo;
+  a.Wh = (const uint16_t *)cl.W;
+  a.Wl = (const uint16_t *)cl.Wlo;
   a.H = bf ? lib.Hb : lib.Hh;
   a.R = bf ? lib.Rb : lib.Rh;
   a.K_pad = lib.K_pad;
   a.N_pad = lib.N_pad;
-  a.n_tiles = lib.K_pad / (kKTile * 2);
-  a.tiles = tiles;
-  a.n_young = n_young;
-  a.n_act = n_act;
-  a.rows = rows;
+  a.rowmask = cl.rowmask;
+  a.mask_words = cl.mask_words;
+  a.n_tiles32 = lib.K_pad / kKTile;
+  a.young_tiles32 = lib.K_young_pad / kKTile;
+  a.counter = cl.counter;
+  a.rows = cl.rows;
   a.lnlv = lib.lnlv_f;
   a.da = lib.dust_a_f;
   a.dd = lib.dust_d_f;
-  a.F = (float *)F;
+  a.F = (float *)cl.F;
+  const void *Yatt = cl.Yatt;
   // the gradient pass (which needs the young part) runs on the FP32 / FP64 paths only
   if (!a.H || !a.R || Yatt) return hipErrorInvalidValue;
   switch (precision) {

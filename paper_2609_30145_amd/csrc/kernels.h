@@ -7,7 +7,7 @@ namespace sps {
 struct PrepLaunch {
   const double *theta;
   int P, B, B_pad;
-  const int *perm;
+  const double *keys;        // batch-ordering keys from launch_keys
   const DevObs *obs_table;
   const int *point_obs;
   void *W, *Wlo;
@@ -21,15 +21,17 @@ struct PrepLaunch {
 };
 
 size_t prep_smem_bytes(const DevLib &lib, int mode);   // mode as PrepLaunch::mode
-hipError_t launch_sort(const DevLib &lib, const double *theta, int P, int B, double *keys, int *perm, hipStream_t s);
+// batch-ordering keys (the weight builder ranks the points by them)
+hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, hipStream_t s);
+// weights, per-row K-tile occupancy bits and per-point rows, each point at its rank
 hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s);
-hipError_t launch_tiles(const uint32_t *rowmask, int mask_words, int B_pad, int MT, int n_tiles32, int young_tiles32,
-                        int tf, int *tiles, int *n_young, int *n_act, unsigned long long *counter, hipStream_t s);
 
 struct ContractLaunch {
   const void *W, *Wlo;       // weights (hi/lo planes for 16-bit)
   int B_pad;
-  const int *tiles, *n_young, *n_act;
+  const uint32_t *rowmask;   // [B_pad][mask_words] K-tile occupancy bits per row (32-wide tiles)
+  int mask_words;
+  unsigned long long *counter;   // executed K tiles are added here (timing), or NULL
   const PointRow *rows;
   void *F;                   // [B_pad][N_pad] attenuated rest-frame spectrum (float or double)
   void *Yatt;                // optional [B_pad][N_pad]: young part after both attenuations

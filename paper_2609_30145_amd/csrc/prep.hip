@@ -31,25 +31,6 @@ __global__ void __launch_bounds__(256) k_keys(DevLib lib, const double *__restri
   if (b < B) keys[b] = sort_key(lib, theta + (size_t)b * P);
 }
 
-// One workgroup per point: rank = number of points with a smaller (key, index).
-__global__ void __launch_bounds__(256) k_sort(const double *__restrict__ keys, int B, int *__restrict__ perm) {
-  __shared__ int cnt[256];
-  const int b = blockIdx.x;
-  const double my = keys[b];
-  int c = 0;
-  for (int j = threadIdx.x; j < B; j += 256) {
-    const double kj = keys[j];
-    c += (kj < my) || (kj == my && j < b);
-  }
-  cnt[threadIdx.x] = c;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) cnt[threadIdx.x] += cnt[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) perm[cnt[0]] = b;
-}
-
 // ---------------------------------------------------------------------------------
 // Weight builder.  One workgroup per sorted row.
 // ---------------------------------------------------------------------------------
@@ -109,7 +90,7 @@ enum WMode { W_F64 = 0, W_F32 = 1, W_BF16 = 2, W_F16 = 3 };
 struct PrepArgs {
   const double *theta;
   int P, B, B_pad;
-  const int *perm;
+  const double *keys;       // [B] batch-ordering keys (k_keys)
   const DevObs *obs_table;
   const int *point_obs;     // [B] observation slot per point, NULL = slot 0
   void *W;                  // F64/F32: [B_pad][K_pad]; 16-bit: hi plane
@@ -197,9 +178,24 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   __shared__ double s_tu;
   __shared__ uint32_t s_bits[64];
 
-  const int r = blockIdx.x;
+  // workgroup b takes point b (caller's order); its row r is the point's rank in the
+  // key order (ties by index).  Workgroups past B clear the padding rows.
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int b = r < a.B ? a.perm[r] : -1;
+  const int b = blockIdx.x < a.B ? blockIdx.x : -1;
+  int r = blockIdx.x;
+  if (b >= 0) {
+    __shared__ int s_rank[4];
+    const double my = a.keys[b];
+    int c = 0;
+    for (int j = tid; j < a.B; j += 256) {
+      const double kj = a.keys[j];
+      c += (kj < my) || (kj == my && j < b);
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane == 0) s_rank[wv] = c;
+    __syncthreads();
+    r = (s_rank[0] + s_rank[1]) + (s_rank[2] + s_rank[3]);
+  }
   const size_t rowoff = (size_t)r * K_pad;
 
   if (b < 0) {   // padding row: zero weights
@@ -482,75 +478,14 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
 }
 
 // ---------------------------------------------------------------------------------
-// Active K-tile list per M tile (OR of the row masks).  Tiles of kKTile * tf columns.
-// ---------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_tiles(const uint32_t *__restrict__ rowmask, int mask_words, int MT,
-                                               int n_tiles32, int young_tiles32, int tf, int *__restrict__ tiles,
-                                               int *__restrict__ n_young, int *__restrict__ n_act,
-                                               unsigned long long *__restrict__ counter) {
-  __shared__ uint32_t acc[64];
-  __shared__ int cnt[256], cy[256];
-  const int mt = blockIdx.x, tid = threadIdx.x;
-  if (tid < 64) acc[tid] = 0u;
-  __syncthreads();
-  for (int idx = tid; idx < MT * mask_words; idx += 256) {
-    const int r = idx / mask_words, w = idx - r * mask_words;
-    const uint32_t v = rowmask[(size_t)(mt * MT + r) * mask_words + w];
-    if (v) atomicOr(&acc[w], v);
-  }
-  __syncthreads();
-  const int n_tiles = (n_tiles32 + tf - 1) / tf;
-  const int y_tiles = young_tiles32 / tf;
-  const int chunk = (n_tiles + 255) / 256;
-  const int t0 = min(tid * chunk, n_tiles), t1 = min(t0 + chunk, n_tiles);
-  auto on_tile = [&](int t) {
-    bool on = false;
-    for (int q = 0; q < tf; ++q) {
-      const int t32 = t * tf + q;
-      if (t32 < n_tiles32) on |= (acc[t32 >> 5] >> (t32 & 31)) & 1u;
-    }
-    return on;
-  };
-  int c = 0, y = 0;
-  for (int t = t0; t < t1; ++t)
-    if (on_tile(t)) {
-      ++c;
-      y += t < y_tiles;
-    }
-  cnt[tid] = c;
-  cy[tid] = y;
-  __syncthreads();
-  // inclusive scan of cnt (Hillis-Steele), sum of cy
-  for (int off = 1; off < 256; off <<= 1) {
-    const int v = tid >= off ? cnt[tid - off] : 0;
-    __syncthreads();
-    cnt[tid] += v;
-    __syncthreads();
-  }
-  for (int s2 = 128; s2 > 0; s2 >>= 1) {
-    if (tid < s2) cy[tid] += cy[tid + s2];
-    __syncthreads();
-  }
-  int pos = cnt[tid] - c;
-  for (int t = t0; t < t1; ++t)
-    if (on_tile(t)) tiles[mt * n_tiles + pos++] = t;
-  if (tid == 0) {
-    n_act[mt] = cnt[255];
-    n_young[mt] = cy[0];
-    if (counter) atomicAdd(counter, (unsigned long long)cnt[255]);
-  }
-}
-
-// ---------------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------------
 size_t prep_smem_bytes(const DevLib &lib, int mode) {
   return sizeof(double) * (size_t)PrepSmem(lib, mode == W_F64).total;
 }
 
-hipError_t launch_sort(const DevLib &lib, const double *theta, int P, int B, double *keys, int *perm, hipStream_t s) {
+hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, hipStream_t s) {
   hipLaunchKernelGGL(k_keys, dim3((B + 255) / 256), dim3(256), 0, s, lib, theta, P, B, keys);
-  hipLaunchKernelGGL(k_sort, dim3(B), dim3(256), 0, s, keys, B, perm);
   return hipGetLastError();
 }
 
@@ -560,7 +495,7 @@ hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s) {
   a.P = pl.P;
   a.B = pl.B;
   a.B_pad = pl.B_pad;
-  a.perm = pl.perm;
+  a.keys = pl.keys;
   a.obs_table = pl.obs_table;
   a.point_obs = pl.point_obs;
   a.W = pl.W;
@@ -592,11 +527,5 @@ hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_tiles(const uint32_t *rowmask, int mask_words, int B_pad, int MT, int n_tiles32, int young_tiles32,
-                        int tf, int *tiles, int *n_young, int *n_act, unsigned long long *counter, hipStream_t s) {
-  hipLaunchKernelGGL(k_tiles, dim3(B_pad / MT), dim3(256), 0, s, rowmask, mask_words, MT, n_tiles32, young_tiles32,
-                     tf, tiles, n_young, n_act, counter);
-  return hipGetLastError();
-}
 
 }  // namespace sps
