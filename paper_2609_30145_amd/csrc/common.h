@@ -79,6 +79,7 @@ struct DevObs {
   const double *ksig;                // [n_pix] continuum kernel dispersion in ln(lambda)
   const double *lsf_vals;            // [n_pix] LSF parameter curve (eq. F2 units) or NULL
   double sigma_gas_kms, lsf_value;   // gas dispersion; constant LSF parameter
+  double fwln_min, fwln_max;         // ln of the shortest and longest filter node
   const double *data, *sigma;        // [n_data]
   const uint8_t *mask;               // [n_data] final inclusion mask
 };

@@ -155,8 +155,8 @@ struct PrepSmem {
 //   A1  theta, node tables, cell bounds and photon rates to LDS; weight row cleared;
 //       Gauss-Legendre partial sums of D_C
 //   A2  wave 0: t_univ and the bin edges; the other waves: the bin metallicities and
-//       their bracketing nodes; all waves: the interpolated line terms 10^Lhat (they
-//       depend on the gas parameters only)
+//       their bracketing nodes; then all waves: the interpolated line terms 10^Lhat
+//       (they depend on the gas parameters only)
 //   B   step-scheme overlap weights, one thread per SSP age (single writer per slot)
 //   C   photon rate per young age, then the line luminosities
 //   D   the row in the contraction's format with its K-tile occupancy bits; the
@@ -254,8 +254,12 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   if (wv == 0) {
     // t_univ in closed form; SFH edges rescaled to it (App. B, Sec. 2.6): T_0 = 0,
     // T_1 = T1, T_n = t_univ, log-uniform in between
+    // (1+z)^{-3/2} by a square root and asinh(x) = ln(x + sqrt(x^2 + 1)) for x > 0: a
+    // shorter chain of double-precision operations than the library pow and asinh
     const double tH_yr = kMpc_km / lib.H0 / kYr_s;
-    const double tu = tH_yr * 2.0 / (3.0 * sqrt(OL)) * asinh(sqrt(OL / Om) * pow(1.0 + z, -1.5));
+    const double opz = 1.0 + z;
+    const double x = sqrt(OL / Om) / (opz * sqrt(opz));
+    const double tu = tH_yr * 2.0 / (3.0 * sqrt(OL)) * log(x + sqrt(x * x + 1.0));
     const double lnR = log(tu / lib.T1);
     for (int i = lane; i <= n_sfh; i += 64) {
       double T;
@@ -305,19 +309,19 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     const size_t o10 = (size_t)((jg + 1) * nu + ju) * slab, o11 = (size_t)((jg + 1) * nu + ju + 1) * slab;
     const double c00 = (1.0 - tg) * (1.0 - tu), c01 = (1.0 - tg) * tu, c10 = tg * (1.0 - tu), c11 = tg * tu;
     const int nq = nl * ny;
-    if (wv > 0) {   // wave 0 is busy with t_univ and the edges
-      for (int q0 = tid - 64; q0 < nq; q0 += 192 * 8) {
+    {
+      for (int q0 = tid; q0 < nq; q0 += 256 * 8) {
         if (MODE == W_F64) {
           const double *tb = lib.line_table;
           double lh[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            const int q = q0 + 192 * u;
+            const int q = q0 + 256 * u;
             lh[u] = q < nq ? c00 * tb[o00 + q] + c01 * tb[o01 + q] + c10 * tb[o10 + q] + c11 * tb[o11 + q] : 0.0;
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            const int q = q0 + 192 * u;
+            const int q = q0 + 256 * u;
             if (q < nq) s_lt[q] = (Acc)exp10(lh[u]);
           }
         } else {
@@ -326,12 +330,12 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
           float lh[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            const int q = q0 + 192 * u;
+            const int q = q0 + 256 * u;
             lh[u] = q < nq ? f00 * tb[o00 + q] + f01 * tb[o01 + q] + f10 * tb[o10 + q] + f11 * tb[o11 + q] : 0.f;
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            const int q = q0 + 192 * u;
+            const int q = q0 + 256 * u;
             if (q < nq) s_lt[q] = (Acc)exp10f(lh[u]);
           }
         }
@@ -388,11 +392,19 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       s_wq[ag] = s;
     }
     __syncthreads();
-    for (int l = tid; l < nl; l += 256) {
+    // two threads per line (adjacent lanes), each over half of the young ages
+    const int half = tid & 1, nyh = (ny + 1) >> 1;
+    const int a0 = half ? nyh : 0, a1 = half ? ny : nyh;
+    for (int l0 = 0; l0 < nl; l0 += 128) {
+      const int l = l0 + (tid >> 1);
       double Ll = 0.0;
-      for (int ag = 0; ag < ny; ++ag) Ll += (double)s_lt[l * ny + ag] * s_wq[ag];
-      if (kind == 0) wacc[a.line_k0 + l] = (Acc)(Ll / kLsun);     // photometry: lines on the model grid
-      else a.Lline[(size_t)r * nl + l] = Ll;                      // spectra: lines on the detector pixels
+      if (l < nl)
+        for (int ag = a0; ag < a1; ++ag) Ll += (double)s_lt[l * ny + ag] * s_wq[ag];
+      Ll += __shfl_xor(Ll, 1);
+      if (l < nl && half == 0) {
+        if (kind == 0) wacc[a.line_k0 + l] = (Acc)(Ll / kLsun);   // photometry: lines on the model grid
+        else a.Lline[(size_t)r * nl + l] = Ll;                    // spectra: lines on the detector pixels
+      }
     }
     __syncthreads();
   }

@@ -40,10 +40,14 @@ __device__ double sigma_inst_mode(int mode, double v, double lam) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
+__global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
   __shared__ double red[256];
-  __shared__ double sbuf[4096];   // photometry: per-node terms; spectra: per-line tables
-  double *s_lnl = sbuf, *s_sl = sbuf + 512, *s_amp = sbuf + 1024;
+  // photometry: per-node terms (in the path's precision); spectra: per-line tables
+  constexpr int kTermBytes = 4096 * (int)sizeof(T), kLineBytes = 3 * 512 * 8;
+  __shared__ __attribute__((aligned(16))) unsigned char sraw[kTermBytes > kLineBytes ? kTermBytes : kLineBytes];
+  T *s_term = (T *)sraw;
+  constexpr int kSegOff = 0, kSegMax = kTermBytes / 4;   // FP32 photometry: model pixels under the filters
+  double *s_lnl = (double *)sraw, *s_sl = s_lnl + 512, *s_amp = s_lnl + 1024;
   __shared__ double s_noise[4];
   const int r = blockIdx.x;
   const PointRow pr = a.rows[r];
@@ -92,62 +96,144 @@ __global__ void __launch_bounds__(256) k_project(DevLib lib, ProjArgs<T> a) {
     const double fac = kC_cms * pr.scale_fnu / (opz * opz * kAng_cm * kAng_cm);
     const double lnopz = log1p(z);
     const double wlo = lib.wave_d[0], whi = lib.wave_d[N - 1];
-    // one pass over all filter nodes, eight per thread in flight, terms kept in LDS.
     // On a log-uniform rest grid the bracketing interval follows from ln(lambda)
     // directly; a node within rounding of a grid point may take the neighbouring
     // interval, where the interpolation weight is within rounding of 0 or 1.
-    for (int j0 = tid; j0 < ob.n_fnodes; j0 += 2048) {
-      int kq[8];
-      double lrq[8];
-      bool in[8];
+    // FP32 path on a log-uniform rest grid: the model pixels under the filters (the
+    // rest-frame span of the nodes) are staged in LDS with one coalesced pass, then each
+    // wave takes whole bands, lanes over the band's nodes, and reduces them itself.  The
+    // weight linear in lambda on [w_k, w_k+1] is (e^{f d} - 1)/(e^d - 1), f the fractional
+    // log index; a node is inside the model grid when its log index lies in [0, N - 1].
+    const double ui0 = -(lnopz + lib.lnw0) * lib.inv_dlnw;   // log index = fwln * inv_dlnw + ui0
+    int seg0 = 0, seg_n = 0;
+    if (sizeof(T) == 4 && lib.log_uniform) {
+      seg0 = min(max((int)floor(ob.fwln_min * lib.inv_dlnw + ui0), 0), N - 2);
+      seg_n = min(max((int)floor(ob.fwln_max * lib.inv_dlnw + ui0), 0), N - 2) + 2 - seg0;
+    }
+    if (sizeof(T) == 4 && lib.log_uniform && seg_n <= kSegMax) {
+      float *seg = (float *)(sraw + kSegOff);
+      for (int k0 = tid; k0 < seg_n; k0 += 256 * 8) {   // eight loads per thread in flight
+        float v[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int j = j0 + 256 * q;
-        in[q] = false;
-        kq[q] = 0;
-        lrq[q] = 0.0;
-        if (j < ob.n_fnodes) {
-          lrq[q] = ob.fw[j] / opz;
-          in[q] = lrq[q] >= wlo && lrq[q] <= whi;
-          if (in[q]) {
-            if (lib.log_uniform) {
-              const int k = (int)floor((ob.fwln[j] - lnopz - lib.lnw0) * lib.inv_dlnw);
-              kq[q] = min(max(k, 0), N - 2);
-            } else {
-              kq[q] = bracket(lib.wave_d, N, lrq[q]);
+        for (int q = 0; q < 8; ++q) v[q] = k0 + 256 * q < seg_n ? (float)Fr[seg0 + k0 + 256 * q] : 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + 256 * q < seg_n) seg[k0 + 256 * q] = v[q];
+      }
+      __syncthreads();
+      const double d = 1.0 / lib.inv_dlnw;
+      const float df = (float)d, inv_em1 = (float)(1.0 / expm1(d));
+      const double umax = (double)(N - 1);
+      const int wave_id = tid >> 6, lane = tid & 63;
+      // wave w takes bands w, w+4, ...; four of its bands at a time, so that their node
+      // loads are in flight together (issued unconditionally from clamped indices) and
+      // their four wave reductions interleave
+      for (int g0 = wave_id; g0 < ob.n_band; g0 += 16) {
+        float part[4] = {0.f, 0.f, 0.f, 0.f};
+        int jlo[4], jhi[4], len = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int band = g0 + 4 * i;
+          jlo[i] = band < ob.n_band ? ob.band_off[band] : 0;
+          jhi[i] = band < ob.n_band ? ob.band_off[band + 1] : 0;
+          len = max(len, jhi[i] - jlo[i]);
+        }
+        for (int jb = 0; jb < len; jb += 128) {   // two nodes per lane and band per pass
+          double uq[8];
+          float rq[8];
+          bool ok[8];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const int j = jlo[i] + jb + 64 * q + lane;
+              ok[2 * i + q] = j < jhi[i];
+              const int jc = j < jhi[i] ? j : 0;
+              uq[2 * i + q] = ob.fwln[jc];
+              rq[2 * i + q] = ob.fr_f[jc];
+            }
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const int n = 2 * i + q;
+              const double u = uq[n] * lib.inv_dlnw + ui0;
+              const bool in = ok[n] && u >= 0.0 && u <= umax;
+              const int k = min(max((int)floor(u), 0), N - 2);
+              const int kk = in ? k - seg0 : 0;
+              const float t = (expf((float)(u - (double)k) * df) - 1.f) * inv_em1;
+              const float f0 = seg[kk], f1 = seg[kk + 1];
+              part[i] += in ? rq[n] * (f0 + t * (f1 - f0)) : 0.f;
+            }
+        }
+        // FP32 butterfly (the terms are FP32 products; at most 4096 of them per band)
+        for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) part[i] += __shfl_xor(part[i], o, 64);
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (g0 + 4 * i < ob.n_band) red[g0 + 4 * i] = (double)part[i];
+        }
+      }
+      __syncthreads();
+      for (int band = tid; band < ob.n_band; band += 256) datum(band, fac * red[band]);
+    } else {
+      // one pass over all filter nodes, eight per thread in flight, terms kept in LDS
+      for (int j0 = tid; j0 < ob.n_fnodes; j0 += 2048) {
+        int kq[8];
+        double lrq[8];
+        bool in[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int j = j0 + 256 * q;
+          in[q] = false;
+          kq[q] = 0;
+          lrq[q] = 0.0;
+          if (j < ob.n_fnodes) {
+            lrq[q] = ob.fw[j] / opz;
+            in[q] = lrq[q] >= wlo && lrq[q] <= whi;
+            if (in[q]) {
+              if (lib.log_uniform) {
+                const int k = (int)floor((ob.fwln[j] - lnopz - lib.lnw0) * lib.inv_dlnw);
+                kq[q] = min(max(k, 0), N - 2);
+              } else {
+                kq[q] = bracket(lib.wave_d, N, lrq[q]);
+              }
             }
           }
         }
-      }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int j = j0 + 256 * q;
-        if (j < ob.n_fnodes) {
-          double term = 0.0;
-          if (in[q]) {
-            const int k = kq[q];
-            const double w0 = lib.wave_d[k], w1 = lib.wave_d[k + 1];
-            const T f0 = Fr[k], f1 = Fr[k + 1];
-            const T w = sizeof(T) == 8 ? (T)ob.fr_d[j] : (T)ob.fr_f[j];
-            const T t = (T)((lrq[q] - w0) / (w1 - w0));
-            term = (double)(w * (f0 + t * (f1 - f0)));
+        for (int q = 0; q < 8; ++q) {
+          const int j = j0 + 256 * q;
+          if (j < ob.n_fnodes) {
+            double term = 0.0;
+            if (in[q]) {
+              const int k = kq[q];
+              const double w0 = lib.wave_d[k], w1 = lib.wave_d[k + 1];
+              const T f0 = Fr[k], f1 = Fr[k + 1];
+              const T w = sizeof(T) == 8 ? (T)ob.fr_d[j] : (T)ob.fr_f[j];
+              const T t = (T)((lrq[q] - w0) / (w1 - w0));
+              term = (double)(w * (f0 + t * (f1 - f0)));
+            }
+            s_term[j] = (T)term;
           }
-          sbuf[j] = term;
         }
       }
+      __syncthreads();
+      // fixed-order band sums: one wave per band
+      const int wave_id = tid >> 6, lane = tid & 63;
+      for (int band = wave_id; band < ob.n_band; band += 4) {
+        const int j0 = ob.band_off[band], j1 = ob.band_off[band + 1];
+        double part = 0.0;
+        for (int j = j0 + lane; j < j1; j += 64) part += (double)s_term[j];
+        const double s = wave_reduce_sum(part);
+        if (lane == 0) red[band] = s;
+      }
+      __syncthreads();
+      for (int band = tid; band < ob.n_band; band += 256) datum(band, fac * red[band]);
     }
-    __syncthreads();
-    // fixed-order band sums: one wave per band
-    const int wave_id = tid >> 6, lane = tid & 63;
-    for (int band = wave_id; band < ob.n_band; band += 4) {
-      const int j0 = ob.band_off[band], j1 = ob.band_off[band + 1];
-      double part = 0.0;
-      for (int j = j0 + lane; j < j1; j += 64) part += sbuf[j];
-      const double s = wave_reduce_sum(part);
-      if (lane == 0) red[band] = s;
-    }
-    __syncthreads();
-    for (int band = tid; band < ob.n_band; band += 256) datum(band, fac * red[band]);
   } else {
     // ---------------- spectrum (eq. F5-F6)
     const double lnopz = log1p(z);

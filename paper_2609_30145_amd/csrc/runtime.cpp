@@ -95,6 +95,11 @@ sps_status upload_obs(const ObsHost &host, DevObs &o, DeviceBuffers &mem, hipStr
     o.fwln = (const double *)put(host.fwln.data(), host.fwln.size() * 8);
     o.fr_d = (const double *)put(host.fr.data(), host.fr.size() * 8);
     o.fr_f = (const float *)put(host.fr_f.data(), host.fr_f.size() * 4);
+    o.fwln_min = o.fwln_max = host.fwln.empty() ? 0.0 : host.fwln[0];
+    for (double v : host.fwln) {
+      o.fwln_min = std::min(o.fwln_min, v);
+      o.fwln_max = std::max(o.fwln_max, v);
+    }
   } else {
     o.pix = (const double *)put(host.pix.data(), host.pix.size() * 8);
     o.lnpix = (const double *)put(host.lnpix.data(), host.lnpix.size() * 8);
