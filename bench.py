@@ -127,6 +127,48 @@ def cpu_baseline(cfg_name, budget_s=12.0, seed=0):
                        f"(FP64 NumPy, BLAS dgemm contraction), {dt:.1f} s")
 
 
+def spectrum_leg(steps=20, warmup=3, seed=0):
+    """The spectroscopic workload at full size: 1024 live points, 3000-pixel prism
+    spectrum (R_fwhm = 100, 5-sigma LSF rows, 128 lines on the pixels); forward + logL
+    in FP16 hi + residual and FP32, and the FP32 gradient (P = 158) for the record."""
+    import torch
+
+    import paper_2609_30145_amd as sps
+    from synth import workloads as wl
+    cfg = wl.CONFIGS["c3"]
+    lib = wl.make_library(cfg, seed)
+    lines = wl.make_lines(cfg, lib, seed + 1)
+    dust = wl.make_dust_tables(cfg, lib["wave"])
+    L = sps.Library(lib, n_sfh=cfg.n_sfh, T1=cfg.T1, n_zh=cfg.n_zh, cosmo=cfg.cosmo, dust=dust, lines=lines,
+                    precisions=("fp32", "fp16"))
+    g = wl.make_spectrum_grid(cfg.n_pix)
+    th_true = wl.make_theta(cfg, 1, seed=seed + 1002)
+    O = sps.Observation(L, "spec", cfg.batch, pix_wave=g["pix_wave"], lsf_mode=g["lsf_mode"],
+                        lsf_value=g["lsf_value"], z_ref=float(th_true[0, 1]), sigma_gas_kms=g["sigma_gas_kms"])
+    m_true = sps.forward(L, O, torch.tensor(th_true, device="cuda"), "fp32")[0].cpu().numpy()
+    d, sg = wl.noisy_spectrum(m_true, seed + 5)
+    O.set_data(d, sg)
+    theta = torch.tensor(wl.make_theta(cfg, cfg.batch, seed=seed + 2), device="cuda")
+    out = {"workload": f"{cfg.batch} live points, {cfg.n_pix}-pixel prism spectrum (R_fwhm 100), library "
+                       f"{cfg.n_age} x {len(cfg.logz)} x {cfg.n_wave}, {cfg.n_lines} lines"}
+    for p in ("fp16", "fp32"):
+        dt, tim = time_precision(L, O, theta, p, steps, warmup)
+        out[f"forward_{p}_evals_per_s"] = round(cfg.batch * steps / dt, 1)
+        out[f"forward_{p}_ms"] = round(1e3 * dt / steps, 4)
+    for _ in range(warmup):
+        sps.logl_grad(L, O, theta, "fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sps.logl_grad(L, O, theta, "fp32")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["gradient_fp32_evals_per_s"] = round(cfg.batch * steps / dt, 1)
+    out["gradient_fp32_ms"] = round(1e3 * dt / steps, 4)
+    out["P"] = int(theta.shape[1])
+    return out
+
+
 def serve_leg(seconds, rate_hz=50.0, target_load=0.5, seed=0, log=None):
     """Poisson stream of photometry / prism-spectrum fit requests served by sps_server on
     the alpha-enhanced library in FP16.  Capacity is measured first with a saturating
@@ -210,6 +252,7 @@ def main():
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--also", default="fp32,bf16", help="other precisions timed for the record")
+    ap.add_argument("--no-spectrum", action="store_true", help="skip the spectroscopic leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -284,6 +327,8 @@ def main():
         "by_precision": {p: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                          for p, r in results.items()},
     }
+    if not args.no_spectrum:
+        out["spectrum"] = spectrum_leg()
     if args.serve_seconds > 0:
         out["serving"] = serve_leg(args.serve_seconds, log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:

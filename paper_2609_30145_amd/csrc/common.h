@@ -80,6 +80,7 @@ struct DevObs {
   const double *lsf_vals;            // [n_pix] LSF parameter curve (eq. F2 units) or NULL
   double sigma_gas_kms, lsf_value;   // gas dispersion; constant LSF parameter
   double fwln_min, fwln_max;         // ln of the shortest and longest filter node
+  double ksig_max;                   // largest continuum kernel dispersion (spectra)
   const double *data, *sigma;        // [n_data]
   const uint8_t *mask;               // [n_data] final inclusion mask
 };

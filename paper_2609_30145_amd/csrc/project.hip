@@ -42,12 +42,17 @@ __device__ double sigma_inst_mode(int mode, double v, double lam) {
 template <typename T>
 __global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
   __shared__ double red[256];
-  // photometry: per-node terms (in the path's precision); spectra: per-line tables
-  constexpr int kTermBytes = 4096 * (int)sizeof(T), kLineBytes = 3 * 512 * 8;
-  __shared__ __attribute__((aligned(16))) unsigned char sraw[kTermBytes > kLineBytes ? kTermBytes : kLineBytes];
+  // LDS: per-line tables (spectra) and, on the FP32 path, a segment of the model row
+  // (photometry: the pixels under the filters; spectra: the pixels under the LSF rows);
+  // the generic photometry path keeps per-node terms instead
+  constexpr int kLineBytes = 3 * 512 * 8, kTermBytes = 4096 * (int)sizeof(T);
+  constexpr int kSegOff = kLineBytes, kSegMax = sizeof(T) == 4 ? 4096 : 0;
+  constexpr int kRaw1 = kSegOff + 4 * kSegMax;
+  constexpr int kRaw = kRaw1 > kTermBytes ? kRaw1 : kTermBytes;
+  __shared__ __attribute__((aligned(16))) unsigned char sraw[kRaw];
   T *s_term = (T *)sraw;
-  constexpr int kSegOff = 0, kSegMax = kTermBytes / 4;   // FP32 photometry: model pixels under the filters
   double *s_lnl = (double *)sraw, *s_sl = s_lnl + 512, *s_amp = s_lnl + 1024;
+  __shared__ double s_slmax[4];
   __shared__ double s_noise[4];
   const int r = blockIdx.x;
   const PointRow pr = a.rows[r];
@@ -238,8 +243,10 @@ __global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
     // ---------------- spectrum (eq. F5-F6)
     const double lnopz = log1p(z);
     const int nl = a.n_line;
+    double slmax = 0.0;
     if (nl > 0) {
       const double Tfac = pr.mass10 / (4.0 * kPi * pr.dl * pr.dl);
+      double my_max = 0.0;
       for (int l = tid; l < nl; l += 256) {
         const double lw = lib.line_wave[l];
         const double lnlv = log(lw / kLamV);
@@ -260,50 +267,126 @@ __global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
         s_lnl[l] = log(lobs);
         s_sl[l] = sl;
         s_amp[l] = Fl / (2.5066282746310002 * sl);
+        my_max = fmax(my_max, sl);
+      }
+      for (int o = 32; o > 0; o >>= 1) my_max = fmax(my_max, __shfl_xor(my_max, o, 64));
+      if ((tid & 63) == 0) s_slmax[tid >> 6] = my_max;
+      __syncthreads();
+      slmax = fmax(fmax(s_slmax[0], s_slmax[1]), fmax(s_slmax[2], s_slmax[3]));
+    }
+    const double lnw0 = lib.lnwave_d[0], lnw1 = lib.lnwave_d[N - 1];
+    // FP32 path on a log-uniform rest grid: the rows' span of model pixels, times
+    // lambda^2, is staged in LDS; the Gaussian row weights come from the recurrence
+    // w_{j+1} = w_j q_j, q_{j+1} = q_j e^{-h^2} (h = node spacing / row width), which
+    // needs three exponentials per row instead of one per tap
+    int seg0 = 0, seg_n = 0;
+    const bool fast = sizeof(T) == 4 && lib.log_uniform;
+    if (fast) {
+      const double ext = 5.0 * ob.ksig_max * lib.inv_dlnw + 2.0;
+      const double ua = (ob.lnpix[0] - lnopz - lnw0) * lib.inv_dlnw - ext;
+      const double ub = (ob.lnpix[ob.n_data - 1] - lnopz - lnw0) * lib.inv_dlnw + ext;
+      seg0 = (int)fmin(fmax(floor(ua), 0.0), (double)(N - 1));
+      seg_n = (int)fmin(fmax(ceil(ub), 0.0), (double)(N - 1)) + 1 - seg0;
+    }
+    if (fast && seg_n <= kSegMax) {
+      float *seg = (float *)(sraw + kSegOff);
+      for (int k0 = tid; k0 < seg_n; k0 += 256 * 8) {   // eight loads per thread in flight
+        float v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = k0 + 256 * q;
+          v[q] = k < seg_n ? (float)Fr[seg0 + k] * (float)lib.lam2_d[seg0 + k] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + 256 * q < seg_n) seg[k0 + 256 * q] = v[q];
       }
       __syncthreads();
-    }
-    double slmax = 0.0;
-    for (int l = 0; l < nl; ++l) slmax = fmax(slmax, s_sl[l]);
-    const double lnw0 = lib.lnwave_d[0], lnw1 = lib.lnwave_d[N - 1];
-    for (int i = tid; i < ob.n_data; i += 256) {
-      const double x = ob.lnpix[i] - lnopz;
-      T cont = (T)0;
-      if (x >= lnw0 && x <= lnw1) {
-        const double s = ob.ksig[i];
-        const int k = lnwave_bracket(lib, x);
-        const double dk = lib.lnwave_d[k + 1] - lib.lnwave_d[k];
-        if (s < 0.5 * dk) {
-          const T t = (T)((x - lib.lnwave_d[k]) / dk);
-          const T fk = Fr[k] * (T)lib.lam2_d[k], fk1 = Fr[k + 1] * (T)lib.lam2_d[k + 1];
-          cont = fk + t * (fk1 - fk);
-        } else {
-          int j = lnwave_lower_bound(lib, x - 5.0 * s);
-          const double inv = 1.0 / s;
-          double num = 0.0, den = 0.0;
-          for (; j < N; ++j) {
-            const double u = (lib.lnwave_d[j] - x) * inv;
-            if (u > 5.0) break;
-            const T w = sizeof(T) == 8 ? (T)exp(-0.5 * u * u) : (T)expf((float)(-0.5 * u * u));
-            num += (double)(w * (Fr[j] * (T)lib.lam2_d[j]));
-            den += (double)w;
+      const double dln = 1.0 / lib.inv_dlnw;
+      int lwin = 0;   // start of the line window: pixels rise with i, so it only moves up
+      for (int i = tid; i < ob.n_data; i += 256) {
+        const double x = ob.lnpix[i] - lnopz;
+        float cont = 0.f;
+        if (x >= lnw0 && x <= lnw1) {
+          const double s = ob.ksig[i];
+          const double ux = (x - lnw0) * lib.inv_dlnw;   // fractional node index of x
+          if (s < 0.5 * dln) {
+            const int k = min((int)floor(ux), N - 2);
+            const float t = (float)(ux - (double)k);
+            const float g0 = seg[k - seg0], g1 = seg[k + 1 - seg0];
+            cont = g0 + t * (g1 - g0);
+          } else {
+            const double rs = s * lib.inv_dlnw;            // row width in node spacings
+            const int j0 = max((int)ceil(ux - 5.0 * rs), 0);
+            const int j1 = min((int)floor(ux + 5.0 * rs), N - 1);
+            const double a0 = ((double)j0 - ux) / rs, h = 1.0 / rs;
+            float w = expf((float)(-0.5 * a0 * a0));
+            float q = expf((float)(-a0 * h - 0.5 * h * h));
+            const float c = expf((float)(-h * h));
+            float num = 0.f, den = 0.f;
+            for (int j = j0; j <= j1; ++j) {
+              const float g = seg[j - seg0];
+              num += w * g;
+              den += w;
+              w *= q;
+              q *= c;
+            }
+            cont = num / den;
           }
-          cont = (T)(num / den);
         }
-      }
-      double m = pr.scale_fnu * (double)cont;
-      if (nl > 0) {
-        const double lp = ob.lnpix[i];
-        // lines sorted by wavelength: window of ln(lambda_obs) within kLineCut * s_max
-        int l = lower_bound_dev(s_lnl, nl, lp - kLineCut * slmax);
-        double lines = 0.0;
-        for (; l < nl && s_lnl[l] <= lp + kLineCut * slmax; ++l) {
-          const double u = (lp - s_lnl[l]) / s_sl[l];
-          lines += s_amp[l] * exp(-0.5 * u * u);
+        double m = pr.scale_fnu * (double)cont;
+        if (nl > 0) {
+          const double lp = ob.lnpix[i];
+          while (lwin < nl && s_lnl[lwin] < lp - kLineCut * slmax) ++lwin;
+          double lines = 0.0;
+          for (int l = lwin; l < nl && s_lnl[l] <= lp + kLineCut * slmax; ++l) {
+            const double u = (lp - s_lnl[l]) / s_sl[l];
+            lines += s_amp[l] * (double)expf((float)(-0.5 * u * u));
+          }
+          m += lines * ob.pix[i] * kAng_cm / kC_cms;
         }
-        m += lines * ob.pix[i] * kAng_cm / kC_cms;
+        datum(i, m / kFnuAB);
       }
-      datum(i, m / kFnuAB);
+    } else {
+      for (int i = tid; i < ob.n_data; i += 256) {
+        const double x = ob.lnpix[i] - lnopz;
+        T cont = (T)0;
+        if (x >= lnw0 && x <= lnw1) {
+          const double s = ob.ksig[i];
+          const int k = lnwave_bracket(lib, x);
+          const double dk = lib.lnwave_d[k + 1] - lib.lnwave_d[k];
+          if (s < 0.5 * dk) {
+            const T t = (T)((x - lib.lnwave_d[k]) / dk);
+            const T fk = Fr[k] * (T)lib.lam2_d[k], fk1 = Fr[k + 1] * (T)lib.lam2_d[k + 1];
+            cont = fk + t * (fk1 - fk);
+          } else {
+            int j = lnwave_lower_bound(lib, x - 5.0 * s);
+            const double inv = 1.0 / s;
+            double num = 0.0, den = 0.0;
+            for (; j < N; ++j) {
+              const double u = (lib.lnwave_d[j] - x) * inv;
+              if (u > 5.0) break;
+              const T w = sizeof(T) == 8 ? (T)exp(-0.5 * u * u) : (T)expf((float)(-0.5 * u * u));
+              num += (double)(w * (Fr[j] * (T)lib.lam2_d[j]));
+              den += (double)w;
+            }
+            cont = (T)(num / den);
+          }
+        }
+        double m = pr.scale_fnu * (double)cont;
+        if (nl > 0) {
+          const double lp = ob.lnpix[i];
+          // lines sorted by wavelength: window of ln(lambda_obs) within kLineCut * s_max
+          int l = lower_bound_dev(s_lnl, nl, lp - kLineCut * slmax);
+          double lines = 0.0;
+          for (; l < nl && s_lnl[l] <= lp + kLineCut * slmax; ++l) {
+            const double u = (lp - s_lnl[l]) / s_sl[l];
+            lines += s_amp[l] * exp(-0.5 * u * u);
+          }
+          m += lines * ob.pix[i] * kAng_cm / kC_cms;
+        }
+        datum(i, m / kFnuAB);
+      }
     }
   }
   // fixed-order reduction of logL (and the noise-parameter gradients): wave sums,

@@ -109,6 +109,8 @@ sps_status upload_obs(const ObsHost &host, DevObs &o, DeviceBuffers &mem, hipStr
     o.has_curve = host.lsf_vals.empty() ? 0 : 1;
     if (o.has_curve) o.lsf_vals = (const double *)put(host.lsf_vals.data(), host.lsf_vals.size() * 8);
     o.sigma_gas_kms = host.sigma_gas;
+    o.ksig_max = 0.0;
+    for (double v : host.ksig) o.ksig_max = std::max(o.ksig_max, v);
   }
   o.data = (const double *)put(host.data.data(), (size_t)host.n_data * 8);
   o.sigma = (const double *)put(host.sigma.data(), (size_t)host.n_data * 8);
