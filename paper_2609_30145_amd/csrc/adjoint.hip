@@ -757,6 +757,7 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
       return fail(SPS_E_HIP, "hipFuncSetAttribute failed");
     attr1[f64 ? 1 : 0] = sm1;
   }
+  (void)hipGetLastError();   // drop a stale code from an unrelated earlier HIP call of this thread
   if (f64) hipLaunchKernelGGL(k_adj_proj<double>, dim3(B), dim3(256), sm1, s, g, aa);
   else hipLaunchKernelGGL(k_adj_proj<float>, dim3(B), dim3(256), sm1, s, g, aa);
   hipError_t e = hipGetLastError();

@@ -388,6 +388,7 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   pk.kexp = kexp;
   pk.Q = Q;
   pk.wave = g.wave_d;
+  (void)hipGetLastError();   // drop a stale code from an unrelated earlier HIP call of this thread
   hipError_t e = launch_pack(g, pk, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -565,6 +566,8 @@ sps_status set_obs_data(ObsHost &h, const double *data, const double *sigma, con
   h.data.assign(n, 0.0);
   h.sigma.assign(n, 1.0);
   h.mask.assign(n, 0);
+  h.ivar.assign(n, 0.0);
+  h.lnorm = 0.0;
   if (!data || !sigma) return SPS_OK;   // no data: logL over an empty mask is 0
   for (int i = 0; i < n; ++i) {
     const bool ok = std::isfinite(data[i]) && std::isfinite(sigma[i]) && sigma[i] > 0 && (!mask || mask[i]);
@@ -572,6 +575,8 @@ sps_status set_obs_data(ObsHost &h, const double *data, const double *sigma, con
     if (ok) {
       h.data[i] = data[i];
       h.sigma[i] = sigma[i];
+      h.ivar[i] = 1.0 / (sigma[i] * sigma[i]);
+      h.lnorm -= 0.5 * std::log(2.0 * M_PI * sigma[i] * sigma[i]);
     }
   }
   return SPS_OK;

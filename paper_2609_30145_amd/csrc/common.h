@@ -83,6 +83,8 @@ struct DevObs {
   double ksig_max;                   // largest continuum kernel dispersion (spectra)
   const double *data, *sigma;        // [n_data]
   const uint8_t *mask;               // [n_data] final inclusion mask
+  const double *ivar;                // [n_data] 1/sigma^2, 0 where masked
+  double lnorm;                      // -1/2 sum ln(2 pi sigma^2) over the included data
 };
 
 // Per-point quantities, stored at the point's sorted row.

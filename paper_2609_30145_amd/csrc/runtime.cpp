@@ -66,7 +66,7 @@ int64_t obs_device_bytes(const ObsHost &h) {
   } else {
     b += 3 * r256(h.pix.size() * 8) + (h.lsf_vals.empty() ? 0 : r256(h.lsf_vals.size() * 8));
   }
-  b += 2 * r256((size_t)h.n_data * 8) + r256((size_t)h.n_data);
+  b += 3 * r256((size_t)h.n_data * 8) + r256((size_t)h.n_data);
   return (int64_t)b;
 }
 
@@ -115,6 +115,8 @@ sps_status upload_obs(const ObsHost &host, DevObs &o, DeviceBuffers &mem, hipStr
   o.data = (const double *)put(host.data.data(), (size_t)host.n_data * 8);
   o.sigma = (const double *)put(host.sigma.data(), (size_t)host.n_data * 8);
   o.mask = (const uint8_t *)put(host.mask.data(), (size_t)host.n_data);
+  o.ivar = (const double *)put(host.ivar.data(), (size_t)host.n_data * 8);
+  o.lnorm = host.lnorm;
   if (!ok) return fail(SPS_E_NOMEM, "observation upload failed");
   return SPS_OK;
 }
@@ -137,6 +139,9 @@ sps_status sps_obs::upload_data() {
   hipError_t e = hipMemcpy((void *)dobs.data, host.data.data(), n * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy((void *)dobs.sigma, host.sigma.data(), n * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy((void *)dobs.mask, host.mask.data(), n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy((void *)dobs.ivar, host.ivar.data(), n * 8, hipMemcpyHostToDevice);
+  dobs.lnorm = host.lnorm;
+  if (e == hipSuccess) e = hipMemcpy(dev_obs, &dobs, sizeof(DevObs), hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(SPS_E_HIP, "observation data upload failed: %s", hipGetErrorString(e));
   return SPS_OK;
 }

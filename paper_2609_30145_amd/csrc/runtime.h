@@ -55,6 +55,10 @@ struct ObsHost {
   double lsf_value = 0, sigma_gas = 0;
   std::vector<double> data, sigma;
   std::vector<uint8_t> mask;
+  // constant-noise form of the likelihood: 1/sigma^2 (0 where masked) and
+  // -1/2 sum ln(2 pi sigma^2) over the included data
+  std::vector<double> ivar;
+  double lnorm = 0;
 };
 
 sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsHost &h, uint32_t *warnings);

@@ -181,6 +181,7 @@ bool sps_server::tick() {
     return true;
   }
   std::copy(reqs.begin(), reqs.end(), h_reqs);
+  (void)hipGetLastError();   // drop a stale code from an unrelated earlier HIP call of this thread
   hipError_t e = hipMemcpyAsync(d_reqs, h_reqs, sizeof(DevReq) * n, hipMemcpyHostToDevice, s_compute);
   if (e == hipSuccess) e = launch_propose(d_reqs, n, P, n_sfh, box, d_theta_all, d_point_obs, total, s_compute);
   if (e != hipSuccess) return false;
