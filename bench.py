@@ -24,12 +24,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0, "bf16_hr": 2500.0,
-               "fp16_hr": 2500.0, "bf16_1pass": 2500.0, "fp16_1pass": 2500.0}
+               "fp16_hr": 2500.0, "bf16_1pass": 2500.0, "fp16_1pass": 2500.0, "bf16_wl": 2500.0,
+               "fp16_wl": 2500.0}
 MFMA_PASSES = {"fp32": 1, "fp64": 1, "bf16": 3, "fp16": 3, "bf16_hr": 2, "fp16_hr": 2, "bf16_1pass": 1,
-               "fp16_1pass": 1}
+               "fp16_1pass": 1, "bf16_wl": 2, "fp16_wl": 2}
 DTYPE = {"fp32": "f32", "fp64": "f64", "bf16": "bf16 (f32 accumulate, residual pass)",
          "fp16": "f16 (f32 accumulate, residual pass)", "bf16_hr": "bf16", "fp16_hr": "f16",
-         "bf16_1pass": "bf16", "fp16_1pass": "f16"}
+         "bf16_1pass": "bf16", "fp16_1pass": "f16", "bf16_wl": "bf16 (f32 accumulate, weight residual pass)",
+         "fp16_wl": "f16 (f32 accumulate, weight residual pass)"}
 
 
 def traffic_record(precision):
@@ -341,8 +343,10 @@ def alg_bytes(cfg, B, precision):
     the FP32/FP64 copy), the weight rows and the rest-frame output."""
     K = cfg.n_age * len(cfg.logz) * len(cfg.afe) + cfg.n_lines
     N = cfg.n_wave
-    lib = {"fp64": 8, "fp32": 4}.get(precision, 4 if precision.endswith(("16", "_hr")) else 2)
-    w = {"fp64": 8, "fp32": 4}.get(precision, 2 if precision.endswith("1pass") or precision.endswith("_hr") else 4)
+    suffix = precision.split("_")[1] if "_" in precision else ""
+    # bytes per library element and per weight: both 16-bit planes where a pass reads them
+    lib = {"fp64": 8, "fp32": 4}.get(precision, 4 if suffix in ("", "hr") else 2)
+    w = {"fp64": 8, "fp32": 4}.get(precision, 4 if suffix in ("", "wl") else 2)
     out = 8 if precision == "fp64" else 4
     return int(K * N * lib + B * K * w + B * N * out)
 

@@ -58,7 +58,8 @@ enum {
  *     and 16-bit residual R, weights as 2^e (W_h + W_l) per point; MFMA passes
  *     W_h.H + W_h.R + W_l.H accumulated in FP32 (one refinement pass over the
  *     residual terms).
- *   *_1PASS    : W_h.H only.   *_HR : W_h.H + W_h.R only. */
+ *   *_1PASS    : W_h.H only.   *_HR : W_h.H + W_h.R only.
+ *   *_WL       : W_h.H + W_l.H (the library residual dropped: two passes). */
 typedef enum {
   SPS_FP64 = 0,
   SPS_FP32 = 1,
@@ -67,7 +68,9 @@ typedef enum {
   SPS_BF16_1PASS = 4,
   SPS_FP16_1PASS = 5,
   SPS_BF16_HR = 6,
-  SPS_FP16_HR = 7
+  SPS_FP16_HR = 7,
+  SPS_BF16_WL = 8,
+  SPS_FP16_WL = 9
 } sps_precision;
 
 typedef struct sps_library sps_library;

@@ -352,17 +352,19 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   pk.LT32 = (float *)al(KN * 4);
   pk.L32n = (float *)al(KN * 4);
   if (L->precisions & (1u << SPS_FP64)) pk.LT64 = (double *)al(KN * 8);
-  const bool want_bf = L->precisions & ((1u << SPS_BF16) | (1u << SPS_BF16_1PASS) | (1u << SPS_BF16_HR));
-  const bool want_h = L->precisions & ((1u << SPS_FP16) | (1u << SPS_FP16_1PASS) | (1u << SPS_FP16_HR));
+  const uint32_t bf_set = (1u << SPS_BF16) | (1u << SPS_BF16_1PASS) | (1u << SPS_BF16_HR) | (1u << SPS_BF16_WL);
+  const uint32_t h_set = (1u << SPS_FP16) | (1u << SPS_FP16_1PASS) | (1u << SPS_FP16_HR) | (1u << SPS_FP16_WL);
+  const bool want_bf = L->precisions & bf_set;
+  const bool want_h = L->precisions & h_set;
   if (want_bf) {
     pk.Hb = (uint16_t *)al(KN * 2);
     pk.Rb = (uint16_t *)al(KN * 2);
-    L->precisions |= (1u << SPS_BF16) | (1u << SPS_BF16_1PASS) | (1u << SPS_BF16_HR);
+    L->precisions |= bf_set;
   }
   if (want_h) {
     pk.Hh = (uint16_t *)al(KN * 2);
     pk.Rh = (uint16_t *)al(KN * 2);
-    L->precisions |= (1u << SPS_FP16) | (1u << SPS_FP16_1PASS) | (1u << SPS_FP16_HR);
+    L->precisions |= h_set;
   }
   if (!ok) {
     delete L;
@@ -625,7 +627,7 @@ extern "C" void sps_obs_destroy(sps_obs *o) {
 // =====================================================================================
 namespace sps {
 
-bool precision_built(const sps_library *L, int p) { return p >= 0 && p <= 7 && (L->precisions >> p) & 1u; }
+bool precision_built(const sps_library *L, int p) { return p >= 0 && p <= 9 && (L->precisions >> p) & 1u; }
 
 sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_table, const int *point_obs,
                           const double *theta, int B, int prec, double *logl, double *model, int ld_model,
@@ -637,16 +639,14 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   // the thread's HIP last-error slot may hold a stale code set by another library's
   // call; clear it so that only this call's own launches are checked below
   (void)hipGetLastError();
-  const int mode = prec == 0 ? 0 : prec == 1 ? 1 : (prec == 2 || prec == 4 || prec == 6) ? 2 : 3;
+  const int mode = prec == 0 ? 0 : prec == 1 ? 1 : (prec == 2 || prec == 4 || prec == 6 || prec == 8) ? 2 : 3;
   const int MT = contract_mtile(prec);
   const int tf = contract_ktile_factor(prec);
-  hipError_t e = launch_keys(g, theta, g.P, B, w.keys, s);
   PrepLaunch pl;
   pl.theta = theta;
   pl.P = g.P;
   pl.B = B;
   pl.B_pad = B_pad;
-  pl.keys = w.keys;
   pl.obs_table = obs_table;
   pl.point_obs = point_obs;
   pl.W = w.W;
@@ -658,7 +658,7 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   pl.kpos = L->kpos_d;
   pl.line_k0 = L->line_k0;
   pl.mode = mode;
-  if (e == hipSuccess) e = launch_prep(g, pl, s);
+  hipError_t e = launch_prep(g, pl, s);
   ContractLaunch cl;
   cl.W = pl.W;
   cl.Wlo = pl.Wlo;

@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
   f32x4 ra[A4], rb[B4];
 #define SPS_GLOAD32(t_)                                                              \
   {                                                                                  \
-    const int k0_ = tl[t_] * KT;                                                     \
+    const int k0_ = tl[min(t_, nact - 1)] * KT;                                      \
     _Pragma("unroll") for (int q = 0; q < A4; ++q) {                                 \
       const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;                   \
       ra[q] = *(const f32x4 *)(W + (size_t)(m0 + row) * K_pad + k0_ + c4 * 4);      \
@@ -172,7 +172,8 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
       *(f32x4 *)(Bs + row * LDSK + c4 * 4) = rb[q];
     }
     __syncthreads();
-    if (t + 1 < nact) SPS_GLOAD32(t + 1);
+    SPS_GLOAD32(t + 1);   // unconditional (past the list: the last tile again, unused), so
+                          // the memory-counter waits cover only the tile being stored
     if (t == ny) {
       if constexpr (PRECISE) {
         bc32p<BM, BN, WTM, WTN>(dacc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);

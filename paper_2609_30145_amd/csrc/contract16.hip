@@ -3,7 +3,8 @@
 // as 2^{e_b} 2^{-e_k} (W_h + W_l), both 16-bit hi + residual pairs (the weight planes
 // in the fragment-tiled layout written by the weight builder).  The products
 // W_h H (main pass), W_h R and W_l H (one refinement pass over the residual terms)
-// accumulate into one FP32 accumulator; the dropped W_l R term is second order.
+// accumulate into one FP32 accumulator; the dropped W_l R term is second order.  The
+// reduced variants take W_h H alone, W_h H + W_h R, or W_h H + W_l H.
 #include "common.h"
 #include "kernels.h"
 
@@ -47,7 +48,7 @@ __device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[6], 
     }
 }
 
-// PASSES: 1 = W_h H; 2 = W_h H + W_h R; 3 = W_h H + W_h R + W_l H.
+// PASSES: 1 = W_h H; 2 = W_h H + W_h R; 3 = W_h H + W_h R + W_l H; 4 = W_h H + W_l H.
 // Block tile 128 (points) x 64 (wavelengths), K tile 64; four waves stacked along M,
 // each 32 x 64 (two 32x32x16 MFMA accumulators).  Each wave reads its own weight
 // fragments straight from global memory into registers (the weight planes are stored
@@ -60,7 +61,7 @@ __device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[6], 
 template <bool BF, int PASSES>
 __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
   constexpr int MT = 128, NT = 64, KT = 64, NCH = KT / 8, WTM = 32, BM = 1, BN = 2;
-  constexpr bool USE_WL = PASSES >= 3, USE_R = PASSES >= 2;
+  constexpr bool USE_WL = PASSES >= 3, USE_R = PASSES == 2 || PASSES == 3;
   constexpr int B8 = NT * KT / 8 / 256;   // 16-byte library chunks per thread and K tile
   __shared__ __attribute__((aligned(16))) uint16_t Bh[2][NT * KT];
   __shared__ __attribute__((aligned(16))) uint16_t Br[2][USE_R ? NT * KT : 8];
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
   u32x4 ah0[4], al0[USE_WL ? 4 : 1], ah1[4], al1[USE_WL ? 4 : 1], rbh[B8], rbr[USE_R ? B8 : 1];
 #define SPS_LOADA(t_, H_, L_)                                                      \
   {                                                                                \
-    const size_t o_ = wbase + (size_t)tl[t_] * (KT * 32);                          \
+    const size_t o_ = wbase + (size_t)tl[min(t_, nact - 1)] * (KT * 32);           \
     _Pragma("unroll") for (int s = 0; s < 4; ++s) {                                \
       H_[s] = *(const u32x4 *)(a.Wh + o_ + s * 256);                               \
       if constexpr (USE_WL) L_[s] = *(const u32x4 *)(a.Wl + o_ + s * 256);         \
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
   }
 #define SPS_LOADB(t_)                                                              \
   {                                                                                \
-    const int k0_ = tl[t_] * KT;                                                   \
+    const int k0_ = tl[min(t_, nact - 1)] * KT;                                    \
     _Pragma("unroll") for (int q = 0; q < B8; ++q) {                               \
       rbh[q] = *(const u32x4 *)(a.H + (offB[q] + k0_));                            \
       if constexpr (USE_R) rbr[q] = *(const u32x4 *)(a.R + (offB[q] + k0_));       \
@@ -162,25 +163,28 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
     SPS_LOADB(0);
     SPS_LOADA(0, ah0, al0);
     SPS_STOREB(0);
-    if (nact > 1) SPS_LOADB(1);
+    SPS_LOADB(1);
   }
   __syncthreads();
   // two K tiles per trip, so the two weight register sets and LDS buffers alternate
   // without copies; LDS buffer b is rewritten only after the barrier that follows its
-  // last read
+  // last read.  Every prefetch is issued unconditionally (tile indices past the list
+  // repeat its last tile and are never multiplied): with no loads under a branch the
+  // waits on the memory counter cover exactly the tile about to be used, and the
+  // prefetched tiles stay in flight across the multiply.
   for (int t = 0; t < nact; t += 2) {
-    if (t + 1 < nact) SPS_LOADA(t + 1, ah1, al1);
+    SPS_LOADA(t + 1, ah1, al1);
     if (t == ny) bc16<BM, BN, WTM>(acc, sp, c_lnlv, wm, lh);
     SPS_MMA(0, ah0, al0);
-    if (t + 1 < nact) SPS_STOREB(1);
-    if (t + 2 < nact) SPS_LOADB(t + 2);
+    SPS_STOREB(1);
+    SPS_LOADB(t + 2);
     __syncthreads();
     if (t + 1 >= nact) break;
-    if (t + 2 < nact) SPS_LOADA(t + 2, ah0, al0);
+    SPS_LOADA(t + 2, ah0, al0);
     if (t + 1 == ny) bc16<BM, BN, WTM>(acc, sp, c_lnlv, wm, lh);
     SPS_MMA(1, ah1, al1);
-    if (t + 2 < nact) SPS_STOREB(0);
-    if (t + 3 < nact) SPS_LOADB(t + 3);
+    SPS_STOREB(0);
+    SPS_LOADB(t + 3);
     __syncthreads();
   }
 #undef SPS_LOADA
@@ -210,7 +214,7 @@ static void launch16(const ContractArgs16 &a, int n_mt, int N_pad, hipStream_t s
 hipError_t launch_contract16_impl(const DevLib &lib, const ContractLaunch &cl, int n_mt, hipStream_t s) {
   ContractArgs16 a;
   const int precision = cl.precision;
-  const bool bf = precision == 2 || precision == 4 || precision == 6;
+  const bool bf = precision == 2 || precision == 4 || precision == 6 || precision == 8;
   a.Wh = (const uint16_t *)cl.W;
   a.Wl = (const uint16_t *)cl.Wlo;
   a.H = bf ? lib.Hb : lib.Hh;
@@ -237,6 +241,8 @@ hipError_t launch_contract16_impl(const DevLib &lib, const ContractLaunch &cl, i
     case 5: launch16<false, 1>(a, n_mt, lib.N_pad, s); break;
     case 6: launch16<true, 2>(a, n_mt, lib.N_pad, s); break;
     case 7: launch16<false, 2>(a, n_mt, lib.N_pad, s); break;
+    case 8: launch16<true, 4>(a, n_mt, lib.N_pad, s); break;
+    case 9: launch16<false, 4>(a, n_mt, lib.N_pad, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

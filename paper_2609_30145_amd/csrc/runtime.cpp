@@ -23,13 +23,8 @@ sps_status Workspace::create(const sps_library *L, int mb, int n_data, int n_fno
     ok = ok && p;
     return p;
   };
-  keys = (double *)al(Bp * 8);
   W = al(Bp * g.K_pad * 8);
   rowmask = (uint32_t *)al(Bp * mask_words * 4);
-  const size_t n_mt = Bp / 64, n_kt = g.K_pad / kKTile;
-  tiles = (int *)al(n_mt * n_kt * 4);
-  n_young = (int *)al(n_mt * 4);
-  n_act = (int *)al(n_mt * 4);
   rows = (PointRow *)al(Bp * sizeof(PointRow));
   F = al(Bp * g.N_pad * 8);
   const size_t gb = forward_only ? 1 : Bp;   // gradient-pass buffers

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsps.so")
 
 SPS_OK, SPS_PENDING = 0, 1
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16_1pass": 4, "fp16_1pass": 5,
-              "bf16_hr": 6, "fp16_hr": 7}
+              "bf16_hr": 6, "fp16_hr": 7, "bf16_wl": 8, "fp16_wl": 9}
 LSF_MODES = {"R_fwhm": 0, "R_sigma": 1, "fwhm_aa": 2, "sigma_aa": 3, "sigma_kms": 4, "fwhm_kms": 5, "R": 6}
 NOISE = {"err_scale": 1, "f_calib": 2, "f_data": 4, "jitter": 8}
 OBS_PHOT, OBS_SPEC = 0, 1

@@ -65,7 +65,7 @@ def test_c0_fp32_matches_oracle_to_1e5(c0):
     assert e.max() < 1e-5
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16_hr", "fp16_hr"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "bf16_hr", "fp16_hr", "bf16_wl", "fp16_wl"])
 def test_c0_low_precision_within_2e3(c0, prec):
     case, L, O, ll_ref, m_ref = c0
     say(f"c0 {prec} B=64")

@@ -27,7 +27,7 @@ if not torch.cuda.is_available():
 import paper_2609_30145_amd as sps  # noqa: E402
 
 N_LAUNCH = 10
-VARIANTS = ["fp32", "fp16", "bf16", "fp16_hr", "bf16_hr", "fp16_1pass", "bf16_1pass"]
+VARIANTS = ["fp32", "fp16", "bf16", "fp16_wl", "bf16_wl", "fp16_hr", "bf16_hr", "fp16_1pass", "bf16_1pass"]
 
 
 def say(m):
