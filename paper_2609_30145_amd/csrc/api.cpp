@@ -642,11 +642,13 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   const int mode = prec == 0 ? 0 : prec == 1 ? 1 : (prec == 2 || prec == 4 || prec == 6 || prec == 8) ? 2 : 3;
   const int MT = contract_mtile(prec);
   const int tf = contract_ktile_factor(prec);
+  hipError_t e = launch_keys(g, theta, g.P, B, w.keys, s);
   PrepLaunch pl;
   pl.theta = theta;
   pl.P = g.P;
   pl.B = B;
   pl.B_pad = B_pad;
+  pl.keys = w.keys;
   pl.obs_table = obs_table;
   pl.point_obs = point_obs;
   pl.W = w.W;
@@ -658,7 +660,7 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   pl.kpos = L->kpos_d;
   pl.line_k0 = L->line_k0;
   pl.mode = mode;
-  hipError_t e = launch_prep(g, pl, s);
+  if (e == hipSuccess) e = launch_prep(g, pl, s);
   ContractLaunch cl;
   cl.W = pl.W;
   cl.Wlo = pl.Wlo;

@@ -7,6 +7,7 @@ namespace sps {
 struct PrepLaunch {
   const double *theta;
   int P, B, B_pad;
+  const double *keys;        // batch-ordering keys from launch_keys
   const DevObs *obs_table;
   const int *point_obs;
   void *W, *Wlo;
@@ -21,6 +22,7 @@ struct PrepLaunch {
 
 size_t prep_smem_bytes(const DevLib &lib, int mode);   // mode as PrepLaunch::mode
 // batch-ordering keys (the weight builder ranks the points by them)
+hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, hipStream_t s);
 // weights, per-row K-tile occupancy bits and per-point rows, each point at its rank
 hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s);
 

@@ -14,22 +14,23 @@ namespace sps {
 // K tiles of the weight matrix are zero for an M tile and can be skipped.
 // ---------------------------------------------------------------------------------
 // The key of a row: its redshift (time-varying enrichment), else the metallicity and
-// alpha brackets, then the redshift.  Bracket indices by a forward scan of the nodes
-// (held in LDS), the same index as the clamped bisection elsewhere.
-__device__ __forceinline__ int scan_bracket(const double *nodes, int n, double x) {
-  const double xc = fmin(fmax(x, nodes[0]), nodes[n - 1]);
-  int j = 0;
-  while (j + 1 < n - 1 && nodes[j + 1] <= xc) ++j;
-  return j;
+// alpha brackets, then the redshift.
+__device__ double sort_key(const DevLib &lib, const double *th) {
+  double z = th[TH_ZRED];
+  if (lib.n_zh > 0) return z;
+  int jz = 0;
+  double t;
+  bool in;
+  if (lib.n_z > 1) grid_split_dev(lib.logz, lib.n_z, th[TH_LOGZSOL], jz, t, in);
+  int ja = 0;
+  if (lib.n_afe > 1) grid_split_dev(lib.afe, lib.n_afe, th[TH_AFE], ja, t, in);
+  return (double)jz * 1.0e6 + (double)ja * 1.0e4 + fmin(fmax(z, 0.0), 9.0e3);
 }
 
-__device__ __forceinline__ double sort_key(const DevLib &lib, const double *th, const double *s_logz,
-                                           const double *s_afe) {
-  const double z = th[TH_ZRED];
-  if (lib.n_zh > 0) return z;
-  const int jz = lib.n_z > 1 ? scan_bracket(s_logz, lib.n_z, th[TH_LOGZSOL]) : 0;
-  const int ja = lib.n_afe > 1 ? scan_bracket(s_afe, lib.n_afe, th[TH_AFE]) : 0;
-  return (double)jz * 1.0e6 + (double)ja * 1.0e4 + fmin(fmax(z, 0.0), 9.0e3);
+__global__ void __launch_bounds__(256) k_keys(DevLib lib, const double *__restrict__ theta, int P, int B,
+                                              double *__restrict__ keys) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b < B) keys[b] = sort_key(lib, theta + (size_t)b * P);
 }
 
 // ---------------------------------------------------------------------------------
@@ -91,6 +92,7 @@ enum WMode { W_F64 = 0, W_F32 = 1, W_BF16 = 2, W_F16 = 3 };
 struct PrepArgs {
   const double *theta;
   int P, B, B_pad;
+  const double *keys;       // [B] batch-ordering keys (k_keys)
   const DevObs *obs_table;
   const int *point_obs;     // [B] observation slot per point, NULL = slot 0
   void *W;                  // F64/F32: [B_pad][K_pad]; 16-bit: hi plane
@@ -185,21 +187,14 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   int r = blockIdx.x;
   if (b >= 0) {
     __shared__ int s_rank[4];
-    if (lib.n_zh == 0) {   // the keys hold metallicity and alpha brackets
-      for (int m = tid; m < nz; m += 256) s_logz[m] = lib.logz[m];
-      for (int m = tid; m < nf; m += 256) s_afe[m] = nf > 1 ? lib.afe[m] : 0.0;
-      __syncthreads();
-    }
-    // every workgroup computes the keys of the whole batch itself (a few strided reads
-    // of theta per thread), so no separate key pass precedes this kernel
-    const double my = sort_key(lib, a.theta + (size_t)b * a.P, s_logz, s_afe);
+    const double my = a.keys[b];
     int c = 0;
-    for (int j0 = tid; j0 < a.B; j0 += 256 * 4) {
+    for (int j0 = tid; j0 < a.B; j0 += 256 * 4) {   // four key loads per thread in flight
       double kq[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = j0 + 256 * u;
-        kq[u] = j < a.B ? sort_key(lib, a.theta + (size_t)j * a.P, s_logz, s_afe) : 0.0;
+        kq[u] = j < a.B ? a.keys[j] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -512,9 +507,15 @@ size_t prep_smem_bytes(const DevLib &lib, int mode) {
   return sizeof(double) * (size_t)PrepSmem(lib, mode == W_F64).total;
 }
 
+hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, hipStream_t s) {
+  hipLaunchKernelGGL(k_keys, dim3((B + 255) / 256), dim3(256), 0, s, lib, theta, P, B, keys);
+  return hipGetLastError();
+}
+
 hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s) {
   PrepArgs a;
   a.theta = pl.theta;
+  a.keys = pl.keys;
   a.P = pl.P;
   a.B = pl.B;
   a.B_pad = pl.B_pad;

@@ -23,6 +23,7 @@ sps_status Workspace::create(const sps_library *L, int mb, int n_data, int n_fno
     ok = ok && p;
     return p;
   };
+  keys = (double *)al(Bp * 8);
   W = al(Bp * g.K_pad * 8);
   rowmask = (uint32_t *)al(Bp * mask_words * 4);
   rows = (PointRow *)al(Bp * sizeof(PointRow));

@@ -26,6 +26,7 @@ struct DeviceBuffers {
 struct Workspace {
   DeviceBuffers mem;
   int max_batch = 0, B_pad_max = 0, mask_words = 0;
+  double *keys = nullptr;       // batch-ordering keys [B_pad]
   void *W = nullptr;             // B_pad * K_pad * 8 bytes
   uint32_t *rowmask = nullptr;
   PointRow *rows = nullptr;
