@@ -17,6 +17,10 @@ namespace sps {
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// nodes of the rows' span owned by one thread in the FP32 spectral transpose (the span is
+// at most 256 * kAdjOwn nodes)
+constexpr int kAdjOwn = 16;
+
 // slots of the per-point adjoint scratch gbuf[r][16]
 enum { GB_Z = 0, GB_TAU_BC, GB_ALPHA_BC, GB_TAU_DIFF, GB_DELTA, GB_LOGMASS, GB_N };
 
@@ -34,6 +38,11 @@ struct AdjArgs {
   void *GY, *GO;                // [B_pad][N_pad]
   double *gbuf;                 // [B_pad][16]
   double *dLl;                  // [B_pad][n_line]
+  int fast;                     // FP32 path: per-node / per-pixel tables fit in LDS after gF
+  int g_bytes;                  // bytes of the first dynamic LDS region (gF, or the span of rows)
+  int nl_lds;                   // line slots of the line tables in LDS (spectra)
+  int seg_cap;                  // FP32 spectra: bound on the rows' span in nodes
+  double inv_pix_step;          // spectra: 1 / smallest ln-wavelength step between pixels
 };
 
 __device__ __forceinline__ double block_sum256(double v, double *red) {
@@ -78,9 +87,15 @@ __device__ double sigma_inst_at(const DevObs &ob, double lam, double *dsig_dlam)
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
-  extern __shared__ double gFl[];     // [N] d logL / d F on the rest grid
+  // dynamic LDS: [d logL / d F on the rest grid, N doubles (FP32 spectra: the span of the
+  // rows in FP32, first f = F lambda^2, then d logL / d F)] [line tables, 5 x nl_lds
+  // doubles] [FP32 path: per-node or per-pixel tables of the transpose]
+  extern __shared__ __attribute__((aligned(16))) unsigned char adj_dyn[];
+  double *gFl = (double *)adj_dyn;
+  double *s_lnl = (double *)(adj_dyn + a.g_bytes), *s_sl = s_lnl + a.nl_lds, *s_dsl = s_sl + a.nl_lds;
+  double *s_F = s_dsl + a.nl_lds, *s_T = s_F + a.nl_lds;
+  unsigned char *xsm = (unsigned char *)(s_T + a.nl_lds);
   __shared__ double red[256];
-  __shared__ double s_lnl[512], s_sl[512], s_dsl[512], s_F[512], s_T[512];
   const int r = blockIdx.x, tid = threadIdx.x;
   const PointRow pr = a.rows[r];
   if (pr.b < 0) return;
@@ -96,11 +111,77 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
   const double ddl = pr.dc + opz * (kC_kms / lib.H0) * kMpc_cm / Ez;   // dD_L/dz [cm]
   const int chunk = (N + 255) / 256;
   const int n0 = min(tid * chunk, N), n1 = min(n0 + chunk, N);
-  for (int n = n0; n < n1; ++n) gFl[n] = 0.0;
+  const bool fast_spec = sizeof(T) == 4 && a.fast && ob.kind != 0;
+  if (!fast_spec)
+    for (int n = n0; n < n1; ++n) gFl[n] = 0.0;
+  int fs_seg0 = 0, fs_segn = 0;   // FP32 spectra: span of the rows, d logL / d F held there
   double gz = 0.0, glm = 0.0, gtb = 0.0, gab = 0.0, gtd = 0.0, gdl = 0.0;
   for (int i = tid; i < ob.n_data; i += 256) glm += gm[i] * mm[i];
 
-  if (ob.kind == 0) {
+  if (ob.kind == 0 && sizeof(T) == 4 && a.fast) {
+    // ---------------- photometry, FP32 path: one thread per filter node over all bands
+    // (the band from the offsets held in LDS), the node's interval found as in the
+    // forward pass; per-node interval and weights kept in LDS for the transpose
+    const double A = kC_cms * pr.scale_fnu / (opz * opz * kAng_cm * kAng_cm);
+    const double dlnA = -1.0 / opz - 2.0 * ddl / pr.dl;
+    const double lnopz = log1p(z);
+    const double wlo = lib.wave_d[0], whi = lib.wave_d[N - 1];
+    const int nfn = ob.n_fnodes, nb = ob.n_band;
+    int *s_bo = (int *)xsm;
+    float *s_c0 = (float *)(s_bo + nb + 1), *s_c1 = s_c0 + nfn;
+    short *s_nk = (short *)(s_c1 + nfn);
+    for (int b = tid; b <= nb; b += 256) s_bo[b] = ob.band_off[b];
+    for (int b = tid; b < nb; b += 256) gz += gm[b] * dlnA * mm[b];
+    __syncthreads();
+#pragma unroll 4
+    for (int j = tid; j < nfn; j += 256) {
+      int lo = 0, hi = nb - 1;   // band of node j: the last b with band_off[b] <= j
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_bo[mid] <= j) lo = mid; else hi = mid - 1;
+      }
+      const double lr = ob.fw[j] / opz;
+      const double coef = gm[lo] * A * ob.fr_d[j];
+      int kk;
+      float c0 = 0.f, c1 = 0.f;
+      // as the forward pass of the gradient pass (linear in lambda, the interval from the
+      // node's log index on a log-uniform grid)
+      if (lr < wlo) {
+        kk = -2;
+      } else if (lr > whi) {
+        kk = N + 1;
+      } else {
+        const int k = min(max((int)floor((ob.fwln[j] - lnopz - lib.lnw0) * lib.inv_dlnw), 0), N - 2);
+        const double w0 = lib.wave_d[k], dw = lib.wave_d[k + 1] - w0;
+        const double t = (lr - w0) / dw;
+        gz += coef * (((double)Fr[k + 1] - (double)Fr[k]) / dw) * (-ob.fw[j] / (opz * opz));
+        kk = k;
+        c0 = (float)(coef * (1.0 - t));
+        c1 = (float)(coef * t);
+      }
+      s_nk[j] = (short)kk;
+      s_c0[j] = c0;
+      s_c1[j] = c1;
+    }
+    __syncthreads();
+    // gather: each thread owns model pixels [n0, n1); bands and nodes in a fixed order
+    if (n0 < n1) {
+      for (int b = 0; b < nb; ++b) {
+        const int j0 = s_bo[b], j1 = s_bo[b + 1];
+        int lo = j0, hi = j1;   // first node with k >= n0 - 1 (k is non-decreasing in a band)
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (s_nk[mid] < n0 - 1) lo = mid + 1; else hi = mid;
+        }
+        for (int j = lo; j < j1; ++j) {
+          const int k = s_nk[j];
+          if (k >= n1) break;
+          if (k >= n0 && k < n1) gFl[k] += s_c0[j];
+          if (k + 1 >= n0 && k + 1 < n1) gFl[k + 1] += s_c1[j];
+        }
+      }
+    }
+  } else if (ob.kind == 0) {
     // ---------------- photometry: m_b = A sum_j c_j interp(F)(lambda_j / (1+z))
     const double A = kC_cms * pr.scale_fnu / (opz * opz * kAng_cm * kAng_cm);
     const double dlnA = -1.0 / opz - 2.0 * ddl / pr.dl;
@@ -142,6 +223,229 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
           const double t = scr[3 * j + 1], coef = scr[3 * j + 2];
           if (k >= n0 && k < n1) gFl[k] += coef * (1.0 - t);
           if (k + 1 >= n0 && k + 1 < n1) gFl[k + 1] += coef * t;
+        }
+      }
+    }
+  } else if (fast_spec) {
+    // ---------------- spectrum, FP32 path on a log-uniform rest grid: f = F lambda^2 over
+    // the span of the rows staged in LDS; per pixel, the row's Gaussian weights by the
+    // recurrence of the forward pass (w_{j+1} = w_j q_j, q_{j+1} = q_j e^{-h^2}); the
+    // transpose gathers, for each owned node, the rows that cover it in pixel order
+    const double S = pr.scale_fnu;
+    const double dlnS = 1.0 / opz - 2.0 * ddl / pr.dl;
+    const double lnopz = log1p(z);
+    const int np = ob.n_data;
+    const double lnw0 = lib.lnwave_d[0], lnw1 = lib.lnwave_d[N - 1];
+    const double dln = 1.0 / lib.inv_dlnw;
+    short *s_j0 = (short *)xsm, *s_j1 = s_j0 + np;
+    float *s_cf = (float *)(xsm + ((4 * (size_t)np + 15) & ~(size_t)15));
+    float *s_a0 = s_cf + np, *s_h = s_a0 + np;
+    int *s_first = (int *)(s_h + np), *s_last = s_first + 256;
+    const double ext = 5.0 * ob.ksig_max * lib.inv_dlnw + 2.0;
+    const double ua = (ob.lnpix[0] - lnopz - lnw0) * lib.inv_dlnw - ext;
+    const double ub = (ob.lnpix[np - 1] - lnopz - lnw0) * lib.inv_dlnw + ext;
+    const int seg0 = (int)fmin(fmax(floor(ua), 0.0), (double)(N - 1));
+    const int seg_n = min((int)fmin(fmax(ceil(ub), 0.0), (double)(N - 1)) + 1 - seg0, a.seg_cap);
+    fs_seg0 = seg0;
+    fs_segn = seg_n;
+    float *seg = (float *)gFl;
+    for (int k0 = tid; k0 < seg_n; k0 += 256 * 8) {   // eight loads per thread in flight
+      float v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = k0 + 256 * q;
+        v[q] = k < seg_n ? (float)Fr[seg0 + k] * (float)lib.lam2_d[seg0 + k] : 0.f;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (k0 + 256 * q < seg_n) seg[k0 + 256 * q] = v[q];
+    }
+    s_first[tid] = INT_MAX;
+    s_last[tid] = -1;
+    __syncthreads();
+    const int chunk_s = (seg_n + 255) / 256;   // nodes per owner in the transpose
+    for (int i = tid; i < np; i += 256) {
+      const double gc = gm[i] / kFnuAB;
+      const double x = ob.lnpix[i] - lnopz;
+      int j0 = 1, j1 = 0;   // empty row
+      float cf = 0.f, a0 = 0.f, hh = 0.f;
+      if (x >= lnw0 && x <= lnw1) {
+        // the forward pass's row on the log-uniform grid: position ux in node units,
+        // width rs; nodes j0..j1 within five widths, or two nodes when the row is
+        // narrower than half a node spacing
+        const double s = ob.ksig[i];
+        const double ux = (x - lnw0) * lib.inv_dlnw;
+        if (s < 0.5 * dln) {   // linear row on nodes k, k+1 (marked by h = 0, t kept in a0)
+          const int k = min((int)floor(ux), N - 2);
+          const float t = (float)(ux - (double)k);
+          const double fk = seg[k - seg0], fk1 = seg[k + 1 - seg0];
+          const double cont = fk + (double)t * (fk1 - fk);
+          gz += gc * (dlnS * S * cont + S * (fk1 - fk) * (-lib.inv_dlnw / opz));
+          j0 = k;
+          j1 = k + 1;
+          cf = (float)(gc * S);
+          a0 = t;
+        } else {
+          const double rs = s * lib.inv_dlnw;
+          j0 = max((int)ceil(ux - 5.0 * rs), 0);
+          j1 = min((int)floor(ux + 5.0 * rs), N - 1);
+          const float hf = 1.f / (float)rs, u0 = (float)((double)j0 - ux) * hf;
+          float w = expf(-0.5f * u0 * u0), q = expf(-u0 * hf - 0.5f * hf * hf);
+          const float c = expf(-hf * hf);
+          float G = 0.f, num = 0.f, sug = 0.f, sugf = 0.f;
+          const float *gp = seg + (j0 - seg0);
+          const int nt = j1 - j0 + 1;
+          int jj = 0;
+          for (; jj + 8 <= nt; jj += 8) {   // eight taps per step: LDS reads ahead of the recurrence
+            float g8[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) g8[e] = gp[jj + e];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const float uw = fmaf((float)(jj + e), hf, u0) * w;
+              G += w;
+              num += w * g8[e];
+              sug += uw;
+              sugf += uw * g8[e];
+              w *= q;
+              q *= c;
+            }
+          }
+          for (; jj < nt; ++jj) {
+            const float fj = gp[jj];
+            const float uw = fmaf((float)jj, hf, u0) * w;
+            G += w;
+            num += w * fj;
+            sug += uw;
+            sugf += uw * fj;
+            w *= q;
+            q *= c;
+          }
+          // d g / d z = -u g / (s (1+z)) summed over the row, with and without f
+          const double inv = 1.0 / s;
+          const double Gd = G, cont = (double)num / Gd;
+          const double dg = (double)sug * (-inv / opz), dgf = (double)sugf * (-inv / opz);
+          gz += gc * (dlnS * S * cont + S * (dgf - cont * dg) / Gd);
+          cf = (float)(gc * S / Gd);
+          a0 = u0;
+          hh = hf;
+        }
+        const int c_lo = max(j0 - seg0, 0) / chunk_s, c_hi = min(j1 - seg0, seg_n - 1) / chunk_s;
+        for (int cc = c_lo; cc <= c_hi; ++cc) {   // owners whose nodes this row covers
+          atomicMin(&s_first[cc], i);
+          atomicMax(&s_last[cc], i);
+        }
+      }
+      s_j0[i] = (short)j0;
+      s_j1[i] = (short)j1;
+      s_cf[i] = cf;
+      s_a0[i] = a0;
+      s_h[i] = hh;
+    }
+    // analytic lines on the pixels (eq. F6)
+    const int nl = a.n_line;
+    if (nl > 0) {
+      const double Kf = pr.mass10 / (4.0 * kPi * pr.dl * pr.dl);
+      const double Eb = 0.85 - 1.9 * pr.delta;
+      for (int l = tid; l < nl; l += 256) {
+        const double lw = lib.line_wave[l];
+        const double lnlv = log(lw / kLamV);
+        const double p = exp(pr.alpha_bc * lnlv), qd = exp(pr.delta * lnlv);
+        const double Tl = exp(-pr.tau_bc * p - pr.tau_diff * qd * (lib.line_a[l] + Eb * lib.line_d[l]));
+        const double lobs = opz * lw;
+        double dsig;
+        const double si = sigma_inst_at(ob, lobs, &dsig);
+        const double sl = sqrt(ob.sigma_gas_kms * ob.sigma_gas_kms + si * si) / kC_kms;
+        s_lnl[l] = log(lobs);
+        s_sl[l] = sl;
+        s_dsl[l] = si * dsig * lw / (kC_kms * kC_kms * sl);
+        s_F[l] = a.Lline[(size_t)r * nl + l] * Tl * Kf;
+        s_T[l] = Tl * Kf;
+      }
+      __syncthreads();
+      // pixels within 10 sigma of a line: a counted loop (its length bounded by the
+      // observation's smallest pixel spacing, pixels past the window masked), split over
+      // two threads per line when the lines fit, halves added in a fixed order
+      const int tpl = nl <= 128 ? 2 : 1;
+      for (int l0 = tid; l0 < nl * tpl; l0 += 256) {
+        const int l = l0 / tpl, part = l0 - l * tpl;
+        const double mu = s_lnl[l], sl = s_sl[l];
+        const double vhi = mu + 10.0 * sl;
+        const int ia = lower_bound_dev(ob.lnpix, np, mu - 10.0 * sl);
+        const int ib = (int)fmin((double)np, (double)ia + ceil(20.0 * sl * a.inv_pix_step) + 2.0);
+        const int im = ia + (ib - ia + 1) / 2;
+        const int i0 = tpl == 1 ? ia : (part == 0 ? ia : im), i1 = tpl == 1 ? ib : (part == 0 ? im : ib);
+        double gFlx = 0.0, gzl = 0.0;
+        const double isl = 1.0 / sl;
+#pragma unroll 4
+        for (int i = i0; i < i1; ++i) {
+          const double lp = ob.lnpix[i];
+          if (lp <= vhi) {
+            const double u = (lp - mu) * isl;
+            const double Nn = (double)expf((float)(-0.5 * u * u)) * (isl / 2.5066282746310002);
+            const double glp = gm[i] / kFnuAB * ob.pix[i] * kAng_cm / kC_cms;
+            gFlx += glp * Nn;
+            gzl += glp * s_F[l] * (Nn * u / sl / opz + Nn * (u * u - 1.0) / sl * s_dsl[l]);
+          }
+        }
+        if (tpl == 2) {
+          const double of = __shfl_xor(gFlx, 1, 64), oz = __shfl_xor(gzl, 1, 64);
+          gFlx = part == 0 ? gFlx + of : of + gFlx;
+          gzl = part == 0 ? gzl + oz : oz + gzl;
+          if (part != 0) continue;
+        }
+        gz += gzl + gFlx * s_F[l] * (-2.0 * ddl / pr.dl);
+        a.dLl[(size_t)r * nl + l] = gFlx * s_T[l];
+        const double lw = lib.line_wave[l];
+        const double lnlv = log(lw / kLamV);
+        const double p = exp(pr.alpha_bc * lnlv), qd = exp(pr.delta * lnlv);
+        const double sh = lib.line_a[l] + Eb * lib.line_d[l];
+        const double gf = gFlx * s_F[l];
+        gtb += gf * (-p);
+        gab += gf * (-pr.tau_bc * p * lnlv);
+        gtd += gf * (-qd * sh);
+        gdl += gf * (-pr.tau_diff * (qd * lnlv * sh - 1.9 * qd * lib.line_d[l]));
+      }
+    }
+    __syncthreads();   // the rows no longer read f: the span now receives d logL / d F
+    {
+      // each thread owns at most kAdjOwn consecutive nodes of the span and adds, in pixel
+      // order, the rows that cover them: per row a window of kAdjOwn LDS values read
+      // together, updated, and written back under a mask (no read-modify-write chain)
+      const int c0 = tid * chunk_s, c1 = min(c0 + chunk_s, seg_n);
+      for (int cc = c0; cc < c1; ++cc) seg[cc] = 0.f;
+      if (c0 < c1) {
+        const int na0 = seg0 + c0, na1 = seg0 + c1 - 1;   // owned nodes
+        for (int i = s_first[tid]; i <= s_last[tid]; ++i) {
+          const int j0 = s_j0[i], j1 = s_j1[i];
+          const int ja = max(j0, na0), jb = min(j1, na1);
+          if (ja > jb) continue;
+          const float cf = s_cf[i], hf = s_h[i];
+          const int base = ja - seg0, cnt = jb - ja;   // window [base, base + cnt]
+          float v[kAdjOwn];
+#pragma unroll
+          for (int e = 0; e < kAdjOwn; ++e) v[e] = seg[min(base + e, seg_n - 1)];
+          if (hf == 0.f) {   // linear row on nodes j0 = k, j1 = k + 1
+            const float t = s_a0[i];
+#pragma unroll
+            for (int e = 0; e < kAdjOwn; ++e) {
+              const int j = ja + e;
+              v[e] += (j == j0 ? cf * (1.f - t) : 0.f) + (j == j1 ? cf * t : 0.f);
+            }
+          } else {
+            const float uu = fmaf((float)(ja - j0), hf, s_a0[i]);
+            float w = expf(-0.5f * uu * uu), q = expf(-uu * hf - 0.5f * hf * hf);
+            const float cq = expf(-hf * hf);
+#pragma unroll
+            for (int e = 0; e < kAdjOwn; ++e) {
+              v[e] += e <= cnt ? cf * w : 0.f;
+              w *= q;
+              q *= cq;
+            }
+          }
+#pragma unroll
+          for (int e = 0; e < kAdjOwn; ++e)
+            if (e <= cnt) seg[base + e] = v[e];
         }
       }
     }
@@ -298,12 +602,29 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
   // ---------------- attenuation adjoint on the owned pixels (eq. D2)
   T *GY = (T *)a.GY + (size_t)r * a.N_pad, *GO = (T *)a.GO + (size_t)r * a.N_pad;
   const double Eb = 0.85 - 1.9 * pr.delta;
-  for (int n = n0; n < n1; ++n) {
+  for (int n = tid; n < N; n += 256) {   // gF complete after the barrier: coalesced pass
     const double l = lib.lnlv_d[n];
-    const double p = exp(pr.alpha_bc * l), qd = exp(pr.delta * l);
-    const double sh = lib.dust_a_d[n] + Eb * lib.dust_d_d[n];
-    const double Tbc = exp(-pr.tau_bc * p), Td = exp(-pr.tau_diff * qd * sh);
-    const double g = gFl[n];
+    const double g = !fast_spec ? gFl[n]
+                                : (n >= fs_seg0 && n < fs_seg0 + fs_segn
+                                       ? (double)((const float *)gFl)[n - fs_seg0] * lib.lam2_d[n]
+                                       : 0.0);
+    double p, qd, sh, Tbc, Td;
+    if (sizeof(T) == 4) {   // FP32 path: the factors in FP32, as the forward epilogue forms them
+      const float lf = lib.lnlv_f[n];
+      const float pf = expf((float)pr.alpha_bc * lf), qf = expf((float)pr.delta * lf);
+      const float shf = lib.dust_a_f[n] + (float)Eb * lib.dust_d_f[n];
+      p = pf;
+      qd = qf;
+      sh = shf;
+      Tbc = expf(-(float)pr.tau_bc * pf);
+      Td = expf(-(float)pr.tau_diff * qf * shf);
+    } else {
+      p = exp(pr.alpha_bc * l);
+      qd = exp(pr.delta * l);
+      sh = lib.dust_a_d[n] + Eb * lib.dust_d_d[n];
+      Tbc = exp(-pr.tau_bc * p);
+      Td = exp(-pr.tau_diff * qd * sh);
+    }
     GY[n] = (T)(g * Td * Tbc);
     GO[n] = (T)(g * Td);
     const double ya = (double)Yr[n], fa = (double)Fr[n];
@@ -316,9 +637,19 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
     GY[n] = (T)0;
     GO[n] = (T)0;
   }
-  const double s_z = block_sum256(gz, red), s_lm = block_sum256(glm, red);
-  const double s_tb = block_sum256(gtb, red), s_ab = block_sum256(gab, red);
-  const double s_td = block_sum256(gtd, red), s_dl = block_sum256(gdl, red);
+  // six block sums at once: wave butterflies, then the four waves in a fixed order
+  double v6[6] = {gz, glm, gtb, gab, gtd, gdl};
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    for (int o = 32; o > 0; o >>= 1) v6[k] += __shfl_xor(v6[k], o, 64);
+  __syncthreads();
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[(tid >> 6) * 6 + k] = v6[k];
+  __syncthreads();
+  const double s_z = (red[0] + red[6]) + (red[12] + red[18]), s_lm = (red[1] + red[7]) + (red[13] + red[19]);
+  const double s_tb = (red[2] + red[8]) + (red[14] + red[20]), s_ab = (red[3] + red[9]) + (red[15] + red[21]);
+  const double s_td = (red[4] + red[10]) + (red[16] + red[22]), s_dl = (red[5] + red[11]) + (red[17] + red[23]);
   if (tid == 0) {
     double *gb = a.gbuf + (size_t)r * 16;
     gb[GB_Z] = s_z;
@@ -511,7 +842,8 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
   double *wq = gm + n;                  // [ny]
   double *gwq = wq + ny;                // [ny]
   double *red = gwq + ny;               // [256]
-  int *zj = (int *)(red + 256);         // [n]
+  double *gsq = red + 256;              // [n_line * ny] per (line, age) entry
+  int *zj = (int *)(gsq + (size_t)lib.n_line * ny);   // [n]
   __shared__ double s_sc[4];
   const int r = blockIdx.x, tid = threadIdx.x;
   const PointRow pr = a.rows[r];
@@ -605,25 +937,30 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
     const double dtg = ig ? 1.0 / (lib.zg[jg + 1] - lib.zg[jg]) : 0.0;
     const double dtu = iu ? 1.0 / (lib.un[ju + 1] - lib.un[ju]) : 0.0;
     const int nu = lib.n_u;
-    // thread per age: sum over lines in a fixed order
+    // thread per (line, age) entry q = l * ny + ag (consecutive threads on consecutive
+    // table entries): 10^Lhat and its derivatives in the gas parameters; the per-age
+    // sums over lines then run in a fixed order
+    const int nq = lib.n_line * ny;
+    const size_t slab = (size_t)lib.n_line * ny;
+    const size_t o00 = (size_t)(jg * nu + ju) * slab, o01 = (size_t)(jg * nu + ju + 1) * slab;
+    const size_t o10 = (size_t)((jg + 1) * nu + ju) * slab, o11 = (size_t)((jg + 1) * nu + ju + 1) * slab;
+    for (int q = tid; q < nq; q += 256) {
+      const int l = q / ny, ag = q - l * ny;
+      const double gL = pr.kind == 0 ? gacc[a.line_k0 + l] / kLsun : a.dLl[(size_t)r * lib.n_line + l];
+      const double t00 = lib.line_table[o00 + q], t01 = lib.line_table[o01 + q];
+      const double t10 = lib.line_table[o10 + q], t11 = lib.line_table[o11 + q];
+      const double lh = (1 - tg) * (1 - tu) * t00 + (1 - tg) * tu * t01 + tg * (1 - tu) * t10 + tg * tu * t11;
+      const double E = exp10(lh);
+      gsq[q] = gL * E;
+      const double gE = gL * wq[ag] * E * 2.302585092994046;
+      ggz += gE * ((1 - tu) * (t10 - t00) + tu * (t11 - t01)) * dtg;
+      ggu += gE * ((1 - tg) * (t01 - t00) + tg * (t11 - t10)) * dtu;
+    }
+    __syncthreads();
     for (int ag = tid; ag < ny; ag += 256) {
-      double gs = 0.0, gzg = 0.0, gu = 0.0;
-      for (int l = 0; l < lib.n_line; ++l) {
-        const double gL = pr.kind == 0 ? gacc[a.line_k0 + l] / kLsun : a.dLl[(size_t)r * lib.n_line + l];
-        const size_t slab = (size_t)lib.n_line * ny;
-        const double *tb = lib.line_table + (size_t)l * ny + ag;
-        const double t00 = tb[(jg * nu + ju) * slab], t01 = tb[(jg * nu + ju + 1) * slab];
-        const double t10 = tb[((jg + 1) * nu + ju) * slab], t11 = tb[((jg + 1) * nu + ju + 1) * slab];
-        const double lh = (1 - tg) * (1 - tu) * t00 + (1 - tg) * tu * t01 + tg * (1 - tu) * t10 + tg * tu * t11;
-        const double E = exp10(lh);
-        gs += gL * E;
-        const double gE = gL * wq[ag] * E * 2.302585092994046;
-        gzg += gE * ((1 - tu) * (t10 - t00) + tu * (t11 - t01)) * dtg;
-        gu += gE * ((1 - tg) * (t01 - t00) + tg * (t11 - t10)) * dtu;
-      }
+      double gs = 0.0;
+      for (int l = 0; l < lib.n_line; ++l) gs += gsq[l * ny + ag];
       gwq[ag] = gs;
-      ggz += gzg;
-      ggu += gu;
     }
     __syncthreads();
     for (int ag = tid; ag < ny; ag += 256)
@@ -679,10 +1016,18 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
     gm[i] = gmi;
     gzeta[i] = gzi;
   }
-  const double s_ze = block_sum256(gz_e, red);
-  const double s_afe = block_sum256(gafe, red);
-  const double s_gz = block_sum256(ggz, red);
-  const double s_gu = block_sum256(ggu, red);
+  // four block sums at once: wave butterflies, then the four waves in a fixed order
+  double v4[4] = {gz_e, gafe, ggz, ggu};
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    for (int o = 32; o > 0; o >>= 1) v4[k] += __shfl_xor(v4[k], o, 64);
+  __syncthreads();
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[(tid >> 6) * 4 + k] = v4[k];
+  __syncthreads();
+  const double s_ze = (red[0] + red[4]) + (red[8] + red[12]), s_afe = (red[1] + red[5]) + (red[9] + red[13]);
+  const double s_gz = (red[2] + red[6]) + (red[10] + red[14]), s_gu = (red[3] + red[7]) + (red[11] + red[15]);
   double *gr = a.grad + (size_t)pr.b * a.P;
   for (int c = tid; c < a.P; c += 256) gr[c] = 0.0;
   __syncthreads();
@@ -749,7 +1094,46 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
   aa.GO = (char *)w.G + (size_t)B_pad * g.N_pad * (f64 ? 8 : 4);
   aa.gbuf = w.gbuf;
   aa.dLl = w.dLl;
-  const size_t sm1 = (size_t)g.N * 8;
+  // dynamic LDS of the projection adjoint: gF [N] in the pass's precision (FP32 spectra:
+  // the span of the rows), the line tables of a spectrum, then on the FP32 path the
+  // per-node or per-pixel tables of the transpose when they fit (two workgroups per CU)
+  const bool spec = o->host.kind != 0;
+  size_t gb = ((size_t)g.N * 8 + 15) & ~(size_t)15, extra = 0;
+  aa.fast = 0;
+  aa.seg_cap = 0;
+  aa.nl_lds = spec ? g.n_line : 0;
+  const size_t lines_b = 40 * (size_t)aa.nl_lds;
+  if (!f64 && !spec && g.log_uniform) {
+    const size_t nfn = o->host.fw.size(), nb = o->host.band_off.size();
+    const size_t t = 10 * nfn + 4 * nb;
+    if (gb + t <= 76 * 1024) {
+      extra = t;
+      aa.fast = 1;
+    }
+  } else if (!f64 && spec && g.log_uniform && o->host.n_data > 0) {
+    const size_t np = (size_t)o->host.n_data;
+    double kmax = 0.0;
+    for (double v : o->host.ksig) kmax = std::max(kmax, v);
+    const double ext = 5.0 * kmax * g.inv_dlnw + 2.0;
+    const double span = (o->host.lnpix.back() - o->host.lnpix.front()) * g.inv_dlnw + 2.0 * ext;
+    const size_t cap = (size_t)std::min((double)g.N, std::ceil(span) + 4.0);
+    const size_t gbf = (cap * 4 + 15) & ~(size_t)15;
+    const size_t t = ((4 * np + 15) & ~(size_t)15) + 12 * np + 2048;
+    if (gbf + lines_b + t <= 76 * 1024 && cap <= 256 * (size_t)kAdjOwn) {
+      gb = gbf;
+      extra = t;
+      aa.fast = 1;
+      aa.seg_cap = (int)cap;
+    }
+  }
+  aa.g_bytes = (int)gb;
+  aa.inv_pix_step = HUGE_VAL;
+  if (spec && o->host.lnpix.size() > 1) {
+    double dmin = HUGE_VAL;
+    for (size_t i = 1; i < o->host.lnpix.size(); ++i) dmin = std::min(dmin, o->host.lnpix[i] - o->host.lnpix[i - 1]);
+    if (dmin > 0.0) aa.inv_pix_step = 1.0 / dmin;
+  }
+  const size_t sm1 = gb + lines_b + extra;
   static size_t attr1[2] = {0, 0};
   if (sm1 > 48 * 1024 && sm1 > attr1[f64 ? 1 : 0]) {
     const void *fn = f64 ? (const void *)k_adj_proj<double> : (const void *)k_adj_proj<float>;
@@ -786,7 +1170,8 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
     ap.gnoise = w.gnoise;
     ap.dLl = w.dLl;
     ap.grad = grad;
-    const size_t sm2 = sizeof(double) * (2 * (size_t)g.K_pad + 6 * (size_t)g.n_sfh + 2 + 2 * g.n_young + 256) +
+    const size_t sm2 = sizeof(double) * (2 * (size_t)g.K_pad + 6 * (size_t)g.n_sfh + 2 + 2 * g.n_young + 256 +
+                                         (size_t)g.n_line * g.n_young) +
                        sizeof(int) * (size_t)g.n_sfh + 64;
     if (sm2 > 150 * 1024) return fail(SPS_E_SHAPE, "gradient pass: library too large for one workgroup");
     static size_t attr2 = 0;

@@ -320,7 +320,36 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     const size_t o10 = (size_t)((jg + 1) * nu + ju) * slab, o11 = (size_t)((jg + 1) * nu + ju + 1) * slab;
     const double c00 = (1.0 - tg) * (1.0 - tu), c01 = (1.0 - tg) * tu, c10 = tg * (1.0 - tu), c11 = tg * tu;
     const int nq = nl * ny;
-    {
+    if (MODE != W_F64 && (nq & 3) == 0) {
+      // 16-byte loads: a thread's four consecutive entries of each corner in one request,
+      // up to four requests per corner in flight (nq is a multiple of 4, so are the
+      // corner offsets, and the table is 16-byte aligned)
+      const float4 *tb = (const float4 *)lib.line_table_f;
+      const float f00 = (float)c00, f01 = (float)c01, f10 = (float)c10, f11 = (float)c11;
+      const int nv = nq >> 2;
+      for (int v0 = tid; v0 < nv; v0 += 256 * 4) {
+        float4 c[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int v = min(v0 + 256 * u, nv - 1);
+          c[u][0] = tb[(o00 >> 2) + v];
+          c[u][1] = tb[(o01 >> 2) + v];
+          c[u][2] = tb[(o10 >> 2) + v];
+          c[u][3] = tb[(o11 >> 2) + v];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int v = v0 + 256 * u;
+          if (v < nv) {
+            const float4 a0 = c[u][0], a1 = c[u][1], a2 = c[u][2], a3 = c[u][3];
+            s_lt[4 * v + 0] = (Acc)exp10f(f00 * a0.x + f01 * a1.x + f10 * a2.x + f11 * a3.x);
+            s_lt[4 * v + 1] = (Acc)exp10f(f00 * a0.y + f01 * a1.y + f10 * a2.y + f11 * a3.y);
+            s_lt[4 * v + 2] = (Acc)exp10f(f00 * a0.z + f01 * a1.z + f10 * a2.z + f11 * a3.z);
+            s_lt[4 * v + 3] = (Acc)exp10f(f00 * a0.w + f01 * a1.w + f10 * a2.w + f11 * a3.w);
+          }
+        }
+      }
+    } else {
       for (int q0 = tid; q0 < nq; q0 += 256 * 8) {
         if (MODE == W_F64) {
           const double *tb = lib.line_table;

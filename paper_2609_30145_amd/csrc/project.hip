@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
     // weight linear in lambda on [w_k, w_k+1] is (e^{f d} - 1)/(e^d - 1), f the fractional
     // log index; a node is inside the model grid when its log index lies in [0, N - 1].
     const double ui0 = -(lnopz + lib.lnw0) * lib.inv_dlnw;   // log index = fwln * inv_dlnw + ui0
-    // (the gradient pass keeps the generic path, whose weights the adjoint transposes)
+    // (the gradient pass keeps the generic path: its band sums are accumulated in FP64)
     int seg0 = 0, seg_n = 0;
     if (sizeof(T) == 4 && lib.log_uniform && !a.gvec) {
       seg0 = min(max((int)floor(ob.fwln_min * lib.inv_dlnw + ui0), 0), N - 2);
@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
     // w_{j+1} = w_j q_j, q_{j+1} = q_j e^{-h^2} (h = node spacing / row width), which
     // needs three exponentials per row instead of one per tap
     int seg0 = 0, seg_n = 0;
-    const bool fast = sizeof(T) == 4 && lib.log_uniform && !a.gvec;   // the gradient pass keeps the generic path
+    const bool fast = sizeof(T) == 4 && lib.log_uniform;   // the adjoint transposes the same rows
     if (fast) {
       const double ext = 5.0 * ob.ksig_max * lib.inv_dlnw + 2.0;
       const double ua = (ob.lnpix[0] - lnopz - lnw0) * lib.inv_dlnw - ext;
