@@ -668,18 +668,38 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
 template <int MT, int NT>
 __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, const float *__restrict__ GO,
                                                  const float *__restrict__ Ln, int N_pad, int K_pad, int K_young_pad,
+                                                 const uint32_t *__restrict__ rowmask, int mask_words,
                                                  double *__restrict__ dW) {
   constexpr int KT = 32, LDSK = KT + 4, WM = 2, WN = 2;
   constexpr int WTM = MT / WM, WTN = NT / WN, BM = WTM / 32, BN = WTN / 32;
   constexpr int A4 = MT * KT / 4 / 256, B4 = NT * KT / 4 / 256;
-  __shared__ __attribute__((aligned(16))) float As[MT * LDSK];
-  __shared__ __attribute__((aligned(16))) float Bs[NT * LDSK];
+  __shared__ __attribute__((aligned(16))) float As[2][MT * LDSK];
+  __shared__ __attribute__((aligned(16))) float Bs[2][NT * LDSK];
+  __shared__ uint32_t s_any;
   const int n_ct = K_pad / NT;
   const int mt = blockIdx.x / n_ct, ct = blockIdx.x % n_ct;
   const int m0 = mt * MT, c0 = ct * NT;
-  const float *G = c0 < K_young_pad ? GY : GO;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN, li = lane & 31, lh = lane >> 5;
+  // a column tile whose weights are zero in every row of the block needs no product: the
+  // rows' occupancy bits (32-wide K tiles) decide, and the block writes zeros
+  if (tid == 0) s_any = 0u;
+  __syncthreads();
+  if (rowmask) {
+    uint32_t any = 0u;
+    for (int rr = tid; rr < MT; rr += 256)
+      for (int t32 = c0 / 32; t32 < (c0 + NT) / 32; ++t32)
+        any |= (rowmask[(size_t)(m0 + rr) * mask_words + (t32 >> 5)] >> (t32 & 31)) & 1u;
+    if (any) s_any = 1u;
+  } else if (tid == 0) {
+    s_any = 1u;
+  }
+  __syncthreads();
+  if (s_any == 0u) {
+    for (int idx = tid; idx < MT * NT; idx += 256) dW[(size_t)(m0 + idx / NT) * K_pad + c0 + idx % NT] = 0.0;
+    return;
+  }
+  const float *G = c0 < K_young_pad ? GY : GO;
   // each 32-wide reduction tile is accumulated in FP32 and the tile partials are summed
   // in FP64, which keeps the differences dW[j+1] - dW[j] of the metallicity adjoint accurate
   double dacc[BM][BN][16];
@@ -691,46 +711,40 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
       for (int e = 0; e < 16; ++e) dacc[i][j][e] = 0.0;
   f32x4 ra[A4], rb[B4];
   const int nt = N_pad / KT;
-#pragma unroll
-  for (int q = 0; q < A4; ++q) {
-    const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
-    ra[q] = *(const f32x4 *)(G + (size_t)(m0 + row) * N_pad + c4 * 4);
+#define SPS_BWD_LOAD(k0_)                                                                  \
+  {                                                                                        \
+    _Pragma("unroll") for (int q = 0; q < A4; ++q) {                                       \
+      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;                         \
+      ra[q] = *(const f32x4 *)(G + (size_t)(m0 + row) * N_pad + (k0_) + c4 * 4);           \
+    }                                                                                      \
+    _Pragma("unroll") for (int q = 0; q < B4; ++q) {                                       \
+      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;                         \
+      rb[q] = *(const f32x4 *)(Ln + (size_t)(c0 + row) * N_pad + (k0_) + c4 * 4);          \
+    }                                                                                      \
   }
-#pragma unroll
-  for (int q = 0; q < B4; ++q) {
-    const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
-    rb[q] = *(const f32x4 *)(Ln + (size_t)(c0 + row) * N_pad + c4 * 4);
+#define SPS_BWD_STORE(buf_)                                                                \
+  {                                                                                        \
+    _Pragma("unroll") for (int q = 0; q < A4; ++q) {                                       \
+      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;                         \
+      *(f32x4 *)(As[buf_] + row * LDSK + c4 * 4) = ra[q];                                  \
+    }                                                                                      \
+    _Pragma("unroll") for (int q = 0; q < B4; ++q) {                                       \
+      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;                         \
+      *(f32x4 *)(Bs[buf_] + row * LDSK + c4 * 4) = rb[q];                                  \
+    }                                                                                      \
   }
+  SPS_BWD_LOAD(0);
+  SPS_BWD_STORE(0);
+  // double-buffered: the tile t + 1 is loaded into registers during the products of tile
+  // t and stored into the other buffer, whose last readers finished before the barrier
   for (int t = 0; t < nt; ++t) {
+    const int buf = t & 1;
+    SPS_BWD_LOAD(min(t + 1, nt - 1) * KT);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < A4; ++q) {
-      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
-      *(f32x4 *)(As + row * LDSK + c4 * 4) = ra[q];
-    }
-#pragma unroll
-    for (int q = 0; q < B4; ++q) {
-      const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
-      *(f32x4 *)(Bs + row * LDSK + c4 * 4) = rb[q];
-    }
-    __syncthreads();
-    if (t + 1 < nt) {
-      const int k0 = (t + 1) * KT;
-#pragma unroll
-      for (int q = 0; q < A4; ++q) {
-        const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
-        ra[q] = *(const f32x4 *)(G + (size_t)(m0 + row) * N_pad + k0 + c4 * 4);
-      }
-#pragma unroll
-      for (int q = 0; q < B4; ++q) {
-        const int idx = tid + 256 * q, row = idx >> 3, c4 = idx & 7;
-        rb[q] = *(const f32x4 *)(Ln + (size_t)(c0 + row) * N_pad + k0 + c4 * 4);
-      }
-    }
     float af[BM][16], bf[BN][16];
 #pragma unroll
     for (int i = 0; i < BM; ++i) {
-      const float *p = As + (wm * WTM + i * 32 + li) * LDSK + lh * 16;
+      const float *p = As[buf] + (wm * WTM + i * 32 + li) * LDSK + lh * 16;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const f32x4 v = *(const f32x4 *)(p + 4 * q);
@@ -739,7 +753,7 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
     }
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
-      const float *p = Bs + (wn * WTN + j * 32 + li) * LDSK + lh * 16;
+      const float *p = Bs[buf] + (wn * WTN + j * 32 + li) * LDSK + lh * 16;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const f32x4 v = *(const f32x4 *)(p + 4 * q);
@@ -760,6 +774,7 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
 #pragma unroll
         for (int j = 0; j < BN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+    SPS_BWD_STORE(buf ^ 1);
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
@@ -767,6 +782,8 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
 #pragma unroll
         for (int e = 0; e < 16; ++e) dacc[i][j][e] += (double)acc[i][j][e];
   }
+#undef SPS_BWD_LOAD
+#undef SPS_BWD_STORE
 #pragma unroll
   for (int i = 0; i < BM; ++i)
 #pragma unroll
@@ -1150,9 +1167,9 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
       hipLaunchKernelGGL(k_bwd_f64, dim3((B_pad / 64) * (g.K_pad / 64)), dim3(256), 0, s, (const double *)aa.GY,
                          (const double *)aa.GO, g.LT64, g.N_pad, g.K_pad, g.K_young_pad, (double *)w.dW);
     } else {
-      hipLaunchKernelGGL((k_bwd_f32<128, 64>), dim3((B_pad / 128) * (g.K_pad / 64)), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_bwd_f32<64, 64>), dim3((B_pad / 64) * (g.K_pad / 64)), dim3(256), 0, s,
                          (const float *)aa.GY, (const float *)aa.GO, g.L32n, g.N_pad, g.K_pad, g.K_young_pad,
-                         (double *)w.dW);
+                         (const uint32_t *)w.rowmask, w.mask_words, (double *)w.dW);
     }
     e = hipGetLastError();
   }
