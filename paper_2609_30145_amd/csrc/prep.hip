@@ -184,32 +184,9 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   // key order (ties by index).  Workgroups past B clear the padding rows.
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int b = blockIdx.x < a.B ? blockIdx.x : -1;
-  int r = blockIdx.x;
-  if (b >= 0) {
-    __shared__ int s_rank[4];
-    const double my = a.keys[b];
-    int c = 0;
-    for (int j0 = tid; j0 < a.B; j0 += 256 * 4) {   // four key loads per thread in flight
-      double kq[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = j0 + 256 * u;
-        kq[u] = j < a.B ? a.keys[j] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = j0 + 256 * u;
-        c += j < a.B && ((kq[u] < my) || (kq[u] == my && j < b));
-      }
-    }
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if (lane == 0) s_rank[wv] = c;
-    __syncthreads();
-    r = (s_rank[0] + s_rank[1]) + (s_rank[2] + s_rank[3]);
-  }
-  const size_t rowoff = (size_t)r * K_pad;
-
   if (b < 0) {   // padding row: zero weights
+    const int r = blockIdx.x;
+    const size_t rowoff = (size_t)r * K_pad;
     for (int k = tid; k < K_pad; k += 256) {
       if (MODE == W_F64) ((double *)a.W)[rowoff + k] = 0.0;
       else if (MODE == W_F32) ((float *)a.W)[rowoff + k] = 0.f;
@@ -227,7 +204,8 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     return;
   }
 
-  // ---- A1
+  // ---- A1 (with the rank): the point's tables into LDS, its rank among the batch keys,
+  // and D_C, behind one barrier
   const double *th = a.theta + (size_t)b * a.P;
   for (int c = tid; c < a.P; c += 256) s_th[c] = th[c];
   for (int m = tid; m < nz; m += 256) s_logz[m] = lib.logz[m];
@@ -243,6 +221,26 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   }
   for (int k = tid; k < K_pad; k += 256) wacc[k] = (Acc)0;
   if (tid < 64) s_bits[tid] = 0u;
+  __shared__ int s_rank[4];
+  {
+    const double my = a.keys[b];
+    int c = 0;
+    for (int j0 = tid; j0 < a.B; j0 += 256 * 4) {   // four key loads per thread in flight
+      double kq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + 256 * u;
+        kq[u] = j < a.B ? a.keys[j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + 256 * u;
+        c += j < a.B && ((kq[u] < my) || (kq[u] == my && j < b));
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane == 0) s_rank[wv] = c;
+  }
   // cosmology (Sec. 2.6): D_C by composite Gauss-Legendre in u = (1+z')^-1/2, where
   // the integrand 2 / sqrt(Om + OL u^6) is smooth
   const double z = th[TH_ZRED];
@@ -259,6 +257,8 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     if (lane == 0) s_part[wv] = part;
   }
   __syncthreads();
+  const int r = (s_rank[0] + s_rank[1]) + (s_rank[2] + s_rank[3]);
+  const size_t rowoff = (size_t)r * K_pad;
   const double dc = kC_kms / lib.H0 * (1.0 - u0) * ((s_part[0] + s_part[1]) + (s_part[2] + s_part[3])) * kMpc_cm;
 
   // ---- A2

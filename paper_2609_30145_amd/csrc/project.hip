@@ -53,7 +53,6 @@ __global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
   T *s_term = (T *)sraw;
   double *s_lnl = (double *)sraw, *s_isl = s_lnl + 512, *s_amp = s_lnl + 1024;
   __shared__ double s_slmax[4];
-  __shared__ double s_noise[4];
   const int r = blockIdx.x;
   const PointRow pr = a.rows[r];
   if (pr.b < 0) return;
@@ -64,15 +63,11 @@ __global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
   const T *Fr = a.F + (size_t)r * a.N_pad;
   const int N = lib.N;
 
-  // noise-floor parameters (ln space)
-  if (tid == 0) {
-    s_noise[0] = (ob.noise_flags & 1) ? exp(th[TH_LOG_ERR_SCALE]) : 1.0;
-    s_noise[1] = (ob.noise_flags & 2) ? exp(th[TH_LOG_F_CALIB]) : 0.0;
-    s_noise[2] = (ob.noise_flags & 4) ? exp(th[TH_LOG_F_DATA]) : 0.0;
-    s_noise[3] = (ob.noise_flags & 8) ? exp(th[TH_LOG_JITTER]) : 0.0;
-  }
-  __syncthreads();
-  const double ns = s_noise[0], fc = s_noise[1], fd = s_noise[2], jt = s_noise[3];
+  // noise-floor parameters (ln space), evaluated by every thread (no barrier)
+  const double ns = (ob.noise_flags & 1) ? exp(th[TH_LOG_ERR_SCALE]) : 1.0;
+  const double fc = (ob.noise_flags & 2) ? exp(th[TH_LOG_F_CALIB]) : 0.0;
+  const double fd = (ob.noise_flags & 4) ? exp(th[TH_LOG_F_DATA]) : 0.0;
+  const double jt = (ob.noise_flags & 8) ? exp(th[TH_LOG_JITTER]) : 0.0;
   double lsum = 0.0;
   double gs[4] = {0.0, 0.0, 0.0, 0.0};
 
