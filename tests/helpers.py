@@ -11,9 +11,17 @@ from oracle import model as om
 from synth import workloads as wl
 
 
-def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=()):
+def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=(), wave_jitter=0.0):
+    """wave_jitter > 0 moves each model wavelength by that fraction of the log step
+    (sinusoidally), so that the grid is no longer log-uniform and the general
+    interpolation paths are taken."""
     B = cfg.batch if B is None else B
     lib = wl.make_library(cfg, seed)
+    if wave_jitter > 0.0:
+        lw = np.log(lib["wave"])
+        step = lw[1] - lw[0]
+        lw = lw + wave_jitter * step * np.sin(0.7 * np.arange(lw.size))
+        lib["wave"] = np.exp(lw)
     lines = wl.make_lines(cfg, lib, seed + 1)
     dust = wl.make_dust_tables(cfg, lib["wave"])
     olib = om.build_library(cfg, lib, lines, dust)

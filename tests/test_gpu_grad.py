@@ -58,6 +58,12 @@ CASES = {
                                          n_wave=1500, n_sfh=20, n_zh=5, n_lines=24), kind="phot"),
     "spec_zh_lines": dict(cfg=wl.reduced(wl.CONFIGS["c3"], n_age=40, logz=tuple(np.linspace(-2.5, 0.5, 8)),
                                          n_wave=1500, n_sfh=16, n_zh=5, n_lines=24, n_pix=300), kind="spec"),
+    # a model grid that is not log-uniform: the general interpolation and LSF paths
+    "phot_nonuniform": dict(cfg=wl.reduced(wl.CONFIGS["c1"], n_age=30, logz=tuple(np.linspace(-2.5, 0.5, 6)),
+                                           n_wave=1200, n_sfh=12, n_zh=4, n_lines=16), kind="phot", jitter=0.2),
+    "spec_nonuniform": dict(cfg=wl.reduced(wl.CONFIGS["c3"], n_age=30, logz=tuple(np.linspace(-2.5, 0.5, 6)),
+                                           n_wave=1200, n_sfh=12, n_zh=4, n_lines=16, n_pix=250), kind="spec",
+                            jitter=0.2),
     "phot_alpha_noise": dict(cfg=wl.reduced(wl.CONFIGS["c4"], n_age=30, logz=(-2.0, -1.0, 0.0),
                                             afe=(0.0, 0.2, 0.4), n_wave=1000, n_sfh=10), kind="phot",
                              noise=("err_scale", "f_calib", "f_data", "jitter")),
@@ -67,7 +73,8 @@ CASES = {
 @pytest.fixture(scope="module", params=list(CASES))
 def gcase(request):
     spec = CASES[request.param]
-    case = make_case(spec["cfg"], B=24, kind=spec["kind"], noise=spec.get("noise", ()))
+    case = make_case(spec["cfg"], B=24, kind=spec["kind"], noise=spec.get("noise", ()),
+                     wave_jitter=spec.get("jitter", 0.0))
     theta = near_truth(case, 24)
     cols = om.columns(spec["cfg"].n_sfh, spec["cfg"].n_zh)
     if spec.get("noise"):

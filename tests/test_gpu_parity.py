@@ -199,3 +199,30 @@ def test_c1_full_low_precision(c1full, prec):
     e = rel_err(m, m_ref)
     say(f"  max rel err {e.max():.3e}")
     assert e.max() < 2e-3
+
+
+# ------------------------------------------------------------------------------ grid not log-uniform
+@pytest.fixture(scope="module", params=["phot", "spec"])
+def nonuniform(request):
+    base = wl.CONFIGS["c1"] if request.param == "phot" else wl.CONFIGS["c3"]
+    cfg = wl.reduced(base, n_age=30, logz=tuple(np.linspace(-2.5, 0.5, 6)), n_wave=1200, n_sfh=12, n_zh=4,
+                     n_lines=16, n_pix=250)
+    case = make_case(cfg, B=40, kind=request.param, wave_jitter=0.2)
+    L, O = gpu_objects(case, precisions=("fp64", "fp32"))
+    ll, m = oracle_run(case)
+    return request.param, case, L, O, ll, m
+
+
+def test_nonuniform_grid_fp64_and_fp32(nonuniform):
+    """A model grid whose log step varies by +-14 %: the general bracketing and LSF
+    paths (no log-index shortcut) against the oracle."""
+    kind, case, L, O, ll_ref, m_ref = nonuniform
+    say(f"non-log-uniform grid, {kind}, B=40")
+    ll, m = gpu_run(L, O, case["theta"], "fp64")
+    e64 = rel_err(m, m_ref)
+    ll32, m32 = gpu_run(L, O, case["theta"], "fp32")
+    e32 = rel_err(m32, m_ref)
+    say(f"  fp64 max rel err {e64.max():.3e}; fp32 {e32.max():.3e}")
+    assert e64.max() < 1e-11
+    assert np.all(np.abs(ll - ll_ref) <= 1e-9 * np.maximum(1.0, np.abs(ll_ref)))
+    assert e32.max() < 1e-5
