@@ -68,7 +68,8 @@ __host__ __device__ inline void propose_point(const double *src, double *dst, in
 
 hipError_t launch_propose(const DevReq *reqs, int n_req, int P, int n_sfh, const ProposalBox &box,
                           double *theta_all, int *point_obs, int n_total, hipStream_t s);
+// thr: [n_req] device scratch for the per-request thresholds
 hipError_t launch_update(const DevReq *reqs, int n_req, int P, const double *theta_all, const double *logl_all,
-                         hipStream_t s);
+                         double *thr, int n_total, hipStream_t s);
 
 }  // namespace sps

@@ -73,6 +73,7 @@ struct sps_server {
   DevReq *d_reqs = nullptr, *h_reqs = nullptr;
   double *d_theta_all = nullptr, *d_logl_all = nullptr;
   int *d_point_obs = nullptr;
+  double *d_thr = nullptr;   // per-request acceptance thresholds of a tick
   DeviceBuffers mem;
   // mock buffers
   std::vector<double> m_theta_all, m_logl_all;
@@ -188,7 +189,7 @@ bool sps_server::tick() {
   if (launch_forward(lib, ws, d_obs_table, d_point_obs, d_theta_all, total, desc.precision, d_logl_all, nullptr, 1,
                      false, 1, nullptr, s_compute) != SPS_OK)
     return false;
-  e = launch_update(d_reqs, n, P, d_theta_all, d_logl_all, s_compute);
+  e = launch_update(d_reqs, n, P, d_theta_all, d_logl_all, d_thr, total, s_compute);
   if (e == hipSuccess) e = hipStreamSynchronize(s_compute);
   return e == hipSuccess;
 }
@@ -339,7 +340,8 @@ extern "C" sps_status sps_server_create(const sps_library *L, const sps_server_d
     S->d_theta_all = (double *)S->mem.alloc((size_t)d->max_points * S->P * 8);
     S->d_logl_all = (double *)S->mem.alloc((size_t)d->max_points * 8);
     S->d_point_obs = (int *)S->mem.alloc((size_t)d->max_points * 4);
-    ok = ok && S->d_obs_table && S->d_reqs && S->d_theta_all && S->d_logl_all && S->d_point_obs;
+    S->d_thr = (double *)S->mem.alloc(sizeof(double) * d->max_active);
+    ok = ok && S->d_obs_table && S->d_reqs && S->d_theta_all && S->d_logl_all && S->d_point_obs && S->d_thr;
     ok = ok && hipHostMalloc((void **)&S->h_reqs, sizeof(DevReq) * d->max_active, hipHostMallocDefault) == hipSuccess;
     if (!ok) {
       sps_server_destroy(S);
