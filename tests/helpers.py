@@ -63,6 +63,23 @@ def gpu_objects(case, precisions=("fp64", "fp32"), max_batch=None):
     return L, O
 
 
+def near_truth(cfg, theta_true, n, seed):
+    """Perturbations of the data-generating vector: 1 % in the dust optical depths and
+    the SFH bin masses, 0.004 dex in mass, 0.01 in the dust slope and the gas parameters.
+    They put the logL bound to the test where a fit is within reach of the data."""
+    rng = np.random.default_rng(seed)
+    cols = wl.theta_columns(cfg.n_sfh, cfg.n_zh)
+    th = np.repeat(theta_true, n, axis=0)
+    th[:, cols["logmass"]] += 0.004 * rng.normal(size=n)
+    for c in ("tau_bc", "tau_diff"):
+        th[:, cols[c]] = np.clip(th[:, cols[c]] * (1.0 + 0.01 * rng.normal(size=n)), 0.0, 4.0)
+    for c in ("delta", "gas_logz", "gas_logu"):
+        th[:, cols[c]] += 0.01 * rng.normal(size=n)
+    s0 = cols["sfh"]
+    th[:, s0:s0 + cfg.n_sfh] *= 1.0 + 0.01 * rng.normal(size=(n, cfg.n_sfh))
+    return th
+
+
 def rel_err(got, ref, floor_frac=1e-3):
     """Per-output error relative to |ref| + floor_frac * max|ref| of the row."""
     got = np.atleast_2d(got)

@@ -1,20 +1,22 @@
 """Precision study of the 16-bit contraction variants on the full-size photometric
-workload: 10 240 seeded parameter vectors (ten launches of 1024) against the FP64
-oracle.  Per-band relative error (median / p99 / max, with the 1e-3 row floor) and
-|dlogL| are printed for every variant; the hi + residual paths (three MFMA passes)
+workload against the FP64 oracle: 10 240 seeded prior draws (ten launches of 1024)
+and one launch of 1024 small perturbations of the vector that made the data, where
+the logL bound matters most.  Per-band relative error (median / p99 / max, with the
+1e-3 row floor) and |dlogL| are printed for every variant.  The variants that carry a
+weight residual (FP16 and BF16 with three MFMA passes, FP16 with two: W_h H + W_l H)
 must meet 2e-3 per band and |dlogL| <= 0.05 wherever the fit is within reach of the
 data (chi^2 per band <= 100, see the reading of the logL bound in the design notes);
-over all vectors the relative logL error must stay below 1e-4 for FP16 and 1e-3 for
-BF16 (hi + residual pairs carry 22 and 16 significant bits; the FP32 path's own worst
-case is a few 1e-5: bands where the model is a tiny fraction of its row but many sigma
-from the data)."""
+over all vectors the relative logL error must stay below 1e-4 for FP16 three-pass and
+1e-3 for the others (hi + residual pairs carry 22 and 16 significant bits; the FP32
+path's own worst case is a few 1e-5: bands where the model is a tiny fraction of its
+row but many sigma from the data)."""
 import sys
 import time
 
 import numpy as np
 import pytest
 
-from helpers import make_case, rel_err
+from helpers import make_case, near_truth, rel_err
 from oracle import model as om
 from synth import workloads as wl
 
@@ -26,7 +28,7 @@ if not torch.cuda.is_available():
 
 import paper_2609_30145_amd as sps  # noqa: E402
 
-N_LAUNCH = 10
+N_LAUNCH = 11          # ten launches of prior draws, one of perturbed truth
 VARIANTS = ["fp32", "fp16", "bf16", "fp16_wl", "bf16_wl", "fp16_hr", "bf16_hr", "fp16_1pass", "bf16_1pass"]
 
 
@@ -40,7 +42,8 @@ def study():
     cfg = wl.CONFIGS["c1"]
     case = make_case(cfg)
     B = cfg.batch
-    theta = np.concatenate([wl.make_theta(cfg, B, seed=7000 + i) for i in range(N_LAUNCH)])
+    theta = np.concatenate([wl.make_theta(cfg, B, seed=7000 + i) for i in range(N_LAUNCH - 1)]
+                           + [near_truth(cfg, case["theta_true"], B, 77)])
     say(f"precision study: {theta.shape[0]} vectors, oracle on the host ...")
     t0 = time.time()
     m_ref = np.concatenate([om.predict(case["olib"], case["obs"], theta[i * B:(i + 1) * B]) for i in range(N_LAUNCH)])
@@ -61,12 +64,14 @@ def study():
         out[v] = (np.concatenate(lls), np.concatenate(ms))
     resid = (obs.data[None, :] - m_ref) / obs.sigma[None, :]
     chi2_band = np.mean(resid ** 2, axis=1)
-    return ll_ref, m_ref, out, chi2_band
+    fit = np.zeros(theta.shape[0], dtype=bool)
+    fit[(N_LAUNCH - 1) * B:] = True
+    return ll_ref, m_ref, out, chi2_band, fit
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_precision_variant(study, variant):
-    ll_ref, m_ref, out, chi2_band = study
+    ll_ref, m_ref, out, chi2_band, fit = study
     ll, m = out[variant]
     e = rel_err(m, m_ref)
     dll = np.abs(ll - ll_ref)
@@ -74,12 +79,14 @@ def test_precision_variant(study, variant):
     rel_ll = dll / np.abs(ll_ref)
     say(f"{variant:11s} band rel err median {np.median(e):.2e} p99 {np.quantile(e, 0.99):.2e} max {e.max():.2e} | "
         f"|dlogL| (chi2/band<=100, n={near.sum()}) median {np.median(dll[near]) if near.any() else 0:.2e} "
-        f"max {dll[near].max() if near.any() else 0:.2e} | all: max |dlogL| {dll.max():.2e} "
-        f"max rel {rel_ll.max():.2e}")
+        f"max {dll[near].max() if near.any() else 0:.2e} | perturbed truth (chi2/band "
+        f"{chi2_band[fit].min():.2f}-{chi2_band[fit].max():.2f}) max {dll[fit].max():.2e} | "
+        f"all: max |dlogL| {dll.max():.2e} max rel {rel_ll.max():.2e}")
+    assert near[fit].all()
     if variant == "fp32":
         assert e.max() < 1e-5
         assert rel_ll.max() < 1e-4
-    elif variant in ("fp16", "bf16"):
+    elif variant in ("fp16", "bf16", "fp16_wl"):
         assert e.max() < 2e-3
-        assert (not near.any()) or dll[near].max() <= 0.05
+        assert dll[near].max() <= 0.05
         assert rel_ll.max() < (1e-4 if variant == "fp16" else 1e-3)

@@ -14,7 +14,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_objects, make_case, rel_err
+from helpers import gpu_objects, make_case, near_truth, rel_err
 from oracle import model as om
 from synth import workloads as wl
 
@@ -33,22 +33,6 @@ N_PRIOR, N_NEAR = 128, 128
 def say(m):
     print(m, flush=True)
     sys.stdout.flush()
-
-
-def near_truth(cfg, theta_true, n, seed):
-    """Perturbations of the data-generating vector: 1 % in mass, the dust optical depths
-    and the SFH bin masses, 0.01 in the dust slope and the gas parameters."""
-    rng = np.random.default_rng(seed)
-    cols = wl.theta_columns(cfg.n_sfh, cfg.n_zh)
-    th = np.repeat(theta_true, n, axis=0)
-    th[:, cols["logmass"]] += 0.004 * rng.normal(size=n)
-    for c in ("tau_bc", "tau_diff"):
-        th[:, cols[c]] = np.clip(th[:, cols[c]] * (1.0 + 0.01 * rng.normal(size=n)), 0.0, 4.0)
-    for c in ("delta", "gas_logz", "gas_logu"):
-        th[:, cols[c]] += 0.01 * rng.normal(size=n)
-    s0 = cols["sfh"]
-    th[:, s0:s0 + cfg.n_sfh] *= 1.0 + 0.01 * rng.normal(size=(n, cfg.n_sfh))
-    return th
 
 
 @pytest.fixture(scope="module")
