@@ -13,7 +13,8 @@ MFMA pass (W_h L_h + W_l L_h), the cheapest variant that meets 2e-3 per band and
 which spectra need, FP32 and BF16 are timed beside it.
 
 Prints one JSON line.  The roofline entry is for the library contraction, timed
-with HIP events recorded around that kernel on the stream it runs on.
+live during the timed steps with HIP events that the kernel's own dispatch stamps
+(start and end) on the stream it runs on.
 """
 from __future__ import annotations
 

@@ -208,10 +208,12 @@ sps_status sps_logl_grad(const sps_library *lib, sps_obs *obs, const double *the
                          int32_t precision, double *logl_dev, double *grad_dev, void *hip_stream);
 
 /* Timing of the library-contraction kernel.  When enabled, every hot call on
- * this observation brackets its contraction kernel with HIP events on the
- * caller's stream; sps_obs_contract_timing synchronises those events and
- * returns the summed milliseconds, the number of launches and the executed
- * K-tile count (for executed-flop accounting), then resets the counters. */
+ * this observation hands a pair of HIP events to the contraction kernel's own
+ * dispatch on the caller's stream (hipExtLaunchKernel), which stamps the
+ * kernel's start and end without a marker between kernels;
+ * sps_obs_contract_timing synchronises those events and returns the summed
+ * milliseconds, the number of launches and the executed K-tile count (for
+ * executed-flop accounting), then resets the counters. */
 sps_status sps_obs_enable_timing(sps_obs *obs, int32_t enable);
 sps_status sps_obs_contract_timing(sps_obs *obs, double *ms_total, int64_t *launches,
                                    int64_t *executed_k_tiles, int64_t *dense_k_tiles);

@@ -289,8 +289,9 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
     }
   }
 
-  if (prep_smem_bytes(g, 0) > 160 * 1024)
-    return fail(SPS_E_SHAPE, "library too large for the per-point weight builder (%zu bytes of LDS)", prep_smem_bytes(g, 0));
+  const size_t prep_lds = std::max(prep_smem_bytes(g, 0), prep_smem_bytes(g, 3));
+  if (prep_lds > 160 * 1024)
+    return fail(SPS_E_SHAPE, "library too large for the per-point weight builder (%zu bytes of LDS)", prep_lds);
   // ---- device copies
   DeviceBuffers &mem = L->mem;
   bool ok = true;
@@ -324,7 +325,22 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   g.gl_w = (const double *)up(glw.data(), glw.size() * 8);
   L->kpos_d = (int *)up(kpos.data(), kpos.size() * 4);
   int *ksrc_d = (int *)up(ksrc.data(), ksrc.size() * 4);
-  double *Q = (double *)al((size_t)std::max(1, nf * nz * ny) * 8);
+  // the weight builder's node tables in one block, in its LDS order (DevLib::prep_tab);
+  // with lines on, the photon rates Q close the block and are written by the packing
+  std::vector<double> ptab((size_t)prep_tab_len(g), 0.0);
+  {
+    size_t o = 0;
+    for (int m = 0; m < nz; ++m) ptab[o++] = d->logz[m];
+    for (int m = 0; m < nf; ++m) ptab[o++] = afe[m];
+    for (int a = 0; a < na; ++a) ptab[o++] = lo[a];
+    for (int a = 0; a < na; ++a) ptab[o++] = hi[a];
+    for (int m = 0; m < g.n_zg; ++m) ptab[o++] = d->zg_nodes[m];
+    for (int m = 0; m < g.n_u; ++m) ptab[o++] = d->u_nodes[m];
+  }
+  double *ptab_d = (double *)up(ptab.data(), ptab.size() * 8);
+  g.prep_tab = ptab_d;
+  const size_t q_off = (size_t)nz + nf + 2 * na + g.n_zg + g.n_u;
+  double *Q = nl > 0 ? (ptab_d ? ptab_d + q_off : nullptr) : (double *)al((size_t)std::max(1, nf * nz * ny) * 8);
   g.Q = Q;
   if (nl > 0) {
     // stored as [zg][u][line][age]: for one (Z_gas, U) corner the (line, age) slab is contiguous
@@ -346,6 +362,8 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   }
   int *kexp = (int *)al((size_t)K_pad * 4);
   g.kexp = kexp;
+  int16_t *kexp16 = (int16_t *)al((size_t)K_pad * 2);
+  g.kexp16 = kexp16;
   const size_t KN = (size_t)K_pad * Np;
   PackLaunch pk;
   memset(&pk, 0, sizeof pk);
@@ -388,6 +406,7 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   pk.ksrc = ksrc_d;
   pk.neb_mask = nl > 0;
   pk.kexp = kexp;
+  pk.kexp16 = kexp16;
   pk.Q = Q;
   pk.wave = g.wave_d;
   (void)hipGetLastError();   // drop a stale code from an unrelated earlier HIP call of this thread
@@ -672,9 +691,10 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   cl.F = w.F;
   cl.Yatt = grad ? w.Yatt : nullptr;
   cl.precision = prec;
-  if (e == hipSuccess && timing_obs) e = timing_obs->timing_begin(s, B_pad / MT, g.K_pad / (kKTile * tf));
+  cl.ev_start = cl.ev_stop = nullptr;
+  if (e == hipSuccess && timing_obs)
+    e = timing_obs->timing_events(B_pad / MT, g.K_pad / (kKTile * tf), &cl.ev_start, &cl.ev_stop);
   if (e == hipSuccess) e = launch_contract(g, cl, s);
-  if (e == hipSuccess && timing_obs) e = timing_obs->timing_end(s);
   ProjectLaunch pj;
   pj.obs_table = obs_table;
   pj.rows = w.rows;

@@ -64,8 +64,20 @@ struct DevLib {
   const uint16_t *Hb, *Rb;           // [N_pad][K_pad] bf16 hi / residual
   const uint16_t *Hh, *Rh;           // [N_pad][K_pad] fp16 hi / residual
   const int *kexp;                   // [K_pad] row exponent e_k of the 16-bit copies
+  const int16_t *kexp16;             // the same as 16-bit integers (weight builder)
   const double *gl_u, *gl_w;         // [n_gl] composite Gauss-Legendre on [0,1]
+  // The weight builder's node tables in one block, in the order of its LDS layout:
+  // logz[n_z], afe[n_afe] (0 when n_afe = 1), cell_lo[n_age], cell_hi[n_age],
+  // zg[n_zg], un[n_u], Q[n_afe][n_z][n_young] (lines only), padded to an even count.
+  const double *prep_tab;
 };
+
+// Length in doubles of DevLib::prep_tab.
+__host__ __device__ inline int prep_tab_len(const DevLib &lib) {
+  const int nq = lib.n_line > 0 ? lib.n_afe * lib.n_z * lib.n_young : 0;
+  const int n = lib.n_z + lib.n_afe + 2 * lib.n_age + lib.n_zg + lib.n_u + nq;
+  return n + (n & 1);
+}
 
 // Observation descriptor in device memory.
 struct DevObs {
@@ -94,8 +106,29 @@ struct PointRow {
   int b;        // original batch index
   int obs;      // observation slot
   int kind;     // observation kind
+  int seg0;     // photometry on a log-uniform grid: first rest-frame pixel under the filters
+  int seg_n;    //   and the number of pixels from there (phot_span)
   int pad;
 };
+
+// Fractional log index of the rest wavelength of an observed filter node, on a
+// log-uniform grid: ln(lambda_obs) / dln(lambda) + ui0, ui0 = -(ln(1+z) + ln lambda_0) /
+// dln(lambda).  One fused multiply-add, so that every caller rounds it the same way.
+__device__ __forceinline__ double phot_u(const DevLib &lib, double fwln, double ui0) {
+  return __fma_rn(fwln, lib.inv_dlnw, ui0);
+}
+__device__ __forceinline__ double phot_ui0(const DevLib &lib, double z) {
+  return -(log1p(z) + lib.lnw0) * lib.inv_dlnw;
+}
+// Rest-frame pixels [seg0, seg0 + seg_n) that the filter nodes of an observation at
+// redshift z interpolate between: from the bracketing interval of the shortest node to
+// that of the longest, clamped to the grid.
+__device__ __forceinline__ void phot_span(const DevLib &lib, double fwln_min, double fwln_max, double z, int &seg0,
+                                          int &seg_n) {
+  const double ui0 = phot_ui0(lib, z);
+  seg0 = min(max((int)floor(phot_u(lib, fwln_min, ui0)), 0), lib.N - 2);
+  seg_n = min(max((int)floor(phot_u(lib, fwln_max, ui0)), 0), lib.N - 2) + 2 - seg0;
+}
 
 // ---------------------------------------------------------------- contraction tiles
 // Block -> (M tile, N tile) for the library contractions.  The hardware deals

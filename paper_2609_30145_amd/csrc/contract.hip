@@ -3,6 +3,8 @@
 // so the birth-cloud transmission is applied to the accumulator once, between the
 // young and the old K tiles; K tiles that are zero for every row of an M tile are
 // skipped through the per-M-tile active list.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -347,13 +349,16 @@ hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStrea
   const int n_mt = cl.B_pad / MT;
   if (cl.precision == 0) {
     a.LTa = lib.LT64;
-    hipLaunchKernelGGL(k_contract_f64, dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
+    hipExtLaunchKernelGGL(k_contract_f64, dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, cl.ev_start, cl.ev_stop, 0,
+                          a);
   } else if (cl.precision == 1) {
     a.LTa = lib.LT32;
     if (cl.Yatt)
-      hipLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, true, 2>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
+      hipExtLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, true, 2>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s,
+                            cl.ev_start, cl.ev_stop, 0, a);
     else
-      hipLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, false, 2>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s, a);
+      hipExtLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, false, 2>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s,
+                            cl.ev_start, cl.ev_stop, 0, a);
   } else {
     return launch_contract16_impl(lib, cl, n_mt, s);
   }

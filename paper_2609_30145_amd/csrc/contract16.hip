@@ -5,6 +5,8 @@
 // W_h H (main pass), W_h R and W_l H (one refinement pass over the residual terms)
 // accumulate into one FP32 accumulator; the dropped W_l R term is second order.  The
 // reduced variants take W_h H alone, W_h H + W_h R, or W_h H + W_l H.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -207,8 +209,8 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
 
 
 template <bool BF, int PASSES>
-static void launch16(const ContractArgs16 &a, int n_mt, int N_pad, hipStream_t s) {
-  hipLaunchKernelGGL((k_contract_16<BF, PASSES>), dim3(n_mt * (N_pad / 64)), dim3(256), 0, s, a);
+static void launch16(const ContractArgs16 &a, int n_mt, int N_pad, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  hipExtLaunchKernelGGL((k_contract_16<BF, PASSES>), dim3(n_mt * (N_pad / 64)), dim3(256), 0, s, e0, e1, 0, a);
 }
 
 hipError_t launch_contract16_impl(const DevLib &lib, const ContractLaunch &cl, int n_mt, hipStream_t s) {
@@ -235,14 +237,14 @@ hipError_t launch_contract16_impl(const DevLib &lib, const ContractLaunch &cl, i
   // the gradient pass (which needs the young part) runs on the FP32 / FP64 paths only
   if (!a.H || !a.R || Yatt) return hipErrorInvalidValue;
   switch (precision) {
-    case 2: launch16<true, 3>(a, n_mt, lib.N_pad, s); break;
-    case 3: launch16<false, 3>(a, n_mt, lib.N_pad, s); break;
-    case 4: launch16<true, 1>(a, n_mt, lib.N_pad, s); break;
-    case 5: launch16<false, 1>(a, n_mt, lib.N_pad, s); break;
-    case 6: launch16<true, 2>(a, n_mt, lib.N_pad, s); break;
-    case 7: launch16<false, 2>(a, n_mt, lib.N_pad, s); break;
-    case 8: launch16<true, 4>(a, n_mt, lib.N_pad, s); break;
-    case 9: launch16<false, 4>(a, n_mt, lib.N_pad, s); break;
+    case 2: launch16<true, 3>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 3: launch16<false, 3>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 4: launch16<true, 1>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 5: launch16<false, 1>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 6: launch16<true, 2>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 7: launch16<false, 2>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 8: launch16<true, 4>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 9: launch16<false, 4>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -36,6 +36,7 @@ struct ContractLaunch {
   void *F;                   // [B_pad][N_pad] attenuated rest-frame spectrum (float or double)
   void *Yatt;                // optional [B_pad][N_pad]: young part after both attenuations
   int precision;             // sps_precision value
+  hipEvent_t ev_start, ev_stop;   // timing: events that take the kernel's own start and end, or NULL
 };
 // M tile used by the contraction of a precision (the occupancy list granularity)
 int contract_mtile(int precision);
@@ -70,6 +71,7 @@ struct PackLaunch {
   float *LT32, *L32n;
   uint16_t *Hb, *Rb, *Hh, *Rh;
   int *kexp;
+  int16_t *kexp16;
   double *Q;                 // [n_afe][n_z][n_young]
   const double *wave;        // [N]
 };

@@ -49,6 +49,7 @@ __global__ void __launch_bounds__(256) k_rowstats(DevLib lib, PackLaunch pk) {
   }
   if (tid == 0) {
     pk.kexp[k] = vmax > 0.0 ? ilogb(vmax) - 14 : 0;
+    pk.kexp16[k] = (int16_t)pk.kexp[k];   // |ilogb| of a double is below 1100
     if (src >= 0) {
       const int a = src % lib.n_age, zm = src / lib.n_age;
       if (a < lib.n_young) pk.Q[(size_t)zm * lib.n_young + a] = kLsun * kAng_cm * red[0] / (kHplanck * kC_cms);

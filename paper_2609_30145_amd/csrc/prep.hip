@@ -128,12 +128,13 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // LDS layout of k_prep, in 8-byte words (the weight row and the line terms are
-// FP64 for the FP64 path and FP32 otherwise).
+// FP64 for the FP64 path and FP32 otherwise).  The node tables (logz .. Q) are one
+// contiguous run in the order of DevLib::prep_tab, so that they arrive in one copy.
 struct PrepSmem {
-  int th, logz, afe, clo, chi, zg, un, Q, edges, zt, zj, wq, wacc, lt, total;
-  __host__ __device__ PrepSmem(const DevLib &lib, bool f64) {
+  int th, logz, afe, clo, chi, zg, un, Q, edges, mr, zt, zj, wq, ke, wacc, lt, total;
+  __host__ __device__ PrepSmem(const DevLib &lib, int mode) {
+    const bool f64 = mode == 0, w16 = mode >= 2;
     const int acc = f64 ? 8 : 4;
-    const int nq = lib.n_line > 0 ? lib.n_afe * lib.n_z * lib.n_young : 0;
     int o = 0;
     th = o;    o += lib.P;
     logz = o;  o += lib.n_z;
@@ -142,11 +143,14 @@ struct PrepSmem {
     chi = o;   o += lib.n_age;
     zg = o;    o += lib.n_zg;
     un = o;    o += lib.n_u;
-    Q = o;     o += nq;
+    Q = o;
+    o = logz + prep_tab_len(lib);                          // Q and the block's padding
     edges = o; o += lib.n_sfh + 1;
+    mr = o;    o += lib.n_sfh;                             // bin mass per unit time
     zt = o;    o += lib.n_sfh;
     zj = o;    o += (lib.n_sfh + 1) / 2;                  // int
     wq = o;    o += lib.n_line > 0 ? lib.n_young : 0;
+    ke = o;    o += w16 ? lib.K_pad / 4 : 0;              // int16 row exponents
     wacc = o;  o += (lib.K_pad * acc + 7) / 8;
     lt = o;    o += (lib.n_line * lib.n_young * acc + 7) / 8;
     total = o;
@@ -154,31 +158,36 @@ struct PrepSmem {
 };
 
 // One workgroup (4 waves) per sorted row:
-//   A1  theta, node tables, cell bounds and photon rates to LDS; weight row cleared;
-//       Gauss-Legendre partial sums of D_C
-//   A2  wave 0: t_univ and the bin edges; the other waves: the bin metallicities and
-//       their bracketing nodes; then all waves: the interpolated line terms 10^Lhat
-//       (they depend on the gas parameters only)
+//   A1  every global load of the phase in flight together: theta, the node-table block,
+//       the 16-bit row exponents, the first batch keys, the quadrature nodes; then the
+//       point's rank among the batch keys, the Gauss-Legendre partial sums of D_C
+//       (waves 0-2) and t_univ with the SFH bin edges (wave 3)
+//   A2  the bin metallicities and their bracketing nodes, the bin mass per unit time;
+//       the interpolated line terms 10^Lhat (they depend on the gas parameters only)
 //   B   step-scheme overlap weights, one thread per SSP age (single writer per slot)
-//   C   photon rate per young age, then the line luminosities
-//   D   the row in the contraction's format with its K-tile occupancy bits; the
-//       per-point row (redshift, distances, scales).
+//   C   photon-weighted young mass per age, then the line luminosities
+//   D   the row in the contraction's format with its K-tile occupancy bits, eight
+//       consecutive K entries per thread; the per-point row (redshift, distances, scales).
 template <int MODE>
 __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   using Acc = typename std::conditional<MODE == W_F64, double, float>::type;
+  constexpr bool W16 = MODE == W_BF16 || MODE == W_F16;
   extern __shared__ double smem[];
-  const PrepSmem L(lib, MODE == W_F64);
+  const PrepSmem L(lib, MODE);
   const int K_pad = lib.K_pad, na = lib.n_age, nz = lib.n_z, nf = lib.n_afe, ny = lib.n_young;
   const int n_sfh = lib.n_sfh, nl = lib.n_line;
   double *s_th = smem + L.th, *s_logz = smem + L.logz, *s_afe = smem + L.afe;
   double *s_clo = smem + L.clo, *s_chi = smem + L.chi, *s_zg = smem + L.zg, *s_un = smem + L.un;
-  double *s_Q = smem + L.Q, *s_edges = smem + L.edges, *s_zt = smem + L.zt, *s_wq = smem + L.wq;
+  double *s_Q = smem + L.Q, *s_edges = smem + L.edges, *s_mr = smem + L.mr, *s_zt = smem + L.zt;
+  double *s_wq = smem + L.wq;
   int *s_zj = (int *)(smem + L.zj);
+  const int16_t *s_ke = (const int16_t *)(smem + L.ke);
   Acc *wacc = (Acc *)(smem + L.wacc);
   Acc *s_lt = (Acc *)(smem + L.lt);
   __shared__ double s_part[4];
   __shared__ double s_tu;
   __shared__ uint32_t s_bits[64];
+  __shared__ int s_rank[4];
 
   // workgroup b takes point b (caller's order); its row r is the point's rank in the
   // key order (ties by index).  Workgroups past B clear the padding rows.
@@ -204,67 +213,54 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     return;
   }
 
-  // ---- A1 (with the rank): the point's tables into LDS, its rank among the batch keys,
-  // and D_C, behind one barrier
+  // ---- A1.  Loads are issued from clamped indices, unconditionally, so that all of them
+  // are in flight before the first use; sizes beyond the unrolled counts take the loops
+  // that follow each store.
+  constexpr int UT = 2, UB = 4, UK = 4, UQ = 4;
   const double *th = a.theta + (size_t)b * a.P;
-  for (int c = tid; c < a.P; c += 256) s_th[c] = th[c];
-  for (int m = tid; m < nz; m += 256) s_logz[m] = lib.logz[m];
-  for (int m = tid; m < nf; m += 256) s_afe[m] = nf > 1 ? lib.afe[m] : 0.0;
-  for (int g = tid; g < na; g += 256) {
-    s_clo[g] = lib.cell_lo[g];
-    s_chi[g] = lib.cell_hi[g];
-  }
-  if (nl > 0) {
-    for (int m = tid; m < lib.n_zg; m += 256) s_zg[m] = lib.zg[m];
-    for (int m = tid; m < lib.n_u; m += 256) s_un[m] = lib.un[m];
-    for (int q = tid; q < nf * nz * ny; q += 256) s_Q[q] = lib.Q[q];
-  }
-  for (int k = tid; k < K_pad; k += 256) wacc[k] = (Acc)0;
-  if (tid < 64) s_bits[tid] = 0u;
-  __shared__ int s_rank[4];
-  {
-    const double my = a.keys[b];
-    int c = 0;
-    for (int j0 = tid; j0 < a.B; j0 += 256 * 4) {   // four key loads per thread in flight
-      double kq[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = j0 + 256 * u;
-        kq[u] = j < a.B ? a.keys[j] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = j0 + 256 * u;
-        c += j < a.B && ((kq[u] < my) || (kq[u] == my && j < b));
-      }
-    }
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if (lane == 0) s_rank[wv] = c;
-  }
-  // cosmology (Sec. 2.6): D_C by composite Gauss-Legendre in u = (1+z')^-1/2, where
-  // the integrand 2 / sqrt(Om + OL u^6) is smooth
   const double z = th[TH_ZRED];
+  const int slot = a.point_obs ? a.point_obs[b] : 0;
+  const int n_gl = lib.n_gl, gi = min(tid, n_gl - 1);
+  const double gu = lib.gl_u[gi], gw = lib.gl_w[gi];
+  const int P = a.P, nt2 = prep_tab_len(lib) >> 1, nk8 = K_pad >> 3;
+  const double2 *tab2 = (const double2 *)lib.prep_tab;
+  const uint4 *ke4 = (const uint4 *)lib.kexp16;
+  double vt[UT], kq[UQ];
+  double2 vb[UB];
+  uint4 vk[UK];
+#pragma unroll
+  for (int u = 0; u < UT; ++u) vt[u] = th[min(tid + 256 * u, P - 1)];
+#pragma unroll
+  for (int u = 0; u < UB; ++u) vb[u] = tab2[min(tid + 256 * u, nt2 - 1)];
+  if (W16) {
+#pragma unroll
+    for (int u = 0; u < UK; ++u) vk[u] = ke4[min(tid + 256 * u, nk8 - 1)];
+  }
+#pragma unroll
+  for (int u = 0; u < UQ; ++u) kq[u] = a.keys[min(tid + 256 * u, a.B - 1)];
+  const double my = a.keys[b];
+
+  // cosmology (Sec. 2.6): D_C by composite Gauss-Legendre in u = (1+z')^-1/2, where
+  // the integrand 2 / sqrt(Om + OL u^6) is smooth (waves 0-2); t_univ in closed form
+  // and the SFH edges rescaled to it (App. B): T_0 = 0, T_1 = T1, T_n = t_univ,
+  // log-uniform in between (wave 3)
   const double Om = lib.Om, OL = 1.0 - lib.Om;
   const double u0 = 1.0 / sqrt(1.0 + z);
-  {
+  if (wv < 3) {
     double part = 0.0;
-    for (int i = tid; i < lib.n_gl; i += 256) {
+    if (tid < n_gl) {
+      const double u = u0 + (1.0 - u0) * gu;
+      const double u2 = u * u;
+      part = gw * 2.0 / sqrt(Om + OL * u2 * u2 * u2);
+    }
+    for (int i = tid + 192; i < n_gl; i += 192) {
       const double u = u0 + (1.0 - u0) * lib.gl_u[i];
       const double u2 = u * u;
       part += lib.gl_w[i] * 2.0 / sqrt(Om + OL * u2 * u2 * u2);
     }
     part = wave_sum(part);
     if (lane == 0) s_part[wv] = part;
-  }
-  __syncthreads();
-  const int r = (s_rank[0] + s_rank[1]) + (s_rank[2] + s_rank[3]);
-  const size_t rowoff = (size_t)r * K_pad;
-  const double dc = kC_kms / lib.H0 * (1.0 - u0) * ((s_part[0] + s_part[1]) + (s_part[2] + s_part[3])) * kMpc_cm;
-
-  // ---- A2
-  if (wv == 0) {
-    // t_univ in closed form; SFH edges rescaled to it (App. B, Sec. 2.6): T_0 = 0,
-    // T_1 = T1, T_n = t_univ, log-uniform in between
+  } else {
     // (1+z)^{-3/2} by a square root and asinh(x) = ln(x + sqrt(x^2 + 1)) for x > 0: a
     // shorter chain of double-precision operations than the library pow and asinh
     const double tH_yr = kMpc_km / lib.H0 / kYr_s;
@@ -280,14 +276,83 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       else T = lib.T1 * exp(lnR * (double)(i - 1) / (double)(n_sfh - 1));
       s_edges[i] = T;
     }
-    if (lane == 0) s_tu = tu;
-  } else {
-    // bin metallicity from the enrichment history (Sec. 2.2.2): nodes and bin centres
-    // are both log-uniform from T1 to t_univ, so the interpolation weight in ln T is
-    // fixed in the normalised coordinate (bin i >= 1 at (i - 1/2)/(n_sfh - 1), node k at
-    // k/(n_zh - 1)); the first bin (centre T1/2) takes node 0
+    if (lane == 0) {
+      s_tu = tu;
+      s_part[3] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UT; ++u)
+    if (tid + 256 * u < P) s_th[tid + 256 * u] = vt[u];
+  for (int c = tid + 256 * UT; c < P; c += 256) s_th[c] = th[c];
+#pragma unroll
+  for (int u = 0; u < UB; ++u) {
+    const int i = tid + 256 * u;
+    if (i < nt2) {
+      s_logz[2 * i] = vb[u].x;
+      s_logz[2 * i + 1] = vb[u].y;
+    }
+  }
+  for (int i = tid + 256 * UB; i < nt2; i += 256) {
+    const double2 v = tab2[i];
+    s_logz[2 * i] = v.x;
+    s_logz[2 * i + 1] = v.y;
+  }
+  if (W16) {
+    uint2 *ke2 = (uint2 *)(smem + L.ke);
+#pragma unroll
+    for (int u = 0; u < UK; ++u) {
+      const int i = tid + 256 * u;
+      if (i < nk8) {
+        ke2[2 * i] = make_uint2(vk[u].x, vk[u].y);
+        ke2[2 * i + 1] = make_uint2(vk[u].z, vk[u].w);
+      }
+    }
+    for (int i = tid + 256 * UK; i < nk8; i += 256) {
+      const uint4 v = ke4[i];
+      ke2[2 * i] = make_uint2(v.x, v.y);
+      ke2[2 * i + 1] = make_uint2(v.z, v.w);
+    }
+  }
+  for (int k = tid; k < K_pad; k += 256) wacc[k] = (Acc)0;
+  if (tid < 64) s_bits[tid] = 0u;
+  {
+    int c = 0;
+#pragma unroll
+    for (int u = 0; u < UQ; ++u) {
+      const int j = tid + 256 * u;
+      c += j < a.B && ((kq[u] < my) || (kq[u] == my && j < b));
+    }
+    for (int j0 = tid + 256 * UQ; j0 < a.B; j0 += 256 * 4) {   // four key loads per thread in flight
+      double kk[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) kk[u] = a.keys[min(j0 + 256 * u, a.B - 1)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + 256 * u;
+        c += j < a.B && ((kk[u] < my) || (kk[u] == my && j < b));
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane == 0) s_rank[wv] = c;
+  }
+  __syncthreads();
+  const int r = (s_rank[0] + s_rank[1]) + (s_rank[2] + s_rank[3]);
+  const size_t rowoff = (size_t)r * K_pad;
+  const double dc = kC_kms / lib.H0 * (1.0 - u0) * ((s_part[0] + s_part[1]) + (s_part[2] + s_part[3])) * kMpc_cm;
+  // the point's observation kind and filter span, requested here and first used in
+  // phase C and at the end
+  const DevObs *obp = a.obs_table + slot;
+  const int kind = obp->kind;
+  const double fw_min = obp->fwln_min, fw_max = obp->fwln_max;
+
+  // ---- A2: bin metallicity from the enrichment history (Sec. 2.2.2): nodes and bin
+  // centres are both log-uniform from T1 to t_univ, so the interpolation weight in ln T
+  // is fixed in the normalised coordinate (bin i >= 1 at (i - 1/2)/(n_sfh - 1), node k
+  // at k/(n_zh - 1)); the first bin (centre T1/2) takes node 0
+  {
     const double *zh = s_th + TH_NSCALAR + n_sfh;
-    for (int i = tid - 64; i < n_sfh; i += 192) {
+    for (int i = tid; i < n_sfh; i += 256) {
       double zeta;
       if (lib.n_zh == 0) {
         zeta = s_th[TH_LOGZSOL];
@@ -305,6 +370,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       if (nz > 1) split_lds(s_logz, nz, zeta, j, t);
       s_zj[i] = j;
       s_zt[i] = t;
+      s_mr[i] = s_th[TH_NSCALAR + i] / (s_edges[i + 1] - s_edges[i]);
     }
   }
   if (nl > 0) {
@@ -401,10 +467,9 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       i = l;
     }
     for (; i < n_sfh && s_edges[i] < hi; ++i) {
-      const double Ti = s_edges[i], Tj = s_edges[i + 1];
-      const double ov = fmin(hi, Tj) - fmax(lo, Ti);
+      const double ov = fmin(hi, s_edges[i + 1]) - fmax(lo, s_edges[i]);
       if (ov <= 0.0) continue;
-      const double w = s_th[TH_NSCALAR + i] * ov / (Tj - Ti);
+      const double w = s_mr[i] * ov;
       const int j = s_zj[i];
       const double t = s_zt[i];
       for (int q = 0; q < (nf > 1 ? 2 : 1); ++q) {
@@ -422,14 +487,22 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   __syncthreads();
 
   // ---- C: nebular lines (App. C): L_l = sum_a 10^Lhat_l(a) sum_{alpha,m} W Q
-  const int slot = a.point_obs ? a.point_obs[b] : 0;
-  const int kind = a.obs_table[slot].kind;
   if (nl > 0) {
-    for (int ag = tid; ag < ny; ag += 256) {
+    // photon-weighted young mass per age: eight lanes per age, each over a strided share
+    // of the (alpha, Z) nodes, combined by a fixed butterfly
+    const int nm = nf * nz;
+    for (int g0 = 0; g0 < ny; g0 += 32) {
+      const int ag = g0 + (tid >> 3), c = tid & 7;
       double s = 0.0;
-      for (int ia = 0; ia < nf; ++ia)
-        for (int m = 0; m < nz; ++m) s += (double)wacc[kpos_of(lib, ia, m, ag)] * s_Q[(ia * nz + m) * ny + ag];
-      s_wq[ag] = s;
+      if (ag < ny)
+        for (int q = c; q < nm; q += 8) {
+          const int ia = q / nz, m = q - ia * nz;
+          s += (double)wacc[kpos_of(lib, ia, m, ag)] * s_Q[q * ny + ag];
+        }
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      s += __shfl_xor(s, 4);
+      if (ag < ny && c == 0) s_wq[ag] = s;
     }
     __syncthreads();
     // two threads per line (adjacent lanes), each over half of the young ages
@@ -449,60 +522,89 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     __syncthreads();
   }
 
-  // ---- D: the row in the contraction's format (thread per K entry) and its K-tile
-  //      occupancy bits: a wave covers two 32-wide tiles per pass (ballot halves)
+  // ---- D: the row in the contraction's format and its K-tile occupancy bits.  A thread
+  //      takes eight consecutive K entries (one 16-byte run of a 16-bit plane); a wave
+  //      covers 512 entries, i.e. 16 tiles of 32, all in one word of the bit mask.
+  const int nk8d = K_pad >> 3;
   double wscale = 1.0;
   int eb = 0;
-  if (MODE == W_BF16 || MODE == W_F16) {
+  if (W16) {
     // W'_k = W_k 2^{e_k} (exact in FP32), kept in the LDS row; the row scale 2^{e_b}
     // puts max |W'| in [2^14, 2^15)
     float mx = 0.f;
-#pragma unroll 4
-    for (int k = tid; k < K_pad; k += 256) {
-      const float x = ldexpf((float)wacc[k], lib.kexp[k]);
-      wacc[k] = (Acc)x;
-      mx = fmaxf(mx, fabsf(x));
+    for (int c = tid; c < nk8d; c += 256) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 8 * c + e;
+        const float x = ldexpf((float)wacc[k], (int)s_ke[k]);
+        wacc[k] = (Acc)x;
+        mx = fmaxf(mx, fabsf(x));
+      }
     }
     double m2 = wave_max((double)mx);
-    __syncthreads();   // every thread has read the D_C partials
-    if (lane == 0) s_part[wv] = m2;
+    if (lane == 0) s_part[wv] = m2;   // the D_C partials were read before the A1 barrier
     __syncthreads();
     m2 = fmax(fmax(s_part[0], s_part[1]), fmax(s_part[2], s_part[3]));
     if (m2 > 0.0) eb = ilogb(m2) - 14;
     wscale = ldexp(1.0, eb);
   }
-  for (int k = tid; k < K_pad; k += 256) {   // K_pad is a multiple of 64: no partial waves
-    bool on;
+  for (int c = tid; c < nk8d; c += 256) {
+    const int k0 = 8 * c;
+    bool on = false;
     if (MODE == W_F64) {
-      const double x = (double)wacc[k];
-      ((double *)a.W)[rowoff + k] = x;
-      on = x != 0.0;
+      double x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        x[e] = (double)wacc[k0 + e];
+        on = on || x[e] != 0.0;
+      }
+      double2 *dst = (double2 *)((double *)a.W + rowoff + k0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dst[e] = make_double2(x[2 * e], x[2 * e + 1]);
     } else if (MODE == W_F32) {
-      const float x = (float)wacc[k];
-      ((float *)a.W)[rowoff + k] = x;
-      on = x != 0.f;
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        x[e] = (float)wacc[k0 + e];
+        on = on || x[e] != 0.f;
+      }
+      float4 *dst = (float4 *)((float *)a.W + rowoff + k0);
+      dst[0] = make_float4(x[0], x[1], x[2], x[3]);
+      dst[1] = make_float4(x[4], x[5], x[6], x[7]);
     } else {
       // hi + residual: x - hi is exact in FP32 (at most 13 significant bits)
-      const float x = ldexpf((float)wacc[k], -eb);
-      uint16_t h, l;
-      if (MODE == W_BF16) {
-        h = bf16_rne(x);
-        l = bf16_rne(x - bf16_to_f(h));
-      } else {
-        h = f16_rne(x);
-        l = f16_rne(x - f16_to_f(h));
+      uint32_t hw[4], lw[4];
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        uint16_t h[2], l[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const float x = ldexpf((float)wacc[k0 + e + q], -eb);
+          if (MODE == W_BF16) {
+            h[q] = bf16_rne(x);
+            l[q] = bf16_rne(x - bf16_to_f(h[q]));
+          } else {
+            h[q] = f16_rne(x);
+            l[q] = f16_rne(x - f16_to_f(h[q]));
+          }
+        }
+        hw[e >> 1] = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+        lw[e >> 1] = (uint32_t)l[0] | ((uint32_t)l[1] << 16);
+        on = on || (hw[e >> 1] | lw[e >> 1]) != 0u;
       }
-      ((uint16_t *)a.W)[w16_pos(r, k, K_pad >> 6)] = h;
-      ((uint16_t *)a.Wlo)[w16_pos(r, k, K_pad >> 6)] = l;
-      on = (h != 0) || (l != 0);
+      // eight consecutive entries of one row are contiguous in the fragment-tiled planes
+      const size_t p = w16_pos(r, k0, K_pad >> 6);
+      *(uint4 *)((uint16_t *)a.W + p) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+      *(uint4 *)((uint16_t *)a.Wlo + p) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
     }
     const unsigned long long bal = __ballot(on);
     if (lane == 0) {
-      const int t0 = (k - lane) / kKTile;   // first of the wave's two tiles
+      const int c0 = c;               // lane 0 holds the wave's first run
       uint32_t bits = 0u;
-      if (bal & 0xffffffffull) bits |= 1u << (t0 & 31);
-      if (bal >> 32) bits |= 1u << ((t0 + 1) & 31);
-      if (bits) atomicOr(&s_bits[t0 >> 5], bits);   // t0 even: both tiles share a word
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if ((bal >> (4 * i)) & 0xfull) bits |= 1u << i;
+      if (bits) atomicOr(&s_bits[c0 >> 7], bits << ((c0 >> 2) & 31));
     }
   }
   __syncthreads();
@@ -524,6 +626,9 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     pr.b = b;
     pr.obs = slot;
     pr.kind = kind;
+    pr.seg0 = 0;
+    pr.seg_n = 0;
+    if (kind == 0 && lib.log_uniform) phot_span(lib, fw_min, fw_max, z, pr.seg0, pr.seg_n);
     pr.pad = 0;
     a.rows[r] = pr;
   }
@@ -533,7 +638,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
 // Host launchers
 // ---------------------------------------------------------------------------------
 size_t prep_smem_bytes(const DevLib &lib, int mode) {
-  return sizeof(double) * (size_t)PrepSmem(lib, mode == W_F64).total;
+  return sizeof(double) * (size_t)PrepSmem(lib, mode).total;
 }
 
 hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, hipStream_t s) {

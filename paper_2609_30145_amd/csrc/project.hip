@@ -40,7 +40,7 @@ __device__ double sigma_inst_mode(int mode, double v, double lam) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
+__global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
   __shared__ double red[256];
   // LDS: per-line tables (spectra) and, on the FP32 path, a segment of the model row
   // (photometry: the pixels under the filters; spectra: the pixels under the LSF rows);
@@ -56,12 +56,28 @@ __global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
   const int r = blockIdx.x;
   const PointRow pr = a.rows[r];
   if (pr.b < 0) return;
-  const DevObs ob = a.obs_table[pr.obs];
   const int tid = threadIdx.x;
-  const double *th = a.theta + (size_t)pr.b * a.P;
-  const double z = pr.z, opz = 1.0 + z;
   const T *Fr = a.F + (size_t)r * a.N_pad;
   const int N = lib.N;
+  // FP32 photometry on a log-uniform rest grid: the model pixels under the filters (the
+  // rest-frame span of the nodes, from the weight builder) are requested first, before
+  // the observation's descriptor is read, sixteen loads per thread in flight
+  const bool fastp = sizeof(T) == 4 && lib.log_uniform && !a.gvec && pr.kind == 0 && pr.seg_n <= kSegMax;
+  if (fastp) {
+    float *seg = (float *)(sraw + kSegOff);
+    const int seg0 = pr.seg0, seg_n = pr.seg_n;
+    for (int k0 = tid; k0 < seg_n; k0 += 256 * 16) {
+      float v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = (float)Fr[seg0 + min(k0 + 256 * q, seg_n - 1)];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (k0 + 256 * q < seg_n) seg[k0 + 256 * q] = v[q];
+    }
+  }
+  const DevObs ob = a.obs_table[pr.obs];
+  const double *th = a.theta + (size_t)pr.b * a.P;
+  const double z = pr.z, opz = 1.0 + z;
 
   // noise-floor parameters (ln space), evaluated by every thread (no barrier)
   const double ns = (ob.noise_flags & 1) ? exp(th[TH_LOG_ERR_SCALE]) : 1.0;
@@ -99,52 +115,49 @@ __global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
     // On a log-uniform rest grid the bracketing interval follows from ln(lambda)
     // directly; a node within rounding of a grid point may take the neighbouring
     // interval, where the interpolation weight is within rounding of 0 or 1.
-    // FP32 path on a log-uniform rest grid: the model pixels under the filters (the
-    // rest-frame span of the nodes) are staged in LDS with one coalesced pass, then each
-    // wave takes whole bands, lanes over the band's nodes, and reduces them itself.  The
-    // weight linear in lambda on [w_k, w_k+1] is (e^{f d} - 1)/(e^d - 1), f the fractional
-    // log index; a node is inside the model grid when its log index lies in [0, N - 1].
-    const double ui0 = -(lnopz + lib.lnw0) * lib.inv_dlnw;   // log index = fwln * inv_dlnw + ui0
+    // FP32 path (fastp): each wave takes whole bands, lanes over the band's nodes, and
+    // reduces them itself.  The weight linear in lambda on [w_k, w_k+1] is
+    // (e^{f d} - 1)/(e^d - 1), f the fractional log index; a node is inside the model grid
+    // when its log index lies in [0, N - 1].
     // (the gradient pass keeps the generic path: its band sums are accumulated in FP64)
-    int seg0 = 0, seg_n = 0;
-    if (sizeof(T) == 4 && lib.log_uniform && !a.gvec) {
-      seg0 = min(max((int)floor(ob.fwln_min * lib.inv_dlnw + ui0), 0), N - 2);
-      seg_n = min(max((int)floor(ob.fwln_max * lib.inv_dlnw + ui0), 0), N - 2) + 2 - seg0;
-    }
-    if (sizeof(T) == 4 && lib.log_uniform && !a.gvec && seg_n <= kSegMax) {
-      float *seg = (float *)(sraw + kSegOff);
-      for (int k0 = tid; k0 < seg_n; k0 += 256 * 8) {   // eight loads per thread in flight
-        float v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = k0 + 256 * q < seg_n ? (float)Fr[seg0 + k0 + 256 * q] : 0.f;
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (k0 + 256 * q < seg_n) seg[k0 + 256 * q] = v[q];
-      }
-      __syncthreads();
+    if (fastp) {
+      const float *seg = (const float *)(sraw + kSegOff);
+      const int seg0 = pr.seg0, seg_n = pr.seg_n;
+      // this thread's band datum, requested before the band sums
+      const int bi = min(tid, ob.n_band - 1);
+      const double d_b = ob.data[bi], s_b = ob.sigma[bi];
+      const bool m_b = ob.mask[bi] != 0;
+      const double ui0 = phot_ui0(lib, z);
       const double d = 1.0 / lib.inv_dlnw;
       const float df = (float)d, inv_em1 = (float)(1.0 / expm1(d));
+      // e^x - 1 for x = f d in [0, d]: below d = 0.05 the series to x^4 is exact to FP32
+      // rounding (and free of the cancellation of expf(x) - 1)
+      const bool series = d < 0.05;
       const double umax = (double)(N - 1);
-      const int wave_id = tid >> 6, lane = tid & 63;
-      // wave w takes bands w, w+4, ...; four of its bands at a time, so that their node
-      // loads are in flight together (issued unconditionally from clamped indices) and
-      // their four wave reductions interleave
-      for (int g0 = wave_id; g0 < ob.n_band; g0 += 16) {
-        float part[4] = {0.f, 0.f, 0.f, 0.f};
-        int jlo[4], jhi[4], len = 0;
+      // the wave index made explicitly uniform, so that the band offsets are scalar loads
+      const int wave_id = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+      __syncthreads();
+      // wave w takes bands w, w+4, ..., eight at a time, so that all their node loads are
+      // in flight together (issued unconditionally from clamped indices) and their eight
+      // wave reductions interleave
+      for (int g0 = wave_id; g0 < ob.n_band; g0 += 32) {
+        float part[8];
+        int jlo[8], jhi[8], len = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int band = g0 + 4 * i;
-          jlo[i] = band < ob.n_band ? ob.band_off[band] : 0;
-          jhi[i] = band < ob.n_band ? ob.band_off[band + 1] : 0;
+        for (int i = 0; i < 8; ++i) {
+          const int band = g0 + 4 * i, bc = min(band, ob.n_band - 1);
+          const int lo = ob.band_off[bc], hi = ob.band_off[bc + 1];
+          jlo[i] = band < ob.n_band ? lo : 0;
+          jhi[i] = band < ob.n_band ? hi : 0;
           len = max(len, jhi[i] - jlo[i]);
+          part[i] = 0.f;
         }
         for (int jb = 0; jb < len; jb += 128) {   // two nodes per lane and band per pass
-          double uq[8];
-          float rq[8];
-          bool ok[8];
+          double uq[16];
+          float rq[16];
+          bool ok[16];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < 8; ++i)
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
               const int j = jlo[i] + jb + 64 * q + lane;
@@ -154,15 +167,19 @@ __global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
               rq[2 * i + q] = ob.fr_f[jc];
             }
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < 8; ++i)
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
               const int n = 2 * i + q;
-              const double u = uq[n] * lib.inv_dlnw + ui0;
+              const double u = phot_u(lib, uq[n], ui0);
               const bool in = ok[n] && u >= 0.0 && u <= umax;
               const int k = min(max((int)floor(u), 0), N - 2);
-              const int kk = in ? k - seg0 : 0;
-              const float t = (expf((float)(u - (double)k) * df) - 1.f) * inv_em1;
+              const int kk = in ? min(max(k - seg0, 0), seg_n - 2) : 0;
+              const float x = (float)(u - (double)k) * df;
+              float em;
+              if (series) em = x * (1.f + x * (0.5f + x * (1.f / 6.f + x * (1.f / 24.f))));
+              else em = expf(x) - 1.f;
+              const float t = em * inv_em1;
               const float f0 = seg[kk], f1 = seg[kk + 1];
               part[i] += in ? rq[n] * (f0 + t * (f1 - f0)) : 0.f;
             }
@@ -170,16 +187,16 @@ __global__ void __launch_bounds__(256, 5) k_project(DevLib lib, ProjArgs<T> a) {
         // FP32 butterfly (the terms are FP32 products; at most 4096 of them per band)
         for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) part[i] += __shfl_xor(part[i], o, 64);
+          for (int i = 0; i < 8; ++i) part[i] += __shfl_xor(part[i], o, 64);
         }
         if (lane == 0) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < 8; ++i)
             if (g0 + 4 * i < ob.n_band) red[g0 + 4 * i] = (double)part[i];
         }
       }
       __syncthreads();
-      for (int band = tid; band < ob.n_band; band += 256) datum(band, fac * red[band]);
+      if (tid < ob.n_band) datum_in(tid, fac * red[tid], m_b, d_b, s_b);   // n_band <= 256
     } else {
       // one pass over all filter nodes, eight per thread in flight, terms kept in LDS
       for (int j0 = tid; j0 < ob.n_fnodes; j0 += 2048) {

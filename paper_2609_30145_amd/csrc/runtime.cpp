@@ -149,9 +149,12 @@ sps_status sps_obs::enable_timing(bool on) {
   if (on && ev_start.empty()) {
     ev_start.resize(kEvents);
     ev_stop.resize(kEvents);
+    // timing-only events: no system-scope fence at record, so that recording them costs
+    // no cache writeback and invalidation between the kernels they bracket
     for (size_t i = 0; i < kEvents; ++i) {
-      if (hipEventCreate(&ev_start[i]) != hipSuccess || hipEventCreate(&ev_stop[i]) != hipSuccess)
-        return fail(SPS_E_HIP, "hipEventCreate failed");
+      if (hipEventCreateWithFlags(&ev_start[i], hipEventDisableSystemFence) != hipSuccess ||
+          hipEventCreateWithFlags(&ev_stop[i], hipEventDisableSystemFence) != hipSuccess)
+        return fail(SPS_E_HIP, "hipEventCreateWithFlags failed");
     }
   }
   timing = on;
@@ -162,7 +165,10 @@ sps_status sps_obs::enable_timing(bool on) {
   return SPS_OK;
 }
 
-hipError_t sps_obs::timing_begin(hipStream_t s, int n_mtiles, int n_ktiles) {
+// The pair of events for the next timed contraction launch: the launch hands them to the
+// kernel's dispatch, which stamps its own start and end (no marker between kernels).
+hipError_t sps_obs::timing_events(int n_mtiles, int n_ktiles, hipEvent_t *start, hipEvent_t *stop) {
+  *start = *stop = nullptr;
   if (!timing) return hipSuccess;
   const size_t i = ev_next % kEvents;
   if (ev_pending >= kEvents) {   // reuse the oldest pair: fold its time in first
@@ -174,17 +180,12 @@ hipError_t sps_obs::timing_begin(hipStream_t s, int n_mtiles, int n_ktiles) {
     --ev_pending;
   }
   dense_tiles += (int64_t)n_mtiles * n_ktiles;
-  return hipEventRecord(ev_start[i], s);
-}
-
-hipError_t sps_obs::timing_end(hipStream_t s) {
-  if (!timing) return hipSuccess;
-  const size_t i = ev_next % kEvents;
-  hipError_t e = hipEventRecord(ev_stop[i], s);
+  *start = ev_start[i];
+  *stop = ev_stop[i];
   ++ev_next;
   ++ev_pending;
   ++launches;
-  return e;
+  return hipSuccess;
 }
 
 sps_status sps_obs::read_timing(double *ms, int64_t *nl, int64_t *exec_tiles, int64_t *dense) {

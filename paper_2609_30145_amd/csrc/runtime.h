@@ -95,8 +95,7 @@ struct sps_obs {
   sps_status upload_operators();
   sps_status upload_data();
   sps_status enable_timing(bool on);
-  hipError_t timing_begin(hipStream_t s, int n_mtiles, int n_ktiles);
-  hipError_t timing_end(hipStream_t s);
+  hipError_t timing_events(int n_mtiles, int n_ktiles, hipEvent_t *start, hipEvent_t *stop);
   sps_status read_timing(double *ms, int64_t *launches, int64_t *exec_tiles, int64_t *dense_tiles);
 };
 

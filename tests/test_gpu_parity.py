@@ -103,7 +103,7 @@ def test_c1_reduced_fp32(c1s):
     assert e.max() < 1e-5
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp16_wl"])
 def test_c1_reduced_low_precision(c1s, prec):
     case, L, O, ll_ref, m_ref = c1s
     say(f"c1-reduced {prec} B=200")
@@ -191,7 +191,7 @@ def test_c1_full_fp32(c1full):
     assert e.max() < 1e-5
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp16_wl"])
 def test_c1_full_low_precision(c1full, prec):
     case, L, O, ll_ref, m_ref = c1full
     say(f"c1 {prec} B=1024 full size")
