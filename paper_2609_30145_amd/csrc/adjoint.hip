@@ -845,30 +845,111 @@ struct AdjPrepArgs {
   double *grad;
 };
 
-__global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
+// LDS layout of k_adj_prep, in doubles.  The young-weight row is dead once the
+// photon-weighted sums are formed; its space then holds the reduction partials.
+struct AdjPrepSmem {
+  int gacc, wrow, red, tab, edges, dT, mass, mr, zt, zd, zf, gzeta, wq, gwq, zj, zk, total;
+  __host__ __device__ AdjPrepSmem(const DevLib &lib) {
+    const int n = lib.n_sfh, ny = lib.n_young;
+    const int nw = lib.n_line > 0 ? ny * lib.n_z * lib.n_afe : 0;
+    const int nr = 8 * ny > 16 ? 8 * ny : 16;
+    int o = 0;
+    gacc = o;  o += lib.K_pad;                   // d logL / d W
+    wrow = o;  red = o;  o += nw > nr ? nw : nr; // young SSP weights; later the partials
+    tab = o;   o += prep_tab_len(lib);           // node tables
+    edges = o; o += n + 1;
+    dT = o;    o += n + 1;                       // d T_i / d z
+    mass = o;  o += n;
+    mr = o;    o += n;                           // bin mass per unit time
+    zt = o;    o += n;
+    zd = o;    o += n;                           // d t / d zeta
+    zf = o;    o += n;                           // bin -> history-node interpolation weight
+    gzeta = o; o += n;
+    wq = o;    o += ny;
+    gwq = o;   o += ny;
+    zj = o;    o += (n + 1) / 2;                 // int: metallicity bracket
+    zk = o;    o += (n + 1) / 2;                 // int: history node
+    total = o;
+  }
+};
+
+// bracketing node j, fraction t and whether x lies inside the grid, on a short grid held
+// in LDS (the clamped split of grid_split_dev, by bisection)
+__device__ __forceinline__ void split_in_lds(const double *nodes, int n, double x, int &j, double &t, bool &inside) {
+  inside = x >= nodes[0] && x <= nodes[n - 1];
+  const double xc = fmin(fmax(x, nodes[0]), nodes[n - 1]);
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (nodes[mid] <= xc) lo = mid; else hi = mid;
+  }
+  j = lo;
+  t = (xc - nodes[lo]) / (nodes[lo + 1] - nodes[lo]);
+}
+
+// One workgroup per sorted row.  The node tables and the row of d logL / d W are copied
+// to LDS first (all loads in flight together); every search then runs in LDS.
+__global__ void __launch_bounds__(256, 4) k_adj_prep(DevLib lib, AdjPrepArgs a) {
   extern __shared__ double sm[];
+  const AdjPrepSmem S(lib);
   const int K_pad = lib.K_pad, n = lib.n_sfh, na = lib.n_age, nz = lib.n_z, nf = lib.n_afe, ny = lib.n_young;
-  double *gacc = sm;                    // [K_pad] d logL / d W
-  double *wrow = gacc + K_pad;          // [K_pad] W (recomputed, lines only)
-  double *edges = wrow + K_pad;         // [n+1]
-  double *dT = edges + n + 1;           // [n+1]
-  double *zt = dT + n + 1;              // [n]
-  double *zd = zt + n;                  // [n] dt/dzeta
-  double *gzeta = zd + n;               // [n]
-  double *gm = gzeta + n;               // [n] d/d mass
-  double *wq = gm + n;                  // [ny]
-  double *gwq = wq + ny;                // [ny]
-  double *red = gwq + ny;               // [256]
-  double *gsq = red + 256;              // [n_line * ny] per (line, age) entry
-  int *zj = (int *)(gsq + (size_t)lib.n_line * ny);   // [n]
-  __shared__ double s_sc[4];
+  const int nl = lib.n_line;
+  double *gacc = sm + S.gacc, *wrow = sm + S.wrow, *tab = sm + S.tab;
+  const double *t_logz = tab, *t_afe = tab + nz, *s_clo = tab + nz + nf, *s_chi = s_clo + na;
+  const double *s_zg = s_chi + na, *s_un = s_zg + lib.n_zg, *s_Q = s_un + lib.n_u;
+  double *edges = sm + S.edges, *dT = sm + S.dT, *mass = sm + S.mass, *mr = sm + S.mr, *zt = sm + S.zt;
+  double *zd = sm + S.zd, *zf = sm + S.zf, *gzeta = sm + S.gzeta, *wq = sm + S.wq, *gwq = sm + S.gwq;
+  double *red = sm + S.red;
+  int *zj = (int *)(sm + S.zj), *zk = (int *)(sm + S.zk);
   const int r = blockIdx.x, tid = threadIdx.x;
   const PointRow pr = a.rows[r];
   if (pr.b < 0) return;
+  double *gr = a.grad + (size_t)pr.b * a.P;
   const double *th = a.theta + (size_t)pr.b * a.P;
-  for (int k = tid; k < K_pad; k += 256) {
-    gacc[k] = ((const double *)a.dW)[(size_t)r * K_pad + k];
-    wrow[k] = 0.0;
+
+  // ---- the row of d logL / d W, the node-table block and the bin masses to LDS
+  {
+    const double2 *g2 = (const double2 *)((const double *)a.dW + (size_t)r * K_pad);   // K_pad even
+    const double2 *t2 = (const double2 *)lib.prep_tab;                                  // even length
+    const int ng2 = K_pad >> 1, nt2 = prep_tab_len(lib) >> 1;
+    double2 vg[5], vt[2];
+    double vm;
+#pragma unroll
+    for (int u = 0; u < 5; ++u) vg[u] = g2[min(tid + 256 * u, ng2 - 1)];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) vt[u] = t2[min(tid + 256 * u, nt2 - 1)];
+    vm = th[TH_NSCALAR + min(tid, n - 1)];
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      const int i = tid + 256 * u;
+      if (i < ng2) {
+        gacc[2 * i] = vg[u].x;
+        gacc[2 * i + 1] = vg[u].y;
+      }
+    }
+    for (int i = tid + 256 * 5; i < ng2; i += 256) {
+      const double2 v = g2[i];
+      gacc[2 * i] = v.x;
+      gacc[2 * i + 1] = v.y;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = tid + 256 * u;
+      if (i < nt2) {
+        tab[2 * i] = vt[u].x;
+        tab[2 * i + 1] = vt[u].y;
+      }
+    }
+    for (int i = tid + 256 * 2; i < nt2; i += 256) {
+      const double2 v = t2[i];
+      tab[2 * i] = v.x;
+      tab[2 * i + 1] = v.y;
+    }
+    if (tid < n) mass[tid] = vm;
+    for (int i = tid + 256; i < n; i += 256) mass[i] = th[TH_NSCALAR + i];
+    for (int c = tid; c < a.P; c += 256) gr[c] = 0.0;   // every column not written below is 0
+    if (nl > 0)
+      for (int k = tid; k < ny * nz * nf; k += 256) wrow[k] = 0.0;
   }
   const double z = pr.z, opz = 1.0 + z, t_univ = pr.t_univ;
   const double Ez = sqrt(lib.Om * opz * opz * opz + 1.0 - lib.Om);
@@ -887,47 +968,62 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
     edges[i] = T;
     dT[i] = d;
   }
+  __syncthreads();
+
+  // ---- bin metallicities and their brackets; alpha bracket
   const double *zh = th + TH_NSCALAR + n;
   for (int i = tid; i < n; i += 256) {
     double zeta;
+    int k = 0;
+    double f = 0.0;
     if (lib.n_zh == 0) zeta = th[TH_LOGZSOL];
     else if (i == 0) zeta = zh[0];
     else {
       const double x = ((double)i - 0.5) / (double)(n - 1) * (double)(lib.n_zh - 1);
-      int k = (int)floor(x);
+      k = (int)floor(x);
       if (k >= lib.n_zh - 1) k = lib.n_zh - 2;
-      const double f = x - (double)k;
+      f = x - (double)k;
       zeta = zh[k] + f * (zh[k + 1] - zh[k]);
     }
     int j = 0;
     double t = 0.0;
     bool in = false;
-    if (nz > 1) grid_split_dev(lib.logz, nz, zeta, j, t, in);
+    if (nz > 1) split_in_lds(t_logz, nz, zeta, j, t, in);
     zj[i] = j;
     zt[i] = t;
-    zd[i] = (nz > 1 && in) ? 1.0 / (lib.logz[j + 1] - lib.logz[j]) : 0.0;
+    zd[i] = (nz > 1 && in) ? 1.0 / (t_logz[j + 1] - t_logz[j]) : 0.0;
+    zk[i] = k;
+    zf[i] = f;
+    mr[i] = mass[i] / (edges[i + 1] - edges[i]);
     gzeta[i] = 0.0;
-    gm[i] = 0.0;
   }
   int ja = 0;
   double ta = 0.0, dta = 0.0;
   if (nf > 1) {
     bool in;
-    grid_split_dev(lib.afe, nf, th[TH_AFE], ja, ta, in);
-    dta = in ? 1.0 / (lib.afe[ja + 1] - lib.afe[ja]) : 0.0;
+    split_in_lds(t_afe, nf, th[TH_AFE], ja, ta, in);
+    dta = in ? 1.0 / (t_afe[ja + 1] - t_afe[ja]) : 0.0;
   }
   __syncthreads();
-  const double *mass = th + TH_NSCALAR;
 
   // ---- lines: recompute the young weights and Q-weighted sums, then back to W and gas
   double ggz = 0.0, ggu = 0.0;
-  if (lib.n_line > 0) {
-    for (int ag = tid; ag < ny; ag += 256) {
-      const double lo = lib.cell_lo[ag], hi = lib.cell_hi[ag];
-      for (int i = 0; i < n && edges[i] < hi; ++i) {
+  if (nl > 0) {
+    for (int ag = tid; ag < ny; ag += 256) {   // young ages: first bin by bisection
+      const double lo = s_clo[ag], hi = s_chi[ag];
+      int i = 0;
+      {
+        int l = 0, h = n;
+        while (l < h) {
+          const int mid = (l + h) >> 1;
+          if (edges[mid + 1] > lo) h = mid; else l = mid + 1;
+        }
+        i = l;
+      }
+      for (; i < n && edges[i] < hi; ++i) {
         const double ov = fmin(hi, edges[i + 1]) - fmax(lo, edges[i]);
         if (ov <= 0.0) continue;
-        const double w = mass[i] * ov / (edges[i + 1] - edges[i]);
+        const double w = mr[i] * ov;
         for (int q = 0; q < (nf > 1 ? 2 : 1); ++q) {
           const int ia = nf > 1 ? ja + q : 0;
           const double fa = nf > 1 ? (q == 0 ? 1.0 - ta : ta) : 1.0;
@@ -939,50 +1035,125 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
           }
         }
       }
-      double s = 0.0;
-      for (int ia = 0; ia < nf; ++ia)
-        for (int m = 0; m < nz; ++m) s += wrow[kpos_of(lib, ia, m, ag)] * lib.Q[(ia * nz + m) * ny + ag];
-      wq[ag] = s;
-      gwq[ag] = 0.0;
+    }
+    __syncthreads();
+    {   // photon-weighted young mass per age: eight lanes per age, fixed butterfly
+      const int nm = nf * nz;
+      for (int g0 = 0; g0 < ny; g0 += 32) {
+        const int ag = g0 + (tid >> 3), c = tid & 7;
+        double sacc = 0.0;
+        if (ag < ny)
+          for (int q = c; q < nm; q += 8) {
+            const int ia = q / nz, m = q - ia * nz;
+            sacc += wrow[kpos_of(lib, ia, m, ag)] * s_Q[q * ny + ag];
+          }
+        sacc += __shfl_xor(sacc, 1);
+        sacc += __shfl_xor(sacc, 2);
+        sacc += __shfl_xor(sacc, 4);
+        if (ag < ny && c == 0) wq[ag] = sacc;
+      }
     }
     __syncthreads();
     int jg = 0, ju = 0;
     double tg = 0.0, tu = 0.0;
     bool ig, iu;
-    grid_split_dev(lib.zg, lib.n_zg, th[TH_GAS_LOGZ], jg, tg, ig);
-    grid_split_dev(lib.un, lib.n_u, th[TH_GAS_LOGU], ju, tu, iu);
-    const double dtg = ig ? 1.0 / (lib.zg[jg + 1] - lib.zg[jg]) : 0.0;
-    const double dtu = iu ? 1.0 / (lib.un[ju + 1] - lib.un[ju]) : 0.0;
+    split_in_lds(s_zg, lib.n_zg, th[TH_GAS_LOGZ], jg, tg, ig);
+    split_in_lds(s_un, lib.n_u, th[TH_GAS_LOGU], ju, tu, iu);
+    const double dtg = ig ? 1.0 / (s_zg[jg + 1] - s_zg[jg]) : 0.0;
+    const double dtu = iu ? 1.0 / (s_un[ju + 1] - s_un[ju]) : 0.0;
     const int nu = lib.n_u;
-    // thread per (line, age) entry q = l * ny + ag (consecutive threads on consecutive
-    // table entries): 10^Lhat and its derivatives in the gas parameters; the per-age
-    // sums over lines then run in a fixed order
-    const int nq = lib.n_line * ny;
-    const size_t slab = (size_t)lib.n_line * ny;
-    const size_t o00 = (size_t)(jg * nu + ju) * slab, o01 = (size_t)(jg * nu + ju + 1) * slab;
-    const size_t o10 = (size_t)((jg + 1) * nu + ju) * slab, o11 = (size_t)((jg + 1) * nu + ju + 1) * slab;
-    for (int q = tid; q < nq; q += 256) {
-      const int l = q / ny, ag = q - l * ny;
-      const double gL = pr.kind == 0 ? gacc[a.line_k0 + l] / kLsun : a.dLl[(size_t)r * lib.n_line + l];
-      const double t00 = lib.line_table[o00 + q], t01 = lib.line_table[o01 + q];
-      const double t10 = lib.line_table[o10 + q], t11 = lib.line_table[o11 + q];
-      const double lh = (1 - tg) * (1 - tu) * t00 + (1 - tg) * tu * t01 + tg * (1 - tu) * t10 + tg * tu * t11;
-      const double E = exp10(lh);
-      gsq[q] = gL * E;
-      const double gE = gL * wq[ag] * E * 2.302585092994046;
-      ggz += gE * ((1 - tu) * (t10 - t00) + tu * (t11 - t01)) * dtg;
-      ggu += gE * ((1 - tg) * (t01 - t00) + tg * (t11 - t10)) * dtu;
+    const size_t slab = (size_t)nl * ny;
+    const double *t00p = lib.line_table + (size_t)(jg * nu + ju) * slab;
+    const double *t01p = lib.line_table + (size_t)(jg * nu + ju + 1) * slab;
+    const double *t10p = lib.line_table + (size_t)((jg + 1) * nu + ju) * slab;
+    const double *t11p = lib.line_table + (size_t)((jg + 1) * nu + ju + 1) * slab;
+    const double c00 = (1 - tg) * (1 - tu), c01 = (1 - tg) * tu, c10 = tg * (1 - tu), c11 = tg * tu;
+    // thread (line group g = tid / 32, age slot tid % 32): the lines l = g, g + 8, ...;
+    // 10^Lhat and its gas derivatives per (line, age), four lines' table loads in flight
+    if (a.f64) {
+    for (int a0 = 0; a0 < ny; a0 += 32) {
+      const int ag = a0 + (tid & 31), g = tid >> 5;
+      const bool act = ag < ny;
+      const int agc = act ? ag : 0;
+      const double wq_a = wq[agc];
+      double gs = 0.0;
+      for (int l0 = g; l0 < nl; l0 += 32) {
+        double v[4][4], gLv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int l = min(l0 + 8 * u, nl - 1);
+          const size_t q = (size_t)l * ny + agc;
+          v[u][0] = t00p[q];
+          v[u][1] = t01p[q];
+          v[u][2] = t10p[q];
+          v[u][3] = t11p[q];
+          gLv[u] = pr.kind == 0 ? gacc[a.line_k0 + l] / kLsun : a.dLl[(size_t)r * nl + l];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (!act || l0 + 8 * u >= nl) continue;
+          const double lh = c00 * v[u][0] + c01 * v[u][1] + c10 * v[u][2] + c11 * v[u][3];
+          const double E = exp10(lh);
+          gs += gLv[u] * E;
+          const double gE = gLv[u] * wq_a * E * 2.302585092994046;
+          ggz += gE * ((1 - tu) * (v[u][2] - v[u][0]) + tu * (v[u][3] - v[u][1])) * dtg;
+          ggu += gE * ((1 - tg) * (v[u][1] - v[u][0]) + tg * (v[u][3] - v[u][2])) * dtu;
+        }
+      }
+      if (act) red[g * ny + ag] = gs;
+    }
+    } else {
+    // FP32 gradient pass: the FP32 table and exponentials (the result feeds FP32 weights)
+    const size_t slab_f = (size_t)nl * ny;
+    const float *f00p = lib.line_table_f + (size_t)(jg * nu + ju) * slab_f;
+    const float *f01p = lib.line_table_f + (size_t)(jg * nu + ju + 1) * slab_f;
+    const float *f10p = lib.line_table_f + (size_t)((jg + 1) * nu + ju) * slab_f;
+    const float *f11p = lib.line_table_f + (size_t)((jg + 1) * nu + ju + 1) * slab_f;
+    const float e00 = (float)c00, e01 = (float)c01, e10 = (float)c10, e11 = (float)c11;
+    for (int a0 = 0; a0 < ny; a0 += 32) {
+      const int ag = a0 + (tid & 31), g = tid >> 5;
+      const bool act = ag < ny;
+      const int agc = act ? ag : 0;
+      const double wq_a = wq[agc];
+      double gs = 0.0;
+      for (int l0 = g; l0 < nl; l0 += 64) {
+        float v[8][4];
+        double gLv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int l = min(l0 + 8 * u, nl - 1);
+          const size_t q = (size_t)l * ny + agc;
+          v[u][0] = f00p[q];
+          v[u][1] = f01p[q];
+          v[u][2] = f10p[q];
+          v[u][3] = f11p[q];
+          gLv[u] = pr.kind == 0 ? gacc[a.line_k0 + l] / kLsun : a.dLl[(size_t)r * nl + l];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (!act || l0 + 8 * u >= nl) continue;
+          const float lh = e00 * v[u][0] + e01 * v[u][1] + e10 * v[u][2] + e11 * v[u][3];
+          const double E = (double)exp10f(lh);
+          gs += gLv[u] * E;
+          const double gE = gLv[u] * wq_a * E * 2.302585092994046;
+          ggz += gE * (double)((1.f - (float)tu) * (v[u][2] - v[u][0]) + (float)tu * (v[u][3] - v[u][1])) * dtg;
+          ggu += gE * (double)((1.f - (float)tg) * (v[u][1] - v[u][0]) + (float)tg * (v[u][3] - v[u][2])) * dtu;
+        }
+      }
+      if (act) red[g * ny + ag] = gs;
+    }
     }
     __syncthreads();
-    for (int ag = tid; ag < ny; ag += 256) {
+    for (int ag = tid; ag < ny; ag += 256) {   // the eight line groups in a fixed order
       double gs = 0.0;
-      for (int l = 0; l < lib.n_line; ++l) gs += gsq[l * ny + ag];
+      for (int g = 0; g < 8; ++g) gs += red[g * ny + ag];
       gwq[ag] = gs;
     }
     __syncthreads();
-    for (int ag = tid; ag < ny; ag += 256)
-      for (int ia = 0; ia < nf; ++ia)
-        for (int m = 0; m < nz; ++m) gacc[kpos_of(lib, ia, m, ag)] += gwq[ag] * lib.Q[(ia * nz + m) * ny + ag];
+    for (int e = tid; e < ny * nz * nf; e += 256) {   // young entries (age, alpha, Z)
+      const int ag = e / (nz * nf), q = e - ag * (nz * nf), ia = q / nz, m = q - ia * nz;
+      gacc[kpos_of(lib, ia, m, ag)] += gwq[ag] * s_Q[(ia * nz + m) * ny + ag];
+    }
     __syncthreads();
   }
 
@@ -990,22 +1161,25 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
   double gz_e = 0.0, gafe = 0.0;
   for (int i = tid; i < n; i += 256) {
     const double Ti = edges[i], Tj = edges[i + 1], dTb = Tj - Ti;
+    const double inv = 1.0 / dTb, mri = mr[i];
     int ag;
     {
       int l = 0, h = na;   // first cell whose upper edge exceeds Ti
       while (l < h) {
         const int mid = (l + h) >> 1;
-        if (lib.cell_hi[mid] > Ti) h = mid; else l = mid + 1;
+        if (s_chi[mid] > Ti) h = mid; else l = mid + 1;
       }
       ag = l;
     }
     double gmi = 0.0, gzi = 0.0;
-    for (; ag < na && lib.cell_lo[ag] < Tj; ++ag) {
-      const double lo = lib.cell_lo[ag], hi = lib.cell_hi[ag];
+    const int j0 = zj[i];
+    const double t0 = zt[i], zdi = zd[i];
+    for (; ag < na && s_clo[ag] < Tj; ++ag) {
+      const double lo = s_clo[ag], hi = s_chi[ag];
       const double upper = fmin(hi, Tj), lower = fmax(lo, Ti);
       const double ovr = upper - lower;
       if (ovr <= 0.0) continue;
-      const double w = mass[i] * ovr / dTb;
+      const double w = mri * ovr;
       double gw = 0.0;
       for (int q = 0; q < (nf > 1 ? 2 : 1); ++q) {
         const int ia = nf > 1 ? ja + q : 0;
@@ -1013,24 +1187,25 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
         const double dfa = nf > 1 ? (q == 0 ? -dta : dta) : 0.0;
         double gA;
         if (nz > 1) {
-          const double g0 = gacc[kpos_of(lib, ia, zj[i], ag)];
-          const double g1 = gacc[kpos_of(lib, ia, zj[i] + 1, ag)];
-          gA = (1.0 - zt[i]) * g0 + zt[i] * g1;
-          gzi += fa * zd[i] * w * (g1 - g0);
+          const double g0 = gacc[kpos_of(lib, ia, j0, ag)];
+          const double g1 = gacc[kpos_of(lib, ia, j0 + 1, ag)];
+          gA = (1.0 - t0) * g0 + t0 * g1;
+          gzi += fa * zdi * w * (g1 - g0);
         } else {
           gA = gacc[kpos_of(lib, ia, 0, ag)];
         }
         gw += fa * gA;
         gafe += dfa * w * gA;
       }
-      gmi += gw * ovr / dTb;
+      gmi += gw * ovr * inv;
+      // w = m ov / dT with ov = min(hi, T_j) - max(lo, T_i): its edge derivatives
       const double dov_i = (Ti > lo) ? -1.0 : 0.0;
       const double dov_j = (Tj < hi) ? 1.0 : 0.0;
-      const double dw_i = mass[i] * (dov_i / dTb + ovr / (dTb * dTb));
-      const double dw_j = mass[i] * (dov_j / dTb - ovr / (dTb * dTb));
+      const double dw_i = mri * (dov_i + ovr * inv);
+      const double dw_j = mri * (dov_j - ovr * inv);
       gz_e += gw * (dw_i * dT[i] + dw_j * dT[i + 1]);
     }
-    gm[i] = gmi;
+    gr[TH_NSCALAR + i] = gmi;   // d logL / d m_i
     gzeta[i] = gzi;
   }
   // four block sums at once: wave butterflies, then the four waves in a fixed order
@@ -1045,11 +1220,7 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
   __syncthreads();
   const double s_ze = (red[0] + red[4]) + (red[8] + red[12]), s_afe = (red[1] + red[5]) + (red[9] + red[13]);
   const double s_gz = (red[2] + red[6]) + (red[10] + red[14]), s_gu = (red[3] + red[7]) + (red[11] + red[15]);
-  double *gr = a.grad + (size_t)pr.b * a.P;
-  for (int c = tid; c < a.P; c += 256) gr[c] = 0.0;
-  __syncthreads();
   const double *gb = a.gbuf + (size_t)r * 16;
-  for (int i = tid; i < n; i += 256) gr[TH_NSCALAR + i] = gm[i];
   if (tid == 0) {
     gr[TH_LOGMASS] = gb[GB_LOGMASS];
     gr[TH_ZRED] = gb[GB_Z] + s_ze;
@@ -1063,24 +1234,30 @@ __global__ void __launch_bounds__(256) k_adj_prep(DevLib lib, AdjPrepArgs a) {
     }
     if (nf > 1) gr[TH_AFE] = s_afe;
     for (int q = 0; q < 4; ++q) gr[TH_LOG_ERR_SCALE + q] = a.gnoise[(size_t)pr.b * 4 + q];
-    // metallicity parameters: transpose of the bin interpolation (fixed order)
-    if (lib.n_zh == 0) {
+    if (lib.n_zh == 0) {   // constant metallicity: every bin's share, in bin order
       double s = 0.0;
       for (int i = 0; i < n; ++i) s += gzeta[i];
       gr[TH_LOGZSOL] = s;
-    } else {
-      double *gz = gr + TH_NSCALAR + n;
-      gz[0] += gzeta[0];
-      for (int i = 1; i < n; ++i) {
-        const double x = ((double)i - 0.5) / (double)(n - 1) * (double)(lib.n_zh - 1);
-        int k = (int)floor(x);
-        if (k >= lib.n_zh - 1) k = lib.n_zh - 2;
-        const double f = x - (double)k;
-        gz[k] += (1.0 - f) * gzeta[i];
-        gz[k + 1] += f * gzeta[i];
-      }
     }
   }
+  // metallicity-history nodes: transpose of the bin interpolation, one thread per node,
+  // each adding its bins' shares in bin order (bin 0 takes node 0 alone).  The node
+  // index of bins 1..n-1 does not decrease with the bin, so node k's bins (index k - 1
+  // or k) are one run, found by bisection.
+  if (lib.n_zh > 0)
+    for (int k = tid; k < lib.n_zh; k += 256) {
+      double sk = k == 0 ? gzeta[0] : 0.0;
+      int l = 1, h = n;   // first bin >= 1 whose node index reaches k - 1
+      while (l < h) {
+        const int mid = (l + h) >> 1;
+        if (zk[mid] < k - 1) l = mid + 1; else h = mid;
+      }
+      for (int i = l; i < n && zk[i] <= k; ++i) {
+        if (zk[i] == k) sk += (1.0 - zf[i]) * gzeta[i];
+        else sk += zf[i] * gzeta[i];   // zk[i] == k - 1
+      }
+      gr[TH_NSCALAR + n + k] = sk;
+    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -1187,9 +1364,7 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
     ap.gnoise = w.gnoise;
     ap.dLl = w.dLl;
     ap.grad = grad;
-    const size_t sm2 = sizeof(double) * (2 * (size_t)g.K_pad + 6 * (size_t)g.n_sfh + 2 + 2 * g.n_young + 256 +
-                                         (size_t)g.n_line * g.n_young) +
-                       sizeof(int) * (size_t)g.n_sfh + 64;
+    const size_t sm2 = sizeof(double) * (size_t)AdjPrepSmem(g).total;
     if (sm2 > 150 * 1024) return fail(SPS_E_SHAPE, "gradient pass: library too large for one workgroup");
     static size_t attr2 = 0;
     if (sm2 > 48 * 1024 && sm2 > attr2) {
