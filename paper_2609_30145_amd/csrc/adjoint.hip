@@ -115,6 +115,8 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
   if (!fast_spec)
     for (int n = n0; n < n1; ++n) gFl[n] = 0.0;
   int fs_seg0 = 0, fs_segn = 0;   // FP32 spectra: span of the rows, d logL / d F held there
+  bool fx = false;                // FP32 photometry: d logL / d F held as fixed point,
+  double fx_inv = 0.0;            //   with this quantum
   double gz = 0.0, glm = 0.0, gtb = 0.0, gab = 0.0, gtd = 0.0, gdl = 0.0;
   for (int i = tid; i < ob.n_data; i += 256) glm += gm[i] * mm[i];
 
@@ -133,52 +135,89 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
     for (int b = tid; b <= nb; b += 256) s_bo[b] = ob.band_off[b];
     for (int b = tid; b < nb; b += 256) gz += gm[b] * dlnA * mm[b];
     __syncthreads();
-#pragma unroll 4
-    for (int j = tid; j < nfn; j += 256) {
-      int lo = 0, hi = nb - 1;   // band of node j: the last b with band_off[b] <= j
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_bo[mid] <= j) lo = mid; else hi = mid - 1;
-      }
-      const double lr = ob.fw[j] / opz;
-      const double coef = gm[lo] * A * ob.fr_d[j];
-      int kk;
-      float c0 = 0.f, c1 = 0.f;
-      // as the forward pass of the gradient pass (linear in lambda, the interval from the
-      // node's log index on a log-uniform grid)
-      if (lr < wlo) {
-        kk = -2;
-      } else if (lr > whi) {
-        kk = N + 1;
-      } else {
-        const int k = min(max((int)floor((ob.fwln[j] - lnopz - lib.lnw0) * lib.inv_dlnw), 0), N - 2);
-        const double w0 = lib.wave_d[k], dw = lib.wave_d[k + 1] - w0;
-        const double t = (lr - w0) / dw;
-        gz += coef * (((double)Fr[k + 1] - (double)Fr[k]) / dw) * (-ob.fw[j] / (opz * opz));
-        kk = k;
-        c0 = (float)(coef * (1.0 - t));
-        c1 = (float)(coef * t);
-      }
-      s_nk[j] = (short)kk;
-      s_c0[j] = c0;
-      s_c1[j] = c1;
-    }
-    __syncthreads();
-    // gather: each thread owns model pixels [n0, n1); bands and nodes in a fixed order
-    if (n0 < n1) {
-      for (int b = 0; b < nb; ++b) {
-        const int j0 = s_bo[b], j1 = s_bo[b + 1];
-        int lo = j0, hi = j1;   // first node with k >= n0 - 1 (k is non-decreasing in a band)
+    // ten nodes per thread per round: their node data, then their grid intervals and model
+    // values, each group of loads in flight together (clamped indices); gz in node order
+    constexpr int UJ = 10;
+    float cmax = 0.f;
+    for (int jb = tid; jb < nfn; jb += 256 * UJ) {
+      double fwq[UJ], frq[UJ], lnq[UJ];
+      int bq[UJ];
+#pragma unroll
+      for (int u = 0; u < UJ; ++u) {
+        const int j = min(jb + 256 * u, nfn - 1);
+        fwq[u] = ob.fw[j];
+        frq[u] = ob.fr_d[j];
+        lnq[u] = ob.fwln[j];
+        int lo = 0, hi = nb - 1;   // band of node j: the last b with band_off[b] <= j
         while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (s_nk[mid] < n0 - 1) lo = mid + 1; else hi = mid;
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_bo[mid] <= j) lo = mid; else hi = mid - 1;
         }
-        for (int j = lo; j < j1; ++j) {
-          const int k = s_nk[j];
-          if (k >= n1) break;
-          if (k >= n0 && k < n1) gFl[k] += s_c0[j];
-          if (k + 1 >= n0 && k + 1 < n1) gFl[k + 1] += s_c1[j];
+        bq[u] = lo;
+      }
+      double gq[UJ], w0q[UJ], w1q[UJ];
+      float f0q[UJ], f1q[UJ];
+      int kq[UJ];
+#pragma unroll
+      for (int u = 0; u < UJ; ++u) {
+        // as the forward pass of the gradient pass (linear in lambda, the interval from the
+        // node's log index on a log-uniform grid)
+        const int k = min(max((int)floor((lnq[u] - lnopz - lib.lnw0) * lib.inv_dlnw), 0), N - 2);
+        kq[u] = k;
+        gq[u] = gm[bq[u]];
+        w0q[u] = lib.wave_d[k];
+        w1q[u] = lib.wave_d[k + 1];
+        f0q[u] = (float)Fr[k];
+        f1q[u] = (float)Fr[k + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < UJ; ++u) {
+        const int j = jb + 256 * u;
+        if (j >= nfn) break;
+        const double lr = fwq[u] / opz;
+        const double coef = gq[u] * A * frq[u];
+        int kk;
+        float c0 = 0.f, c1 = 0.f;
+        if (lr < wlo) {
+          kk = -2;
+        } else if (lr > whi) {
+          kk = N + 1;
+        } else {
+          const double w0 = w0q[u], dw = w1q[u] - w0;
+          const double t = (lr - w0) / dw;
+          gz += coef * (((double)f1q[u] - (double)f0q[u]) / dw) * (-fwq[u] / (opz * opz));
+          kk = kq[u];
+          c0 = (float)(coef * (1.0 - t));
+          c1 = (float)(coef * t);
         }
+        cmax = fmaxf(cmax, fmaxf(fabsf(c0), fabsf(c1)));
+        s_nk[j] = (short)kk;
+        s_c0[j] = c0;
+        s_c1[j] = c1;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) cmax = fmaxf(cmax, __shfl_xor(cmax, o, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = (double)cmax;
+    __syncthreads();
+    // scatter: every node adds its two shares to d logL / d F as 64-bit fixed point (LDS
+    // integer atomics), so the sums do not depend on the order of the additions.  The
+    // scale leaves headroom for all nfn shares landing on one pixel: the largest share
+    // stays below 2^(62 - hb), hb the bit length of nfn (2^-50 of it is the quantum at
+    // nfn = 2560).
+    {
+      const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+      const int e = m > 0.0 ? max(ilogb(m) + 1, -960) : 0;   // scale and quantum stay normal
+      const int hb = 32 - __clz(nfn);
+      const double scale = ldexp(1.0, 62 - hb - e);
+      fx_inv = ldexp(1.0, e + hb - 62);
+      fx = true;
+      unsigned long long *gi = (unsigned long long *)gFl;
+      for (int j = tid; j < nfn; j += 256) {
+        const int k = s_nk[j];
+        if (k < 0 || k > N - 2) continue;   // outside the model grid: no share
+        const long long q0 = llrint((double)s_c0[j] * scale), q1 = llrint((double)s_c1[j] * scale);
+        if (q0 != 0) atomicAdd(gi + k, (unsigned long long)q0);
+        if (q1 != 0) atomicAdd(gi + k + 1, (unsigned long long)q1);
       }
     }
   } else if (ob.kind == 0) {
@@ -602,36 +641,58 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
   // ---------------- attenuation adjoint on the owned pixels (eq. D2)
   T *GY = (T *)a.GY + (size_t)r * a.N_pad, *GO = (T *)a.GO + (size_t)r * a.N_pad;
   const double Eb = 0.85 - 1.9 * pr.delta;
-  for (int n = tid; n < N; n += 256) {   // gF complete after the barrier: coalesced pass
-    const double l = lib.lnlv_d[n];
-    const double g = !fast_spec ? gFl[n]
-                                : (n >= fs_seg0 && n < fs_seg0 + fs_segn
-                                       ? (double)((const float *)gFl)[n - fs_seg0] * lib.lam2_d[n]
-                                       : 0.0);
-    double p, qd, sh, Tbc, Td;
-    if (sizeof(T) == 4) {   // FP32 path: the factors in FP32, as the forward epilogue forms them
-      const float lf = lib.lnlv_f[n];
-      const float pf = expf((float)pr.alpha_bc * lf), qf = expf((float)pr.delta * lf);
-      const float shf = lib.dust_a_f[n] + (float)Eb * lib.dust_d_f[n];
-      p = pf;
-      qd = qf;
-      sh = shf;
-      Tbc = expf(-(float)pr.tau_bc * pf);
-      Td = expf(-(float)pr.tau_diff * qf * shf);
-    } else {
-      p = exp(pr.alpha_bc * l);
-      qd = exp(pr.delta * l);
-      sh = lib.dust_a_d[n] + Eb * lib.dust_d_d[n];
-      Tbc = exp(-pr.tau_bc * p);
-      Td = exp(-pr.tau_diff * qd * sh);
+  // gF is complete after the barrier: a coalesced pass, eight nodes per thread with all
+  // their loads in flight (clamped indices); each thread's sums still run in node order
+  for (int nb = tid; nb < N; nb += 256 * 8) {
+    double lq[8], gq[8], ddq[8], yq[8], fq[8];
+    float lfq[8], daq[8], dfq[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int n = min(nb + 256 * u, N - 1);
+      lq[u] = lib.lnlv_d[n];
+      ddq[u] = lib.dust_d_d[n];
+      yq[u] = (double)Yr[n];
+      fq[u] = (double)Fr[n];
+      if (fx) gq[u] = (double)(long long)((const unsigned long long *)gFl)[n] * fx_inv;
+      else if (!fast_spec) gq[u] = gFl[n];
+      else gq[u] = (n >= fs_seg0 && n < fs_seg0 + fs_segn) ? (double)((const float *)gFl)[n - fs_seg0] * lib.lam2_d[n]
+                                                           : 0.0;
+      if (sizeof(T) == 4) {
+        lfq[u] = lib.lnlv_f[n];
+        daq[u] = lib.dust_a_f[n];
+        dfq[u] = lib.dust_d_f[n];
+      }
     }
-    GY[n] = (T)(g * Td * Tbc);
-    GO[n] = (T)(g * Td);
-    const double ya = (double)Yr[n], fa = (double)Fr[n];
-    gtb += g * ya * (-p);
-    gab += g * ya * (-pr.tau_bc * p * l);
-    gtd += g * fa * (-qd * sh);
-    gdl += g * fa * (-pr.tau_diff * (qd * l * sh - 1.9 * qd * lib.dust_d_d[n]));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int n = nb + 256 * u;
+      if (n >= N) break;
+      const double l = lq[u], g = gq[u];
+      double p, qd, sh, Tbc, Td;
+      if (sizeof(T) == 4) {   // FP32 path: the factors in FP32, as the forward epilogue forms them
+        const float lf = lfq[u];
+        const float pf = expf((float)pr.alpha_bc * lf), qf = expf((float)pr.delta * lf);
+        const float shf = daq[u] + (float)Eb * dfq[u];
+        p = pf;
+        qd = qf;
+        sh = shf;
+        Tbc = expf(-(float)pr.tau_bc * pf);
+        Td = expf(-(float)pr.tau_diff * qf * shf);
+      } else {
+        p = exp(pr.alpha_bc * l);
+        qd = exp(pr.delta * l);
+        sh = lib.dust_a_d[n] + Eb * ddq[u];
+        Tbc = exp(-pr.tau_bc * p);
+        Td = exp(-pr.tau_diff * qd * sh);
+      }
+      GY[n] = (T)(g * Td * Tbc);
+      GO[n] = (T)(g * Td);
+      const double ya = yq[u], fa = fq[u];
+      gtb += g * ya * (-p);
+      gab += g * ya * (-pr.tau_bc * p * l);
+      gtd += g * fa * (-qd * sh);
+      gdl += g * fa * (-pr.tau_diff * (qd * l * sh - 1.9 * qd * ddq[u]));
+    }
   }
   for (int n = N + tid; n < a.N_pad; n += 256) {
     GY[n] = (T)0;
