@@ -280,6 +280,8 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
     float *s_cf = (float *)(xsm + ((4 * (size_t)np + 15) & ~(size_t)15));
     float *s_a0 = s_cf + np, *s_h = s_a0 + np;
     int *s_first = (int *)(s_h + np), *s_last = s_first + 256;
+    // ln lambda of every 16th pixel, on the next 8-byte boundary (the host sizing leaves the slack)
+    double *s_lp16 = (double *)(((uintptr_t)(s_last + 256) + 7) & ~(uintptr_t)7);
     const double ext = 5.0 * ob.ksig_max * lib.inv_dlnw + 2.0;
     const double ua = (ob.lnpix[0] - lnopz - lnw0) * lib.inv_dlnw - ext;
     const double ub = (ob.lnpix[np - 1] - lnopz - lnw0) * lib.inv_dlnw + ext;
@@ -303,16 +305,26 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
     s_last[tid] = -1;
     __syncthreads();
     const int chunk_s = (seg_n + 255) / 256;   // nodes per owner in the transpose
+    // the next pixel's inputs are requested while the current row is summed
+    double gm_n = gm[min(tid, np - 1)], lp_n = ob.lnpix[min(tid, np - 1)], ks_n = ob.ksig[min(tid, np - 1)];
     for (int i = tid; i < np; i += 256) {
-      const double gc = gm[i] / kFnuAB;
-      const double x = ob.lnpix[i] - lnopz;
+      const double gc = gm_n / kFnuAB;
+      const double lpi = lp_n, ksi = ks_n;
+      {
+        const int inx = min(i + 256, np - 1);
+        gm_n = gm[inx];
+        lp_n = ob.lnpix[inx];
+        ks_n = ob.ksig[inx];
+      }
+      if ((i & 15) == 0) s_lp16[i >> 4] = lpi;
+      const double x = lpi - lnopz;
       int j0 = 1, j1 = 0;   // empty row
       float cf = 0.f, a0 = 0.f, hh = 0.f;
       if (x >= lnw0 && x <= lnw1) {
         // the forward pass's row on the log-uniform grid: position ux in node units,
         // width rs; nodes j0..j1 within five widths, or two nodes when the row is
         // narrower than half a node spacing
-        const double s = ob.ksig[i];
+        const double s = ksi;
         const double ux = (x - lnw0) * lib.inv_dlnw;
         if (s < 0.5 * dln) {   // linear row on nodes k, k+1 (marked by h = 0, t kept in a0)
           const int k = min((int)floor(ux), N - 2);
@@ -402,29 +414,56 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
         s_T[l] = Tl * Kf;
       }
       __syncthreads();
-      // pixels within 10 sigma of a line: a counted loop (its length bounded by the
-      // observation's smallest pixel spacing, pixels past the window masked), split over
-      // two threads per line when the lines fit, halves added in a fixed order
+      // pixels within 10 sigma of a line, split over two threads per line when the lines
+      // fit, halves added in a fixed order
       const int tpl = nl <= 128 ? 2 : 1;
       for (int l0 = tid; l0 < nl * tpl; l0 += 256) {
         const int l = l0 / tpl, part = l0 - l * tpl;
         const double mu = s_lnl[l], sl = s_sl[l];
         const double vhi = mu + 10.0 * sl;
-        const int ia = lower_bound_dev(ob.lnpix, np, mu - 10.0 * sl);
-        const int ib = (int)fmin((double)np, (double)ia + ceil(20.0 * sl * a.inv_pix_step) + 2.0);
+        // the pixels within 10 sigma: [ia, ib) with ia the first ln lambda >= mu - 10 sl and
+        // ib the first > mu + 10 sl, each by bisection on every 16th pixel in LDS, then the
+        // (at most 15) candidates of that block, loaded together
+        const int nc = (np + 15) >> 4;
+        auto first_pix = [&](double v, bool strict) {   // first i with lnpix[i] >= v (> v if strict)
+          int lo = 0, hi = nc;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (strict ? s_lp16[mid] <= v : s_lp16[mid] < v) lo = mid + 1; else hi = mid;
+          }
+          const int b0 = max(16 * (lo - 1) + 1, 0), b1 = min(16 * lo, np);
+          int cnt = 0;
+#pragma unroll
+          for (int e = 0; e < 15; ++e) {
+            const double x = ob.lnpix[min(b0 + e, np - 1)];
+            cnt += (b0 + e < b1) && (strict ? x <= v : x < v);
+          }
+          return b0 + cnt;
+        };
+        const int ia = first_pix(mu - 10.0 * sl, false);
+        const int ib = max(first_pix(vhi, true), ia);
         const int im = ia + (ib - ia + 1) / 2;
         const int i0 = tpl == 1 ? ia : (part == 0 ? ia : im), i1 = tpl == 1 ? ib : (part == 0 ? im : ib);
         double gFlx = 0.0, gzl = 0.0;
-        const double isl = 1.0 / sl;
-#pragma unroll 4
-        for (int i = i0; i < i1; ++i) {
-          const double lp = ob.lnpix[i];
-          if (lp <= vhi) {
-            const double u = (lp - mu) * isl;
-            const double Nn = (double)expf((float)(-0.5 * u * u)) * (isl / 2.5066282746310002);
-            const double glp = gm[i] / kFnuAB * ob.pix[i] * kAng_cm / kC_cms;
+        const double isl = 1.0 / sl, nrm = isl / 2.5066282746310002, gscale = kAng_cm / (kFnuAB * kC_cms);
+        const double zf = s_F[l] * isl / opz, df = s_F[l] * isl * s_dsl[l];
+        for (int ib8 = i0; ib8 < i1; ib8 += 8) {   // eight pixels' loads in flight (clamped)
+          double lpq[8], gq[8], pq[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int i = min(ib8 + e, np - 1);
+            lpq[e] = ob.lnpix[i];
+            gq[e] = gm[i];
+            pq[e] = ob.pix[i];
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            if (ib8 + e >= i1) break;
+            const double u = (lpq[e] - mu) * isl;
+            const double Nn = (double)expf((float)(-0.5 * u * u)) * nrm;
+            const double glp = gq[e] * pq[e] * gscale;
             gFlx += glp * Nn;
-            gzl += glp * s_F[l] * (Nn * u / sl / opz + Nn * (u * u - 1.0) / sl * s_dsl[l]);
+            gzl += glp * Nn * (u * zf + (u * u - 1.0) * df);
           }
         }
         if (tpl == 2) {
@@ -1373,7 +1412,7 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
     const double span = (o->host.lnpix.back() - o->host.lnpix.front()) * g.inv_dlnw + 2.0 * ext;
     const size_t cap = (size_t)std::min((double)g.N, std::ceil(span) + 4.0);
     const size_t gbf = (cap * 4 + 15) & ~(size_t)15;
-    const size_t t = ((4 * np + 15) & ~(size_t)15) + 12 * np + 2048;
+    const size_t t = ((4 * np + 15) & ~(size_t)15) + 12 * np + 2048 + 8 * (np / 16 + 2);
     if (gbf + lines_b + t <= 76 * 1024 && cap <= 256 * (size_t)kAdjOwn) {
       gb = gbf;
       extra = t;
