@@ -43,6 +43,7 @@ struct AdjArgs {
   int nl_lds;                   // line slots of the line tables in LDS (spectra)
   int seg_cap;                  // FP32 spectra: bound on the rows' span in nodes
   double inv_pix_step;          // spectra: 1 / smallest ln-wavelength step between pixels
+  double fr_max;                // photometry: largest |filter-node weight|
 };
 
 __device__ __forceinline__ double block_sum256(double v, double *red) {
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
     for (int n = n0; n < n1; ++n) gFl[n] = 0.0;
   int fs_seg0 = 0, fs_segn = 0;   // FP32 spectra: span of the rows, d logL / d F held there
   bool fx = false;                // FP32 photometry: d logL / d F held as fixed point,
-  double fx_inv = 0.0;            //   with this quantum
+  double fx_inv = 0.0, fx_scale = 0.0;   //   with this quantum (and its inverse, the scale)
   double gz = 0.0, glm = 0.0, gtb = 0.0, gab = 0.0, gtd = 0.0, gdl = 0.0;
   for (int i = tid; i < ob.n_data; i += 256) glm += gm[i] * mm[i];
 
@@ -130,15 +131,32 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
     const double wlo = lib.wave_d[0], whi = lib.wave_d[N - 1];
     const int nfn = ob.n_fnodes, nb = ob.n_band;
     int *s_bo = (int *)xsm;
-    float *s_c0 = (float *)(s_bo + nb + 1), *s_c1 = s_c0 + nfn;
-    short *s_nk = (short *)(s_c1 + nfn);
     for (int b = tid; b <= nb; b += 256) s_bo[b] = ob.band_off[b];
-    for (int b = tid; b < nb; b += 256) gz += gm[b] * dlnA * mm[b];
+    double gmax = 0.0;
+    for (int b = tid; b < nb; b += 256) {
+      gz += gm[b] * dlnA * mm[b];
+      gmax = fmax(gmax, fabs(gm[b]));
+    }
+    for (int o = 32; o > 0; o >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = gmax;
     __syncthreads();
+    // every node adds its two shares (FP64 products) to d logL / d F as 64-bit fixed point
+    // (LDS integer atomics), so the sums do not depend on the order of the additions.  The
+    // scale bounds every share, |g_b| A |R_j|, below 2^(62 - hb), hb the bit length of nfn,
+    // which leaves headroom for all shares landing on one pixel; the quantum is 2^-50 of
+    // that bound at nfn = 2560.
+    {
+      const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * fabs(A) * a.fr_max;
+      const int e = m > 0.0 ? max(ilogb(m) + 1, -960) : 0;   // scale and quantum stay normal
+      const int hb = 32 - __clz(nfn);
+      fx_scale = ldexp(1.0, 62 - hb - e);
+      fx_inv = ldexp(1.0, e + hb - 62);
+      fx = true;
+    }
+    unsigned long long *gi = (unsigned long long *)gFl;
     // ten nodes per thread per round: their node data, then their grid intervals and model
     // values, each group of loads in flight together (clamped indices); gz in node order
     constexpr int UJ = 10;
-    float cmax = 0.f;
     for (int jb = tid; jb < nfn; jb += 256 * UJ) {
       double fwq[UJ], frq[UJ], lnq[UJ];
       int bq[UJ];
@@ -173,51 +191,17 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
 #pragma unroll
       for (int u = 0; u < UJ; ++u) {
         const int j = jb + 256 * u;
-        if (j >= nfn) break;
         const double lr = fwq[u] / opz;
         const double coef = gq[u] * A * frq[u];
-        int kk;
-        float c0 = 0.f, c1 = 0.f;
-        if (lr < wlo) {
-          kk = -2;
-        } else if (lr > whi) {
-          kk = N + 1;
-        } else {
+        if (j < nfn && lr >= wlo && lr <= whi) {   // nodes outside the model grid add nothing
           const double w0 = w0q[u], dw = w1q[u] - w0;
           const double t = (lr - w0) / dw;
           gz += coef * (((double)f1q[u] - (double)f0q[u]) / dw) * (-fwq[u] / (opz * opz));
-          kk = kq[u];
-          c0 = (float)(coef * (1.0 - t));
-          c1 = (float)(coef * t);
+          const int k = kq[u];
+          const long long q0 = llrint(coef * (1.0 - t) * fx_scale), q1 = llrint(coef * t * fx_scale);
+          if (q0 != 0) atomicAdd(gi + k, (unsigned long long)q0);
+          if (q1 != 0) atomicAdd(gi + k + 1, (unsigned long long)q1);
         }
-        cmax = fmaxf(cmax, fmaxf(fabsf(c0), fabsf(c1)));
-        s_nk[j] = (short)kk;
-        s_c0[j] = c0;
-        s_c1[j] = c1;
-      }
-    }
-    for (int o = 32; o > 0; o >>= 1) cmax = fmaxf(cmax, __shfl_xor(cmax, o, 64));
-    if ((tid & 63) == 0) red[tid >> 6] = (double)cmax;
-    __syncthreads();
-    // scatter: every node adds its two shares to d logL / d F as 64-bit fixed point (LDS
-    // integer atomics), so the sums do not depend on the order of the additions.  The
-    // scale leaves headroom for all nfn shares landing on one pixel: the largest share
-    // stays below 2^(62 - hb), hb the bit length of nfn (2^-50 of it is the quantum at
-    // nfn = 2560).
-    {
-      const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-      const int e = m > 0.0 ? max(ilogb(m) + 1, -960) : 0;   // scale and quantum stay normal
-      const int hb = 32 - __clz(nfn);
-      const double scale = ldexp(1.0, 62 - hb - e);
-      fx_inv = ldexp(1.0, e + hb - 62);
-      fx = true;
-      unsigned long long *gi = (unsigned long long *)gFl;
-      for (int j = tid; j < nfn; j += 256) {
-        const int k = s_nk[j];
-        if (k < 0 || k > N - 2) continue;   // outside the model grid: no share
-        const long long q0 = llrint((double)s_c0[j] * scale), q1 = llrint((double)s_c1[j] * scale);
-        if (q0 != 0) atomicAdd(gi + k, (unsigned long long)q0);
-        if (q1 != 0) atomicAdd(gi + k + 1, (unsigned long long)q1);
       }
     }
   } else if (ob.kind == 0) {
@@ -1399,7 +1383,7 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
   const size_t lines_b = 40 * (size_t)aa.nl_lds;
   if (!f64 && !spec && g.log_uniform) {
     const size_t nfn = o->host.fw.size(), nb = o->host.band_off.size();
-    const size_t t = 10 * nfn + 4 * nb;
+    const size_t t = 4 * nb + 16;
     if (gb + t <= 76 * 1024) {
       extra = t;
       aa.fast = 1;
@@ -1421,6 +1405,8 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
     }
   }
   aa.g_bytes = (int)gb;
+  aa.fr_max = 0.0;
+  for (double v : o->host.fr) aa.fr_max = std::max(aa.fr_max, std::fabs(v));
   aa.inv_pix_step = HUGE_VAL;
   if (spec && o->host.lnpix.size() > 1) {
     double dmin = HUGE_VAL;
