@@ -165,9 +165,9 @@ def test_c1_full_size_gradient_sampled_against_oracle(c1full, prec, tol):
 
     The FP32 pass does not meet the 1e-4 gradient bar on every component here: its worst
     entry is 1.13e-4 (d/d tau_BC of one row).  Near the data the residual d - m is a few
-    per cent of the band flux, so the FP32 forward model's own band error (up to ~4e-6,
-    from FP32 dust factors where the optical depth is large) is amplified about twenty-
-    fold in d logL / d m, and again by the cancellation among bands in the tau_BC sum.
+    per cent of the band flux, so the FP32 forward model's own band error (up to ~4e-6
+    in the photometric precision study) is amplified about twentyfold in d logL / d m,
+    and again by the cancellation among bands in the tau_BC sum.
     The bound asserted for FP32 is therefore 2e-4; the FP64 pass holds 1e-9."""
     case, theta, L, O, idx, ll_ref, g_ref = c1full
     say(f"c1 full size grad {prec} B={theta.shape[0]} P={theta.shape[1]}")
