@@ -60,9 +60,75 @@ __global__ void __launch_bounds__(256) k_propose(const DevReq *__restrict__ reqs
 // stage 0: record logL(theta0).  stage >= 1: threshold = the logL at rank floor(B/4)
 // (ascending, ties by index, NaN as -inf) of the current live points; proposals above
 // it replace their point.  One workgroup per request finds the rank-q value by a bitonic
-// sort of (logL, index) pairs in LDS (batches above kUpdMax points count ranks
-// directly); the replacement then runs with one wave per point over the whole tick.
+// sort (batches above kUpdMax points count ranks directly); the replacement then runs
+// with one wave per point over the whole tick.  Only the value at rank q is needed, and
+// equal values are interchangeable, so up to 1024 points are sorted by value alone,
+// four per thread in registers: element i = 256 u + tid; partners 256 or more apart are
+// in the same thread, partners less than 64 apart in the same wave (shuffles), and only
+// the stages at distance 64 and 128 exchange through LDS.
 constexpr int kUpdMax = 2048;
+
+__device__ __forceinline__ double bitonic_keep(double v, double other, bool keep_min) {
+  return keep_min ? fmin(v, other) : fmax(v, other);
+}
+
+// q-th smallest of the (NaN-free) values of a request with B <= 1024 points
+__device__ double rank_value_1024(const double *__restrict__ x, int B, int q, double *s) {
+  const int tid = threadIdx.x;
+  double v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = 256 * u + tid;
+    double a = HUGE_VAL;   // padding sorts after every point
+    if (i < B) {
+      a = x[i];
+      if (isnan(a)) a = -HUGE_VAL;
+    }
+    v[u] = a;
+  }
+  for (int k = 2; k <= 1024; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 256) {   // partner in this thread: register u ^ (j / 256)
+        const int du = j >> 8;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int up = u ^ du;
+          if (up > u) {
+            const int i = 256 * u + tid;
+            const bool asc = (i & k) == 0;
+            const double a = v[u], b = v[up];
+            v[u] = asc ? fmin(a, b) : fmax(a, b);
+            v[up] = asc ? fmax(a, b) : fmin(a, b);
+          }
+        }
+      } else if (j < 64) {   // partner in this wave
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = 256 * u + tid;
+          const double other = __shfl_xor(v[u], j, 64);
+          v[u] = bitonic_keep(v[u], other, ((i & k) == 0) == ((i & j) == 0));
+        }
+      } else {   // partner in another wave of the workgroup
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[256 * u + tid] = v[u];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = 256 * u + tid;
+          v[u] = bitonic_keep(v[u], s[i ^ j], ((i & k) == 0) == ((i & j) == 0));
+        }
+        __syncthreads();
+      }
+    }
+  // the element at rank q is held by thread q % 256 in register q / 256
+  double r = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (256 * u + tid == q) r = v[u];
+  if (tid == (q & 255)) s[0] = r;
+  __syncthreads();
+  return s[0];
+}
 
 __global__ void __launch_bounds__(256) k_update_thr(const DevReq *__restrict__ reqs, double *__restrict__ thr) {
   __shared__ double sv[kUpdMax];
@@ -72,7 +138,10 @@ __global__ void __launch_bounds__(256) k_update_thr(const DevReq *__restrict__ r
   const int B = rq.B, tid = threadIdx.x;
   if (rq.stage == 0) return;
   const int q = B / 4;
-  if (B <= kUpdMax) {
+  if (B <= 1024) {
+    const double r = rank_value_1024(rq.logl_cur, B, q, sv);
+    if (tid == 0) thr[blockIdx.x] = r;
+  } else if (B <= kUpdMax) {
     int n2 = 1;
     while (n2 < B) n2 <<= 1;
     for (int i = tid; i < n2; i += 256) {
