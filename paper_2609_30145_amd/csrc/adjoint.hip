@@ -42,7 +42,6 @@ struct AdjArgs {
   int g_bytes;                  // bytes of the first dynamic LDS region (gF, or the span of rows)
   int nl_lds;                   // line slots of the line tables in LDS (spectra)
   int seg_cap;                  // FP32 spectra: bound on the rows' span in nodes
-  double inv_pix_step;          // spectra: 1 / smallest ln-wavelength step between pixels
   double fr_max;                // photometry: largest |filter-node weight|
 };
 
@@ -1407,12 +1406,7 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
   aa.g_bytes = (int)gb;
   aa.fr_max = 0.0;
   for (double v : o->host.fr) aa.fr_max = std::max(aa.fr_max, std::fabs(v));
-  aa.inv_pix_step = HUGE_VAL;
-  if (spec && o->host.lnpix.size() > 1) {
-    double dmin = HUGE_VAL;
-    for (size_t i = 1; i < o->host.lnpix.size(); ++i) dmin = std::min(dmin, o->host.lnpix[i] - o->host.lnpix[i - 1]);
-    if (dmin > 0.0) aa.inv_pix_step = 1.0 / dmin;
-  }
+
   const size_t sm1 = gb + lines_b + extra;
   static size_t attr1[2] = {0, 0};
   if (sm1 > 48 * 1024 && sm1 > attr1[f64 ? 1 : 0]) {
