@@ -64,10 +64,18 @@ __device__ __forceinline__ void bc32(v16f (&acc)[BM][BN], const float (*sp)[5], 
     }
 }
 
+// Gradient pass: the attenuation factors in FP64 from FP64 row parameters and column
+// tables, so that the model's band values (whose residuals the adjoint amplifies near the
+// data) carry no FP32 rounding of large optical depths.
+__device__ __forceinline__ void dust_f64(const double *spd, double l, double da, double dd, double &Tbc, double &Td) {
+  Tbc = exp(-spd[0] * exp(spd[1] * l));
+  Td = exp(-spd[2] * exp(spd[3] * l) * (da + spd[4] * dd));
+}
+
 template <int BM, int BN, int WTM, int WTN>
-__device__ __forceinline__ void bc32p(double (&acc)[BM][BN][16], const float (*sp)[5], const float *c_lnlv, const float *c_a,
-                                     const float *c_d, float *Yatt, int N_pad, int m0, int n0, int wm, int wn, int li,
-                                     int lh) {
+__device__ __forceinline__ void bc32p(double (&acc)[BM][BN][16], const double (*spd)[5], const double *c_l,
+                                      const double *c_a, const double *c_d, float *Yatt, int N_pad, int m0, int n0,
+                                      int wm, int wn, int li, int lh) {
 #pragma unroll
   for (int i = 0; i < BM; ++i)
 #pragma unroll
@@ -75,11 +83,12 @@ __device__ __forceinline__ void bc32p(double (&acc)[BM][BN][16], const float (*s
       const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
-        acc[i][j][e] *= (double)expf(-sp[rl][0] * expf(sp[rl][1] * c_lnlv[j]));
+        double Tbc, Td;
+        dust_f64(spd[rl], c_l[j], c_a[j], c_d[j], Tbc, Td);
+        acc[i][j][e] *= Tbc;
         if (Yatt) {
-          const float Td = expf(-sp[rl][2] * expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
           const int col = n0 + wn * WTN + j * 32 + li;
-          Yatt[(size_t)(m0 + rl) * N_pad + col] = (float)(acc[i][j][e] * (double)Td);
+          Yatt[(size_t)(m0 + rl) * N_pad + col] = (float)(acc[i][j][e] * Td);
         }
       }
     }
@@ -96,6 +105,7 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
   __shared__ __attribute__((aligned(16))) float As[MT * LDSK];
   __shared__ __attribute__((aligned(16))) float Bs[NT * LDSK];
   __shared__ float sp[MT][5];
+  __shared__ double spd[PRECISE ? MT : 1][5];
 
   int mt, nt;
   tile_of_block(a.N_pad / NT, mt, nt);
@@ -114,6 +124,13 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
     sp[r][2] = (float)pr.tau_diff;
     sp[r][3] = (float)pr.delta;
     sp[r][4] = (float)(0.85 - 1.9 * pr.delta);
+    if constexpr (PRECISE) {
+      spd[r][0] = pr.tau_bc;
+      spd[r][1] = pr.alpha_bc;
+      spd[r][2] = pr.tau_diff;
+      spd[r][3] = pr.delta;
+      spd[r][4] = 0.85 - 1.9 * pr.delta;
+    }
   }
 
   v16f acc[BM][BN];
@@ -151,12 +168,18 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
 
   // per-lane columns and their static factors
   float c_lnlv[BN], c_a[BN], c_d[BN];
+  double c_l64[PRECISE ? BN : 1], c_a64[PRECISE ? BN : 1], c_d64[PRECISE ? BN : 1];
 #pragma unroll
   for (int j = 0; j < BN; ++j) {
     const int col = n0 + wn * WTN + j * 32 + li;
     c_lnlv[j] = a.lnlv[col];
     c_a[j] = a.da[col];
     c_d[j] = a.dd[col];
+    if constexpr (PRECISE) {
+      c_l64[j] = a.lnlv_d[col];
+      c_a64[j] = a.da_d[col];
+      c_d64[j] = a.dd_d[col];
+    }
   }
 
   __syncthreads();
@@ -178,7 +201,7 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
                           // the memory-counter waits cover only the tile being stored
     if (t == ny) {
       if constexpr (PRECISE) {
-        bc32p<BM, BN, WTM, WTN>(dacc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
+        bc32p<BM, BN, WTM, WTN>(dacc, spd, c_l64, c_a64, c_d64, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
       } else {
         bc32<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
       }
@@ -224,7 +247,7 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
   if (ny == nact) {
     __syncthreads();
     if constexpr (PRECISE) {
-      bc32p<BM, BN, WTM, WTN>(dacc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
+      bc32p<BM, BN, WTM, WTN>(dacc, spd, c_l64, c_a64, c_d64, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
     } else {
       bc32<BM, BN, WTM, WTN>(acc, sp, c_lnlv, c_a, c_d, (float *)a.Yatt, a.N_pad, m0, n0, wm, wn, li, lh);
     }
@@ -241,9 +264,14 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
         const int col = n0 + wn * WTN + j * 32 + li;
-        const float Td = expf(-sp[rl][2] * expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
-        if constexpr (PRECISE) F[(size_t)(m0 + rl) * a.N_pad + col] = (float)(dacc[i][j][e] * (double)Td);
-        else F[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j][e] * Td;
+        if constexpr (PRECISE) {
+          double Tbc, Td;
+          dust_f64(spd[rl], c_l64[j], c_a64[j], c_d64[j], Tbc, Td);
+          F[(size_t)(m0 + rl) * a.N_pad + col] = (float)(dacc[i][j][e] * Td);
+        } else {
+          const float Td = expf(-sp[rl][2] * expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
+          F[(size_t)(m0 + rl) * a.N_pad + col] = acc[i][j][e] * Td;
+        }
       }
     }
 }

@@ -157,18 +157,17 @@ def c1full():
     return case, theta, L, O, idx, ll_ref, g_ref
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 2e-4)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-4)])
 def test_c1_full_size_gradient_sampled_against_oracle(c1full, prec, tol):
     """B = 1024 live points of the 20-band photometry near the data (the FP32 pass adds the
     filter-node shares to d logL / d F as fixed point in one launch); twelve rows spread
     over the batch are checked against the oracle adjoint.
 
-    The FP32 pass does not meet the 1e-4 gradient bar on every component here: its worst
-    entry is 1.13e-4 (d/d tau_BC of one row).  Near the data the residual d - m is a few
-    per cent of the band flux, so the FP32 forward model's own band error (up to ~4e-6
-    in the photometric precision study) is amplified about twentyfold in d logL / d m,
-    and again by the cancellation among bands in the tau_BC sum.
-    The bound asserted for FP32 is therefore 2e-4; the FP64 pass holds 1e-9."""
+    Near the data the residual d - m is a few per cent of the band flux, so a band error
+    of the forward model is amplified about twentyfold in d logL / d m.  The FP32 pass
+    therefore forms the attenuation factors of its forward contraction in FP64: with the
+    FP32 factors of the forward-only path (band errors up to ~4e-6 where the optical
+    depth is large) the worst entry here was 1.13e-4 (d/d tau_BC)."""
     case, theta, L, O, idx, ll_ref, g_ref = c1full
     say(f"c1 full size grad {prec} B={theta.shape[0]} P={theta.shape[1]}")
     ll, g = gpu_grad(L, O, theta, prec)
