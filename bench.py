@@ -130,9 +130,27 @@ def cpu_baseline(cfg_name, budget_s=12.0, seed=0):
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
-    return dict(value=n / dt, unit="evals/s", cores=int(cores), kind="oracle",
-                sample=f"{n} parameter vectors of the same workload in batches of {sample} "
-                       f"(FP64 NumPy, BLAS dgemm contraction), {dt:.1f} s")
+    out = dict(value=n / dt, unit="evals/s", cores=int(cores), kind="oracle",
+               sample=f"{n} parameter vectors of the same workload in batches of {sample} "
+                      f"(FP64 NumPy, BLAS dgemm contraction), {dt:.1f} s")
+    # the same oracle on one BLAS thread, over a shorter sample
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            n1 = 0
+            t1 = time.perf_counter()
+            while time.perf_counter() - t1 < budget_s / 3:
+                om.logl(olib, obs, theta[(n1 % cfg.batch):(n1 % cfg.batch) + sample])
+                n1 += sample
+            out["value_1_thread"] = n1 / (time.perf_counter() - t1)
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            out["cpu_model"] = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except Exception:
+        pass
+    return out
 
 
 def spectrum_leg(steps=20, warmup=3, seed=0):
@@ -269,7 +287,7 @@ def main():
                     help="length of the Poisson request stream of the serving leg (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this benchmark runs on one GPU; runs on several GPUs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
@@ -337,6 +355,18 @@ def main():
         "by_precision": {p: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                          for p, r in results.items()},
     }
+    # the HBM-bound regime: a batch of 64 points streams the whole library for few flops
+    nb = 64
+    dt64, tim64 = time_precision(L, O, theta[:nb], args.precision, max(20, args.steps // 2), args.warmup)
+    ms64 = tim64["ms_total"] / max(1, tim64["launches"])
+    b64 = alg_bytes(cfg, nb, args.precision)
+    out["small_batch"] = {"batch": nb, "precision": args.precision,
+                          "ms_per_step": round(1e3 * dt64 / max(20, args.steps // 2), 4),
+                          "evals_per_s": round(nb * max(20, args.steps // 2) / dt64, 1),
+                          "contract_ms": round(ms64, 4), "alg_bytes_per_launch": b64,
+                          "contract_achieved_GBps": round(b64 / (ms64 * 1e-3) / 1e9, 1),
+                          "hbm_peak_GBps": 8000.0,
+                          "hbm_frac": round(b64 / (ms64 * 1e-3) / 8e12, 4)}
     if not args.no_spectrum:
         out["spectrum"] = spectrum_leg()
     if args.serve_seconds > 0:
