@@ -281,6 +281,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--also", default="fp16,fp32,bf16", help="other precisions timed for the record")
     ap.add_argument("--no-spectrum", action="store_true", help="skip the spectroscopic leg")
+    ap.add_argument("--no-small-batch", action="store_true", help="skip the 64-point leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -356,17 +357,18 @@ def main():
                          for p, r in results.items()},
     }
     # the HBM-bound regime: a batch of 64 points streams the whole library for few flops
-    nb = 64
-    dt64, tim64 = time_precision(L, O, theta[:nb], args.precision, max(20, args.steps // 2), args.warmup)
-    ms64 = tim64["ms_total"] / max(1, tim64["launches"])
-    b64 = alg_bytes(cfg, nb, args.precision)
-    out["small_batch"] = {"batch": nb, "precision": args.precision,
-                          "ms_per_step": round(1e3 * dt64 / max(20, args.steps // 2), 4),
-                          "evals_per_s": round(nb * max(20, args.steps // 2) / dt64, 1),
-                          "contract_ms": round(ms64, 4), "alg_bytes_per_launch": b64,
-                          "contract_achieved_GBps": round(b64 / (ms64 * 1e-3) / 1e9, 1),
-                          "hbm_peak_GBps": 8000.0,
-                          "hbm_frac": round(b64 / (ms64 * 1e-3) / 8e12, 4)}
+    if not args.no_small_batch:
+        nb, st64 = 64, max(20, args.steps // 2)
+        dt64, tim64 = time_precision(L, O, theta[:nb], args.precision, st64, args.warmup)
+        ms64 = tim64["ms_total"] / max(1, tim64["launches"])
+        b64 = alg_bytes(cfg, nb, args.precision)
+        out["small_batch"] = {"batch": nb, "precision": args.precision,
+                              "ms_per_step": round(1e3 * dt64 / st64, 4),
+                              "evals_per_s": round(nb * st64 / dt64, 1),
+                              "contract_ms": round(ms64, 4), "alg_bytes_per_launch": b64,
+                              "contract_achieved_GBps": round(b64 / (ms64 * 1e-3) / 1e9, 1),
+                              "hbm_peak_GBps": 8000.0,
+                              "hbm_frac": round(b64 / (ms64 * 1e-3) / 8e12, 4)}
     if not args.no_spectrum:
         out["spectrum"] = spectrum_leg()
     if args.serve_seconds > 0:

@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   Acc *wacc = (Acc *)(smem + L.wacc);
   Acc *s_lt = (Acc *)(smem + L.lt);
   __shared__ double s_part[4];
-  __shared__ double s_tu;
+  __shared__ double s_tu, s_m10;
   __shared__ uint32_t s_bits[64];
   __shared__ int s_rank[4];
 
@@ -260,6 +260,9 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     }
     part = wave_sum(part);
     if (lane == 0) s_part[wv] = part;
+    // the mass scale 10^logmass, off the critical path (wave 2 has no quadrature nodes
+    // while n_gl <= 128)
+    if (wv == 2 && lane == 0) s_m10 = exp10(th[TH_LOGMASS]);
   } else {
     // (1+z)^{-3/2} by a square root and asinh(x) = ln(x + sqrt(x^2 + 1)) for x > 0: a
     // shorter chain of double-precision operations than the library pow and asinh
@@ -616,7 +619,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     pr.t_univ = s_tu;
     pr.dc = dc;
     pr.dl = (1.0 + z) * dc;
-    pr.mass10 = exp10(s_th[TH_LOGMASS]);
+    pr.mass10 = s_m10;
     pr.scale_fnu = pr.mass10 * (1.0 + z) / (4.0 * kPi * pr.dl * pr.dl) * kLsun * kAng_cm / kC_cms;
     pr.wscale = wscale;
     pr.tau_bc = s_th[TH_TAU_BC];
