@@ -471,27 +471,26 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
     __syncthreads();   // the rows no longer read f: the span now receives d logL / d F
     {
       // each thread owns at most kAdjOwn consecutive nodes of the span and adds, in pixel
-      // order, the rows that cover them: per row a window of kAdjOwn LDS values read
-      // together, updated, and written back under a mask (no read-modify-write chain)
+      // order, the rows that cover them into one register per owned node; a row's weights
+      // follow the recurrence from its first owned node on, and the nodes are written once
       const int c0 = tid * chunk_s, c1 = min(c0 + chunk_s, seg_n);
-      for (int cc = c0; cc < c1; ++cc) seg[cc] = 0.f;
       if (c0 < c1) {
         const int na0 = seg0 + c0, na1 = seg0 + c1 - 1;   // owned nodes
+        float acc[kAdjOwn];
+#pragma unroll
+        for (int e = 0; e < kAdjOwn; ++e) acc[e] = 0.f;
         for (int i = s_first[tid]; i <= s_last[tid]; ++i) {
           const int j0 = s_j0[i], j1 = s_j1[i];
           const int ja = max(j0, na0), jb = min(j1, na1);
           if (ja > jb) continue;
           const float cf = s_cf[i], hf = s_h[i];
-          const int base = ja - seg0, cnt = jb - ja;   // window [base, base + cnt]
-          float v[kAdjOwn];
-#pragma unroll
-          for (int e = 0; e < kAdjOwn; ++e) v[e] = seg[min(base + e, seg_n - 1)];
+          const int lo = ja - na0, hi = jb - na0;   // owned offsets the row covers
           if (hf == 0.f) {   // linear row on nodes j0 = k, j1 = k + 1
             const float t = s_a0[i];
 #pragma unroll
             for (int e = 0; e < kAdjOwn; ++e) {
-              const int j = ja + e;
-              v[e] += (j == j0 ? cf * (1.f - t) : 0.f) + (j == j1 ? cf * t : 0.f);
+              const int j = na0 + e;
+              acc[e] += (j == j0 ? cf * (1.f - t) : 0.f) + (j == j1 ? cf * t : 0.f);
             }
           } else {
             const float uu = fmaf((float)(ja - j0), hf, s_a0[i]);
@@ -499,15 +498,16 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
             const float cq = expf(-hf * hf);
 #pragma unroll
             for (int e = 0; e < kAdjOwn; ++e) {
-              v[e] += e <= cnt ? cf * w : 0.f;
-              w *= q;
-              q *= cq;
+              const bool on = e >= lo;   // the recurrence starts at the row's first owned node
+              acc[e] += on && e <= hi ? cf * w : 0.f;
+              w = on ? w * q : w;
+              q = on ? q * cq : q;
             }
           }
-#pragma unroll
-          for (int e = 0; e < kAdjOwn; ++e)
-            if (e <= cnt) seg[base + e] = v[e];
         }
+#pragma unroll
+        for (int e = 0; e < kAdjOwn; ++e)
+          if (c0 + e < c1) seg[c0 + e] = acc[e];
       }
     }
   } else {
