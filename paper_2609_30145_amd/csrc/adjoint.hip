@@ -8,6 +8,7 @@
 //   k_adj_prep   line luminosities (eq. C2) and SSP weights (App. B) back to theta,
 //                including the SFH edges' dependence on t_univ(z).
 #include <climits>
+#include <type_traits>
 
 #include "kernels.h"
 #include "runtime.h"
@@ -471,43 +472,43 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
     __syncthreads();   // the rows no longer read f: the span now receives d logL / d F
     {
       // each thread owns at most kAdjOwn consecutive nodes of the span and adds, in pixel
-      // order, the rows that cover them into one register per owned node; a row's weights
-      // follow the recurrence from its first owned node on, and the nodes are written once
+      // order, the rows that cover them into one register per owned node (as many
+      // registers as the owner size rounded up to 8, 12 or 16), then writes its nodes
+      // once.  A row's weight at node j is the Gaussian 2^(u^2 log2(e) / -2), u = (j - j0) h
+      // + a0, one hardware exp2 per node (the row normalisation G is the forward's).
       const int c0 = tid * chunk_s, c1 = min(c0 + chunk_s, seg_n);
-      if (c0 < c1) {
+      auto owner = [&](auto own_c) {
+        constexpr int OWN = decltype(own_c)::value;
         const int na0 = seg0 + c0, na1 = seg0 + c1 - 1;   // owned nodes
-        float acc[kAdjOwn];
+        float acc[OWN];
 #pragma unroll
-        for (int e = 0; e < kAdjOwn; ++e) acc[e] = 0.f;
+        for (int e = 0; e < OWN; ++e) acc[e] = 0.f;
         for (int i = s_first[tid]; i <= s_last[tid]; ++i) {
           const int j0 = s_j0[i], j1 = s_j1[i];
-          const int ja = max(j0, na0), jb = min(j1, na1);
-          if (ja > jb) continue;
-          const float cf = s_cf[i], hf = s_h[i];
-          const int lo = ja - na0, hi = jb - na0;   // owned offsets the row covers
-          if (hf == 0.f) {   // linear row on nodes j0 = k, j1 = k + 1
-            const float t = s_a0[i];
+          if (max(j0, na0) > min(j1, na1)) continue;
+          const float cf = s_cf[i], hf = s_h[i], a0 = s_a0[i];
+          const int lo = j0 - na0, hi = j1 - na0;   // the row's nodes as owned offsets
+          if (hf == 0.f) {   // linear row on nodes j0 = k, j1 = k + 1 (a0 holds t)
 #pragma unroll
-            for (int e = 0; e < kAdjOwn; ++e) {
-              const int j = na0 + e;
-              acc[e] += (j == j0 ? cf * (1.f - t) : 0.f) + (j == j1 ? cf * t : 0.f);
-            }
+            for (int e = 0; e < OWN; ++e) acc[e] += (e == lo ? cf * (1.f - a0) : 0.f) + (e == hi ? cf * a0 : 0.f);
           } else {
-            const float uu = fmaf((float)(ja - j0), hf, s_a0[i]);
-            float w = expf(-0.5f * uu * uu), q = expf(-uu * hf - 0.5f * hf * hf);
-            const float cq = expf(-hf * hf);
+            const float ub = fmaf((float)(na0 - j0), hf, a0);   // u at the first owned node
 #pragma unroll
-            for (int e = 0; e < kAdjOwn; ++e) {
-              const bool on = e >= lo;   // the recurrence starts at the row's first owned node
-              acc[e] += on && e <= hi ? cf * w : 0.f;
-              w = on ? w * q : w;
-              q = on ? q * cq : q;
+            for (int e = 0; e < OWN; ++e) {
+              const float u = fmaf((float)e, hf, ub);
+              const float w = __builtin_amdgcn_exp2f(u * u * -0.72134752044448170f);
+              acc[e] += e >= lo && e <= hi ? cf * w : 0.f;
             }
           }
         }
 #pragma unroll
-        for (int e = 0; e < kAdjOwn; ++e)
+        for (int e = 0; e < OWN; ++e)
           if (c0 + e < c1) seg[c0 + e] = acc[e];
+      };
+      if (c0 < c1) {
+        if (chunk_s <= 8) owner(std::integral_constant<int, 8>{});
+        else if (chunk_s <= 12) owner(std::integral_constant<int, 12>{});
+        else owner(std::integral_constant<int, kAdjOwn>{});
       }
     }
   } else {
