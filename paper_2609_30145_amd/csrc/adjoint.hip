@@ -748,12 +748,14 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
 // ---------------------------------------------------------------------------------
 // dW[r][k] = sum_n G_seg(k)[r][n] L[k][n]; G_Y for young-segment columns, G_O for old.
 // FP32: MFMA 32x32x2 with the reduction (wavelength) axis contiguous in both operands.
+// With n_split = 2 the wavelength tiles are halved between two blocks per output tile,
+// which write dW and dW + split_stride; the weight-builder adjoint adds the two halves.
 // ---------------------------------------------------------------------------------
 template <int MT, int NT>
 __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, const float *__restrict__ GO,
                                                  const float *__restrict__ Ln, int N_pad, int K_pad, int K_young_pad,
                                                  const uint32_t *__restrict__ rowmask, int mask_words,
-                                                 double *__restrict__ dW) {
+                                                 double *__restrict__ dW, int n_split, size_t split_stride) {
   constexpr int KT = 32, LDSK = KT + 4, WM = 2, WN = 2;
   constexpr int WTM = MT / WM, WTN = NT / WN, BM = WTM / 32, BN = WTN / 32;
   constexpr int A4 = MT * KT / 4 / 256, B4 = NT * KT / 4 / 256;
@@ -761,7 +763,9 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
   __shared__ __attribute__((aligned(16))) float Bs[2][NT * LDSK];
   __shared__ uint32_t s_any;
   const int n_ct = K_pad / NT;
-  const int mt = blockIdx.x / n_ct, ct = blockIdx.x % n_ct;
+  const int tile = blockIdx.x / n_split, half = blockIdx.x - tile * n_split;
+  const int mt = tile / n_ct, ct = tile % n_ct;
+  dW += half * split_stride;
   const int m0 = mt * MT, c0 = ct * NT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN, li = lane & 31, lh = lane >> 5;
@@ -794,7 +798,8 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
 #pragma unroll
       for (int e = 0; e < 16; ++e) dacc[i][j][e] = 0.0;
   f32x4 ra[A4], rb[B4];
-  const int nt = N_pad / KT;
+  const int nt_all = N_pad / KT;
+  const int ta = nt_all * half / n_split, nt = nt_all * (half + 1) / n_split;   // this block's wavelength tiles
 #define SPS_BWD_LOAD(k0_)                                                                  \
   {                                                                                        \
     _Pragma("unroll") for (int q = 0; q < A4; ++q) {                                       \
@@ -817,12 +822,12 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
       *(f32x4 *)(Bs[buf_] + row * LDSK + c4 * 4) = rb[q];                                  \
     }                                                                                      \
   }
-  SPS_BWD_LOAD(0);
+  SPS_BWD_LOAD(ta * KT);
   SPS_BWD_STORE(0);
   // double-buffered: the tile t + 1 is loaded into registers during the products of tile
   // t and stored into the other buffer, whose last readers finished before the barrier
-  for (int t = 0; t < nt; ++t) {
-    const int buf = t & 1;
+  for (int t = ta; t < nt; ++t) {
+    const int buf = (t - ta) & 1;
     SPS_BWD_LOAD(min(t + 1, nt - 1) * KT);
     __syncthreads();
     float af[BM][16], bf[BN][16];
@@ -922,6 +927,7 @@ struct AdjPrepArgs {
   int P, B;
   const PointRow *rows;
   const void *dW;
+  const double *dW2;   // second half of the FP32 dW split over wavelengths, or NULL
   int f64;
   const int *kpos;
   int line_k0;
@@ -994,12 +1000,24 @@ __global__ void __launch_bounds__(256, 4) k_adj_prep(DevLib lib, AdjPrepArgs a) 
   // ---- the row of d logL / d W, the node-table block and the bin masses to LDS
   {
     const double2 *g2 = (const double2 *)((const double *)a.dW + (size_t)r * K_pad);   // K_pad even
+    // FP32 pass: dW in two wavelength halves, added here (first half + second half)
+    const double2 *h2 = a.dW2 ? (const double2 *)(a.dW2 + (size_t)r * K_pad) : nullptr;
     const double2 *t2 = (const double2 *)lib.prep_tab;                                  // even length
     const int ng2 = K_pad >> 1, nt2 = prep_tab_len(lib) >> 1;
     double2 vg[5], vt[2];
     double vm;
 #pragma unroll
     for (int u = 0; u < 5; ++u) vg[u] = g2[min(tid + 256 * u, ng2 - 1)];
+    if (h2) {
+      double2 vh[5];
+#pragma unroll
+      for (int u = 0; u < 5; ++u) vh[u] = h2[min(tid + 256 * u, ng2 - 1)];
+#pragma unroll
+      for (int u = 0; u < 5; ++u) {
+        vg[u].x += vh[u].x;
+        vg[u].y += vh[u].y;
+      }
+    }
 #pragma unroll
     for (int u = 0; u < 2; ++u) vt[u] = t2[min(tid + 256 * u, nt2 - 1)];
     vm = th[TH_NSCALAR + min(tid, n - 1)];
@@ -1012,7 +1030,12 @@ __global__ void __launch_bounds__(256, 4) k_adj_prep(DevLib lib, AdjPrepArgs a) 
       }
     }
     for (int i = tid + 256 * 5; i < ng2; i += 256) {
-      const double2 v = g2[i];
+      double2 v = g2[i];
+      if (h2) {
+        const double2 vh = h2[i];
+        v.x += vh.x;
+        v.y += vh.y;
+      }
       gacc[2 * i] = v.x;
       gacc[2 * i + 1] = v.y;
     }
@@ -1419,15 +1442,21 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
   (void)hipGetLastError();   // drop a stale code from an unrelated earlier HIP call of this thread
   if (f64) hipLaunchKernelGGL(k_adj_proj<double>, dim3(B), dim3(256), sm1, s, g, aa);
   else hipLaunchKernelGGL(k_adj_proj<float>, dim3(B), dim3(256), sm1, s, g, aa);
+  int n_split = 1;   // FP32 dW: wavelength halves (see below)
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
     if (f64) {
       hipLaunchKernelGGL(k_bwd_f64, dim3((B_pad / 64) * (g.K_pad / 64)), dim3(256), 0, s, (const double *)aa.GY,
                          (const double *)aa.GO, g.LT64, g.N_pad, g.K_pad, g.K_young_pad, (double *)w.dW);
     } else {
-      hipLaunchKernelGGL((k_bwd_f32<64, 64>), dim3((B_pad / 64) * (g.K_pad / 64)), dim3(256), 0, s,
-                         (const float *)aa.GY, (const float *)aa.GO, g.L32n, g.N_pad, g.K_pad, g.K_young_pad,
-                         (const uint32_t *)w.rowmask, w.mask_words, (double *)w.dW);
+      // halve the wavelength range over two blocks per output tile when that lowers the
+      // largest number of tiles any CU has to finish (four blocks fit a CU)
+      const int n_tiles = (B_pad / 64) * (g.K_pad / 64);
+      const int full = (n_tiles + 255) / 256, halves = (2 * n_tiles + 255) / 256;
+      n_split = halves < 2 * full ? 2 : 1;
+      hipLaunchKernelGGL((k_bwd_f32<64, 64>), dim3(n_tiles * n_split), dim3(256), 0, s, (const float *)aa.GY,
+                         (const float *)aa.GO, g.L32n, g.N_pad, g.K_pad, g.K_young_pad, (const uint32_t *)w.rowmask,
+                         w.mask_words, (double *)w.dW, n_split, (size_t)w.B_pad_max * g.K_pad);
     }
     e = hipGetLastError();
   }
@@ -1438,6 +1467,7 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
     ap.B = B;
     ap.rows = w.rows;
     ap.dW = w.dW;
+    ap.dW2 = n_split == 2 ? (const double *)w.dW + (size_t)w.B_pad_max * g.K_pad : nullptr;
     ap.f64 = f64 ? 1 : 0;
     ap.kpos = L->kpos_d;
     ap.line_k0 = L->line_k0;

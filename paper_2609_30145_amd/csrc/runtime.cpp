@@ -39,7 +39,7 @@ sps_status Workspace::create(const sps_library *L, int mb, int n_data, int n_fno
   scr = (double *)al(gb * (size_t)std::max(1, ld_scr) * 8);
   dLl = (double *)al(gb * (size_t)std::max(1, g.n_line) * 8);
   G = al(gb * g.N_pad * 8 * 2);
-  dW = al(gb * g.K_pad * 8);
+  dW = al(gb * g.K_pad * 8 * 2);   // FP32 gradient: two wavelength halves
   counter = (unsigned long long *)al(8);
   if (!ok) return fail(SPS_E_NOMEM, "workspace allocation failed (max_batch=%d)", mb);
   if (hipMemset(counter, 0, 8) != hipSuccess) return fail(SPS_E_HIP, "hipMemset failed");

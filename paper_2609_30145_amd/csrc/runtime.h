@@ -39,7 +39,7 @@ struct Workspace {
   int ld_scr = 0;
   double *dLl = nullptr;         // adjoint d logL / d L_line [B_pad][n_line]
   void *G = nullptr;             // adjoint [B_pad][N_pad] float/double
-  void *dW = nullptr;            // adjoint [B_pad][K_pad] float/double
+  void *dW = nullptr;            // adjoint [2][B_pad_max][K_pad] double (two wavelength halves)
   unsigned long long *counter = nullptr;
   sps_status create(const sps_library *L, int max_batch, int n_data, int n_fnodes, bool forward_only = false);
 };
