@@ -431,17 +431,18 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
         double gFlx = 0.0, gzl = 0.0;
         const double isl = 1.0 / sl, nrm = isl / 2.5066282746310002, gscale = kAng_cm / (kFnuAB * kC_cms);
         const double zf = s_F[l] * isl / opz, df = s_F[l] * isl * s_dsl[l];
-        for (int ib8 = i0; ib8 < i1; ib8 += 8) {   // eight pixels' loads in flight (clamped)
-          double lpq[8], gq[8], pq[8];
+        constexpr int LB = 16;   // pixels whose loads are in flight together (clamped)
+        for (int ib8 = i0; ib8 < i1; ib8 += LB) {
+          double lpq[LB], gq[LB], pq[LB];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
+          for (int e = 0; e < LB; ++e) {
             const int i = min(ib8 + e, np - 1);
             lpq[e] = ob.lnpix[i];
             gq[e] = gm[i];
             pq[e] = ob.pix[i];
           }
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
+          for (int e = 0; e < LB; ++e) {
             if (ib8 + e >= i1) break;
             const double u = (lpq[e] - mu) * isl;
             const double Nn = (double)expf((float)(-0.5 * u * u)) * nrm;
