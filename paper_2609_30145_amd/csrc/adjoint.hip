@@ -751,18 +751,23 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
 // FP32: MFMA 32x32x2 with the reduction (wavelength) axis contiguous in both operands.
 // With n_split = 2 the wavelength tiles are halved between two blocks per output tile,
 // which write dW and dW + split_stride; the weight-builder adjoint adds the two halves.
+// With rows given (photometry on a log-uniform grid), G is zero outside each row's
+// rest-frame span under the filters, so the block's wavelength range is the union of
+// its rows' spans (two nodes of margin each side).
 // ---------------------------------------------------------------------------------
 template <int MT, int NT>
 __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, const float *__restrict__ GO,
                                                  const float *__restrict__ Ln, int N_pad, int K_pad, int K_young_pad,
                                                  const uint32_t *__restrict__ rowmask, int mask_words,
-                                                 double *__restrict__ dW, int n_split, size_t split_stride) {
+                                                 double *__restrict__ dW, int n_split, size_t split_stride,
+                                                 const PointRow *__restrict__ rows) {
   constexpr int KT = 32, LDSK = KT + 4, WM = 2, WN = 2;
   constexpr int WTM = MT / WM, WTN = NT / WN, BM = WTM / 32, BN = WTN / 32;
   constexpr int A4 = MT * KT / 4 / 256, B4 = NT * KT / 4 / 256;
   __shared__ __attribute__((aligned(16))) float As[2][MT * LDSK];
   __shared__ __attribute__((aligned(16))) float Bs[2][NT * LDSK];
   __shared__ uint32_t s_any;
+  __shared__ int s_lo, s_hi, s_full;
   const int n_ct = K_pad / NT;
   const int tile = blockIdx.x / n_split, half = blockIdx.x - tile * n_split;
   const int mt = tile / n_ct, ct = tile % n_ct;
@@ -772,8 +777,24 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
   const int wm = wave / WN, wn = wave % WN, li = lane & 31, lh = lane >> 5;
   // a column tile whose weights are zero in every row of the block needs no product: the
   // rows' occupancy bits (32-wide K tiles) decide, and the block writes zeros
-  if (tid == 0) s_any = 0u;
+  if (tid == 0) {
+    s_any = 0u;
+    s_lo = INT_MAX;
+    s_hi = 0;
+    s_full = rows ? 0 : 1;
+  }
   __syncthreads();
+  if (rows && tid < MT) {
+    const PointRow &pr = rows[m0 + tid];
+    if (pr.b >= 0) {
+      if (pr.kind != 0 || pr.seg_n <= 0) {
+        s_full = 1;
+      } else {
+        atomicMin(&s_lo, pr.seg0 - 2);
+        atomicMax(&s_hi, pr.seg0 + pr.seg_n + 2);
+      }
+    }
+  }
   if (rowmask) {
     uint32_t any = 0u;
     for (int rr = tid; rr < MT; rr += 256)
@@ -800,7 +821,12 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
       for (int e = 0; e < 16; ++e) dacc[i][j][e] = 0.0;
   f32x4 ra[A4], rb[B4];
   const int nt_all = N_pad / KT;
-  const int ta = nt_all * half / n_split, nt = nt_all * (half + 1) / n_split;   // this block's wavelength tiles
+  int t_lo = 0, t_hi = nt_all;   // wavelength tiles where some row's G can be nonzero
+  if (!s_full) {
+    t_lo = min(max(s_lo, 0) / KT, nt_all);
+    t_hi = max(min((s_hi + KT - 1) / KT, nt_all), t_lo);
+  }
+  const int ta = t_lo + (t_hi - t_lo) * half / n_split, nt = t_lo + (t_hi - t_lo) * (half + 1) / n_split;
 #define SPS_BWD_LOAD(k0_)                                                                  \
   {                                                                                        \
     _Pragma("unroll") for (int q = 0; q < A4; ++q) {                                       \
@@ -823,8 +849,10 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
       *(f32x4 *)(Bs[buf_] + row * LDSK + c4 * 4) = rb[q];                                  \
     }                                                                                      \
   }
-  SPS_BWD_LOAD(ta * KT);
-  SPS_BWD_STORE(0);
+  if (ta < nt) {   // an empty range leaves this half's dW zero
+    SPS_BWD_LOAD(ta * KT);
+    SPS_BWD_STORE(0);
+  }
   // double-buffered: the tile t + 1 is loaded into registers during the products of tile
   // t and stored into the other buffer, whose last readers finished before the barrier
   for (int t = ta; t < nt; ++t) {
@@ -1457,7 +1485,8 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
       n_split = halves < 2 * full ? 2 : 1;
       hipLaunchKernelGGL((k_bwd_f32<64, 64>), dim3(n_tiles * n_split), dim3(256), 0, s, (const float *)aa.GY,
                          (const float *)aa.GO, g.L32n, g.N_pad, g.K_pad, g.K_young_pad, (const uint32_t *)w.rowmask,
-                         w.mask_words, (double *)w.dW, n_split, (size_t)w.B_pad_max * g.K_pad);
+                         w.mask_words, (double *)w.dW, n_split, (size_t)w.B_pad_max * g.K_pad,
+                         !spec && g.log_uniform ? (const PointRow *)w.rows : nullptr);
     }
     e = hipGetLastError();
   }
