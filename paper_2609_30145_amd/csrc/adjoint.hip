@@ -751,16 +751,19 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
 // FP32: MFMA 32x32x2 with the reduction (wavelength) axis contiguous in both operands.
 // With n_split = 2 the wavelength tiles are halved between two blocks per output tile,
 // which write dW and dW + split_stride; the weight-builder adjoint adds the two halves.
-// With rows given (photometry on a log-uniform grid), G is zero outside each row's
-// rest-frame span under the filters, so the block's wavelength range is the union of
-// its rows' spans (two nodes of margin each side).
+// With rows given (a log-uniform grid), G is zero outside each row's rest-frame span:
+// the span under the filters for photometry (span_mode 1), and for spectra (span_mode 2)
+// the pixels' rest-frame range widened by the LSF rows, [su0, su1] - ln(1+z)/dln in node
+// units; the block's wavelength range is the union of its rows' spans (two nodes of
+// margin each side).
 // ---------------------------------------------------------------------------------
 template <int MT, int NT>
 __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, const float *__restrict__ GO,
                                                  const float *__restrict__ Ln, int N_pad, int K_pad, int K_young_pad,
                                                  const uint32_t *__restrict__ rowmask, int mask_words,
                                                  double *__restrict__ dW, int n_split, size_t split_stride,
-                                                 const PointRow *__restrict__ rows) {
+                                                 const PointRow *__restrict__ rows, int span_mode, double su0,
+                                                 double su1, double inv_dlnw) {
   constexpr int KT = 32, LDSK = KT + 4, WM = 2, WN = 2;
   constexpr int WTM = MT / WM, WTN = NT / WN, BM = WTM / 32, BN = WTN / 32;
   constexpr int A4 = MT * KT / 4 / 256, B4 = NT * KT / 4 / 256;
@@ -787,11 +790,15 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
   if (rows && tid < MT) {
     const PointRow &pr = rows[m0 + tid];
     if (pr.b >= 0) {
-      if (pr.kind != 0 || pr.seg_n <= 0) {
-        s_full = 1;
-      } else {
+      if (span_mode == 2 && pr.kind != 0) {
+        const double off = log1p(pr.z) * inv_dlnw;
+        atomicMin(&s_lo, (int)floor(su0 - off) - 2);
+        atomicMax(&s_hi, (int)ceil(su1 - off) + 3);
+      } else if (span_mode == 1 && pr.kind == 0 && pr.seg_n > 0) {
         atomicMin(&s_lo, pr.seg0 - 2);
         atomicMax(&s_hi, pr.seg0 + pr.seg_n + 2);
+      } else {
+        s_full = 1;
       }
     }
   }
@@ -1478,6 +1485,16 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
       hipLaunchKernelGGL(k_bwd_f64, dim3((B_pad / 64) * (g.K_pad / 64)), dim3(256), 0, s, (const double *)aa.GY,
                          (const double *)aa.GO, g.LT64, g.N_pad, g.K_pad, g.K_young_pad, (double *)w.dW);
     } else {
+      // spectra: the pixels' range in node units (rest frame at z = 0), widened by five
+      // LSF widths and two nodes, as the projection's row span
+      double su0 = 0.0, su1 = 0.0;
+      if (spec && o->host.n_data > 0) {
+        double kmax = 0.0;
+        for (double v : o->host.ksig) kmax = std::max(kmax, v);
+        const double ext = 5.0 * kmax * g.inv_dlnw + 2.0;
+        su0 = (o->host.lnpix.front() - g.lnw0) * g.inv_dlnw - ext;
+        su1 = (o->host.lnpix.back() - g.lnw0) * g.inv_dlnw + ext;
+      }
       // halve the wavelength range over two blocks per output tile when that lowers the
       // largest number of tiles any CU has to finish (four blocks fit a CU)
       const int n_tiles = (B_pad / 64) * (g.K_pad / 64);
@@ -1486,7 +1503,7 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
       hipLaunchKernelGGL((k_bwd_f32<64, 64>), dim3(n_tiles * n_split), dim3(256), 0, s, (const float *)aa.GY,
                          (const float *)aa.GO, g.L32n, g.N_pad, g.K_pad, g.K_young_pad, (const uint32_t *)w.rowmask,
                          w.mask_words, (double *)w.dW, n_split, (size_t)w.B_pad_max * g.K_pad,
-                         !spec && g.log_uniform ? (const PointRow *)w.rows : nullptr);
+                         g.log_uniform ? (const PointRow *)w.rows : nullptr, spec ? 2 : 1, su0, su1, g.inv_dlnw);
     }
     e = hipGetLastError();
   }
