@@ -52,7 +52,7 @@ def _fd(L, obs, th, cols_to_check, h=1e-6, trunc=5.0):
 def _check(L, obs, theta, cols, trunc=5.0, tol=2e-5):
     for b in range(theta.shape[0]):
         ll, g = adjoint.grad_point(L, obs, theta[b], trunc)
-        assert ll == pytest.approx(om.logl(L, obs, theta[b], trunc=trunc)[0], rel=1e-12)
+        assert ll == pytest.approx(om.logl(L, obs, theta[b], trunc=trunc)[0], rel=1e-12, abs=0.0)
         fd = _fd(L, obs, theta[b], cols, trunc=trunc)
         gmax = max(abs(v) for v in fd.values())
         for c, v in fd.items():
@@ -110,4 +110,4 @@ def test_logmass_gradient_closed_form():
         m = om.predict(L, obs, theta[b])[0]
         expect = math.log(10) * np.sum(m * (obs.data - m) / obs.sigma ** 2)
         _, g = adjoint.grad_point(L, obs, theta[b])
-        assert g[cols["logmass"]] == pytest.approx(expect, rel=1e-12)
+        assert g[cols["logmass"]] == pytest.approx(expect, rel=1e-12, abs=0.0)

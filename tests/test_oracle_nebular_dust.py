@@ -22,7 +22,7 @@ def test_ionising_rate_matches_fnu_form_of_eq_C1():
     f_nu = f_lam_cm * lam_cm ** 2 / C_CMS            # Lsun per Hz
     integrand = f_nu / lam_cm
     q_ref = LSUN / H_PLANCK * np.sum(0.5 * (integrand[1:] + integrand[:-1]) * np.diff(lam_cm))
-    assert Q == pytest.approx(q_ref, rel=1e-12)
+    assert Q == pytest.approx(q_ref, rel=1e-12, abs=0.0)
 
 
 def test_ionising_rate_flat_spectrum_closed_form():
@@ -30,7 +30,7 @@ def test_ionising_rate_flat_spectrum_closed_form():
     flux = np.full((1, 1, 1, len(wave)), 2.0)
     Q = nebular.ionising_rate(wave, flux)[0, 0, 0]
     # int_100^912 2 lambda dlambda = 912^2 - 100^2  [Lsun A per Msun]
-    assert Q == pytest.approx(LSUN * ANG * (912.0 ** 2 - 100.0 ** 2) / (H_PLANCK * C_CMS), rel=1e-13)
+    assert Q == pytest.approx(LSUN * ANG * (912.0 ** 2 - 100.0 ** 2) / (H_PLANCK * C_CMS), rel=1e-13, abs=0.0)
 
 
 def test_line_profiles_conserve_flux_and_have_two_pixel_sigma():
@@ -40,13 +40,13 @@ def test_line_profiles_conserve_flux_and_have_two_pixel_sigma():
     for l, lam in enumerate(lines):
         g = G[l]
         # integral over the grid, by an independent trapezoid, is 1
-        assert np.trapezoid(g, wave) == pytest.approx(1.0, rel=1e-12)
+        assert np.trapezoid(g, wave) == pytest.approx(1.0, rel=1e-12, abs=0.0)
         mean = np.trapezoid(g * wave, wave)
         var = np.trapezoid(g * (wave - mean) ** 2, wave)
         k = np.searchsorted(wave, lam) - 1
         pix = wave[k + 1] - wave[k]
         assert abs(mean - lam) < 0.05 * pix
-        assert math.sqrt(var) == pytest.approx(2.0 * pix, rel=0.03)
+        assert math.sqrt(var) == pytest.approx(2.0 * pix, rel=0.03, abs=0.0)
         assert np.count_nonzero(g) <= 21
 
 
@@ -87,7 +87,7 @@ def test_dust_zero_optical_depth_is_identity():
 def test_dust_optical_depth_at_v_band():
     # at 5500 A with a(V)=1, d(V)=0 the optical depth is the parameter itself
     t = dust.diffuse_tau(np.array([5500.0]), 0.8, -0.4, np.array([1.0]), np.array([0.0]))
-    assert t[0] == pytest.approx(0.8, rel=1e-15)
+    assert t[0] == pytest.approx(0.8, rel=1e-15, abs=0.0)
     t = dust.birth_cloud_tau(np.array([5500.0, 11000.0]), 1.2, -0.7)
     assert t[0] == pytest.approx(1.2) and t[1] == pytest.approx(1.2 * 2 ** -0.7)
     # the bump strength falls with delta: E_b(0) = 0.85, E_b(0.2) = 0.47

@@ -62,7 +62,7 @@ def test_filter_interpolation_linear_is_exact():
     f_ab = FNU_AB * C_CMS / (lam * ANG_CM) ** 2
     dl = projection.local_spacing(lam)
     ref = np.sum(R * lam * dl * 1e-18 * (1 + 1e-5 * lam)) / np.sum(R * lam * dl * f_ab)
-    assert m == pytest.approx(ref, rel=1e-13)
+    assert m == pytest.approx(ref, rel=1e-13, abs=0.0)
 
 
 # ---------------------------------------------------------------------------- spectra
@@ -116,7 +116,7 @@ def test_lsf_gaussian_widths_compose_in_quadrature():
     var = np.sum(w * (lnp - mu) ** 2)
     expect = s_in ** 2 + (sig[1500] / C_KMS) ** 2
     assert mu == pytest.approx(math.log(20000.0), abs=1e-4)
-    assert var == pytest.approx(expect, rel=0.02)
+    assert var == pytest.approx(expect, rel=0.02, abs=0.0)
 
 
 def test_narrow_lsf_reduces_to_linear_interpolation():
@@ -136,7 +136,7 @@ def test_line_profiles_on_pixels_integrate_to_line_flux():
     f = projection.line_profile_pixels(pix, Fl, lobs, s)
     nu = C_CMS / (pix * ANG_CM)
     total = -np.trapezoid(f, nu)
-    assert total == pytest.approx(Fl.sum(), rel=1e-6)
+    assert total == pytest.approx(Fl.sum(), rel=1e-6, abs=0.0)
 
 
 # ---------------------------------------------------------------------------- likelihood
@@ -146,9 +146,9 @@ def test_logl_matches_normal_logpdf_and_perfect_model():
     m = d + rng.normal(size=30) * 0.1
     s = rng.uniform(0.05, 0.3, 30)
     mask = likelihood.inclusion_mask(d, s)
-    assert likelihood.lnlike(d, m, s, mask) == pytest.approx(stats.norm.logpdf(d, m, s).sum(), rel=1e-13)
+    assert likelihood.lnlike(d, m, s, mask) == pytest.approx(stats.norm.logpdf(d, m, s).sum(), rel=1e-13, abs=0.0)
     assert likelihood.lnlike(d, d, s, mask) == pytest.approx(-0.5 * np.sum(np.log(2 * np.pi * s ** 2)),
-                                                             rel=1e-14)
+                                                             rel=1e-14, abs=0.0)
 
 
 def test_mask_excludes_bad_data():
@@ -168,7 +168,7 @@ def test_noise_scale_maximum_at_chi2_over_n():
     res = optimize.minimize_scalar(lambda sc: -likelihood.lnlike(d, m, s, mask, s=sc),
                                    bounds=(0.1, 10), method="bounded", options=dict(xatol=1e-10))
     chi2 = np.sum((d / s) ** 2)
-    assert res.x == pytest.approx(math.sqrt(chi2 / 40), rel=1e-6)
+    assert res.x == pytest.approx(math.sqrt(chi2 / 40), rel=1e-6, abs=0.0)
 
 
 def test_noise_floor_terms_add_in_quadrature():

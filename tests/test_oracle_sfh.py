@@ -62,7 +62,7 @@ def test_single_age_bin_goes_to_one_node():
 
 def test_edges_rescale_to_age_of_universe():
     e = sfh.sfh_edges(5e9, 12, 3e6)
-    assert e[0] == 0 and e[1] == 3e6 and e[-1] == pytest.approx(5e9, rel=1e-15)
+    assert e[0] == 0 and e[1] == 3e6 and e[-1] == pytest.approx(5e9, rel=1e-15, abs=0.0)
     r = e[2:] / e[1:-1]
     assert np.allclose(r, r[0], rtol=1e-12)
 
