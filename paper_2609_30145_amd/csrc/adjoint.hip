@@ -335,6 +335,11 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
             float g8[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) g8[e] = gp[jj + e];
+            if (jj > 0) {   // restarted from the exact Gaussian every step, as in the forward pass
+              const float a = u0 + (float)jj * hf;
+              w = expf(-0.5f * a * a);
+              q = expf(-a * hf - 0.5f * hf * hf);
+            }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
               const float uw = fmaf((float)(jj + e), hf, u0) * w;
@@ -790,7 +795,7 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
   if (rows && tid < MT) {
     const PointRow &pr = rows[m0 + tid];
     if (pr.b >= 0) {
-      if (span_mode == 2 && pr.kind != 0) {
+      if (span_mode == 2 && pr.kind != 0 && isfinite(pr.z)) {
         const double off = log1p(pr.z) * inv_dlnw;
         atomicMin(&s_lo, (int)floor(su0 - off) - 2);
         atomicMax(&s_hi, (int)ceil(su1 - off) + 3);

@@ -126,8 +126,15 @@ __device__ __forceinline__ double phot_ui0(const DevLib &lib, double z) {
 __device__ __forceinline__ void phot_span(const DevLib &lib, double fwln_min, double fwln_max, double z, int &seg0,
                                           int &seg_n) {
   const double ui0 = phot_ui0(lib, z);
-  seg0 = min(max((int)floor(phot_u(lib, fwln_min, ui0)), 0), lib.N - 2);
-  seg_n = min(max((int)floor(phot_u(lib, fwln_max, ui0)), 0), lib.N - 2) + 2 - seg0;
+  const double u0 = phot_u(lib, fwln_min, ui0), u1 = phot_u(lib, fwln_max, ui0);
+  if (!(isfinite(u0) && isfinite(u1))) {   // non-finite redshift: no pixels
+    seg0 = 0;
+    seg_n = 0;
+    return;
+  }
+  const double top = (double)(lib.N - 2);
+  seg0 = (int)fmin(fmax(floor(u0), 0.0), top);
+  seg_n = (int)fmin(fmax(floor(u1), 0.0), top) + 2 - seg0;
 }
 
 // ---------------------------------------------------------------- contraction tiles

@@ -15,8 +15,11 @@ namespace sps {
 // ---------------------------------------------------------------------------------
 // The key of a row: its redshift (time-varying enrichment), else the metallicity and
 // alpha brackets, then the redshift.
+// A redshift that is not a number sorts last (+inf), so that ties are broken by the batch
+// index and every row still takes a distinct rank; its own outputs come out non-finite.
 __device__ double sort_key(const DevLib &lib, const double *th) {
   double z = th[TH_ZRED];
+  if (z != z) z = HUGE_VAL;
   if (lib.n_zh > 0) return z;
   int jz = 0;
   double t;

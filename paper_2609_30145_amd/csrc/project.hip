@@ -361,7 +361,10 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
             float w = expf(-0.5f * a0 * a0);
             float q = expf(-a0 * h - 0.5f * h * h);
             const float c = expf(-h * h);
-            // eight taps per step: their LDS reads are independent of the recurrence
+            // eight taps per step: their LDS reads are independent of the recurrence, and
+            // every step restarts it from the exact Gaussian (two exponentials), so that
+            // the FP32 rounding of q and c compounds over at most eight taps however wide
+            // the row (a row of a few hundred taps drifted by ~1e-5 otherwise)
             float num = 0.f, den = 0.f;
             const float *gp = seg + (j0 - seg0);
             const int nt = j1 - j0 + 1;
@@ -370,6 +373,11 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
               float g[8];
 #pragma unroll
               for (int e = 0; e < 8; ++e) g[e] = gp[jj + e];
+              if (jj > 0) {
+                const float a = a0 + (float)jj * h;
+                w = expf(-0.5f * a * a);
+                q = expf(-a * h - 0.5f * h * h);
+              }
 #pragma unroll
               for (int e = 0; e < 8; ++e) {
                 num += w * g[e];

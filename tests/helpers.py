@@ -11,10 +11,11 @@ from oracle import model as om
 from synth import workloads as wl
 
 
-def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=(), wave_jitter=0.0):
+def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=(), wave_jitter=0.0, spec=None):
     """wave_jitter > 0 moves each model wavelength by that fraction of the log step
     (sinusoidally), so that the grid is no longer log-uniform and the general
-    interpolation paths are taken."""
+    interpolation paths are taken.  ``spec`` overrides entries of the spectrum grid
+    (lsf_mode, lsf_value: a constant or an array on the pixels, sigma_gal_kms, ...)."""
     B = cfg.batch if B is None else B
     lib = wl.make_library(cfg, seed)
     if wave_jitter > 0.0:
@@ -36,6 +37,9 @@ def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=()
         obs.data, obs.sigma = wl.noisy_photometry(m_true, seed + 5)
     else:
         g = wl.make_spectrum_grid(n_pix or cfg.n_pix or 3000)
+        g.update(spec or {})
+        if callable(g["lsf_value"]):
+            g["lsf_value"] = g["lsf_value"](g["pix_wave"])
         z_true = float(theta_true[0, 1])
         obs = om.Spectrum(g["pix_wave"], g["lsf_mode"], g["lsf_value"], g["sigma_gas_kms"], g["sigma_gal_kms"],
                           z_ref=z_true, noise=nz)
@@ -46,21 +50,30 @@ def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=()
 
 
 def gpu_objects(case, precisions=("fp64", "fp32"), max_batch=None):
-    """Library and observation on the GPU for a case (imports the binding lazily)."""
+    """Library and observation on the GPU for a case (imports the binding lazily).  The
+    observation's mask and, for spectra, an LSF curve tabulated on the pixels (an array
+    lsf_value in the oracle's observation) are passed on."""
     import paper_2609_30145_amd as sps
     cfg = case["cfg"]
     L = sps.Library(case["lib"], n_sfh=cfg.n_sfh, T1=cfg.T1, n_zh=cfg.n_zh, cosmo=cfg.cosmo, dust=case["dust"],
                     lines=case["lines"], precisions=precisions)
+    return L, gpu_observation(L, case, max_batch)
+
+
+def gpu_observation(L, case, max_batch=None):
+    import paper_2609_30145_amd as sps
     obs = case["obs"]
     mb = max_batch or case["theta"].shape[0]
     noise = tuple(k for k, v in (obs.noise or {}).items() if v)
     if case["kind"] == "phot":
-        O = sps.Observation(L, "phot", mb, filters=obs.filters, data=obs.data, sigma=obs.sigma, noise=noise)
-    else:
-        O = sps.Observation(L, "spec", mb, pix_wave=obs.pix_wave, lsf_mode=obs.lsf_mode, lsf_value=obs.lsf_value,
-                            z_ref=obs.z_ref, sigma_gal_kms=obs.sigma_gal_kms, sigma_gas_kms=obs.sigma_gas_kms,
-                            data=obs.data, sigma=obs.sigma, noise=noise)
-    return L, O
+        return sps.Observation(L, "phot", mb, filters=obs.filters, data=obs.data, sigma=obs.sigma, mask=obs.mask,
+                               noise=noise)
+    curve = np.ndim(obs.lsf_value) > 0
+    return sps.Observation(L, "spec", mb, pix_wave=obs.pix_wave, lsf_mode=obs.lsf_mode,
+                           lsf_value=1.0 if curve else obs.lsf_value,
+                           lsf_curve=np.asarray(obs.lsf_value) if curve else None, z_ref=obs.z_ref,
+                           sigma_gal_kms=obs.sigma_gal_kms, sigma_gas_kms=obs.sigma_gas_kms, data=obs.data,
+                           sigma=obs.sigma, mask=obs.mask, noise=noise)
 
 
 def near_truth(cfg, theta_true, n, seed):
@@ -80,9 +93,134 @@ def near_truth(cfg, theta_true, n, seed):
     return th
 
 
-def rel_err(got, ref, floor_frac=1e-3):
-    """Per-output error relative to |ref| + floor_frac * max|ref| of the row."""
+def rel_err(got, ref):
+    """Plain per-output relative error |got - ref| / |ref|: 0 where both are 0, inf where
+    only the reference is 0."""
+    got = np.atleast_2d(np.asarray(got, dtype=np.float64))
+    ref = np.atleast_2d(np.asarray(ref, dtype=np.float64))
+    d = np.abs(got - ref)
+    a = np.abs(ref)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        e = np.where(a > 0, d / np.where(a > 0, a, 1.0), np.where(d > 0, np.inf, 0.0))
+    return e
+
+
+def floored_err(got, ref, floor_frac=1e-3):
+    """Diagnostic only: error relative to |ref| + floor_frac * max|ref| of the row."""
     got = np.atleast_2d(got)
     ref = np.atleast_2d(ref)
     scale = np.abs(ref) + floor_frac * np.max(np.abs(ref), axis=1, keepdims=True)
     return np.abs(got - ref) / scale
+
+
+def model_err(got, ref, sigma, floor=1e-6):
+    """Per-output error |got - ref| / max(|ref|, floor * sigma_i): the plain relative error,
+    except for outputs more than 1/floor below the datum's uncertainty (FP32 cannot
+    represent spectra attenuated by e^-90 and more, whose contribution to logL is nil).
+    sigma_i that are not finite and positive (masked data) take the median of the rest."""
+    sg = np.asarray(sigma, dtype=np.float64)
+    ok = np.isfinite(sg) & (sg > 0)
+    sg = np.where(ok, np.abs(sg), np.median(np.abs(sg[ok])))
+    got = np.atleast_2d(np.asarray(got, dtype=np.float64))
+    ref = np.atleast_2d(np.asarray(ref, dtype=np.float64))
+    den = np.maximum(np.abs(ref), floor * sg[None, :])
+    return np.abs(got - ref) / den
+
+
+def worst_entries(got, ref, sigma, n=3):
+    """Text listing of the n outputs with the largest plain relative error (row, column,
+    oracle value, GPU value, sigma)."""
+    e = rel_err(got, ref)
+    e = np.where(np.isfinite(e), e, 1e300)
+    flat = np.argsort(e, axis=None)[::-1][:n]
+    out = []
+    for f in flat:
+        r, c = np.unravel_index(f, e.shape)
+        out.append(f"[{r},{c}] ref {ref[r, c]:.4e} got {got[r, c]:.4e} sigma {np.asarray(sigma)[c]:.3e}")
+    return "; ".join(out)
+
+
+def perturbed_oracle(case, rel, seed):
+    """The oracle library and observation built from inputs rounded at relative size `rel`:
+    every SSP flux element moved by rel * N(0, 1) of itself and every SSP spectrum as a
+    whole by another rel * N(0, 1) (the rounding of its weight, coherent over wavelength);
+    every log line-table entry moved by rel * N(0, 1) of itself; the filter transmissions
+    node by node, or the LSF width pixel by pixel (a row's width is rounded once, coherent
+    over the row)."""
+    import copy
+    rng = np.random.default_rng(seed)
+    lib = dict(case["lib"])
+    f = np.asarray(case["lib"]["flux"])
+    lib["flux"] = f * (1.0 + rel * rng.normal(size=f.shape)) * (1.0 + rel * rng.normal(size=f.shape[:3] + (1,)))
+    lines = case["lines"]
+    if lines is not None:
+        lines = dict(lines)
+        lt = case["lines"]["line_table"]
+        lines["line_table"] = lt * (1.0 + rel * rng.normal(size=lt.shape))
+    obs = copy.copy(case["obs"])
+    if obs.kind == "phot":
+        obs.filters = [(lam, R * (1.0 + rel * rng.normal(size=R.shape))) for lam, R in case["obs"].filters]
+    else:
+        v = np.broadcast_to(np.asarray(obs.lsf_value, dtype=np.float64), obs.pix_wave.shape)
+        obs.lsf_value = v * (1.0 + rel * rng.normal(size=v.shape))
+    return om.build_library(case["cfg"], lib, lines, case["dust"]), obs
+
+
+def grad_noise(case, theta, draws=2, rel=2.0 ** -24):
+    """Rounding-noise estimate of each gradient component, per row: the RMS change of the
+    FP64 oracle adjoint when its inputs are perturbed at the size of one FP32 rounding
+    (2^-24 relative; see perturbed_oracle).  Components formed as differences of nearly
+    equal sums (the enrichment-history nodes: adjacent metallicities; log U: adjacent table
+    corners) or as sums over residuals of both signs carry a noise far above 2^-24 of
+    their value; this estimate follows them."""
+    from oracle import adjoint
+    theta = np.atleast_2d(theta)
+    g0 = adjoint.logl_grad(case["olib"], case["obs"], theta)[1]
+    acc = np.zeros_like(g0)
+    for k in range(draws):
+        olib, obs = perturbed_oracle(case, rel, 9100 + k)
+        gk = adjoint.logl_grad(olib, obs, theta)[1]
+        acc += (gk - g0) ** 2
+    return np.sqrt(acc / draws)
+
+
+def grad_scale(olib, obs, theta, model=None):
+    """Cancellation-free magnitude S_p of each gradient component, per row (FP64 oracle).
+
+    d logL / d theta_p = sum_i g_i J_ip with g_i = d logL / d m_i and J = d m / d theta.
+    Near the data the terms of both signs cancel, and a relative error eps of the model
+    moves the component by up to about eps * sum_i |m_i| / sigma_i^2 |J_ip|, besides the
+    error of the sum itself, of order eps * sum_i |g_i| |J_ip|.  The two sums are taken with
+    the oracle adjoint on data moved so that g_i becomes |m_i| / sigma_i^2 and
+    |d_i - m_i| / sigma_i^2 (d' = m + |m| and d' = m + |d - m|); where J_ip changes sign
+    across outputs they are lower bounds."""
+    import copy
+
+    from oracle import adjoint
+    theta = np.atleast_2d(theta)
+    if model is None:
+        model = om.predict(olib, obs, theta)
+    out = np.zeros(theta.shape)
+    for b in range(theta.shape[0]):
+        m = model[b]
+        for dprime in (m + np.abs(m), m + np.abs(obs.data - m)):
+            o2 = copy.copy(obs)
+            o2.data = np.where(np.isfinite(obs.data), dprime, obs.data)
+            out[b] += np.abs(adjoint.logl_grad(olib, o2, theta[b:b + 1])[1][0])
+    return out
+
+
+def grad_ratio(got, ref, scale, noise, tol, model_acc=1e-2, k_noise=10.0):
+    """Per-component ratio |got - ref| / (tol |ref| + model_acc tol S_p + k_noise n_p), with
+    S_p from grad_scale and n_p from grad_noise; a gradient passes where every ratio is
+    <= 1.  The second term is what a forward model accurate to model_acc * tol moves the
+    component by (1e-6 for FP32: ten times inside the 1e-5 forward bar); the third covers
+    components formed as differences of nearly equal sums, whose rounding noise is far
+    above their value times the unit roundoff, with k_noise for the several independent
+    roundings of the GPU path against the single rounding of the estimate."""
+    got = np.atleast_2d(got)
+    ref = np.atleast_2d(ref)
+    den = tol * np.abs(ref) + model_acc * tol * np.asarray(scale) + k_noise * np.asarray(noise)
+    d = np.abs(got - ref)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(den > 0, d / np.where(den > 0, den, 1.0), np.where(d > 0, np.inf, 0.0))

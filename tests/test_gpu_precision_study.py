@@ -1,8 +1,8 @@
 """Precision study of the 16-bit contraction variants on the full-size photometric
 workload against the FP64 oracle: 10 240 seeded prior draws (ten launches of 1024)
 and one launch of 1024 small perturbations of the vector that made the data, where
-the logL bound matters most.  Per-band relative error (median / p99 / max, with the
-1e-3 row floor) and |dlogL| are printed for every variant.  The variants that carry a
+the logL bound matters most.  Per-band relative error (median / p99 / max; floored at 1e-6 of the band's sigma,
+which only bands attenuated below FP32 range reach) and |dlogL| are printed for every variant.  The variants that carry a
 weight residual (FP16 and BF16 with three MFMA passes, FP16 with two: W_h H + W_l H)
 must meet 2e-3 per band and |dlogL| <= 0.05 wherever the fit is within reach of the
 data (chi^2 per band <= 100, see the reading of the logL bound in the design notes);
@@ -16,7 +16,7 @@ import time
 import numpy as np
 import pytest
 
-from helpers import make_case, near_truth, rel_err
+from helpers import make_case, model_err, near_truth
 from oracle import model as om
 from synth import workloads as wl
 
@@ -66,14 +66,15 @@ def study():
     chi2_band = np.mean(resid ** 2, axis=1)
     fit = np.zeros(theta.shape[0], dtype=bool)
     fit[(N_LAUNCH - 1) * B:] = True
-    return ll_ref, m_ref, out, chi2_band, fit
+    return ll_ref, m_ref, out, chi2_band, fit, obs.sigma
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_precision_variant(study, variant):
-    ll_ref, m_ref, out, chi2_band, fit = study
+    ll_ref, m_ref, out, chi2_band, fit, sigma = study
     ll, m = out[variant]
-    e = rel_err(m, m_ref)
+    e = model_err(m, m_ref, sigma)
+    n_floor = int(np.sum(np.abs(m_ref) < 1e-6 * sigma[None, :]))
     dll = np.abs(ll - ll_ref)
     near = chi2_band <= 100.0
     rel_ll = dll / np.abs(ll_ref)
@@ -81,7 +82,7 @@ def test_precision_variant(study, variant):
         f"|dlogL| (chi2/band<=100, n={near.sum()}) median {np.median(dll[near]) if near.any() else 0:.2e} "
         f"max {dll[near].max() if near.any() else 0:.2e} | perturbed truth (chi2/band "
         f"{chi2_band[fit].min():.2f}-{chi2_band[fit].max():.2f}) max {dll[fit].max():.2e} | "
-        f"all: max |dlogL| {dll.max():.2e} max rel {rel_ll.max():.2e}")
+        f"all: max |dlogL| {dll.max():.2e} max rel {rel_ll.max():.2e} | {n_floor} bands below 1e-6 sigma")
     assert near[fit].all()
     if variant == "fp32":
         assert e.max() < 1e-5

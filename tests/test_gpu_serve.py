@@ -1,12 +1,16 @@
 """GPU request server: continuous batching of photometry and spectra requests on one
-library; each request's result is the same alone and in the mix, and its final logL
-agrees with a direct sps_logl evaluation of its final live points."""
+library; each request's result is the same alone and in the mix, its final logL agrees
+with a direct sps_logl evaluation of its final live points, and with the FP64 oracle's
+logL of those points (relative 1e-4 for FP32 and FP16 hi + residual, which also holds each
+band or pixel of the forward model within 1e-5 and 2e-3 of the oracle)."""
 import sys
 import time
 
 import numpy as np
 import pytest
 
+from helpers import model_err
+from oracle import model as om
 from synth import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -30,8 +34,16 @@ def say(m):
 def glib():
     lib = wl.make_library(CFG, 0)
     dust = wl.make_dust_tables(CFG, lib["wave"])
-    return sps.Library(lib, n_sfh=CFG.n_sfh, T1=CFG.T1, n_zh=CFG.n_zh, cosmo=CFG.cosmo, dust=dust,
-                       precisions=("fp32", "fp16"))
+    G = sps.Library(lib, n_sfh=CFG.n_sfh, T1=CFG.T1, n_zh=CFG.n_zh, cosmo=CFG.cosmo, dust=dust,
+                    precisions=("fp32", "fp16"))
+    G.oracle = om.build_library(CFG, lib, None, dust)
+    return G
+
+
+def _oracle_obs(kind, o):
+    if kind == "phot":
+        return om.Photometry(filters=o["filters"], data=o["data"], sigma=o["sigma"])
+    return om.Spectrum(o["pix_wave"], "R_fwhm", 100.0, 100.0, 0.0, z_ref=3.0, data=o["data"], sigma=o["sigma"])
 
 
 def _obs(kind, n, seed):
@@ -83,3 +95,22 @@ def test_alone_equals_mixed_and_matches_direct_logl(glib, precision):
         th = torch.tensor(alone[k]["theta"], device="cuda")
         ll = sps.logl(glib, O, th, precision).cpu().numpy()
         assert np.array_equal(ll, alone[k]["logl"]), k
+    # every request's final live points against the FP64 oracle
+    mtol = 1e-5 if precision == "fp32" else 2e-3
+    for k, (kind, n, B) in enumerate(JOBS):
+        o = _obs(kind, n, k)
+        oo = _oracle_obs(kind, o)
+        th = alone[k]["theta"]
+        m_ref = om.predict(glib.oracle, oo, th)
+        ll_ref = om.logl(glib.oracle, oo, th, model=m_ref)
+        lle = np.abs(alone[k]["logl"] - ll_ref) / np.abs(ll_ref)
+        if kind == "phot":
+            O = sps.Observation(glib, "phot", B, filters=o["filters"], data=o["data"], sigma=o["sigma"])
+        else:
+            O = sps.Observation(glib, "spec", B, pix_wave=o["pix_wave"], lsf_mode="R_fwhm", lsf_value=100.0,
+                                z_ref=3.0, sigma_gas_kms=100.0, data=o["data"], sigma=o["sigma"])
+        m = sps.forward(glib, O, torch.tensor(th, device="cuda"), precision).cpu().numpy()
+        e = model_err(m, m_ref, o["sigma"])
+        say(f"  request {k} ({kind}, {n}, B={B}) vs oracle: logL rel err {lle.max():.3e}, model rel err {e.max():.3e}")
+        assert lle.max() < 1e-4, k
+        assert e.max() < mtol, k

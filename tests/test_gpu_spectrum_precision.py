@@ -4,8 +4,8 @@ spectrum (R_fwhm = 100, five-sigma LSF rows, 128 lines on the pixels), library
 
 Of the 256 vectors, 128 are prior draws and 128 are small perturbations of the vector
 that made the data, so that the logL bound is exercised where the fit is within reach
-(chi^2 per pixel <= 100, the same reading as for photometry).  Per-pixel relative error
-uses the 1e-3 row floor.  Every low-precision variant must meet 2e-3 per pixel; the
+(chi^2 per pixel <= 100, the same reading as for photometry).  Per-pixel error is the relative
+error floored at 1e-6 of the pixel's sigma.  Every low-precision variant must meet 2e-3 per pixel; the
 FP16 hi + residual path (the default) must also hold |dlogL| <= 0.05 near the data.
 BF16 hi + residual (16 significant bits) and the two-pass variants are measured and
 reported: over 3000 pixels their per-pixel errors add up to more than the logL bound."""
@@ -14,7 +14,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_objects, make_case, near_truth, rel_err
+from helpers import gpu_objects, make_case, model_err, near_truth
 from oracle import model as om
 from synth import workloads as wl
 
@@ -51,14 +51,14 @@ def spec_study():
         out[v] = (ll.cpu().numpy(), m.cpu().numpy())
     obs = case["obs"]
     chi2_pix = np.mean(((obs.data[None, :] - m_ref) / obs.sigma[None, :]) ** 2, axis=1)
-    return ll_ref, m_ref, out, chi2_pix
+    return ll_ref, m_ref, out, chi2_pix, obs.sigma
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_spectrum_precision_variant(spec_study, variant):
-    ll_ref, m_ref, out, chi2_pix = spec_study
+    ll_ref, m_ref, out, chi2_pix, sigma = spec_study
     ll, m = out[variant]
-    e = rel_err(m, m_ref)
+    e = model_err(m, m_ref, sigma)
     dll = np.abs(ll - ll_ref)
     near = chi2_pix <= 100.0
     fit = np.zeros_like(near)
