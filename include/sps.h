@@ -207,6 +207,22 @@ sps_status sps_logl(const sps_library *lib, sps_obs *obs, const double *theta_de
 sps_status sps_logl_grad(const sps_library *lib, sps_obs *obs, const double *theta_dev, int32_t B,
                          int32_t precision, double *logl_dev, double *grad_dev, void *hip_stream);
 
+/* Allocation-free variant of sps_logl, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and stream semantics as sps_logl; the per-call scratch of the
+ * forward path (batch keys, weight rows, K-tile bits, per-point rows, the attenuated
+ * rest-frame spectrum, line luminosities) lives in one static device array of
+ * SPS_STATIC_SCRATCH_BYTES per GPU, held until the process ends, instead of the
+ * observation's workspace, so the observation may be created with max_batch = 1.  The
+ * call allocates nothing and never synchronises.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (on different streams, or from different
+ * threads without ordering) race.  Errors: SPS_E_SHAPE when B points at this precision
+ * need more scratch than the array holds (64 MiB: on a 2496 x 6016 library with 128
+ * lines, up to B = 1792 at FP32 or 16 bit and B = 896 at FP64), otherwise as sps_logl. */
+#define SPS_STATIC_SCRATCH_BYTES (64ull << 20)
+sps_status sps_logl_static(const sps_library *lib, const sps_obs *obs, const double *theta_dev, int32_t B,
+                           int32_t precision, double *logl_dev, double *model_dev, void *hip_stream);
+
 /* Timing of the library-contraction kernel.  When enabled, every hot call on
  * this observation hands a pair of HIP events to the contraction kernel's own
  * dispatch on the caller's stream (hipExtLaunchKernel), which stamps the

@@ -417,6 +417,11 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
     return fail(SPS_E_HIP, "library packing failed: %s", hipGetErrorString(e));
   }
   tmp.release();
+  const sps_status st = static_scratch_init(d->device);
+  if (st != SPS_OK) {
+    delete L;
+    return st;
+  }
   *out = L;
   return SPS_OK;
 }

@@ -110,6 +110,9 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
                           const double *theta, int B, int prec, double *logl, double *model, int ld_model,
                           bool grad, int ld_g, sps_obs *timing_obs, hipStream_t s);
 bool precision_built(const sps_library *L, int p);
+// Device address of the allocation-free entry point's static scratch on `device`, looked
+// up once per device (called by sps_library_load).
+sps_status static_scratch_init(int device);
 // Device copies of an observation's operators and data (used by sps_obs and the server).
 sps_status upload_obs(const ObsHost &h, DevObs &o, DeviceBuffers &mem, hipStream_t s);
 int64_t obs_device_bytes(const ObsHost &h);

@@ -88,13 +88,14 @@ def lib():
         L.sps_forward.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp, vp]
         L.sps_logl.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
         L.sps_logl_grad.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
+        L.sps_logl_static.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
         L.sps_obs_enable_timing.argtypes = [vp, C.c_int32]
         L.sps_obs_contract_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                               C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.sps_last_error.restype = C.c_char_p
         L.sps_version.restype = C.c_char_p
         for name in ("sps_library_load", "sps_library_info_get", "sps_theta_layout", "sps_obs_create",
-                     "sps_obs_set_data", "sps_obs_n_data", "sps_forward", "sps_logl", "sps_logl_grad",
+                     "sps_obs_set_data", "sps_obs_n_data", "sps_forward", "sps_logl", "sps_logl_grad", "sps_logl_static",
                      "sps_obs_enable_timing", "sps_obs_contract_timing"):
             getattr(L, name).restype = C.c_int32
         _lib = L
@@ -290,6 +291,20 @@ def logl(library, obs, theta, precision="fp32", stream=None, return_model=False)
     check(lib().sps_logl(library.handle, obs.handle, C.c_void_p(theta.data_ptr()), theta.shape[0],
                          PRECISIONS[precision], C.c_void_p(out.data_ptr()),
                          C.c_void_p(model.data_ptr()) if model is not None else None, _stream_ptr(stream)))
+    return (out, model) if return_model else out
+
+
+def logl_static(library, obs, theta, precision="fp32", stream=None, return_model=False):
+    """logL [B] (float64) through the allocation-free entry point — sps_logl_static."""
+    import torch
+    _check_theta(library, theta)
+    out = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
+    model = None
+    if return_model:
+        model = torch.empty((theta.shape[0], obs.n_data), dtype=torch.float64, device=theta.device)
+    check(lib().sps_logl_static(library.handle, obs.handle, C.c_void_p(theta.data_ptr()), theta.shape[0],
+                                PRECISIONS[precision], C.c_void_p(out.data_ptr()),
+                                C.c_void_p(model.data_ptr()) if model is not None else None, _stream_ptr(stream)))
     return (out, model) if return_model else out
 
 
