@@ -685,7 +685,14 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   pl.line_k0 = L->line_k0;
   pl.mode = mode;
   if (e == hipSuccess) e = launch_prep(g, pl, s);
+  // forward launches on a log-uniform grid compute only the tiles whose pixels the projection
+  // reads (the rows' spans); the gradient pass needs F everywhere (the attenuation adjoint
+  // multiplies it by d logL / d F, zero outside the spans), the FP64 instance stays dense
+  const int n_nt = g.N_pad / 64;
+  const bool span = !grad && g.log_uniform && prec != SPS_FP64 && w.tiles && B_pad / MT <= kTileListMaxM;
   ContractLaunch cl;
+  cl.list = span ? w.tiles : nullptr;
+  if (span && e == hipSuccess) e = launch_tile_list(w.rows, B_pad, MT, n_nt, prec != SPS_FP32, w.tiles, s);
   cl.W = pl.W;
   cl.Wlo = pl.Wlo;
   cl.B_pad = B_pad;
@@ -698,7 +705,7 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   cl.precision = prec;
   cl.ev_start = cl.ev_stop = nullptr;
   if (e == hipSuccess && timing_obs)
-    e = timing_obs->timing_events(B_pad / MT, g.K_pad / (kKTile * tf), &cl.ev_start, &cl.ev_stop);
+    e = timing_obs->timing_events((B_pad / MT) * n_nt, g.K_pad / (kKTile * tf), &cl.ev_start, &cl.ev_stop);
   if (e == hipSuccess) e = launch_contract(g, cl, s);
   ProjectLaunch pj;
   pj.obs_table = obs_table;

@@ -93,6 +93,7 @@ struct DevObs {
   double sigma_gas_kms, lsf_value;   // gas dispersion; constant LSF parameter
   double fwln_min, fwln_max;         // ln of the shortest and longest filter node
   double ksig_max;                   // largest continuum kernel dispersion (spectra)
+  double lnpix_lo, lnpix_hi;         // ln of the first and last pixel (spectra)
   const double *data, *sigma;        // [n_data]
   const uint8_t *mask;               // [n_data] final inclusion mask
   const double *ivar;                // [n_data] 1/sigma^2, 0 where masked
@@ -106,8 +107,8 @@ struct PointRow {
   int b;        // original batch index
   int obs;      // observation slot
   int kind;     // observation kind
-  int seg0;     // photometry on a log-uniform grid: first rest-frame pixel under the filters
-  int seg_n;    //   and the number of pixels from there (phot_span)
+  int seg0;     // log-uniform grid: first rest-frame pixel the projection reads (photometry:
+  int seg_n;    //   phot_span; spectra: spec_span) and the number of pixels from there
   int pad;
 };
 
@@ -137,7 +138,47 @@ __device__ __forceinline__ void phot_span(const DevLib &lib, double fwln_min, do
   seg_n = (int)fmin(fmax(floor(u1), 0.0), top) + 2 - seg0;
 }
 
+// Rest-frame pixels [seg0, seg0 + seg_n) that the banded LSF rows of a spectrum at redshift
+// z read on a log-uniform grid: the pixels' rest range widened by five of the widest row's
+// dispersions and two nodes, clamped to the grid (none for a non-finite redshift).
+__device__ __forceinline__ void spec_span(const DevLib &lib, double lnpix_lo, double lnpix_hi, double ksig_max, double z,
+                                          int &seg0, int &seg_n) {
+  const double lnopz = log1p(z);
+  const double ext = 5.0 * ksig_max * lib.inv_dlnw + 2.0;
+  const double ua = (lnpix_lo - lnopz - lib.lnw0) * lib.inv_dlnw - ext;
+  const double ub = (lnpix_hi - lnopz - lib.lnw0) * lib.inv_dlnw + ext;
+  if (!(isfinite(ua) && isfinite(ub))) {
+    seg0 = 0;
+    seg_n = 0;
+    return;
+  }
+  const double top = (double)(lib.N - 1);
+  seg0 = (int)fmin(fmax(floor(ua), 0.0), top);
+  seg_n = (int)fmin(fmax(ceil(ub), 0.0), top) + 1 - seg0;
+}
+
 // ---------------------------------------------------------------- contraction tiles
+// Forward launches on a log-uniform grid skip the (M tile, N tile) pairs whose 64 model
+// pixels no row of the M tile reads (its span, PointRow seg0/seg_n).  k_tile_list writes
+// the others as a list: count at list[0], then (mt << 16) | nt, in N-tile-major order
+// (16-bit kernel: the XCDs split the library columns) or M-tile-major order (FP32 kernel:
+// an XCD keeps its weight rows in L2).  Block b goes to XCD b mod 8, and XCD x takes the
+// x-th eighth of the list, so the blocks that do work are dealt evenly; blocks past the
+// list return at once (returns false).
+constexpr int kSpanTile = 64;          // model pixels per contraction N tile
+constexpr int kTileListMaxM = 1024;    // M tiles a tile list can hold
+__device__ __forceinline__ bool span_block_tile(const int *__restrict__ list, int &mt, int &nt) {
+  const int count = list[0];
+  const int per = (count + 7) >> 3;
+  const int x = blockIdx.x & 7, l = blockIdx.x >> 3;
+  const int logical = x * per + l;
+  if (l >= per || logical >= count) return false;
+  const int v = list[1 + logical];
+  mt = v >> 16;
+  nt = v & 0xffff;
+  return true;
+}
+
 // Block -> (M tile, N tile) for the library contractions.  The hardware deals
 // consecutive blocks round-robin to the 8 XCDs; XCD x takes the consecutive tiles
 // [x*nblk/8, (x+1)*nblk/8) of the order (N tile, then M tile), so the XCDs split the

@@ -5,6 +5,8 @@
 // skipped through the per-M-tile active list.
 #include <hip/hip_ext.h>
 
+#include <climits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -24,6 +26,7 @@ struct ContractArgs {
   const float *lnlv, *da, *dd;
   const double *lnlv_d, *da_d, *dd_d;
   void *F, *Yatt;
+  const int *list;   // SPAN: the (M tile, N tile) pairs to compute (k_tile_list)
 };
 
 // blockIdx -> (m tile, n tile) for the FP32 / FP64 kernels: each XCD takes a contiguous
@@ -95,8 +98,9 @@ __device__ __forceinline__ void bc32p(double (&acc)[BM][BN][16], const double (*
 }
 
 // PRECISE (gradient pass): each 32-wide K tile is accumulated in FP32 and the tile
-// partials are summed in FP64.
-template <int MT, int NT, int WM, int WN, bool PRECISE, int MINW = 1>
+// partials are summed in FP64.  SPAN: the block's tile comes from the compacted list of
+// pairs that meet the rows' spans (blocks past the list return at once).
+template <int MT, int NT, int WM, int WN, bool PRECISE, int MINW = 1, bool SPAN = false>
 __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
   constexpr int KT = 32, LDSK = KT + 4;
   constexpr int WTM = MT / WM, WTN = NT / WN, BM = WTM / 32, BN = WTN / 32;
@@ -108,7 +112,11 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
   __shared__ double spd[PRECISE ? MT : 1][5];
 
   int mt, nt;
-  tile_of_block(a.N_pad / NT, mt, nt);
+  if constexpr (SPAN) {
+    if (!span_block_tile(a.list, mt, nt)) return;
+  } else {
+    tile_of_block(a.N_pad / NT, mt, nt);
+  }
   const int m0 = mt * MT, n0 = nt * NT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
@@ -150,7 +158,7 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
   __shared__ int s_n[2];
   int nact, ny;
   block_tile_list(a.rowmask, a.mask_words, m0, MT, 1, a.n_tiles32, a.young_tiles32, tl, s_or, s_n, nact, ny);
-  if (nt == 0 && threadIdx.x == 0 && a.counter) atomicAdd(a.counter, (unsigned long long)nact);
+  if (threadIdx.x == 0 && a.counter) atomicAdd(a.counter, (unsigned long long)nact);   // (M, K, N) tiles run
 
   f32x4 ra[A4], rb[B4];
 #define SPS_GLOAD32(t_)                                                              \
@@ -304,7 +312,7 @@ __global__ void __launch_bounds__(256) k_contract_f64(ContractArgs a) {
   __shared__ int s_n[2];
   int nact, ny;
   block_tile_list(a.rowmask, a.mask_words, m0, MT, 1, a.n_tiles32, a.young_tiles32, tl, s_or, s_n, nact, ny);
-  if (nt == 0 && threadIdx.x == 0 && a.counter) atomicAdd(a.counter, (unsigned long long)nact);
+  if (threadIdx.x == 0 && a.counter) atomicAdd(a.counter, (unsigned long long)nact);   // (M, K, N) tiles run
   auto apply_bc = [&]() {
     for (int i = 0; i < 4; ++i)
       for (int j = 0; j < 4; ++j) {
@@ -347,6 +355,67 @@ __global__ void __launch_bounds__(256) k_contract_f64(ContractArgs a) {
 }
 
 // ---------------------------------------------------------------------------------
+// The tile list of a span-limited forward launch (common.h: span_block_tile).  One
+// workgroup: each M tile's span in N tiles from its rows' pixel spans, per-item counts
+// (N tiles in N-tile-major order, M tiles otherwise), a block-wide exclusive scan, and the
+// pairs written in order.
+__global__ void __launch_bounds__(256) k_tile_list(const PointRow *__restrict__ rows, int B_pad, int MT, int n_nt,
+                                                   int nt_major, int *__restrict__ list) {
+  __shared__ int lo[kTileListMaxM], hi[kTileListMaxM];
+  __shared__ int s_wsum[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n_mt = B_pad / MT;
+  for (int m = tid; m < n_mt; m += 256) {
+    lo[m] = INT_MAX;
+    hi[m] = -1;
+  }
+  __syncthreads();
+  for (int r = tid; r < B_pad; r += 256) {
+    const PointRow &pr = rows[r];
+    if (pr.b >= 0 && pr.seg_n > 0) {   // one pixel of margin each side
+      atomicMin(&lo[r / MT], max(pr.seg0 - 1, 0) / kSpanTile);
+      atomicMax(&hi[r / MT], min(pr.seg0 + pr.seg_n, n_nt * kSpanTile - 1) / kSpanTile);
+    }
+  }
+  __syncthreads();
+  const int n_items = nt_major ? n_nt : n_mt;
+  auto count_of = [&](int i) {
+    if (!nt_major) return hi[i] >= lo[i] ? hi[i] - lo[i] + 1 : 0;
+    int c = 0;
+    for (int m = 0; m < n_mt; ++m) c += (lo[m] <= i && i <= hi[m]) ? 1 : 0;
+    return c;
+  };
+  const int chunk = (n_items + 255) / 256, i0 = min(tid * chunk, n_items), i1 = min(i0 + chunk, n_items);
+  int mine = 0;
+  for (int i = i0; i < i1; ++i) mine += count_of(i);
+  int incl = mine;   // inclusive scan of the chunk counts: waves, then the four wave totals
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
+  }
+  if (lane == 63) s_wsum[wv] = incl;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wv; ++w) base += s_wsum[w];
+  int off = base + incl - mine;
+  for (int i = i0; i < i1; ++i) {
+    if (nt_major) {
+      for (int m = 0; m < n_mt; ++m)
+        if (lo[m] <= i && i <= hi[m]) list[1 + off++] = (m << 16) | i;
+    } else {
+      for (int n = lo[i]; n <= hi[i]; ++n) list[1 + off++] = (i << 16) | n;
+    }
+  }
+  if (tid == 0) list[0] = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+}
+
+hipError_t launch_tile_list(const PointRow *rows, int B_pad, int MT, int n_nt, bool nt_major, int *list,
+                            hipStream_t s) {
+  if (B_pad / MT > kTileListMaxM || n_nt > 0xffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tile_list, dim3(1), dim3(256), 0, s, rows, B_pad, MT, n_nt, nt_major ? 1 : 0, list);
+  return hipGetLastError();
+}
+
 int contract_mtile(int precision) { return precision <= 1 ? 64 : 128; }
 int contract_ktile_factor(int precision) { return precision >= 2 ? 2 : 1; }
 
@@ -373,6 +442,7 @@ hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStrea
   a.dd_d = lib.dust_d_d;
   a.F = cl.F;
   a.Yatt = cl.Yatt;
+  a.list = cl.list;
   const int MT = contract_mtile(cl.precision);
   const int n_mt = cl.B_pad / MT;
   if (cl.precision == 0) {
@@ -381,12 +451,16 @@ hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStrea
                           a);
   } else if (cl.precision == 1) {
     a.LTa = lib.LT32;
+    const dim3 grid(n_mt * (lib.N_pad / 64));
     if (cl.Yatt)
-      hipExtLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, true, 2>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s,
-                            cl.ev_start, cl.ev_stop, 0, a);
+      hipExtLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, true, 2>), grid, dim3(256), 0, s, cl.ev_start, cl.ev_stop, 0,
+                            a);
+    else if (cl.list)
+      hipExtLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, false, 2, true>), grid, dim3(256), 0, s, cl.ev_start,
+                            cl.ev_stop, 0, a);
     else
-      hipExtLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, false, 2>), dim3(n_mt * (lib.N_pad / 64)), dim3(256), 0, s,
-                            cl.ev_start, cl.ev_stop, 0, a);
+      hipExtLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, false, 2>), grid, dim3(256), 0, s, cl.ev_start, cl.ev_stop,
+                            0, a);
   } else {
     return launch_contract16_impl(lib, cl, n_mt, s);
   }

@@ -26,6 +26,7 @@ struct ContractArgs16 {
   const PointRow *rows;
   const float *lnlv, *da, *dd;
   float *F;
+  const int *list;   // SPAN: the (M tile, N tile) pairs to compute (k_tile_list)
 };
 
 template <bool BF, int PASSES>
@@ -60,7 +61,9 @@ __device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[6], 
 // LDS rows are unpadded with the 16-byte chunks XOR-swizzled: chunk c of row r sits at
 // c ^ (r & 7) ^ ((r >> 3) & 1), which keeps 16-byte reads of 8 consecutive rows, and of
 // the 8 rows of one parity among 16 consecutive rows, on distinct banks.
-template <bool BF, int PASSES>
+// SPAN: the block's tile comes from the compacted list of pairs that meet the rows' spans
+// (blocks past the list return at once); otherwise every pair of the grid.
+template <bool BF, int PASSES, bool SPAN>
 __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
   constexpr int MT = 128, NT = 64, KT = 64, NCH = KT / 8, WTM = 32, BM = 1, BN = 2;
   constexpr bool USE_WL = PASSES >= 3, USE_R = PASSES == 2 || PASSES == 3;
@@ -72,7 +75,11 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
 
   const int n_nt = a.N_pad / NT;
   int mt, nt;
-  balanced_tile(gridDim.x / n_nt, n_nt, 3, mt, nt);
+  if constexpr (SPAN) {
+    if (!span_block_tile(a.list, mt, nt)) return;
+  } else {
+    balanced_tile(gridDim.x / n_nt, n_nt, 3, mt, nt);
+  }
   const int m0 = mt * MT, n0 = nt * NT;
   const int tid = threadIdx.x, lane = tid & 63, wm = tid >> 6;
   const int li = lane & 31, lh = lane >> 5;
@@ -98,7 +105,7 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
   __shared__ int s_n[2];
   int nact, ny;
   block_tile_list(a.rowmask, a.mask_words, m0, MT, 2, a.n_tiles32, a.young_tiles32, tl, s_or, s_n, nact, ny);
-  if (nt == 0 && tid == 0 && a.counter) atomicAdd(a.counter, (unsigned long long)nact);
+  if (tid == 0 && a.counter) atomicAdd(a.counter, (unsigned long long)nact);   // (M, K, N) tiles run
   // weight fragments of this wave's 32-row group: lane (li, lh) takes chunk lh*4 + s of
   // row li at MFMA step s (the same permutation of K as the library fragments below)
   const size_t wbase = (size_t)((m0 >> 5) + wm) * n_kt * (KT * 32) + (size_t)(lh * 4) * 256 + li * 8;
@@ -210,7 +217,9 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
 
 template <bool BF, int PASSES>
 static void launch16(const ContractArgs16 &a, int n_mt, int N_pad, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  hipExtLaunchKernelGGL((k_contract_16<BF, PASSES>), dim3(n_mt * (N_pad / 64)), dim3(256), 0, s, e0, e1, 0, a);
+  const dim3 grid(n_mt * (N_pad / 64));
+  if (a.list) hipExtLaunchKernelGGL((k_contract_16<BF, PASSES, true>), grid, dim3(256), 0, s, e0, e1, 0, a);
+  else hipExtLaunchKernelGGL((k_contract_16<BF, PASSES, false>), grid, dim3(256), 0, s, e0, e1, 0, a);
 }
 
 hipError_t launch_contract16_impl(const DevLib &lib, const ContractLaunch &cl, int n_mt, hipStream_t s) {
@@ -233,6 +242,7 @@ hipError_t launch_contract16_impl(const DevLib &lib, const ContractLaunch &cl, i
   a.da = lib.dust_a_f;
   a.dd = lib.dust_d_f;
   a.F = (float *)cl.F;
+  a.list = cl.list;
   const void *Yatt = cl.Yatt;
   // the gradient pass (which needs the young part) runs on the FP32 / FP64 paths only
   if (!a.H || !a.R || Yatt) return hipErrorInvalidValue;

@@ -37,7 +37,13 @@ struct ContractLaunch {
   void *Yatt;                // optional [B_pad][N_pad]: young part after both attenuations
   int precision;             // sps_precision value
   hipEvent_t ev_start, ev_stop;   // timing: events that take the kernel's own start and end, or NULL
+  const int *list;           // span-limited launch: the tile list (launch_tile_list), or NULL: every tile
 };
+// The tile list of a span-limited forward launch: the (M tile, N tile) pairs whose pixels
+// some row of the M tile reads (common.h: span_block_tile); list holds 1 + (B_pad/MT) *
+// n_nt ints.  N-tile-major for the 16-bit kernel, M-tile-major for FP32.
+hipError_t launch_tile_list(const PointRow *rows, int B_pad, int MT, int n_nt, bool nt_major, int *list,
+                            hipStream_t s);
 // M tile used by the contraction of a precision (the occupancy list granularity)
 int contract_mtile(int precision);
 int contract_ktile_factor(int precision);   // K tile in units of kKTile

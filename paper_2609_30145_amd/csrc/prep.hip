@@ -351,6 +351,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   const DevObs *obp = a.obs_table + slot;
   const int kind = obp->kind;
   const double fw_min = obp->fwln_min, fw_max = obp->fwln_max;
+  const double px_lo = obp->lnpix_lo, px_hi = obp->lnpix_hi, ks_max = obp->ksig_max;
 
   // ---- A2: bin metallicity from the enrichment history (Sec. 2.2.2): nodes and bin
   // centres are both log-uniform from T1 to t_univ, so the interpolation weight in ln T
@@ -634,7 +635,10 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     pr.kind = kind;
     pr.seg0 = 0;
     pr.seg_n = 0;
-    if (kind == 0 && lib.log_uniform) phot_span(lib, fw_min, fw_max, z, pr.seg0, pr.seg_n);
+    if (lib.log_uniform) {
+      if (kind == 0) phot_span(lib, fw_min, fw_max, z, pr.seg0, pr.seg_n);
+      else spec_span(lib, px_lo, px_hi, ks_max, z, pr.seg0, pr.seg_n);
+    }
     pr.pad = 0;
     a.rows[r] = pr;
   }

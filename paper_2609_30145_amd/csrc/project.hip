@@ -297,13 +297,7 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
     // needs three exponentials per row instead of one per tap
     int seg0 = 0, seg_n = 0;
     const bool fast = sizeof(T) == 4 && lib.log_uniform;   // the adjoint transposes the same rows
-    if (fast) {
-      const double ext = 5.0 * ob.ksig_max * lib.inv_dlnw + 2.0;
-      const double ua = (ob.lnpix[0] - lnopz - lnw0) * lib.inv_dlnw - ext;
-      const double ub = (ob.lnpix[ob.n_data - 1] - lnopz - lnw0) * lib.inv_dlnw + ext;
-      seg0 = (int)fmin(fmax(floor(ua), 0.0), (double)(N - 1));
-      seg_n = (int)fmin(fmax(ceil(ub), 0.0), (double)(N - 1)) + 1 - seg0;
-    }
+    if (fast) spec_span(lib, ob.lnpix_lo, ob.lnpix_hi, ob.ksig_max, z, seg0, seg_n);
     if (fast && seg_n <= kSegMax) {
       float *seg = (float *)(sraw + kSegOff);
       for (int k0 = tid; k0 < seg_n; k0 += 256 * 8) {   // eight loads per thread in flight

@@ -28,6 +28,7 @@ sps_status Workspace::create(const sps_library *L, int mb, int n_data, int n_fno
   rowmask = (uint32_t *)al(Bp * mask_words * 4);
   rows = (PointRow *)al(Bp * sizeof(PointRow));
   F = al(Bp * g.N_pad * 8);
+  tiles = (int *)al(((Bp + 63) / 64 * (g.N_pad / kSpanTile) + 1) * 4);
   const size_t gb = forward_only ? 1 : Bp;   // gradient-pass buffers
   Yatt = al(gb * g.N_pad * 8);
   Lline = (double *)al(Bp * (size_t)std::max(1, g.n_line) * 8);
@@ -107,6 +108,8 @@ sps_status upload_obs(const ObsHost &host, DevObs &o, DeviceBuffers &mem, hipStr
     o.sigma_gas_kms = host.sigma_gas;
     o.ksig_max = 0.0;
     for (double v : host.ksig) o.ksig_max = std::max(o.ksig_max, v);
+    o.lnpix_lo = host.lnpix.empty() ? 0.0 : host.lnpix.front();
+    o.lnpix_hi = host.lnpix.empty() ? 0.0 : host.lnpix.back();
   }
   o.data = (const double *)put(host.data.data(), (size_t)host.n_data * 8);
   o.sigma = (const double *)put(host.sigma.data(), (size_t)host.n_data * 8);
@@ -179,7 +182,7 @@ hipError_t sps_obs::timing_events(int n_mtiles, int n_ktiles, hipEvent_t *start,
     ms_total += ms;
     --ev_pending;
   }
-  dense_tiles += (int64_t)n_mtiles * n_ktiles;
+  dense_tiles += (int64_t)n_mtiles * n_ktiles;   // (M tile, N tile) pairs times K tiles
   *start = ev_start[i];
   *stop = ev_stop[i];
   ++ev_next;

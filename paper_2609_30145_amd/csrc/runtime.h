@@ -31,6 +31,7 @@ struct Workspace {
   uint32_t *rowmask = nullptr;
   PointRow *rows = nullptr;
   void *F = nullptr, *Yatt = nullptr;   // B_pad * N_pad * 8 bytes each
+  int *tiles = nullptr;          // the contraction's tile list (k_tile_list): 1 + (B_pad/64) * (N_pad/64) ints
   double *Lline = nullptr;
   double *gvec = nullptr, *gnoise = nullptr;
   double *gbuf = nullptr;        // adjoint per-point sums [B_pad][16]

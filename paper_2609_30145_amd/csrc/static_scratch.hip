@@ -60,7 +60,8 @@ size_t static_scratch_bytes(const DevLib &g, int B, int prec) {
   const size_t f_el = prec == SPS_FP64 ? 8 : 4;
   return align256(Bp * 8) + align256(Bp * g.K_pad * w_el) + align256(Bp * mask_words * 4) +
          align256(Bp * sizeof(PointRow)) + align256(Bp * g.N_pad * f_el) +
-         align256(Bp * (size_t)(g.n_line > 0 ? g.n_line : 1) * 8);
+         align256(Bp * (size_t)(g.n_line > 0 ? g.n_line : 1) * 8) +
+         align256(((Bp + 63) / 64 * (g.N_pad / kSpanTile) + 1) * 4);
 }
 
 }  // namespace sps
@@ -100,6 +101,7 @@ extern "C" sps_status sps_logl_static(const sps_library *L, const sps_obs *o, co
   w.rows = (PointRow *)take(Bp * sizeof(PointRow));
   w.F = take(Bp * g.N_pad * f_el);
   w.Lline = (double *)take(Bp * (size_t)(g.n_line > 0 ? g.n_line : 1) * 8);
+  w.tiles = (int *)take(((Bp + 63) / 64 * (g.N_pad / kSpanTile) + 1) * 4);
   w.counter = nullptr;
   return launch_forward(L, w, o->dev_obs, nullptr, theta, B, prec, logl, model, o->host.n_data, false,
                         o->host.n_data, nullptr, (hipStream_t)stream);
