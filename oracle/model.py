@@ -3,12 +3,15 @@
 Order of operations (Fig. A1, Tiers A-D):
   1. per point: z -> t_univ(z), D_L(z) (Sec. 2.6); SFH edges rescaled to t_univ.
   2. SFH (step scheme) and ZH -> SSP weights W[alpha, m, a] (App. B).
-  3. nebular line luminosities from the young weights and Q_ma (App. C).
+  3. nebular line luminosities and continuum from the weights and Q_ma (App. C),
+     each cube interpolated trilinearly in (Z_gas, age, log U).
   4. contraction with the SSP grid, young and old parts kept apart (eq. 1, D2);
      on the photometric path the lines are added to the young part on the model
      grid (Sec. 2.3.1); the ionising continuum of nebular-covered ages is
-     removed (f_ob = 0, Fig. A1 "combine" step).
-  5. attenuation F = e^{-tau_d}(Y e^{-tau_BC} + O) (App. D.1).
+     removed from the young part (Fig. A1 "combine" step) and, with an escape
+     geometry, a fraction f_ob of it restored (Sec. 2.3.2, App. D.1).
+  5. attenuation F = e^{-tau_d}(Y e^{-tau_BC} + O) (App. D.1), or its escape-geometry
+     forms (eq. runaway_mix; the picket fence of Sec. 2.3.2).
   6. observer frame: F_nu^obs = 10^logmass (1+z) Lsun F_lambda lambda^2 / (c 4 pi D_L^2) (Sec. 2.6).
   7. projection onto the observation (App. E or App. F) and logL (eq. 6, G1).
 """
@@ -27,11 +30,19 @@ SCALARS = ("logmass", "zred", "tau_bc", "alpha_bc", "tau_diff", "delta", "logzso
            "log_jitter")
 
 
-def columns(n_sfh, n_zh):
+ESCAPE_GEOMETRIES = ("none", "runaway_bc", "picket")
+
+
+def columns(n_sfh, n_zh, escape=False):
+    """Column offsets of theta: the scalars, the SFH bin masses, the enrichment nodes and,
+    for a library with an escape geometry, frac_obrun = f_ob last (Sec. 2.3.2)."""
     c = {n: i for i, n in enumerate(SCALARS)}
     c["sfh"] = len(SCALARS)
     c["zh"] = len(SCALARS) + n_sfh
     c["P"] = len(SCALARS) + n_sfh + n_zh
+    if escape:
+        c["frac_obrun"] = c["P"]
+        c["P"] += 1
     return c
 
 
@@ -57,16 +68,30 @@ class Library:
     Q: np.ndarray = None
     lines: dict | None = None
     G: np.ndarray | None = None
-    n_neb: int = 0
+    n_neb: int = 0            # nebular-covered ages are [neb_a0, n_neb)
+    neb_a0: int = 0
+    cont: dict | None = None  # nebular continuum cube (App. C) or None
+    escape: str = "none"      # fesc_geometry: "none" (f_ob = 0), "runaway_bc", "picket"
+    flux_ion: np.ndarray | None = None   # raw ionising continuum of nebular-covered ages
 
 
-def build_library(cfg, lib, lines=None, dust_tab=None) -> Library:
-    """Static, parameter-independent preparation of the SSP grid (done once)."""
+def build_library(cfg, lib, lines=None, dust_tab=None, cont=None, escape="none") -> Library:
+    """Static, parameter-independent preparation of the SSP grid (done once).
+
+    ``lines``: line_wave, line_table [n_line][n_tau][n_zg][n_u] of log10(L_l/Q), zg_nodes,
+    u_nodes and, optionally, line_tau (the table's own age axis; without it the age axis
+    is the set of birth-cloud SSP ages).  ``cont``: cont_table [n_tau][n_zg][n_u][n_wave]
+    of log10(L_nu/Q) on the library's wavelengths with its own tau_nodes, zg_nodes and
+    u_nodes (App. C).  Nebular emission goes to the SSP ages inside every cube's age
+    range; they must be birth-cloud ages.  ``escape`` selects the f_ob geometry.
+    """
     ages, wave = lib["ages"], lib["wave"]
     flux_raw = np.asarray(lib["flux"], dtype=np.float64)
     H0, Om = cfg.cosmo
     if dust_tab is None:
         dust_tab = dict(dust_a=np.zeros_like(wave), dust_d=np.zeros_like(wave))
+    if escape not in ESCAPE_GEOMETRIES:
+        raise ValueError(f"escape geometry must be one of {ESCAPE_GEOMETRIES}")
     L = Library(ages=ages, logz=np.asarray(lib["logz"]), afe=np.asarray(lib["afe"]), wave=wave,
                 flux=flux_raw.copy(), flux_raw=flux_raw, t_young=lib["t_young"],
                 n_sfh=cfg.n_sfh, T1=cfg.T1, n_zh=cfg.n_zh, H0=H0, Om=Om,
@@ -74,14 +99,37 @@ def build_library(cfg, lib, lines=None, dust_tab=None) -> Library:
     L.young = ages < L.t_young
     L.lo, L.hi = sfh.age_cells(ages)
     L.Q = nebular.ionising_rate(wave, flux_raw)
+    L.escape = escape
+    ranges = []
     if lines is not None:
-        L.lines = lines
-        L.n_neb = lines["line_table"].shape[1]
-        if not np.all(L.young[:L.n_neb]) or L.n_neb != int(L.young.sum()):
-            raise ValueError("line table ages must be exactly the birth-cloud ages")
-        # f_ob = 0: the ionising continuum of nebular-covered ages is reprocessed
-        L.flux[:, :, :L.n_neb, wave < LAM_LYMAN] = 0.0
+        L.lines = dict(lines)
+        if "line_tau" not in lines or lines["line_tau"] is None:
+            n_y = int(L.young.sum())
+            if lines["line_table"].shape[1] != n_y:
+                raise ValueError("a line table without its own age axis must be on the birth-cloud ages")
+            L.lines["line_tau"] = ages[:n_y].copy()
+        lt = L.lines["line_tau"]
+        ranges.append((lt[0], lt[-1]))
         L.G = nebular.line_profiles_grid(wave, lines["line_wave"])
+    if cont is not None:
+        if cont["cont_table"].shape[-1] != len(wave):
+            raise ValueError("the continuum cube must be tabulated on the library wavelengths")
+        L.cont = dict(cont)
+        ranges.append((cont["tau_nodes"][0], cont["tau_nodes"][-1]))
+    if ranges:
+        sel = nebular.nebular_age_mask(ages, ranges)
+        idx = np.flatnonzero(sel)
+        if len(idx) == 0:
+            raise ValueError("no SSP age falls inside the nebular grids' age range")
+        if np.any(~L.young[idx]):
+            raise ValueError("nebular-covered SSP ages must be birth-cloud ages")
+        L.neb_a0, L.n_neb = int(idx[0]), int(idx[-1]) + 1
+        ion = wave < LAM_LYMAN
+        # the ionising continuum of nebular-covered ages is reprocessed (absent from the
+        # young stellar light); an escape geometry restores a fraction f_ob of it
+        L.flux_ion = np.zeros_like(flux_raw)
+        L.flux_ion[:, :, L.neb_a0:L.n_neb, ion] = flux_raw[:, :, L.neb_a0:L.n_neb, ion]
+        L.flux[:, :, L.neb_a0:L.n_neb, ion] = 0.0
     return L
 
 
@@ -126,41 +174,92 @@ def point_weights(L: Library, th, cols):
 
 
 def point_lines(L: Library, th, cols, W):
-    """Step 3: line luminosities [erg/s per Msun of the weights]."""
+    """Step 3: line luminosities [erg/s per Msun of the weights] and Lhat [n_line, n_neb]."""
     if L.lines is None:
         return np.zeros(0), None
-    lhat = nebular.line_table_interp(L.lines["line_table"], L.lines["zg_nodes"],
-                                     L.lines["u_nodes"], th[cols["gas_logz"]], th[cols["gas_logu"]])
-    return nebular.line_luminosity(W, L.Q, lhat, L.n_neb), lhat
+    ages = L.ages[L.neb_a0:L.n_neb]
+    lhat = nebular.line_table_at_ages(L.lines["line_table"], L.lines["zg_nodes"], L.lines["line_tau"],
+                                      L.lines["u_nodes"], th[cols["gas_logz"]], th[cols["gas_logu"]], ages)
+    return nebular.line_luminosity(W, L.Q, lhat, L.n_neb, L.neb_a0), lhat
+
+
+def point_continuum(L: Library, th, cols, W):
+    """Step 3, continuum: the nebular continuum [Lsun/A per Msun of the weights] or 0."""
+    if L.cont is None:
+        return 0.0
+    c = L.cont
+    sel = np.zeros(len(L.ages), dtype=bool)
+    sel[L.neb_a0:L.n_neb] = True
+    chat = nebular.continuum_at_ages(c["cont_table"], c["zg_nodes"], c["tau_nodes"], c["u_nodes"],
+                                     th[cols["gas_logz"]], th[cols["gas_logu"]], L.ages[sel])
+    return nebular.continuum_luminosity(W, L.Q, chat, sel, L.wave)
+
+
+def escape_fraction(L: Library, th, cols):
+    """f_ob = theta[frac_obrun] clamped to [0, 1], or 0 without an escape geometry."""
+    if L.escape == "none":
+        return 0.0
+    return min(max(float(th[cols["frac_obrun"]]), 0.0), 1.0)
+
+
+def young_factors(L: Library, f):
+    """(p, q, s): the young light crosses the birth cloud with transmission
+    p e^{-tau_BC} + q and the nebular emission is scaled by s (Sec. 2.3.2, App. C, D.1):
+    no geometry (1, 0, 1); runaway_bc (1 - f, f, 1 - f), the runaway mixture on the young
+    array whose nebular part carries the covered fraction; picket (1 - f, 0, 1), only the
+    covered fraction (1 - f) of the young light, nebular emission included, is attenuated."""
+    if L.escape == "runaway_bc":
+        return 1.0 - f, f, 1.0 - f
+    if L.escape == "picket":
+        return 1.0 - f, 0.0, 1.0
+    return 1.0, 0.0, 1.0
 
 
 def rest_frame(L: Library, theta, lines_on_grid=True):
     """Steps 1-5 for the whole batch: W, lines, Y, O and attenuated F [B, n_wave]."""
     theta = np.atleast_2d(theta)
     B = theta.shape[0]
-    cols = columns(L.n_sfh, L.n_zh)
+    cols = columns(L.n_sfh, L.n_zh, L.escape != "none")
     n_k = L.flux.shape[0] * L.flux.shape[1] * L.flux.shape[2]
     Wk = np.zeros((B, n_k))
     per = []
     Lline = np.zeros((B, 0 if L.lines is None else len(L.lines["line_wave"])))
+    neb = np.zeros((B, len(L.wave)))
     for b in range(B):
         p = point_weights(L, theta[b], cols)
         Wk[b] = p["W"].reshape(-1)
         Lline[b], p["lhat"] = point_lines(L, theta[b], cols, p["W"])
+        neb[b] = point_continuum(L, theta[b], cols, p["W"])
         per.append(p)
     young_k = np.broadcast_to(L.young, L.flux.shape[:3]).reshape(-1)
     f = L.flux.reshape(n_k, -1)
     Y = Wk[:, young_k] @ f[young_k]
     O = Wk[:, ~young_k] @ f[~young_k]
+    I = np.zeros_like(Y) if L.flux_ion is None else Wk @ L.flux_ion.reshape(n_k, -1)
+    lines_grid = np.zeros_like(Y)
     if L.lines is not None and lines_on_grid:
-        Y = Y + (Lline / LSUN) @ L.G
+        lines_grid = (Lline / LSUN) @ L.G
     wave = L.wave
     F = np.empty_like(Y)
+    Yn = np.empty_like(Y)
+    fob = np.zeros(B)
     for b in range(B):
         th = theta[b]
-        F[b] = dust.attenuate(Y[b], O[b], wave, th[cols["tau_bc"]], th[cols["alpha_bc"]],
-                              th[cols["tau_diff"]], th[cols["delta"]], L.dust_a, L.dust_d)
-    return dict(per=per, W=Wk, Lline=Lline, Y=Y, O=O, F=F, cols=cols)
+        fob[b] = escape_fraction(L, th, cols)
+        pf, qf, sf = young_factors(L, fob[b])
+        # young light after the escape geometry's scaling of the nebular part
+        Yb = Yn[b] = Y[b] + sf * (neb[b] + lines_grid[b])
+        T_bc = np.exp(-dust.birth_cloud_tau(wave, th[cols["tau_bc"]], th[cols["alpha_bc"]]))
+        T_d = np.exp(-dust.diffuse_tau(wave, th[cols["tau_diff"]], th[cols["delta"]], L.dust_a, L.dust_d))
+        if L.escape == "picket":
+            # the fraction f_ob of the young stars, ionising continuum included, sees no dust
+            F[b] = T_d * ((pf * T_bc + qf) * Yb + O[b]) + fob[b] * (Y[b] + I[b])
+        else:
+            # the restored ionising continuum bypasses the birth cloud, then the screen
+            F[b] = T_d * ((pf * T_bc + qf) * Yb + fob[b] * I[b] + O[b])
+    # Y: the young light before the birth cloud (stars, then the scaled nebular emission);
+    # Ystar: its stellar part alone
+    return dict(per=per, W=Wk, Lline=Lline, Y=Yn, Ystar=Y, O=O, I=I, neb=neb, F=F, cols=cols, fob=fob)
 
 
 def observer_scale(L: Library, th, cols):
@@ -176,13 +275,15 @@ def fnu_observed(L: Library, F_row, scale):
 
 
 def line_fluxes(L: Library, th, cols, Lline, dl):
-    """F_l = L_l T_BC(lambda_l) T_d(lambda_l) 10^logmass / (4 pi D_L^2) (App. I.1)."""
+    """F_l = s L_l (p T_BC + q)(lambda_l) T_d(lambda_l) 10^logmass / (4 pi D_L^2) (App. I.1),
+    with the escape geometry's (p, q, s) (young_factors; (1, 0, 1) without one)."""
     lw = L.lines["line_wave"]
     a = np.interp(lw, L.wave, L.dust_a)
     d = np.interp(lw, L.wave, L.dust_d)
-    T = np.exp(-dust.birth_cloud_tau(lw, th[cols["tau_bc"]], th[cols["alpha_bc"]])
-               - dust.diffuse_tau(lw, th[cols["tau_diff"]], th[cols["delta"]], a, d))
-    return Lline * T * 10.0 ** th[cols["logmass"]] / (4.0 * math.pi * dl * dl)
+    pf, qf, sf = young_factors(L, escape_fraction(L, th, cols))
+    T_bc = np.exp(-dust.birth_cloud_tau(lw, th[cols["tau_bc"]], th[cols["alpha_bc"]]))
+    T_d = np.exp(-dust.diffuse_tau(lw, th[cols["tau_diff"]], th[cols["delta"]], a, d))
+    return sf * Lline * (pf * T_bc + qf) * T_d * 10.0 ** th[cols["logmass"]] / (4.0 * math.pi * dl * dl)
 
 
 def predict(L: Library, obs, theta, rf=None, trunc=5.0):
@@ -238,7 +339,7 @@ def logl(L: Library, obs, theta, model=None, trunc=5.0):
     theta = np.atleast_2d(theta)
     if model is None:
         model = predict(L, obs, theta, trunc=trunc)
-    cols = columns(L.n_sfh, L.n_zh)
+    cols = columns(L.n_sfh, L.n_zh, L.escape != "none")
     mask = likelihood.inclusion_mask(obs.data, obs.sigma, obs.mask)
     out = np.empty(theta.shape[0])
     for b in range(theta.shape[0]):

@@ -43,12 +43,16 @@ THETA_SCALARS = (
 N_SCALARS = len(THETA_SCALARS)
 
 
-def theta_columns(n_sfh: int, n_zh: int) -> dict:
-    """Column offsets of the theta layout (scalars, then sfh[n_sfh], then zh[n_zh])."""
+def theta_columns(n_sfh: int, n_zh: int, escape: bool = False) -> dict:
+    """Column offsets of the theta layout (scalars, then sfh[n_sfh], then zh[n_zh], then,
+    for a library with an ionising-photon escape geometry, frac_obrun)."""
     cols = {name: i for i, name in enumerate(THETA_SCALARS)}
     cols["sfh"] = N_SCALARS
     cols["zh"] = N_SCALARS + n_sfh
     cols["P"] = N_SCALARS + n_sfh + n_zh
+    if escape:
+        cols["frac_obrun"] = cols["P"]
+        cols["P"] += 1
     return cols
 
 
@@ -166,15 +170,23 @@ def make_library(cfg: Config, seed: int = 0, noise: float = 0.1) -> dict:
     return dict(ages=ages, logz=logz, afe=afe, wave=wave, flux=flux, t_young=cfg.t_young)
 
 
-def make_lines(cfg: Config, lib: dict, seed: int = 1) -> dict | None:
-    """Synthetic photoionisation line table log10(L_line/Q) [n_line, n_neb_age, n_zg, n_u].
+def make_lines(cfg: Config, lib: dict, seed: int = 1, line_tau=None) -> dict | None:
+    """Synthetic photoionisation line table log10(L_line/Q) [n_line, n_tau, n_zg, n_u].
 
-    The table's age axis is the set of SSP ages younger than ``t_young``.
+    Without ``line_tau`` the table's age axis is the set of SSP ages younger than
+    ``t_young``; with it, the table is on those ages (yr) and carries them as
+    ``line_tau`` (a grid of its own, as the photoionisation grids have).
     """
     if cfg.n_lines == 0:
         return None
     rng = np.random.default_rng(seed)
-    n_neb = int(np.sum(lib["ages"] < cfg.t_young))
+    if line_tau is None:
+        n_tau = int(np.sum(lib["ages"] < cfg.t_young))
+        an = np.arange(n_tau) / max(n_tau - 1, 1)
+    else:
+        line_tau = np.asarray(line_tau, dtype=np.float64)
+        n_tau = len(line_tau)
+        an = (line_tau - line_tau[0]) / (line_tau[-1] - line_tau[0])
     line_wave = np.sort(np.exp(rng.uniform(np.log(1000.0), np.log(2e4), cfg.n_lines)))
     zg = np.linspace(-1.3, 0.3, 7)
     lu = np.linspace(-4.0, -1.0, 7)
@@ -184,14 +196,50 @@ def make_lines(cfg: Config, lib: dict, seed: int = 1) -> dict | None:
     sa = rng.uniform(-1.0, 0.0, cfg.n_lines)
     zn = (zg - zg.mean()) / np.ptp(zg)
     un = (lu - lu.mean()) / np.ptp(lu)
-    an = np.arange(n_neb) / max(n_neb - 1, 1)
     table = (base[:, None, None, None]
              + sa[:, None, None, None] * an[None, :, None, None]
              + sz[:, None, None, None] * zn[None, None, :, None]
              + su[:, None, None, None] * un[None, None, None, :]
              + 0.3 * (zn[None, None, :, None] * un[None, None, None, :])
-             + rng.normal(0.0, 0.05, size=(cfg.n_lines, n_neb, len(zg), len(lu))))
-    return dict(line_wave=line_wave, line_table=table, zg_nodes=zg, u_nodes=lu)
+             + rng.normal(0.0, 0.05, size=(cfg.n_lines, n_tau, len(zg), len(lu))))
+    out = dict(line_wave=line_wave, line_table=table, zg_nodes=zg, u_nodes=lu)
+    if line_tau is not None:
+        out["line_tau"] = line_tau
+    return out
+
+
+CONT_TAU = (5e5, 1e6, 2e6, 3e6, 5e6, 7e6, 1e7)   # yr: ages of the continuum cube
+LINE_TAU = (5e5, 1e6, 2e6, 3e6, 4e6, 6e6, 1e7)   # yr: ages of a line cube with its own axis
+
+
+def make_nebular_continuum(wave: np.ndarray, seed: int = 3, tau_nodes=CONT_TAU) -> dict:
+    """Synthetic nebular continuum cube log10(L_nu/Q) [n_tau, n_zg, n_u, n_wave] on the
+    library wavelengths (L_nu in erg/s/Hz, Q in photons/s), standing in for the
+    photoionisation grids (App. C).  Its axes differ from the line table's.
+
+    Shape: a smooth level with Balmer (3646 A) and Paschen (8204 A) jumps, nothing
+    below the Lyman limit (-38), linear trends and a cross term in the normalised
+    (Z_gas, age, log U) coordinates and 0.03 dex of iid scatter.  The level, -25.2 at
+    5000 A, makes the continuum a sizeable fraction (tens of per cent) of the young
+    stellar light of ``make_library``'s spectra at optical wavelengths.
+    """
+    rng = np.random.default_rng(seed)
+    tau = np.asarray(tau_nodes, dtype=np.float64)
+    zg = np.linspace(-2.0, 0.4, 5)
+    lu = np.linspace(-4.0, -1.0, 4)
+    lw = np.log10(np.asarray(wave, dtype=np.float64) / 5000.0)
+    c0 = -25.2 - 0.2 * lw ** 2 + 0.35 * (wave < 3646.0) + 0.15 * (wave < 8204.0)
+    c0 = np.where(wave < 912.0, -38.0, c0)
+    tn = (tau - tau[0]) / (tau[-1] - tau[0])
+    zn = (zg - zg.mean()) / np.ptp(zg)
+    un = (lu - lu.mean()) / np.ptp(lu)
+    cube = (c0[None, None, None, :]
+            - 0.3 * tn[:, None, None, None]
+            + 0.25 * zn[None, :, None, None]
+            - 0.15 * un[None, None, :, None]
+            + 0.2 * (zn[None, :, None, None] * un[None, None, :, None])
+            + rng.normal(0.0, 0.03, size=(len(tau), len(zg), len(lu), len(wave))))
+    return dict(cont_table=cube, tau_nodes=tau, zg_nodes=zg, u_nodes=lu)
 
 
 def make_dust_tables(cfg: Config, wave: np.ndarray) -> dict:
@@ -273,19 +321,22 @@ def _clipped_t(rng, nu, scale, clip, size):
     return np.clip(rng.standard_t(nu, size) * scale, -clip, clip)
 
 
-def make_theta(cfg: Config, B: int | None = None, seed: int = 2) -> np.ndarray:
+def make_theta(cfg: Config, B: int | None = None, seed: int = 2, escape: bool = False) -> np.ndarray:
     """Draw theta[B, P] from the configuration's priors.
 
     SFH: c0 uses Dirichlet(1,...,1) bin masses; the others draw clipped Student-t
     (nu=2, sigma=0.3, |d|<=1) log10 ratios between adjacent bins and normalise to
     one solar mass (the continuity-prior shape of Sec. 4.2, applied to masses).
     Enrichment history: zeta_0 ~ U(-2.2, 0.3) plus a clipped Student-t random
-    walk with sigma 0.2, clamped to the grid.
+    walk with sigma 0.2, clamped to the grid.  With ``escape``, a last column
+    frac_obrun ~ U(0, 1) from a stream of its own (the other columns are unchanged).
     """
     B = cfg.batch if B is None else B
     rng = np.random.default_rng(seed)
-    cols = theta_columns(cfg.n_sfh, cfg.n_zh)
+    cols = theta_columns(cfg.n_sfh, cfg.n_zh, escape)
     th = np.zeros((B, cols["P"]))
+    if escape:
+        th[:, cols["frac_obrun"]] = np.random.default_rng(seed + 7919).uniform(0.0, 1.0, B)
     zlo, zhi = cfg.z_range
     th[:, cols["logmass"]] = rng.uniform(8.0, 11.0, B)
     th[:, cols["zred"]] = rng.uniform(zlo, zhi, B)
