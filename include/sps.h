@@ -97,17 +97,44 @@ typedef struct {
   double H0, Om;        /* flat LambdaCDM (Sec. 2.6): km/s/Mpc, Omega_m */
   const double *dust_a; /* [n_wave] diffuse-law shape a(lambda); NULL = zeros */
   const double *dust_d; /* [n_wave] bump shape d(lambda); NULL = zeros */
-  /* nebular lines (App. C); n_line = 0 disables nebular emission.  The line
-   * table's age axis must be exactly the SSP ages younger than t_young. */
+  /* nebular lines (App. C); n_line = 0: no lines.  Without n_line_tau the line
+   * table's age axis is exactly the SSP ages younger than t_young. */
   int32_t n_line, n_zg, n_u;
   const double *line_wave;  /* [n_line] rest Angstrom */
-  const double *line_table; /* [n_line][n_young][n_zg][n_u] log10(L_line/Q), erg */
+  const double *line_table; /* [n_line][n_line_tau or n_young][n_zg][n_u] log10(L_line/Q), erg */
   const double *zg_nodes;   /* [n_zg] gas log10(Z/Zsun) */
   const double *u_nodes;    /* [n_u] log10 U */
   uint32_t precisions;  /* bitmask of (1u << sps_precision) copies to build;
                            FP32 is always built */
   int32_t device;       /* HIP device ordinal */
+  /* Full nebular grid evaluation (Sec. 2.3.1, App. C), optional (zero / NULL: off).
+   * The line table may carry an age axis of its own (n_line_tau > 0, line_tau[] in yr,
+   * strictly increasing); the nebular continuum cube cont_table holds log10(L_nu/Q)
+   * (L_nu in erg/s/Hz, Q in photons/s) on its own (age, log Z_gas, log U) axes, tabulated
+   * on the library's wavelengths.  Each cube is interpolated trilinearly (linearly in
+   * age) and scaled by Q_ma (eq. C1); nebular emission goes to the SSP ages inside every
+   * cube's age range, which must be birth-cloud ages (at most 128 of them with a
+   * continuum).  SPS_E_INVAL when an axis is not increasing, a table is not finite or no
+   * SSP age, or one older than t_young, falls in the range. */
+  int32_t n_line_tau;
+  const double *line_tau;   /* [n_line_tau] yr */
+  int32_t n_cont_tau, n_cont_zg, n_cont_u;
+  const double *cont_tau;   /* [n_cont_tau] yr */
+  const double *cont_zg;    /* [n_cont_zg] gas log10(Z/Zsun) */
+  const double *cont_u;     /* [n_cont_u] log10 U */
+  const double *cont_table; /* [n_cont_tau][n_cont_zg][n_cont_u][n_wave] log10(L_nu/Q) */
+  /* Ionising-photon escape (Sec. 2.3.2, App. D.1): sps_escape.  With a geometry, theta
+   * gains a last column frac_obrun = f_ob (clamped to [0, 1]); nebular emission is
+   * scaled by the covered fraction and a fraction f_ob of the nebular ages' ionising
+   * continuum is restored: SPS_ESCAPE_RUNAWAY_BC puts the young light (stars, nebular
+   * continuum and lines) through (1 - f_ob) e^{-tau_BC} + f_ob and lets the restored
+   * ionising continuum bypass the birth cloud (eq. runaway_mix); SPS_ESCAPE_PICKET lets
+   * f_ob of the young stars, ionising continuum included, escape free of both dust
+   * components and attenuates the covered rest (and its nebular emission) by both. */
+  int32_t escape;
 } sps_library_desc;
+
+typedef enum { SPS_ESCAPE_NONE = 0, SPS_ESCAPE_RUNAWAY_BC = 1, SPS_ESCAPE_PICKET = 2 } sps_escape;
 
 typedef struct {
   int32_t K, K_pad, K_young_pad, N, N_pad, n_young, n_line;
@@ -115,11 +142,13 @@ typedef struct {
 } sps_library_info;
 
 /* Copies the grid to the device, packs it in young-first K order (young SSP
- * rows, then the line-profile rows, then old rows, each padded), removes the
- * ionising continuum of nebular-covered ages (f_ob = 0, Fig. A1), computes Q_ma
- * (eq. C1) and builds the requested precision copies (per-row 2^e scaling and
- * 16-bit hi/residual split), plus an N-major FP32 copy for the adjoint.
- * Errors: SPS_E_INVAL (bad values), SPS_E_NOMEM, SPS_E_HIP. */
+ * rows, then the line-profile rows, then, with an escape geometry, the raw ionising
+ * continuum of the nebular ages, then old rows, each padded), removes the ionising
+ * continuum of nebular-covered ages from their SSP rows (Fig. A1), computes Q_ma
+ * (eq. C1), resamples the nebular cubes onto the SSP ages and builds the requested
+ * precision copies (per-row 2^e scaling and 16-bit hi/residual split), plus an N-major
+ * FP32 copy for the adjoint.
+ * Errors: SPS_E_INVAL (bad values), SPS_E_SHAPE, SPS_E_NOMEM, SPS_E_HIP. */
 sps_status sps_library_load(const sps_library_desc *desc, sps_library **out);
 sps_status sps_library_info_get(const sps_library *lib, sps_library_info *out);
 void sps_library_destroy(sps_library *lib);
@@ -128,11 +157,13 @@ void sps_library_destroy(sps_library *lib);
  * 14 scalar columns (in this order: logmass, zred, tau_bc, alpha_bc, tau_diff,
  * delta, logzsol, gas_logz, gas_logu, afe, log_err_scale, log_f_calib,
  * log_f_data, log_jitter), then sfh[n_sfh] bin masses (Msun formed per unit of
- * 10^logmass), then zh[n_zh] enrichment nodes.  Unused columns are ignored. */
+ * 10^logmass), then zh[n_zh] enrichment nodes, then, for a library with an escape
+ * geometry, frac_obrun (else frac_obrun = -1).  Unused columns are ignored. */
 typedef struct {
   int32_t P, n_scalar, sfh, n_sfh, zh, n_zh;
   int32_t logmass, zred, tau_bc, alpha_bc, tau_diff, delta, logzsol, gas_logz, gas_logu, afe;
   int32_t log_err_scale, log_f_calib, log_f_data, log_jitter;
+  int32_t frac_obrun;
 } sps_layout;
 sps_status sps_theta_layout(const sps_library *lib, sps_layout *out);
 
@@ -203,7 +234,8 @@ sps_status sps_logl(const sps_library *lib, sps_obs *obs, const double *theta_de
                     int32_t precision, double *logl_dev, double *model_dev, void *hip_stream);
 /* logl_dev [B] and grad_dev [B, P] = d logL / d theta (FP64; columns the
  * model does not use are zero).  Hand-written reverse pass.  Supported for
- * SPS_FP64 and SPS_FP32. */
+ * SPS_FP64 and SPS_FP32, for libraries without a nebular continuum cube, an
+ * escape geometry or a line table on an age axis of its own (else SPS_E_INVAL). */
 sps_status sps_logl_grad(const sps_library *lib, sps_obs *obs, const double *theta_dev, int32_t B,
                          int32_t precision, double *logl_dev, double *grad_dev, void *hip_stream);
 

@@ -124,7 +124,44 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
     if (ny == 0) return fail(SPS_E_INVAL, "nebular lines need SSP ages younger than t_young");
     if (!increasing(d->line_wave, nl) || !increasing(d->zg_nodes, d->n_zg) || !increasing(d->u_nodes, d->n_u))
       return fail(SPS_E_INVAL, "line wavelengths and table axes must be strictly increasing");
-    if (!finite_all(d->line_table, (size_t)nl * ny * d->n_zg * d->n_u)) return fail(SPS_E_INVAL, "line table not finite");
+    if (d->n_line_tau < 0 || (d->n_line_tau > 0 && (d->n_line_tau < 2 || !d->line_tau)))
+      return fail(SPS_E_INVAL, "line_tau needs n_line_tau >= 2 ages");
+    if (d->n_line_tau > 0 && (!finite_all(d->line_tau, d->n_line_tau) || !increasing(d->line_tau, d->n_line_tau)))
+      return fail(SPS_E_INVAL, "line_tau must be finite and strictly increasing");
+    const int nlt = d->n_line_tau > 0 ? d->n_line_tau : ny;
+    if (!finite_all(d->line_table, (size_t)nl * nlt * d->n_zg * d->n_u)) return fail(SPS_E_INVAL, "line table not finite");
+  }
+  const bool has_cont = d->n_cont_tau > 0;
+  if (has_cont) {
+    if (d->n_cont_tau < 2 || d->n_cont_zg < 2 || d->n_cont_u < 2 || !d->cont_tau || !d->cont_zg || !d->cont_u ||
+        !d->cont_table)
+      return fail(SPS_E_INVAL, "nebular continuum cube incomplete (each axis needs >= 2 nodes)");
+    if (!finite_all(d->cont_tau, d->n_cont_tau) || !increasing(d->cont_tau, d->n_cont_tau) ||
+        !finite_all(d->cont_zg, d->n_cont_zg) || !increasing(d->cont_zg, d->n_cont_zg) ||
+        !finite_all(d->cont_u, d->n_cont_u) || !increasing(d->cont_u, d->n_cont_u))
+      return fail(SPS_E_INVAL, "nebular continuum axes must be finite and strictly increasing");
+    if (!finite_all(d->cont_table, (size_t)d->n_cont_tau * d->n_cont_zg * d->n_cont_u * N))
+      return fail(SPS_E_INVAL, "nebular continuum cube not finite");
+  }
+  if (d->escape < SPS_ESCAPE_NONE || d->escape > SPS_ESCAPE_PICKET) return fail(SPS_E_INVAL, "unknown escape geometry");
+  // nebular-covered SSP ages [neb_a0, neb_a1): inside every cube's age range (App. C)
+  int neb_a0 = 0, neb_a1 = 0;
+  if (nl > 0 || has_cont) {
+    double lo = -HUGE_VAL, hi = HUGE_VAL;
+    if (nl > 0) {
+      lo = std::max(lo, d->n_line_tau > 0 ? d->line_tau[0] : d->ages[0]);
+      hi = std::min(hi, d->n_line_tau > 0 ? d->line_tau[d->n_line_tau - 1] : d->ages[ny - 1]);
+    }
+    if (has_cont) {
+      lo = std::max(lo, d->cont_tau[0]);
+      hi = std::min(hi, d->cont_tau[d->n_cont_tau - 1]);
+    }
+    while (neb_a0 < na && d->ages[neb_a0] < lo) ++neb_a0;
+    neb_a1 = neb_a0;
+    while (neb_a1 < na && d->ages[neb_a1] <= hi) ++neb_a1;
+    if (neb_a1 <= neb_a0) return fail(SPS_E_INVAL, "no SSP age falls inside the nebular grids' age range");
+    if (neb_a1 > ny) return fail(SPS_E_INVAL, "nebular-covered SSP ages must be birth-cloud ages (younger than t_young)");
+    if (has_cont && neb_a1 - neb_a0 > 128) return fail(SPS_E_SHAPE, "at most 128 nebular-covered SSP ages with a continuum");
   }
   if (d->device >= 0) {
     int dev_count = 0;
@@ -143,6 +180,7 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   L->n_line = nl;
   L->n_sfh = d->n_sfh;
   L->n_zh = d->n_zh;
+  L->line_tau_axis = nl > 0 && d->n_line_tau > 0;
   L->precisions = d->precisions | (1u << SPS_FP32);
   L->wave_h.assign(d->wave, d->wave + N);
   L->logz_lo = d->logz[0];
@@ -162,7 +200,21 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   g.n_u = nl ? d->n_u : 0;
   g.n_sfh = d->n_sfh;
   g.n_zh = d->n_zh;
-  g.P = TH_NSCALAR + d->n_sfh + d->n_zh;
+  g.P = TH_NSCALAR + d->n_sfh + d->n_zh + (d->escape ? 1 : 0);
+  g.th_fob = TH_NSCALAR + d->n_sfh + d->n_zh;
+  g.escape = d->escape;
+  g.neb_a0 = neb_a0;
+  g.neb_a1 = neb_a1;
+  g.has_neb = (nl > 0 || has_cont) ? 1 : 0;
+  g.has_cont = has_cont ? 1 : 0;
+  g.n_cz = has_cont ? d->n_cont_zg : 0;
+  g.n_cu = has_cont ? d->n_cont_u : 0;
+  g.ion_nlim = N;
+  for (int n = 0; n < N; ++n)
+    if (d->wave[n] >= kLamLyman) {
+      g.ion_nlim = n;
+      break;
+    }
   g.T1 = d->T1;
   g.H0 = d->H0;
   g.Om = d->Om;
@@ -171,14 +223,25 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   // ---- young-first K order.  Time-varying enrichment: age-major (old ages beyond
   //      t_univ(z) form whole zero tiles); constant metallicity: metallicity-major
   //      (rows of one metallicity/alpha bracket share a few (Z, alpha) blocks).
+  //      With an escape geometry the raw ionising continuum of the nebular ages follows
+  //      the young segment as rows of its own (ion rows, age-major); under the picket
+  //      fence the line rows start on a K tile of their own, so that the dust-free pass
+  //      can take the young stellar rows without them.
   const int kyo = ny * nz * nf;
-  const int K_young_pad = round_up(kyo + nl, kKAlign);
+  const int line_k0 = d->escape == SPS_ESCAPE_PICKET ? round_up(kyo, kKAlign) : kyo;
+  const int K_young_pad = round_up(line_k0 + nl, kKAlign);
+  const int n_ion = d->escape ? (neb_a1 - neb_a0) * nz * nf : 0;
+  const int K_old0 = K_young_pad + round_up(n_ion, kKAlign);
   const int kold = (na - ny) * nz * nf;
-  const int K_pad = K_young_pad + round_up(kold, kKAlign);
+  const int K_pad = K_old0 + round_up(kold, kKAlign);
   g.K = nf * nz * na + nl;
   g.K_pad = K_pad;
   if (K_pad > kMaxKPad) return fail(SPS_E_SHAPE, "library too large: %d weight rows after padding (at most %d)", K_pad, kMaxKPad);
   g.K_young_pad = K_young_pad;
+  g.line_k0 = line_k0;
+  g.ion_k0 = K_young_pad;
+  g.n_ion = n_ion;
+  g.K_old0 = K_old0;
   std::vector<int> kpos((size_t)nf * nz * na), ksrc(K_pad, INT_MIN);
   g.zmajor = d->n_zh > 0 ? 0 : 1;
   auto place = [&](int a0, int a1, int kbase) {
@@ -194,10 +257,14 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
     }
   };
   place(0, ny, 0);
-  place(ny, na, K_young_pad);
+  place(ny, na, K_old0);
   for (int s = 0; s < nf * nz * na; ++s) ksrc[kpos[s]] = s;
-  L->line_k0 = kyo;
-  for (int l = 0; l < nl; ++l) ksrc[kyo + l] = -1 - l;
+  L->line_k0 = line_k0;
+  for (int l = 0; l < nl; ++l) ksrc[line_k0 + l] = -1 - l;
+  for (int q = 0; q < n_ion; ++q) {   // ion row q: ((a - neb_a0) * nz + m) * nf + ia
+    const int ia = q % nf, m = (q / nf) % nz, a = neb_a0 + q / (nf * nz);
+    ksrc[K_young_pad + q] = kIonSrc - ((ia * nz + m) * na + a);
+  }
 
   if (d->device < 0) {   // host-only library: layout and observation operators only
     L->precisions = 0;
@@ -340,17 +407,37 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   double *ptab_d = (double *)up(ptab.data(), ptab.size() * 8);
   g.prep_tab = ptab_d;
   const size_t q_off = (size_t)nz + nf + 2 * na + g.n_zg + g.n_u;
-  double *Q = nl > 0 ? (ptab_d ? ptab_d + q_off : nullptr) : (double *)al((size_t)std::max(1, nf * nz * ny) * 8);
+  double *Q = g.has_neb ? (ptab_d ? ptab_d + q_off : nullptr) : (double *)al((size_t)std::max(1, nf * nz * ny) * 8);
   g.Q = Q;
+  // bracketing node j and fraction t of x on an increasing axis, clamped (the age step of
+  // the cubes' trilinear interpolation, done once here for the fixed SSP ages)
+  auto split = [](const double *x, int n, double v, int &j, double &t) {
+    const double vc = std::min(std::max(v, x[0]), x[n - 1]);
+    j = 0;
+    while (j + 1 < n - 1 && x[j + 1] <= vc) ++j;
+    t = (vc - x[j]) / (x[j + 1] - x[j]);
+  };
   if (nl > 0) {
-    // stored as [zg][u][line][age]: for one (Z_gas, U) corner the (line, age) slab is contiguous
+    // stored as [zg][u][line][young age]: for one (Z_gas, U) corner the (line, age) slab is
+    // contiguous.  A table with an age axis of its own is interpolated linearly in age at
+    // each nebular SSP age; young ages outside the nebular range take -1000 (10^-1000 = 0).
+    const int nlt = d->n_line_tau > 0 ? d->n_line_tau : ny;
     std::vector<double> ltT((size_t)nl * ny * d->n_zg * d->n_u);
-    for (int l = 0; l < nl; ++l)
-      for (int a = 0; a < ny; ++a)
+    for (int a = 0; a < ny; ++a) {
+      int j = a;
+      double t = 0.0;
+      if (d->n_line_tau > 0 && a >= neb_a0 && a < neb_a1) split(d->line_tau, nlt, d->ages[a], j, t);
+      for (int l = 0; l < nl; ++l)
         for (int ig = 0; ig < d->n_zg; ++ig)
-          for (int iu = 0; iu < d->n_u; ++iu)
-            ltT[(((size_t)ig * d->n_u + iu) * nl + l) * ny + a] =
-                d->line_table[(((size_t)l * ny + a) * d->n_zg + ig) * d->n_u + iu];
+          for (int iu = 0; iu < d->n_u; ++iu) {
+            double v = -1000.0;
+            if (a >= neb_a0 && a < neb_a1) {
+              auto at = [&](int jt) { return d->line_table[(((size_t)l * nlt + jt) * d->n_zg + ig) * d->n_u + iu]; };
+              v = d->n_line_tau > 0 ? (1.0 - t) * at(j) + t * at(j + 1) : at(a);
+            }
+            ltT[(((size_t)ig * d->n_u + iu) * nl + l) * ny + a] = v;
+          }
+    }
     g.line_table = (const double *)up(ltT.data(), ltT.size() * 8);
     std::vector<float> ltF(ltT.begin(), ltT.end());
     g.line_table_f = (const float *)up(ltF.data(), ltF.size() * 4);
@@ -359,6 +446,47 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
     g.line_wave = (const double *)up(d->line_wave, nl * 8);
     g.line_a = (const double *)up(line_a.data(), nl * 8);
     g.line_d = (const double *)up(line_d.data(), nl * 8);
+  }
+  if (has_cont) {
+    // nebular continuum: the cube interpolated linearly in age at each nebular SSP age,
+    // [age][zg][u][N_pad]; per pixel the largest value c_ref is taken out (FP32: every
+    // term 2^x has x <= 0) and 10^{c_ref} c / lambda^2 / Lsun * kWqScale kept apart
+    const int nct = d->n_cont_tau, ncz = d->n_cont_zg, ncu = d->n_cont_u, n_nc = neb_a1 - neb_a0;
+    const size_t plane = (size_t)ncz * ncu;
+    std::vector<double> cres((size_t)n_nc * plane * Np, 0.0), cref(Np, -HUGE_VAL);
+    for (int q = 0; q < n_nc; ++q) {
+      int j;
+      double t;
+      split(d->cont_tau, nct, d->ages[neb_a0 + q], j, t);
+      for (size_t c = 0; c < plane; ++c)
+        for (int n = 0; n < N; ++n) {
+          const double v = (1.0 - t) * d->cont_table[((size_t)j * plane + c) * N + n] +
+                           t * d->cont_table[((size_t)(j + 1) * plane + c) * N + n];
+          cres[((size_t)q * plane + c) * Np + n] = v;
+          cref[n] = std::max(cref[n], v);
+        }
+    }
+    std::vector<double> cd(cres.size()), scd(Np, 0.0);
+    std::vector<float> cf(cres.size()), scf(Np, 0.f);
+    const double log2_10 = 3.321928094887362347870319429489390175864831393;
+    for (size_t i = 0; i < cres.size(); ++i) {
+      const int n = (int)(i % Np);
+      const double x = n < N ? cres[i] - cref[n] : -1000.0;
+      cd[i] = x;
+      cf[i] = (float)(x * log2_10);
+    }
+    for (int n = 0; n < N; ++n) {
+      scd[n] = std::pow(10.0, cref[n]) * (kC_cms / kAng_cm) / (d->wave[n] * d->wave[n]) / kLsun * kWqScale;
+      scf[n] = (float)scd[n];
+    }
+    g.cz = (const double *)up(d->cont_zg, ncz * 8);
+    g.cu = (const double *)up(d->cont_u, ncu * 8);
+    if (L->precisions & (1u << SPS_FP64)) {
+      g.cont_d = (const double *)up(cd.data(), cd.size() * 8);
+      g.cont_sc_d = (const double *)up(scd.data(), Np * 8);
+    }
+    g.cont_f = (const float *)up(cf.data(), cf.size() * 4);
+    g.cont_sc_f = (const float *)up(scf.data(), Np * 4);
   }
   int *kexp = (int *)al((size_t)K_pad * 4);
   g.kexp = kexp;
@@ -404,7 +532,7 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
     return fail(SPS_E_NOMEM, "sps_library_load: staging allocation failed");
   }
   pk.ksrc = ksrc_d;
-  pk.neb_mask = nl > 0;
+  pk.neb_mask = g.has_neb;
   pk.kexp = kexp;
   pk.kexp16 = kexp16;
   pk.Q = Q;
@@ -467,6 +595,7 @@ extern "C" sps_status sps_theta_layout(const sps_library *L, sps_layout *o) {
   o->log_f_calib = TH_LOG_F_CALIB;
   o->log_f_data = TH_LOG_F_DATA;
   o->log_jitter = TH_LOG_JITTER;
+  o->frac_obrun = L->dev.escape ? L->dev.th_fob : -1;
   return SPS_OK;
 }
 
@@ -681,9 +810,11 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   pl.mask_words = w.mask_words;
   pl.rows = w.rows;
   pl.Lline = w.Lline;
+  pl.WQ = g.has_cont ? w.WQ : nullptr;
   pl.kpos = L->kpos_d;
   pl.line_k0 = L->line_k0;
   pl.mode = mode;
+  if (g.has_cont && !w.WQ) return fail(SPS_E_STATE, "workspace has no nebular-continuum buffer");
   if (e == hipSuccess) e = launch_prep(g, pl, s);
   // forward launches on a log-uniform grid compute only the tiles whose pixels the projection
   // reads (the rows' spans); the gradient pass needs F everywhere (the attenuation adjoint
@@ -703,10 +834,30 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   cl.F = w.F;
   cl.Yatt = grad ? w.Yatt : nullptr;
   cl.precision = prec;
+  cl.pass = 0;
   cl.ev_start = cl.ev_stop = nullptr;
   if (e == hipSuccess && timing_obs)
     e = timing_obs->timing_events((B_pad / MT) * n_nt, g.K_pad / (kKTile * tf), &cl.ev_start, &cl.ev_stop);
   if (e == hipSuccess) e = launch_contract(g, cl, s);
+  if (g.escape == SPS_ESCAPE_PICKET && e == hipSuccess) {
+    // the picket fence's dust-free part: f_ob (young stars + ionising continuum), added to F
+    ContractLaunch c1 = cl;
+    c1.pass = 1;
+    c1.ev_start = c1.ev_stop = nullptr;
+    e = launch_contract(g, c1, s);
+  }
+  if (g.has_cont && e == hipSuccess) {
+    NebLaunch nb;
+    nb.theta = theta;
+    nb.rows = w.rows;
+    nb.WQ = w.WQ;
+    nb.F = w.F;
+    nb.list = cl.list;
+    nb.B_pad = B_pad;
+    nb.MT = cl.list ? MT : 64;
+    nb.f64 = prec == SPS_FP64;
+    e = launch_nebular(g, nb, s);
+  }
   ProjectLaunch pj;
   pj.obs_table = obs_table;
   pj.rows = w.rows;
@@ -754,6 +905,9 @@ extern "C" sps_status sps_logl_grad(const sps_library *L, sps_obs *o, const doub
                                     double *logl, double *grad, void *stream) {
   if (!logl || !grad) return fail(SPS_E_INVAL, "logl_dev / grad_dev is NULL");
   if (prec != SPS_FP64 && prec != SPS_FP32) return fail(SPS_E_INVAL, "gradients are available for FP64 and FP32");
+  if (L && (L->dev.has_cont || L->dev.escape || L->line_tau_axis))
+    return fail(SPS_E_INVAL, "gradients are not available for libraries with a nebular continuum cube, an escape "
+                "geometry or a line table on an age axis of its own");
   sps_status st = run_forward(L, o, theta, B, prec, logl, nullptr, true, (hipStream_t)stream);
   if (st != SPS_OK) return st;
   return run_adjoint(L, o, theta, B, prec, grad, (hipStream_t)stream);

@@ -27,6 +27,10 @@ constexpr int kMAlign = 128;    // batch rows padded to this (contraction M tile
 constexpr int kKTile = 32;      // K tile of the occupancy bitmask (FP32 / FP64 kernels)
 constexpr int kMaxKPad = 32768; // largest padded K (weight rows) a library may have
 constexpr int kMaxKTiles32 = kMaxKPad / kKTile;
+// Library row sources (packing): s >= 0 SSP flat index (ia * n_z + m) * n_age + a; -1 - l
+// line l's profile; kIonSrc - s the raw ionising continuum (below 912 A) of SSP s; INT_MIN
+// padding.
+constexpr int kIonSrc = -(1 << 24);
 
 // theta scalar columns (see include/sps.h)
 enum ThetaCol {
@@ -38,6 +42,20 @@ enum ThetaCol {
 // Device-resident library (all pointers are device pointers).
 struct DevLib {
   int n_age, n_z, n_afe, N, N_pad, K, K_pad, K_young_pad, n_young, n_line, n_zg, n_u;
+  // Nebular emission (App. C) and ionising-photon escape (Sec. 2.3.2).  Ages [neb_a0,
+  // neb_a1) (birth-cloud ages) take nebular emission; has_neb: lines or continuum on.
+  // escape: 0 none, 1 runaway_bc, 2 picket; th_fob: theta column of f_ob.  With an escape
+  // geometry the raw ionising continuum of the nebular ages has K rows [ion_k0, ion_k0 +
+  // n_ion) between the young segment and the old rows, which start at K_old0; ion_nlim is
+  // the first model pixel at or above 912 A (the ionising rows are zero from there on).
+  int neb_a0, neb_a1, has_neb, escape, th_fob, ion_k0, n_ion, K_old0, ion_nlim, line_k0;
+  // Nebular continuum: cube axes (n_cz, n_cu) and, per nebular age, the log2 cube minus a
+  // per-pixel reference, [neb age][n_cz][n_cu][N_pad], with 10^ref * c / lambda^2 / Lsun *
+  // kWqScale per pixel (cont_sc); FP64 copies in log10 units for the FP64 path.
+  int has_cont, n_cz, n_cu;
+  const double *cz, *cu;
+  const float *cont_f, *cont_sc_f;
+  const double *cont_d, *cont_sc_d;
   int n_sfh, n_zh, P, n_gl;
   int log_uniform;                   // wave grid uniform in ln(lambda) (direct indexing)
   int zmajor;                        // K order: 0 age-major, 1 metallicity-major (see kpos_of)
@@ -46,7 +64,7 @@ struct DevLib {
   const double *cell_lo, *cell_hi;   // [n_age] linear-time Voronoi cells
   const double *logz, *afe;          // nodes
   const double *Q;                   // [n_afe][n_z][n_young] photons/s/Msun
-  const double *line_table;          // [n_zg][n_u][n_line][n_young]
+  const double *line_table;          // [n_zg][n_u][n_line][n_young] (-1000 outside the nebular ages)
   const float *line_table_f;         // the same in FP32 (FP32 and 16-bit paths)
   const double *zg, *un;             // nebular table axes
   const double *line_wave;           // [n_line] rest A
@@ -68,13 +86,17 @@ struct DevLib {
   const double *gl_u, *gl_w;         // [n_gl] composite Gauss-Legendre on [0,1]
   // The weight builder's node tables in one block, in the order of its LDS layout:
   // logz[n_z], afe[n_afe] (0 when n_afe = 1), cell_lo[n_age], cell_hi[n_age],
-  // zg[n_zg], un[n_u], Q[n_afe][n_z][n_young] (lines only), padded to an even count.
+  // zg[n_zg], un[n_u], Q[n_afe][n_z][n_young] (nebular emission only), padded to an even count.
   const double *prep_tab;
 };
 
+// Nebular continuum: photon-weighted masses sum_m W Q are carried in units of 2^150
+// photons/s (FP32 range), the factor folded into cont_sc.
+constexpr double kWqScale = 1.4272476927059599e45;   // 2^150
+
 // Length in doubles of DevLib::prep_tab.
 __host__ __device__ inline int prep_tab_len(const DevLib &lib) {
-  const int nq = lib.n_line > 0 ? lib.n_afe * lib.n_z * lib.n_young : 0;
+  const int nq = lib.has_neb ? lib.n_afe * lib.n_z * lib.n_young : 0;
   const int n = lib.n_z + lib.n_afe + 2 * lib.n_age + lib.n_zg + lib.n_u + nq;
   return n + (n & 1);
 }
@@ -104,6 +126,9 @@ struct DevObs {
 struct PointRow {
   double z, t_univ, dl, dc, scale_fnu, mass10, wscale;
   double tau_bc, alpha_bc, tau_diff, delta;
+  // escape geometry: the young light crosses the birth cloud with transmission
+  // bc_p e^{-tau_BC} + bc_q; nebular emission is scaled by neb_s; fob = f_ob
+  double bc_p, bc_q, neb_s, fob;
   int b;        // original batch index
   int obs;      // observation slot
   int kind;     // observation kind
@@ -202,14 +227,22 @@ __device__ __forceinline__ void balanced_tile(int n_mt, int n_nt, int blocks_per
   nt = n;
 }
 
+// K-tile ranges a contraction launch leaves out, in 32-wide tiles: [lo0, hi0) and
+// [lo1, hi1) (empty ranges: nothing left out).  The escape-geometry passes use them to
+// split the K order between the attenuated and the dust-free parts.
+struct TileSkip {
+  int lo0, hi0, lo1, hi1;
+};
+
 // Active K-tile list of the M tile whose rows start at m0: OR of the rows' occupancy
-// bits (one bit per 32-wide K tile, mask_words words per row), grouped into tiles of
-// 32*tf; the young tiles come first in the K order, so the list starts with them.
-// Run by the whole block; s_tl receives the tile ids in order, s_or is 64 words of
-// scratch, s_n two ints.  Returns the list length and the count of young tiles.
+// bits (one bit per 32-wide K tile, mask_words words per row), less the skipped ranges,
+// grouped into tiles of 32*tf; the young tiles come first in the K order, so the list
+// starts with them.  Run by the whole block; s_tl receives the tile ids in order, s_or
+// is 64 words of scratch, s_n two ints.  Returns the list length and the count of young
+// tiles.
 __device__ __forceinline__ void block_tile_list(const uint32_t *__restrict__ rowmask, int mask_words, int m0, int MT,
                                                 int tf, int n_tiles32, int young_tiles32, int *s_tl, uint32_t *s_or,
-                                                int *s_n, int &n_act, int &n_young) {
+                                                int *s_n, int &n_act, int &n_young, TileSkip skip = TileSkip{0, 0, 0, 0}) {
   const int tid = threadIdx.x;
   if (tid < 64) s_or[tid] = 0u;
   __syncthreads();
@@ -228,7 +261,8 @@ __device__ __forceinline__ void block_tile_list(const uint32_t *__restrict__ row
       if (t < n_tiles)
         for (int q = 0; q < tf; ++q) {
           const int t32 = t * tf + q;
-          if (t32 < n_tiles32) on |= ((s_or[t32 >> 5] >> (t32 & 31)) & 1u) != 0u;
+          const bool skipped = (t32 >= skip.lo0 && t32 < skip.hi0) || (t32 >= skip.lo1 && t32 < skip.hi1);
+          if (t32 < n_tiles32 && !skipped) on |= ((s_or[t32 >> 5] >> (t32 & 31)) & 1u) != 0u;
         }
       const unsigned long long bal = __ballot(on);
       if (on) s_tl[count + __popcll(bal & ((1ull << tid) - 1ull))] = t;
@@ -244,6 +278,29 @@ __device__ __forceinline__ void block_tile_list(const uint32_t *__restrict__ row
   __syncthreads();
   n_act = s_n[0];
   n_young = s_n[1];
+}
+
+// The skipped K ranges of a contraction launch over an N tile (above_lyman: the tile
+// starts at or above 912 A):
+// pass 0 (the attenuated sum) leaves out the ionising rows under the picket fence, and
+// above the Lyman limit (where they are zero) under either geometry; pass 1 (the picket
+// fence's dust-free part) keeps only the young stellar rows and the ionising rows.
+__host__ __device__ inline TileSkip escape_skip(const DevLib &lib, int pass, bool above_lyman) {
+  TileSkip s{0, 0, 0, 0};
+  if (!lib.escape) return s;
+  const int i0 = lib.ion_k0 / kKTile, i1 = lib.K_old0 / kKTile;
+  if (pass == 0) {
+    if (lib.escape == 2 || above_lyman) {
+      s.lo0 = i0;
+      s.hi0 = i1;
+    }
+  } else {
+    s.lo0 = lib.line_k0 / kKTile;   // the line rows (tile-aligned under the picket fence)
+    s.hi0 = i0;
+    s.lo1 = above_lyman ? i0 : i1;
+    s.hi1 = lib.K_pad / kKTile;
+  }
+  return s;
 }
 
 // ---------------------------------------------------------------- device helpers
@@ -276,7 +333,7 @@ __device__ __forceinline__ int kpos_of(const DevLib &lib, int ia, int m, int a) 
   const int nz = lib.n_z, nf = lib.n_afe, ny = lib.n_young;
   if (a < ny) return lib.zmajor ? (m * nf + ia) * ny + a : (a * nz + m) * nf + ia;
   const int no = lib.n_age - ny, ao = a - ny;
-  return lib.K_young_pad + (lib.zmajor ? (m * nf + ia) * no + ao : (ao * nz + m) * nf + ia);
+  return lib.K_old0 + (lib.zmajor ? (m * nf + ia) * no + ao : (ao * nz + m) * nf + ia);
 }
 
 // k with wave[k] <= lr < wave[k+1] (lr inside the grid), limited to [0, N-2]

@@ -27,6 +27,10 @@ struct ContractArgs {
   const double *lnlv_d, *da_d, *dd_d;
   void *F, *Yatt;
   const int *list;   // SPAN: the (M tile, N tile) pairs to compute (k_tile_list)
+  // escape geometry: K ranges left out below / at and above the Lyman limit (pixel
+  // ion_nlim); pass 1 adds the picket fence's dust-free part f_ob (young stars + ionising)
+  TileSkip skip_lo, skip_hi;
+  int ion_nlim, pass;
 };
 
 // blockIdx -> (m tile, n tile) for the FP32 / FP64 kernels: each XCD takes a contiguous
@@ -47,7 +51,7 @@ __device__ __forceinline__ void tile_of_block(int n_ntiles, int &mt, int &nt) {
 // floats of its LDS row per 32-wide K tile.
 // ---------------------------------------------------------------------------------
 template <int BM, int BN, int WTM, int WTN>
-__device__ __forceinline__ void bc32(v16f (&acc)[BM][BN], const float (*sp)[5], const float *c_lnlv, const float *c_a,
+__device__ __forceinline__ void bc32(v16f (&acc)[BM][BN], const float (*sp)[8], const float *c_lnlv, const float *c_a,
                                      const float *c_d, float *Yatt, int N_pad, int m0, int n0, int wm, int wn, int li,
                                      int lh) {
 #pragma unroll
@@ -57,7 +61,7 @@ __device__ __forceinline__ void bc32(v16f (&acc)[BM][BN], const float (*sp)[5], 
       const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
-        acc[i][j][e] *= expf(-sp[rl][0] * expf(sp[rl][1] * c_lnlv[j]));
+        acc[i][j][e] *= sp[rl][5] * expf(-sp[rl][0] * expf(sp[rl][1] * c_lnlv[j])) + sp[rl][6];
         if (Yatt) {
           const float Td = expf(-sp[rl][2] * expf(sp[rl][3] * c_lnlv[j]) * (c_a[j] + sp[rl][4] * c_d[j]));
           const int col = n0 + wn * WTN + j * 32 + li;
@@ -108,7 +112,7 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
   constexpr int A4 = MT * KT / 4 / 256, B4 = NT * KT / 4 / 256;
   __shared__ __attribute__((aligned(16))) float As[MT * LDSK];
   __shared__ __attribute__((aligned(16))) float Bs[NT * LDSK];
-  __shared__ float sp[MT][5];
+  __shared__ float sp[MT][8];
   __shared__ double spd[PRECISE ? MT : 1][5];
 
   int mt, nt;
@@ -132,6 +136,9 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
     sp[r][2] = (float)pr.tau_diff;
     sp[r][3] = (float)pr.delta;
     sp[r][4] = (float)(0.85 - 1.9 * pr.delta);
+    sp[r][5] = (float)pr.bc_p;
+    sp[r][6] = (float)pr.bc_q;
+    sp[r][7] = (float)pr.fob;
     if constexpr (PRECISE) {
       spd[r][0] = pr.tau_bc;
       spd[r][1] = pr.alpha_bc;
@@ -157,7 +164,9 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
   __shared__ uint32_t s_or[64];
   __shared__ int s_n[2];
   int nact, ny;
-  block_tile_list(a.rowmask, a.mask_words, m0, MT, 1, a.n_tiles32, a.young_tiles32, tl, s_or, s_n, nact, ny);
+  // pass 1 (no birth cloud): every tile counts as young, so the transmission never applies
+  block_tile_list(a.rowmask, a.mask_words, m0, MT, 1, a.n_tiles32, a.pass ? a.n_tiles32 : a.young_tiles32, tl, s_or,
+                  s_n, nact, ny, n0 >= a.ion_nlim ? a.skip_hi : a.skip_lo);
   if (threadIdx.x == 0 && a.counter) atomicAdd(a.counter, (unsigned long long)nact);   // (M, K, N) tiles run
 
   f32x4 ra[A4], rb[B4];
@@ -252,6 +261,21 @@ __global__ void __launch_bounds__(256, MINW) k_contract_f32(ContractArgs a) {
           }
     }
   }
+  if (!PRECISE && a.pass) {   // the picket fence's dust-free part, added to the attenuated sum
+    float *F = (float *)a.F;
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+#pragma unroll
+        for (int j = 0; j < BN; ++j) {
+          const int col = n0 + wn * WTN + j * 32 + li;
+          F[(size_t)(m0 + rl) * a.N_pad + col] += acc[i][j][e] * sp[rl][7];
+        }
+      }
+    return;
+  }
   if (ny == nact) {
     __syncthreads();
     if constexpr (PRECISE) {
@@ -291,7 +315,7 @@ __global__ void __launch_bounds__(256) k_contract_f64(ContractArgs a) {
   constexpr int MT = 64, NT = 64, KT = 32, LDSK = KT + 1;
   __shared__ double As[MT * LDSK];
   __shared__ double Bs[NT * LDSK];
-  __shared__ double sp[MT][5];
+  __shared__ double sp[MT][8];
   int mt, nt;
   tile_of_block(a.N_pad / NT, mt, nt);
   const int m0 = mt * MT, n0 = nt * NT;
@@ -305,19 +329,23 @@ __global__ void __launch_bounds__(256) k_contract_f64(ContractArgs a) {
     sp[r][2] = pr.tau_diff;
     sp[r][3] = pr.delta;
     sp[r][4] = 0.85 - 1.9 * pr.delta;
+    sp[r][5] = pr.bc_p;
+    sp[r][6] = pr.bc_q;
+    sp[r][7] = pr.fob;
   }
   double acc[4][4] = {};
   __shared__ int tl[kMaxKTiles32];
   __shared__ uint32_t s_or[64];
   __shared__ int s_n[2];
   int nact, ny;
-  block_tile_list(a.rowmask, a.mask_words, m0, MT, 1, a.n_tiles32, a.young_tiles32, tl, s_or, s_n, nact, ny);
+  block_tile_list(a.rowmask, a.mask_words, m0, MT, 1, a.n_tiles32, a.pass ? a.n_tiles32 : a.young_tiles32, tl, s_or,
+                  s_n, nact, ny, n0 >= a.ion_nlim ? a.skip_hi : a.skip_lo);
   if (threadIdx.x == 0 && a.counter) atomicAdd(a.counter, (unsigned long long)nact);   // (M, K, N) tiles run
   auto apply_bc = [&]() {
     for (int i = 0; i < 4; ++i)
       for (int j = 0; j < 4; ++j) {
         const int rl = ty + 16 * i, col = n0 + tx + 16 * j;
-        const double T = exp(-sp[rl][0] * exp(sp[rl][1] * a.lnlv_d[col]));
+        const double T = sp[rl][5] * exp(-sp[rl][0] * exp(sp[rl][1] * a.lnlv_d[col])) + sp[rl][6];
         acc[i][j] *= T;
         if (a.Yatt) {
           const double Td = exp(-sp[rl][2] * exp(sp[rl][3] * a.lnlv_d[col]) * (a.da_d[col] + sp[rl][4] * a.dd_d[col]));
@@ -344,8 +372,16 @@ __global__ void __launch_bounds__(256) k_contract_f64(ContractArgs a) {
     }
   }
   __syncthreads();
-  if (ny == nact) apply_bc();
   double *F = (double *)a.F;
+  if (a.pass) {   // the picket fence's dust-free part, added to the attenuated sum
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        const int rl = ty + 16 * i, col = n0 + tx + 16 * j;
+        F[(size_t)(m0 + rl) * a.N_pad + col] += acc[i][j] * sp[rl][7];
+      }
+    return;
+  }
+  if (ny == nact) apply_bc();
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < 4; ++j) {
       const int rl = ty + 16 * i, col = n0 + tx + 16 * j;
@@ -443,6 +479,10 @@ hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStrea
   a.F = cl.F;
   a.Yatt = cl.Yatt;
   a.list = cl.list;
+  a.pass = cl.pass;
+  a.ion_nlim = lib.ion_nlim;
+  a.skip_lo = escape_skip(lib, cl.pass, false);
+  a.skip_hi = escape_skip(lib, cl.pass, true);
   const int MT = contract_mtile(cl.precision);
   const int n_mt = cl.B_pad / MT;
   if (cl.precision == 0) {

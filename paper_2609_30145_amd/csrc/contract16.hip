@@ -27,6 +27,10 @@ struct ContractArgs16 {
   const float *lnlv, *da, *dd;
   float *F;
   const int *list;   // SPAN: the (M tile, N tile) pairs to compute (k_tile_list)
+  // escape geometry: K ranges left out below / at and above the Lyman limit (pixel
+  // ion_nlim); pass 1 adds the picket fence's dust-free part f_ob (young stars + ionising)
+  TileSkip skip_lo, skip_hi;
+  int ion_nlim, pass;
 };
 
 template <bool BF, int PASSES>
@@ -38,16 +42,17 @@ __device__ __forceinline__ v16f mfma16(const u32x4 &a, const u32x4 &b, v16f c) {
   }
 }
 
-// Birth-cloud transmission applied to the young-part accumulator.
+// Birth-cloud transmission p e^{-tau_BC} + q applied to the young-part accumulator.
 template <int BM, int BN, int WTM>
-__device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[6], const float *c_lnlv, int wm, int lh) {
+__device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[8], const float *c_lnlv, int wm, int lh) {
 #pragma unroll
   for (int i = 0; i < BM; ++i)
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int rl = wm * WTM + i * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
 #pragma unroll
-      for (int j = 0; j < BN; ++j) acc[i][j][e] *= expf(-sp[rl][0] * expf(sp[rl][1] * c_lnlv[j]));
+      for (int j = 0; j < BN; ++j)
+        acc[i][j][e] *= sp[rl][6] * expf(-sp[rl][0] * expf(sp[rl][1] * c_lnlv[j])) + sp[rl][7];
     }
 }
 
@@ -70,7 +75,7 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
   constexpr int B8 = NT * KT / 8 / 256;   // 16-byte library chunks per thread and K tile
   __shared__ __attribute__((aligned(16))) uint16_t Bh[2][NT * KT];
   __shared__ __attribute__((aligned(16))) uint16_t Br[2][USE_R ? NT * KT : 8];
-  __shared__ float sp[MT][6];
+  __shared__ float sp[MT][8];
 #define SPS_SW(r_, c_) ((r_) * KT + (((c_) ^ ((r_) & 7) ^ (((r_) >> 3) & 1)) << 3))
 
   const int n_nt = a.N_pad / NT;
@@ -92,7 +97,9 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
     sp[r][2] = (float)pr.tau_diff;
     sp[r][3] = (float)pr.delta;
     sp[r][4] = (float)(0.85 - 1.9 * pr.delta);
-    sp[r][5] = (float)pr.wscale;
+    sp[r][5] = (float)(a.pass ? pr.fob * pr.wscale : pr.wscale);
+    sp[r][6] = (float)pr.bc_p;
+    sp[r][7] = (float)pr.bc_q;
   }
   v16f acc[BM][BN];
 #pragma unroll
@@ -104,7 +111,9 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
   __shared__ uint32_t s_or[64];
   __shared__ int s_n[2];
   int nact, ny;
-  block_tile_list(a.rowmask, a.mask_words, m0, MT, 2, a.n_tiles32, a.young_tiles32, tl, s_or, s_n, nact, ny);
+  // pass 1 (no birth cloud): every tile counts as young, so the transmission never applies
+  block_tile_list(a.rowmask, a.mask_words, m0, MT, 2, a.n_tiles32, a.pass ? a.n_tiles32 : a.young_tiles32, tl, s_or,
+                  s_n, nact, ny, n0 >= a.ion_nlim ? a.skip_hi : a.skip_lo);
   if (tid == 0 && a.counter) atomicAdd(a.counter, (unsigned long long)nact);   // (M, K, N) tiles run
   // weight fragments of this wave's 32-row group: lane (li, lh) takes chunk lh*4 + s of
   // row li at MFMA step s (the same permutation of K as the library fragments below)
@@ -201,6 +210,18 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
 #undef SPS_STOREB
 #undef SPS_MMA
 #undef SPS_SW
+  if (a.pass) {   // the picket fence's dust-free part, added to the attenuated sum
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int rl = wm * WTM + 8 * (e >> 2) + 4 * lh + (e & 3);
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        float *f = a.F + (size_t)(m0 + rl) * a.N_pad + n0 + j * 32 + li;
+        *f += acc[0][j][e] * sp[rl][5];
+      }
+    }
+    return;
+  }
   if (ny == nact) bc16<BM, BN, WTM>(acc, sp, c_lnlv, wm, lh);
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -243,6 +264,10 @@ hipError_t launch_contract16_impl(const DevLib &lib, const ContractLaunch &cl, i
   a.dd = lib.dust_d_f;
   a.F = (float *)cl.F;
   a.list = cl.list;
+  a.pass = cl.pass;
+  a.ion_nlim = lib.ion_nlim;
+  a.skip_lo = escape_skip(lib, cl.pass, false);
+  a.skip_hi = escape_skip(lib, cl.pass, true);
   const void *Yatt = cl.Yatt;
   // the gradient pass (which needs the young part) runs on the FP32 / FP64 paths only
   if (!a.H || !a.R || Yatt) return hipErrorInvalidValue;

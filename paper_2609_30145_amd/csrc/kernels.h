@@ -15,6 +15,7 @@ struct PrepLaunch {
   int mask_words;
   PointRow *rows;
   double *Lline;
+  double *WQ;                // [B_pad][nebular ages] photon-weighted masses (continuum), or NULL
   const int *kpos;
   int line_k0;
   int mode;   // 0 f64, 1 f32, 2 bf16, 3 f16
@@ -38,6 +39,7 @@ struct ContractLaunch {
   int precision;             // sps_precision value
   hipEvent_t ev_start, ev_stop;   // timing: events that take the kernel's own start and end, or NULL
   const int *list;           // span-limited launch: the tile list (launch_tile_list), or NULL: every tile
+  int pass;                  // 0: the attenuated sum; 1: the picket fence's dust-free part, added to F
 };
 // The tile list of a span-limited forward launch: the (M tile, N tile) pairs whose pixels
 // some row of the M tile reads (common.h: span_block_tile); list holds 1 + (B_pad/MT) *
@@ -66,6 +68,17 @@ struct ProjectLaunch {
   int ld_g;
 };
 hipError_t launch_project(const DevLib &lib, const ProjectLaunch &pl, hipStream_t s);
+
+// nebular continuum added to F (App. C); a no-op for a library without a continuum cube
+struct NebLaunch {
+  const double *theta;
+  const PointRow *rows;
+  const double *WQ;          // [B_pad][nebular ages] from the weight builder
+  void *F;
+  const int *list;           // the contraction's tile list, or NULL: every tile
+  int B_pad, MT, f64;
+};
+hipError_t launch_nebular(const DevLib &lib, const NebLaunch &nl, hipStream_t s);
 
 // library packing
 struct PackLaunch {

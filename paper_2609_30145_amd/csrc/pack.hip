@@ -1,9 +1,10 @@
 // Load-time packing of the SSP library (done once per library).
 //  * Q_ma: hydrogen-ionising photon rate of each unattenuated SSP (eq. C1), written
 //    for f_lambda in Lsun/A: (Lsun/(h c)) * trapezoid of f lambda over lambda <= 912 A.
-//  * f_ob = 0: the ionising continuum of nebular-covered (young) ages is removed
-//    (the "combine" step of Fig. A1) when nebular lines are on.
-//  * young-first K order: young SSP rows, line-profile rows, old SSP rows.
+//  * the ionising continuum of nebular-covered ages is removed from their SSP rows (the
+//    "combine" step of Fig. A1) when nebular emission is on; with an escape geometry it
+//    has rows of its own, which the weight builder scales by f_ob (Sec. 2.3.2).
+//  * young-first K order: young SSP rows, line-profile rows, ionising rows, old SSP rows.
 //  * copies: FP64 and FP32 K-contiguous [N_pad][K_pad], FP32 N-contiguous [K_pad][N_pad]
 //    for the adjoint, and 16-bit hi + residual planes with a per-row power of two.
 #include <climits>
@@ -15,9 +16,13 @@ namespace sps {
 
 __device__ __forceinline__ double src_value(const DevLib &lib, const PackLaunch &pk, int src, int n) {
   if (n >= lib.N || src == INT_MIN) return 0.0;
+  if (src <= kIonSrc) {   // the raw ionising continuum of a nebular age (escape geometries)
+    const int s = kIonSrc - src;
+    return lib.wave_d[n] < kLamLyman ? pk.flux[(size_t)s * lib.N + n] : 0.0;
+  }
   if (src < 0) return pk.lineprof[(size_t)(-1 - src) * lib.N + n];
   const int a = src % lib.n_age;
-  if (pk.neb_mask && a < lib.n_young && lib.wave_d[n] < kLamLyman) return 0.0;
+  if (pk.neb_mask && a >= lib.neb_a0 && a < lib.neb_a1 && lib.wave_d[n] < kLamLyman) return 0.0;
   return pk.flux[(size_t)src * lib.N + n];
 }
 

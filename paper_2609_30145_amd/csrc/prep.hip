@@ -104,6 +104,7 @@ struct PrepArgs {
   int mask_words;
   PointRow *rows;           // [B_pad]
   double *Lline;            // [B_pad][n_line] (spectra: line luminosities, erg/s per Msun)
+  double *WQ;               // [B_pad][neb_a1 - neb_a0] sum_{alpha,m} W Q per nebular age / kWqScale, or NULL
   const int *kpos;          // [n_afe][n_z][n_age] -> K position
   int line_k0;              // K position of line 0 (photometric path)
 };
@@ -152,7 +153,7 @@ struct PrepSmem {
     mr = o;    o += lib.n_sfh;                             // bin mass per unit time
     zt = o;    o += lib.n_sfh;
     zj = o;    o += (lib.n_sfh + 1) / 2;                  // int
-    wq = o;    o += lib.n_line > 0 ? lib.n_young : 0;
+    wq = o;    o += lib.has_neb ? lib.n_young : 0;
     ke = o;    o += w16 ? lib.K_pad / 4 : 0;              // int16 row exponents
     wacc = o;  o += (lib.K_pad * acc + 7) / 8;
     lt = o;    o += (lib.n_line * lib.n_young * acc + 7) / 8;
@@ -493,8 +494,34 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   }
   __syncthreads();
 
-  // ---- C: nebular lines (App. C): L_l = sum_a 10^Lhat_l(a) sum_{alpha,m} W Q
-  if (nl > 0) {
+  // ---- escape geometry (Sec. 2.3.2): f_ob from its theta column, clamped to [0, 1] (a NaN
+  //      stays NaN); the young light's birth-cloud transmission bc_p e^{-tau_BC} + bc_q and
+  //      the nebular scale neb_s: runaway_bc (1 - f, f, 1 - f), picket (1 - f, 0, 1)
+  double fob = 0.0, bc_p = 1.0, bc_q = 0.0, neb_s = 1.0;
+  if (lib.escape) {
+    const double x = s_th[lib.th_fob];
+    fob = x != x ? x : fmin(fmax(x, 0.0), 1.0);
+    bc_p = 1.0 - fob;
+    if (lib.escape == 1) {
+      bc_q = fob;
+      neb_s = 1.0 - fob;
+    }
+    // the ionising rows: W_ma of the nebular ages, times f_ob under runaway_bc (the restored
+    // fraction, which bypasses the birth cloud); the picket fence's dust-free pass applies
+    // f_ob itself
+    const int nion = lib.n_ion;
+    const Acc sc = lib.escape == 1 ? (Acc)fob : (Acc)1;
+    for (int q = tid; q < nion; q += 256) {
+      const int ia = q % nf, m = (q / nf) % nz, ag = lib.neb_a0 + q / (nf * nz);
+      wacc[lib.ion_k0 + q] = sc * wacc[kpos_of(lib, ia, m, ag)];
+    }
+  }
+
+  // ---- C: nebular emission (App. C): the photon-weighted mass sum_{alpha,m} W Q per
+  //      nebular age, the line luminosities L_l = sum_a 10^Lhat_l(a) sum_{alpha,m} W Q (the
+  //      line table is -1000 outside the nebular ages) and, for the continuum, the per-age
+  //      sums themselves
+  if (lib.has_neb) {
     // photon-weighted young mass per age: eight lanes per age, each over a strided share
     // of the (alpha, Z) nodes, combined by a fixed butterfly
     const int nm = nf * nz;
@@ -512,6 +539,12 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       if (ag < ny && c == 0) s_wq[ag] = s;
     }
     __syncthreads();
+    if (a.WQ) {
+      const int n_nc = lib.neb_a1 - lib.neb_a0;
+      for (int q = tid; q < n_nc; q += 256) a.WQ[(size_t)r * n_nc + q] = s_wq[lib.neb_a0 + q] / kWqScale;
+    }
+  }
+  if (nl > 0) {
     // two threads per line (adjacent lanes), each over half of the young ages
     const int half = tid & 1, nyh = (ny + 1) >> 1;
     const int a0 = half ? nyh : 0, a1 = half ? ny : nyh;
@@ -521,13 +554,14 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       if (l < nl)
         for (int ag = a0; ag < a1; ++ag) Ll += (double)s_lt[l * ny + ag] * s_wq[ag];
       Ll += __shfl_xor(Ll, 1);
+      Ll *= neb_s;
       if (l < nl && half == 0) {
         if (kind == 0) wacc[a.line_k0 + l] = (Acc)(Ll / kLsun);   // photometry: lines on the model grid
         else a.Lline[(size_t)r * nl + l] = Ll;                    // spectra: lines on the detector pixels
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
 
   // ---- D: the row in the contraction's format and its K-tile occupancy bits.  A thread
   //      takes eight consecutive K entries (one 16-byte run of a 16-bit plane); a wave
@@ -630,6 +664,10 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     pr.alpha_bc = s_th[TH_ALPHA_BC];
     pr.tau_diff = s_th[TH_TAU_DIFF];
     pr.delta = s_th[TH_DELTA];
+    pr.bc_p = bc_p;
+    pr.bc_q = bc_q;
+    pr.neb_s = neb_s;
+    pr.fob = fob;
     pr.b = b;
     pr.obs = slot;
     pr.kind = kind;
@@ -671,6 +709,7 @@ hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s) {
   a.mask_words = pl.mask_words;
   a.rows = pl.rows;
   a.Lline = pl.Lline;
+  a.WQ = pl.WQ;
   a.kpos = pl.kpos;
   a.line_k0 = pl.line_k0;
   const size_t sm = prep_smem_bytes(lib, pl.mode);

@@ -265,9 +265,11 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
       for (int l = tid; l < nl; l += 256) {
         const double lw = lib.line_wave[l];
         const double lnlv = log(lw / kLamV);
-        const double tau = pr.tau_bc * exp(pr.alpha_bc * lnlv) +
-                           pr.tau_diff * exp(pr.delta * lnlv) * (lib.line_a[l] + (0.85 - 1.9 * pr.delta) * lib.line_d[l]);
-        const double Fl = a.Lline[(size_t)r * nl + l] * exp(-tau) * Tfac;
+        // the young light's birth-cloud transmission (with an escape geometry's mixture),
+        // then the diffuse screen
+        const double tbc = pr.bc_p * exp(-pr.tau_bc * exp(pr.alpha_bc * lnlv)) + pr.bc_q;
+        const double td = exp(-pr.tau_diff * exp(pr.delta * lnlv) * (lib.line_a[l] + (0.85 - 1.9 * pr.delta) * lib.line_d[l]));
+        const double Fl = a.Lline[(size_t)r * nl + l] * tbc * td * Tfac;
         const double lobs = opz * lw;
         double v = ob.lsf_value;
         if (ob.has_curve) {

@@ -32,6 +32,7 @@ sps_status Workspace::create(const sps_library *L, int mb, int n_data, int n_fno
   const size_t gb = forward_only ? 1 : Bp;   // gradient-pass buffers
   Yatt = al(gb * g.N_pad * 8);
   Lline = (double *)al(Bp * (size_t)std::max(1, g.n_line) * 8);
+  if (g.has_cont) WQ = (double *)al(Bp * (size_t)(g.neb_a1 - g.neb_a0) * 8);
   gvec = (double *)al(gb * (size_t)std::max(1, n_data) * 8);
   gnoise = (double *)al(gb * 4 * 8);
   gbuf = (double *)al(gb * 16 * 8);

@@ -33,6 +33,7 @@ struct Workspace {
   void *F = nullptr, *Yatt = nullptr;   // B_pad * N_pad * 8 bytes each
   int *tiles = nullptr;          // the contraction's tile list (k_tile_list): 1 + (B_pad/64) * (N_pad/64) ints
   double *Lline = nullptr;
+  double *WQ = nullptr;          // nebular continuum: photon-weighted masses [B_pad][nebular ages]
   double *gvec = nullptr, *gnoise = nullptr;
   double *gbuf = nullptr;        // adjoint per-point sums [B_pad][16]
   double *mbuf = nullptr;        // model at sorted rows [B_pad][n_data] (gradient pass)
@@ -72,6 +73,7 @@ struct sps_library {
   std::vector<double> wave_h;      // host copy of the wavelength grid
   int n_age = 0, n_z = 0, n_afe = 0, N = 0, n_young = 0, n_line = 0, n_sfh = 0, n_zh = 0;
   int line_k0 = 0;
+  bool line_tau_axis = false;      // the line table came on an age axis of its own
   uint32_t precisions = 0;
   sps::DevLib dev;
   int *kpos_d = nullptr;

@@ -1,6 +1,7 @@
 // Allocation-free forward + logL: sps_logl with the per-call scratch of the forward path
 // (batch keys, weight rows, K-tile occupancy bits, per-point rows, the attenuated
-// rest-frame spectrum, line luminosities) carved from one file-scope device array
+// rest-frame spectrum, line luminosities, the tile list, the nebular-continuum masses)
+// carved from one file-scope device array
 // instead of the observation's workspace.  For callers that cannot allocate device
 // memory: code under HIP graph capture, tight serving loops, harnesses that forbid it.
 #include <hip/hip_runtime.h>
@@ -61,7 +62,8 @@ size_t static_scratch_bytes(const DevLib &g, int B, int prec) {
   return align256(Bp * 8) + align256(Bp * g.K_pad * w_el) + align256(Bp * mask_words * 4) +
          align256(Bp * sizeof(PointRow)) + align256(Bp * g.N_pad * f_el) +
          align256(Bp * (size_t)(g.n_line > 0 ? g.n_line : 1) * 8) +
-         align256(((Bp + 63) / 64 * (g.N_pad / kSpanTile) + 1) * 4);
+         align256(((Bp + 63) / 64 * (g.N_pad / kSpanTile) + 1) * 4) +
+         align256(Bp * (size_t)(g.has_cont ? g.neb_a1 - g.neb_a0 : 1) * 8);
 }
 
 }  // namespace sps
@@ -102,6 +104,7 @@ extern "C" sps_status sps_logl_static(const sps_library *L, const sps_obs *o, co
   w.F = take(Bp * g.N_pad * f_el);
   w.Lline = (double *)take(Bp * (size_t)(g.n_line > 0 ? g.n_line : 1) * 8);
   w.tiles = (int *)take(((Bp + 63) / 64 * (g.N_pad / kSpanTile) + 1) * 4);
+  w.WQ = (double *)take(Bp * (size_t)(g.has_cont ? g.neb_a1 - g.neb_a0 : 1) * 8);
   w.counter = nullptr;
   return launch_forward(L, w, o->dev_obs, nullptr, theta, B, prec, logl, model, o->host.n_data, false,
                         o->host.n_data, nullptr, (hipStream_t)stream);

@@ -34,7 +34,13 @@ class LibraryDesc(C.Structure):
                 ("H0", C.c_double), ("Om", C.c_double), ("dust_a", _dp), ("dust_d", _dp),
                 ("n_line", C.c_int32), ("n_zg", C.c_int32), ("n_u", C.c_int32),
                 ("line_wave", _dp), ("line_table", _dp), ("zg_nodes", _dp), ("u_nodes", _dp),
-                ("precisions", C.c_uint32), ("device", C.c_int32)]
+                ("precisions", C.c_uint32), ("device", C.c_int32),
+                ("n_line_tau", C.c_int32), ("line_tau", _dp),
+                ("n_cont_tau", C.c_int32), ("n_cont_zg", C.c_int32), ("n_cont_u", C.c_int32),
+                ("cont_tau", _dp), ("cont_zg", _dp), ("cont_u", _dp), ("cont_table", _dp),
+                ("escape", C.c_int32)]
+
+ESCAPE = {"none": 0, "runaway_bc": 1, "picket": 2}
 
 
 class LibraryInfo(C.Structure):
@@ -47,7 +53,7 @@ class Layout(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "P", "n_scalar", "sfh", "n_sfh", "zh", "n_zh", "logmass", "zred", "tau_bc", "alpha_bc", "tau_diff",
         "delta", "logzsol", "gas_logz", "gas_logu", "afe", "log_err_scale", "log_f_calib", "log_f_data",
-        "log_jitter")]
+        "log_jitter", "frac_obrun")]
 
 
 class ObsDesc(C.Structure):
@@ -126,9 +132,12 @@ class Library:
     """Device-resident SSP library and model configuration (sps_library_load)."""
 
     def __init__(self, lib_arrays: dict, n_sfh: int, T1: float, n_zh: int, cosmo=(70.0, 0.3),
-                 dust: dict | None = None, lines: dict | None = None, precisions=("fp32",), device: int = 0):
+                 dust: dict | None = None, lines: dict | None = None, precisions=("fp32",), device: int = 0,
+                 cont: dict | None = None, escape: str = "none"):
         """``device=-1`` loads a host-only library (layout and observation operators; used by
-        the mock server executor)."""
+        the mock server executor).  ``lines`` may carry ``line_tau`` (the table's own age axis);
+        ``cont`` is a nebular continuum cube (cont_table [tau][zg][u][wave], tau_nodes,
+        zg_nodes, u_nodes); ``escape`` is "none", "runaway_bc" or "picket"."""
         L = lib()
         keep = []
         ages, logz, wave = _arr(lib_arrays["ages"]), _arr(lib_arrays["logz"]), _arr(lib_arrays["wave"])
@@ -154,6 +163,19 @@ class Library:
             keep += [lw, lt, zg, un]
             d.n_line, d.n_zg, d.n_u = len(lw), len(zg), len(un)
             d.line_wave, d.line_table, d.zg_nodes, d.u_nodes = _ptr(lw), _ptr(lt), _ptr(zg), _ptr(un)
+            if lines.get("line_tau") is not None:
+                ltau = _arr(lines["line_tau"])
+                keep.append(ltau)
+                d.n_line_tau, d.line_tau = len(ltau), _ptr(ltau)
+        if cont is not None:
+            ct, cz, cu = _arr(cont["tau_nodes"]), _arr(cont["zg_nodes"]), _arr(cont["u_nodes"])
+            cc = _arr(cont["cont_table"])
+            if cc.shape != (len(ct), len(cz), len(cu), d.n_wave):
+                raise ValueError(f"cont_table shape {cc.shape} != {(len(ct), len(cz), len(cu), d.n_wave)}")
+            keep += [ct, cz, cu, cc]
+            d.n_cont_tau, d.n_cont_zg, d.n_cont_u = len(ct), len(cz), len(cu)
+            d.cont_tau, d.cont_zg, d.cont_u, d.cont_table = _ptr(ct), _ptr(cz), _ptr(cu), _ptr(cc)
+        d.escape = ESCAPE[escape]
         mask = 0
         for p in precisions:
             mask |= 1 << PRECISIONS[p]

@@ -11,11 +11,15 @@ from oracle import model as om
 from synth import workloads as wl
 
 
-def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=(), wave_jitter=0.0, spec=None):
+def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=(), wave_jitter=0.0, spec=None,
+              cont=None, escape="none", line_tau=None):
     """wave_jitter > 0 moves each model wavelength by that fraction of the log step
     (sinusoidally), so that the grid is no longer log-uniform and the general
     interpolation paths are taken.  ``spec`` overrides entries of the spectrum grid
-    (lsf_mode, lsf_value: a constant or an array on the pixels, sigma_gal_kms, ...)."""
+    (lsf_mode, lsf_value: a constant or an array on the pixels, sigma_gal_kms, ...).
+    ``cont``: True for the synthetic nebular continuum cube, or a dict of arguments of
+    its generator (tau_nodes); ``escape``: the f_ob geometry (theta then carries frac_obrun); ``line_tau``: an
+    age axis of the line table's own."""
     B = cfg.batch if B is None else B
     lib = wl.make_library(cfg, seed)
     if wave_jitter > 0.0:
@@ -23,11 +27,16 @@ def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=()
         step = lw[1] - lw[0]
         lw = lw + wave_jitter * step * np.sin(0.7 * np.arange(lw.size))
         lib["wave"] = np.exp(lw)
-    lines = wl.make_lines(cfg, lib, seed + 1)
+    lines = wl.make_lines(cfg, lib, seed + 1, line_tau=line_tau)
     dust = wl.make_dust_tables(cfg, lib["wave"])
-    olib = om.build_library(cfg, lib, lines, dust)
-    theta = wl.make_theta(cfg, B, seed=theta_seed)
-    theta_true = wl.make_theta(cfg, 1, seed=theta_seed + 1000)
+    if cont is not None and cont is not False:
+        cont = wl.make_nebular_continuum(lib["wave"], seed + 3, **(cont if isinstance(cont, dict) else {}))
+    else:
+        cont = None
+    olib = om.build_library(cfg, lib, lines, dust, cont=cont, escape=escape)
+    esc = escape != "none"
+    theta = wl.make_theta(cfg, B, seed=theta_seed, escape=esc)
+    theta_true = wl.make_theta(cfg, 1, seed=theta_seed + 1000, escape=esc)
     kind = kind or ("spec" if cfg.spectrum else "phot")
     nz = {n: True for n in noise}
     if kind == "phot":
@@ -46,7 +55,7 @@ def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=()
         m_true = om.predict(olib, obs, theta_true)[0]
         obs.data, obs.sigma = wl.noisy_spectrum(m_true, seed + 5)
     return dict(cfg=cfg, lib=lib, lines=lines, dust=dust, olib=olib, theta=theta, theta_true=theta_true,
-                obs=obs, kind=kind)
+                obs=obs, kind=kind, cont=cont, escape=escape)
 
 
 def gpu_objects(case, precisions=("fp64", "fp32"), max_batch=None):
@@ -56,7 +65,8 @@ def gpu_objects(case, precisions=("fp64", "fp32"), max_batch=None):
     import paper_2609_30145_amd as sps
     cfg = case["cfg"]
     L = sps.Library(case["lib"], n_sfh=cfg.n_sfh, T1=cfg.T1, n_zh=cfg.n_zh, cosmo=cfg.cosmo, dust=case["dust"],
-                    lines=case["lines"], precisions=precisions)
+                    lines=case["lines"], precisions=precisions, cont=case.get("cont"),
+                    escape=case.get("escape", "none"))
     return L, gpu_observation(L, case, max_batch)
 
 
