@@ -195,6 +195,41 @@ def spectrum_leg(steps=20, warmup=3, seed=0):
     return out
 
 
+def nebular_leg(base, steps=20, warmup=3, seed=0):
+    """The photometric workload at full size with the nebular continuum cube (7 ages x 5
+    Z_gas x 4 log U on the 5994 wavelengths; 26 nebular SSP ages) and the runaway_bc escape
+    geometry (f_ob ~ U(0, 1): the ionising rows active): forward + logL throughput at the
+    headline precision and FP32, and the time it adds per step to the plain workload."""
+    import torch
+
+    import paper_2609_30145_amd as sps
+    from synth import workloads as wl
+    cfg = wl.CONFIGS["c1"]
+    lib = wl.make_library(cfg, seed)
+    lines = wl.make_lines(cfg, lib, seed + 1)
+    dust = wl.make_dust_tables(cfg, lib["wave"])
+    cont = wl.make_nebular_continuum(lib["wave"], seed + 3)
+    L = sps.Library(lib, n_sfh=cfg.n_sfh, T1=cfg.T1, n_zh=cfg.n_zh, cosmo=cfg.cosmo, dust=dust, lines=lines,
+                    precisions=("fp32", "fp16"), cont=cont, escape="runaway_bc")
+    filters = wl.make_filters(cfg.filters)
+    th_true = wl.make_theta(cfg, 1, seed=seed + 1002, escape=True)
+    O = sps.Observation(L, "phot", cfg.batch, filters=filters)
+    m_true = sps.forward(L, O, torch.tensor(th_true, device="cuda"), "fp32")[0].cpu().numpy()
+    d, sg = wl.noisy_photometry(m_true, seed + 5)
+    O.set_data(d, sg)
+    theta = torch.tensor(wl.make_theta(cfg, cfg.batch, seed=seed + 2, escape=True), device="cuda")
+    out = {"workload": f"c1 photometry, {cfg.batch} live points, with a nebular continuum cube (7 ages x 5 Z_gas x "
+                       f"4 log U, 26 nebular SSP ages) and the runaway_bc escape geometry (f_ob ~ U(0, 1))"}
+    for p in ("fp16_wl", "fp32"):
+        dt, tim = time_precision(L, O, theta, p, steps, warmup)
+        ms = 1e3 * dt / steps
+        out[f"{p}_evals_per_s"] = round(cfg.batch * steps / dt, 1)
+        out[f"{p}_ms_per_step"] = round(ms, 4)
+        if p in base:
+            out[f"{p}_added_ms_per_step"] = round(ms - base[p]["ms_per_step"], 4)
+    return out
+
+
 def serve_leg(seconds, rate_hz=50.0, target_load=0.5, seed=0, log=None):
     """Poisson stream of photometry / prism-spectrum fit requests served by sps_server on
     the alpha-enhanced library in FP16.  Capacity is measured first with a saturating
@@ -282,6 +317,7 @@ def main():
     ap.add_argument("--also", default="fp16,fp32,bf16", help="other precisions timed for the record")
     ap.add_argument("--no-spectrum", action="store_true", help="skip the spectroscopic leg")
     ap.add_argument("--no-small-batch", action="store_true", help="skip the 64-point leg")
+    ap.add_argument("--no-nebular", action="store_true", help="skip the nebular-continuum / escape leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -371,6 +407,8 @@ def main():
                               "hbm_frac": round(b64 / (ms64 * 1e-3) / 8e12, 4)}
     if not args.no_spectrum:
         out["spectrum"] = spectrum_leg()
+    if not args.no_nebular and args.workload == "c1":
+        out["nebular"] = nebular_leg(results)
     if args.serve_seconds > 0:
         out["serving"] = serve_leg(args.serve_seconds, log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:

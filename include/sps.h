@@ -114,8 +114,9 @@ typedef struct {
    * on the library's wavelengths.  Each cube is interpolated trilinearly (linearly in
    * age) and scaled by Q_ma (eq. C1); nebular emission goes to the SSP ages inside every
    * cube's age range, which must be birth-cloud ages (at most 128 of them with a
-   * continuum).  SPS_E_INVAL when an axis is not increasing, a table is not finite or no
-   * SSP age, or one older than t_young, falls in the range. */
+   * continuum, whose cube has at most 128 (Z_gas, U) nodes: else SPS_E_SHAPE).
+   * SPS_E_INVAL when an axis is not increasing, a table is not finite or no SSP age,
+   * or one older than t_young, falls in the range. */
   int32_t n_line_tau;
   const double *line_tau;   /* [n_line_tau] yr */
   int32_t n_cont_tau, n_cont_zg, n_cont_u;

@@ -140,6 +140,7 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
         !finite_all(d->cont_zg, d->n_cont_zg) || !increasing(d->cont_zg, d->n_cont_zg) ||
         !finite_all(d->cont_u, d->n_cont_u) || !increasing(d->cont_u, d->n_cont_u))
       return fail(SPS_E_INVAL, "nebular continuum axes must be finite and strictly increasing");
+    if ((int64_t)d->n_cont_zg * d->n_cont_u > 128) return fail(SPS_E_SHAPE, "nebular continuum cube: at most 128 (Z_gas, U) nodes");
     if (!finite_all(d->cont_table, (size_t)d->n_cont_tau * d->n_cont_zg * d->n_cont_u * N))
       return fail(SPS_E_INVAL, "nebular continuum cube not finite");
   }

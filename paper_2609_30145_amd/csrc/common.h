@@ -129,6 +129,10 @@ struct PointRow {
   // escape geometry: the young light crosses the birth cloud with transmission
   // bc_p e^{-tau_BC} + bc_q; nebular emission is scaled by neb_s; fob = f_ob
   double bc_p, bc_q, neb_s, fob;
+  // nebular continuum: the point's cell (nc_j) and fractions (nc_t) on the cube's
+  // (log Z_gas, log U) axes
+  double nc_t[2];
+  int nc_j[2];
   int b;        // original batch index
   int obs;      // observation slot
   int kind;     // observation kind

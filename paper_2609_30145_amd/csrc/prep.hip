@@ -668,6 +668,13 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     pr.bc_q = bc_q;
     pr.neb_s = neb_s;
     pr.fob = fob;
+    pr.nc_j[0] = pr.nc_j[1] = 0;
+    pr.nc_t[0] = pr.nc_t[1] = 0.0;
+    if (lib.has_cont) {
+      bool in;
+      grid_split_dev(lib.cz, lib.n_cz, s_th[TH_GAS_LOGZ], pr.nc_j[0], pr.nc_t[0], in);
+      grid_split_dev(lib.cu, lib.n_cu, s_th[TH_GAS_LOGU], pr.nc_j[1], pr.nc_t[1], in);
+    }
     pr.b = b;
     pr.obs = slot;
     pr.kind = kind;
