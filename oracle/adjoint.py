@@ -66,10 +66,11 @@ def _dsigma_inst_dlam(obs, lam_obs):
 def grad_point(L, obs, th, trunc=5.0):
     """(logL, d logL/d theta) for one parameter vector.
 
-    Covers the model without the nebular continuum and without an escape geometry, with
-    nebular-covered ages starting at the youngest SSP age."""
-    if L.cont is not None or L.escape != "none" or L.neb_a0 != 0:
-        raise NotImplementedError("the adjoint covers neither the nebular continuum nor f_ob")
+    Covers the model with the step SFH scheme, without the nebular continuum, an escape
+    geometry or the IGM, with nebular-covered ages starting at the youngest SSP age."""
+    if L.cont is not None or L.escape != "none" or L.neb_a0 != 0 or L.sfh_scheme != "step" or L.igm:
+        raise NotImplementedError("the adjoint covers the step SFH scheme without the nebular continuum, "
+                                  "f_ob or the IGM")
     cols = columns(L.n_sfh, L.n_zh)
     P = cols["P"]
     g = np.zeros(P)

@@ -22,7 +22,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import cosmology, dust, likelihood, nebular, projection, sfh
+from . import cosmology, dust, igm, likelihood, nebular, projection, sfh
 from .constants import ANG_CM, C_CMS, C_KMS, FNU_AB, LAM_LYMAN, LSUN
 
 SCALARS = ("logmass", "zred", "tau_bc", "alpha_bc", "tau_diff", "delta", "logzsol",
@@ -33,9 +33,10 @@ SCALARS = ("logmass", "zred", "tau_bc", "alpha_bc", "tau_diff", "delta", "logzso
 ESCAPE_GEOMETRIES = ("none", "runaway_bc", "picket")
 
 
-def columns(n_sfh, n_zh, escape=False):
-    """Column offsets of theta: the scalars, the SFH bin masses, the enrichment nodes and,
-    for a library with an escape geometry, frac_obrun = f_ob last (Sec. 2.3.2)."""
+def columns(n_sfh, n_zh, escape=False, igm=False):
+    """Column offsets of theta: the scalars, the SFH values (bin masses, or node SFRs under
+    the linear scheme), the enrichment nodes, then frac_obrun = f_ob for a library with an
+    escape geometry (Sec. 2.3.2) and igm_factor for one with IGM transmission (Sec. 2.6)."""
     c = {n: i for i, n in enumerate(SCALARS)}
     c["sfh"] = len(SCALARS)
     c["zh"] = len(SCALARS) + n_sfh
@@ -43,7 +44,15 @@ def columns(n_sfh, n_zh, escape=False):
     if escape:
         c["frac_obrun"] = c["P"]
         c["P"] += 1
+    if igm:
+        c["igm_factor"] = c["P"]
+        c["P"] += 1
     return c
+
+
+def lib_columns(L):
+    """columns() for a library."""
+    return columns(L.n_sfh, L.n_zh, L.escape != "none", L.igm)
 
 
 @dataclass
@@ -72,10 +81,13 @@ class Library:
     neb_a0: int = 0
     cont: dict | None = None  # nebular continuum cube (App. C) or None
     escape: str = "none"      # fesc_geometry: "none" (f_ob = 0), "runaway_bc", "picket"
+    sfh_scheme: str = "step"  # SFH -> age weights: "step" or "linear" (App. B)
+    igm: bool = False         # Madau (1995) IGM transmission with theta[igm_factor]
     flux_ion: np.ndarray | None = None   # raw ionising continuum of nebular-covered ages
 
 
-def build_library(cfg, lib, lines=None, dust_tab=None, cont=None, escape="none") -> Library:
+def build_library(cfg, lib, lines=None, dust_tab=None, cont=None, escape="none", sfh_scheme="step",
+                  igm=False) -> Library:
     """Static, parameter-independent preparation of the SSP grid (done once).
 
     ``lines``: line_wave, line_table [n_line][n_tau][n_zg][n_u] of log10(L_l/Q), zg_nodes,
@@ -83,7 +95,8 @@ def build_library(cfg, lib, lines=None, dust_tab=None, cont=None, escape="none")
     is the set of birth-cloud SSP ages).  ``cont``: cont_table [n_tau][n_zg][n_u][n_wave]
     of log10(L_nu/Q) on the library's wavelengths with its own tau_nodes, zg_nodes and
     u_nodes (App. C).  Nebular emission goes to the SSP ages inside every cube's age
-    range; they must be birth-cloud ages.  ``escape`` selects the f_ob geometry.
+    range; they must be birth-cloud ages.  ``escape`` selects the f_ob geometry,
+    ``sfh_scheme`` the step or linear (tent-integral) weights, ``igm`` the IGM transmission.
     """
     ages, wave = lib["ages"], lib["wave"]
     flux_raw = np.asarray(lib["flux"], dtype=np.float64)
@@ -100,6 +113,10 @@ def build_library(cfg, lib, lines=None, dust_tab=None, cont=None, escape="none")
     L.lo, L.hi = sfh.age_cells(ages)
     L.Q = nebular.ionising_rate(wave, flux_raw)
     L.escape = escape
+    if sfh_scheme not in ("step", "linear"):
+        raise ValueError("sfh_scheme must be 'step' or 'linear'")
+    L.sfh_scheme = sfh_scheme
+    L.igm = bool(igm)
     ranges = []
     if lines is not None:
         L.lines = dict(lines)
@@ -163,8 +180,11 @@ def point_weights(L: Library, th, cols):
     z = th[cols["zred"]]
     t_univ = float(cosmology.age_of_universe_yr(z, L.H0, L.Om))
     edges = sfh.sfh_edges(t_univ, L.n_sfh, L.T1)
-    masses = th[cols["sfh"]:cols["sfh"] + L.n_sfh]
-    w = sfh.step_weights(edges, masses, L.lo, L.hi)
+    vals = th[cols["sfh"]:cols["sfh"] + L.n_sfh]
+    if L.sfh_scheme == "linear":
+        w = sfh.tent_weights(edges, vals, L.ages)
+    else:
+        w = sfh.step_weights(edges, vals, L.lo, L.hi)
     if L.n_zh:
         zeta = sfh.bin_metallicity_hist(th[cols["zh"]:cols["zh"] + L.n_zh], edges, L.T1, t_univ)
     else:
@@ -219,7 +239,7 @@ def rest_frame(L: Library, theta, lines_on_grid=True):
     """Steps 1-5 for the whole batch: W, lines, Y, O and attenuated F [B, n_wave]."""
     theta = np.atleast_2d(theta)
     B = theta.shape[0]
-    cols = columns(L.n_sfh, L.n_zh, L.escape != "none")
+    cols = lib_columns(L)
     n_k = L.flux.shape[0] * L.flux.shape[1] * L.flux.shape[2]
     Wk = np.zeros((B, n_k))
     per = []
@@ -283,7 +303,16 @@ def line_fluxes(L: Library, th, cols, Lline, dl):
     pf, qf, sf = young_factors(L, escape_fraction(L, th, cols))
     T_bc = np.exp(-dust.birth_cloud_tau(lw, th[cols["tau_bc"]], th[cols["alpha_bc"]]))
     T_d = np.exp(-dust.diffuse_tau(lw, th[cols["tau_diff"]], th[cols["delta"]], a, d))
-    return sf * Lline * (pf * T_bc + qf) * T_d * 10.0 ** th[cols["logmass"]] / (4.0 * math.pi * dl * dl)
+    F = sf * Lline * (pf * T_bc + qf) * T_d * 10.0 ** th[cols["logmass"]] / (4.0 * math.pi * dl * dl)
+    return F * igm_transmission(L, th, cols, (1.0 + th[cols["zred"]]) * lw)
+
+
+def igm_transmission(L: Library, th, cols, lam_obs):
+    """IGM transmission at observed wavelengths (1 without IGM): Madau (1995) with the
+    optical depth scaled by theta[igm_factor] (Sec. 2.6)."""
+    if not L.igm:
+        return np.ones_like(np.asarray(lam_obs, dtype=np.float64))
+    return igm.transmission(lam_obs, th[cols["zred"]], th[cols["igm_factor"]])
 
 
 def predict(L: Library, obs, theta, rf=None, trunc=5.0):
@@ -300,8 +329,11 @@ def predict(L: Library, obs, theta, rf=None, trunc=5.0):
     for b in range(theta.shape[0]):
         th = theta[b]
         scale, dl = observer_scale(L, th, cols)
-        fnu = fnu_observed(L, rf["F"][b], scale)
         z = th[cols["zred"]]
+        # observer frame: mass, flux factor and the IGM transmission at lambda (1 + z), on
+        # the rest grid (Sec. 2.6); reading for spectra: the IGM is applied before the
+        # continuum kernel as a whole (exact when sigma_gal = 0)
+        fnu = fnu_observed(L, rf["F"][b], scale) * igm_transmission(L, th, cols, L.wave * (1.0 + z))
         if not spec:
             out.append(projection.band_maggies(L.wave, fnu, z, obs.filters))
             continue
@@ -339,7 +371,7 @@ def logl(L: Library, obs, theta, model=None, trunc=5.0):
     theta = np.atleast_2d(theta)
     if model is None:
         model = predict(L, obs, theta, trunc=trunc)
-    cols = columns(L.n_sfh, L.n_zh, L.escape != "none")
+    cols = lib_columns(L)
     mask = likelihood.inclusion_mask(obs.data, obs.sigma, obs.mask)
     out = np.empty(theta.shape[0])
     for b in range(theta.shape[0]):

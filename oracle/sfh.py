@@ -92,3 +92,63 @@ def ssp_weights(w, zeta, logz_nodes, afe=0.0, afe_nodes=(0.0,)):
             for iz, fz in zsplit:
                 W[ia, iz, :] += fa * fz * w[i, :]
     return W
+
+
+def _psi_integrals(alpha, beta, u, v):
+    """For psi(t) = alpha + beta t on [u, v] (0 < u <= v): (int psi dt, int psi ln t dt)."""
+    i0 = alpha * (v - u) + 0.5 * beta * (v * v - u * u)
+    F = lambda t: alpha * (t * np.log(t) - t) + beta * (0.5 * t * t * np.log(t) - 0.25 * t * t)
+    return i0, F(v) - F(u)
+
+
+def tent_weights(edges, psi_nodes, ages):
+    """Linear scheme (App. B, eq. tent_integral): w[i, a], the mass of SFH bin i given to
+    SSP age node a.
+
+    The SFR is piecewise linear in lookback time through (T_i, psi_i); the spectrum between
+    adjacent age nodes t_j < t_{j+1} is the linear-in-ln t mix a_j(t) s(t_j) + b_{j+1}(t)
+    s(t_{j+1}), a_j = ln(t_{j+1}/t) / ln(t_{j+1}/t_j), b_{j+1} = 1 - a_j, so node j takes
+    int psi a_j over [t_j, t_{j+1}] plus int psi b_j over [t_{j-1}, t_j], each split at the
+    bin edges and evaluated in closed form (int psi and int psi ln t of a linear psi).
+    Each bin's weights are clipped at zero and rescaled to its trapezoidal mass
+    (psi_i + psi_{i+1}) (T_{i+1} - T_i) / 2.
+
+    Readings: psi_nodes holds psi at T_0 .. T_{n-1} (n = number of bins, element 0 the
+    most recent) and the SFR at the oldest edge T_n repeats psi_{n-1}; lookback times
+    below the youngest age node or above the oldest belong to that end node alone (the
+    interpolation is clamped, like the metallicity axis).
+    """
+    edges = np.asarray(edges, dtype=np.float64)
+    n = len(edges) - 1
+    psi = np.concatenate([np.asarray(psi_nodes, dtype=np.float64), [psi_nodes[-1]]])
+    t = np.asarray(ages, dtype=np.float64)
+    na = len(t)
+    L = np.log(t)
+    w = np.zeros((n, na))
+    for i in range(n):
+        T0, T1 = edges[i], edges[i + 1]
+        beta = (psi[i + 1] - psi[i]) / (T1 - T0)
+        alpha = psi[i] - beta * T0
+        # below the youngest node: all to node 0
+        u, v = T0, min(T1, t[0])
+        if v > u:
+            w[i, 0] += alpha * (v - u) + 0.5 * beta * (v * v - u * u)
+        # between nodes j and j+1
+        for j in range(na - 1):
+            u, v = max(T0, t[j]), min(T1, t[j + 1])
+            if v <= u:
+                continue
+            i0, i1 = _psi_integrals(alpha, beta, u, v)
+            to_j = (L[j + 1] * i0 - i1) / (L[j + 1] - L[j])
+            w[i, j] += to_j
+            w[i, j + 1] += i0 - to_j
+        # above the oldest node: all to the last node
+        u, v = max(T0, t[-1]), T1
+        if v > u:
+            w[i, -1] += alpha * (v - u) + 0.5 * beta * (v * v - u * u)
+        w[i] = np.maximum(w[i], 0.0)
+        m_i = 0.5 * (psi[i] + psi[i + 1]) * (T1 - T0)
+        s = w[i].sum()
+        if s > 0.0:
+            w[i] *= m_i / s
+    return w

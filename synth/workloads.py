@@ -43,15 +43,19 @@ THETA_SCALARS = (
 N_SCALARS = len(THETA_SCALARS)
 
 
-def theta_columns(n_sfh: int, n_zh: int, escape: bool = False) -> dict:
+def theta_columns(n_sfh: int, n_zh: int, escape: bool = False, igm: bool = False) -> dict:
     """Column offsets of the theta layout (scalars, then sfh[n_sfh], then zh[n_zh], then,
-    for a library with an ionising-photon escape geometry, frac_obrun)."""
+    for a library with an ionising-photon escape geometry, frac_obrun, then, with IGM
+    transmission, igm_factor)."""
     cols = {name: i for i, name in enumerate(THETA_SCALARS)}
     cols["sfh"] = N_SCALARS
     cols["zh"] = N_SCALARS + n_sfh
     cols["P"] = N_SCALARS + n_sfh + n_zh
     if escape:
         cols["frac_obrun"] = cols["P"]
+        cols["P"] += 1
+    if igm:
+        cols["igm_factor"] = cols["P"]
         cols["P"] += 1
     return cols
 
@@ -321,22 +325,27 @@ def _clipped_t(rng, nu, scale, clip, size):
     return np.clip(rng.standard_t(nu, size) * scale, -clip, clip)
 
 
-def make_theta(cfg: Config, B: int | None = None, seed: int = 2, escape: bool = False) -> np.ndarray:
+def make_theta(cfg: Config, B: int | None = None, seed: int = 2, escape: bool = False, igm: bool = False,
+               sfh_scheme: str = "step") -> np.ndarray:
     """Draw theta[B, P] from the configuration's priors.
 
     SFH: c0 uses Dirichlet(1,...,1) bin masses; the others draw clipped Student-t
     (nu=2, sigma=0.3, |d|<=1) log10 ratios between adjacent bins and normalise to
     one solar mass (the continuity-prior shape of Sec. 4.2, applied to masses).
     Enrichment history: zeta_0 ~ U(-2.2, 0.3) plus a clipped Student-t random
-    walk with sigma 0.2, clamped to the grid.  With ``escape``, a last column
-    frac_obrun ~ U(0, 1) from a stream of its own (the other columns are unchanged).
+    walk with sigma 0.2, clamped to the grid.  With ``escape``, a column frac_obrun ~
+    U(0, 1) and with ``igm`` a column igm_factor ~ U(0.5, 1.5), each from a stream of its
+    own (the other columns are unchanged).  Under the linear SFH scheme the SFH values are
+    node SFRs: the bin masses divided by 1e10 / n_sfh years.
     """
     B = cfg.batch if B is None else B
     rng = np.random.default_rng(seed)
-    cols = theta_columns(cfg.n_sfh, cfg.n_zh, escape)
+    cols = theta_columns(cfg.n_sfh, cfg.n_zh, escape, igm)
     th = np.zeros((B, cols["P"]))
     if escape:
         th[:, cols["frac_obrun"]] = np.random.default_rng(seed + 7919).uniform(0.0, 1.0, B)
+    if igm:
+        th[:, cols["igm_factor"]] = np.random.default_rng(seed + 104729).uniform(0.5, 1.5, B)
     zlo, zhi = cfg.z_range
     th[:, cols["logmass"]] = rng.uniform(8.0, 11.0, B)
     th[:, cols["zred"]] = rng.uniform(zlo, zhi, B)
@@ -370,7 +379,7 @@ def make_theta(cfg: Config, B: int | None = None, seed: int = 2, escape: bool = 
             th[:, cols["logzsol"]] = rng.uniform(-2.2, 0.3, B)
         if len(cfg.afe) > 1:
             th[:, cols["afe"]] = rng.uniform(min(cfg.afe), max(cfg.afe), B)
-    th[:, cols["sfh"]:cols["sfh"] + cfg.n_sfh] = m
+    th[:, cols["sfh"]:cols["sfh"] + cfg.n_sfh] = m if sfh_scheme == "step" else m * cfg.n_sfh / 1e10
     return th
 
 

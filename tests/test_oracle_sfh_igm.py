@@ -1,0 +1,139 @@
+"""Pins for the oracle's linear (tent-integral) SFH scheme (App. B, eq. tent_integral) and
+the IGM transmission (Sec. 2.6, final paragraph; Madau 1995).
+
+The tent weights are checked against brute-force quadrature of eq. tent_integral, per-bin
+mass conservation, and the narrow-burst limit (a burst between two age nodes is split by
+the log-age interpolation weights).  The IGM coefficients are the published ones and are
+not pinned by anything outside the formula (parity unpinned); the pins fix its structure:
+identity redward of Lyman alpha and at zero scaling, the power law in the optical-depth
+scaling, the Lyman alpha forest's lambda^3.46 law, continuity at the Lyman limit, and that
+photometric bands redward of Lyman alpha are untouched.
+"""
+import numpy as np
+import pytest
+
+from oracle import igm
+from oracle import model as om
+from oracle import sfh
+from synth import workloads as wl
+
+AGES = np.geomspace(1e6, 1.3e10, 40)
+
+
+def _brute_tent(edges, psi_nodes, ages, nq=100000):
+    """eq. tent_integral by the midpoint rule on every bin (no closed form)."""
+    psi = np.concatenate([psi_nodes, [psi_nodes[-1]]])
+    out = np.zeros((len(edges) - 1, len(ages)))
+    for i in range(len(edges) - 1):
+        T0, T1 = edges[i], edges[i + 1]
+        tt = T0 + (np.arange(nq) + 0.5) / nq * (T1 - T0)
+        ps = psi[i] + (psi[i + 1] - psi[i]) * (tt - T0) / (T1 - T0)
+        j = np.searchsorted(ages, tt) - 1
+        lo = j < 0
+        hi = j >= len(ages) - 1
+        mid = ~lo & ~hi
+        jm = j[mid]
+        a = np.log(ages[jm + 1] / tt[mid]) / np.log(ages[jm + 1] / ages[jm])
+        np.add.at(out[i], jm, ps[mid] * a)
+        np.add.at(out[i], jm + 1, ps[mid] * (1.0 - a))
+        out[i, 0] += ps[lo].sum()
+        out[i, -1] += ps[hi].sum()
+        out[i] *= (T1 - T0) / nq
+    return out
+
+
+def test_tent_weights_match_quadrature_of_the_tent_integral():
+    rng = np.random.default_rng(3)
+    edges = sfh.sfh_edges(1.1e10, 12, 3e6)
+    psi = np.exp(rng.normal(0.0, 1.0, 12)) * 1e-9
+    w = sfh.tent_weights(edges, psi, AGES)
+    ref = _brute_tent(edges, psi, AGES)
+    np.testing.assert_allclose(w, ref, rtol=0.0, atol=1e-7 * np.abs(ref).max())
+
+
+def test_tent_weights_conserve_each_bins_trapezoid_mass():
+    rng = np.random.default_rng(4)
+    edges = sfh.sfh_edges(9e9, 30, 3e6)
+    psi = np.exp(rng.normal(0.0, 2.0, 30)) * 1e-9
+    w = sfh.tent_weights(edges, psi, AGES)
+    p = np.concatenate([psi, [psi[-1]]])
+    mass = 0.5 * (p[:-1] + p[1:]) * np.diff(edges)
+    np.testing.assert_allclose(w.sum(axis=1), mass, rtol=1e-13, atol=0.0)
+    assert np.all(w >= 0.0)
+
+
+def test_narrow_burst_is_split_by_the_log_age_weights():
+    # a constant-SFR burst of width 1e-6 of its age between nodes j and j+1 puts mass m at
+    # t: (1 - b) m on node j and b m on node j+1, b = ln(t / t_j) / ln(t_{j+1} / t_j)
+    j, frac = 17, 0.37
+    t = AGES[j] * (AGES[j + 1] / AGES[j]) ** frac
+    h = 1e-6 * t
+    edges = np.array([0.0, t - h, t + h, t + 2 * h, 2e10])
+    psi = np.array([0.0, 1.0, 1.0, 0.0])
+    w = sfh.tent_weights(edges, psi, AGES)
+    # bin 1 holds the burst at constant SFR; the others ramp up to and down from it
+    m = w[1].sum()
+    assert m == pytest.approx(edges[2] - edges[1], rel=1e-12, abs=0.0)   # its trapezoid mass
+    # (the closed form loses about eight digits to cancellation over so narrow a bin)
+    assert w[1, j] / m == pytest.approx(1.0 - frac, rel=1e-7, abs=0.0)
+    assert w[1, j + 1] / m == pytest.approx(frac, rel=1e-7, abs=0.0)
+    assert np.count_nonzero(w[1]) == 2
+
+
+def test_model_linear_scheme_forms_the_trapezoid_masses():
+    cfg = wl.reduced(wl.CONFIGS["c1"], n_age=40, logz=(-2.0, -1.0, 0.0), n_wave=600, n_sfh=10, n_zh=0, n_lines=0)
+    lib = wl.make_library(cfg, 0)
+    L = om.build_library(cfg, lib, None, wl.make_dust_tables(cfg, lib["wave"]), sfh_scheme="linear")
+    th = wl.make_theta(cfg, 3, seed=5, sfh_scheme="linear")
+    cols = om.lib_columns(L)
+    for b in range(3):
+        p = om.point_weights(L, th[b], cols)
+        psi = np.concatenate([th[b, cols["sfh"]:cols["sfh"] + cfg.n_sfh], [th[b, cols["sfh"] + cfg.n_sfh - 1]]])
+        mass = np.sum(0.5 * (psi[:-1] + psi[1:]) * np.diff(p["edges"]))
+        assert p["W"].sum() == pytest.approx(mass, rel=1e-12, abs=0.0)
+
+
+def test_igm_is_identity_redward_of_lyman_alpha_and_at_zero_scaling():
+    for z in (0.5, 3.0, 7.2):
+        lam = np.geomspace(1215.67 * (1 + z), 6e4, 200)
+        assert np.all(igm.transmission(lam, z, 1.3) == 1.0)
+        lam = np.geomspace(912.0 * (1 + z) * 0.5, 1215.6 * (1 + z), 300)
+        assert np.all(igm.transmission(lam, z, 0.0) == 1.0)
+        T1 = igm.transmission(lam, z, 1.0)
+        # absorbers between z = 0 and the source: the Ly alpha forest covers (1216 A, 1216 (1 + z))
+        forest = lam > 1215.67
+        assert np.all(T1[forest] < 1.0) and np.all(T1 > 0.0) and np.all(T1 <= 1.0)
+        np.testing.assert_allclose(igm.transmission(lam, z, 0.6), T1 ** 0.6, rtol=1e-13, atol=0.0)
+
+
+def test_igm_lyman_alpha_forest_follows_its_power_law_and_the_limit_is_continuous():
+    z = 4.0
+    # between Ly beta and Ly alpha (observed) only the Ly alpha forest absorbs: tau ~ lambda^3.46
+    l1, l2 = 1030.0 * (1 + z), 1200.0 * (1 + z)
+    t1, t2 = igm.madau_tau(np.array([l1, l2]), z)
+    assert np.log(t2 / t1) / np.log(l2 / l1) == pytest.approx(3.46, rel=1e-12, abs=0.0)
+    # the Lyman-limit term starts from zero at the source's limit
+    ll = 911.75 * (1 + z)
+    tau = igm.madau_tau(np.array([ll * (1 - 1e-9), ll * (1 + 1e-9)]), z)
+    assert tau[0] == pytest.approx(tau[1], rel=1e-6, abs=0.0)
+    # and absorbs more at shorter wavelengths below it
+    lam = np.linspace(0.7, 0.999, 50) * ll
+    assert np.all(np.diff(igm.madau_tau(lam, z)) < 0.0)
+
+
+def test_model_bands_redward_of_lyman_alpha_are_untouched_by_the_igm():
+    cfg = wl.reduced(wl.CONFIGS["c1"], n_age=40, logz=(-2.0, -1.0, 0.0), n_wave=1500, n_sfh=10, n_zh=0, n_lines=0)
+    lib = wl.make_library(cfg, 0)
+    dust = wl.make_dust_tables(cfg, lib["wave"])
+    L0 = om.build_library(cfg, lib, None, dust)
+    L1 = om.build_library(cfg, lib, None, dust, igm=True)
+    filters = wl.make_filters("gauss20")
+    obs = om.Photometry(filters=filters)
+    th = wl.make_theta(cfg, 4, seed=8, igm=True)
+    th[:, 1] = [0.6, 1.0, 1.5, 2.0]                  # Ly alpha below every filter's nodes
+    reddest_blue_edge = min(f[0].min() for f in filters)
+    assert np.all(1215.67 * (1 + th[:, 1]) < reddest_blue_edge)
+    assert np.array_equal(om.predict(L1, obs, th), om.predict(L0, obs, th[:, :-1]))
+    th[:, 1] = 9.0                                   # now the bluest bands see the forest
+    m0, m1 = om.predict(L0, obs, th[:, :-1]), om.predict(L1, obs, th)
+    assert np.all(m1 <= m0) and np.any(m1 < 0.9 * m0)
