@@ -133,7 +133,19 @@ typedef struct {
    * f_ob of the young stars, ionising continuum included, escape free of both dust
    * components and attenuates the covered rest (and its nebular emission) by both. */
   int32_t escape;
+  /* SFH to age weights (App. B): SPS_SFH_STEP (bin masses, linear-time cell overlap) or
+   * SPS_SFH_LINEAR (theta's SFH values are the SFR at the lookback edges T_0 .. T_{n-1},
+   * the last repeated at T_n, Msun/yr per unit of 10^logmass; piecewise-linear SFR
+   * integrated against the linear-in-ln(age) tent of each SSP age node, eq. tent_integral,
+   * clipped at zero and rescaled to each bin's trapezoid mass). */
+  int32_t sfh_scheme;
+  /* IGM transmission (Sec. 2.6): 0 off, 1 the Madau (1995) Lyman-series and Lyman-limit
+   * optical depth scaled by a theta column igm_factor (after frac_obrun), applied at
+   * lambda (1 + z) to the observer-frame model and to each line. */
+  int32_t igm;
 } sps_library_desc;
+
+typedef enum { SPS_SFH_STEP = 0, SPS_SFH_LINEAR = 1 } sps_sfh_scheme;
 
 typedef enum { SPS_ESCAPE_NONE = 0, SPS_ESCAPE_RUNAWAY_BC = 1, SPS_ESCAPE_PICKET = 2 } sps_escape;
 
@@ -158,13 +170,14 @@ void sps_library_destroy(sps_library *lib);
  * 14 scalar columns (in this order: logmass, zred, tau_bc, alpha_bc, tau_diff,
  * delta, logzsol, gas_logz, gas_logu, afe, log_err_scale, log_f_calib,
  * log_f_data, log_jitter), then sfh[n_sfh] bin masses (Msun formed per unit of
- * 10^logmass), then zh[n_zh] enrichment nodes, then, for a library with an escape
- * geometry, frac_obrun (else frac_obrun = -1).  Unused columns are ignored. */
+ * 10^logmass; node SFRs under SPS_SFH_LINEAR), then zh[n_zh] enrichment nodes, then,
+ * for a library with an escape geometry, frac_obrun, then, with the IGM, igm_factor
+ * (each -1 when absent).  Unused columns are ignored. */
 typedef struct {
   int32_t P, n_scalar, sfh, n_sfh, zh, n_zh;
   int32_t logmass, zred, tau_bc, alpha_bc, tau_diff, delta, logzsol, gas_logz, gas_logu, afe;
   int32_t log_err_scale, log_f_calib, log_f_data, log_jitter;
-  int32_t frac_obrun;
+  int32_t frac_obrun, igm_factor;
 } sps_layout;
 sps_status sps_theta_layout(const sps_library *lib, sps_layout *out);
 
@@ -236,7 +249,8 @@ sps_status sps_logl(const sps_library *lib, sps_obs *obs, const double *theta_de
 /* logl_dev [B] and grad_dev [B, P] = d logL / d theta (FP64; columns the
  * model does not use are zero).  Hand-written reverse pass.  Supported for
  * SPS_FP64 and SPS_FP32, for libraries without a nebular continuum cube, an
- * escape geometry or a line table on an age axis of its own (else SPS_E_INVAL). */
+ * escape geometry, a line table on an age axis of its own, the linear SFH scheme or
+ * the IGM (else SPS_E_INVAL). */
 sps_status sps_logl_grad(const sps_library *lib, sps_obs *obs, const double *theta_dev, int32_t B,
                          int32_t precision, double *logl_dev, double *grad_dev, void *hip_stream);
 

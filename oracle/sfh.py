@@ -94,11 +94,23 @@ def ssp_weights(w, zeta, logz_nodes, afe=0.0, afe_nodes=(0.0,)):
     return W
 
 
-def _psi_integrals(alpha, beta, u, v):
-    """For psi(t) = alpha + beta t on [u, v] (0 < u <= v): (int psi dt, int psi ln t dt)."""
-    i0 = alpha * (v - u) + 0.5 * beta * (v * v - u * u)
-    F = lambda t: alpha * (t * np.log(t) - t) + beta * (0.5 * t * t * np.log(t) - 0.25 * t * t)
-    return i0, F(v) - F(u)
+def _log_moments(X):
+    """A = int_0^X ln(1+x) dx and B = int_0^X x ln(1+x) dx, by their closed forms, or by
+    their Taylor series below X = 0.05 (where the closed forms cancel)."""
+    if X < 0.05:
+        A = sum((-1) ** k * X ** k / (k * (k - 1)) for k in range(2, 16))
+        B = sum((-1) ** (n + 1) * X ** (n + 2) / (n * (n + 2)) for n in range(1, 15))
+        return A, B
+    lp = np.log1p(X)
+    return (1.0 + X) * lp - X, 0.5 * (X * X - 1.0) * lp - 0.25 * X * X + 0.5 * X
+
+
+def _piece(psi_u, beta, u, v):
+    """For psi(t) = psi_u + beta (t - u) on [u, v]: (int psi dt, int psi ln(t/u) dt), written
+    about the piece's own lower end so that no large terms cancel."""
+    X = (v - u) / u
+    A, B = _log_moments(X)
+    return (v - u) * (psi_u + 0.5 * beta * (v - u)), u * (psi_u * A + beta * u * B)
 
 
 def tent_weights(edges, psi_nodes, ages):
@@ -109,7 +121,9 @@ def tent_weights(edges, psi_nodes, ages):
     adjacent age nodes t_j < t_{j+1} is the linear-in-ln t mix a_j(t) s(t_j) + b_{j+1}(t)
     s(t_{j+1}), a_j = ln(t_{j+1}/t) / ln(t_{j+1}/t_j), b_{j+1} = 1 - a_j, so node j takes
     int psi a_j over [t_j, t_{j+1}] plus int psi b_j over [t_{j-1}, t_j], each split at the
-    bin edges and evaluated in closed form (int psi and int psi ln t of a linear psi).
+    bin edges and evaluated in closed form, written about each piece's lower end u (the
+    SFR as psi(u) + beta (t - u), ln t as ln u + ln(1 + (t - u)/u)) so that no large terms
+    cancel: the naive form alpha + beta t, alpha = psi_i - beta T_i, loses up to ~1e-11.
     Each bin's weights are clipped at zero and rescaled to its trapezoidal mass
     (psi_i + psi_{i+1}) (T_{i+1} - T_i) / 2.
 
@@ -123,29 +137,30 @@ def tent_weights(edges, psi_nodes, ages):
     psi = np.concatenate([np.asarray(psi_nodes, dtype=np.float64), [psi_nodes[-1]]])
     t = np.asarray(ages, dtype=np.float64)
     na = len(t)
-    L = np.log(t)
     w = np.zeros((n, na))
     for i in range(n):
         T0, T1 = edges[i], edges[i + 1]
         beta = (psi[i + 1] - psi[i]) / (T1 - T0)
-        alpha = psi[i] - beta * T0
+        at = lambda x: psi[i] + beta * (x - T0)            # the SFR at x in the bin
         # below the youngest node: all to node 0
         u, v = T0, min(T1, t[0])
         if v > u:
-            w[i, 0] += alpha * (v - u) + 0.5 * beta * (v * v - u * u)
-        # between nodes j and j+1
+            w[i, 0] += (v - u) * (at(u) + 0.5 * beta * (v - u))
+        # between nodes j and j+1: node j takes int psi ln(t_{j+1}/t), node j+1 int psi
+        # ln(t/t_j), each over ln(t_{j+1}/t_j); with I = int psi ln(t/u) about the piece's
+        # lower end u: ln(t_{j+1}/u) int psi - I and ln(u/t_j) int psi + I
         for j in range(na - 1):
             u, v = max(T0, t[j]), min(T1, t[j + 1])
             if v <= u:
                 continue
-            i0, i1 = _psi_integrals(alpha, beta, u, v)
-            to_j = (L[j + 1] * i0 - i1) / (L[j + 1] - L[j])
-            w[i, j] += to_j
-            w[i, j + 1] += i0 - to_j
+            i0, I = _piece(at(u), beta, u, v)
+            dL = np.log(t[j + 1] / t[j])
+            w[i, j] += (np.log(t[j + 1] / u) * i0 - I) / dL
+            w[i, j + 1] += (np.log(u / t[j]) * i0 + I) / dL
         # above the oldest node: all to the last node
         u, v = max(T0, t[-1]), T1
         if v > u:
-            w[i, -1] += alpha * (v - u) + 0.5 * beta * (v * v - u * u)
+            w[i, -1] += (v - u) * (at(u) + 0.5 * beta * (v - u))
         w[i] = np.maximum(w[i], 0.0)
         m_i = 0.5 * (psi[i] + psi[i + 1]) * (T1 - T0)
         s = w[i].sum()

@@ -145,6 +145,8 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
       return fail(SPS_E_INVAL, "nebular continuum cube not finite");
   }
   if (d->escape < SPS_ESCAPE_NONE || d->escape > SPS_ESCAPE_PICKET) return fail(SPS_E_INVAL, "unknown escape geometry");
+  if (d->sfh_scheme != SPS_SFH_STEP && d->sfh_scheme != SPS_SFH_LINEAR) return fail(SPS_E_INVAL, "unknown SFH scheme");
+  if (d->igm != 0 && d->igm != 1) return fail(SPS_E_INVAL, "igm must be 0 or 1");
   // nebular-covered SSP ages [neb_a0, neb_a1): inside every cube's age range (App. C)
   int neb_a0 = 0, neb_a1 = 0;
   if (nl > 0 || has_cont) {
@@ -201,8 +203,11 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   g.n_u = nl ? d->n_u : 0;
   g.n_sfh = d->n_sfh;
   g.n_zh = d->n_zh;
-  g.P = TH_NSCALAR + d->n_sfh + d->n_zh + (d->escape ? 1 : 0);
+  g.P = TH_NSCALAR + d->n_sfh + d->n_zh + (d->escape ? 1 : 0) + (d->igm ? 1 : 0);
   g.th_fob = TH_NSCALAR + d->n_sfh + d->n_zh;
+  g.th_igm = g.th_fob + (d->escape ? 1 : 0);
+  g.igm = d->igm;
+  g.sfh_scheme = d->sfh_scheme;
   g.escape = d->escape;
   g.neb_a0 = neb_a0;
   g.neb_a1 = neb_a1;
@@ -404,6 +409,10 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
     for (int a = 0; a < na; ++a) ptab[o++] = hi[a];
     for (int m = 0; m < g.n_zg; ++m) ptab[o++] = d->zg_nodes[m];
     for (int m = 0; m < g.n_u; ++m) ptab[o++] = d->u_nodes[m];
+    if (g.sfh_scheme) {   // the ages close the block, after Q (written by the packing)
+      size_t oa = o + (g.has_neb ? (size_t)nf * nz * ny : 0);
+      for (int a = 0; a < na; ++a) ptab[oa++] = d->ages[a];
+    }
   }
   double *ptab_d = (double *)up(ptab.data(), ptab.size() * 8);
   g.prep_tab = ptab_d;
@@ -597,6 +606,7 @@ extern "C" sps_status sps_theta_layout(const sps_library *L, sps_layout *o) {
   o->log_f_data = TH_LOG_F_DATA;
   o->log_jitter = TH_LOG_JITTER;
   o->frac_obrun = L->dev.escape ? L->dev.th_fob : -1;
+  o->igm_factor = L->dev.igm ? L->dev.th_igm : -1;
   return SPS_OK;
 }
 
@@ -906,9 +916,9 @@ extern "C" sps_status sps_logl_grad(const sps_library *L, sps_obs *o, const doub
                                     double *logl, double *grad, void *stream) {
   if (!logl || !grad) return fail(SPS_E_INVAL, "logl_dev / grad_dev is NULL");
   if (prec != SPS_FP64 && prec != SPS_FP32) return fail(SPS_E_INVAL, "gradients are available for FP64 and FP32");
-  if (L && (L->dev.has_cont || L->dev.escape || L->line_tau_axis))
+  if (L && (L->dev.has_cont || L->dev.escape || L->line_tau_axis || L->dev.sfh_scheme || L->dev.igm))
     return fail(SPS_E_INVAL, "gradients are not available for libraries with a nebular continuum cube, an escape "
-                "geometry or a line table on an age axis of its own");
+                "geometry, a line table on an age axis of its own, the linear SFH scheme or the IGM");
   sps_status st = run_forward(L, o, theta, B, prec, logl, nullptr, true, (hipStream_t)stream);
   if (st != SPS_OK) return st;
   return run_adjoint(L, o, theta, B, prec, grad, (hipStream_t)stream);

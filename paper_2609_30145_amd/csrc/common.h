@@ -53,6 +53,8 @@ struct DevLib {
   // per-pixel reference, [neb age][n_cz][n_cu][N_pad], with 10^ref * c / lambda^2 / Lsun *
   // kWqScale per pixel (cont_sc); FP64 copies in log10 units for the FP64 path.
   int has_cont, n_cz, n_cu;
+  int sfh_scheme;                    // 0 step, 1 linear (tent integral; ages close prep_tab)
+  int igm, th_igm;                   // Madau IGM and the theta column of igm_factor
   const double *cz, *cu;
   const float *cont_f, *cont_sc_f;
   const double *cont_d, *cont_sc_d;
@@ -86,7 +88,8 @@ struct DevLib {
   const double *gl_u, *gl_w;         // [n_gl] composite Gauss-Legendre on [0,1]
   // The weight builder's node tables in one block, in the order of its LDS layout:
   // logz[n_z], afe[n_afe] (0 when n_afe = 1), cell_lo[n_age], cell_hi[n_age],
-  // zg[n_zg], un[n_u], Q[n_afe][n_z][n_young] (nebular emission only), padded to an even count.
+  // zg[n_zg], un[n_u], Q[n_afe][n_z][n_young] (nebular emission only), ages[n_age] (linear SFH
+// scheme only), padded to an even count.
   const double *prep_tab;
 };
 
@@ -97,7 +100,7 @@ constexpr double kWqScale = 1.4272476927059599e45;   // 2^150
 // Length in doubles of DevLib::prep_tab.
 __host__ __device__ inline int prep_tab_len(const DevLib &lib) {
   const int nq = lib.has_neb ? lib.n_afe * lib.n_z * lib.n_young : 0;
-  const int n = lib.n_z + lib.n_afe + 2 * lib.n_age + lib.n_zg + lib.n_u + nq;
+  const int n = lib.n_z + lib.n_afe + 2 * lib.n_age + lib.n_zg + lib.n_u + nq + (lib.sfh_scheme ? lib.n_age : 0);
   return n + (n & 1);
 }
 
@@ -400,6 +403,37 @@ __device__ __forceinline__ void grid_split_dev(const double *nodes, int n, doubl
   j = jj;
   t = (xc - nodes[jj]) / (nodes[jj + 1] - nodes[jj]);
 }
+
+// IGM (Sec. 2.6): the Madau (1995) optical depth of the Lyman-series forest (Ly alpha to
+// Ly delta, A_j (lambda/lambda_j)^3.46 where lambda_j < lambda < lambda_j (1 + z)) and of
+// Lyman-limit systems below the source's limit, at observed wavelength lam (A).
+template <typename T>
+__device__ __forceinline__ T igm_tau(T lam, T z) {
+  const T lj[4] = {(T)1215.67, (T)1025.72, (T)972.54, (T)949.74};
+  const T aj[4] = {(T)3.6e-3, (T)1.7e-3, (T)1.2e-3, (T)9.3e-4};
+  const T xe = (T)1 + z;
+  T tau = (T)0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (lam > lj[j] && lam < lj[j] * xe) tau += aj[j] * exp((T)3.46 * log(lam / lj[j]));
+  const T xc = lam / (T)911.75;
+  if (xc > (T)1 && xc < xe) {
+    const T lc = log(xc), le = log(xe);
+    auto pw = [](T l, T e) { return exp(e * l); };
+    tau += (T)0.25 * xc * xc * xc * (pw(le, (T)0.46) - pw(lc, (T)0.46)) +
+           (T)9.4 * pw(lc, (T)1.5) * (pw(le, (T)0.18) - pw(lc, (T)0.18)) -
+           (T)0.7 * xc * xc * xc * (pw(lc, (T)-1.32) - pw(le, (T)-1.32)) - (T)0.023 * (pw(le, (T)1.68) - pw(lc, (T)1.68));
+  }
+  return tau;
+}
+
+// IGM transmission of a point (theta row th) at observed wavelength lam: 1 without the IGM
+// or redward of Ly alpha.
+__device__ __forceinline__ double igm_T(const DevLib &lib, const double *th, double z, double lam) {
+  if (!lib.igm || !(lam < 1215.67 * (1.0 + z))) return 1.0;
+  return exp(-th[lib.th_igm] * igm_tau<double>(lam, z));
+}
+
 
 }  // namespace sps
 

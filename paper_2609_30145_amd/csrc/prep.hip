@@ -135,7 +135,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // FP64 for the FP64 path and FP32 otherwise).  The node tables (logz .. Q) are one
 // contiguous run in the order of DevLib::prep_tab, so that they arrive in one copy.
 struct PrepSmem {
-  int th, logz, afe, clo, chi, zg, un, Q, edges, mr, zt, zj, wq, ke, wacc, lt, total;
+  int th, logz, afe, clo, chi, zg, un, Q, ages, edges, mr, zt, zj, wq, ke, wacc, lt, total;
   __host__ __device__ PrepSmem(const DevLib &lib, int mode) {
     const bool f64 = mode == 0, w16 = mode >= 2;
     const int acc = f64 ? 8 : 4;
@@ -148,7 +148,8 @@ struct PrepSmem {
     zg = o;    o += lib.n_zg;
     un = o;    o += lib.n_u;
     Q = o;
-    o = logz + prep_tab_len(lib);                          // Q and the block's padding
+    ages = Q + (lib.has_neb ? lib.n_afe * lib.n_z * lib.n_young : 0);   // linear SFH scheme only
+    o = logz + prep_tab_len(lib);                          // Q, the ages and the block's padding
     edges = o; o += lib.n_sfh + 1;
     mr = o;    o += lib.n_sfh;                             // bin mass per unit time
     zt = o;    o += lib.n_sfh;
@@ -160,6 +161,74 @@ struct PrepSmem {
     total = o;
   }
 };
+
+// Linear SFH scheme (App. B, eq. tent_integral): the mass an SFH bin [T0, T1] with SFR
+// linear from p0 to p1 gives SSP age node ag: the integral of the SFR against the node's
+// tent (linear in ln t between neighbouring nodes; the whole interval below the first node
+// and above the last), the pieces added in the order lower end, lower half, upper half,
+// upper end.  Each piece [u, v] is written about its own start u, the SFR as
+// psi(u) + beta (t - u) and ln t as ln u + ln(1 + x), x = (t - u)/u, so that no large terms
+// cancel: with A = int_0^X ln(1+x) dx and B = int_0^X x ln(1+x) dx (X = (v - u)/u, closed
+// forms, or Taylor series below X = 0.05), int psi = (v - u)(psi(u) + beta (v - u)/2) and
+// I = int psi ln(t/u) = u (psi(u) A + beta u B); the lower half takes ln(u/t_{ag-1}) int psi
+// + I and the upper half ln(t_{ag+1}/u) int psi - I, each over ln(t_{ag+1}/t_ag).
+__device__ __forceinline__ void log_moments(double X, double &A, double &B) {
+  if (X < 0.05) {
+    double a = 0.0, b = 0.0, xk = X * X, xn = X * X * X;
+    for (int k = 2; k <= 15; ++k) {
+      a += ((k & 1) ? -xk : xk) / (double)(k * (k - 1));
+      xk *= X;
+    }
+    for (int n = 1; n <= 14; ++n) {
+      b += ((n & 1) ? xn : -xn) / (double)(n * (n + 2));
+      xn *= X;
+    }
+    A = a;
+    B = b;
+  } else {
+    const double lp = log1p(X);
+    A = (1.0 + X) * lp - X;
+    B = 0.5 * (X * X - 1.0) * lp - 0.25 * X * X + 0.5 * X;
+  }
+}
+
+__device__ double tent_mass(const double *ages, int na, int ag, double T0, double T1, double p0, double p1) {
+  const double beta = (p1 - p0) / (T1 - T0);
+  auto at = [&](double x) { return p0 + beta * (x - T0); };
+  auto piece = [&](double u, double v, double &i0, double &I) {
+    double A, B;
+    log_moments((v - u) / u, A, B);
+    const double pu = at(u);
+    i0 = (v - u) * (pu + 0.5 * beta * (v - u));
+    I = u * (pu * A + beta * u * B);
+  };
+  double c = 0.0;
+  if (ag == 0) {
+    const double u = T0, v = fmin(T1, ages[0]);
+    if (v > u) c += (v - u) * (at(u) + 0.5 * beta * (v - u));
+  }
+  if (ag > 0) {   // weight ln(t / t_{ag-1}) / ln(t_ag / t_{ag-1}) on [t_{ag-1}, t_ag]
+    const double u = fmax(T0, ages[ag - 1]), v = fmin(T1, ages[ag]);
+    if (v > u) {
+      double i0, I;
+      piece(u, v, i0, I);
+      c += (log(u / ages[ag - 1]) * i0 + I) / log(ages[ag] / ages[ag - 1]);
+    }
+  }
+  if (ag + 1 < na) {   // weight ln(t_{ag+1} / t) / ln(t_{ag+1} / t_ag) on [t_ag, t_{ag+1}]
+    const double u = fmax(T0, ages[ag]), v = fmin(T1, ages[ag + 1]);
+    if (v > u) {
+      double i0, I;
+      piece(u, v, i0, I);
+      c += (log(ages[ag + 1] / u) * i0 - I) / log(ages[ag + 1] / ages[ag]);
+    }
+  }
+  if (ag == na - 1) {
+    const double u = fmax(T0, ages[na - 1]), v = T1;
+    if (v > u) c += (v - u) * (at(u) + 0.5 * beta * (v - u));
+  }
+  return c;
+}
 
 // One workgroup (4 waves) per sorted row:
 //   A1  every global load of the phase in flight together: theta, the node-table block,
@@ -183,6 +252,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   double *s_th = smem + L.th, *s_logz = smem + L.logz, *s_afe = smem + L.afe;
   double *s_clo = smem + L.clo, *s_chi = smem + L.chi, *s_zg = smem + L.zg, *s_un = smem + L.un;
   double *s_Q = smem + L.Q, *s_edges = smem + L.edges, *s_mr = smem + L.mr, *s_zt = smem + L.zt;
+  const double *s_ages = smem + L.ages;
   double *s_wq = smem + L.wq;
   int *s_zj = (int *)(smem + L.zj);
   const int16_t *s_ke = (const int16_t *)(smem + L.ke);
@@ -378,7 +448,22 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       if (nz > 1) split_lds(s_logz, nz, zeta, j, t);
       s_zj[i] = j;
       s_zt[i] = t;
-      s_mr[i] = s_th[TH_NSCALAR + i] / (s_edges[i + 1] - s_edges[i]);
+      if (lib.sfh_scheme == 0) {
+        s_mr[i] = s_th[TH_NSCALAR + i] / (s_edges[i + 1] - s_edges[i]);
+      } else {
+        // linear scheme: the factor that rescales bin i's clipped tent masses to its
+        // trapezoid mass (p_i + p_{i+1}) (T_{i+1} - T_i) / 2, the last SFR repeated
+        const double p0 = s_th[TH_NSCALAR + i], p1 = s_th[TH_NSCALAR + min(i + 1, n_sfh - 1)];
+        const double T0 = s_edges[i], T1 = s_edges[i + 1];
+        double sum = 0.0;
+        for (int ag = 0; ag < na; ++ag) {
+          const double lo = ag == 0 ? 0.0 : s_ages[ag - 1], hi = ag == na - 1 ? HUGE_VAL : s_ages[ag + 1];
+          if (hi <= T0 || lo >= T1) continue;
+          sum += fmax(tent_mass(s_ages, na, ag, T0, T1, p0, p1), 0.0);
+        }
+        const double m = 0.5 * (p0 + p1) * (T1 - T0);
+        s_mr[i] = sum > 0.0 ? m / sum : 1.0;
+      }
     }
   }
   if (nl > 0) {
@@ -462,7 +547,39 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   int ja = 0;
   double ta = 0.0;
   if (nf > 1) split_lds(s_afe, nf, s_th[TH_AFE], ja, ta);
-  for (int ag = tid; ag < na; ag += 256) {
+  for (int ag = tid; ag < na && lib.sfh_scheme == 1; ag += 256) {
+    // linear scheme: every bin under the node's tent, [t_{ag-1}, t_{ag+1}] (from 0 for the
+    // first node, to +inf for the last)
+    const double lo = ag == 0 ? 0.0 : s_ages[ag - 1], hi = ag == na - 1 ? HUGE_VAL : s_ages[ag + 1];
+    int i = 0;
+    {
+      int l = 0, h = n_sfh;
+      while (l < h) {
+        const int mid = (l + h) >> 1;
+        if (s_edges[mid + 1] > lo) h = mid; else l = mid + 1;
+      }
+      i = l;
+    }
+    for (; i < n_sfh && s_edges[i] < hi; ++i) {
+      const double p0 = s_th[TH_NSCALAR + i], p1 = s_th[TH_NSCALAR + min(i + 1, n_sfh - 1)];
+      const double c = fmax(tent_mass(s_ages, na, ag, s_edges[i], s_edges[i + 1], p0, p1), 0.0);
+      if (c == 0.0) continue;
+      const double w = c * s_mr[i];
+      const int j = s_zj[i];
+      const double t = s_zt[i];
+      for (int q = 0; q < (nf > 1 ? 2 : 1); ++q) {
+        const int ia = nf > 1 ? ja + q : 0;
+        const double fa = nf > 1 ? (q == 0 ? 1.0 - ta : ta) : 1.0;
+        if (nz > 1) {
+          wacc[kpos_of(lib, ia, j, ag)] += (Acc)(fa * (1.0 - t) * w);
+          wacc[kpos_of(lib, ia, j + 1, ag)] += (Acc)(fa * t * w);
+        } else {
+          wacc[kpos_of(lib, ia, 0, ag)] += (Acc)(fa * w);
+        }
+      }
+    }
+  }
+  for (int ag = tid; ag < na && lib.sfh_scheme == 0; ag += 256) {
     const double lo = s_clo[ag], hi = s_chi[ag];
     // first bin whose upper edge exceeds lo
     int i = 0;

@@ -76,6 +76,11 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
       for (int q = 0; q < 16; ++q)
         if (k0 + 256 * q < seg_n) seg[k0 + 256 * q] = v[q];
     }
+    if (lib.igm) {   // the IGM transmission at lambda (1 + z) of the pixels blueward of Ly alpha (FP64:
+                     // optical depths of tens amplify FP32 rounding past the FP32 tolerance)
+      const double *thb = a.theta + (size_t)pr.b * a.P;
+      for (int k = tid; k < seg_n; k += 256) seg[k] *= (float)igm_T(lib, thb, pr.z, lib.wave_d[seg0 + k] * (1.0 + pr.z));
+    }
   }
   const DevObs ob = a.obs_table[pr.obs];
   const double *th = a.theta + (size_t)pr.b * a.P;
@@ -232,7 +237,7 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
             if (in[q]) {
               const int k = kq[q];
               const double w0 = lib.wave_d[k], w1 = lib.wave_d[k + 1];
-              const T f0 = Fr[k], f1 = Fr[k + 1];
+              const T f0 = Fr[k] * (T)igm_T(lib, th, z, w0 * opz), f1 = Fr[k + 1] * (T)igm_T(lib, th, z, w1 * opz);
               const T w = sizeof(T) == 8 ? (T)ob.fr_d[j] : (T)ob.fr_f[j];
               const T t = (T)((lrq[q] - w0) / (w1 - w0));
               term = (double)(w * (f0 + t * (f1 - f0)));
@@ -269,8 +274,8 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
         // then the diffuse screen
         const double tbc = pr.bc_p * exp(-pr.tau_bc * exp(pr.alpha_bc * lnlv)) + pr.bc_q;
         const double td = exp(-pr.tau_diff * exp(pr.delta * lnlv) * (lib.line_a[l] + (0.85 - 1.9 * pr.delta) * lib.line_d[l]));
-        const double Fl = a.Lline[(size_t)r * nl + l] * tbc * td * Tfac;
         const double lobs = opz * lw;
+        const double Fl = a.Lline[(size_t)r * nl + l] * tbc * td * Tfac * igm_T(lib, th, z, lobs);
         double v = ob.lsf_value;
         if (ob.has_curve) {
           const int np = ob.n_data;
@@ -308,6 +313,13 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
         for (int q = 0; q < 8; ++q) {
           const int k = k0 + 256 * q;
           v[q] = k < seg_n ? (float)Fr[seg0 + k] * (float)lib.lam2_d[seg0 + k] : 0.f;
+        }
+        if (lib.igm) {   // the IGM transmission at lambda (1 + z), blueward of Ly alpha (FP64)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int k = k0 + 256 * q;
+            if (k < seg_n) v[q] *= (float)igm_T(lib, th, z, lib.wave_d[seg0 + k] * opz);
+          }
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q)
@@ -424,7 +436,8 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
           const double dk = lib.lnwave_d[k + 1] - lib.lnwave_d[k];
           if (s < 0.5 * dk) {
             const T t = (T)((x - lib.lnwave_d[k]) / dk);
-            const T fk = Fr[k] * (T)lib.lam2_d[k], fk1 = Fr[k + 1] * (T)lib.lam2_d[k + 1];
+            const T fk = Fr[k] * (T)(lib.lam2_d[k] * igm_T(lib, th, z, lib.wave_d[k] * opz));
+            const T fk1 = Fr[k + 1] * (T)(lib.lam2_d[k + 1] * igm_T(lib, th, z, lib.wave_d[k + 1] * opz));
             cont = fk + t * (fk1 - fk);
           } else {
             int j = lnwave_lower_bound(lib, x - 5.0 * s);
@@ -434,7 +447,7 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
               const double u = (lib.lnwave_d[j] - x) * inv;
               if (u > 5.0) break;
               const T w = sizeof(T) == 8 ? (T)exp(-0.5 * u * u) : (T)expf((float)(-0.5 * u * u));
-              num += (double)(w * (Fr[j] * (T)lib.lam2_d[j]));
+              num += (double)(w * (Fr[j] * (T)(lib.lam2_d[j] * igm_T(lib, th, z, lib.wave_d[j] * opz))));
               den += (double)w;
             }
             cont = (T)(num / den);

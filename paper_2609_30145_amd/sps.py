@@ -38,9 +38,10 @@ class LibraryDesc(C.Structure):
                 ("n_line_tau", C.c_int32), ("line_tau", _dp),
                 ("n_cont_tau", C.c_int32), ("n_cont_zg", C.c_int32), ("n_cont_u", C.c_int32),
                 ("cont_tau", _dp), ("cont_zg", _dp), ("cont_u", _dp), ("cont_table", _dp),
-                ("escape", C.c_int32)]
+                ("escape", C.c_int32), ("sfh_scheme", C.c_int32), ("igm", C.c_int32)]
 
 ESCAPE = {"none": 0, "runaway_bc": 1, "picket": 2}
+SFH_SCHEMES = {"step": 0, "linear": 1}
 
 
 class LibraryInfo(C.Structure):
@@ -53,7 +54,7 @@ class Layout(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "P", "n_scalar", "sfh", "n_sfh", "zh", "n_zh", "logmass", "zred", "tau_bc", "alpha_bc", "tau_diff",
         "delta", "logzsol", "gas_logz", "gas_logu", "afe", "log_err_scale", "log_f_calib", "log_f_data",
-        "log_jitter", "frac_obrun")]
+        "log_jitter", "frac_obrun", "igm_factor")]
 
 
 class ObsDesc(C.Structure):
@@ -133,11 +134,12 @@ class Library:
 
     def __init__(self, lib_arrays: dict, n_sfh: int, T1: float, n_zh: int, cosmo=(70.0, 0.3),
                  dust: dict | None = None, lines: dict | None = None, precisions=("fp32",), device: int = 0,
-                 cont: dict | None = None, escape: str = "none"):
+                 cont: dict | None = None, escape: str = "none", sfh_scheme: str = "step", igm: bool = False):
         """``device=-1`` loads a host-only library (layout and observation operators; used by
         the mock server executor).  ``lines`` may carry ``line_tau`` (the table's own age axis);
         ``cont`` is a nebular continuum cube (cont_table [tau][zg][u][wave], tau_nodes,
-        zg_nodes, u_nodes); ``escape`` is "none", "runaway_bc" or "picket"."""
+        zg_nodes, u_nodes); ``escape`` is "none", "runaway_bc" or "picket"; ``sfh_scheme`` is
+        "step" or "linear"; ``igm`` switches the Madau IGM transmission on."""
         L = lib()
         keep = []
         ages, logz, wave = _arr(lib_arrays["ages"]), _arr(lib_arrays["logz"]), _arr(lib_arrays["wave"])
@@ -176,6 +178,8 @@ class Library:
             d.n_cont_tau, d.n_cont_zg, d.n_cont_u = len(ct), len(cz), len(cu)
             d.cont_tau, d.cont_zg, d.cont_u, d.cont_table = _ptr(ct), _ptr(cz), _ptr(cu), _ptr(cc)
         d.escape = ESCAPE[escape]
+        d.sfh_scheme = SFH_SCHEMES[sfh_scheme]
+        d.igm = 1 if igm else 0
         mask = 0
         for p in precisions:
             mask |= 1 << PRECISIONS[p]

@@ -42,6 +42,39 @@ def _brute_tent(edges, psi_nodes, ages, nq=100000):
     return out
 
 
+def test_tent_weights_hold_twelve_digits_on_sloped_bins_far_from_t0():
+    # bins of a few per cent of their lookback time with SFRs changing tenfold across them:
+    # the closed form in alpha + beta t (alpha = psi_i - beta T_i) cancels there; written
+    # about each piece's own start it keeps its digits.  Reference: each piece between two
+    # age nodes integrated by 24-point Gauss-Legendre in extended precision (the integrand
+    # is analytic on a piece, so the rule is exact to rounding)
+    ages = np.geomspace(1e6, 1.3e10, 107)
+    edges = np.concatenate([[0.0], np.geomspace(3e6, 1.2e10, 121)])
+    psi = np.where(np.arange(121) % 2 == 0, 1e-9, 1e-8)
+    w = sfh.tent_weights(edges, psi, ages)
+    ld = np.longdouble
+    gx, gw = np.polynomial.legendre.leggauss(24)
+    gx, gw = gx.astype(ld), gw.astype(ld)
+    for i in (60, 90, 118):
+        T0, T1 = ld(edges[i]), ld(edges[i + 1])
+        p0, p1 = ld(psi[i]), ld(psi[i + 1] if i + 1 < len(psi) else psi[-1])
+        ref = np.zeros(len(ages), dtype=ld)
+        for j in range(len(ages) - 1):
+            u, v = max(T0, ld(ages[j])), min(T1, ld(ages[j + 1]))
+            if v <= u:
+                continue
+            tt = 0.5 * (u + v) + 0.5 * (v - u) * gx
+            ps = p0 + (p1 - p0) * (tt - T0) / (T1 - T0)
+            a = np.log(ld(ages[j + 1]) / tt) / np.log(ld(ages[j + 1]) / ld(ages[j]))
+            ref[j] += 0.5 * (v - u) * np.sum(gw * ps * a)
+            ref[j + 1] += 0.5 * (v - u) * np.sum(gw * ps * (1 - a))
+        nz = ref > 0
+        err = np.abs(w[i][nz] - ref[nz].astype(float)) / ref[nz].astype(float)
+        assert err.max() < 1e-12
+        # the bin's weights sum to its trapezoid mass to rounding
+        assert w[i].sum() == pytest.approx(float(0.5 * (p0 + p1) * (T1 - T0)), rel=1e-14, abs=0.0)
+
+
 def test_tent_weights_match_quadrature_of_the_tent_integral():
     rng = np.random.default_rng(3)
     edges = sfh.sfh_edges(1.1e10, 12, 3e6)
@@ -74,9 +107,8 @@ def test_narrow_burst_is_split_by_the_log_age_weights():
     # bin 1 holds the burst at constant SFR; the others ramp up to and down from it
     m = w[1].sum()
     assert m == pytest.approx(edges[2] - edges[1], rel=1e-12, abs=0.0)   # its trapezoid mass
-    # (the closed form loses about eight digits to cancellation over so narrow a bin)
-    assert w[1, j] / m == pytest.approx(1.0 - frac, rel=1e-7, abs=0.0)
-    assert w[1, j + 1] / m == pytest.approx(frac, rel=1e-7, abs=0.0)
+    assert w[1, j] / m == pytest.approx(1.0 - frac, rel=1e-11, abs=0.0)
+    assert w[1, j + 1] / m == pytest.approx(frac, rel=1e-11, abs=0.0)
     assert np.count_nonzero(w[1]) == 2
 
 
