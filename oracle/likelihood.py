@@ -37,3 +37,44 @@ def lnlike(data, model, sigma, mask, s=1.0, f_calib=None, f_data=None, jitter=No
     v = effective_variance(sg, model, d, s, f_calib, f_data, jitter)
     terms = -0.5 * (d - model) ** 2 / v - 0.5 * np.log(2.0 * np.pi * v)
     return float(np.sum(np.where(mask, terms, 0.0)))
+
+
+# ---------------------------------------------------------------------------------
+# Spectrophotometric calibration polynomial (Sec. 3.2, App. H.3, eq. app_polymarg)
+# ---------------------------------------------------------------------------------
+def chebyshev_design(pix_wave, order):
+    """A[i, m] = T_m(x_i), x the pixel wavelengths mapped linearly onto [-1, 1] (reading:
+    the first and last pixel of the observation map to -1 and +1)."""
+    lam = np.asarray(pix_wave, dtype=np.float64)
+    x = 2.0 * (lam - lam[0]) / (lam[-1] - lam[0]) - 1.0
+    return np.polynomial.chebyshev.chebvander(x, order)
+
+
+def calibrated_lnlike(data, model, sigma, mask, A, prior_sd, mode, s=1.0, f_calib=None, f_data=None,
+                      jitter=None):
+    """The calibrated model mu (1 + sum_m c_m T_m(x)): the residual r = d - mu is linear in c,
+    r = D c + n, D = diag(mu) A, n ~ N(0, C), C = diag(sigma_eff^2) at the uncalibrated model,
+    prior c ~ N(0, diag(s_m^2)); with M = D^T C^-1 D + diag(s_m^-2) and b = D^T C^-1 r:
+
+      mode "marginal" (eq. app_polymarg): lnL_diag(r) + b^T M^-1 b / 2 - ln|M| / 2 - ln|Lambda| / 2;
+      mode "optimise": lnL_diag(r - D c_hat) at the regularised best fit c_hat = M^-1 b
+      (Sec. 3.2: the polynomial optimised at each evaluation, with regularisation 1/s_m).
+    """
+    d = np.where(mask, data, 0.0)
+    sg = np.where(mask, sigma, 1.0)
+    v = effective_variance(sg, model, d, s, f_calib, f_data, jitter)
+    r = np.where(mask, d - model, 0.0)
+    iv = np.where(mask, 1.0 / v, 0.0)
+    D = model[:, None] * A
+    Mm = D.T @ (iv[:, None] * D) + np.diag(1.0 / np.asarray(prior_sd, dtype=np.float64) ** 2)
+    b = D.T @ (iv * r)
+    chat = np.linalg.solve(Mm, b)
+    if mode == "marginal":
+        base = lnlike(data, model, sigma, mask, s, f_calib, f_data, jitter)
+        _, logdet = np.linalg.slogdet(Mm)
+        return base + 0.5 * b @ chat - 0.5 * logdet - np.sum(np.log(prior_sd))
+    if mode == "optimise":
+        res = r - D @ chat
+        terms = -0.5 * res ** 2 * iv - 0.5 * np.log(2.0 * np.pi * v)
+        return float(np.sum(np.where(mask, terms, 0.0)))
+    raise ValueError(mode)

@@ -173,6 +173,11 @@ class Spectrum:
     mask: np.ndarray | None = None
     noise: dict = field(default_factory=dict)
     kind: str = "spec"
+    # spectrophotometric calibration polynomial (Sec. 3.2, App. H.3): None, "marginal" or
+    # "optimise", the Chebyshev order and the prior widths s_m of the coefficients
+    calib: str | None = None
+    calib_order: int = 0
+    calib_prior: np.ndarray | None = None
 
 
 def point_weights(L: Library, th, cols):
@@ -373,8 +378,14 @@ def logl(L: Library, obs, theta, model=None, trunc=5.0):
         model = predict(L, obs, theta, trunc=trunc)
     cols = lib_columns(L)
     mask = likelihood.inclusion_mask(obs.data, obs.sigma, obs.mask)
+    calib = getattr(obs, "calib", None)
+    A = likelihood.chebyshev_design(obs.pix_wave, obs.calib_order) if calib else None
     out = np.empty(theta.shape[0])
     for b in range(theta.shape[0]):
         s, fc, fd, j = noise_terms(obs, theta[b], cols)
-        out[b] = likelihood.lnlike(obs.data, model[b], obs.sigma, mask, s, fc, fd, j)
+        if calib:
+            out[b] = likelihood.calibrated_lnlike(obs.data, model[b], obs.sigma, mask, A, obs.calib_prior, calib,
+                                                  s, fc, fd, j)
+        else:
+            out[b] = likelihood.lnlike(obs.data, model[b], obs.sigma, mask, s, fc, fd, j)
     return out
