@@ -68,8 +68,8 @@ def grad_point(L, obs, th, trunc=5.0):
 
     Covers the model with the step SFH scheme, without the nebular continuum, an escape
     geometry or the IGM, with nebular-covered ages starting at the youngest SSP age."""
-    if getattr(obs, "calib", None):
-        raise NotImplementedError("the adjoint does not cover the calibration polynomial")
+    if getattr(obs, "calib", None) or obs.kind == "lines":
+        raise NotImplementedError("the adjoint covers neither the calibration polynomial nor line catalogues")
     if L.cont is not None or L.escape != "none" or L.neb_a0 != 0 or L.sfh_scheme != "step" or L.igm:
         raise NotImplementedError("the adjoint covers the step SFH scheme without the nebular continuum, "
                                   "f_ob or the IGM")

@@ -78,3 +78,17 @@ def calibrated_lnlike(data, model, sigma, mask, A, prior_sd, mode, s=1.0, f_cali
         terms = -0.5 * res ** 2 * iv - 0.5 * np.log(2.0 * np.pi * v)
         return float(np.sum(np.where(mask, terms, 0.0)))
     raise ValueError(mode)
+
+
+# ---------------------------------------------------------------------------------
+# Emission-line catalogues (App. I.2, eq. app_line_chi2_det / app_line_chi2_UL)
+# ---------------------------------------------------------------------------------
+def lines_lnlike(data, model, sigma, mask, upper):
+    """-chi^2 / 2 over the mask: detections ((d - m)/sigma)^2; upper limits the same when the
+    model exceeds the limit, else 0.  Reading: the noise floor and the normalisation term
+    do not enter (App. I.2 adds -chi^2_lines / 2)."""
+    d = np.where(mask, data, 0.0)
+    sg = np.where(mask, sigma, 1.0)
+    chi2 = ((d - model) / sg) ** 2
+    chi2 = np.where(upper & (model <= d), 0.0, chi2)
+    return float(-0.5 * np.sum(np.where(mask, chi2, 0.0)))

@@ -180,6 +180,19 @@ class Spectrum:
     calib_prior: np.ndarray | None = None
 
 
+@dataclass
+class Lines:
+    """Emission-line catalogue (Sec. 3.3, App. I): entry k is the sum of the library lines
+    blends[k] (an unresolved blend); integrated fluxes in erg/s/cm^2; upper[k] flags an
+    upper limit."""
+    blends: list
+    data: np.ndarray | None = None
+    sigma: np.ndarray | None = None
+    mask: np.ndarray | None = None
+    upper: np.ndarray | None = None
+    kind: str = "lines"
+
+
 def point_weights(L: Library, th, cols):
     """Steps 1-2 for one parameter vector: t_univ, edges, W[alpha, m, a]."""
     z = th[cols["zred"]]
@@ -324,6 +337,17 @@ def predict(L: Library, obs, theta, rf=None, trunc=5.0):
     """Model observables [B, n] (maggies) for photometry or a spectrum."""
     theta = np.atleast_2d(theta)
     spec = obs.kind == "spec"
+    if obs.kind == "lines":
+        # the line fluxes of App. I.1 summed over each entry's blend; no continuum
+        if rf is None:
+            rf = rest_frame(L, theta, lines_on_grid=False)
+        cols = rf["cols"]
+        out = []
+        for b in range(theta.shape[0]):
+            _, dl = observer_scale(L, theta[b], cols)
+            Fl = line_fluxes(L, theta[b], cols, rf["Lline"][b], dl)
+            out.append([float(np.sum(Fl[list(bl)])) for bl in obs.blends])
+        return np.array(out)
     if rf is None:
         rf = rest_frame(L, theta, lines_on_grid=not spec)
     cols = rf["cols"]
@@ -378,6 +402,10 @@ def logl(L: Library, obs, theta, model=None, trunc=5.0):
         model = predict(L, obs, theta, trunc=trunc)
     cols = lib_columns(L)
     mask = likelihood.inclusion_mask(obs.data, obs.sigma, obs.mask)
+    if obs.kind == "lines":
+        up = np.zeros(len(obs.blends), dtype=bool) if obs.upper is None else np.asarray(obs.upper, dtype=bool)
+        return np.array([likelihood.lines_lnlike(obs.data, model[b], obs.sigma, mask, up)
+                         for b in range(theta.shape[0])])
     calib = getattr(obs, "calib", None)
     A = likelihood.chebyshev_design(obs.pix_wave, obs.calib_order) if calib else None
     out = np.empty(theta.shape[0])
