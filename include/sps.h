@@ -184,7 +184,9 @@ sps_status sps_theta_layout(const sps_library *lib, sps_layout *out);
 /* ------------------------------------------------------------------------- */
 /* Observations (Sec. 3): photometry (App. E) or a spectrum (App. F)          */
 /* ------------------------------------------------------------------------- */
-enum { SPS_OBS_PHOT = 0, SPS_OBS_SPEC = 1 };
+enum { SPS_OBS_PHOT = 0, SPS_OBS_SPEC = 1, SPS_OBS_LINES = 2 };
+/* calibration polynomial of a spectrum (Sec. 3.2, App. H.3) */
+enum { SPS_CALIB_NONE = 0, SPS_CALIB_MARGINAL = 1, SPS_CALIB_OPTIMISE = 2 };
 /* LSF unit conventions of eq. F2.  SPS_LSF_BARE_R is rejected (SPS_E_INVAL):
  * a resolving power must state whether it is lambda/FWHM or lambda/sigma. */
 enum {
@@ -197,7 +199,7 @@ enum { SPS_NOISE_ERR_SCALE = 1, SPS_NOISE_F_CALIB = 2, SPS_NOISE_F_DATA = 4, SPS
 enum { SPS_WARN_LSF_FINER_THAN_LIBRARY = 1 };
 
 typedef struct {
-  int32_t kind;               /* SPS_OBS_PHOT or SPS_OBS_SPEC */
+  int32_t kind;               /* SPS_OBS_PHOT, SPS_OBS_SPEC or SPS_OBS_LINES */
   /* photometry: n_band filter curves concatenated; filter_len[b] nodes each,
    * observer-frame Angstrom, strictly increasing within a curve */
   int32_t n_band;
@@ -220,6 +222,24 @@ typedef struct {
                                  finite(sigma), sigma > 0 (App. H.1) */
   uint32_t noise_flags;       /* SPS_NOISE_* */
   int32_t max_batch;          /* workspace is sized for B <= max_batch */
+  /* spectrum: spectrophotometric calibration polynomial (Sec. 3.2, App. H.3).  The model
+   * mu (1 + sum_m c_m T_m(x)), T_m Chebyshev polynomials on the pixel wavelengths mapped
+   * onto [-1, 1] (first pixel -1, last +1), c ~ N(0, diag(calib_prior^2)):
+   * SPS_CALIB_MARGINAL integrates the coefficients out (eq. app_polymarg),
+   * SPS_CALIB_OPTIMISE evaluates the likelihood at their regularised best fit; the noise
+   * model is that of the uncalibrated model, and the model returned is mu.  Order in
+   * [0, 7]; calib_prior [calib_order + 1] widths > 0.  No gradient (SPS_E_INVAL). */
+  int32_t calib_mode;
+  int32_t calib_order;
+  const double *calib_prior;
+  /* emission-line catalogue (SPS_OBS_LINES, Sec. 3.3, App. I): n_band entries, entry k
+   * the sum of line_len[k] of the library's lines, their indices concatenated in
+   * line_index (an unresolved blend); data and sigma are integrated fluxes in erg/s/cm^2;
+   * upper[k] != 0 marks an upper limit (one-sided chi-squared, eq. app_line_chi2_UL),
+   * NULL none.  logL = -chi^2 / 2 over the inclusion mask (App. I.2). */
+  const int32_t *line_len;
+  const int32_t *line_index;
+  const uint8_t *upper;
 } sps_obs_desc;
 
 /* Builds the observation's fixed operators (filter rows of eq. E1, kernel
@@ -242,15 +262,19 @@ void sps_obs_destroy(sps_obs *obs);
  * B > max_batch), SPS_E_HIP. */
 sps_status sps_forward(const sps_library *lib, sps_obs *obs, const double *theta_dev, int32_t B,
                        int32_t precision, double *model_dev, void *hip_stream);
-/* logl_dev [B] FP64: eq. (6) with eq. G1 over the inclusion mask.
- * model_dev may be NULL; when given it also receives the model. */
+/* logl_dev [B] FP64: eq. (6) with eq. G1 over the inclusion mask; a spectrum with a
+ * calibration polynomial adds its marginal or optimised term (Sec. 3.2, App. H.3), a line
+ * catalogue takes -chi^2/2 with one-sided upper limits (App. I.2).
+ * model_dev may be NULL; when given it also receives the model (for a calibrated
+ * spectrum, the model before calibration). */
 sps_status sps_logl(const sps_library *lib, sps_obs *obs, const double *theta_dev, int32_t B,
                     int32_t precision, double *logl_dev, double *model_dev, void *hip_stream);
 /* logl_dev [B] and grad_dev [B, P] = d logL / d theta (FP64; columns the
  * model does not use are zero).  Hand-written reverse pass.  Supported for
  * SPS_FP64 and SPS_FP32, for libraries without a nebular continuum cube, an
  * escape geometry, a line table on an age axis of its own, the linear SFH scheme or
- * the IGM (else SPS_E_INVAL). */
+ * the IGM, and for photometry and spectra without a calibration polynomial (a line
+ * catalogue or a calibrated spectrum: SPS_E_INVAL). */
 sps_status sps_logl_grad(const sps_library *lib, sps_obs *obs, const double *theta_dev, int32_t B,
                          int32_t precision, double *logl_dev, double *grad_dev, void *hip_stream);
 
@@ -265,7 +289,8 @@ sps_status sps_logl_grad(const sps_library *lib, sps_obs *obs, const double *the
  * array: calls that overlap on one GPU (on different streams, or from different
  * threads without ordering) race.  Errors: SPS_E_SHAPE when B points at this precision
  * need more scratch than the array holds (64 MiB: on a 2496 x 6016 library with 128
- * lines, up to B = 1792 at FP32 or 16 bit and B = 896 at FP64), otherwise as sps_logl. */
+ * lines, up to B = 1792 at FP32 or 16 bit and B = 896 at FP64); SPS_E_INVAL for a
+ * spectrum with a calibration polynomial; otherwise as sps_logl. */
 #define SPS_STATIC_SCRATCH_BYTES (64ull << 20)
 sps_status sps_logl_static(const sps_library *lib, const sps_obs *obs, const double *theta_dev, int32_t B,
                            int32_t precision, double *logl_dev, double *model_dev, void *hip_stream);

@@ -720,6 +720,42 @@ sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsH
     h.lsf_value = d->lsf_value;
     if (d->lsf_curve) h.lsf_vals.assign(d->lsf_curve, d->lsf_curve + np);
     h.sigma_gas = d->sigma_gas_kms;
+    // calibration polynomial (Sec. 3.2, App. H.3): x maps the first pixel to -1, the last to +1
+    if (d->calib_mode < SPS_CALIB_NONE || d->calib_mode > SPS_CALIB_OPTIMISE)
+      return fail(SPS_E_INVAL, "unknown calibration mode %d", d->calib_mode);
+    h.calib_mode = d->calib_mode;
+    if (d->calib_mode != SPS_CALIB_NONE) {
+      if (d->calib_order < 0 || d->calib_order > 7) return fail(SPS_E_SHAPE, "calib_order must be in [0, 7]");
+      if (!d->calib_prior) return fail(SPS_E_INVAL, "calib_prior is NULL");
+      for (int m = 0; m <= d->calib_order; ++m)
+        if (!(d->calib_prior[m] > 0) || !std::isfinite(d->calib_prior[m]))
+          return fail(SPS_E_INVAL, "calibration prior widths must be finite and > 0");
+      h.calib_order = d->calib_order;
+      h.calib_prior.assign(d->calib_prior, d->calib_prior + d->calib_order + 1);
+      h.calib_xs = 2.0 / (d->pix_wave[np - 1] - d->pix_wave[0]);
+      h.calib_x0 = -1.0 - d->pix_wave[0] * h.calib_xs;
+    }
+  } else if (d->kind == SPS_OBS_LINES) {
+    // emission-line catalogue (Sec. 3.3, App. I): blends of the library's lines
+    const int nk = d->n_band;
+    if (L->n_line < 1) return fail(SPS_E_INVAL, "a line catalogue needs a library with nebular lines");
+    if (nk < 1 || nk > 4096) return fail(SPS_E_SHAPE, "a line catalogue holds 1 to 4096 entries");
+    if (!d->line_len || !d->line_index) return fail(SPS_E_INVAL, "line_len / line_index are NULL");
+    h.n_data = nk;
+    h.loff.assign(1, 0);
+    for (int k = 0; k < nk; ++k) {
+      const int n = d->line_len[k];
+      if (n < 1 || n > L->n_line) return fail(SPS_E_SHAPE, "catalogue entry %d: blend of %d lines", k, n);
+      for (int j = 0; j < n; ++j) {
+        const int l = d->line_index[h.loff.back() + j];
+        if (l < 0 || l >= L->n_line) return fail(SPS_E_INVAL, "catalogue entry %d: line index %d", k, l);
+        h.lidx.push_back(l);
+      }
+      h.loff.push_back(h.loff.back() + n);
+    }
+    h.upper.assign(nk, 0);
+    if (d->upper)
+      for (int k = 0; k < nk; ++k) h.upper[k] = d->upper[k] ? 1 : 0;
   } else {
     return fail(SPS_E_INVAL, "unknown observation kind %d", d->kind);
   }
@@ -830,11 +866,17 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   // forward launches on a log-uniform grid compute only the tiles whose pixels the projection
   // reads (the rows' spans); the gradient pass needs F everywhere (the attenuation adjoint
   // multiplies it by d logL / d F, zero outside the spans), the FP64 instance stays dense
+  // the single-observation path knows its observation: a line catalogue needs no rest-frame
+  // spectrum (no contraction), a calibration polynomial the model at the sorted rows and a
+  // pass of its own after the projection
+  const bool lines_only = timing_obs && timing_obs->host.kind == SPS_OBS_LINES;
+  const bool calib = timing_obs && timing_obs->host.calib_mode != SPS_CALIB_NONE;
+  if (calib && (grad || !w.mbuf)) return fail(SPS_E_INVAL, "calibration polynomial: no gradient, and a full workspace");
   const int n_nt = g.N_pad / 64;
   const bool span = !grad && g.log_uniform && prec != SPS_FP64 && w.tiles && B_pad / MT <= kTileListMaxM;
   ContractLaunch cl;
   cl.list = span ? w.tiles : nullptr;
-  if (span && e == hipSuccess) e = launch_tile_list(w.rows, B_pad, MT, n_nt, prec != SPS_FP32, w.tiles, s);
+  if (span && !lines_only && e == hipSuccess) e = launch_tile_list(w.rows, B_pad, MT, n_nt, prec != SPS_FP32, w.tiles, s);
   cl.W = pl.W;
   cl.Wlo = pl.Wlo;
   cl.B_pad = B_pad;
@@ -847,17 +889,17 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   cl.precision = prec;
   cl.pass = 0;
   cl.ev_start = cl.ev_stop = nullptr;
-  if (e == hipSuccess && timing_obs)
+  if (e == hipSuccess && timing_obs && !lines_only)
     e = timing_obs->timing_events((B_pad / MT) * n_nt, g.K_pad / (kKTile * tf), &cl.ev_start, &cl.ev_stop);
-  if (e == hipSuccess) e = launch_contract(g, cl, s);
-  if (g.escape == SPS_ESCAPE_PICKET && e == hipSuccess) {
+  if (e == hipSuccess && !lines_only) e = launch_contract(g, cl, s);
+  if (g.escape == SPS_ESCAPE_PICKET && !lines_only && e == hipSuccess) {
     // the picket fence's dust-free part: f_ob (young stars + ionising continuum), added to F
     ContractLaunch c1 = cl;
     c1.pass = 1;
     c1.ev_start = c1.ev_stop = nullptr;
     e = launch_contract(g, c1, s);
   }
-  if (g.has_cont && e == hipSuccess) {
+  if (g.has_cont && !lines_only && e == hipSuccess) {
     NebLaunch nb;
     nb.theta = theta;
     nb.rows = w.rows;
@@ -882,10 +924,21 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   pj.logl = logl;
   pj.gvec = grad ? w.gvec : nullptr;
   pj.gnoise = grad ? w.gnoise : nullptr;
-  pj.msorted = grad ? w.mbuf : nullptr;
+  pj.msorted = grad || calib ? w.mbuf : nullptr;
   pj.ld_model = ld_model;
   pj.ld_g = ld_g;
   if (e == hipSuccess) e = launch_project(g, pj, s);
+  if (calib && e == hipSuccess) {
+    CalibLaunch cb;
+    cb.obs_table = obs_table;
+    cb.rows = w.rows;
+    cb.theta = theta;
+    cb.msorted = w.mbuf;
+    cb.ld = ld_g;
+    cb.B_pad = B_pad;
+    cb.logl = logl;
+    e = launch_calib(g, cb, s);
+  }
   if (e != hipSuccess) return fail(SPS_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
   return SPS_OK;
 }
@@ -916,6 +969,8 @@ extern "C" sps_status sps_logl_grad(const sps_library *L, sps_obs *o, const doub
                                     double *logl, double *grad, void *stream) {
   if (!logl || !grad) return fail(SPS_E_INVAL, "logl_dev / grad_dev is NULL");
   if (prec != SPS_FP64 && prec != SPS_FP32) return fail(SPS_E_INVAL, "gradients are available for FP64 and FP32");
+  if (o && (o->host.kind == SPS_OBS_LINES || o->host.calib_mode != SPS_CALIB_NONE))
+    return fail(SPS_E_INVAL, "gradients are not available for line catalogues or calibrated spectra");
   if (L && (L->dev.has_cont || L->dev.escape || L->line_tau_axis || L->dev.sfh_scheme || L->dev.igm))
     return fail(SPS_E_INVAL, "gradients are not available for libraries with a nebular continuum cube, an escape "
                 "geometry, a line table on an age axis of its own, the linear SFH scheme or the IGM");

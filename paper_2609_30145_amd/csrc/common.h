@@ -123,6 +123,14 @@ struct DevObs {
   const uint8_t *mask;               // [n_data] final inclusion mask
   const double *ivar;                // [n_data] 1/sigma^2, 0 where masked
   double lnorm;                      // -1/2 sum ln(2 pi sigma^2) over the included data
+  // spectrum calibration polynomial: mode (0 off, 1 marginal, 2 optimise), order, x = pixel
+  // wavelength * calib_xs + calib_x0 on [-1, 1], prior inverse variances, sum of ln s_m
+  int calib_mode, calib_order;
+  double calib_xs, calib_x0, calib_lnsd;
+  double calib_ivar[8];
+  // line catalogue: entry k sums lines lidx[loff[k] .. loff[k+1]); upper[k]: upper limit
+  const int *loff, *lidx;
+  const uint8_t *upper;
 };
 
 // Per-point quantities, stored at the point's sorted row.

@@ -69,6 +69,18 @@ struct ProjectLaunch {
 };
 hipError_t launch_project(const DevLib &lib, const ProjectLaunch &pl, hipStream_t s);
 
+// spectrum calibration polynomial (App. H.3): the correction to logL from the model at the
+// sorted rows (written by the projection), per point
+struct CalibLaunch {
+  const DevObs *obs_table;
+  const PointRow *rows;
+  const double *theta;
+  const double *msorted;     // [B_pad][ld] model at the sorted rows
+  int ld, B_pad;
+  double *logl;              // [B] or NULL
+};
+hipError_t launch_calib(const DevLib &lib, const CalibLaunch &cl, hipStream_t s);
+
 // nebular continuum added to F (App. C); a no-op for a library without a continuum cube
 struct NebLaunch {
   const double *theta;

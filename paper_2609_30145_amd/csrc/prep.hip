@@ -799,7 +799,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     pr.seg_n = 0;
     if (lib.log_uniform) {
       if (kind == 0) phot_span(lib, fw_min, fw_max, z, pr.seg0, pr.seg_n);
-      else spec_span(lib, px_lo, px_hi, ks_max, z, pr.seg0, pr.seg_n);
+      else if (kind == 1) spec_span(lib, px_lo, px_hi, ks_max, z, pr.seg0, pr.seg_n);
     }
     pr.pad = 0;
     a.rows[r] = pr;

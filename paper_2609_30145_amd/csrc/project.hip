@@ -259,6 +259,32 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
       __syncthreads();
       for (int band = tid; band < ob.n_band; band += 256) datum(band, fac * red[band]);
     }
+  } else if (ob.kind == 2) {
+    // ---------------- emission-line catalogue (App. I.1-I.2): the line fluxes through the
+    // young light's birth-cloud transmission, the diffuse screen, mass over 4 pi D_L^2 and
+    // the IGM at the line, summed over each entry's blend; detections take the Gaussian
+    // chi-squared, upper limits its one-sided form, logL = -chi^2 / 2 (no normalisation)
+    double *s_fl = s_lnl;   // [n_line] line fluxes, erg/s/cm^2
+    const int nl = a.n_line;
+    const double Tfac = pr.mass10 / (4.0 * kPi * pr.dl * pr.dl);
+    for (int l = tid; l < nl; l += 256) {
+      const double lw = lib.line_wave[l];
+      const double lnlv = log(lw / kLamV);
+      const double tbc = pr.bc_p * exp(-pr.tau_bc * exp(pr.alpha_bc * lnlv)) + pr.bc_q;
+      const double td = exp(-pr.tau_diff * exp(pr.delta * lnlv) * (lib.line_a[l] + (0.85 - 1.9 * pr.delta) * lib.line_d[l]));
+      s_fl[l] = a.Lline[(size_t)r * nl + l] * tbc * td * Tfac * igm_T(lib, th, z, opz * lw);
+    }
+    __syncthreads();
+    for (int k = tid; k < ob.n_data; k += 256) {
+      double m = 0.0;
+      for (int j = ob.loff[k]; j < ob.loff[k + 1]; ++j) m += s_fl[ob.lidx[j]];
+      if (a.model) a.model[(size_t)pr.b * a.ld_model + k] = m;
+      if (a.msorted) a.msorted[(size_t)r * a.ld_g + k] = m;
+      if (ob.mask[k]) {
+        const double res = (ob.data[k] - m) / ob.sigma[k];
+        if (!ob.upper[k] || m > ob.data[k]) lsum -= 0.5 * res * res;
+      }
+    }
   } else {
     // ---------------- spectrum (eq. F5-F6)
     const double lnopz = log1p(z);
@@ -489,6 +515,118 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
       a.gnoise[(size_t)pr.b * 4 + tid] = (g[0] + g[1]) + (g[2] + g[3]);
     }
   }
+}
+
+// ---------------------------------------------------------------------------------
+// Spectrophotometric calibration polynomial (Sec. 3.2, App. H.3, eq. app_polymarg).  One
+// workgroup per sorted row: with D = diag(mu) A (A_im = T_m(x_i), Chebyshev), C the noise
+// of the uncalibrated model mu and r = d - mu over the mask, the sums G = D^T C^-1 D and
+// b = D^T C^-1 r are accumulated in FP64 per thread (Chebyshev recurrence per pixel),
+// reduced in a fixed order, and one thread solves M = G + Lambda^-1 by Cholesky: the
+// marginal form adds b^T M^-1 b / 2 - ln|M| / 2 - ln|Lambda| / 2 to logL, the optimised form
+// c^T b - c^T G c / 2 at c = M^-1 b (the diagonal likelihood at the regularised best fit).
+// ---------------------------------------------------------------------------------
+constexpr int kCalMax = 8;                          // coefficients at most (order 7)
+constexpr int kCalG = kCalMax * (kCalMax + 1) / 2;  // packed upper triangle of G
+
+__global__ void __launch_bounds__(256) k_calib(DevLib lib, CalibLaunch a) {
+  __shared__ double red[4][kCalG + kCalMax];
+  const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const PointRow pr = a.rows[r];
+  if (pr.b < 0) return;
+  const DevObs ob = a.obs_table[pr.obs];
+  if (ob.kind != 1 || ob.calib_mode == 0) return;
+  const int nc = ob.calib_order + 1;
+  const double *th = a.theta + (size_t)pr.b * lib.P;
+  const double ns = (ob.noise_flags & 1) ? exp(th[TH_LOG_ERR_SCALE]) : 1.0;
+  const double fc = (ob.noise_flags & 2) ? exp(th[TH_LOG_F_CALIB]) : 0.0;
+  const double fd = (ob.noise_flags & 4) ? exp(th[TH_LOG_F_DATA]) : 0.0;
+  const double jt = (ob.noise_flags & 8) ? exp(th[TH_LOG_JITTER]) : 0.0;
+  double G[kCalG], bv[kCalMax];
+#pragma unroll
+  for (int q = 0; q < kCalG; ++q) G[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < kCalMax; ++q) bv[q] = 0.0;
+  const double *mu = a.msorted + (size_t)r * a.ld;
+  for (int i = tid; i < ob.n_data; i += 256) {
+    if (!ob.mask[i]) continue;
+    const double m = mu[i], d = ob.data[i], sg = ob.sigma[i];
+    const double v = ns * ns * sg * sg + fc * fc * m * m + fd * fd * d * d + jt * jt;
+    const double w = 1.0 / v, res = d - m;
+    const double x = ob.pix[i] * ob.calib_xs + ob.calib_x0;
+    double T[kCalMax];
+    T[0] = 1.0;
+    T[1] = x;
+#pragma unroll
+    for (int q = 2; q < kCalMax; ++q) T[q] = 2.0 * x * T[q - 1] - T[q - 2];
+#pragma unroll
+    for (int p = 0, q = 0; p < kCalMax; ++p) {
+      const double Dp = m * T[p];
+      bv[p] += Dp * res * w;
+#pragma unroll
+      for (int u = p; u < kCalMax; ++u, ++q) G[q] += Dp * m * T[u] * w;
+    }
+  }
+  // fixed-order reduction: each wave by a butterfly, then the four waves in order
+#pragma unroll
+  for (int q = 0; q < kCalG; ++q) G[q] = wave_reduce_sum(G[q]);
+#pragma unroll
+  for (int q = 0; q < kCalMax; ++q) bv[q] = wave_reduce_sum(bv[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < kCalG; ++q) red[wv][q] = G[q];
+#pragma unroll
+    for (int q = 0; q < kCalMax; ++q) red[wv][kCalG + q] = bv[q];
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  double M[kCalMax][kCalMax], Gm[kCalMax][kCalMax], b[kCalMax];
+  for (int p = 0, q = 0; p < kCalMax; ++p)
+    for (int u = p; u < kCalMax; ++u, ++q) {
+      const double g = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+      Gm[p][u] = Gm[u][p] = g;
+    }
+  for (int p = 0; p < nc; ++p) {
+    b[p] = (red[0][kCalG + p] + red[1][kCalG + p]) + (red[2][kCalG + p] + red[3][kCalG + p]);
+    for (int u = 0; u < nc; ++u) M[p][u] = Gm[p][u] + (p == u ? ob.calib_ivar[p] : 0.0);
+  }
+  // Cholesky M = L L^T (in place, lower), then c = M^-1 b by two triangular solves
+  double logdet = 0.0;
+  for (int j = 0; j < nc; ++j) {
+    double s = M[j][j];
+    for (int k = 0; k < j; ++k) s -= M[j][k] * M[j][k];
+    const double ljj = sqrt(s);
+    M[j][j] = ljj;
+    logdet += 2.0 * log(ljj);
+    for (int i = j + 1; i < nc; ++i) {
+      double t = M[i][j];
+      for (int k = 0; k < j; ++k) t -= M[i][k] * M[j][k];
+      M[i][j] = t / ljj;
+    }
+  }
+  double y[kCalMax], c[kCalMax];
+  for (int i = 0; i < nc; ++i) {
+    double t = b[i];
+    for (int k = 0; k < i; ++k) t -= M[i][k] * y[k];
+    y[i] = t / M[i][i];
+  }
+  for (int i = nc - 1; i >= 0; --i) {
+    double t = y[i];
+    for (int k = i + 1; k < nc; ++k) t -= M[k][i] * c[k];
+    c[i] = t / M[i][i];
+  }
+  double bc = 0.0, cGc = 0.0;
+  for (int p = 0; p < nc; ++p) {
+    bc += b[p] * c[p];
+    for (int u = 0; u < nc; ++u) cGc += c[p] * Gm[p][u] * c[u];
+  }
+  const double corr = ob.calib_mode == 1 ? 0.5 * bc - 0.5 * logdet - ob.calib_lnsd : bc - 0.5 * cGc;
+  if (a.logl) a.logl[pr.b] += corr;
+}
+
+hipError_t launch_calib(const DevLib &lib, const CalibLaunch &cl, hipStream_t s) {
+  hipLaunchKernelGGL(k_calib, dim3(cl.B_pad), dim3(256), 0, s, lib, cl);
+  return hipGetLastError();
 }
 
 hipError_t launch_project(const DevLib &lib, const ProjectLaunch &pl, hipStream_t s) {

@@ -98,7 +98,7 @@ sps_status upload_obs(const ObsHost &host, DevObs &o, DeviceBuffers &mem, hipStr
       o.fwln_min = std::min(o.fwln_min, v);
       o.fwln_max = std::max(o.fwln_max, v);
     }
-  } else {
+  } else if (host.kind == SPS_OBS_SPEC) {
     o.pix = (const double *)put(host.pix.data(), host.pix.size() * 8);
     o.lnpix = (const double *)put(host.lnpix.data(), host.lnpix.size() * 8);
     o.ksig = (const double *)put(host.ksig.data(), host.ksig.size() * 8);
@@ -111,6 +111,21 @@ sps_status upload_obs(const ObsHost &host, DevObs &o, DeviceBuffers &mem, hipStr
     for (double v : host.ksig) o.ksig_max = std::max(o.ksig_max, v);
     o.lnpix_lo = host.lnpix.empty() ? 0.0 : host.lnpix.front();
     o.lnpix_hi = host.lnpix.empty() ? 0.0 : host.lnpix.back();
+    o.calib_mode = host.calib_mode;
+    o.calib_order = host.calib_order;
+    o.calib_xs = host.calib_xs;
+    o.calib_x0 = host.calib_x0;
+    o.calib_lnsd = 0.0;
+    for (int m = 0; m < 8; ++m) o.calib_ivar[m] = 0.0;
+    for (size_t m = 0; m < host.calib_prior.size() && m < 8; ++m) {
+      o.calib_ivar[m] = 1.0 / (host.calib_prior[m] * host.calib_prior[m]);
+      o.calib_lnsd += std::log(host.calib_prior[m]);
+    }
+  }
+  if (host.kind == SPS_OBS_LINES) {
+    o.loff = (const int *)put(host.loff.data(), host.loff.size() * 4);
+    o.lidx = (const int *)put(host.lidx.data(), std::max<size_t>(1, host.lidx.size()) * 4);
+    o.upper = (const uint8_t *)put(host.upper.data(), host.upper.size());
   }
   o.data = (const double *)put(host.data.data(), (size_t)host.n_data * 8);
   o.sigma = (const double *)put(host.sigma.data(), (size_t)host.n_data * 8);

@@ -60,6 +60,11 @@ struct ObsHost {
   // -1/2 sum ln(2 pi sigma^2) over the included data
   std::vector<double> ivar;
   double lnorm = 0;
+  int calib_mode = 0, calib_order = 0;
+  std::vector<double> calib_prior;
+  double calib_xs = 0, calib_x0 = 0;
+  std::vector<int> loff, lidx;       // line catalogue blends
+  std::vector<uint8_t> upper;
 };
 
 sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsHost &h, uint32_t *warnings);

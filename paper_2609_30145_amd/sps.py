@@ -20,7 +20,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "bf16_1pass": 4, "fp16
               "bf16_hr": 6, "fp16_hr": 7, "bf16_wl": 8, "fp16_wl": 9}
 LSF_MODES = {"R_fwhm": 0, "R_sigma": 1, "fwhm_aa": 2, "sigma_aa": 3, "sigma_kms": 4, "fwhm_kms": 5, "R": 6}
 NOISE = {"err_scale": 1, "f_calib": 2, "f_data": 4, "jitter": 8}
-OBS_PHOT, OBS_SPEC = 0, 1
+OBS_PHOT, OBS_SPEC, OBS_LINES = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -62,7 +62,11 @@ class ObsDesc(C.Structure):
                 ("filter_trans", _dp), ("n_pix", C.c_int32), ("pix_wave", _dp), ("lsf_mode", C.c_int32),
                 ("lsf_value", C.c_double), ("lsf_curve", _dp), ("z_ref", C.c_double),
                 ("sigma_gal_kms", C.c_double), ("sigma_gas_kms", C.c_double), ("data", _dp), ("sigma", _dp),
-                ("mask", _u8p), ("noise_flags", C.c_uint32), ("max_batch", C.c_int32)]
+                ("mask", _u8p), ("noise_flags", C.c_uint32), ("max_batch", C.c_int32),
+                ("calib_mode", C.c_int32), ("calib_order", C.c_int32), ("calib_prior", _dp),
+                ("line_len", _ip), ("line_index", _ip), ("upper", _u8p)]
+
+CALIB = {None: 0, "marginal": 1, "optimise": 2}
 
 
 class SpsError(RuntimeError):
@@ -213,17 +217,32 @@ class Library:
 
 
 class Observation:
-    """Photometry or spectrum bound to a library (sps_obs_create)."""
+    """Photometry, a spectrum or an emission-line catalogue bound to a library (sps_obs_create).
+
+    Spectra take ``calib`` ("marginal" or "optimise"), ``calib_order`` and ``calib_prior``
+    for the calibration polynomial; a line catalogue ("lines") takes ``blends`` (per entry,
+    the library line indices it sums) and ``upper`` (per entry, an upper-limit flag)."""
 
     def __init__(self, library: Library, kind: str, max_batch: int, filters=None, pix_wave=None,
                  lsf_mode="R_fwhm", lsf_value=100.0, lsf_curve=None, z_ref=0.0, sigma_gal_kms=0.0,
-                 sigma_gas_kms=0.0, data=None, sigma=None, mask=None, noise=()):
+                 sigma_gas_kms=0.0, data=None, sigma=None, mask=None, noise=(), calib=None, calib_order=0,
+                 calib_prior=None, blends=None, upper=None):
         L = lib()
         self.library = library
         keep = []
         d = ObsDesc()
-        d.kind = OBS_PHOT if kind == "phot" else OBS_SPEC if kind == "spec" else 99
-        if kind == "phot":
+        d.kind = {"phot": OBS_PHOT, "spec": OBS_SPEC, "lines": OBS_LINES}.get(kind, 99)
+        if kind == "lines":
+            ln = _arr([len(bl) for bl in blends], np.int32)
+            li = _arr(np.concatenate([np.asarray(bl, dtype=np.int32) for bl in blends]), np.int32)
+            keep += [ln, li]
+            d.n_band, d.line_len, d.line_index = len(blends), _ptr(ln, C.c_int32), _ptr(li, C.c_int32)
+            if upper is not None:
+                up = _arr(upper, np.uint8)
+                keep.append(up)
+                d.upper = _ptr(up, C.c_uint8)
+            self.n_data = len(blends)
+        elif kind == "phot":
             lens = _arr([len(f[0]) for f in filters], np.int32)
             fw = _arr(np.concatenate([f[0] for f in filters]))
             ft = _arr(np.concatenate([f[1] for f in filters]))
@@ -242,6 +261,11 @@ class Observation:
                 keep.append(lc)
                 d.lsf_curve = _ptr(lc)
             d.z_ref, d.sigma_gal_kms, d.sigma_gas_kms = float(z_ref), float(sigma_gal_kms), float(sigma_gas_kms)
+            d.calib_mode = CALIB[calib]
+            if calib is not None:
+                cp = _arr(calib_prior)
+                keep.append(cp)
+                d.calib_order, d.calib_prior = int(calib_order), _ptr(cp)
             self.n_data = len(pw)
         if data is not None:
             da, sg = _arr(data), _arr(sigma)
