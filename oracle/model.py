@@ -22,7 +22,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import cosmology, dust, igm, likelihood, nebular, projection, sfh
+from . import cosmology, dust, igm, kinematics, likelihood, nebular, projection, sfh
 from .constants import ANG_CM, C_CMS, C_KMS, FNU_AB, LAM_LYMAN, LSUN
 
 SCALARS = ("logmass", "zred", "tau_bc", "alpha_bc", "tau_diff", "delta", "logzsol",
@@ -33,10 +33,11 @@ SCALARS = ("logmass", "zred", "tau_bc", "alpha_bc", "tau_diff", "delta", "logzso
 ESCAPE_GEOMETRIES = ("none", "runaway_bc", "picket")
 
 
-def columns(n_sfh, n_zh, escape=False, igm=False):
+def columns(n_sfh, n_zh, escape=False, igm=False, vdisp=False):
     """Column offsets of theta: the scalars, the SFH values (bin masses, or node SFRs under
     the linear scheme), the enrichment nodes, then frac_obrun = f_ob for a library with an
-    escape geometry (Sec. 2.3.2) and igm_factor for one with IGM transmission (Sec. 2.6)."""
+    escape geometry (Sec. 2.3.2), igm_factor for one with IGM transmission (Sec. 2.6) and
+    sigma_gal [km/s] for one with a free stellar velocity dispersion (Sec. 2.5)."""
     c = {n: i for i, n in enumerate(SCALARS)}
     c["sfh"] = len(SCALARS)
     c["zh"] = len(SCALARS) + n_sfh
@@ -47,12 +48,15 @@ def columns(n_sfh, n_zh, escape=False, igm=False):
     if igm:
         c["igm_factor"] = c["P"]
         c["P"] += 1
+    if vdisp:
+        c["sigma_gal"] = c["P"]
+        c["P"] += 1
     return c
 
 
 def lib_columns(L):
     """columns() for a library."""
-    return columns(L.n_sfh, L.n_zh, L.escape != "none", L.igm)
+    return columns(L.n_sfh, L.n_zh, L.escape != "none", L.igm, L.sigma_gal_max > 0.0)
 
 
 @dataclass
@@ -83,11 +87,12 @@ class Library:
     escape: str = "none"      # fesc_geometry: "none" (f_ob = 0), "runaway_bc", "picket"
     sfh_scheme: str = "step"  # SFH -> age weights: "step" or "linear" (App. B)
     igm: bool = False         # Madau (1995) IGM transmission with theta[igm_factor]
+    sigma_gal_max: float = 0.0  # > 0: theta[sigma_gal] in [0, sigma_gal_max] km/s, Fourier stage
     flux_ion: np.ndarray | None = None   # raw ionising continuum of nebular-covered ages
 
 
 def build_library(cfg, lib, lines=None, dust_tab=None, cont=None, escape="none", sfh_scheme="step",
-                  igm=False) -> Library:
+                  igm=False, sigma_gal_max=0.0) -> Library:
     """Static, parameter-independent preparation of the SSP grid (done once).
 
     ``lines``: line_wave, line_table [n_line][n_tau][n_zg][n_u] of log10(L_l/Q), zg_nodes,
@@ -96,7 +101,9 @@ def build_library(cfg, lib, lines=None, dust_tab=None, cont=None, escape="none",
     of log10(L_nu/Q) on the library's wavelengths with its own tau_nodes, zg_nodes and
     u_nodes (App. C).  Nebular emission goes to the SSP ages inside every cube's age
     range; they must be birth-cloud ages.  ``escape`` selects the f_ob geometry,
-    ``sfh_scheme`` the step or linear (tent-integral) weights, ``igm`` the IGM transmission.
+    ``sfh_scheme`` the step or linear (tent-integral) weights, ``igm`` the IGM transmission,
+    ``sigma_gal_max`` > 0 a free stellar velocity dispersion up to that value [km/s],
+    applied in the Fourier stage (the grid must then be uniform in ln lambda).
     """
     ages, wave = lib["ages"], lib["wave"]
     flux_raw = np.asarray(lib["flux"], dtype=np.float64)
@@ -117,6 +124,11 @@ def build_library(cfg, lib, lines=None, dust_tab=None, cont=None, escape="none",
         raise ValueError("sfh_scheme must be 'step' or 'linear'")
     L.sfh_scheme = sfh_scheme
     L.igm = bool(igm)
+    if sigma_gal_max < 0.0 or not math.isfinite(sigma_gal_max):
+        raise ValueError("sigma_gal_max must be finite and >= 0")
+    if sigma_gal_max > 0.0:
+        kinematics.log_step(wave)
+    L.sigma_gal_max = float(sigma_gal_max)
     ranges = []
     if lines is not None:
         L.lines = dict(lines)
@@ -355,14 +367,19 @@ def predict(L: Library, obs, theta, rf=None, trunc=5.0):
     if spec:
         sig_k = projection.kernel_sigma_kms(obs.pix_wave, obs.lsf_mode, obs.lsf_value, L.wave,
                                             obs.z_ref, obs.sigma_gal_kms)
+    vd = fourier_stage_plan(L, obs, sig_k if spec else None)
     for b in range(theta.shape[0]):
         th = theta[b]
         scale, dl = observer_scale(L, th, cols)
         z = th[cols["zred"]]
-        # observer frame: mass, flux factor and the IGM transmission at lambda (1 + z), on
-        # the rest grid (Sec. 2.6); reading for spectra: the IGM is applied before the
-        # continuum kernel as a whole (exact when sigma_gal = 0)
-        fnu = fnu_observed(L, rf["F"][b], scale) * igm_transmission(L, th, cols, L.wave * (1.0 + z))
+        # observer frame: mass and flux factor (Sec. 2.6), then the free velocity dispersion
+        # on the continuum (Sec. 2.5, App. F), then the IGM transmission at lambda (1 + z),
+        # on the rest grid (the data-flow figure of App. A puts the IGM after sigma_gal and
+        # before the instrument's kernel)
+        fnu = fnu_observed(L, rf["F"][b], scale)
+        if vd is not None:
+            fnu = fourier_stage(L, vd, fnu, z, th[cols["sigma_gal"]])
+        fnu = fnu * igm_transmission(L, th, cols, L.wave * (1.0 + z))
         if not spec:
             out.append(projection.band_maggies(L.wave, fnu, z, obs.filters))
             continue
@@ -376,6 +393,35 @@ def predict(L: Library, obs, theta, rf=None, trunc=5.0):
             cont = cont + projection.line_profile_pixels(obs.pix_wave, Fl, lobs, s_l)
         out.append(cont / FNU_AB)
     return np.array(out)
+
+
+def fourier_stage_plan(L: Library, obs, sig_k=None):
+    """Window rule and transform length of an observation's Fourier stage (Sec. 2.5,
+    App. F): the observed range it covers (the pixels, or every filter node) and the
+    margin M in nodes; None without a free sigma_gal."""
+    if L.sigma_gal_max <= 0.0:
+        return None
+    dlnl = kinematics.log_step(L.wave)
+    mg = kinematics.margin_nodes(L.sigma_gal_max, dlnl)
+    if obs.kind == "spec":
+        lo, hi = float(obs.pix_wave[0]), float(obs.pix_wave[-1])
+        M = kinematics.margin_nodes(np.max(sig_k), dlnl) + mg + 2
+    else:
+        lo = min(float(np.min(f[0])) for f in obs.filters)
+        hi = max(float(np.max(f[0])) for f in obs.filters)
+        M = mg + 2
+    return dict(lo=lo, hi=hi, M=M, dlnl=dlnl, n_fft=kinematics.fft_length(lo, hi, dlnl, M, L.sigma_gal_max))
+
+
+def fourier_stage(L: Library, vd, fnu, z, sigma):
+    """The continuum on the rest grid with its window broadened by sigma [km/s]; NaN
+    everywhere for sigma outside [0, sigma_gal_max]."""
+    if not (0.0 <= sigma <= L.sigma_gal_max):
+        return np.full_like(fnu, np.nan)
+    j0, j1 = kinematics.window(L.wave, vd["lo"], vd["hi"], z, vd["M"])
+    out = fnu.copy()
+    out[j0:j1] = kinematics.fourier_broaden(fnu[j0:j1], vd["n_fft"], sigma, vd["dlnl"])
+    return out
 
 
 def _lsf_at(obs, lam_obs):

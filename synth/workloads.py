@@ -43,10 +43,10 @@ THETA_SCALARS = (
 N_SCALARS = len(THETA_SCALARS)
 
 
-def theta_columns(n_sfh: int, n_zh: int, escape: bool = False, igm: bool = False) -> dict:
+def theta_columns(n_sfh: int, n_zh: int, escape: bool = False, igm: bool = False, vdisp: bool = False) -> dict:
     """Column offsets of the theta layout (scalars, then sfh[n_sfh], then zh[n_zh], then,
     for a library with an ionising-photon escape geometry, frac_obrun, then, with IGM
-    transmission, igm_factor)."""
+    transmission, igm_factor, then, with a free stellar velocity dispersion, sigma_gal)."""
     cols = {name: i for i, name in enumerate(THETA_SCALARS)}
     cols["sfh"] = N_SCALARS
     cols["zh"] = N_SCALARS + n_sfh
@@ -56,6 +56,9 @@ def theta_columns(n_sfh: int, n_zh: int, escape: bool = False, igm: bool = False
         cols["P"] += 1
     if igm:
         cols["igm_factor"] = cols["P"]
+        cols["P"] += 1
+    if vdisp:
+        cols["sigma_gal"] = cols["P"]
         cols["P"] += 1
     return cols
 
@@ -326,7 +329,7 @@ def _clipped_t(rng, nu, scale, clip, size):
 
 
 def make_theta(cfg: Config, B: int | None = None, seed: int = 2, escape: bool = False, igm: bool = False,
-               sfh_scheme: str = "step") -> np.ndarray:
+               sfh_scheme: str = "step", vdisp: float = 0.0) -> np.ndarray:
     """Draw theta[B, P] from the configuration's priors.
 
     SFH: c0 uses Dirichlet(1,...,1) bin masses; the others draw clipped Student-t
@@ -335,13 +338,16 @@ def make_theta(cfg: Config, B: int | None = None, seed: int = 2, escape: bool = 
     Enrichment history: zeta_0 ~ U(-2.2, 0.3) plus a clipped Student-t random
     walk with sigma 0.2, clamped to the grid.  With ``escape``, a column frac_obrun ~
     U(0, 1) and with ``igm`` a column igm_factor ~ U(0.5, 1.5), each from a stream of its
-    own (the other columns are unchanged).  Under the linear SFH scheme the SFH values are
-    node SFRs: the bin masses divided by 1e10 / n_sfh years.
+    own (the other columns are unchanged); with ``vdisp`` > 0 a column sigma_gal ~
+    U(0, vdisp) km/s.  Under the linear SFH scheme the SFH values are node SFRs: the bin
+    masses divided by 1e10 / n_sfh years.
     """
     B = cfg.batch if B is None else B
     rng = np.random.default_rng(seed)
-    cols = theta_columns(cfg.n_sfh, cfg.n_zh, escape, igm)
+    cols = theta_columns(cfg.n_sfh, cfg.n_zh, escape, igm, vdisp > 0.0)
     th = np.zeros((B, cols["P"]))
+    if vdisp > 0.0:
+        th[:, cols["sigma_gal"]] = np.random.default_rng(seed + 15485863).uniform(0.0, vdisp, B)
     if escape:
         th[:, cols["frac_obrun"]] = np.random.default_rng(seed + 7919).uniform(0.0, 1.0, B)
     if igm:
