@@ -143,6 +143,17 @@ typedef struct {
    * optical depth scaled by a theta column igm_factor (after frac_obrun), applied at
    * lambda (1 + z) to the observer-frame model and to each line. */
   int32_t igm;
+  /* Free stellar velocity dispersion (Sec. 2.5, App. F): > 0 adds a theta column
+   * sigma_gal (km/s, after igm_factor) admitted in [0, sigma_gal_max] (a point outside
+   * gets a NaN model and logL); 0 = no column.  Every observation's continuum is then
+   * broadened in the Fourier stage: the rest-frame nodes the projection reads (the
+   * pixels' range plus the banded kernel's and sigma_gal_max's reach, or the filter
+   * nodes' range plus sigma_gal_max's reach), padded with their edge values to a
+   * power-of-two transform of at most 8192 points, are multiplied by
+   * exp(-2 pi^2 sigma_gal^2 nu^2), nu conjugate to c ln(lambda); before the IGM and the
+   * instrument's kernel.  Needs a wavelength grid uniform in ln(lambda) (else
+   * SPS_E_INVAL).  The fixed sigma_gal_kms of a spectrum stays folded into its kernel. */
+  double sigma_gal_max;
 } sps_library_desc;
 
 typedef enum { SPS_SFH_STEP = 0, SPS_SFH_LINEAR = 1 } sps_sfh_scheme;
@@ -171,13 +182,14 @@ void sps_library_destroy(sps_library *lib);
  * delta, logzsol, gas_logz, gas_logu, afe, log_err_scale, log_f_calib,
  * log_f_data, log_jitter), then sfh[n_sfh] bin masses (Msun formed per unit of
  * 10^logmass; node SFRs under SPS_SFH_LINEAR), then zh[n_zh] enrichment nodes, then,
- * for a library with an escape geometry, frac_obrun, then, with the IGM, igm_factor
- * (each -1 when absent).  Unused columns are ignored. */
+ * for a library with an escape geometry, frac_obrun, then, with the IGM, igm_factor,
+ * then, with a free velocity dispersion, sigma_gal (each -1 when absent).  Unused
+ * columns are ignored. */
 typedef struct {
   int32_t P, n_scalar, sfh, n_sfh, zh, n_zh;
   int32_t logmass, zred, tau_bc, alpha_bc, tau_diff, delta, logzsol, gas_logz, gas_logu, afe;
   int32_t log_err_scale, log_f_calib, log_f_data, log_jitter;
-  int32_t frac_obrun, igm_factor;
+  int32_t frac_obrun, igm_factor, sigma_gal;
 } sps_layout;
 sps_status sps_theta_layout(const sps_library *lib, sps_layout *out);
 

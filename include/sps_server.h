@@ -70,7 +70,9 @@ typedef struct {
   int64_t hbm_in_use, hbm_peak, hbm_budget;
 } sps_stats;
 
-/* Errors: SPS_E_INVAL, SPS_E_NOMEM, SPS_E_HIP. */
+/* Errors: SPS_E_INVAL (also for a library with a free sigma_gal: each launch mixes
+ * observations, while the Fourier stage's transform belongs to one), SPS_E_NOMEM,
+ * SPS_E_HIP. */
 sps_status sps_server_create(const sps_library *lib, const sps_server_desc *desc, sps_server **out);
 /* Copies the request and queues it; returns at once.  SPS_E_BUDGET when its
  * state can never fit the budget, SPS_E_SHAPE for B outside [1, max_points],

@@ -16,7 +16,8 @@ BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.cpp", "runtime.cpp", "server.cpp", "prep.hip", "contract.hip", "contract16.hip",
-           "project.hip", "pack.hip", "adjoint.hip", "serve.hip", "static_scratch.hip", "nebular.hip"]
+           "project.hip", "pack.hip", "adjoint.hip", "serve.hip", "static_scratch.hip", "nebular.hip",
+           "vdisp.hip"]
 
 # Packed-FP32 instructions are disabled for all device code (they are formed by the
 # compiler from float2 arithmetic otherwise).

@@ -147,6 +147,15 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   if (d->escape < SPS_ESCAPE_NONE || d->escape > SPS_ESCAPE_PICKET) return fail(SPS_E_INVAL, "unknown escape geometry");
   if (d->sfh_scheme != SPS_SFH_STEP && d->sfh_scheme != SPS_SFH_LINEAR) return fail(SPS_E_INVAL, "unknown SFH scheme");
   if (d->igm != 0 && d->igm != 1) return fail(SPS_E_INVAL, "igm must be 0 or 1");
+  if (!(d->sigma_gal_max >= 0) || !std::isfinite(d->sigma_gal_max))
+    return fail(SPS_E_INVAL, "sigma_gal_max must be finite and >= 0");
+  if (d->sigma_gal_max > 0) {
+    // the Fourier stage's uniform ln(lambda) grid is the model grid itself
+    const double dl = (std::log(d->wave[N - 1]) - std::log(d->wave[0])) / (N - 1);
+    for (int n = 0; n + 1 < N; ++n)
+      if (std::fabs((std::log(d->wave[n + 1]) - std::log(d->wave[n])) / dl - 1.0) >= 1e-6)
+        return fail(SPS_E_INVAL, "a free sigma_gal needs a wavelength grid uniform in ln(lambda)");
+  }
   // nebular-covered SSP ages [neb_a0, neb_a1): inside every cube's age range (App. C)
   int neb_a0 = 0, neb_a1 = 0;
   if (nl > 0 || has_cont) {
@@ -203,10 +212,13 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   g.n_u = nl ? d->n_u : 0;
   g.n_sfh = d->n_sfh;
   g.n_zh = d->n_zh;
-  g.P = TH_NSCALAR + d->n_sfh + d->n_zh + (d->escape ? 1 : 0) + (d->igm ? 1 : 0);
+  g.P = TH_NSCALAR + d->n_sfh + d->n_zh + (d->escape ? 1 : 0) + (d->igm ? 1 : 0) + (d->sigma_gal_max > 0 ? 1 : 0);
   g.th_fob = TH_NSCALAR + d->n_sfh + d->n_zh;
   g.th_igm = g.th_fob + (d->escape ? 1 : 0);
   g.igm = d->igm;
+  g.vdisp = d->sigma_gal_max > 0 ? 1 : 0;
+  g.th_sgal = g.th_igm + (d->igm ? 1 : 0);
+  g.vd_max = d->sigma_gal_max;
   g.sfh_scheme = d->sfh_scheme;
   g.escape = d->escape;
   g.neb_a0 = neb_a0;
@@ -305,6 +317,7 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
     g.log_uniform = dev < 1e-6 ? 1 : 0;
     g.lnw0 = std::log(d->wave[0]);
     g.inv_dlnw = 1.0 / dl;
+    g.dlnw = dl;
   }
   // Voronoi cells of the age nodes (App. B): first from 0, last to +inf
   std::vector<double> lo(na), hi(na);
@@ -607,6 +620,7 @@ extern "C" sps_status sps_theta_layout(const sps_library *L, sps_layout *o) {
   o->log_jitter = TH_LOG_JITTER;
   o->frac_obrun = L->dev.escape ? L->dev.th_fob : -1;
   o->igm_factor = L->dev.igm ? L->dev.th_igm : -1;
+  o->sigma_gal = L->dev.vdisp ? L->dev.th_sgal : -1;
   return SPS_OK;
 }
 
@@ -629,6 +643,7 @@ static double sigma_inst_host(int mode, double v, double lam) {
 
 sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsHost &h, uint32_t *warnings) {
   if (warnings) *warnings = 0;
+  double vd_ksig_kms_max = 0.0;   // widest continuum kernel of a spectrum (km/s)
   h.kind = d->kind;
   if (d->kind == SPS_OBS_PHOT) {
     if (d->n_band < 1 || d->n_band > 256) return fail(SPS_E_SHAPE, "n_band must be in [1, 256]");
@@ -713,7 +728,9 @@ sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsH
       }
       if (si < sl) ++finer;
       const double sfix2 = std::max(si * si - sl * sl, 0.0);
-      h.ksig[i] = std::sqrt(sfix2 + d->sigma_gal_kms * d->sigma_gal_kms) / kC_kms;
+      const double sk = std::sqrt(sfix2 + d->sigma_gal_kms * d->sigma_gal_kms);
+      vd_ksig_kms_max = std::max(vd_ksig_kms_max, sk);
+      h.ksig[i] = sk / kC_kms;
     }
     if (finer && warnings) *warnings |= SPS_WARN_LSF_FINER_THAN_LIBRARY;
     h.lsf_mode = d->lsf_mode;
@@ -760,6 +777,45 @@ sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsH
     return fail(SPS_E_INVAL, "unknown observation kind %d", d->kind);
   }
   h.noise_flags = d->noise_flags & 15u;
+  if (L->dev.vdisp && (h.kind == SPS_OBS_PHOT || h.kind == SPS_OBS_SPEC)) {
+    // Fourier stage of a free sigma_gal (Sec. 2.5, App. F): the observed range whose rest
+    // frame the projection reads, the window margin M in nodes (the banded rows' reach,
+    // sigma_max's reach, the interpolation brackets) and the power-of-two transform length
+    // that holds the longest window plus sigma_max's reach on each side
+    const double dlnl = L->dev.dlnw;
+    const int mg = (int)std::ceil(5.0 * L->dev.vd_max / (kC_kms * dlnl));
+    double lo, hi;
+    int M;
+    if (h.kind == SPS_OBS_SPEC) {
+      lo = h.pix.front();
+      hi = h.pix.back();
+      M = (int)std::ceil(5.0 * vd_ksig_kms_max / (kC_kms * dlnl)) + mg + 2;
+    } else {
+      lo = *std::min_element(h.fw.begin(), h.fw.end());
+      hi = *std::max_element(h.fw.begin(), h.fw.end());
+      M = mg + 2;
+    }
+    const double need = std::ceil(std::log(hi / lo) / dlnl) + 2.0 * M + 2.0 + 2.0 * mg;
+    int n = 1, lg = 0;
+    while (n < need && n <= kVdispMaxFFT) {
+      n *= 2;
+      ++lg;
+    }
+    if (n > kVdispMaxFFT)
+      return fail(SPS_E_SHAPE, "the Fourier stage of this observation needs a transform of %.0f points (at most %d)",
+                  need, kVdispMaxFFT);
+    h.vd_M = M;
+    h.vd_nfft = n;
+    h.vd_log2 = lg;
+    h.vd_lnlo = std::log(lo);
+    h.vd_lnhi = std::log(hi);
+    h.vd_dlnl = dlnl;
+    h.vd_tw.resize((size_t)n);
+    for (int k = 0; k < n / 2; ++k) {
+      h.vd_tw[2 * k] = std::cos(2.0 * kPi * k / n);
+      h.vd_tw[2 * k + 1] = -std::sin(2.0 * kPi * k / n);
+    }
+  }
   return SPS_OK;
 }
 
@@ -831,10 +887,11 @@ bool precision_built(const sps_library *L, int p) { return p >= 0 && p <= 9 && (
 
 sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_table, const int *point_obs,
                           const double *theta, int B, int prec, double *logl, double *model, int ld_model,
-                          bool grad, int ld_g, sps_obs *timing_obs, hipStream_t s) {
+                          bool grad, int ld_g, const ObsHost *one, sps_obs *timing_obs, hipStream_t s) {
   if (B < 1 || B > w.max_batch) return fail(SPS_E_SHAPE, "B=%d outside [1, max_batch=%d]", B, w.max_batch);
   if (!precision_built(L, prec)) return fail(SPS_E_INVAL, "precision %d not built into this library", prec);
   const DevLib &g = L->dev;
+  if (g.vdisp && !one) return fail(SPS_E_INVAL, "a free sigma_gal needs a single observation per launch");
   const int B_pad = (B + kMAlign - 1) / kMAlign * kMAlign;
   // the thread's HIP last-error slot may hold a stale code set by another library's
   // call; clear it so that only this call's own launches are checked below
@@ -869,8 +926,8 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   // the single-observation path knows its observation: a line catalogue needs no rest-frame
   // spectrum (no contraction), a calibration polynomial the model at the sorted rows and a
   // pass of its own after the projection
-  const bool lines_only = timing_obs && timing_obs->host.kind == SPS_OBS_LINES;
-  const bool calib = timing_obs && timing_obs->host.calib_mode != SPS_CALIB_NONE;
+  const bool lines_only = one && one->kind == SPS_OBS_LINES;
+  const bool calib = one && one->calib_mode != SPS_CALIB_NONE;
   if (calib && (grad || !w.mbuf)) return fail(SPS_E_INVAL, "calibration polynomial: no gradient, and a full workspace");
   const int n_nt = g.N_pad / 64;
   const bool span = !grad && g.log_uniform && prec != SPS_FP64 && w.tiles && B_pad / MT <= kTileListMaxM;
@@ -911,6 +968,19 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
     nb.f64 = prec == SPS_FP64;
     e = launch_nebular(g, nb, s);
   }
+  if (g.vdisp && one->vd_nfft > 0 && e == hipSuccess) {
+    // the Fourier stage of a free sigma_gal, before the projection (which applies the IGM)
+    VdispLaunch vl;
+    vl.obs = obs_table;
+    vl.theta = theta;
+    vl.rows = w.rows;
+    vl.F = w.F;
+    vl.B_pad = B_pad;
+    vl.nfft = one->vd_nfft;
+    vl.log2n = one->vd_log2;
+    vl.f64 = prec == SPS_FP64;
+    e = launch_vdisp(g, vl, s);
+  }
   ProjectLaunch pj;
   pj.obs_table = obs_table;
   pj.rows = w.rows;
@@ -948,7 +1018,7 @@ sps_status run_forward(const sps_library *L, sps_obs *o, const double *theta, in
   if (!L || !o || !theta) return fail(SPS_E_INVAL, "NULL argument");
   if (o->lib != L) return fail(SPS_E_INVAL, "observation belongs to another library");
   return launch_forward(L, o->ws, o->dev_obs, nullptr, theta, B, prec, logl, model, o->host.n_data,
-                        want_grad_buffers, o->host.n_data, o, s);
+                        want_grad_buffers, o->host.n_data, &o->host, o, s);
 }
 
 }  // namespace sps
@@ -971,9 +1041,10 @@ extern "C" sps_status sps_logl_grad(const sps_library *L, sps_obs *o, const doub
   if (prec != SPS_FP64 && prec != SPS_FP32) return fail(SPS_E_INVAL, "gradients are available for FP64 and FP32");
   if (o && (o->host.kind == SPS_OBS_LINES || o->host.calib_mode != SPS_CALIB_NONE))
     return fail(SPS_E_INVAL, "gradients are not available for line catalogues or calibrated spectra");
-  if (L && (L->dev.has_cont || L->dev.escape || L->line_tau_axis || L->dev.sfh_scheme || L->dev.igm))
+  if (L && (L->dev.has_cont || L->dev.escape || L->line_tau_axis || L->dev.sfh_scheme || L->dev.igm || L->dev.vdisp))
     return fail(SPS_E_INVAL, "gradients are not available for libraries with a nebular continuum cube, an escape "
-                "geometry, a line table on an age axis of its own, the linear SFH scheme or the IGM");
+                "geometry, a line table on an age axis of its own, the linear SFH scheme, the IGM or a free "
+                "sigma_gal");
   sps_status st = run_forward(L, o, theta, B, prec, logl, nullptr, true, (hipStream_t)stream);
   if (st != SPS_OK) return st;
   return run_adjoint(L, o, theta, B, prec, grad, (hipStream_t)stream);

@@ -31,6 +31,9 @@ constexpr int kMaxKTiles32 = kMaxKPad / kKTile;
 // line l's profile; kIonSrc - s the raw ionising continuum (below 912 A) of SSP s; INT_MIN
 // padding.
 constexpr int kIonSrc = -(1 << 24);
+// Longest transform of the Fourier stage of a free sigma_gal (two FP64 complex rows of it
+// fill 128 KB of LDS)
+constexpr int kVdispMaxFFT = 8192;
 
 // theta scalar columns (see include/sps.h)
 enum ThetaCol {
@@ -55,6 +58,8 @@ struct DevLib {
   int has_cont, n_cz, n_cu;
   int sfh_scheme;                    // 0 step, 1 linear (tent integral; ages close prep_tab)
   int igm, th_igm;                   // Madau IGM and the theta column of igm_factor
+  int vdisp, th_sgal;                // free stellar velocity dispersion and its theta column
+  double vd_max;                     // largest admitted sigma_gal [km/s]
   const double *cz, *cu;
   const float *cont_f, *cont_sc_f;
   const double *cont_d, *cont_sc_d;
@@ -62,7 +67,7 @@ struct DevLib {
   int log_uniform;                   // wave grid uniform in ln(lambda) (direct indexing)
   int zmajor;                        // K order: 0 age-major, 1 metallicity-major (see kpos_of)
   double T1, H0, Om, t_young;
-  double lnw0, inv_dlnw;             // ln(lambda_0) and 1/dln(lambda) when log_uniform
+  double lnw0, inv_dlnw, dlnw;       // ln(lambda_0), 1/dln(lambda) and dln(lambda) when log_uniform
   const double *cell_lo, *cell_hi;   // [n_age] linear-time Voronoi cells
   const double *logz, *afe;          // nodes
   const double *Q;                   // [n_afe][n_z][n_young] photons/s/Msun
@@ -131,6 +136,12 @@ struct DevObs {
   // line catalogue: entry k sums lines lidx[loff[k] .. loff[k+1]); upper[k]: upper limit
   const int *loff, *lidx;
   const uint8_t *upper;
+  // Fourier stage of a free sigma_gal: window margin in nodes, transform length (a power
+  // of two) and its log2, ln of the observed range's ends, the grid's dln(lambda), and the
+  // twiddles e^{-2 pi i k / n}, k < n / 2, as (cos, sin) pairs
+  int vd_M, vd_nfft, vd_log2, vd_pad;
+  double vd_lnlo, vd_lnhi, vd_dlnl;
+  const double *vd_tw;
 };
 
 // Per-point quantities, stored at the point's sorted row.
@@ -149,8 +160,27 @@ struct PointRow {
   int kind;     // observation kind
   int seg0;     // log-uniform grid: first rest-frame pixel the projection reads (photometry:
   int seg_n;    //   phot_span; spectra: spec_span) and the number of pixels from there
-  int pad;
+  int cov0;     // pixels [cov0, cov0 + cov_n) of F that must be computed: the span above, or
+  int cov_n;    //   with a free sigma_gal the Fourier stage's window (vdisp_window), which holds it
 };
+
+// Window [j0, j0 + n) of the Fourier stage of a free sigma_gal (Sec. 2.5, App. F) at
+// redshift z: from floor(u(lambda_lo)) - M to floor(u(lambda_hi)) + 1 + M, clamped to the
+// grid, u(lambda) = (ln lambda - ln(1 + z) - ln lambda_0) / dln(lambda); empty for a
+// non-finite redshift or a range off the grid.
+__device__ __forceinline__ void vdisp_window(const DevLib &lib, double lnlo, double lnhi, int M, double dlnl,
+                                             double z, int &j0, int &n) {
+  const double lnopz = log1p(z);
+  const double u0 = (lnlo - lnopz - lib.lnw0) / dlnl, u1 = (lnhi - lnopz - lib.lnw0) / dlnl;
+  j0 = 0;
+  n = 0;
+  if (!(isfinite(u0) && isfinite(u1))) return;
+  const double a = fmax(floor(u0) - M, 0.0), b = fmin(floor(u1) + 2.0 + M, (double)lib.N);
+  if (b > a) {
+    j0 = (int)a;
+    n = (int)b - j0;
+  }
+}
 
 // Fractional log index of the rest wavelength of an observed filter node, on a
 // log-uniform grid: ln(lambda_obs) / dln(lambda) + ui0, ui0 = -(ln(1+z) + ln lambda_0) /

@@ -408,9 +408,9 @@ __global__ void __launch_bounds__(256) k_tile_list(const PointRow *__restrict__ 
   __syncthreads();
   for (int r = tid; r < B_pad; r += 256) {
     const PointRow &pr = rows[r];
-    if (pr.b >= 0 && pr.seg_n > 0) {   // one pixel of margin each side
-      atomicMin(&lo[r / MT], max(pr.seg0 - 1, 0) / kSpanTile);
-      atomicMax(&hi[r / MT], min(pr.seg0 + pr.seg_n, n_nt * kSpanTile - 1) / kSpanTile);
+    if (pr.b >= 0 && pr.cov_n > 0) {   // one pixel of margin each side
+      atomicMin(&lo[r / MT], max(pr.cov0 - 1, 0) / kSpanTile);
+      atomicMax(&hi[r / MT], min(pr.cov0 + pr.cov_n, n_nt * kSpanTile - 1) / kSpanTile);
     }
   }
   __syncthreads();

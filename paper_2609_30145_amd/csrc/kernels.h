@@ -92,6 +92,17 @@ struct NebLaunch {
 };
 hipError_t launch_nebular(const DevLib &lib, const NebLaunch &nl, hipStream_t s);
 
+// Fourier stage of a free sigma_gal (Sec. 2.5, App. F): every row's window of F (PointRow
+// cov0 / cov_n) broadened in place, one workgroup per pair of sorted rows
+struct VdispLaunch {
+  const DevObs *obs;         // the observation (device): twiddles and the grid step
+  const double *theta;       // [B, P] caller's order
+  const PointRow *rows;
+  void *F;                   // [B_pad][N_pad] FP32, or FP64 when f64
+  int B_pad, nfft, log2n, f64;
+};
+hipError_t launch_vdisp(const DevLib &lib, const VdispLaunch &vl, hipStream_t s);
+
 // library packing
 struct PackLaunch {
   const double *flux;        // [n_afe][n_z][n_age][N] raw

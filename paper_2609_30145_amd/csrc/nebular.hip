@@ -95,13 +95,13 @@ __global__ void __launch_bounds__(kNebThreads) k_nebc(DevLib lib, NebArgs a) {
     wq3 = src[min(tid + 3 * kNebThreads, last)];
   }
   // per row: live (a real point and, on span-limited launches, one whose projection reads
-  // this N tile: its pixels [seg0, seg0 + seg_n) with the tile list's one-pixel margin),
+  // this N tile: its pixels [cov0, cov0 + cov_n) with the tile list's one-pixel margin),
   // the corners of its cell, the bilinear weights, the attenuation parameters
   if (tid < MT) {
     const int r = tid;
     const PointRow &pr = a.rows[m0 + r];
     bool live = pr.b >= 0;
-    if (live && a.list && pr.seg_n > 0) live = pr.seg0 - 1 < n0 + kSpanTile && pr.seg0 + pr.seg_n + 1 > n0;
+    if (live && a.list && pr.cov_n > 0) live = pr.cov0 - 1 < n0 + kSpanTile && pr.cov0 + pr.cov_n + 1 > n0;
     s_live[r] = live;
     const int jz = pr.nc_j[0], ju = pr.nc_j[1];
     const double tz = pr.nc_t[0], tu = pr.nc_t[1];

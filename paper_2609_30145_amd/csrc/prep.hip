@@ -423,6 +423,8 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   const int kind = obp->kind;
   const double fw_min = obp->fwln_min, fw_max = obp->fwln_max;
   const double px_lo = obp->lnpix_lo, px_hi = obp->lnpix_hi, ks_max = obp->ksig_max;
+  const double vd_lo = obp->vd_lnlo, vd_hi = obp->vd_lnhi, vd_dl = obp->vd_dlnl;
+  const int vd_M = obp->vd_M, vd_n = obp->vd_nfft;
 
   // ---- A2: bin metallicity from the enrichment history (Sec. 2.2.2): nodes and bin
   // centres are both log-uniform from T1 to t_univ, so the interpolation weight in ln T
@@ -801,7 +803,9 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       if (kind == 0) phot_span(lib, fw_min, fw_max, z, pr.seg0, pr.seg_n);
       else if (kind == 1) spec_span(lib, px_lo, px_hi, ks_max, z, pr.seg0, pr.seg_n);
     }
-    pr.pad = 0;
+    pr.cov0 = pr.seg0;
+    pr.cov_n = pr.seg_n;
+    if (lib.vdisp && vd_n > 0 && (kind == 0 || kind == 1)) vdisp_window(lib, vd_lo, vd_hi, vd_M, vd_dl, z, pr.cov0, pr.cov_n);
     a.rows[r] = pr;
   }
 }

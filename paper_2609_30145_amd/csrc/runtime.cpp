@@ -64,7 +64,7 @@ int64_t obs_device_bytes(const ObsHost &h) {
   } else {
     b += 3 * r256(h.pix.size() * 8) + (h.lsf_vals.empty() ? 0 : r256(h.lsf_vals.size() * 8));
   }
-  b += 3 * r256((size_t)h.n_data * 8) + r256((size_t)h.n_data);
+  b += 3 * r256((size_t)h.n_data * 8) + r256((size_t)h.n_data) + r256(h.vd_tw.size() * 8);
   return (int64_t)b;
 }
 
@@ -126,6 +126,15 @@ sps_status upload_obs(const ObsHost &host, DevObs &o, DeviceBuffers &mem, hipStr
     o.loff = (const int *)put(host.loff.data(), host.loff.size() * 4);
     o.lidx = (const int *)put(host.lidx.data(), std::max<size_t>(1, host.lidx.size()) * 4);
     o.upper = (const uint8_t *)put(host.upper.data(), host.upper.size());
+  }
+  if (host.vd_nfft > 0) {
+    o.vd_M = host.vd_M;
+    o.vd_nfft = host.vd_nfft;
+    o.vd_log2 = host.vd_log2;
+    o.vd_lnlo = host.vd_lnlo;
+    o.vd_lnhi = host.vd_lnhi;
+    o.vd_dlnl = host.vd_dlnl;
+    o.vd_tw = (const double *)put(host.vd_tw.data(), host.vd_tw.size() * 8);
   }
   o.data = (const double *)put(host.data.data(), (size_t)host.n_data * 8);
   o.sigma = (const double *)put(host.sigma.data(), (size_t)host.n_data * 8);

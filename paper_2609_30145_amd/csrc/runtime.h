@@ -65,6 +65,9 @@ struct ObsHost {
   double calib_xs = 0, calib_x0 = 0;
   std::vector<int> loff, lidx;       // line catalogue blends
   std::vector<uint8_t> upper;
+  int vd_M = 0, vd_nfft = 0, vd_log2 = 0;   // Fourier stage of a free sigma_gal
+  double vd_lnlo = 0, vd_lnhi = 0, vd_dlnl = 0;
+  std::vector<double> vd_tw;
 };
 
 sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsHost &h, uint32_t *warnings);
@@ -113,10 +116,12 @@ sps_status run_forward(const sps_library *L, sps_obs *o, const double *theta, in
 sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, int B, int prec, double *grad,
                        hipStream_t s);
 // The forward launch sequence on an explicit workspace and observation table
-// (point_obs: observation slot per point, NULL = slot 0).
+// (point_obs: observation slot per point, NULL = slot 0).  `one` is the host side of the
+// observation when every point has the same one (NULL on the serving path, which mixes
+// observations): line catalogues, calibration polynomials and a free sigma_gal need it.
 sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_table, const int *point_obs,
                           const double *theta, int B, int prec, double *logl, double *model, int ld_model,
-                          bool grad, int ld_g, sps_obs *timing_obs, hipStream_t s);
+                          bool grad, int ld_g, const ObsHost *one, sps_obs *timing_obs, hipStream_t s);
 bool precision_built(const sps_library *L, int p);
 // Device address of the allocation-free entry point's static scratch on `device`, looked
 // up once per device (called by sps_library_load).

@@ -187,7 +187,7 @@ bool sps_server::tick() {
   if (e == hipSuccess) e = launch_propose(d_reqs, n, P, n_sfh, box, d_theta_all, d_point_obs, total, s_compute);
   if (e != hipSuccess) return false;
   if (launch_forward(lib, ws, d_obs_table, d_point_obs, d_theta_all, total, desc.precision, d_logl_all, nullptr, 1,
-                     false, 1, nullptr, s_compute) != SPS_OK)
+                     false, 1, nullptr, nullptr, s_compute) != SPS_OK)
     return false;
   e = launch_update(d_reqs, n, P, d_theta_all, d_logl_all, d_thr, total, s_compute);
   if (e == hipSuccess) e = hipStreamSynchronize(s_compute);
@@ -305,6 +305,7 @@ extern "C" sps_status sps_server_create(const sps_library *L, const sps_server_d
   const bool mock = d->device < 0;
   if (!mock && L->device < 0) return fail(SPS_E_STATE, "host-only library: the GPU server needs a device library");
   if (!mock && !precision_built(L, d->precision)) return fail(SPS_E_INVAL, "precision %d not built", d->precision);
+  if (L->dev.vdisp) return fail(SPS_E_INVAL, "the server's mixed launches do not take a free sigma_gal");
   auto *S = new sps_server();
   S->lib = L;
   S->desc = *d;

@@ -109,5 +109,5 @@ extern "C" sps_status sps_logl_static(const sps_library *L, const sps_obs *o, co
   w.WQ = (double *)take(Bp * (size_t)(g.has_cont ? g.neb_a1 - g.neb_a0 : 1) * 8);
   w.counter = nullptr;
   return launch_forward(L, w, o->dev_obs, nullptr, theta, B, prec, logl, model, o->host.n_data, false,
-                        o->host.n_data, nullptr, (hipStream_t)stream);
+                        o->host.n_data, &o->host, nullptr, (hipStream_t)stream);
 }

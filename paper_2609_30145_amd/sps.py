@@ -38,7 +38,8 @@ class LibraryDesc(C.Structure):
                 ("n_line_tau", C.c_int32), ("line_tau", _dp),
                 ("n_cont_tau", C.c_int32), ("n_cont_zg", C.c_int32), ("n_cont_u", C.c_int32),
                 ("cont_tau", _dp), ("cont_zg", _dp), ("cont_u", _dp), ("cont_table", _dp),
-                ("escape", C.c_int32), ("sfh_scheme", C.c_int32), ("igm", C.c_int32)]
+                ("escape", C.c_int32), ("sfh_scheme", C.c_int32), ("igm", C.c_int32),
+                ("sigma_gal_max", C.c_double)]
 
 ESCAPE = {"none": 0, "runaway_bc": 1, "picket": 2}
 SFH_SCHEMES = {"step": 0, "linear": 1}
@@ -54,7 +55,7 @@ class Layout(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "P", "n_scalar", "sfh", "n_sfh", "zh", "n_zh", "logmass", "zred", "tau_bc", "alpha_bc", "tau_diff",
         "delta", "logzsol", "gas_logz", "gas_logu", "afe", "log_err_scale", "log_f_calib", "log_f_data",
-        "log_jitter", "frac_obrun", "igm_factor")]
+        "log_jitter", "frac_obrun", "igm_factor", "sigma_gal")]
 
 
 class ObsDesc(C.Structure):
@@ -138,12 +139,14 @@ class Library:
 
     def __init__(self, lib_arrays: dict, n_sfh: int, T1: float, n_zh: int, cosmo=(70.0, 0.3),
                  dust: dict | None = None, lines: dict | None = None, precisions=("fp32",), device: int = 0,
-                 cont: dict | None = None, escape: str = "none", sfh_scheme: str = "step", igm: bool = False):
+                 cont: dict | None = None, escape: str = "none", sfh_scheme: str = "step", igm: bool = False,
+                 sigma_gal_max: float = 0.0):
         """``device=-1`` loads a host-only library (layout and observation operators; used by
         the mock server executor).  ``lines`` may carry ``line_tau`` (the table's own age axis);
         ``cont`` is a nebular continuum cube (cont_table [tau][zg][u][wave], tau_nodes,
         zg_nodes, u_nodes); ``escape`` is "none", "runaway_bc" or "picket"; ``sfh_scheme`` is
-        "step" or "linear"; ``igm`` switches the Madau IGM transmission on."""
+        "step" or "linear"; ``igm`` switches the Madau IGM transmission on; ``sigma_gal_max`` > 0
+        adds a free stellar velocity dispersion column (km/s, Fourier stage)."""
         L = lib()
         keep = []
         ages, logz, wave = _arr(lib_arrays["ages"]), _arr(lib_arrays["logz"]), _arr(lib_arrays["wave"])
@@ -184,6 +187,7 @@ class Library:
         d.escape = ESCAPE[escape]
         d.sfh_scheme = SFH_SCHEMES[sfh_scheme]
         d.igm = 1 if igm else 0
+        d.sigma_gal_max = float(sigma_gal_max)
         mask = 0
         for p in precisions:
             mask |= 1 << PRECISIONS[p]

@@ -12,14 +12,15 @@ from synth import workloads as wl
 
 
 def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=(), wave_jitter=0.0, spec=None,
-              cont=None, escape="none", line_tau=None, sfh_scheme="step", igm=False):
+              cont=None, escape="none", line_tau=None, sfh_scheme="step", igm=False, vdisp=0.0):
     """wave_jitter > 0 moves each model wavelength by that fraction of the log step
     (sinusoidally), so that the grid is no longer log-uniform and the general
     interpolation paths are taken.  ``spec`` overrides entries of the spectrum grid
     (lsf_mode, lsf_value: a constant or an array on the pixels, sigma_gal_kms, ...).
     ``cont``: True for the synthetic nebular continuum cube, or a dict of arguments of
     its generator (tau_nodes); ``escape``: the f_ob geometry (theta then carries frac_obrun); ``line_tau``: an
-    age axis of the line table's own; ``sfh_scheme`` "step" or "linear"; ``igm`` the IGM."""
+    age axis of the line table's own; ``sfh_scheme`` "step" or "linear"; ``igm`` the IGM; ``vdisp`` > 0 a
+    free sigma_gal up to that many km/s (theta drawn uniformly below it)."""
     B = cfg.batch if B is None else B
     lib = wl.make_library(cfg, seed)
     if wave_jitter > 0.0:
@@ -33,10 +34,12 @@ def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=()
         cont = wl.make_nebular_continuum(lib["wave"], seed + 3, **(cont if isinstance(cont, dict) else {}))
     else:
         cont = None
-    olib = om.build_library(cfg, lib, lines, dust, cont=cont, escape=escape, sfh_scheme=sfh_scheme, igm=igm)
+    olib = om.build_library(cfg, lib, lines, dust, cont=cont, escape=escape, sfh_scheme=sfh_scheme, igm=igm,
+                            sigma_gal_max=vdisp)
     esc = escape != "none"
-    theta = wl.make_theta(cfg, B, seed=theta_seed, escape=esc, igm=igm, sfh_scheme=sfh_scheme)
-    theta_true = wl.make_theta(cfg, 1, seed=theta_seed + 1000, escape=esc, igm=igm, sfh_scheme=sfh_scheme)
+    theta = wl.make_theta(cfg, B, seed=theta_seed, escape=esc, igm=igm, sfh_scheme=sfh_scheme, vdisp=vdisp)
+    theta_true = wl.make_theta(cfg, 1, seed=theta_seed + 1000, escape=esc, igm=igm, sfh_scheme=sfh_scheme,
+                               vdisp=vdisp)
     kind = kind or ("spec" if cfg.spectrum else "phot")
     nz = {n: True for n in noise}
     if kind == "phot":
@@ -55,7 +58,7 @@ def make_case(cfg, B=None, seed=0, theta_seed=2, kind=None, n_pix=None, noise=()
         m_true = om.predict(olib, obs, theta_true)[0]
         obs.data, obs.sigma = wl.noisy_spectrum(m_true, seed + 5)
     return dict(cfg=cfg, lib=lib, lines=lines, dust=dust, olib=olib, theta=theta, theta_true=theta_true,
-                obs=obs, kind=kind, cont=cont, escape=escape, sfh_scheme=sfh_scheme, igm=igm)
+                obs=obs, kind=kind, cont=cont, escape=escape, sfh_scheme=sfh_scheme, igm=igm, vdisp=vdisp)
 
 
 def gpu_objects(case, precisions=("fp64", "fp32"), max_batch=None):
@@ -67,7 +70,7 @@ def gpu_objects(case, precisions=("fp64", "fp32"), max_batch=None):
     L = sps.Library(case["lib"], n_sfh=cfg.n_sfh, T1=cfg.T1, n_zh=cfg.n_zh, cosmo=cfg.cosmo, dust=case["dust"],
                     lines=case["lines"], precisions=precisions, cont=case.get("cont"),
                     escape=case.get("escape", "none"), sfh_scheme=case.get("sfh_scheme", "step"),
-                    igm=case.get("igm", False))
+                    igm=case.get("igm", False), sigma_gal_max=case.get("vdisp", 0.0))
     return L, gpu_observation(L, case, max_batch)
 
 
