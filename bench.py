@@ -230,6 +230,85 @@ def nebular_leg(base, steps=20, warmup=3, seed=0):
     return out
 
 
+def features_leg(base_spec, base_phot, steps=20, warmup=3, seed=0):
+    """The paper's optional stages at full size, each timed as forward + logL on 1024 live
+    points, with the time it adds to the plain workload's step:
+      - the 3000-pixel prism spectrum with a free stellar velocity dispersion (sigma_gal ~
+        U(0, 500) km/s, the Fourier stage), and also with a calibration polynomial of order
+        5, marginalised (FP16 hi + residual, the spectroscopic default);
+      - the photometric workload under the linear (tent-integral) SFH scheme with the IGM
+        (FP16 weight residual, the photometric default);
+      - a catalogue of 16 entries (single lines and blends, three upper limits) of the 128
+        library lines (no contraction)."""
+    import torch
+
+    import paper_2609_30145_amd as sps
+    from synth import workloads as wl
+    out = {}
+    cfg = wl.CONFIGS["c3"]
+    lib = wl.make_library(cfg, seed)
+    lines = wl.make_lines(cfg, lib, seed + 1)
+    dust = wl.make_dust_tables(cfg, lib["wave"])
+    L = sps.Library(lib, n_sfh=cfg.n_sfh, T1=cfg.T1, n_zh=cfg.n_zh, cosmo=cfg.cosmo, dust=dust, lines=lines,
+                    precisions=("fp16",), sigma_gal_max=500.0)
+    g = wl.make_spectrum_grid(cfg.n_pix)
+    th_true = wl.make_theta(cfg, 1, seed=seed + 1002, vdisp=500.0)
+    theta = torch.tensor(wl.make_theta(cfg, cfg.batch, seed=seed + 2, vdisp=500.0), device="cuda")
+    for tag, calib in (("spectrum_vdisp", {}), ("spectrum_vdisp_calib",
+                                                dict(calib="marginal", calib_order=5, calib_prior=np.full(6, 0.1)))):
+        O = sps.Observation(L, "spec", cfg.batch, pix_wave=g["pix_wave"], lsf_mode=g["lsf_mode"],
+                            lsf_value=g["lsf_value"], z_ref=float(th_true[0, 1]), sigma_gas_kms=g["sigma_gas_kms"],
+                            **calib)
+        m_true = sps.forward(L, O, torch.tensor(th_true, device="cuda"), "fp16")[0].cpu().numpy()
+        d, sg = wl.noisy_spectrum(m_true, seed + 5)
+        O.set_data(d, sg)
+        dt, _ = time_precision(L, O, theta, "fp16", steps, warmup)
+        ms = 1e3 * dt / steps
+        out[tag] = {"precision": "fp16", "evals_per_s": round(cfg.batch * steps / dt, 1), "ms_per_step": round(ms, 4),
+                    "added_ms_per_step": round(ms - base_spec["forward_fp16_ms"], 4) if base_spec else None}
+    out["spectrum_vdisp"]["workload"] = (f"{cfg.batch} live points, {cfg.n_pix}-pixel prism spectrum, free sigma_gal "
+                                         f"~ U(0, 500) km/s (Fourier stage)")
+    out["spectrum_vdisp_calib"]["workload"] = "the same with a marginalised calibration polynomial of order 5"
+    del L, lib
+    cfg = wl.CONFIGS["c1"]
+    lib = wl.make_library(cfg, seed)
+    lines = wl.make_lines(cfg, lib, seed + 1)
+    dust = wl.make_dust_tables(cfg, lib["wave"])
+    L = sps.Library(lib, n_sfh=cfg.n_sfh, T1=cfg.T1, n_zh=cfg.n_zh, cosmo=cfg.cosmo, dust=dust, lines=lines,
+                    precisions=("fp16",), sfh_scheme="linear", igm=True)
+    filters = wl.make_filters(cfg.filters)
+    th_true = wl.make_theta(cfg, 1, seed=seed + 1002, igm=True, sfh_scheme="linear")
+    O = sps.Observation(L, "phot", cfg.batch, filters=filters)
+    m_true = sps.forward(L, O, torch.tensor(th_true, device="cuda"), "fp16")[0].cpu().numpy()
+    d, sg = wl.noisy_photometry(m_true, seed + 5)
+    O.set_data(d, sg)
+    theta = torch.tensor(wl.make_theta(cfg, cfg.batch, seed=seed + 2, igm=True, sfh_scheme="linear"), device="cuda")
+    dt, _ = time_precision(L, O, theta, "fp16_wl", steps, warmup)
+    ms = 1e3 * dt / steps
+    out["linear_sfh_igm"] = {"workload": f"c1 photometry, {cfg.batch} live points, linear (tent-integral) SFH scheme "
+                                         f"and Madau IGM (igm_factor ~ U(0.5, 1.5))",
+                             "precision": "fp16_wl", "evals_per_s": round(cfg.batch * steps / dt, 1),
+                             "ms_per_step": round(ms, 4),
+                             "added_ms_per_step": round(ms - base_phot["ms_per_step"], 4) if base_phot else None}
+    del L
+    L = sps.Library(lib, n_sfh=cfg.n_sfh, T1=cfg.T1, n_zh=cfg.n_zh, cosmo=cfg.cosmo, dust=dust, lines=lines,
+                    precisions=("fp16",))
+    blends = [[i] for i in range(0, 120, 12)] + [[3, 4], [20, 21, 22], [40, 41], [60, 61], [80, 81, 82], [100, 101]]
+    upper = np.zeros(len(blends), dtype=bool)
+    upper[[2, 7, 11]] = True
+    O = sps.Observation(L, "lines", cfg.batch, blends=blends, upper=upper)
+    th_true = wl.make_theta(cfg, 1, seed=seed + 1002)
+    f_true = sps.forward(L, O, torch.tensor(th_true, device="cuda"), "fp16")[0].cpu().numpy()
+    O.set_data(f_true * (1.0 + 0.1 * np.random.default_rng(seed + 5).normal(size=f_true.size)), 0.1 * f_true)
+    theta = torch.tensor(wl.make_theta(cfg, cfg.batch, seed=seed + 2), device="cuda")
+    dt, _ = time_precision(L, O, theta, "fp16_wl", steps, warmup)
+    out["lines"] = {"workload": f"{cfg.batch} live points, catalogue of {len(blends)} entries (single lines and "
+                                f"blends of the 128 library lines, 3 upper limits)",
+                    "precision": "fp16_wl", "evals_per_s": round(cfg.batch * steps / dt, 1),
+                    "ms_per_step": round(1e3 * dt / steps, 4)}
+    return out
+
+
 def serve_leg(seconds, rate_hz=50.0, target_load=0.5, seed=0, log=None):
     """Poisson stream of photometry / prism-spectrum fit requests served by sps_server on
     the alpha-enhanced library in FP16.  Capacity is measured first with a saturating
@@ -318,6 +397,8 @@ def main():
     ap.add_argument("--no-spectrum", action="store_true", help="skip the spectroscopic leg")
     ap.add_argument("--no-small-batch", action="store_true", help="skip the 64-point leg")
     ap.add_argument("--no-nebular", action="store_true", help="skip the nebular-continuum / escape leg")
+    ap.add_argument("--no-features", action="store_true",
+                    help="skip the leg of optional stages (sigma_gal, calibration, linear SFH + IGM, lines)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 5 times (HBM counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -409,6 +490,8 @@ def main():
         out["spectrum"] = spectrum_leg()
     if not args.no_nebular and args.workload == "c1":
         out["nebular"] = nebular_leg(results)
+    if not args.no_features and args.workload == "c1":
+        out["features"] = features_leg(out.get("spectrum"), results.get("fp16_wl"))
     if args.serve_seconds > 0:
         out["serving"] = serve_leg(args.serve_seconds, log=lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:

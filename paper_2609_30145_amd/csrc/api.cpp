@@ -928,7 +928,8 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   // pass of its own after the projection
   const bool lines_only = one && one->kind == SPS_OBS_LINES;
   const bool calib = one && one->calib_mode != SPS_CALIB_NONE;
-  if (calib && (grad || !w.mbuf)) return fail(SPS_E_INVAL, "calibration polynomial: no gradient, and a full workspace");
+  if (calib && (grad || !w.mbuf || !w.scr || w.ld_scr < 24))
+    return fail(SPS_E_INVAL, "calibration polynomial: no gradient, and a full workspace");
   const int n_nt = g.N_pad / 64;
   const bool span = !grad && g.log_uniform && prec != SPS_FP64 && w.tiles && B_pad / MT <= kTileListMaxM;
   ContractLaunch cl;
@@ -1006,6 +1007,8 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
     cb.msorted = w.mbuf;
     cb.ld = ld_g;
     cb.B_pad = B_pad;
+    cb.sums = w.scr;
+    cb.ld_sums = w.ld_scr;
     cb.logl = logl;
     e = launch_calib(g, cb, s);
   }

@@ -77,6 +77,8 @@ struct CalibLaunch {
   const double *theta;
   const double *msorted;     // [B_pad][ld] model at the sorted rows
   int ld, B_pad;
+  double *sums;              // [B_pad][ld_sums] per-row sums (S_0..S_14, b_0..b_7), ld_sums >= 23
+  int ld_sums;
   double *logl;              // [B] or NULL
 };
 hipError_t launch_calib(const DevLib &lib, const CalibLaunch &cl, hipStream_t s);

@@ -135,7 +135,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // FP64 for the FP64 path and FP32 otherwise).  The node tables (logz .. Q) are one
 // contiguous run in the order of DevLib::prep_tab, so that they arrive in one copy.
 struct PrepSmem {
-  int th, logz, afe, clo, chi, zg, un, Q, ages, edges, mr, zt, zj, wq, ke, wacc, lt, total;
+  int th, logz, afe, clo, chi, zg, un, Q, ages, edges, mr, zt, zj, wq, ke, wacc, lt, lr, total;
   __host__ __device__ PrepSmem(const DevLib &lib, int mode) {
     const bool f64 = mode == 0, w16 = mode >= 2;
     const int acc = f64 ? 8 : 4;
@@ -158,6 +158,7 @@ struct PrepSmem {
     ke = o;    o += w16 ? lib.K_pad / 4 : 0;              // int16 row exponents
     wacc = o;  o += (lib.K_pad * acc + 7) / 8;
     lt = o;    o += (lib.n_line * lib.n_young * acc + 7) / 8;
+    lr = o;    o += lib.sfh_scheme ? lib.n_age : 0;       // ln(t_a / t_{a-1}) (linear scheme)
     total = o;
   }
 };
@@ -172,19 +173,28 @@ struct PrepSmem {
 // forms, or Taylor series below X = 0.05), int psi = (v - u)(psi(u) + beta (v - u)/2) and
 // I = int psi ln(t/u) = u (psi(u) A + beta u B); the lower half takes ln(u/t_{ag-1}) int psi
 // + I and the upper half ln(t_{ag+1}/u) int psi - I, each over ln(t_{ag+1}/t_ag).
+// Taylor coefficients of A / X^2 ((-1)^k / (k (k - 1)), k = 2 .. 15) and of B / X^3
+// ((-1)^(n+1) / (n (n + 2)), n = 1 .. 14), rounded once at compile time
+struct LogMomentSeries {
+  double a[14], b[14];
+  constexpr LogMomentSeries() : a(), b() {
+    for (int k = 2; k <= 15; ++k) a[k - 2] = ((k & 1) ? -1.0 : 1.0) / (double)(k * (k - 1));
+    for (int n = 1; n <= 14; ++n) b[n - 1] = ((n & 1) ? 1.0 : -1.0) / (double)(n * (n + 2));
+  }
+};
+__device__ constexpr LogMomentSeries kLogMomentSeries{};
+
 __device__ __forceinline__ void log_moments(double X, double &A, double &B) {
   if (X < 0.05) {
-    double a = 0.0, b = 0.0, xk = X * X, xn = X * X * X;
-    for (int k = 2; k <= 15; ++k) {
-      a += ((k & 1) ? -xk : xk) / (double)(k * (k - 1));
-      xk *= X;
+    // Horner from the highest power
+    double a = kLogMomentSeries.a[13], b = kLogMomentSeries.b[13];
+#pragma unroll
+    for (int k = 12; k >= 0; --k) {
+      a = __fma_rn(a, X, kLogMomentSeries.a[k]);
+      b = __fma_rn(b, X, kLogMomentSeries.b[k]);
     }
-    for (int n = 1; n <= 14; ++n) {
-      b += ((n & 1) ? xn : -xn) / (double)(n * (n + 2));
-      xn *= X;
-    }
-    A = a;
-    B = b;
+    A = a * X * X;
+    B = b * X * X * X;
   } else {
     const double lp = log1p(X);
     A = (1.0 + X) * lp - X;
@@ -192,7 +202,10 @@ __device__ __forceinline__ void log_moments(double X, double &A, double &B) {
   }
 }
 
-__device__ double tent_mass(const double *ages, int na, int ag, double T0, double T1, double p0, double p1) {
+// lr[a] = ln(t_a / t_{a-1}) (a >= 1), formed once per point; the logarithms of a piece's
+// end over a node are taken only where the end is not the node itself.
+__device__ double tent_mass(const double *ages, const double *lr, int na, int ag, double T0, double T1, double p0,
+                            double p1) {
   const double beta = (p1 - p0) / (T1 - T0);
   auto at = [&](double x) { return p0 + beta * (x - T0); };
   auto piece = [&](double u, double v, double &i0, double &I) {
@@ -212,7 +225,7 @@ __device__ double tent_mass(const double *ages, int na, int ag, double T0, doubl
     if (v > u) {
       double i0, I;
       piece(u, v, i0, I);
-      c += (log(u / ages[ag - 1]) * i0 + I) / log(ages[ag] / ages[ag - 1]);
+      c += ((u == ages[ag - 1] ? 0.0 : log(u / ages[ag - 1])) * i0 + I) / lr[ag];
     }
   }
   if (ag + 1 < na) {   // weight ln(t_{ag+1} / t) / ln(t_{ag+1} / t_ag) on [t_ag, t_{ag+1}]
@@ -220,7 +233,7 @@ __device__ double tent_mass(const double *ages, int na, int ag, double T0, doubl
     if (v > u) {
       double i0, I;
       piece(u, v, i0, I);
-      c += (log(ages[ag + 1] / u) * i0 - I) / log(ages[ag + 1] / ages[ag]);
+      c += ((u == ages[ag] ? lr[ag + 1] : log(ages[ag + 1] / u)) * i0 - I) / lr[ag + 1];
     }
   }
   if (ag == na - 1) {
@@ -253,6 +266,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   double *s_clo = smem + L.clo, *s_chi = smem + L.chi, *s_zg = smem + L.zg, *s_un = smem + L.un;
   double *s_Q = smem + L.Q, *s_edges = smem + L.edges, *s_mr = smem + L.mr, *s_zt = smem + L.zt;
   const double *s_ages = smem + L.ages;
+  double *s_lr = smem + L.lr;
   double *s_wq = smem + L.wq;
   int *s_zj = (int *)(smem + L.zj);
   const int16_t *s_ke = (const int16_t *)(smem + L.ke);
@@ -426,6 +440,11 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   const double vd_lo = obp->vd_lnlo, vd_hi = obp->vd_lnhi, vd_dl = obp->vd_dlnl;
   const int vd_M = obp->vd_M, vd_n = obp->vd_nfft;
 
+  if (lib.sfh_scheme == 1) {   // the age nodes' log ratios for the tent integrals
+    for (int ag = 1 + tid; ag < na; ag += 256) s_lr[ag] = log(s_ages[ag] / s_ages[ag - 1]);
+    __syncthreads();
+  }
+
   // ---- A2: bin metallicity from the enrichment history (Sec. 2.2.2): nodes and bin
   // centres are both log-uniform from T1 to t_univ, so the interpolation weight in ln T
   // is fixed in the normalised coordinate (bin i >= 1 at (i - 1/2)/(n_sfh - 1), node k
@@ -457,12 +476,20 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
         // trapezoid mass (p_i + p_{i+1}) (T_{i+1} - T_i) / 2, the last SFR repeated
         const double p0 = s_th[TH_NSCALAR + i], p1 = s_th[TH_NSCALAR + min(i + 1, n_sfh - 1)];
         const double T0 = s_edges[i], T1 = s_edges[i + 1];
-        double sum = 0.0;
-        for (int ag = 0; ag < na; ++ag) {
-          const double lo = ag == 0 ? 0.0 : s_ages[ag - 1], hi = ag == na - 1 ? HUGE_VAL : s_ages[ag + 1];
-          if (hi <= T0 || lo >= T1) continue;
-          sum += fmax(tent_mass(s_ages, na, ag, T0, T1, p0, p1), 0.0);
+        // the nodes whose tents [t_{ag-1}, t_{ag+1}] meet the bin, in increasing order: from
+        // the first whose tent ends above T0 (bisection) while the tent starts below T1
+        int ag = 0;
+        {
+          int l = 0, h = na - 1;
+          while (l < h) {
+            const int mid = (l + h) >> 1;
+            if (s_ages[mid + 1] > T0) h = mid; else l = mid + 1;
+          }
+          ag = l;
         }
+        double sum = 0.0;
+        for (; ag < na && (ag == 0 ? 0.0 : s_ages[ag - 1]) < T1; ++ag)
+          sum += fmax(tent_mass(s_ages, s_lr, na, ag, T0, T1, p0, p1), 0.0);
         const double m = 0.5 * (p0 + p1) * (T1 - T0);
         s_mr[i] = sum > 0.0 ? m / sum : 1.0;
       }
@@ -564,7 +591,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     }
     for (; i < n_sfh && s_edges[i] < hi; ++i) {
       const double p0 = s_th[TH_NSCALAR + i], p1 = s_th[TH_NSCALAR + min(i + 1, n_sfh - 1)];
-      const double c = fmax(tent_mass(s_ages, na, ag, s_edges[i], s_edges[i + 1], p0, p1), 0.0);
+      const double c = fmax(tent_mass(s_ages, s_lr, na, ag, s_edges[i], s_edges[i + 1], p0, p1), 0.0);
       if (c == 0.0) continue;
       const double w = c * s_mr[i];
       const int j = s_zj[i];

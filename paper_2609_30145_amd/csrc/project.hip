@@ -520,21 +520,81 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
 // ---------------------------------------------------------------------------------
 // Spectrophotometric calibration polynomial (Sec. 3.2, App. H.3, eq. app_polymarg).  One
 // workgroup per sorted row: with D = diag(mu) A (A_im = T_m(x_i), Chebyshev), C the noise
-// of the uncalibrated model mu and r = d - mu over the mask, the sums G = D^T C^-1 D and
-// b = D^T C^-1 r are accumulated in FP64 per thread (Chebyshev recurrence per pixel),
-// reduced in a fixed order, and one thread solves M = G + Lambda^-1 by Cholesky: the
-// marginal form adds b^T M^-1 b / 2 - ln|M| / 2 - ln|Lambda| / 2 to logL, the optimised form
-// c^T b - c^T G c / 2 at c = M^-1 b (the diagonal likelihood at the regularised best fit).
+// of the uncalibrated model mu and r = d - mu over the mask, G = D^T C^-1 D and
+// b = D^T C^-1 r.  Since T_p T_u = (T_{p+u} + T_{|p-u|}) / 2, G_pu = (S_{p+u} + S_{|p-u|}) / 2
+// with S_k = sum_i mu_i^2 T_k(x_i) / C_i, k <= 2 order: each thread accumulates S and b in
+// FP64 over its pixels (Chebyshev recurrence), the sums are reduced in a fixed order and
+// stored, and a second kernel, one thread per row, solves M = G + Lambda^-1 by Cholesky in
+// registers: the marginal form adds
+// b^T M^-1 b / 2 - ln|M| / 2 - ln|Lambda| / 2 to logL, the optimised form c^T b - c^T G c / 2
+// at c = M^-1 b (the diagonal likelihood at the regularised best fit).
 // ---------------------------------------------------------------------------------
-constexpr int kCalMax = 8;                          // coefficients at most (order 7)
-constexpr int kCalG = kCalMax * (kCalMax + 1) / 2;  // packed upper triangle of G
+constexpr int kCalMax = 8;                 // coefficients at most (order 7)
+constexpr int kCalS = 2 * kCalMax - 1;     // S_0 .. S_14
+
+// The NC x NC solve of one row, unrolled so that everything stays in registers: G and b
+// from the four waves' sums, Cholesky M = G + Lambda^-1 = L L^T, c = M^-1 b by two
+// triangular solves, and the marginal or optimised correction.
+template <int NC>
+__device__ __forceinline__ double calib_solve(const double *__restrict__ sums, const DevObs &ob) {
+  double G[NC][NC], M[NC][NC], b[NC], y[NC], c[NC];
+  auto Sk = [&](int k) { return sums[k]; };
+#pragma unroll
+  for (int p = 0; p < NC; ++p) {
+    b[p] = Sk(kCalS + p);
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      G[p][u] = 0.5 * (Sk(p + u) + Sk(p > u ? p - u : u - p));
+      M[p][u] = G[p][u] + (p == u ? ob.calib_ivar[p] : 0.0);
+    }
+  }
+  double logdet = 0.0;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    double s = M[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= M[j][k] * M[j][k];
+    const double ljj = sqrt(s);
+    M[j][j] = ljj;
+    logdet += 2.0 * log(ljj);
+#pragma unroll
+    for (int i = j + 1; i < NC; ++i) {
+      double t = M[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= M[i][k] * M[j][k];
+      M[i][j] = t / ljj;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    double t = b[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) t -= M[i][k] * y[k];
+    y[i] = t / M[i][i];
+  }
+#pragma unroll
+  for (int i = NC - 1; i >= 0; --i) {
+    double t = y[i];
+#pragma unroll
+    for (int k = i + 1; k < NC; ++k) t -= M[k][i] * c[k];
+    c[i] = t / M[i][i];
+  }
+  double bc = 0.0, cGc = 0.0;
+#pragma unroll
+  for (int p = 0; p < NC; ++p) {
+    bc += b[p] * c[p];
+#pragma unroll
+    for (int u = 0; u < NC; ++u) cGc += c[p] * G[p][u] * c[u];
+  }
+  return ob.calib_mode == 1 ? 0.5 * bc - 0.5 * logdet - ob.calib_lnsd : bc - 0.5 * cGc;
+}
 
 __global__ void __launch_bounds__(256) k_calib(DevLib lib, CalibLaunch a) {
-  __shared__ double red[4][kCalG + kCalMax];
+  __shared__ double red[4][kCalS + kCalMax];
   const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const PointRow pr = a.rows[r];
   if (pr.b < 0) return;
-  const DevObs ob = a.obs_table[pr.obs];
+  const DevObs &ob = a.obs_table[pr.obs];
   if (ob.kind != 1 || ob.calib_mode == 0) return;
   const int nc = ob.calib_order + 1;
   const double *th = a.theta + (size_t)pr.b * lib.P;
@@ -542,9 +602,9 @@ __global__ void __launch_bounds__(256) k_calib(DevLib lib, CalibLaunch a) {
   const double fc = (ob.noise_flags & 2) ? exp(th[TH_LOG_F_CALIB]) : 0.0;
   const double fd = (ob.noise_flags & 4) ? exp(th[TH_LOG_F_DATA]) : 0.0;
   const double jt = (ob.noise_flags & 8) ? exp(th[TH_LOG_JITTER]) : 0.0;
-  double G[kCalG], bv[kCalMax];
+  double S[kCalS], bv[kCalMax];
 #pragma unroll
-  for (int q = 0; q < kCalG; ++q) G[q] = 0.0;
+  for (int q = 0; q < kCalS; ++q) S[q] = 0.0;
 #pragma unroll
   for (int q = 0; q < kCalMax; ++q) bv[q] = 0.0;
   const double *mu = a.msorted + (size_t)r * a.ld;
@@ -552,80 +612,67 @@ __global__ void __launch_bounds__(256) k_calib(DevLib lib, CalibLaunch a) {
     if (!ob.mask[i]) continue;
     const double m = mu[i], d = ob.data[i], sg = ob.sigma[i];
     const double v = ns * ns * sg * sg + fc * fc * m * m + fd * fd * d * d + jt * jt;
-    const double w = 1.0 / v, res = d - m;
+    const double w = 1.0 / v;
+    const double q0 = m * m * w, r0 = m * (d - m) * w;
     const double x = ob.pix[i] * ob.calib_xs + ob.calib_x0;
-    double T[kCalMax];
-    T[0] = 1.0;
-    T[1] = x;
+    double t0 = 1.0, t1 = x;
+    S[0] += q0;
+    S[1] += q0 * x;
+    bv[0] += r0;
+    bv[1] += r0 * x;
 #pragma unroll
-    for (int q = 2; q < kCalMax; ++q) T[q] = 2.0 * x * T[q - 1] - T[q - 2];
-#pragma unroll
-    for (int p = 0, q = 0; p < kCalMax; ++p) {
-      const double Dp = m * T[p];
-      bv[p] += Dp * res * w;
-#pragma unroll
-      for (int u = p; u < kCalMax; ++u, ++q) G[q] += Dp * m * T[u] * w;
+    for (int k = 2; k < kCalS; ++k) {
+      const double t2 = 2.0 * x * t1 - t0;
+      S[k] += q0 * t2;
+      if (k < kCalMax) bv[k] += r0 * t2;
+      t0 = t1;
+      t1 = t2;
     }
   }
   // fixed-order reduction: each wave by a butterfly, then the four waves in order
 #pragma unroll
-  for (int q = 0; q < kCalG; ++q) G[q] = wave_reduce_sum(G[q]);
+  for (int q = 0; q < kCalS; ++q) S[q] = wave_reduce_sum(S[q]);
 #pragma unroll
   for (int q = 0; q < kCalMax; ++q) bv[q] = wave_reduce_sum(bv[q]);
   if (lane == 0) {
 #pragma unroll
-    for (int q = 0; q < kCalG; ++q) red[wv][q] = G[q];
+    for (int q = 0; q < kCalS; ++q) red[wv][q] = S[q];
 #pragma unroll
-    for (int q = 0; q < kCalMax; ++q) red[wv][kCalG + q] = bv[q];
+    for (int q = 0; q < kCalMax; ++q) red[wv][kCalS + q] = bv[q];
   }
   __syncthreads();
-  if (tid != 0) return;
-  double M[kCalMax][kCalMax], Gm[kCalMax][kCalMax], b[kCalMax];
-  for (int p = 0, q = 0; p < kCalMax; ++p)
-    for (int u = p; u < kCalMax; ++u, ++q) {
-      const double g = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
-      Gm[p][u] = Gm[u][p] = g;
-    }
-  for (int p = 0; p < nc; ++p) {
-    b[p] = (red[0][kCalG + p] + red[1][kCalG + p]) + (red[2][kCalG + p] + red[3][kCalG + p]);
-    for (int u = 0; u < nc; ++u) M[p][u] = Gm[p][u] + (p == u ? ob.calib_ivar[p] : 0.0);
+  for (int q = tid; q < kCalS + kCalMax; q += 256)
+    a.sums[(size_t)r * a.ld_sums + q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+}
+
+// One thread per sorted row: the row's solve (a kernel of its own, so that the unrolled
+// solve's registers do not limit the occupancy of the sums)
+__global__ void __launch_bounds__(64) k_calib_solve(CalibLaunch a) {
+  const int r = blockIdx.x * 64 + threadIdx.x;
+  if (r >= a.B_pad) return;
+  const PointRow &pr = a.rows[r];
+  if (pr.b < 0) return;
+  const DevObs &ob = a.obs_table[pr.obs];
+  if (ob.kind != 1 || ob.calib_mode == 0) return;
+  const double *sums = a.sums + (size_t)r * a.ld_sums;
+  double corr = 0.0;
+  switch (ob.calib_order + 1) {
+    case 1: corr = calib_solve<1>(sums, ob); break;
+    case 2: corr = calib_solve<2>(sums, ob); break;
+    case 3: corr = calib_solve<3>(sums, ob); break;
+    case 4: corr = calib_solve<4>(sums, ob); break;
+    case 5: corr = calib_solve<5>(sums, ob); break;
+    case 6: corr = calib_solve<6>(sums, ob); break;
+    case 7: corr = calib_solve<7>(sums, ob); break;
+    default: corr = calib_solve<8>(sums, ob); break;
   }
-  // Cholesky M = L L^T (in place, lower), then c = M^-1 b by two triangular solves
-  double logdet = 0.0;
-  for (int j = 0; j < nc; ++j) {
-    double s = M[j][j];
-    for (int k = 0; k < j; ++k) s -= M[j][k] * M[j][k];
-    const double ljj = sqrt(s);
-    M[j][j] = ljj;
-    logdet += 2.0 * log(ljj);
-    for (int i = j + 1; i < nc; ++i) {
-      double t = M[i][j];
-      for (int k = 0; k < j; ++k) t -= M[i][k] * M[j][k];
-      M[i][j] = t / ljj;
-    }
-  }
-  double y[kCalMax], c[kCalMax];
-  for (int i = 0; i < nc; ++i) {
-    double t = b[i];
-    for (int k = 0; k < i; ++k) t -= M[i][k] * y[k];
-    y[i] = t / M[i][i];
-  }
-  for (int i = nc - 1; i >= 0; --i) {
-    double t = y[i];
-    for (int k = i + 1; k < nc; ++k) t -= M[k][i] * c[k];
-    c[i] = t / M[i][i];
-  }
-  double bc = 0.0, cGc = 0.0;
-  for (int p = 0; p < nc; ++p) {
-    bc += b[p] * c[p];
-    for (int u = 0; u < nc; ++u) cGc += c[p] * Gm[p][u] * c[u];
-  }
-  const double corr = ob.calib_mode == 1 ? 0.5 * bc - 0.5 * logdet - ob.calib_lnsd : bc - 0.5 * cGc;
   if (a.logl) a.logl[pr.b] += corr;
 }
 
 hipError_t launch_calib(const DevLib &lib, const CalibLaunch &cl, hipStream_t s) {
+  if (cl.ld_sums < kCalS + kCalMax) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_calib, dim3(cl.B_pad), dim3(256), 0, s, lib, cl);
+  hipLaunchKernelGGL(k_calib_solve, dim3((cl.B_pad + 63) / 64), dim3(64), 0, s, cl);
   return hipGetLastError();
 }
 

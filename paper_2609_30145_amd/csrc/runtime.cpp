@@ -37,7 +37,7 @@ sps_status Workspace::create(const sps_library *L, int mb, int n_data, int n_fno
   gnoise = (double *)al(gb * 4 * 8);
   gbuf = (double *)al(gb * 16 * 8);
   mbuf = (double *)al(gb * (size_t)std::max(1, n_data) * 8);
-  ld_scr = std::max(3 * n_fnodes, 8 * n_data);
+  ld_scr = std::max(std::max(3 * n_fnodes, 8 * n_data), 24);   // also the calibration sums
   scr = (double *)al(gb * (size_t)std::max(1, ld_scr) * 8);
   dLl = (double *)al(gb * (size_t)std::max(1, g.n_line) * 8);
   G = al(gb * g.N_pad * 8 * 2);

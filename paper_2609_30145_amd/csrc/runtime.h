@@ -37,7 +37,7 @@ struct Workspace {
   double *gvec = nullptr, *gnoise = nullptr;
   double *gbuf = nullptr;        // adjoint per-point sums [B_pad][16]
   double *mbuf = nullptr;        // model at sorted rows [B_pad][n_data] (gradient pass)
-  double *scr = nullptr;         // adjoint per-node / per-pixel scratch [B_pad][ld_scr]
+  double *scr = nullptr;         // adjoint per-node / per-pixel scratch [B_pad][ld_scr]; calibration sums
   int ld_scr = 0;
   double *dLl = nullptr;         // adjoint d logL / d L_line [B_pad][n_line]
   void *G = nullptr;             // adjoint [B_pad][N_pad] float/double
