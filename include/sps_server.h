@@ -61,7 +61,7 @@ typedef struct {
 typedef struct {
   int64_t submitted, completed, rejected, cancelled, active, pending;
   int64_t ticks, evals;
-  double busy_s;             /* wall time with at least one active request */
+  double busy_s;             /* wall time with at least one batched launch in flight */
   double evals_per_s;        /* evals / busy_s */
   double mean_points_per_tick;
   double p50_latency_s[2], p99_latency_s[2];   /* [0] photometry, [1] spectra */

@@ -32,17 +32,71 @@ sps_status fail(sps_status code, const char *fmt, ...) {
 
 static int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+DeviceArena::~DeviceArena() {
+  if (base) (void)hipFree(base);
+}
+bool DeviceArena::init(size_t n) {
+  n = (n + 255) / 256 * 256;
+  if (hipMalloc((void **)&base, n) != hipSuccess) {
+    base = nullptr;
+    return false;
+  }
+  size = n;
+  free_blocks.clear();
+  free_blocks[0] = n;
+  return true;
+}
+void *DeviceArena::alloc(size_t n) {
+  n = (std::max<size_t>(n, 1) + 255) / 256 * 256;
+  for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+    if (it->second < n) continue;
+    const size_t off = it->first, len = it->second;
+    free_blocks.erase(it);
+    if (len > n) free_blocks[off + n] = len - n;
+    return base + off;
+  }
+  return nullptr;
+}
+void DeviceArena::free(void *p, size_t n) {
+  n = (std::max<size_t>(n, 1) + 255) / 256 * 256;
+  size_t off = (size_t)((char *)p - base);
+  auto nx = free_blocks.lower_bound(off);
+  if (nx != free_blocks.end() && off + n == nx->first) {   // merge with the block after
+    n += nx->second;
+    nx = free_blocks.erase(nx);
+  }
+  if (nx != free_blocks.begin()) {   // and with the block before
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second == off) {
+      off = pv->first;
+      n += pv->second;
+      free_blocks.erase(pv);
+    }
+  }
+  free_blocks[off] = n;
+}
+
 DeviceBuffers::~DeviceBuffers() { release(); }
 void DeviceBuffers::release() {
-  for (void *p : ptrs) (void)hipFree(p);
+  for (size_t k = 0; k < ptrs.size(); ++k) {
+    if (arena) arena->free(ptrs[k], sizes[k]);
+    else (void)hipFree(ptrs[k]);
+  }
   ptrs.clear();
+  sizes.clear();
   bytes = 0;
 }
 void *DeviceBuffers::alloc(size_t n) {
   if (n == 0) n = 16;
   void *p = nullptr;
-  if (hipMalloc(&p, n) != hipSuccess) return nullptr;
+  if (arena) {
+    p = arena->alloc(n);
+    if (!p) return nullptr;
+  } else if (hipMalloc(&p, n) != hipSuccess) {
+    return nullptr;
+  }
   ptrs.push_back(p);
+  sizes.push_back(n);
   bytes += (int64_t)n;
   return p;
 }
@@ -899,13 +953,15 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   const int mode = prec == 0 ? 0 : prec == 1 ? 1 : (prec == 2 || prec == 4 || prec == 6 || prec == 8) ? 2 : 3;
   const int MT = contract_mtile(prec);
   const int tf = contract_ktile_factor(prec);
-  hipError_t e = launch_keys(g, theta, g.P, B, w.keys, s);
+  int *ranks = B >= kRankKernelMinB ? w.ranks : nullptr;
+  hipError_t e = launch_keys(g, theta, g.P, B, w.keys, ranks, s);
   PrepLaunch pl;
   pl.theta = theta;
   pl.P = g.P;
   pl.B = B;
   pl.B_pad = B_pad;
   pl.keys = w.keys;
+  pl.ranks = ranks;
   pl.obs_table = obs_table;
   pl.point_obs = point_obs;
   pl.W = w.W;

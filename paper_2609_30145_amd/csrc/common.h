@@ -237,6 +237,12 @@ __device__ __forceinline__ void spec_span(const DevLib &lib, double lnpix_lo, do
 // list return at once (returns false).
 constexpr int kSpanTile = 64;          // model pixels per contraction N tile
 constexpr int kTileListMaxM = 1024;    // M tiles a tile list can hold
+// Ints of the tile-list buffer for up to Bp rows: the count, the pairs, then each 64-row
+// M tile's span in N tiles (lo, hi)
+__host__ __device__ inline size_t tile_list_ints(size_t Bp, int N_pad) {
+  const size_t m64 = (Bp + 63) / 64;
+  return 1 + m64 * (size_t)(N_pad / kSpanTile) + 2 * m64;
+}
 __device__ __forceinline__ bool span_block_tile(const int *__restrict__ list, int &mt, int &nt) {
   const int count = list[0];
   const int per = (count + 7) >> 3;

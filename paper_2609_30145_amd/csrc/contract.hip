@@ -391,26 +391,60 @@ __global__ void __launch_bounds__(256) k_contract_f64(ContractArgs a) {
 }
 
 // ---------------------------------------------------------------------------------
-// The tile list of a span-limited forward launch (common.h: span_block_tile).  One
-// workgroup: each M tile's span in N tiles from its rows' pixel spans, per-item counts
-// (N tiles in N-tile-major order, M tiles otherwise), a block-wide exclusive scan, and the
-// pairs written in order.
-__global__ void __launch_bounds__(256) k_tile_list(const PointRow *__restrict__ rows, int B_pad, int MT, int n_nt,
-                                                   int nt_major, int *__restrict__ list) {
+// The tile list of a span-limited forward launch (common.h: span_block_tile).
+// k_tile_span: one workgroup per M tile, one thread per row, the tile's span in N tiles
+// from its rows' pixel spans (one pixel of margin each side) by a min / max reduction.
+// k_tile_list, one workgroup: per-item counts (N tiles in N-tile-major order, M tiles
+// otherwise), a block-wide exclusive scan, and the pairs written in order.
+__global__ void __launch_bounds__(128) k_tile_span(const PointRow *__restrict__ rows, int MT, int n_nt,
+                                                   int *__restrict__ spans) {
+  __shared__ int s_lo[2], s_hi[2];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const PointRow &pr = rows[(size_t)blockIdx.x * MT + t];
+  int lo = INT_MAX, hi = -1;
+  if (pr.b >= 0 && pr.cov_n > 0) {
+    lo = max(pr.cov0 - 1, 0) / kSpanTile;
+    hi = min(pr.cov0 + pr.cov_n, n_nt * kSpanTile - 1) / kSpanTile;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o));
+    hi = max(hi, __shfl_xor(hi, o));
+  }
+  if (lane == 0) {
+    s_lo[wv] = lo;
+    s_hi[wv] = hi;
+  }
+  __syncthreads();
+  if (t == 0) {
+    spans[2 * blockIdx.x] = MT > 64 ? min(s_lo[0], s_lo[1]) : s_lo[0];
+    spans[2 * blockIdx.x + 1] = MT > 64 ? max(s_hi[0], s_hi[1]) : s_hi[0];
+  }
+}
+
+// (spans == NULL: small batches, whose rows the list kernel reduces itself, one launch less)
+__global__ void __launch_bounds__(256) k_tile_list(const PointRow *__restrict__ rows, const int *__restrict__ spans,
+                                                   int B_pad, int MT, int n_nt, int nt_major, int *__restrict__ list) {
   __shared__ int lo[kTileListMaxM], hi[kTileListMaxM];
   __shared__ int s_wsum[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n_mt = B_pad / MT;
-  for (int m = tid; m < n_mt; m += 256) {
-    lo[m] = INT_MAX;
-    hi[m] = -1;
-  }
-  __syncthreads();
-  for (int r = tid; r < B_pad; r += 256) {
-    const PointRow &pr = rows[r];
-    if (pr.b >= 0 && pr.cov_n > 0) {   // one pixel of margin each side
-      atomicMin(&lo[r / MT], max(pr.cov0 - 1, 0) / kSpanTile);
-      atomicMax(&hi[r / MT], min(pr.cov0 + pr.cov_n, n_nt * kSpanTile - 1) / kSpanTile);
+  if (spans) {
+    for (int m = tid; m < n_mt; m += 256) {
+      lo[m] = spans[2 * m];
+      hi[m] = spans[2 * m + 1];
+    }
+  } else {
+    for (int m = tid; m < n_mt; m += 256) {
+      lo[m] = INT_MAX;
+      hi[m] = -1;
+    }
+    __syncthreads();
+    for (int r = tid; r < B_pad; r += 256) {
+      const PointRow &pr = rows[r];
+      if (pr.b >= 0 && pr.cov_n > 0) {   // one pixel of margin each side
+        atomicMin(&lo[r / MT], max(pr.cov0 - 1, 0) / kSpanTile);
+        atomicMax(&hi[r / MT], min(pr.cov0 + pr.cov_n, n_nt * kSpanTile - 1) / kSpanTile);
+      }
     }
   }
   __syncthreads();
@@ -447,8 +481,12 @@ __global__ void __launch_bounds__(256) k_tile_list(const PointRow *__restrict__ 
 
 hipError_t launch_tile_list(const PointRow *rows, int B_pad, int MT, int n_nt, bool nt_major, int *list,
                             hipStream_t s) {
-  if (B_pad / MT > kTileListMaxM || n_nt > 0xffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_tile_list, dim3(1), dim3(256), 0, s, rows, B_pad, MT, n_nt, nt_major ? 1 : 0, list);
+  if (B_pad / MT > kTileListMaxM || n_nt > 0xffff || (MT != 64 && MT != 128) || B_pad % MT) return hipErrorInvalidValue;
+  // large batches: the M tiles' spans by a kernel of their own, stored after the largest
+  // list these rows can make (tile_list_ints)
+  int *spans = B_pad >= kRankKernelMinB ? list + 1 + (size_t)((B_pad + 63) / 64) * n_nt : nullptr;
+  if (spans) hipLaunchKernelGGL(k_tile_span, dim3(B_pad / MT), dim3(MT), 0, s, rows, MT, n_nt, spans);
+  hipLaunchKernelGGL(k_tile_list, dim3(1), dim3(256), 0, s, rows, spans, B_pad, MT, n_nt, nt_major ? 1 : 0, list);
   return hipGetLastError();
 }
 

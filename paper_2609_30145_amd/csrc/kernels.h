@@ -8,6 +8,7 @@ struct PrepLaunch {
   const double *theta;
   int P, B, B_pad;
   const double *keys;        // batch-ordering keys from launch_keys
+  const int *ranks;          // each point's row in the key order, from launch_keys, or NULL
   const DevObs *obs_table;
   const int *point_obs;
   void *W, *Wlo;
@@ -23,7 +24,11 @@ struct PrepLaunch {
 
 size_t prep_smem_bytes(const DevLib &lib, int mode);   // mode as PrepLaunch::mode
 // batch-ordering keys (the weight builder ranks the points by them)
-hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, hipStream_t s);
+// batch-ordering keys and, when ranks is not NULL, each point's rank among them (ties by
+// index; the weight builder ranks its own point otherwise)
+constexpr int kRankKernelMinB = 2048;   // batches from this size rank in a kernel of their own
+hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, int *ranks,
+                       hipStream_t s);
 // weights, per-row K-tile occupancy bits and per-point rows, each point at its rank
 hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s);
 

@@ -36,6 +36,52 @@ __global__ void __launch_bounds__(256) k_keys(DevLib lib, const double *__restri
   if (b < B) keys[b] = sort_key(lib, theta + (size_t)b * P);
 }
 
+// Rank of every point in the key order, ties by batch index: rank[b] = #{j : key_j < key_b
+// or (key_j == key_b and j < b)}.  A workgroup takes 64 points (one per lane); the batch's
+// keys stream through LDS 4096 at a time and each wave compares its lanes' keys against its
+// quarter of every chunk (the keys are read once per 64 points, not once per point).  For
+// large batches only (kRankKernelMinB): below that the weight builder ranks its own point,
+// which saves a launch.
+__global__ void __launch_bounds__(256) k_rank(const double *__restrict__ keys, int B, int *__restrict__ ranks) {
+  constexpr int CH = 4096;   // keys per chunk in LDS (32 KB), sixteen loads per thread in flight
+  __shared__ double s_k[CH];
+  __shared__ int s_c[4][64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int b = blockIdx.x * 64 + lane;
+  const double my = keys[min(b, B - 1)];
+  int c = 0;
+  for (int j0 = 0; j0 < B; j0 += CH) {
+    double v[CH / 256];
+#pragma unroll
+    for (int q = 0; q < CH / 256; ++q) v[q] = keys[min(j0 + tid + 256 * q, B - 1)];
+#pragma unroll
+    for (int q = 0; q < CH / 256; ++q) s_k[tid + 256 * q] = v[q];
+    __syncthreads();
+    // wave wv compares its lanes' keys with the chunk's keys wv, wv + 4, wv + 8, ...
+    const int n = min(CH, B - j0);
+    const int full = n & ~63;
+    for (int u0 = wv * 16; u0 < full; u0 += 64) {
+      double kk[16];
+#pragma unroll
+      for (int w = 0; w < 16; ++w) kk[w] = s_k[u0 + w];
+#pragma unroll
+      for (int w = 0; w < 16; ++w) {
+        const int j = j0 + u0 + w;
+        c += (kk[w] < my) || (kk[w] == my && j < b);
+      }
+    }
+    for (int u = full + wv; u < n; u += 4) {
+      const double k = s_k[u];
+      const int j = j0 + u;
+      c += (k < my) || (k == my && j < b);
+    }
+    __syncthreads();
+  }
+  s_c[wv][lane] = c;
+  __syncthreads();
+  if (wv == 0 && b < B) ranks[b] = (s_c[0][lane] + s_c[1][lane]) + (s_c[2][lane] + s_c[3][lane]);
+}
+
 // ---------------------------------------------------------------------------------
 // Weight builder.  One workgroup per sorted row.
 // ---------------------------------------------------------------------------------
@@ -96,6 +142,7 @@ struct PrepArgs {
   const double *theta;
   int P, B, B_pad;
   const double *keys;       // [B] batch-ordering keys (k_keys)
+  const int *ranks;         // [B] each point's row in the key order (k_rank), or NULL: ranked here
   const DevObs *obs_table;
   const int *point_obs;     // [B] observation slot per point, NULL = slot 0
   void *W;                  // F64/F32: [B_pad][K_pad]; 16-bit: hi plane
@@ -313,7 +360,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   const int P = a.P, nt2 = prep_tab_len(lib) >> 1, nk8 = K_pad >> 3;
   const double2 *tab2 = (const double2 *)lib.prep_tab;
   const uint4 *ke4 = (const uint4 *)lib.kexp16;
-  double vt[UT], kq[UQ];
+  double vt[UT];
   double2 vb[UB];
   uint4 vk[UK];
 #pragma unroll
@@ -324,9 +371,12 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
 #pragma unroll
     for (int u = 0; u < UK; ++u) vk[u] = ke4[min(tid + 256 * u, nk8 - 1)];
   }
+  double kq[UQ], my = 0.0;
+  if (!a.ranks) {   // small batches rank themselves (no k_rank launch)
 #pragma unroll
-  for (int u = 0; u < UQ; ++u) kq[u] = a.keys[min(tid + 256 * u, a.B - 1)];
-  const double my = a.keys[b];
+    for (int u = 0; u < UQ; ++u) kq[u] = a.keys[min(tid + 256 * u, a.B - 1)];
+    my = a.keys[b];
+  }
 
   // cosmology (Sec. 2.6): D_C by composite Gauss-Legendre in u = (1+z')^-1/2, where
   // the integrand 2 / sqrt(Om + OL u^6) is smooth (waves 0-2); t_univ in closed form
@@ -407,7 +457,11 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   }
   for (int k = tid; k < K_pad; k += 256) wacc[k] = (Acc)0;
   if (tid < 64) s_bits[tid] = 0u;
-  {
+  int r;   // the point's row: its rank in the key order, ties by index
+  if (a.ranks) {
+    r = a.ranks[b];
+    __syncthreads();
+  } else {
     int c = 0;
 #pragma unroll
     for (int u = 0; u < UQ; ++u) {
@@ -426,9 +480,9 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     }
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
     if (lane == 0) s_rank[wv] = c;
+    __syncthreads();
+    r = (s_rank[0] + s_rank[1]) + (s_rank[2] + s_rank[3]);
   }
-  __syncthreads();
-  const int r = (s_rank[0] + s_rank[1]) + (s_rank[2] + s_rank[3]);
   const size_t rowoff = (size_t)r * K_pad;
   const double dc = kC_kms / lib.H0 * (1.0 - u0) * ((s_part[0] + s_part[1]) + (s_part[2] + s_part[3])) * kMpc_cm;
   // the point's observation kind and filter span, requested here and first used in
@@ -844,8 +898,10 @@ size_t prep_smem_bytes(const DevLib &lib, int mode) {
   return sizeof(double) * (size_t)PrepSmem(lib, mode).total;
 }
 
-hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, hipStream_t s) {
+hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, int *ranks,
+                       hipStream_t s) {
   hipLaunchKernelGGL(k_keys, dim3((B + 255) / 256), dim3(256), 0, s, lib, theta, P, B, keys);
+  if (ranks) hipLaunchKernelGGL(k_rank, dim3((B + 63) / 64), dim3(256), 0, s, keys, B, ranks);
   return hipGetLastError();
 }
 
@@ -853,6 +909,7 @@ hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s) {
   PrepArgs a;
   a.theta = pl.theta;
   a.keys = pl.keys;
+  a.ranks = pl.ranks;
   a.P = pl.P;
   a.B = pl.B;
   a.B_pad = pl.B_pad;

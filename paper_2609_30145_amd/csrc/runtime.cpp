@@ -24,11 +24,12 @@ sps_status Workspace::create(const sps_library *L, int mb, int n_data, int n_fno
     return p;
   };
   keys = (double *)al(Bp * 8);
+  ranks = (int *)al(Bp * 4);
   W = al(Bp * g.K_pad * 8);
   rowmask = (uint32_t *)al(Bp * mask_words * 4);
   rows = (PointRow *)al(Bp * sizeof(PointRow));
   F = al(Bp * g.N_pad * 8);
-  tiles = (int *)al(((Bp + 63) / 64 * (g.N_pad / kSpanTile) + 1) * 4);
+  tiles = (int *)al(tile_list_ints(Bp, g.N_pad) * 4);
   const size_t gb = forward_only ? 1 : Bp;   // gradient-pass buffers
   Yatt = al(gb * g.N_pad * 8);
   Lline = (double *)al(Bp * (size_t)std::max(1, g.n_line) * 8);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/sps.h"
@@ -13,9 +14,24 @@ namespace sps {
 sps_status fail(sps_status code, const char *fmt, ...);
 
 // Owns a set of device allocations.
+// A host-side first-fit sub-allocator over one device allocation: alloc and free make no
+// HIP call (so they never wait on running kernels); blocks are 256-byte aligned.  Used by
+// one thread at a time.
+struct DeviceArena {
+  char *base = nullptr;
+  size_t size = 0;
+  std::map<size_t, size_t> free_blocks;   // offset -> length
+  ~DeviceArena();
+  bool init(size_t n);
+  void *alloc(size_t n);
+  void free(void *p, size_t n);
+};
+
 struct DeviceBuffers {
   std::vector<void *> ptrs;
+  std::vector<size_t> sizes;
   int64_t bytes = 0;
+  DeviceArena *arena = nullptr;   // set: blocks come from (and return to) the arena
   ~DeviceBuffers();
   void release();
   void *alloc(size_t n);
@@ -27,11 +43,13 @@ struct Workspace {
   DeviceBuffers mem;
   int max_batch = 0, B_pad_max = 0, mask_words = 0;
   double *keys = nullptr;       // batch-ordering keys [B_pad]
+  int *ranks = nullptr;          // each point's row in the key order [B_pad]
   void *W = nullptr;             // B_pad * K_pad * 8 bytes
   uint32_t *rowmask = nullptr;
   PointRow *rows = nullptr;
   void *F = nullptr, *Yatt = nullptr;   // B_pad * N_pad * 8 bytes each
-  int *tiles = nullptr;          // the contraction's tile list (k_tile_list): 1 + (B_pad/64) * (N_pad/64) ints
+  int *tiles = nullptr;          // the contraction's tile list (k_tile_list): 1 + (B_pad/64) * (N_pad/64) ints,
+                                 // then each M tile's span in N tiles (2 * B_pad/64 ints)
   double *Lline = nullptr;
   double *WQ = nullptr;          // nebular continuum: photon-weighted masses [B_pad][nebular ages]
   double *gvec = nullptr, *gnoise = nullptr;

@@ -54,6 +54,7 @@ struct sps_server {
   std::mutex mu;
   std::condition_variable cv, done_cv;
   bool stop = false;
+  bool broken = false;   // the scheduler stopped after a device error
   std::thread thr;
   uint64_t next_ticket = 1;
   std::deque<std::shared_ptr<Request>> pending;
@@ -70,18 +71,44 @@ struct sps_server {
   Workspace ws;
   hipStream_t s_compute = nullptr, s_copy = nullptr;
   DevObs *d_obs_table = nullptr;
-  DevReq *d_reqs = nullptr, *h_reqs = nullptr;
+  DevReq *d_reqs = nullptr;
   double *d_theta_all = nullptr, *d_logl_all = nullptr;
   int *d_point_obs = nullptr;
   double *d_thr = nullptr;   // per-request acceptance thresholds of a tick
   DeviceBuffers mem;
+  DeviceArena arena;         // the requests' device state, within the HBM budget
+  // pipelined ticks (GPU executor): at most kInFlight enqueued; tick t uses host buffers
+  // t mod kInFlight (its request descriptors, and the pinned staging its finishing
+  // requests' results are copied into)
+  static constexpr int kInFlight = 2;
+  DevReq *h_reqs2[kInFlight] = {nullptr, nullptr};
+  double *h_stage[kInFlight] = {nullptr, nullptr};
+  hipEvent_t ev_tick[kInFlight] = {nullptr, nullptr};
+  hipEvent_t ev_adm = nullptr;
+  struct Leaving {
+    std::shared_ptr<Request> r;
+    size_t off;      // results at h_stage[buf] + off (theta rows, then logl)
+    bool results;    // false: cancelled, released without results
+  };
+  struct TickRec {
+    int buf = 0;
+    std::vector<Leaving> leaving;
+  };
+  std::deque<TickRec> inflight;
+  int64_t tick_no = 0;
+  Clock::time_point busy_since;
   // mock buffers
   std::vector<double> m_theta_all, m_logl_all;
 
   void run();
-  bool admit_one(std::shared_ptr<Request> &r);
+  void run_mock();
+  void run_gpu();
+  int admit_one(std::shared_ptr<Request> &r);   // 1 admitted, 0 no room yet, -1 failed
   void release_device(Request &r);
   bool tick();
+  bool enqueue_tick();
+  void finish_tick(TickRec &t, bool ok);
+  void admission(std::unique_lock<std::mutex> &lk);
   double mock_logl(const double *th) const;
 };
 
@@ -96,23 +123,26 @@ double sps_server::mock_logl(const double *th) const {
   return s;
 }
 
-bool sps_server::admit_one(std::shared_ptr<Request> &r) {
+int sps_server::admit_one(std::shared_ptr<Request> &r) {
   r->slot = free_slots.back();
   free_slots.pop_back();
-  if (mock) return true;
-  if (hipSetDevice(lib->device) != hipSuccess) return false;
+  if (mock) return 1;
+  // device state from the arena (no HIP allocation call); uploads on the copy stream, which
+  // the compute stream waits for (an event) before the next tick: the host never waits
+  r->mem.arena = &arena;
   r->d_theta = (double *)r->mem.alloc(r256((size_t)r->B * P * 8));
   r->d_logl = (double *)r->mem.alloc(r256((size_t)r->B * 8));
-  if (!r->d_theta || !r->d_logl) return false;
+  if (!r->d_theta || !r->d_logl) return 0;
+  const sps_status st = upload_obs(r->obs, r->dobs, r->mem, s_copy);
+  if (st == SPS_E_NOMEM) return 0;   // the arena is fragmented: retry when blocks come back
+  if (st != SPS_OK) return -1;
   if (hipMemcpyAsync(r->d_theta, r->theta.data(), (size_t)r->B * P * 8, hipMemcpyHostToDevice, s_copy) !=
       hipSuccess)
-    return false;
-  if (upload_obs(r->obs, r->dobs, r->mem, s_copy) != SPS_OK) return false;
+    return -1;
   if (hipMemcpyAsync(d_obs_table + r->slot, &r->dobs, sizeof(DevObs), hipMemcpyHostToDevice, s_copy) !=
       hipSuccess)
-    return false;
-  // the compute stream only touches this request after the copy stream drains
-  return hipStreamSynchronize(s_copy) == hipSuccess;
+    return -1;
+  return 1;
 }
 
 void sps_server::release_device(Request &r) {
@@ -122,7 +152,7 @@ void sps_server::release_device(Request &r) {
   r.d_theta = r.d_logl = nullptr;
 }
 
-// One batched evaluation of every active request's current stage.
+// One batched evaluation of every active request's current stage (host-only executor).
 bool sps_server::tick() {
   const int n = (int)active.size();
   int total = 0;
@@ -181,65 +211,74 @@ bool sps_server::tick() {
     }
     return true;
   }
-  std::copy(reqs.begin(), reqs.end(), h_reqs);
-  (void)hipGetLastError();   // drop a stale code from an unrelated earlier HIP call of this thread
-  hipError_t e = hipMemcpyAsync(d_reqs, h_reqs, sizeof(DevReq) * n, hipMemcpyHostToDevice, s_compute);
-  if (e == hipSuccess) e = launch_propose(d_reqs, n, P, n_sfh, box, d_theta_all, d_point_obs, total, s_compute);
-  if (e != hipSuccess) return false;
-  if (launch_forward(lib, ws, d_obs_table, d_point_obs, d_theta_all, total, desc.precision, d_logl_all, nullptr, 1,
-                     false, 1, nullptr, nullptr, s_compute) != SPS_OK)
-    return false;
-  e = launch_update(d_reqs, n, P, d_theta_all, d_logl_all, d_thr, total, s_compute);
-  if (e == hipSuccess) e = hipStreamSynchronize(s_compute);
-  return e == hipSuccess;
+  return false;   // the GPU executor enqueues its ticks (enqueue_tick)
 }
 
 void sps_server::run() {
-  if (!mock) (void)hipSetDevice(lib->device);
+  if (mock) run_mock();
+  else run_gpu();
+}
+
+// Admission, FIFO while the budget, the point capacity, the slots and (GPU) the arena allow.
+// Called with the lock held; drops it around the uploads.
+void sps_server::admission(std::unique_lock<std::mutex> &lk) {
+  bool uploaded = false;
+  while (!pending.empty()) {
+    auto r = pending.front();
+    if (r->cancel) {
+      pending.pop_front();
+      r->state = SPS_REQ_CANCELLED;
+      r->t_done = seconds_since(t0);
+      ++n_cancelled;
+      done_cv.notify_all();
+      continue;
+    }
+    if (in_use + r->bytes > desc.hbm_budget_bytes || active_points + r->B > desc.max_points || free_slots.empty())
+      break;
+    pending.pop_front();
+    lk.unlock();
+    const int ok = admit_one(r);
+    lk.lock();
+    if (ok == 0) {   // no contiguous room in the arena yet: back to the head of the queue
+      release_device(*r);
+      pending.push_front(r);
+      break;
+    }
+    in_use += r->bytes;
+    peak = std::max(peak, in_use);
+    active_points += r->B;
+    r->t_admit = seconds_since(t0);
+    const double qd = r->t_admit - r->t_submit;
+    queue_sum += qd;
+    queue_max = std::max(queue_max, qd);
+    if (ok < 0) {
+      release_device(*r);
+      in_use -= r->bytes;
+      active_points -= r->B;
+      r->state = SPS_REQ_FAILED;
+      r->t_done = r->t_admit;
+      done_cv.notify_all();
+      continue;
+    }
+    uploaded = true;
+    r->state = SPS_REQ_ACTIVE;
+    active.push_back(r);
+  }
+  if (uploaded && !mock) {   // the next tick's kernels wait for the uploads on the GPU
+    if (hipEventRecord(ev_adm, s_copy) != hipSuccess || hipStreamWaitEvent(s_compute, ev_adm, 0) != hipSuccess)
+      (void)hipStreamSynchronize(s_copy);
+  }
+}
+
+void sps_server::run_mock() {
   std::unique_lock<std::mutex> lk(mu);
   while (!stop) {
-    // ---- admission: FIFO while the budget, the point capacity and the slots allow
-    while (!pending.empty()) {
-      auto r = pending.front();
-      if (r->cancel) {
-        pending.pop_front();
-        r->state = SPS_REQ_CANCELLED;
-        r->t_done = seconds_since(t0);
-        ++n_cancelled;
-        done_cv.notify_all();
-        continue;
-      }
-      if (in_use + r->bytes > desc.hbm_budget_bytes || active_points + r->B > desc.max_points ||
-          free_slots.empty())
-        break;
-      pending.pop_front();
-      in_use += r->bytes;
-      peak = std::max(peak, in_use);
-      active_points += r->B;
-      lk.unlock();
-      const bool ok = admit_one(r);
-      lk.lock();
-      r->t_admit = seconds_since(t0);
-      const double qd = r->t_admit - r->t_submit;
-      queue_sum += qd;
-      queue_max = std::max(queue_max, qd);
-      if (!ok) {
-        release_device(*r);
-        in_use -= r->bytes;
-        active_points -= r->B;
-        r->state = SPS_REQ_FAILED;
-        r->t_done = r->t_admit;
-        done_cv.notify_all();
-        continue;
-      }
-      r->state = SPS_REQ_ACTIVE;
-      active.push_back(r);
-    }
+    admission(lk);
     if (active.empty()) {
       cv.wait_for(lk, std::chrono::milliseconds(2));
       continue;
     }
-    // ---- one batched launch of all active requests
+    // ---- one batched evaluation of all active requests
     const auto tb = Clock::now();
     const int points = (int)active_points;
     lk.unlock();
@@ -256,11 +295,6 @@ void sps_server::run() {
       r->stage += 1;
       const bool finished = r->stage > r->n_iter;
       if (!ok || r->cancel || finished) {
-        if (ok && finished && !r->cancel && !mock) {
-          if (hipMemcpy(r->theta.data(), r->d_theta, (size_t)r->B * P * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-              hipMemcpy(r->logl.data(), r->d_logl, (size_t)r->B * 8, hipMemcpyDeviceToHost) != hipSuccess)
-            r->state = SPS_REQ_FAILED;
-        }
         release_device(*r);
         in_use -= r->bytes;
         active_points -= r->B;
@@ -269,7 +303,7 @@ void sps_server::run() {
         else if (r->cancel) {
           r->state = SPS_REQ_CANCELLED;
           ++n_cancelled;
-        } else if (r->state != SPS_REQ_FAILED) {
+        } else {
           r->state = SPS_REQ_DONE;
           ++n_completed;
           lat[r->kind].push_back(r->t_done - r->t_submit);
@@ -281,11 +315,172 @@ void sps_server::run() {
     active.swap(keep);
     done_cv.notify_all();
   }
-  // shutdown: everything not finished is cancelled
   for (auto &r : active) {
     release_device(*r);
     r->state = SPS_REQ_CANCELLED;
     ++n_cancelled;
+  }
+  active.clear();
+  for (auto &r : pending) {
+    r->state = SPS_REQ_CANCELLED;
+    ++n_cancelled;
+  }
+  pending.clear();
+  done_cv.notify_all();
+}
+
+// Enqueues one tick over every active request on the compute stream (no host wait): the
+// request descriptors from pinned buffer t mod kInFlight, proposals, the batched forward +
+// logL, the acceptance update; requests at their last stage leave the batch, their results
+// copied after the update into that tick's pinned staging.  Called without the lock (the
+// active list changes on this thread only); the bookkeeping after the launches takes it.
+bool sps_server::enqueue_tick() {
+  const int buf = (int)(tick_no % kInFlight);
+  const int n = (int)active.size();
+  DevReq *hr = h_reqs2[buf];
+  int total = 0;
+  for (int q = 0; q < n; ++q) {
+    Request &r = *active[q];
+    hr[q].theta_cur = r.d_theta;
+    hr[q].logl_cur = r.d_logl;
+    hr[q].seed = r.seed;
+    hr[q].off = total;
+    hr[q].B = r.B;
+    hr[q].stage = r.stage;
+    hr[q].slot = r.slot;
+    total += r.B;
+  }
+  (void)hipGetLastError();   // drop a stale code from an unrelated earlier HIP call of this thread
+  hipError_t e = hipMemcpyAsync(d_reqs, hr, sizeof(DevReq) * n, hipMemcpyHostToDevice, s_compute);
+  if (e == hipSuccess) e = launch_propose(d_reqs, n, P, n_sfh, box, d_theta_all, d_point_obs, total, s_compute);
+  if (e != hipSuccess) return false;
+  if (launch_forward(lib, ws, d_obs_table, d_point_obs, d_theta_all, total, desc.precision, d_logl_all, nullptr, 1,
+                     false, 1, nullptr, nullptr, s_compute) != SPS_OK)
+    return false;
+  e = launch_update(d_reqs, n, P, d_theta_all, d_logl_all, d_thr, total, s_compute);
+  std::lock_guard<std::mutex> g(mu);
+  TickRec t;
+  t.buf = buf;
+  size_t off = 0;
+  std::vector<std::shared_ptr<Request>> keep;
+  for (auto &r : active) {
+    r->evals += r->B;
+    r->stage += 1;
+    if (r->stage > r->n_iter) {
+      double *st = h_stage[buf] + off;
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(st, r->d_theta, (size_t)r->B * P * 8, hipMemcpyDeviceToHost, s_compute);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(st + (size_t)r->B * P, r->d_logl, (size_t)r->B * 8, hipMemcpyDeviceToHost, s_compute);
+      t.leaving.push_back({r, off, true});
+      off += (size_t)r->B * (P + 1);
+      active_points -= r->B;   // no later tick holds its points (its memory stays until this one ends)
+    } else {
+      keep.push_back(r);
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(ev_tick[buf], s_compute);
+  if (inflight.empty()) busy_since = Clock::now();
+  active.swap(keep);
+  inflight.push_back(std::move(t));
+  ++n_ticks;
+  ++tick_no;
+  points_sum += total;
+  n_evals += total;
+  return e == hipSuccess;
+}
+
+// The oldest tick has completed (ok) or the stream failed: its leaving requests finish and
+// their device memory and slots return (their points left the batch when they did).
+// Called with the lock held.
+void sps_server::finish_tick(TickRec &t, bool ok) {
+  for (auto &lv : t.leaving) {
+    Request &r = *lv.r;
+    if (ok && lv.results) {
+      const double *st = h_stage[t.buf] + lv.off;
+      std::copy(st, st + (size_t)r.B * P, r.theta.data());
+      std::copy(st + (size_t)r.B * P, st + (size_t)r.B * (P + 1), r.logl.data());
+    }
+    release_device(r);
+    in_use -= r.bytes;
+    r.t_done = seconds_since(t0);
+    if (!ok) {
+      r.state = SPS_REQ_FAILED;
+    } else if (!lv.results) {
+      r.state = SPS_REQ_CANCELLED;
+      ++n_cancelled;
+    } else {
+      r.state = SPS_REQ_DONE;
+      ++n_completed;
+      lat[r.kind].push_back(r.t_done - r.t_submit);
+    }
+  }
+}
+
+void sps_server::run_gpu() {
+  (void)hipSetDevice(lib->device);
+  std::unique_lock<std::mutex> lk(mu);
+  bool failed = false;
+  while (!stop && !failed) {
+    admission(lk);
+    // cancelled requests leave the batch; a tick in flight may still read their state, so
+    // they are released with the newest one
+    std::vector<std::shared_ptr<Request>> keep;
+    for (auto &r : active) {
+      if (!r->cancel) {
+        keep.push_back(r);
+        continue;
+      }
+      active_points -= r->B;
+      if (!inflight.empty()) {
+        inflight.back().leaving.push_back({r, 0, false});
+      } else {
+        TickRec t0r;
+        t0r.leaving.push_back({r, 0, false});
+        finish_tick(t0r, true);
+      }
+    }
+    active.swap(keep);
+    if (!active.empty() && (int)inflight.size() < kInFlight) {
+      lk.unlock();
+      const bool ok = enqueue_tick();
+      lk.lock();
+      if (!ok) failed = true;
+      continue;
+    }
+    if (!inflight.empty()) {
+      const hipEvent_t ev = ev_tick[inflight.front().buf];
+      lk.unlock();
+      const bool ok = hipEventSynchronize(ev) == hipSuccess;
+      lk.lock();
+      TickRec t = std::move(inflight.front());
+      inflight.pop_front();
+      if (inflight.empty()) busy += seconds_since(busy_since);
+      finish_tick(t, ok);
+      if (!ok) failed = true;
+      done_cv.notify_all();
+      continue;
+    }
+    cv.wait_for(lk, std::chrono::milliseconds(2));
+  }
+  broken = failed;
+  // shutdown (or a failed stream): drain the GPU; ticks in flight finish their requests
+  // (failed if the stream failed); everything else is cancelled
+  lk.unlock();
+  const bool drained = hipStreamSynchronize(s_compute) == hipSuccess && !failed;
+  lk.lock();
+  while (!inflight.empty()) {
+    finish_tick(inflight.front(), drained);
+    inflight.pop_front();
+    if (inflight.empty()) busy += seconds_since(busy_since);
+  }
+  for (auto &r : active) {
+    release_device(*r);
+    in_use -= r->bytes;
+    active_points -= r->B;
+    r->state = failed ? SPS_REQ_FAILED : SPS_REQ_CANCELLED;
+    if (!failed) ++n_cancelled;
+    r->t_done = seconds_since(t0);
   }
   active.clear();
   for (auto &r : pending) {
@@ -343,7 +538,15 @@ extern "C" sps_status sps_server_create(const sps_library *L, const sps_server_d
     S->d_point_obs = (int *)S->mem.alloc((size_t)d->max_points * 4);
     S->d_thr = (double *)S->mem.alloc(sizeof(double) * d->max_active);
     ok = ok && S->d_obs_table && S->d_reqs && S->d_theta_all && S->d_logl_all && S->d_point_obs && S->d_thr;
-    ok = ok && hipHostMalloc((void **)&S->h_reqs, sizeof(DevReq) * d->max_active, hipHostMallocDefault) == hipSuccess;
+    for (int k = 0; k < sps_server::kInFlight; ++k) {
+      ok = ok && hipHostMalloc((void **)&S->h_reqs2[k], sizeof(DevReq) * d->max_active, hipHostMallocDefault) ==
+                     hipSuccess;
+      ok = ok && hipHostMalloc((void **)&S->h_stage[k], (size_t)d->max_points * (S->P + 1) * 8,
+                               hipHostMallocDefault) == hipSuccess;
+      ok = ok && hipEventCreateWithFlags(&S->ev_tick[k], hipEventDisableTiming) == hipSuccess;
+    }
+    ok = ok && hipEventCreateWithFlags(&S->ev_adm, hipEventDisableTiming) == hipSuccess;
+    ok = ok && S->arena.init((size_t)d->hbm_budget_bytes + (64u << 10));   // + slack for block rounding
     if (!ok) {
       sps_server_destroy(S);
       return st != SPS_OK ? st : fail(SPS_E_NOMEM, "server allocation failed");
@@ -391,6 +594,7 @@ extern "C" sps_status sps_submit(sps_server *S, const sps_request *q, uint64_t *
   r->bytes = obs_device_bytes(r->obs) + (int64_t)r256((size_t)q->B * S->P * 8) + (int64_t)r256((size_t)q->B * 8);
   std::lock_guard<std::mutex> g(S->mu);
   if (S->stop) return fail(SPS_E_STATE, "server is shutting down");
+  if (S->broken) return fail(SPS_E_HIP, "the server stopped after a device error");
   if (r->bytes > S->desc.hbm_budget_bytes) {
     ++S->n_rejected;
     return fail(SPS_E_BUDGET, "request needs %lld bytes, budget is %lld", (long long)r->bytes,
@@ -529,7 +733,12 @@ extern "C" void sps_server_destroy(sps_server *S) {
     (void)hipSetDevice(S->lib->device);
     if (S->s_compute) (void)hipStreamDestroy(S->s_compute);
     if (S->s_copy) (void)hipStreamDestroy(S->s_copy);
-    if (S->h_reqs) (void)hipHostFree(S->h_reqs);
+    for (int k = 0; k < sps_server::kInFlight; ++k) {
+      if (S->h_reqs2[k]) (void)hipHostFree(S->h_reqs2[k]);
+      if (S->h_stage[k]) (void)hipHostFree(S->h_stage[k]);
+      if (S->ev_tick[k]) (void)hipEventDestroy(S->ev_tick[k]);
+    }
+    if (S->ev_adm) (void)hipEventDestroy(S->ev_adm);
   }
   delete S;
 }

@@ -59,10 +59,9 @@ size_t static_scratch_bytes(const DevLib &g, int B, int prec) {
   const int mask_words = (g.K_pad / kKTile + 31) / 32;
   const size_t w_el = prec == SPS_FP64 ? 8 : 4;   // 16-bit paths: hi and residual planes
   const size_t f_el = prec == SPS_FP64 ? 8 : 4;
-  return align256(Bp * 8) + align256(Bp * g.K_pad * w_el) + align256(Bp * mask_words * 4) +
+  return align256(Bp * 8) + align256(Bp * 4) + align256(Bp * g.K_pad * w_el) + align256(Bp * mask_words * 4) +
          align256(Bp * sizeof(PointRow)) + align256(Bp * g.N_pad * f_el) +
-         align256(Bp * (size_t)(g.n_line > 0 ? g.n_line : 1) * 8) +
-         align256(((Bp + 63) / 64 * (g.N_pad / kSpanTile) + 1) * 4) +
+         align256(Bp * (size_t)(g.n_line > 0 ? g.n_line : 1) * 8) + align256(tile_list_ints(Bp, g.N_pad) * 4) +
          align256(Bp * (size_t)(g.has_cont ? g.neb_a1 - g.neb_a0 : 1) * 8);
 }
 
@@ -100,12 +99,13 @@ extern "C" sps_status sps_logl_static(const sps_library *L, const sps_obs *o, co
     return p;
   };
   w.keys = (double *)take(Bp * 8);
+  w.ranks = (int *)take(Bp * 4);
   w.W = take(Bp * g.K_pad * w_el);
   w.rowmask = (uint32_t *)take(Bp * w.mask_words * 4);
   w.rows = (PointRow *)take(Bp * sizeof(PointRow));
   w.F = take(Bp * g.N_pad * f_el);
   w.Lline = (double *)take(Bp * (size_t)(g.n_line > 0 ? g.n_line : 1) * 8);
-  w.tiles = (int *)take(((Bp + 63) / 64 * (g.N_pad / kSpanTile) + 1) * 4);
+  w.tiles = (int *)take(tile_list_ints(Bp, g.N_pad) * 4);
   w.WQ = (double *)take(Bp * (size_t)(g.has_cont ? g.neb_a1 - g.neb_a0 : 1) * 8);
   w.counter = nullptr;
   return launch_forward(L, w, o->dev_obs, nullptr, theta, B, prec, logl, model, o->host.n_data, false,

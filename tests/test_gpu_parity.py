@@ -8,7 +8,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import gpu_objects, make_case, model_err, worst_entries
+from helpers import gpu_observation, gpu_objects, make_case, model_err, worst_entries
 from oracle import model as om
 from synth import workloads as wl
 
@@ -126,6 +126,22 @@ def test_batch_edges_single_point_and_composition(c1s):
     assert np.array_equal(llp, ll_all[perm])
     ll2, m2 = gpu_run(L, O, case["theta"], "fp32")
     assert np.array_equal(m2, m_all) and np.array_equal(ll2, ll_all)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_large_batch_ranking_path_is_bitwise_the_small_one(c1s, prec):
+    # batches from 2048 points rank in a kernel of their own and reduce the M tiles' spans
+    # in another; the row results must not depend on which path ordered the batch.  The
+    # 200 vectors repeated make a 2200-point batch with every key tied ten-fold or more.
+    case, L, _, _, _ = c1s
+    say(f"c1-reduced {prec} B=2200 (rank kernel) against B=200 (in-builder rank)")
+    Ob = gpu_observation(L, case, max_batch=2304)
+    big = np.tile(case["theta"], (11, 1))
+    ll_b, m_b = gpu_run(L, Ob, big, prec)
+    ll_s, m_s = gpu_run(L, Ob, case["theta"], prec)
+    for k in range(11):
+        assert np.array_equal(m_b[200 * k:200 * (k + 1)], m_s)
+        assert np.array_equal(ll_b[200 * k:200 * (k + 1)], ll_s)
 
 
 def test_batch_larger_than_workspace_is_rejected(c1s):
