@@ -92,3 +92,41 @@ def lines_lnlike(data, model, sigma, mask, upper):
     chi2 = ((d - model) / sg) ** 2
     chi2 = np.where(upper & (model <= d), 0.0, chi2)
     return float(-0.5 * np.sum(np.where(mask, chi2, 0.0)))
+
+
+# ---------------------------------------------------------------------------------
+# Analytic marginalisation of line fluxes (Sec. 4.1, App. I.3, eq. app_line_marg)
+# ---------------------------------------------------------------------------------
+def line_marginal_lnlike(data, model, sigma, mask, A, alpha_bar, prior_sd, flat, s=1.0, f_calib=None,
+                         f_data=None, jitter=None, return_mean=False):
+    """The data are linear in the fitted line fluxes alpha: d = mu + A alpha + n.  ``model`` is
+    the full model at the grid fluxes alpha_bar (mu + A alpha_bar), A[i, j] the unit-flux
+    profile of line j on pixel i, n ~ N(0, diag(sigma_eff^2)) with sigma_eff at that model.
+    Line j takes a Gaussian prior N(alpha_bar_j, prior_sd_j^2), or a flat prior where
+    flat[j] (its grid flux then does not enter the residual).  With r = d - mu - A alpha_0
+    (alpha_0 = alpha_bar, 0 on flat lines), b = A^T W r, P = A^T W A + diag(prior_sd^-2) over
+    the Gaussian lines:
+
+      ln Z = lnL_diag(r) + b^T P^-1 b / 2 - ln|P| / 2 - sum_G ln s_j + (m_flat / 2) ln(2 pi),
+
+    and the fluxes given theta are Gaussian with mean alpha_0 + P^-1 b (returned as well
+    with ``return_mean``)."""
+    A = np.asarray(A, dtype=np.float64)
+    flat = np.asarray(flat, dtype=bool)
+    alpha_bar = np.asarray(alpha_bar, dtype=np.float64)
+    prior_sd = np.asarray(prior_sd, dtype=np.float64)
+    d = np.where(mask, data, 0.0)
+    sg = np.where(mask, sigma, 1.0)
+    v = effective_variance(sg, model, d, s, f_calib, f_data, jitter)
+    iv = np.where(mask, 1.0 / v, 0.0)
+    alpha0 = np.where(flat, 0.0, alpha_bar)
+    resid_model = model - A @ np.where(flat, alpha_bar, 0.0)      # mu + A alpha_0
+    r = np.where(mask, d - resid_model, 0.0)
+    base = float(np.sum(np.where(mask, -0.5 * r * r * iv - 0.5 * np.log(2.0 * np.pi * np.where(mask, v, 1.0)), 0.0)))
+    b = A.T @ (iv * r)
+    P = A.T @ (iv[:, None] * A) + np.diag(np.where(flat, 0.0, 1.0 / np.where(flat, 1.0, prior_sd) ** 2))
+    x = np.linalg.solve(P, b)
+    _, logdet = np.linalg.slogdet(P)
+    lnz = base + 0.5 * b @ x - 0.5 * logdet - np.sum(np.log(prior_sd[~flat])) \
+        + 0.5 * np.count_nonzero(flat) * np.log(2.0 * np.pi)
+    return (lnz, alpha0 + x) if return_mean else lnz

@@ -190,6 +190,12 @@ class Spectrum:
     calib: str | None = None
     calib_order: int = 0
     calib_prior: np.ndarray | None = None
+    # analytic marginalisation of the line fluxes (Sec. 4.1, App. I.3): None, "gauss" (prior
+    # N(F_l, (frac F_l)^2) around the grid flux, flat for the lines flagged in line_flat) or
+    # "flat" (every line flat)
+    line_marg: str | None = None
+    line_prior_frac: float = 0.0
+    line_flat: np.ndarray | None = None
 
 
 @dataclass
@@ -385,14 +391,38 @@ def predict(L: Library, obs, theta, rf=None, trunc=5.0):
             continue
         cont = projection.spectrum_continuum(obs.pix_wave, sig_k, L.wave, fnu, z, trunc)
         if L.lines is not None:
-            Fl = line_fluxes(L, th, cols, rf["Lline"][b], dl)
-            lobs = (1.0 + z) * L.lines["line_wave"]
-            s_l = np.sqrt(obs.sigma_gas_kms ** 2
-                          + projection.sigma_inst_kms(lobs, obs.lsf_mode,
-                                                      _lsf_at(obs, lobs)) ** 2) / C_KMS
+            Fl, lobs, s_l = spectrum_line_terms(L, obs, th, cols, rf["Lline"][b], dl)
             cont = cont + projection.line_profile_pixels(obs.pix_wave, Fl, lobs, s_l)
         out.append(cont / FNU_AB)
     return np.array(out)
+
+
+def spectrum_line_terms(L: Library, obs, th, cols, Lline_row, dl):
+    """Per library line: observer-frame flux F_l (App. I.1), observed wavelength and the
+    profile width s_l in ln(lambda) (eq. app_line_profile)."""
+    Fl = line_fluxes(L, th, cols, Lline_row, dl)
+    lobs = (1.0 + th[cols["zred"]]) * L.lines["line_wave"]
+    s_l = np.sqrt(obs.sigma_gas_kms ** 2
+                  + projection.sigma_inst_kms(lobs, obs.lsf_mode, _lsf_at(obs, lobs)) ** 2) / C_KMS
+    return Fl, lobs, s_l
+
+
+def line_marg_terms(L: Library, obs, th, cols, Lline_row):
+    """The lines fitted by the marginalisation of a spectrum (App. I.3) at one point: those
+    whose observed wavelength lies within the pixel range, less the Gaussian-prior lines
+    with no grid flux (fixed at zero); their unit-flux profiles on the pixels (maggies per
+    erg/s/cm^2), grid fluxes, prior widths frac * F_l and flat flags."""
+    _, dl = observer_scale(L, th, cols)
+    Fl, lobs, s_l = spectrum_line_terms(L, obs, th, cols, Lline_row, dl)
+    n_l = len(Fl)
+    flat_all = obs.line_marg == "flat"
+    flat = np.ones(n_l, dtype=bool) if flat_all else (
+        np.zeros(n_l, dtype=bool) if obs.line_flat is None else np.asarray(obs.line_flat, dtype=bool))
+    inwin = (lobs >= obs.pix_wave[0]) & (lobs <= obs.pix_wave[-1])
+    sel = np.flatnonzero(inwin & (flat | (Fl > 0.0)))
+    A = np.stack([projection.line_profile_pixels(obs.pix_wave, np.array([1.0]), lobs[[j]], s_l[[j]]) / FNU_AB
+                  for j in sel], axis=1) if len(sel) else np.zeros((len(obs.pix_wave), 0))
+    return dict(idx=sel, A=A, alpha_bar=Fl[sel], prior_sd=obs.line_prior_frac * Fl[sel], flat=flat[sel])
 
 
 def fourier_stage_plan(L: Library, obs, sig_k=None):
@@ -454,10 +484,19 @@ def logl(L: Library, obs, theta, model=None, trunc=5.0):
                          for b in range(theta.shape[0])])
     calib = getattr(obs, "calib", None)
     A = likelihood.chebyshev_design(obs.pix_wave, obs.calib_order) if calib else None
+    lmarg = getattr(obs, "line_marg", None)
+    if lmarg is not None:
+        if calib:
+            raise ValueError("line marginalisation and a calibration polynomial together are not supported")
+        rf = rest_frame(L, theta, lines_on_grid=False)
     out = np.empty(theta.shape[0])
     for b in range(theta.shape[0]):
         s, fc, fd, j = noise_terms(obs, theta[b], cols)
-        if calib:
+        if lmarg is not None:
+            t = line_marg_terms(L, obs, theta[b], cols, rf["Lline"][b])
+            out[b] = likelihood.line_marginal_lnlike(obs.data, model[b], obs.sigma, mask, t["A"], t["alpha_bar"],
+                                                     t["prior_sd"], t["flat"], s, fc, fd, j)
+        elif calib:
             out[b] = likelihood.calibrated_lnlike(obs.data, model[b], obs.sigma, mask, A, obs.calib_prior, calib,
                                                   s, fc, fd, j)
         else:
