@@ -235,7 +235,8 @@ def features_leg(base_spec, base_phot, steps=20, warmup=3, seed=0):
     points, with the time it adds to the plain workload's step:
       - the 3000-pixel prism spectrum with a free stellar velocity dispersion (sigma_gal ~
         U(0, 500) km/s, the Fourier stage), and also with a calibration polynomial of order
-        5, marginalised (FP16 hi + residual, the spectroscopic default);
+        5, marginalised, or with the line fluxes marginalised (FP16 hi + residual, the
+        spectroscopic default);
       - the photometric workload under the linear (tent-integral) SFH scheme with the IGM
         (FP16 weight residual, the photometric default);
       - a catalogue of 16 entries (single lines and blends, three upper limits) of the 128
@@ -254,8 +255,9 @@ def features_leg(base_spec, base_phot, steps=20, warmup=3, seed=0):
     g = wl.make_spectrum_grid(cfg.n_pix)
     th_true = wl.make_theta(cfg, 1, seed=seed + 1002, vdisp=500.0)
     theta = torch.tensor(wl.make_theta(cfg, cfg.batch, seed=seed + 2, vdisp=500.0), device="cuda")
-    for tag, calib in (("spectrum_vdisp", {}), ("spectrum_vdisp_calib",
-                                                dict(calib="marginal", calib_order=5, calib_prior=np.full(6, 0.1)))):
+    for tag, calib in (("spectrum_vdisp", {}),
+                       ("spectrum_vdisp_calib", dict(calib="marginal", calib_order=5, calib_prior=np.full(6, 0.1))),
+                       ("spectrum_vdisp_linemarg", dict(line_marg="gauss", line_prior_frac=0.3))):
         O = sps.Observation(L, "spec", cfg.batch, pix_wave=g["pix_wave"], lsf_mode=g["lsf_mode"],
                             lsf_value=g["lsf_value"], z_ref=float(th_true[0, 1]), sigma_gas_kms=g["sigma_gas_kms"],
                             **calib)
@@ -269,6 +271,8 @@ def features_leg(base_spec, base_phot, steps=20, warmup=3, seed=0):
     out["spectrum_vdisp"]["workload"] = (f"{cfg.batch} live points, {cfg.n_pix}-pixel prism spectrum, free sigma_gal "
                                          f"~ U(0, 500) km/s (Fourier stage)")
     out["spectrum_vdisp_calib"]["workload"] = "the same with a marginalised calibration polynomial of order 5"
+    out["spectrum_vdisp_linemarg"]["workload"] = ("the same with the line fluxes marginalised (Gaussian priors of 30 "
+                                                  "per cent around the grid fluxes)")
     del L, lib
     cfg = wl.CONFIGS["c1"]
     lib = wl.make_library(cfg, seed)

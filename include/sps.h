@@ -252,7 +252,23 @@ typedef struct {
   const int32_t *line_len;
   const int32_t *line_index;
   const uint8_t *upper;
+  /* spectrum: analytic marginalisation of the line fluxes (Sec. 4.1, App. I.3,
+   * eq. app_line_marg).  The library lines whose observed wavelength lies within the pixel
+   * range are free amplitudes alpha with unit-flux profiles A on the pixels:
+   * SPS_LINEMARG_GAUSS gives each the prior N(F_l, (line_prior_frac F_l)^2) around its grid
+   * flux F_l (flat for the lines flagged in line_flat [n_line], NULL none; Gaussian lines
+   * with F_l = 0 stay fixed at 0), SPS_LINEMARG_FLAT a flat prior to all.  logL becomes
+   * lnL_diag(r) + b^T P^-1 b / 2 - ln|P| / 2 - sum ln s_l + (m_flat / 2) ln 2 pi with
+   * r = d - mu - A alpha_0, b = A^T W r, P = A^T W A + diag(s^-2) (W at the grid model); the
+   * model returned is the grid model.  At most 128 library lines in any rest-frame interval
+   * as wide as the pixel range (else SPS_E_SHAPE); spectra of at most 8192 pixels; not with a
+   * calibration polynomial; no gradient, no allocation-free call (SPS_E_INVAL). */
+  int32_t line_marg;
+  double line_prior_frac;
+  const uint8_t *line_flat;
 } sps_obs_desc;
+
+enum { SPS_LINEMARG_NONE = 0, SPS_LINEMARG_GAUSS = 1, SPS_LINEMARG_FLAT = 2 };
 
 /* Builds the observation's fixed operators (filter rows of eq. E1, kernel
  * widths of eq. F4, line-width table) and its workspace.  *warnings (may be
@@ -284,9 +300,10 @@ sps_status sps_logl(const sps_library *lib, sps_obs *obs, const double *theta_de
 /* logl_dev [B] and grad_dev [B, P] = d logL / d theta (FP64; columns the
  * model does not use are zero).  Hand-written reverse pass.  Supported for
  * SPS_FP64 and SPS_FP32, for libraries without a nebular continuum cube, an
- * escape geometry, a line table on an age axis of its own, the linear SFH scheme or
- * the IGM, and for photometry and spectra without a calibration polynomial (a line
- * catalogue or a calibrated spectrum: SPS_E_INVAL). */
+ * escape geometry, a line table on an age axis of its own, the linear SFH scheme, the
+ * IGM or a free sigma_gal, and for photometry and spectra without a calibration
+ * polynomial or marginalised line fluxes (a line catalogue, a calibrated spectrum or one
+ * with marginalised line fluxes: SPS_E_INVAL). */
 sps_status sps_logl_grad(const sps_library *lib, sps_obs *obs, const double *theta_dev, int32_t B,
                          int32_t precision, double *logl_dev, double *grad_dev, void *hip_stream);
 
@@ -302,7 +319,8 @@ sps_status sps_logl_grad(const sps_library *lib, sps_obs *obs, const double *the
  * threads without ordering) race.  Errors: SPS_E_SHAPE when B points at this precision
  * need more scratch than the array holds (64 MiB: on a 2496 x 6016 library with 128
  * lines, up to B = 1792 at FP32 or 16 bit and B = 896 at FP64); SPS_E_INVAL for a
- * spectrum with a calibration polynomial; otherwise as sps_logl. */
+ * spectrum with a calibration polynomial or marginalised line fluxes; otherwise as
+ * sps_logl. */
 #define SPS_STATIC_SCRATCH_BYTES (64ull << 20)
 sps_status sps_logl_static(const sps_library *lib, const sps_obs *obs, const double *theta_dev, int32_t B,
                            int32_t precision, double *logl_dev, double *model_dev, void *hip_stream);

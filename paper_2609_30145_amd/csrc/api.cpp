@@ -249,6 +249,7 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   L->line_tau_axis = nl > 0 && d->n_line_tau > 0;
   L->precisions = d->precisions | (1u << SPS_FP32);
   L->wave_h.assign(d->wave, d->wave + N);
+  if (nl > 0) L->line_wave_h.assign(d->line_wave, d->line_wave + nl);
   L->logz_lo = d->logz[0];
   L->logz_hi = d->logz[nz - 1];
   L->afe_lo = nf > 1 ? d->afe[0] : 0.0;
@@ -806,6 +807,34 @@ sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsH
       h.calib_xs = 2.0 / (d->pix_wave[np - 1] - d->pix_wave[0]);
       h.calib_x0 = -1.0 - d->pix_wave[0] * h.calib_xs;
     }
+    // analytic marginalisation of the line fluxes (Sec. 4.1, App. I.3)
+    if (d->line_marg < SPS_LINEMARG_NONE || d->line_marg > SPS_LINEMARG_FLAT)
+      return fail(SPS_E_INVAL, "unknown line_marg mode %d", d->line_marg);
+    h.lm_mode = d->line_marg;
+    if (h.lm_mode != SPS_LINEMARG_NONE) {
+      const int nl = L->n_line;
+      if (nl < 1) return fail(SPS_E_INVAL, "line marginalisation needs a library with nebular lines");
+      if (h.calib_mode != SPS_CALIB_NONE)
+        return fail(SPS_E_INVAL, "line marginalisation and a calibration polynomial together are not supported");
+      if (np > 8192) return fail(SPS_E_SHAPE, "line marginalisation takes spectra of at most 8192 pixels");
+      if (h.lm_mode == SPS_LINEMARG_GAUSS && !(d->line_prior_frac > 0 && std::isfinite(d->line_prior_frac)))
+        return fail(SPS_E_INVAL, "line_prior_frac must be finite and > 0");
+      h.lm_frac = d->line_prior_frac;
+      if (d->line_flat) {
+        h.lm_flat.resize(nl);
+        for (int l = 0; l < nl; ++l) h.lm_flat[l] = d->line_flat[l] ? 1 : 0;
+      }
+      // at most kLineMargMax lines in any rest interval as wide as the pixel range (ln)
+      const double width = std::log(d->pix_wave[np - 1] / d->pix_wave[0]);
+      int most = 0;
+      for (int l0 = 0, l1 = 0; l0 < nl; ++l0) {
+        while (l1 < nl && std::log(L->line_wave_h[l1] / L->line_wave_h[l0]) <= width) ++l1;
+        most = std::max(most, l1 - l0);
+      }
+      if (most > kLineMargMax)
+        return fail(SPS_E_SHAPE, "up to %d library lines fall within the pixel range; the marginalisation fits at "
+                    "most %d", most, kLineMargMax);
+    }
   } else if (d->kind == SPS_OBS_LINES) {
     // emission-line catalogue (Sec. 3.3, App. I): blends of the library's lines
     const int nk = d->n_band;
@@ -984,8 +1013,9 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   // pass of its own after the projection
   const bool lines_only = one && one->kind == SPS_OBS_LINES;
   const bool calib = one && one->calib_mode != SPS_CALIB_NONE;
-  if (calib && (grad || !w.mbuf || !w.scr || w.ld_scr < 24))
-    return fail(SPS_E_INVAL, "calibration polynomial: no gradient, and a full workspace");
+  const bool lmarg = one && one->lm_mode != SPS_LINEMARG_NONE;
+  if ((calib || lmarg) && (grad || !w.mbuf || !w.scr || w.ld_scr < std::max(24, 2 * one->n_data)))
+    return fail(SPS_E_INVAL, "calibration polynomial / line marginalisation: no gradient, and a full workspace");
   const int n_nt = g.N_pad / 64;
   const bool span = !grad && g.log_uniform && prec != SPS_FP64 && w.tiles && B_pad / MT <= kTileListMaxM;
   ContractLaunch cl;
@@ -1051,7 +1081,7 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   pj.logl = logl;
   pj.gvec = grad ? w.gvec : nullptr;
   pj.gnoise = grad ? w.gnoise : nullptr;
-  pj.msorted = grad || calib ? w.mbuf : nullptr;
+  pj.msorted = grad || calib || lmarg ? w.mbuf : nullptr;
   pj.ld_model = ld_model;
   pj.ld_g = ld_g;
   if (e == hipSuccess) e = launch_project(g, pj, s);
@@ -1067,6 +1097,20 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
     cb.ld_sums = w.ld_scr;
     cb.logl = logl;
     e = launch_calib(g, cb, s);
+  }
+  if (lmarg && e == hipSuccess) {
+    LineMargLaunch lm;
+    lm.obs_table = obs_table;
+    lm.rows = w.rows;
+    lm.theta = theta;
+    lm.Lline = w.Lline;
+    lm.msorted = w.mbuf;
+    lm.ld = ld_g;
+    lm.scr = w.scr;
+    lm.ld_scr = w.ld_scr;
+    lm.B_pad = B_pad;
+    lm.logl = logl;
+    e = launch_linemarg(g, lm, s);
   }
   if (e != hipSuccess) return fail(SPS_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
   return SPS_OK;
@@ -1098,8 +1142,10 @@ extern "C" sps_status sps_logl_grad(const sps_library *L, sps_obs *o, const doub
                                     double *logl, double *grad, void *stream) {
   if (!logl || !grad) return fail(SPS_E_INVAL, "logl_dev / grad_dev is NULL");
   if (prec != SPS_FP64 && prec != SPS_FP32) return fail(SPS_E_INVAL, "gradients are available for FP64 and FP32");
-  if (o && (o->host.kind == SPS_OBS_LINES || o->host.calib_mode != SPS_CALIB_NONE))
-    return fail(SPS_E_INVAL, "gradients are not available for line catalogues or calibrated spectra");
+  if (o && (o->host.kind == SPS_OBS_LINES || o->host.calib_mode != SPS_CALIB_NONE ||
+            o->host.lm_mode != SPS_LINEMARG_NONE))
+    return fail(SPS_E_INVAL, "gradients are not available for line catalogues, calibrated spectra or marginalised "
+                "line fluxes");
   if (L && (L->dev.has_cont || L->dev.escape || L->line_tau_axis || L->dev.sfh_scheme || L->dev.igm || L->dev.vdisp))
     return fail(SPS_E_INVAL, "gradients are not available for libraries with a nebular continuum cube, an escape "
                 "geometry, a line table on an age axis of its own, the linear SFH scheme, the IGM or a free "

@@ -142,7 +142,15 @@ struct DevObs {
   int vd_M, vd_nfft, vd_log2, vd_pad;
   double vd_lnlo, vd_lnhi, vd_dlnl;
   const double *vd_tw;
+  // analytic marginalisation of the line fluxes of a spectrum: mode (0 off, 1 Gaussian prior
+  // of width lm_frac F_l, flat where lm_flat[l]; 2 flat), per-line flat flags or NULL
+  int lm_mode, lm_pad;
+  double lm_frac;
+  const uint8_t *lm_flat;
 };
+// Lines a spectrum's marginalisation fits at most (its dense normal matrix lives in LDS:
+// 129 KB of the workgroup's 150 KB)
+constexpr int kLineMargMax = 128;
 
 // Per-point quantities, stored at the point's sorted row.
 struct PointRow {

@@ -76,6 +76,21 @@ hipError_t launch_project(const DevLib &lib, const ProjectLaunch &pl, hipStream_
 
 // spectrum calibration polynomial (App. H.3): the correction to logL from the model at the
 // sorted rows (written by the projection), per point
+// analytic marginalisation of a spectrum's line fluxes (App. I.3): one workgroup per row,
+// after the projection (which leaves the grid model at the sorted rows)
+struct LineMargLaunch {
+  const DevObs *obs_table;
+  const PointRow *rows;
+  const double *theta;
+  const double *Lline;       // [B_pad][n_line] line luminosities from the weight builder
+  const double *msorted;     // [B_pad][ld] grid model at the sorted rows
+  int ld;
+  double *scr;               // [B_pad][ld_scr] per-row scratch: residuals and weights, ld_scr >= 2 n_pix
+  int ld_scr, B_pad;
+  double *logl;              // [B] or NULL: overwritten with the marginal likelihood
+};
+hipError_t launch_linemarg(const DevLib &lib, const LineMargLaunch &lm, hipStream_t s);
+
 struct CalibLaunch {
   const DevObs *obs_table;
   const PointRow *rows;

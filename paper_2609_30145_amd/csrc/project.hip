@@ -39,6 +39,33 @@ __device__ double sigma_inst_mode(int mode, double v, double lam) {
   }
 }
 
+// A library line at one point of a spectrum (App. I.1, eq. app_line_profile): its observer-
+// frame flux (the young light's birth-cloud transmission with an escape geometry's mixture,
+// the diffuse screen, mass over 4 pi D_L^2 and the IGM at the line), its observed wavelength
+// and its profile width in ln(lambda) (gas dispersion and the instrument at the line).
+__device__ __forceinline__ void spec_line_terms(const DevLib &lib, const DevObs &ob, const PointRow &pr,
+                                                const double *th, double Lline, int l, double &Fl, double &lobs,
+                                                double &sl) {
+  const double z = pr.z, opz = 1.0 + z;
+  const double Tfac = pr.mass10 / (4.0 * kPi * pr.dl * pr.dl);
+  const double lw = lib.line_wave[l];
+  const double lnlv = log(lw / kLamV);
+  const double tbc = pr.bc_p * exp(-pr.tau_bc * exp(pr.alpha_bc * lnlv)) + pr.bc_q;
+  const double td = exp(-pr.tau_diff * exp(pr.delta * lnlv) * (lib.line_a[l] + (0.85 - 1.9 * pr.delta) * lib.line_d[l]));
+  lobs = opz * lw;
+  Fl = Lline * tbc * td * Tfac * igm_T(lib, th, z, lobs);
+  double v = ob.lsf_value;
+  if (ob.has_curve) {
+    const int np = ob.n_data;
+    const double lc = fmin(fmax(lobs, ob.pix[0]), ob.pix[np - 1]);
+    const int k = bracket(ob.pix, np, lc);
+    const double t = (lc - ob.pix[k]) / (ob.pix[k + 1] - ob.pix[k]);
+    v = ob.lsf_vals[k] + t * (ob.lsf_vals[k + 1] - ob.lsf_vals[k]);
+  }
+  const double si = sigma_inst_mode(ob.lsf_mode, v, lobs);
+  sl = sqrt(ob.sigma_gas_kms * ob.sigma_gas_kms + si * si) / kC_kms;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
   __shared__ double red[256];
@@ -291,27 +318,10 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
     const int nl = a.n_line;
     double slmax = 0.0;
     if (nl > 0) {
-      const double Tfac = pr.mass10 / (4.0 * kPi * pr.dl * pr.dl);
       double my_max = 0.0;
       for (int l = tid; l < nl; l += 256) {
-        const double lw = lib.line_wave[l];
-        const double lnlv = log(lw / kLamV);
-        // the young light's birth-cloud transmission (with an escape geometry's mixture),
-        // then the diffuse screen
-        const double tbc = pr.bc_p * exp(-pr.tau_bc * exp(pr.alpha_bc * lnlv)) + pr.bc_q;
-        const double td = exp(-pr.tau_diff * exp(pr.delta * lnlv) * (lib.line_a[l] + (0.85 - 1.9 * pr.delta) * lib.line_d[l]));
-        const double lobs = opz * lw;
-        const double Fl = a.Lline[(size_t)r * nl + l] * tbc * td * Tfac * igm_T(lib, th, z, lobs);
-        double v = ob.lsf_value;
-        if (ob.has_curve) {
-          const int np = ob.n_data;
-          const double lc = fmin(fmax(lobs, ob.pix[0]), ob.pix[np - 1]);
-          const int k = bracket(ob.pix, np, lc);
-          const double t = (lc - ob.pix[k]) / (ob.pix[k + 1] - ob.pix[k]);
-          v = ob.lsf_vals[k] + t * (ob.lsf_vals[k + 1] - ob.lsf_vals[k]);
-        }
-        const double si = sigma_inst_mode(ob.lsf_mode, v, lobs);
-        const double sl = sqrt(ob.sigma_gas_kms * ob.sigma_gas_kms + si * si) / kC_kms;
+        double Fl, lobs, sl;
+        spec_line_terms(lib, ob, pr, th, a.Lline[(size_t)r * nl + l], l, Fl, lobs, sl);
         s_lnl[l] = log(lobs);
         s_isl[l] = 1.0 / sl;
         s_amp[l] = Fl / (2.5066282746310002 * sl);
@@ -667,6 +677,180 @@ __global__ void __launch_bounds__(64) k_calib_solve(CalibLaunch a) {
     default: corr = calib_solve<8>(sums, ob); break;
   }
   if (a.logl) a.logl[pr.b] += corr;
+}
+
+// ---------------------------------------------------------------------------------
+// Analytic marginalisation of a spectrum's line fluxes (Sec. 4.1, App. I.3, eq.
+// app_line_marg).  One workgroup per sorted row.  The fitted lines are those observed within
+// the pixel range (a Gaussian-prior line with no grid flux stays fixed at 0), in wavelength
+// order, at most kLineMargMax; line j's unit-flux profile on pixel i is
+// A_ij = lambda_i / c N(ln lambda_i; ln lambda_j^obs, s_j) / f_nu^AB, taken within kLineCut
+// s_j of the line as in the projection.  Phases:
+//   1  per library line: grid flux, observed wavelength and width (spec_line_terms), the
+//      fitted ones compacted in order by one wave (ballot prefix), each with its pixel window;
+//   2  per pixel: W_i = 1 / sigma_eff^2 at the grid model (0 off the mask) and the residual
+//      r_i = d_i - m_i plus the flat lines' grid profiles, into the row's scratch; the
+//      diagonal likelihood of r;
+//   3  b_j = sum_i A_ij W_i r_i (a wave per line) and P_jk = sum_i A_ij A_ik W_i over the
+//      two windows' overlap (a wave per pair; pairs whose windows do not meet are 0), plus
+//      s_j^-2 on the Gaussian lines' diagonal;
+//   4  P = L L^T in LDS, right-looking, one column per step, with L y = b carried along:
+//      ln Z = lnL_diag(r) + y^T y / 2 - sum ln L_jj - sum_G ln s_j + (m_flat / 2) ln 2 pi.
+// ---------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) {
+  constexpr int NM = kLineMargMax;
+  __shared__ double sP[NM][NM + 1];
+  __shared__ double s_b[NM], s_F[NM], s_lnl[NM], s_isl[NM];
+  __shared__ int s_p0[NM], s_p1[NM];
+  __shared__ unsigned char s_flat[NM];
+  __shared__ double t_F[512], t_lnl[512], t_sl[512];
+  __shared__ unsigned char t_fit[512], t_flat[512];
+  __shared__ double red[4], s_lnsg;
+  __shared__ int s_n, s_nflat;
+  const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const PointRow &pr = a.rows[r];
+  if (pr.b < 0) return;
+  const DevObs &ob = a.obs_table[pr.obs];
+  if (ob.kind != 1 || ob.lm_mode == 0) return;
+  const double *th = a.theta + (size_t)pr.b * lib.P;
+  const int nl = lib.n_line, np = ob.n_data;
+  const double pix_lo = ob.pix[0], pix_hi = ob.pix[np - 1];
+  // ---- 1. the library lines, then the fitted ones in order
+  for (int l = tid; l < nl; l += 256) {
+    double Fl, lobs, sl;
+    spec_line_terms(lib, ob, pr, th, a.Lline[(size_t)r * nl + l], l, Fl, lobs, sl);
+    const bool flat = ob.lm_mode == 2 || (ob.lm_flat && ob.lm_flat[l]);
+    t_F[l] = Fl;
+    t_lnl[l] = log(lobs);
+    t_sl[l] = sl;
+    t_flat[l] = flat ? 1 : 0;
+    t_fit[l] = (lobs >= pix_lo && lobs <= pix_hi && (flat || Fl > 0.0)) ? 1 : 0;
+  }
+  __syncthreads();
+  if (wv == 0) {
+    int base = 0, nflat = 0;
+    double lnsg = 0.0;
+    for (int l0 = 0; l0 < nl; l0 += 64) {
+      const int l = l0 + lane;
+      const bool f = l < nl && t_fit[l];
+      const unsigned long long m = __ballot(f);
+      const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+      if (f && pos < NM) {
+        s_F[pos] = t_F[l];
+        s_lnl[pos] = t_lnl[l];
+        s_isl[pos] = 1.0 / t_sl[l];
+        s_flat[pos] = t_flat[l];
+        const double w = kLineCut * t_sl[l];
+        s_p0[pos] = lower_bound_dev(ob.lnpix, np, t_lnl[l] - w);
+        int hi = lower_bound_dev(ob.lnpix, np, t_lnl[l] + w);
+        while (hi < np && ob.lnpix[hi] <= t_lnl[l] + w) ++hi;
+        s_p1[pos] = hi;
+        if (t_flat[l]) ++nflat;
+        else lnsg += log(ob.lm_frac * t_F[l]);
+      }
+      base += __popcll(m);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      nflat += __shfl_xor(nflat, o);
+      lnsg += __shfl_xor(lnsg, o);
+    }
+    if (lane == 0) {
+      s_n = min(base, NM);
+      s_nflat = nflat;
+      s_lnsg = lnsg;
+    }
+  }
+  __syncthreads();
+  const int n = s_n;
+  // unit-flux profile of fitted line j at pixel i (maggies per erg/s/cm^2)
+  auto A = [&](int j, int i) {
+    const double u = (ob.lnpix[i] - s_lnl[j]) * s_isl[j];
+    return ob.pix[i] * (kAng_cm / kC_cms / kFnuAB) * (0.3989422804014327 * s_isl[j]) * exp(-0.5 * u * u);
+  };
+  // ---- 2. weights and residuals at the grid model; the diagonal likelihood of r
+  const double ns = (ob.noise_flags & 1) ? exp(th[TH_LOG_ERR_SCALE]) : 1.0;
+  const double fc = (ob.noise_flags & 2) ? exp(th[TH_LOG_F_CALIB]) : 0.0;
+  const double fd = (ob.noise_flags & 4) ? exp(th[TH_LOG_F_DATA]) : 0.0;
+  const double jt = (ob.noise_flags & 8) ? exp(th[TH_LOG_JITTER]) : 0.0;
+  const double *mu = a.msorted + (size_t)r * a.ld;
+  double *sr = a.scr + (size_t)r * a.ld_scr, *sw = sr + np;
+  double lsum = 0.0;
+  for (int i = tid; i < np; i += 256) {
+    double w = 0.0, rr = 0.0;
+    if (ob.mask[i]) {
+      const double m = mu[i], d = ob.data[i], sg = ob.sigma[i];
+      const double v = ns * ns * sg * sg + fc * fc * m * m + fd * fd * d * d + jt * jt;
+      w = 1.0 / v;
+      rr = d - m;
+      for (int j = 0; j < n; ++j)
+        if (s_flat[j] && i >= s_p0[j] && i < s_p1[j]) rr += s_F[j] * A(j, i);
+      lsum += -0.5 * rr * rr * w - 0.5 * log(2.0 * kPi * v);
+    }
+    sr[i] = rr;
+    sw[i] = w;
+  }
+  lsum = wave_reduce_sum(lsum);
+  if (lane == 0) red[wv] = lsum;
+  __syncthreads();
+  const double lnl_diag = (red[0] + red[1]) + (red[2] + red[3]);
+  // ---- 3. b and the normal matrix P
+  for (int j = wv; j < n; j += 4) {
+    double acc = 0.0;
+    for (int i = s_p0[j] + lane; i < s_p1[j]; i += 64) acc += A(j, i) * sw[i] * sr[i];
+    acc = wave_reduce_sum(acc);
+    if (lane == 0) s_b[j] = acc;
+  }
+  for (int j = 0, q = 0; j < n; ++j)
+    for (int k = j; k < n; ++k, ++q) {
+      if ((q & 3) != wv) continue;
+      const int lo = max(s_p0[j], s_p0[k]), hi = min(s_p1[j], s_p1[k]);
+      double acc = 0.0;
+      for (int i = lo + lane; i < hi; i += 64) acc += A(j, i) * A(k, i) * sw[i];
+      acc = wave_reduce_sum(acc);
+      if (lane == 0) {
+        if (j == k && !s_flat[j]) {
+          const double sj = ob.lm_frac * s_F[j];
+          acc += 1.0 / (sj * sj);
+        }
+        sP[j][k] = acc;
+        sP[k][j] = acc;
+      }
+    }
+  __syncthreads();
+  // ---- 4. Cholesky with the forward solve carried along
+  double sum_ln = 0.0, ssq = 0.0;   // thread 0
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      const double ljj = sqrt(sP[j][j]);
+      sP[j][j] = ljj;
+      const double y = s_b[j] / ljj;
+      s_b[j] = y;
+      sum_ln += log(ljj);
+      ssq += y * y;
+    }
+    __syncthreads();
+    const double ljj = sP[j][j], yj = s_b[j];
+    for (int i = j + 1 + tid; i < n; i += 256) {
+      const double lij = sP[i][j] / ljj;
+      sP[i][j] = lij;
+      s_b[i] -= lij * yj;
+    }
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int q = tid; q < m * m; q += 256) {
+      const int i = j + 1 + q / m, k = j + 1 + q % m;
+      if (k <= i) sP[i][k] -= sP[i][j] * sP[k][j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && a.logl)
+    a.logl[pr.b] = lnl_diag + 0.5 * ssq - sum_ln - s_lnsg + 0.5 * (double)s_nflat * log(2.0 * kPi);
+}
+
+hipError_t launch_linemarg(const DevLib &lib, const LineMargLaunch &lm, hipStream_t s) {
+  if (lib.n_line > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_linemarg, dim3(lm.B_pad), dim3(256), 0, s, lib, lm);
+  return hipGetLastError();
 }
 
 hipError_t launch_calib(const DevLib &lib, const CalibLaunch &cl, hipStream_t s) {

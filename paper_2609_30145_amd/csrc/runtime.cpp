@@ -65,7 +65,7 @@ int64_t obs_device_bytes(const ObsHost &h) {
   } else {
     b += 3 * r256(h.pix.size() * 8) + (h.lsf_vals.empty() ? 0 : r256(h.lsf_vals.size() * 8));
   }
-  b += 3 * r256((size_t)h.n_data * 8) + r256((size_t)h.n_data) + r256(h.vd_tw.size() * 8);
+  b += 3 * r256((size_t)h.n_data * 8) + r256((size_t)h.n_data) + r256(h.vd_tw.size() * 8) + r256(h.lm_flat.size());
   return (int64_t)b;
 }
 
@@ -127,6 +127,11 @@ sps_status upload_obs(const ObsHost &host, DevObs &o, DeviceBuffers &mem, hipStr
     o.loff = (const int *)put(host.loff.data(), host.loff.size() * 4);
     o.lidx = (const int *)put(host.lidx.data(), std::max<size_t>(1, host.lidx.size()) * 4);
     o.upper = (const uint8_t *)put(host.upper.data(), host.upper.size());
+  }
+  if (host.lm_mode) {
+    o.lm_mode = host.lm_mode;
+    o.lm_frac = host.lm_frac;
+    if (!host.lm_flat.empty()) o.lm_flat = (const uint8_t *)put(host.lm_flat.data(), host.lm_flat.size());
   }
   if (host.vd_nfft > 0) {
     o.vd_M = host.vd_M;

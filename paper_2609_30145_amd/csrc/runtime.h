@@ -86,6 +86,9 @@ struct ObsHost {
   int vd_M = 0, vd_nfft = 0, vd_log2 = 0;   // Fourier stage of a free sigma_gal
   double vd_lnlo = 0, vd_lnhi = 0, vd_dlnl = 0;
   std::vector<double> vd_tw;
+  int lm_mode = 0;                   // line-flux marginalisation (spectra)
+  double lm_frac = 0;
+  std::vector<uint8_t> lm_flat;
 };
 
 sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsHost &h, uint32_t *warnings);
@@ -97,6 +100,7 @@ struct sps_library {
   int device = 0;                  // -1: host-only (layout and operators, no device copies)
   double logz_lo = 0, logz_hi = 0, afe_lo = 0, afe_hi = 0;
   std::vector<double> wave_h;      // host copy of the wavelength grid
+  std::vector<double> line_wave_h; // host copy of the line wavelengths (rest Angstrom)
   int n_age = 0, n_z = 0, n_afe = 0, N = 0, n_young = 0, n_line = 0, n_sfh = 0, n_zh = 0;
   int line_k0 = 0;
   bool line_tau_axis = false;      // the line table came on an age axis of its own

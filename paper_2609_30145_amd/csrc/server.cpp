@@ -570,8 +570,10 @@ extern "C" sps_status sps_submit(sps_server *S, const sps_request *q, uint64_t *
   if (q->n_iter < 0) return reject(fail(SPS_E_INVAL, "n_iter must be >= 0"));
   auto r = std::make_shared<Request>();
   sps_status st = build_obs_operators(S->lib, &q->obs, r->obs, nullptr);
-  if (st == SPS_OK && (q->obs.kind == SPS_OBS_LINES || r->obs.calib_mode != SPS_CALIB_NONE))
-    st = fail(SPS_E_INVAL, "the server fits photometry and spectra without a calibration polynomial");
+  if (st == SPS_OK && (q->obs.kind == SPS_OBS_LINES || r->obs.calib_mode != SPS_CALIB_NONE ||
+                       r->obs.lm_mode != SPS_LINEMARG_NONE))
+    st = fail(SPS_E_INVAL, "the server fits photometry and spectra without a calibration polynomial or line "
+              "marginalisation");
   if (st == SPS_OK) st = set_obs_data(r->obs, q->obs.data, q->obs.sigma, q->obs.mask);
   if (st != SPS_OK) {
     std::lock_guard<std::mutex> g(S->mu);

@@ -76,8 +76,9 @@ extern "C" sps_status sps_logl_static(const sps_library *L, const sps_obs *o, co
   if (L->device < 0) return fail(SPS_E_STATE, "host-only library");
   if (B < 1) return fail(SPS_E_SHAPE, "B=%d must be >= 1", B);
   if (!precision_built(L, prec)) return fail(SPS_E_INVAL, "precision %d not built into this library", prec);
-  if (o->host.calib_mode != SPS_CALIB_NONE)
-    return fail(SPS_E_INVAL, "sps_logl_static: a calibration polynomial needs the observation's own workspace (sps_logl)");
+  if (o->host.calib_mode != SPS_CALIB_NONE || o->host.lm_mode != SPS_LINEMARG_NONE)
+    return fail(SPS_E_INVAL, "sps_logl_static: a calibration polynomial or line marginalisation needs the "
+                "observation's own workspace (sps_logl)");
   const DevLib &g = L->dev;
   const size_t need = static_scratch_bytes(g, B, prec);
   if (need > kStaticScratchBytes)

@@ -65,9 +65,11 @@ class ObsDesc(C.Structure):
                 ("sigma_gal_kms", C.c_double), ("sigma_gas_kms", C.c_double), ("data", _dp), ("sigma", _dp),
                 ("mask", _u8p), ("noise_flags", C.c_uint32), ("max_batch", C.c_int32),
                 ("calib_mode", C.c_int32), ("calib_order", C.c_int32), ("calib_prior", _dp),
-                ("line_len", _ip), ("line_index", _ip), ("upper", _u8p)]
+                ("line_len", _ip), ("line_index", _ip), ("upper", _u8p),
+                ("line_marg", C.c_int32), ("line_prior_frac", C.c_double), ("line_flat", _u8p)]
 
 CALIB = {None: 0, "marginal": 1, "optimise": 2}
+LINEMARG = {None: 0, "gauss": 1, "flat": 2}
 
 
 class SpsError(RuntimeError):
@@ -224,13 +226,14 @@ class Observation:
     """Photometry, a spectrum or an emission-line catalogue bound to a library (sps_obs_create).
 
     Spectra take ``calib`` ("marginal" or "optimise"), ``calib_order`` and ``calib_prior``
-    for the calibration polynomial; a line catalogue ("lines") takes ``blends`` (per entry,
+    for the calibration polynomial, or ``line_marg`` ("gauss" or "flat"),
+    ``line_prior_frac`` and ``line_flat`` to marginalise the line fluxes; a line catalogue ("lines") takes ``blends`` (per entry,
     the library line indices it sums) and ``upper`` (per entry, an upper-limit flag)."""
 
     def __init__(self, library: Library, kind: str, max_batch: int, filters=None, pix_wave=None,
                  lsf_mode="R_fwhm", lsf_value=100.0, lsf_curve=None, z_ref=0.0, sigma_gal_kms=0.0,
                  sigma_gas_kms=0.0, data=None, sigma=None, mask=None, noise=(), calib=None, calib_order=0,
-                 calib_prior=None, blends=None, upper=None):
+                 calib_prior=None, blends=None, upper=None, line_marg=None, line_prior_frac=0.0, line_flat=None):
         L = lib()
         self.library = library
         keep = []
@@ -270,6 +273,12 @@ class Observation:
                 cp = _arr(calib_prior)
                 keep.append(cp)
                 d.calib_order, d.calib_prior = int(calib_order), _ptr(cp)
+            d.line_marg = LINEMARG[line_marg]
+            d.line_prior_frac = float(line_prior_frac)
+            if line_flat is not None:
+                lf = _arr(line_flat, np.uint8)
+                keep.append(lf)
+                d.line_flat = _ptr(lf, C.c_uint8)
             self.n_data = len(pw)
         if data is not None:
             da, sg = _arr(data), _arr(sigma)
