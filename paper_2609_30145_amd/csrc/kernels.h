@@ -85,7 +85,7 @@ struct LineMargLaunch {
   const double *Lline;       // [B_pad][n_line] line luminosities from the weight builder
   const double *msorted;     // [B_pad][ld] grid model at the sorted rows
   int ld;
-  double *scr;               // [B_pad][ld_scr] per-row scratch: residuals and weights, ld_scr >= 2 n_pix
+  double *scr;               // [B_pad][ld_scr] per-row scratch: residuals, weights (ld_scr >= 2 n_pix), then the profiles
   int ld_scr, B_pad;
   double *logl;              // [B] or NULL: overwritten with the marginal likelihood
 };

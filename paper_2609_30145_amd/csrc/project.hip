@@ -694,14 +694,16 @@ __global__ void __launch_bounds__(64) k_calib_solve(CalibLaunch a) {
 //   3  b_j = sum_i A_ij W_i r_i (a wave per line) and P_jk = sum_i A_ij A_ik W_i over the
 //      two windows' overlap (a wave per pair; pairs whose windows do not meet are 0), plus
 //      s_j^-2 on the Gaussian lines' diagonal;
-//   4  P = L L^T in LDS, right-looking, one column per step, with L y = b carried along:
+//   4  P = L L^T in LDS, right-looking, one column per step (a thread per row, rows outside
+//      the band of overlapping lines skipped), with L y = b carried along:
 //      ln Z = lnL_diag(r) + y^T y / 2 - sum ln L_jj - sum_G ln s_j + (m_flat / 2) ln 2 pi.
 // ---------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) {
   constexpr int NM = kLineMargMax;
+  static_assert(NM <= 256, "the factorisation takes one row per thread");
   __shared__ double sP[NM][NM + 1];
-  __shared__ double s_b[NM], s_F[NM], s_lnl[NM], s_isl[NM];
-  __shared__ int s_p0[NM], s_p1[NM];
+  __shared__ double s_b[NM], s_F[NM], s_lnl[NM], s_isl[NM], s_L[NM];
+  __shared__ int s_p0[NM], s_p1[NM], s_aoff[NM], s_poff[NM + 1], s_atab;
   __shared__ unsigned char s_flat[NM];
   __shared__ double t_F[512], t_lnl[512], t_sl[512];
   __shared__ unsigned char t_fit[512], t_flat[512];
@@ -762,6 +764,9 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
   }
   __syncthreads();
   const int n = s_n;
+  if (n == 0) {   // no line to fit: the grid model's likelihood stands
+    return;
+  }
   // unit-flux profile of fitted line j at pixel i (maggies per erg/s/cm^2)
   auto A = [&](int j, int i) {
     const double u = (ob.lnpix[i] - s_lnl[j]) * s_isl[j];
@@ -793,53 +798,89 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
   if (lane == 0) red[wv] = lsum;
   __syncthreads();
   const double lnl_diag = (red[0] + red[1]) + (red[2] + red[3]);
-  // ---- 3. b and the normal matrix P
+  // ---- 3. b and the normal matrix P.  The profiles are tabulated once into the row's
+  // scratch (after r and W) when they fit, line j's window at s_aoff[j]; the pairs that
+  // overlap, (j, k) with k from j up to the last line whose window starts before line j's
+  // ends (windows start in line order), are enumerated and dealt over the waves; the other
+  // entries are 0.
+  double *abuf = sw + np;
+  if (tid == 0) {
+    int off = 0, npair = 0;
+    for (int j = 0; j < n; ++j) {
+      s_aoff[j] = off;
+      off += s_p1[j] - s_p0[j];
+      int k = j;
+      while (k + 1 < n && s_p0[k + 1] < s_p1[j]) ++k;
+      s_poff[j] = npair;
+      npair += k - j + 1;
+    }
+    s_poff[n] = npair;
+    s_atab = off <= a.ld_scr - 2 * np ? 1 : 0;
+  }
+  for (int q = tid; q < n * n; q += 256) sP[q / n][q % n] = 0.0;
+  __syncthreads();
+  const bool atab = s_atab != 0;
+  if (atab) {
+    const int total = s_aoff[n - 1] + (s_p1[n - 1] - s_p0[n - 1]);
+    for (int t = tid; t < total; t += 256) {
+      int lo = 0, hi = n - 1;   // the line whose window holds entry t
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_aoff[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      abuf[t] = A(lo, s_p0[lo] + (t - s_aoff[lo]));
+    }
+    __syncthreads();
+  }
+  auto Ag = [&](int j, int i) { return atab ? abuf[s_aoff[j] + (i - s_p0[j])] : A(j, i); };
   for (int j = wv; j < n; j += 4) {
     double acc = 0.0;
-    for (int i = s_p0[j] + lane; i < s_p1[j]; i += 64) acc += A(j, i) * sw[i] * sr[i];
+    for (int i = s_p0[j] + lane; i < s_p1[j]; i += 64) acc += Ag(j, i) * sw[i] * sr[i];
     acc = wave_reduce_sum(acc);
     if (lane == 0) s_b[j] = acc;
   }
-  for (int j = 0, q = 0; j < n; ++j)
-    for (int k = j; k < n; ++k, ++q) {
-      if ((q & 3) != wv) continue;
-      const int lo = max(s_p0[j], s_p0[k]), hi = min(s_p1[j], s_p1[k]);
-      double acc = 0.0;
-      for (int i = lo + lane; i < hi; i += 64) acc += A(j, i) * A(k, i) * sw[i];
-      acc = wave_reduce_sum(acc);
-      if (lane == 0) {
-        if (j == k && !s_flat[j]) {
-          const double sj = ob.lm_frac * s_F[j];
-          acc += 1.0 / (sj * sj);
-        }
-        sP[j][k] = acc;
-        sP[k][j] = acc;
-      }
+  const int npair = s_poff[n];
+  for (int q = wv; q < npair; q += 4) {
+    int j = 0, hi = n - 1;   // the pair's first line
+    while (j < hi) {
+      const int mid = (j + hi + 1) >> 1;
+      if (s_poff[mid] <= q) j = mid; else hi = mid - 1;
     }
+    const int k = j + (q - s_poff[j]);
+    const int lo = max(s_p0[j], s_p0[k]), up = min(s_p1[j], s_p1[k]);
+    double acc = 0.0;
+    for (int i = lo + lane; i < up; i += 64) acc += Ag(j, i) * Ag(k, i) * sw[i];
+    acc = wave_reduce_sum(acc);
+    if (lane == 0) {
+      if (j == k && !s_flat[j]) {
+        const double sj = ob.lm_frac * s_F[j];
+        acc += 1.0 / (sj * sj);
+      }
+      sP[j][k] = acc;
+      sP[k][j] = acc;
+    }
+  }
   __syncthreads();
-  // ---- 4. Cholesky with the forward solve carried along
+  // ---- 4. Cholesky with the forward solve carried along: for column j every thread forms
+  // L_jj and y_j, thread i > j its L_ij (into s_L); then thread i updates its row of the
+  // trailing matrix and b_i (rows with L_ij = 0, outside the band of overlapping lines, skip)
   double sum_ln = 0.0, ssq = 0.0;   // thread 0
   for (int j = 0; j < n; ++j) {
+    const double ljj = sqrt(sP[j][j]), yj = s_b[j] / ljj;
     if (tid == 0) {
-      const double ljj = sqrt(sP[j][j]);
-      sP[j][j] = ljj;
-      const double y = s_b[j] / ljj;
-      s_b[j] = y;
       sum_ln += log(ljj);
-      ssq += y * y;
+      ssq += yj * yj;
+    }
+    const int i = j + 1 + tid;   // n <= 128 < 256: one row per thread
+    double lij = 0.0;
+    if (i < n) {
+      lij = sP[i][j] / ljj;
+      s_L[i] = lij;
     }
     __syncthreads();
-    const double ljj = sP[j][j], yj = s_b[j];
-    for (int i = j + 1 + tid; i < n; i += 256) {
-      const double lij = sP[i][j] / ljj;
-      sP[i][j] = lij;
+    if (i < n && lij != 0.0) {
+      for (int k = j + 1; k <= i; ++k) sP[i][k] -= lij * s_L[k];
       s_b[i] -= lij * yj;
-    }
-    __syncthreads();
-    const int m = n - j - 1;
-    for (int q = tid; q < m * m; q += 256) {
-      const int i = j + 1 + q / m, k = j + 1 + q % m;
-      if (k <= i) sP[i][k] -= sP[i][j] * sP[k][j];
     }
     __syncthreads();
   }
