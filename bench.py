@@ -150,7 +150,67 @@ def cpu_baseline(cfg_name, budget_s=12.0, seed=0):
             out["cpu_model"] = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
     except Exception:
         pass
+    out["legs"] = cpu_baseline_legs(seed)
     return out
+
+
+def cpu_baseline_legs(seed=0):
+    """The oracle on the other workloads, each over one bounded sample: forward + logL of the
+    small photometric workload (B = 64), of the headline photometric workload at B = 64 and
+    in one batch of 1024, of the 3000-pixel spectrum at B = 64 (its projection is a loop over
+    points, so the rate does not depend on the batch), and the spectrum's adjoint on 16
+    points.  Medians over repeats where a call is short."""
+    from oracle import adjoint as oa
+    from oracle import model as om
+    from synth import workloads as wl
+    legs = []
+
+    def case(name):
+        cfg = wl.CONFIGS[name]
+        lib = wl.make_library(cfg, seed)
+        lines = wl.make_lines(cfg, lib, seed + 1)
+        dust = wl.make_dust_tables(cfg, lib["wave"])
+        olib = om.build_library(cfg, lib, lines, dust)
+        th_true = wl.make_theta(cfg, 1, seed=seed + 1002)
+        if cfg.n_pix:
+            g = wl.make_spectrum_grid(cfg.n_pix)
+            obs = om.Spectrum(g["pix_wave"], g["lsf_mode"], g["lsf_value"], g["sigma_gas_kms"], 0.0,
+                              z_ref=float(th_true[0, 1]))
+            obs.data, obs.sigma = wl.noisy_spectrum(om.predict(olib, obs, th_true)[0], seed + 5)
+        else:
+            obs = om.Photometry(filters=wl.make_filters(cfg.filters))
+            obs.data, obs.sigma = wl.noisy_photometry(om.predict(olib, obs, th_true)[0], seed + 5)
+        return cfg, olib, obs, wl.make_theta(cfg, max(cfg.batch, 64), seed=seed + 2)
+
+    def timed(fn, reps):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    for name, Bs, reps in (("c0", (64,), 5), ("c1", (64, 1024), 3), ("c3", (64,), 1)):
+        cfg, olib, obs, theta = case(name)
+        what = (f"{cfg.n_pix}-pixel spectrum" if cfg.n_pix else f"{cfg.filters} photometry") + \
+               f", library {cfg.n_age} x {len(cfg.logz)} x {cfg.n_wave}"
+        for B in Bs:
+            r = reps if B < 1024 else 1
+            if r > 1:
+                om.logl(olib, obs, theta[:B])       # warm-up
+            dt = timed(lambda: om.logl(olib, obs, theta[:B]), r)
+            legs.append(dict(workload=f"{name}: {what}", path="forward + logL (FP64)", B=B,
+                             value=round(B / dt, 2), unit="evals/s",
+                             sample=(f"median of {r} calls" if r > 1 else "one call") +
+                                    f" on {B} vectors, {dt:.2f} s per call"))
+        if name == "c3":
+            n = 16
+            t0 = time.perf_counter()
+            oa.logl_grad(olib, obs, theta[:n])
+            dt = time.perf_counter() - t0
+            legs.append(dict(workload=f"{name}: {what}", path="forward + logL + gradient (FP64 adjoint)", B=n,
+                             value=round(n / dt, 2), unit="evals/s", sample=f"one call on {n} vectors, {dt:.2f} s"))
+    return legs
 
 
 def spectrum_leg(steps=20, warmup=3, seed=0):

@@ -44,6 +44,7 @@ struct AdjArgs {
   int nl_lds;                   // line slots of the line tables in LDS (spectra)
   int seg_cap;                  // FP32 spectra: bound on the rows' span in nodes
   double fr_max;                // photometry: largest |filter-node weight|
+  int f_spans;                  // F and Yatt were formed only over the rows' spans (PointRow seg0 / seg_n)
 };
 
 __device__ __forceinline__ double block_sum256(double v, double *red) {
@@ -266,11 +267,10 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
     int *s_first = (int *)(s_h + np), *s_last = s_first + 256;
     // ln lambda of every 16th pixel, on the next 8-byte boundary (the host sizing leaves the slack)
     double *s_lp16 = (double *)(((uintptr_t)(s_last + 256) + 7) & ~(uintptr_t)7);
-    const double ext = 5.0 * ob.ksig_max * lib.inv_dlnw + 2.0;
-    const double ua = (ob.lnpix[0] - lnopz - lnw0) * lib.inv_dlnw - ext;
-    const double ub = (ob.lnpix[np - 1] - lnopz - lnw0) * lib.inv_dlnw + ext;
-    const int seg0 = (int)fmin(fmax(floor(ua), 0.0), (double)(N - 1));
-    const int seg_n = min((int)fmin(fmax(ceil(ub), 0.0), (double)(N - 1)) + 1 - seg0, a.seg_cap);
+    // the row's span as the weight builder set it (common.h: spec_span); at least one node,
+    // so that a row with a non-finite redshift still has owners in the transpose
+    const int seg0 = pr.seg0;
+    const int seg_n = max(min(pr.seg_n, a.seg_cap), 1);
     fs_seg0 = seg0;
     fs_segn = seg_n;
     float *seg = (float *)gFl;
@@ -671,13 +671,16 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
   T *GY = (T *)a.GY + (size_t)r * a.N_pad, *GO = (T *)a.GO + (size_t)r * a.N_pad;
   const double Eb = 0.85 - 1.9 * pr.delta;
   // gF is complete after the barrier: a coalesced pass, eight nodes per thread with all
-  // their loads in flight (clamped indices); each thread's sums still run in node order
+  // their loads in flight (clamped indices); each thread's sums still run in node order.
+  // d logL / d F is zero outside the row's span; where the forward pass formed F and the
+  // young part only over the rows' spans they are not read there (G = 0 is written)
+  const int sp_lo = a.f_spans ? pr.seg0 : 0, sp_hi = a.f_spans ? pr.seg0 + pr.seg_n : N;
   for (int nb = tid; nb < N; nb += 256 * 8) {
     double lq[8], gq[8], ddq[8], yq[8], fq[8];
     float lfq[8], daq[8], dfq[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int n = min(nb + 256 * u, N - 1);
+      const int n = min(max(nb + 256 * u, sp_lo), max(sp_hi - 1, 0));
       lq[u] = lib.lnlv_d[n];
       ddq[u] = lib.dust_d_d[n];
       yq[u] = (double)Yr[n];
@@ -696,6 +699,11 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
     for (int u = 0; u < 8; ++u) {
       const int n = nb + 256 * u;
       if (n >= N) break;
+      if (n < sp_lo || n >= sp_hi) {
+        GY[n] = (T)0;
+        GO[n] = (T)0;
+        continue;
+      }
       const double l = lq[u], g = gq[u];
       double p, qd, sh, Tbc, Td;
       if (sizeof(T) == 4) {   // FP32 path: the factors in FP32, as the forward epilogue forms them
@@ -756,19 +764,17 @@ __global__ void __launch_bounds__(256) k_adj_proj(DevLib lib, AdjArgs a) {
 // FP32: MFMA 32x32x2 with the reduction (wavelength) axis contiguous in both operands.
 // With n_split = 2 the wavelength tiles are halved between two blocks per output tile,
 // which write dW and dW + split_stride; the weight-builder adjoint adds the two halves.
-// With rows given (a log-uniform grid), G is zero outside each row's rest-frame span:
-// the span under the filters for photometry (span_mode 1), and for spectra (span_mode 2)
-// the pixels' rest-frame range widened by the LSF rows, [su0, su1] - ln(1+z)/dln in node
-// units; the block's wavelength range is the union of its rows' spans (two nodes of
-// margin each side).
+// With rows given (a log-uniform grid), G is zero outside each row's rest-frame span
+// (PointRow seg0 / seg_n: the span under the filters for photometry, the pixels' rest
+// range widened by the LSF rows for spectra); the block's wavelength range is the union
+// of its rows' spans (two nodes of margin each side), the whole grid if a row has none.
 // ---------------------------------------------------------------------------------
 template <int MT, int NT>
 __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, const float *__restrict__ GO,
                                                  const float *__restrict__ Ln, int N_pad, int K_pad, int K_young_pad,
                                                  const uint32_t *__restrict__ rowmask, int mask_words,
                                                  double *__restrict__ dW, int n_split, size_t split_stride,
-                                                 const PointRow *__restrict__ rows, int span_mode, double su0,
-                                                 double su1, double inv_dlnw) {
+                                                 const PointRow *__restrict__ rows) {
   constexpr int KT = 32, LDSK = KT + 4, WM = 2, WN = 2;
   constexpr int WTM = MT / WM, WTN = NT / WN, BM = WTM / 32, BN = WTN / 32;
   constexpr int A4 = MT * KT / 4 / 256, B4 = NT * KT / 4 / 256;
@@ -795,11 +801,7 @@ __global__ void __launch_bounds__(256) k_bwd_f32(const float *__restrict__ GY, c
   if (rows && tid < MT) {
     const PointRow &pr = rows[m0 + tid];
     if (pr.b >= 0) {
-      if (span_mode == 2 && pr.kind != 0 && isfinite(pr.z)) {
-        const double off = log1p(pr.z) * inv_dlnw;
-        atomicMin(&s_lo, (int)floor(su0 - off) - 2);
-        atomicMax(&s_hi, (int)ceil(su1 - off) + 3);
-      } else if (span_mode == 1 && pr.kind == 0 && pr.seg_n > 0) {
+      if (pr.seg_n > 0) {
         atomicMin(&s_lo, pr.seg0 - 2);
         atomicMax(&s_hi, pr.seg0 + pr.seg_n + 2);
       } else {
@@ -1426,6 +1428,7 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
   aa.obs_table = o->dev_obs;
   aa.F = w.F;
   aa.Yatt = w.Yatt;
+  aa.f_spans = w.f_spans && g.log_uniform ? 1 : 0;
   aa.gvec = w.gvec;
   aa.model = w.mbuf;
   aa.ld_g = o->host.n_data;
@@ -1456,8 +1459,8 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
     const size_t np = (size_t)o->host.n_data;
     double kmax = 0.0;
     for (double v : o->host.ksig) kmax = std::max(kmax, v);
-    const double ext = 5.0 * kmax * g.inv_dlnw + 2.0;
-    const double span = (o->host.lnpix.back() - o->host.lnpix.front()) * g.inv_dlnw + 2.0 * ext;
+    // the longest span spec_span gives a row at any redshift, plus the rounding of its ends
+    const double span = (o->host.lnpix.back() - o->host.lnpix.front()) * g.inv_dlnw + 2.0 * spec_span_ext(kmax, g.inv_dlnw);
     const size_t cap = (size_t)std::min((double)g.N, std::ceil(span) + 4.0);
     const size_t gbf = (cap * 4 + 15) & ~(size_t)15;
     const size_t t = ((4 * np + 15) & ~(size_t)15) + 12 * np + 2048 + 8 * (np / 16 + 2);
@@ -1490,16 +1493,6 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
       hipLaunchKernelGGL(k_bwd_f64, dim3((B_pad / 64) * (g.K_pad / 64)), dim3(256), 0, s, (const double *)aa.GY,
                          (const double *)aa.GO, g.LT64, g.N_pad, g.K_pad, g.K_young_pad, (double *)w.dW);
     } else {
-      // spectra: the pixels' range in node units (rest frame at z = 0), widened by five
-      // LSF widths and two nodes, as the projection's row span
-      double su0 = 0.0, su1 = 0.0;
-      if (spec && o->host.n_data > 0) {
-        double kmax = 0.0;
-        for (double v : o->host.ksig) kmax = std::max(kmax, v);
-        const double ext = 5.0 * kmax * g.inv_dlnw + 2.0;
-        su0 = (o->host.lnpix.front() - g.lnw0) * g.inv_dlnw - ext;
-        su1 = (o->host.lnpix.back() - g.lnw0) * g.inv_dlnw + ext;
-      }
       // halve the wavelength range over two blocks per output tile when that lowers the
       // largest number of tiles any CU has to finish (four blocks fit a CU)
       const int n_tiles = (B_pad / 64) * (g.K_pad / 64);
@@ -1508,7 +1501,7 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
       hipLaunchKernelGGL((k_bwd_f32<64, 64>), dim3(n_tiles * n_split), dim3(256), 0, s, (const float *)aa.GY,
                          (const float *)aa.GO, g.L32n, g.N_pad, g.K_pad, g.K_young_pad, (const uint32_t *)w.rowmask,
                          w.mask_words, (double *)w.dW, n_split, (size_t)w.B_pad_max * g.K_pad,
-                         g.log_uniform ? (const PointRow *)w.rows : nullptr, spec ? 2 : 1, su0, su1, g.inv_dlnw);
+                         g.log_uniform ? (const PointRow *)w.rows : nullptr);
     }
     e = hipGetLastError();
   }

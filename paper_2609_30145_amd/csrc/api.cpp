@@ -1005,9 +1005,9 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   pl.mode = mode;
   if (g.has_cont && !w.WQ) return fail(SPS_E_STATE, "workspace has no nebular-continuum buffer");
   if (e == hipSuccess) e = launch_prep(g, pl, s);
-  // forward launches on a log-uniform grid compute only the tiles whose pixels the projection
-  // reads (the rows' spans); the gradient pass needs F everywhere (the attenuation adjoint
-  // multiplies it by d logL / d F, zero outside the spans), the FP64 instance stays dense
+  // launches on a log-uniform grid compute only the tiles whose pixels the projection reads
+  // (the rows' spans); so does the gradient pass, whose attenuation adjoint reads F and the
+  // young part only where d logL / d F can be nonzero; the FP64 instance stays dense
   // the single-observation path knows its observation: a line catalogue needs no rest-frame
   // spectrum (no contraction), a calibration polynomial the model at the sorted rows and a
   // pass of its own after the projection
@@ -1017,7 +1017,8 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   if ((calib || lmarg) && (grad || !w.mbuf || !w.scr || w.ld_scr < std::max(24, 2 * one->n_data)))
     return fail(SPS_E_INVAL, "calibration polynomial / line marginalisation: no gradient, and a full workspace");
   const int n_nt = g.N_pad / 64;
-  const bool span = !grad && g.log_uniform && prec != SPS_FP64 && w.tiles && B_pad / MT <= kTileListMaxM;
+  const bool span = g.log_uniform && prec != SPS_FP64 && w.tiles && B_pad / MT <= kTileListMaxM;
+  w.f_spans = span && !lines_only;
   ContractLaunch cl;
   cl.list = span ? w.tiles : nullptr;
   if (span && !lines_only && e == hipSuccess) e = launch_tile_list(w.rows, B_pad, MT, n_nt, prec != SPS_FP32, w.tiles, s);

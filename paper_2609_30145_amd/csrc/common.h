@@ -216,13 +216,19 @@ __device__ __forceinline__ void phot_span(const DevLib &lib, double fwln_min, do
   seg_n = (int)fmin(fmax(floor(u1), 0.0), top) + 2 - seg0;
 }
 
+// Nodes by which a spectrum's span reaches past its pixels' rest range on each side: five
+// of the widest LSF row's dispersions (the rows' cut) and two nodes.
+__host__ __device__ inline double spec_span_ext(double ksig_max, double inv_dlnw) {
+  return 5.0 * ksig_max * inv_dlnw + 2.0;
+}
+
 // Rest-frame pixels [seg0, seg0 + seg_n) that the banded LSF rows of a spectrum at redshift
-// z read on a log-uniform grid: the pixels' rest range widened by five of the widest row's
-// dispersions and two nodes, clamped to the grid (none for a non-finite redshift).
+// z read on a log-uniform grid: the pixels' rest range widened by spec_span_ext, clamped to
+// the grid (none for a non-finite redshift).
 __device__ __forceinline__ void spec_span(const DevLib &lib, double lnpix_lo, double lnpix_hi, double ksig_max, double z,
                                           int &seg0, int &seg_n) {
   const double lnopz = log1p(z);
-  const double ext = 5.0 * ksig_max * lib.inv_dlnw + 2.0;
+  const double ext = spec_span_ext(ksig_max, lib.inv_dlnw);
   const double ua = (lnpix_lo - lnopz - lib.lnw0) * lib.inv_dlnw - ext;
   const double ub = (lnpix_hi - lnopz - lib.lnw0) * lib.inv_dlnw + ext;
   if (!(isfinite(ua) && isfinite(ub))) {

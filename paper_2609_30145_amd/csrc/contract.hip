@@ -530,7 +530,10 @@ hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStrea
   } else if (cl.precision == 1) {
     a.LTa = lib.LT32;
     const dim3 grid(n_mt * (lib.N_pad / 64));
-    if (cl.Yatt)
+    if (cl.Yatt && cl.list)
+      hipExtLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, true, 2, true>), grid, dim3(256), 0, s, cl.ev_start,
+                            cl.ev_stop, 0, a);
+    else if (cl.Yatt)
       hipExtLaunchKernelGGL((k_contract_f32<64, 64, 2, 2, true, 2>), grid, dim3(256), 0, s, cl.ev_start, cl.ev_stop, 0,
                             a);
     else if (cl.list)

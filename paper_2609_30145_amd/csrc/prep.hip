@@ -301,7 +301,9 @@ __device__ double tent_mass(const double *ages, const double *lr, int na, int ag
 //   C   photon-weighted young mass per age, then the line luminosities
 //   D   the row in the contraction's format with its K-tile occupancy bits, eight
 //       consecutive K entries per thread; the per-point row (redshift, distances, scales).
-template <int MODE>
+// LINEAR: the SFH scheme (lib.sfh_scheme), a template argument so that the step scheme's
+// kernel does not carry the tent integrals' registers
+template <int MODE, bool LINEAR>
 __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   using Acc = typename std::conditional<MODE == W_F64, double, float>::type;
   constexpr bool W16 = MODE == W_BF16 || MODE == W_F16;
@@ -494,7 +496,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   const double vd_lo = obp->vd_lnlo, vd_hi = obp->vd_lnhi, vd_dl = obp->vd_dlnl;
   const int vd_M = obp->vd_M, vd_n = obp->vd_nfft;
 
-  if (lib.sfh_scheme == 1) {   // the age nodes' log ratios for the tent integrals
+  if (LINEAR) {   // the age nodes' log ratios for the tent integrals
     for (int ag = 1 + tid; ag < na; ag += 256) s_lr[ag] = log(s_ages[ag] / s_ages[ag - 1]);
     __syncthreads();
   }
@@ -523,7 +525,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       if (nz > 1) split_lds(s_logz, nz, zeta, j, t);
       s_zj[i] = j;
       s_zt[i] = t;
-      if (lib.sfh_scheme == 0) {
+      if (!LINEAR) {
         s_mr[i] = s_th[TH_NSCALAR + i] / (s_edges[i + 1] - s_edges[i]);
       } else {
         // linear scheme: the factor that rescales bin i's clipped tent masses to its
@@ -630,7 +632,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   int ja = 0;
   double ta = 0.0;
   if (nf > 1) split_lds(s_afe, nf, s_th[TH_AFE], ja, ta);
-  for (int ag = tid; ag < na && lib.sfh_scheme == 1; ag += 256) {
+  for (int ag = tid; ag < na && LINEAR; ag += 256) {
     // linear scheme: every bin under the node's tent, [t_{ag-1}, t_{ag+1}] (from 0 for the
     // first node, to +inf for the last)
     const double lo = ag == 0 ? 0.0 : s_ages[ag - 1], hi = ag == na - 1 ? HUGE_VAL : s_ages[ag + 1];
@@ -662,7 +664,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       }
     }
   }
-  for (int ag = tid; ag < na && lib.sfh_scheme == 0; ag += 256) {
+  for (int ag = tid; ag < na && !LINEAR; ag += 256) {
     const double lo = s_clo[ag], hi = s_chi[ag];
     // first bin whose upper edge exceeds lo
     int i = 0;
@@ -926,23 +928,19 @@ hipError_t launch_prep(const DevLib &lib, const PrepLaunch &pl, hipStream_t s) {
   a.line_k0 = pl.line_k0;
   const size_t sm = prep_smem_bytes(lib, pl.mode);
   if (sm > 160 * 1024) return hipErrorInvalidValue;
-  static size_t attr_set[4] = {0, 0, 0, 0};
-  const void *fn[4] = {(const void *)k_prep<W_F64>, (const void *)k_prep<W_F32>, (const void *)k_prep<W_BF16>,
-                       (const void *)k_prep<W_F16>};
-  const int md = pl.mode & 3;
+  static size_t attr_set[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const void *fn[8] = {(const void *)k_prep<W_F64, false>, (const void *)k_prep<W_F32, false>,
+                       (const void *)k_prep<W_BF16, false>, (const void *)k_prep<W_F16, false>,
+                       (const void *)k_prep<W_F64, true>,  (const void *)k_prep<W_F32, true>,
+                       (const void *)k_prep<W_BF16, true>,  (const void *)k_prep<W_F16, true>};
+  const int md = (pl.mode & 3) + (lib.sfh_scheme == 1 ? 4 : 0);
   if (sm > 48 * 1024 && sm > attr_set[md]) {
     hipError_t e = hipFuncSetAttribute(fn[md], hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
     attr_set[md] = sm;
   }
-  const dim3 g(pl.B_pad), blk(256);
-  switch (pl.mode) {
-    case W_F64: hipLaunchKernelGGL(k_prep<W_F64>, g, blk, sm, s, lib, a); break;
-    case W_F32: hipLaunchKernelGGL(k_prep<W_F32>, g, blk, sm, s, lib, a); break;
-    case W_BF16: hipLaunchKernelGGL(k_prep<W_BF16>, g, blk, sm, s, lib, a); break;
-    default: hipLaunchKernelGGL(k_prep<W_F16>, g, blk, sm, s, lib, a); break;
-  }
-  return hipGetLastError();
+  void *args[2] = {(void *)&lib, (void *)&a};
+  return hipLaunchKernel(fn[md], dim3(pl.B_pad), dim3(256), args, sm, s);
 }
 
 

@@ -39,10 +39,19 @@ __device__ double sigma_inst_mode(int mode, double v, double lam) {
   }
 }
 
+// The IGM transmission where the kernel was built with it (IGM = lib.igm), else 1: a
+// template argument so that kernels without the IGM do not carry its registers.
+template <bool IGM>
+__device__ __forceinline__ double igm_at(const DevLib &lib, const double *th, double z, double lam) {
+  if constexpr (IGM) return igm_T(lib, th, z, lam);
+  else return 1.0;
+}
+
 // A library line at one point of a spectrum (App. I.1, eq. app_line_profile): its observer-
 // frame flux (the young light's birth-cloud transmission with an escape geometry's mixture,
 // the diffuse screen, mass over 4 pi D_L^2 and the IGM at the line), its observed wavelength
 // and its profile width in ln(lambda) (gas dispersion and the instrument at the line).
+template <bool IGM>
 __device__ __forceinline__ void spec_line_terms(const DevLib &lib, const DevObs &ob, const PointRow &pr,
                                                 const double *th, double Lline, int l, double &Fl, double &lobs,
                                                 double &sl) {
@@ -53,7 +62,7 @@ __device__ __forceinline__ void spec_line_terms(const DevLib &lib, const DevObs 
   const double tbc = pr.bc_p * exp(-pr.tau_bc * exp(pr.alpha_bc * lnlv)) + pr.bc_q;
   const double td = exp(-pr.tau_diff * exp(pr.delta * lnlv) * (lib.line_a[l] + (0.85 - 1.9 * pr.delta) * lib.line_d[l]));
   lobs = opz * lw;
-  Fl = Lline * tbc * td * Tfac * igm_T(lib, th, z, lobs);
+  Fl = Lline * tbc * td * Tfac * igm_at<IGM>(lib, th, z, lobs);
   double v = ob.lsf_value;
   if (ob.has_curve) {
     const int np = ob.n_data;
@@ -66,7 +75,7 @@ __device__ __forceinline__ void spec_line_terms(const DevLib &lib, const DevObs 
   sl = sqrt(ob.sigma_gas_kms * ob.sigma_gas_kms + si * si) / kC_kms;
 }
 
-template <typename T>
+template <typename T, bool IGM>
 __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
   __shared__ double red[256];
   // LDS: per-line tables (spectra) and, on the FP32 path, a segment of the model row
@@ -103,10 +112,10 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
       for (int q = 0; q < 16; ++q)
         if (k0 + 256 * q < seg_n) seg[k0 + 256 * q] = v[q];
     }
-    if (lib.igm) {   // the IGM transmission at lambda (1 + z) of the pixels blueward of Ly alpha (FP64:
+    if (IGM) {   // the IGM transmission at lambda (1 + z) of the pixels blueward of Ly alpha (FP64:
                      // optical depths of tens amplify FP32 rounding past the FP32 tolerance)
       const double *thb = a.theta + (size_t)pr.b * a.P;
-      for (int k = tid; k < seg_n; k += 256) seg[k] *= (float)igm_T(lib, thb, pr.z, lib.wave_d[seg0 + k] * (1.0 + pr.z));
+      for (int k = tid; k < seg_n; k += 256) seg[k] *= (float)igm_at<IGM>(lib, thb, pr.z, lib.wave_d[seg0 + k] * (1.0 + pr.z));
     }
   }
   const DevObs ob = a.obs_table[pr.obs];
@@ -264,7 +273,7 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
             if (in[q]) {
               const int k = kq[q];
               const double w0 = lib.wave_d[k], w1 = lib.wave_d[k + 1];
-              const T f0 = Fr[k] * (T)igm_T(lib, th, z, w0 * opz), f1 = Fr[k + 1] * (T)igm_T(lib, th, z, w1 * opz);
+              const T f0 = Fr[k] * (T)igm_at<IGM>(lib, th, z, w0 * opz), f1 = Fr[k + 1] * (T)igm_at<IGM>(lib, th, z, w1 * opz);
               const T w = sizeof(T) == 8 ? (T)ob.fr_d[j] : (T)ob.fr_f[j];
               const T t = (T)((lrq[q] - w0) / (w1 - w0));
               term = (double)(w * (f0 + t * (f1 - f0)));
@@ -299,7 +308,7 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
       const double lnlv = log(lw / kLamV);
       const double tbc = pr.bc_p * exp(-pr.tau_bc * exp(pr.alpha_bc * lnlv)) + pr.bc_q;
       const double td = exp(-pr.tau_diff * exp(pr.delta * lnlv) * (lib.line_a[l] + (0.85 - 1.9 * pr.delta) * lib.line_d[l]));
-      s_fl[l] = a.Lline[(size_t)r * nl + l] * tbc * td * Tfac * igm_T(lib, th, z, opz * lw);
+      s_fl[l] = a.Lline[(size_t)r * nl + l] * tbc * td * Tfac * igm_at<IGM>(lib, th, z, opz * lw);
     }
     __syncthreads();
     for (int k = tid; k < ob.n_data; k += 256) {
@@ -321,7 +330,7 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
       double my_max = 0.0;
       for (int l = tid; l < nl; l += 256) {
         double Fl, lobs, sl;
-        spec_line_terms(lib, ob, pr, th, a.Lline[(size_t)r * nl + l], l, Fl, lobs, sl);
+        spec_line_terms<IGM>(lib, ob, pr, th, a.Lline[(size_t)r * nl + l], l, Fl, lobs, sl);
         s_lnl[l] = log(lobs);
         s_isl[l] = 1.0 / sl;
         s_amp[l] = Fl / (2.5066282746310002 * sl);
@@ -350,11 +359,11 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
           const int k = k0 + 256 * q;
           v[q] = k < seg_n ? (float)Fr[seg0 + k] * (float)lib.lam2_d[seg0 + k] : 0.f;
         }
-        if (lib.igm) {   // the IGM transmission at lambda (1 + z), blueward of Ly alpha (FP64)
+        if (IGM) {   // the IGM transmission at lambda (1 + z), blueward of Ly alpha (FP64)
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
             const int k = k0 + 256 * q;
-            if (k < seg_n) v[q] *= (float)igm_T(lib, th, z, lib.wave_d[seg0 + k] * opz);
+            if (k < seg_n) v[q] *= (float)igm_at<IGM>(lib, th, z, lib.wave_d[seg0 + k] * opz);
           }
         }
 #pragma unroll
@@ -472,8 +481,8 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
           const double dk = lib.lnwave_d[k + 1] - lib.lnwave_d[k];
           if (s < 0.5 * dk) {
             const T t = (T)((x - lib.lnwave_d[k]) / dk);
-            const T fk = Fr[k] * (T)(lib.lam2_d[k] * igm_T(lib, th, z, lib.wave_d[k] * opz));
-            const T fk1 = Fr[k + 1] * (T)(lib.lam2_d[k + 1] * igm_T(lib, th, z, lib.wave_d[k + 1] * opz));
+            const T fk = Fr[k] * (T)(lib.lam2_d[k] * igm_at<IGM>(lib, th, z, lib.wave_d[k] * opz));
+            const T fk1 = Fr[k + 1] * (T)(lib.lam2_d[k + 1] * igm_at<IGM>(lib, th, z, lib.wave_d[k + 1] * opz));
             cont = fk + t * (fk1 - fk);
           } else {
             int j = lnwave_lower_bound(lib, x - 5.0 * s);
@@ -483,7 +492,7 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
               const double u = (lib.lnwave_d[j] - x) * inv;
               if (u > 5.0) break;
               const T w = sizeof(T) == 8 ? (T)exp(-0.5 * u * u) : (T)expf((float)(-0.5 * u * u));
-              num += (double)(w * (Fr[j] * (T)(lib.lam2_d[j] * igm_T(lib, th, z, lib.wave_d[j] * opz))));
+              num += (double)(w * (Fr[j] * (T)(lib.lam2_d[j] * igm_at<IGM>(lib, th, z, lib.wave_d[j] * opz))));
               den += (double)w;
             }
             cont = (T)(num / den);
@@ -720,7 +729,7 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
   // ---- 1. the library lines, then the fitted ones in order
   for (int l = tid; l < nl; l += 256) {
     double Fl, lobs, sl;
-    spec_line_terms(lib, ob, pr, th, a.Lline[(size_t)r * nl + l], l, Fl, lobs, sl);
+    spec_line_terms<true>(lib, ob, pr, th, a.Lline[(size_t)r * nl + l], l, Fl, lobs, sl);
     const bool flat = ob.lm_mode == 2 || (ob.lm_flat && ob.lm_flat[l]);
     t_F[l] = Fl;
     t_lnl[l] = log(lobs);
@@ -905,11 +914,13 @@ hipError_t launch_project(const DevLib &lib, const ProjectLaunch &pl, hipStream_
   if (pl.f64) {
     ProjArgs<double> a{pl.obs_table, pl.rows, (const double *)pl.F, lib.N_pad, lib.n_line, pl.theta, pl.P, pl.B,
                        pl.Lline, pl.model, pl.logl, pl.gvec, pl.gnoise, pl.msorted, pl.ld_model, pl.ld_g};
-    hipLaunchKernelGGL(k_project<double>, dim3(pl.B), dim3(256), 0, s, lib, a);
+    if (lib.igm) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_project<double, true>), dim3(pl.B), dim3(256), 0, s, lib, a);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_project<double, false>), dim3(pl.B), dim3(256), 0, s, lib, a);
   } else {
     ProjArgs<float> a{pl.obs_table, pl.rows, (const float *)pl.F, lib.N_pad, lib.n_line, pl.theta, pl.P, pl.B,
                       pl.Lline, pl.model, pl.logl, pl.gvec, pl.gnoise, pl.msorted, pl.ld_model, pl.ld_g};
-    hipLaunchKernelGGL(k_project<float>, dim3(pl.B), dim3(256), 0, s, lib, a);
+    if (lib.igm) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_project<float, true>), dim3(pl.B), dim3(256), 0, s, lib, a);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_project<float, false>), dim3(pl.B), dim3(256), 0, s, lib, a);
   }
   return hipGetLastError();
 }

@@ -50,6 +50,7 @@ struct Workspace {
   void *F = nullptr, *Yatt = nullptr;   // B_pad * N_pad * 8 bytes each
   int *tiles = nullptr;          // the contraction's tile list (k_tile_list): 1 + (B_pad/64) * (N_pad/64) ints,
                                  // then each M tile's span in N tiles (2 * B_pad/64 ints)
+  bool f_spans = false;          // the last forward pass formed F (and Yatt) only over the rows' spans
   double *Lline = nullptr;
   double *WQ = nullptr;          // nebular continuum: photon-weighted masses [B_pad][nebular ages]
   double *gvec = nullptr, *gnoise = nullptr;
