@@ -139,9 +139,15 @@ typedef struct {
    * integrated against the linear-in-ln(age) tent of each SSP age node, eq. tent_integral,
    * clipped at zero and rescaled to each bin's trapezoid mass). */
   int32_t sfh_scheme;
-  /* IGM transmission (Sec. 2.6): 0 off, 1 the Madau (1995) Lyman-series and Lyman-limit
-   * optical depth scaled by a theta column igm_factor (after frac_obrun), applied at
-   * lambda (1 + z) to the observer-frame model and to each line. */
+  /* IGM transmission (Sec. 2.6), a bit mask: 0 off; SPS_IGM_MADAU the Madau (1995)
+   * Lyman-series and Lyman-limit optical depth scaled by a theta column igm_factor (after
+   * frac_obrun), applied at lambda (1 + z) to the observer-frame model and to each line;
+   * with it, optionally, SPS_IGM_DAMPING the damping wing of a partly neutral IGM between
+   * z = 6 and the source (Miralda-Escude 1998, Totani et al. 2006; neutral fraction in a
+   * theta column x_hi; tau_GP(z) = 3.88e5 ((1 + z) / 7)^1.5; the Gunn-Peterson depth
+   * blueward of the source's Lyman alpha inside that range) and SPS_IGM_DLA a damped
+   * Lyman-alpha absorber (Tepper-Garcia 2006 Voigt profile, b = 10 km/s) of column
+   * 10^log_nhi cm^-2 at z_dla (two theta columns).  Other values: SPS_E_INVAL. */
   int32_t igm;
   /* Free stellar velocity dispersion (Sec. 2.5, App. F): > 0 adds a theta column
    * sigma_gal (km/s, after igm_factor) admitted in [0, sigma_gal_max] (a point outside
@@ -157,6 +163,7 @@ typedef struct {
 } sps_library_desc;
 
 typedef enum { SPS_SFH_STEP = 0, SPS_SFH_LINEAR = 1 } sps_sfh_scheme;
+enum { SPS_IGM_MADAU = 1, SPS_IGM_DAMPING = 2, SPS_IGM_DLA = 4 };
 
 typedef enum { SPS_ESCAPE_NONE = 0, SPS_ESCAPE_RUNAWAY_BC = 1, SPS_ESCAPE_PICKET = 2 } sps_escape;
 
@@ -183,13 +190,15 @@ void sps_library_destroy(sps_library *lib);
  * log_f_data, log_jitter), then sfh[n_sfh] bin masses (Msun formed per unit of
  * 10^logmass; node SFRs under SPS_SFH_LINEAR), then zh[n_zh] enrichment nodes, then,
  * for a library with an escape geometry, frac_obrun, then, with the IGM, igm_factor,
- * then, with a free velocity dispersion, sigma_gal (each -1 when absent).  Unused
- * columns are ignored. */
+ * x_hi with its damping wing, log_nhi and z_dla with its damped absorber, then, with a
+ * free velocity dispersion, sigma_gal (each -1 when absent).  Unused columns are
+ * ignored. */
 typedef struct {
   int32_t P, n_scalar, sfh, n_sfh, zh, n_zh;
   int32_t logmass, zred, tau_bc, alpha_bc, tau_diff, delta, logzsol, gas_logz, gas_logu, afe;
   int32_t log_err_scale, log_f_calib, log_f_data, log_jitter;
   int32_t frac_obrun, igm_factor, sigma_gal;
+  int32_t x_hi, log_nhi, z_dla;
 } sps_layout;
 sps_status sps_theta_layout(const sps_library *lib, sps_layout *out);
 

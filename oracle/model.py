@@ -33,11 +33,12 @@ SCALARS = ("logmass", "zred", "tau_bc", "alpha_bc", "tau_diff", "delta", "logzso
 ESCAPE_GEOMETRIES = ("none", "runaway_bc", "picket")
 
 
-def columns(n_sfh, n_zh, escape=False, igm=False, vdisp=False):
+def columns(n_sfh, n_zh, escape=False, igm=0, vdisp=False):
     """Column offsets of theta: the scalars, the SFH values (bin masses, or node SFRs under
     the linear scheme), the enrichment nodes, then frac_obrun = f_ob for a library with an
-    escape geometry (Sec. 2.3.2), igm_factor for one with IGM transmission (Sec. 2.6) and
-    sigma_gal [km/s] for one with a free stellar velocity dispersion (Sec. 2.5)."""
+    escape geometry (Sec. 2.3.2); for one with IGM transmission (Sec. 2.6; igm a bit mask,
+    IGM_* below) igm_factor, then x_HI with the damping wing and logN_HI, z_dla with the
+    absorber; sigma_gal [km/s] for one with a free stellar velocity dispersion (Sec. 2.5)."""
     c = {n: i for i, n in enumerate(SCALARS)}
     c["sfh"] = len(SCALARS)
     c["zh"] = len(SCALARS) + n_sfh
@@ -45,13 +46,24 @@ def columns(n_sfh, n_zh, escape=False, igm=False, vdisp=False):
     if escape:
         c["frac_obrun"] = c["P"]
         c["P"] += 1
-    if igm:
+    igm = int(igm)
+    if igm & IGM_MADAU:
         c["igm_factor"] = c["P"]
         c["P"] += 1
+    if igm & IGM_DAMPING:
+        c["x_hi"] = c["P"]
+        c["P"] += 1
+    if igm & IGM_DLA:
+        c["log_nhi"] = c["P"]
+        c["z_dla"] = c["P"] + 1
+        c["P"] += 2
     if vdisp:
         c["sigma_gal"] = c["P"]
         c["P"] += 1
     return c
+
+
+IGM_MADAU, IGM_DAMPING, IGM_DLA = 1, 2, 4   # IGM bit mask: the additions need the Madau IGM
 
 
 def lib_columns(L):
@@ -86,7 +98,7 @@ class Library:
     cont: dict | None = None  # nebular continuum cube (App. C) or None
     escape: str = "none"      # fesc_geometry: "none" (f_ob = 0), "runaway_bc", "picket"
     sfh_scheme: str = "step"  # SFH -> age weights: "step" or "linear" (App. B)
-    igm: bool = False         # Madau (1995) IGM transmission with theta[igm_factor]
+    igm: int = 0              # IGM bit mask: Madau (1995) with theta[igm_factor], + damping wing, + DLA
     sigma_gal_max: float = 0.0  # > 0: theta[sigma_gal] in [0, sigma_gal_max] km/s, Fourier stage
     flux_ion: np.ndarray | None = None   # raw ionising continuum of nebular-covered ages
 
@@ -101,7 +113,8 @@ def build_library(cfg, lib, lines=None, dust_tab=None, cont=None, escape="none",
     of log10(L_nu/Q) on the library's wavelengths with its own tau_nodes, zg_nodes and
     u_nodes (App. C).  Nebular emission goes to the SSP ages inside every cube's age
     range; they must be birth-cloud ages.  ``escape`` selects the f_ob geometry,
-    ``sfh_scheme`` the step or linear (tent-integral) weights, ``igm`` the IGM transmission,
+    ``sfh_scheme`` the step or linear (tent-integral) weights, ``igm`` the IGM transmission
+    (True or IGM_MADAU, optionally | IGM_DAMPING, | IGM_DLA),
     ``sigma_gal_max`` > 0 a free stellar velocity dispersion up to that value [km/s],
     applied in the Fourier stage (the grid must then be uniform in ln lambda).
     """
@@ -123,7 +136,9 @@ def build_library(cfg, lib, lines=None, dust_tab=None, cont=None, escape="none",
     if sfh_scheme not in ("step", "linear"):
         raise ValueError("sfh_scheme must be 'step' or 'linear'")
     L.sfh_scheme = sfh_scheme
-    L.igm = bool(igm)
+    L.igm = int(igm)
+    if L.igm not in (0, 1, 3, 5, 7):
+        raise ValueError("igm: 0, or IGM_MADAU with optional IGM_DAMPING and IGM_DLA")
     if sigma_gal_max < 0.0 or not math.isfinite(sigma_gal_max):
         raise ValueError("sigma_gal_max must be finite and >= 0")
     if sigma_gal_max > 0.0:
@@ -345,10 +360,14 @@ def line_fluxes(L: Library, th, cols, Lline, dl):
 
 def igm_transmission(L: Library, th, cols, lam_obs):
     """IGM transmission at observed wavelengths (1 without IGM): Madau (1995) with the
-    optical depth scaled by theta[igm_factor] (Sec. 2.6)."""
+    optical depth scaled by theta[igm_factor], plus the damping wing of theta[x_HI] and the
+    absorber of theta[logN_HI] at theta[z_dla] where the library has them (Sec. 2.6)."""
     if not L.igm:
         return np.ones_like(np.asarray(lam_obs, dtype=np.float64))
-    return igm.transmission(lam_obs, th[cols["zred"]], th[cols["igm_factor"]])
+    return igm.transmission(lam_obs, th[cols["zred"]], th[cols["igm_factor"]],
+                            x_hi=th[cols["x_hi"]] if L.igm & IGM_DAMPING else None,
+                            log_nhi=th[cols["log_nhi"]] if L.igm & IGM_DLA else None,
+                            z_dla=th[cols["z_dla"]] if L.igm & IGM_DLA else None)
 
 
 def predict(L: Library, obs, theta, rf=None, trunc=5.0):

@@ -200,7 +200,8 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   }
   if (d->escape < SPS_ESCAPE_NONE || d->escape > SPS_ESCAPE_PICKET) return fail(SPS_E_INVAL, "unknown escape geometry");
   if (d->sfh_scheme != SPS_SFH_STEP && d->sfh_scheme != SPS_SFH_LINEAR) return fail(SPS_E_INVAL, "unknown SFH scheme");
-  if (d->igm != 0 && d->igm != 1) return fail(SPS_E_INVAL, "igm must be 0 or 1");
+  if (d->igm != 0 && d->igm != 1 && d->igm != 3 && d->igm != 5 && d->igm != 7)
+    return fail(SPS_E_INVAL, "igm: 0, or SPS_IGM_MADAU with optional SPS_IGM_DAMPING and SPS_IGM_DLA");
   if (!(d->sigma_gal_max >= 0) || !std::isfinite(d->sigma_gal_max))
     return fail(SPS_E_INVAL, "sigma_gal_max must be finite and >= 0");
   if (d->sigma_gal_max > 0) {
@@ -267,12 +268,15 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   g.n_u = nl ? d->n_u : 0;
   g.n_sfh = d->n_sfh;
   g.n_zh = d->n_zh;
-  g.P = TH_NSCALAR + d->n_sfh + d->n_zh + (d->escape ? 1 : 0) + (d->igm ? 1 : 0) + (d->sigma_gal_max > 0 ? 1 : 0);
+  const int igm_cols = (d->igm & 1) + ((d->igm >> 1) & 1) + 2 * ((d->igm >> 2) & 1);
+  g.P = TH_NSCALAR + d->n_sfh + d->n_zh + (d->escape ? 1 : 0) + igm_cols + (d->sigma_gal_max > 0 ? 1 : 0);
   g.th_fob = TH_NSCALAR + d->n_sfh + d->n_zh;
   g.th_igm = g.th_fob + (d->escape ? 1 : 0);
   g.igm = d->igm;
+  g.th_xhi = g.th_igm + 1;
+  g.th_nhi = g.th_xhi + ((d->igm >> 1) & 1);
   g.vdisp = d->sigma_gal_max > 0 ? 1 : 0;
-  g.th_sgal = g.th_igm + (d->igm ? 1 : 0);
+  g.th_sgal = g.th_igm + igm_cols;
   g.vd_max = d->sigma_gal_max;
   g.sfh_scheme = d->sfh_scheme;
   g.escape = d->escape;
@@ -676,6 +680,9 @@ extern "C" sps_status sps_theta_layout(const sps_library *L, sps_layout *o) {
   o->frac_obrun = L->dev.escape ? L->dev.th_fob : -1;
   o->igm_factor = L->dev.igm ? L->dev.th_igm : -1;
   o->sigma_gal = L->dev.vdisp ? L->dev.th_sgal : -1;
+  o->x_hi = (L->dev.igm & 2) ? L->dev.th_xhi : -1;
+  o->log_nhi = (L->dev.igm & 4) ? L->dev.th_nhi : -1;
+  o->z_dla = (L->dev.igm & 4) ? L->dev.th_nhi + 1 : -1;
   return SPS_OK;
 }
 

@@ -57,7 +57,8 @@ struct DevLib {
   // kWqScale per pixel (cont_sc); FP64 copies in log10 units for the FP64 path.
   int has_cont, n_cz, n_cu;
   int sfh_scheme;                    // 0 step, 1 linear (tent integral; ages close prep_tab)
-  int igm, th_igm;                   // Madau IGM and the theta column of igm_factor
+  int igm, th_igm;                   // IGM bit mask (1 Madau, 2 damping wing, 4 damped absorber),
+  int th_xhi, th_nhi;                //   theta columns of igm_factor, x_HI, logN_HI (z_dla next)
   int vdisp, th_sgal;                // free stellar velocity dispersion and its theta column
   double vd_max;                     // largest admitted sigma_gal [km/s]
   const double *cz, *cu;
@@ -467,13 +468,15 @@ __device__ __forceinline__ void grid_split_dev(const double *nodes, int n, doubl
 // Lyman-limit systems below the source's limit, at observed wavelength lam (A).
 template <typename T>
 __device__ __forceinline__ T igm_tau(T lam, T z) {
-  const T lj[4] = {(T)1215.67, (T)1025.72, (T)972.54, (T)949.74};
-  const T aj[4] = {(T)3.6e-3, (T)1.7e-3, (T)1.2e-3, (T)9.3e-4};
   const T xe = (T)1 + z;
   T tau = (T)0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-    if (lam > lj[j] && lam < lj[j] * xe) tau += aj[j] * exp((T)3.46 * log(lam / lj[j]));
+  auto series = [&](T lj, T aj) {   // Lyman alpha .. delta
+    if (lam > lj && lam < lj * xe) tau += aj * exp((T)3.46 * log(lam / lj));
+  };
+  series((T)1215.67, (T)3.6e-3);
+  series((T)1025.72, (T)1.7e-3);
+  series((T)972.54, (T)1.2e-3);
+  series((T)949.74, (T)9.3e-4);
   const T xc = lam / (T)911.75;
   if (xc > (T)1 && xc < xe) {
     const T lc = log(xc), le = log(xe);
@@ -485,11 +488,55 @@ __device__ __forceinline__ T igm_tau(T lam, T z) {
   return tau;
 }
 
-// IGM transmission of a point (theta row th) at observed wavelength lam: 1 without the IGM
-// or redward of Ly alpha.
+// Damping wing of a partly neutral IGM (Miralda-Escude 1998, Totani et al. 2006): neutral
+// fraction x between z = 6 and the source at z.  Redward of the source's Lyman alpha the
+// scattering wing integrated through the region, x tau_GP(z) (R_alpha / pi) ((1 + z_o) /
+// (1 + z))^1.5 [I(x_u) - I(x_l)] with I the antiderivative of t^4.5 / (1 - t)^2, x_u = (1 +
+// z) / (1 + z_o), x_l = 7 / (1 + z_o); blueward, inside the region, the Gunn-Peterson
+// depth x tau_GP(z_o); tau_GP(z) = 3.88e5 ((1 + z) / 7)^1.5.
+__device__ __forceinline__ double igm_damping_I(double t) {
+  const double s = sqrt(t);
+  return t * t * t * t * s / (1.0 - t) + (9.0 / 7.0) * t * t * t * s + 1.8 * t * t * s + 3.0 * t * s + 9.0 * s -
+         4.5 * log((1.0 + s) / (1.0 - s));
+}
+__device__ __forceinline__ double igm_damping_tau(double lam, double z, double x) {
+  const double zl = 6.0, opz_o = lam / 1215.67, opz = 1.0 + z;
+  if (!(z > zl) || x == 0.0) return 0.0;
+  const double gp = 3.88e5 / (7.0 * 2.6457513110645906);   // tau_GP / (1 + z)^1.5
+  if (opz_o > opz) {
+    const double r_alpha = 6.265e8 * 1215.67e-8 / (4.0 * kPi * kC_cms);
+    return x * gp * opz_o * sqrt(opz_o) * (r_alpha / kPi) *
+           (igm_damping_I(opz / opz_o) - igm_damping_I((1.0 + zl) / opz_o));
+  }
+  if (opz_o > 1.0 + zl) return x * gp * opz_o * sqrt(opz_o);
+  return 0.0;
+}
+// Damped Lyman-alpha absorber (Tepper-Garcia 2006): column 10^lnh cm^-2 at zd, Doppler
+// parameter 10 km/s; N (pi e^2 / m_e c) f H(a, x) / (sqrt(pi) dnu_D), x = (nu - nu_alpha) /
+// dnu_D in the absorber's frame, H by Tepper-Garcia's approximation (for x^2 < 1e-4 its
+// limit H0 - a (2 - 4 x^2 + 5/3 x^4) / sqrt(pi), free of the cancellation).
+__device__ __forceinline__ double igm_dla_tau(double lam, double zd, double lnh) {
+  const double lam_a = 1215.67e-8, dnu_d = 10.0e5 / lam_a;
+  const double a = 6.265e8 / (4.0 * kPi * dnu_d);
+  const double x = (kC_cms * (1.0 + zd) / (lam * 1e-8) - kC_cms / lam_a) / dnu_d;
+  const double u = x * x, h0 = exp(-u);
+  const double corr = u < 1e-4 ? 2.0 - 4.0 * u + (5.0 / 3.0) * u * u
+                               : (h0 * h0 * (4.0 * u * u + 7.0 * u + 4.0 + 1.5 / u) - 1.5 / u - 1.0) / u;
+  const double H = h0 - a * corr * 0.56418958354775628;   // 1 / sqrt(pi)
+  // pi e^2 / (m_e c) f_alpha / sqrt(pi), cgs
+  const double k = kPi * 4.80320471e-10 * 4.80320471e-10 / (9.1093837015e-28 * kC_cms) * 0.4164 * 0.56418958354775628;
+  return exp10(lnh) * k * H / dnu_d;
+}
+
+// IGM transmission of a point (theta row th) at observed wavelength lam: 1 without the IGM;
+// the Madau depth (blueward of Ly alpha) scaled by igm_factor, plus the damping wing and
+// the absorber where the library has them.
 __device__ __forceinline__ double igm_T(const DevLib &lib, const double *th, double z, double lam) {
-  if (!lib.igm || !(lam < 1215.67 * (1.0 + z))) return 1.0;
-  return exp(-th[lib.th_igm] * igm_tau<double>(lam, z));
+  if (!lib.igm) return 1.0;
+  double tau = lam < 1215.67 * (1.0 + z) ? th[lib.th_igm] * igm_tau<double>(lam, z) : 0.0;
+  if (lib.igm & 2) tau += igm_damping_tau(lam, z, th[lib.th_xhi]);
+  if (lib.igm & 4) tau += igm_dla_tau(lam, th[lib.th_nhi + 1], th[lib.th_nhi]);
+  return tau == 0.0 ? 1.0 : exp(-tau);
 }
 
 

@@ -439,11 +439,35 @@ __global__ void __launch_bounds__(256) k_tile_list(const PointRow *__restrict__ 
       hi[m] = -1;
     }
     __syncthreads();
-    for (int r = tid; r < B_pad; r += 256) {
-      const PointRow &pr = rows[r];
-      if (pr.b >= 0 && pr.cov_n > 0) {   // one pixel of margin each side
-        atomicMin(&lo[r / MT], max(pr.cov0 - 1, 0) / kSpanTile);
-        atomicMax(&hi[r / MT], min(pr.cov0 + pr.cov_n, n_nt * kSpanTile - 1) / kSpanTile);
+    // the 64 consecutive rows of a wave lie in one M tile (MT is 64 or 128): eight rows
+    // per lane with their loads in flight, a wave reduction, one LDS atomic per wave and row
+    // group (one pixel of margin each side of a row's span)
+    for (int base = 0; base < B_pad; base += 256 * 8) {
+      int b[8], c0[8], cn[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int r = min(base + 256 * q + tid, B_pad - 1);
+        b[q] = rows[r].b;
+        c0[q] = rows[r].cov0;
+        cn[q] = rows[r].cov_n;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int r0 = base + 256 * q + wv * 64;
+        if (r0 >= B_pad) break;
+        int l = INT_MAX, h = -1;
+        if (b[q] >= 0 && cn[q] > 0) {
+          l = max(c0[q] - 1, 0) / kSpanTile;
+          h = min(c0[q] + cn[q], n_nt * kSpanTile - 1) / kSpanTile;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          l = min(l, __shfl_xor(l, o));
+          h = max(h, __shfl_xor(h, o));
+        }
+        if (lane == 0) {
+          atomicMin(&lo[r0 / MT], l);
+          atomicMax(&hi[r0 / MT], h);
+        }
       }
     }
   }

@@ -182,7 +182,7 @@ __device__ __forceinline__ double wave_max(double v) {
 // FP64 for the FP64 path and FP32 otherwise).  The node tables (logz .. Q) are one
 // contiguous run in the order of DevLib::prep_tab, so that they arrive in one copy.
 struct PrepSmem {
-  int th, logz, afe, clo, chi, zg, un, Q, ages, edges, mr, zt, zj, wq, ke, wacc, lt, lr, total;
+  int th, logz, afe, clo, chi, zg, un, Q, ages, edges, mr, zt, zj, wq, ke, wacc, lt, lr, pc, pidx, total;
   __host__ __device__ PrepSmem(const DevLib &lib, int mode) {
     const bool f64 = mode == 0, w16 = mode >= 2;
     const int acc = f64 ? 8 : 4;
@@ -206,6 +206,12 @@ struct PrepSmem {
     wacc = o;  o += (lib.K_pad * acc + 7) / 8;
     lt = o;    o += (lib.n_line * lib.n_young * acc + 7) / 8;
     lr = o;    o += lib.sfh_scheme ? lib.n_age : 0;       // ln(t_a / t_{a-1}) (linear scheme)
+    // linear scheme: the tent masses of the (bin, node) pairs whose intervals overlap.  A
+    // tent spans two of the n_age + 1 cells between nodes, and a bin partition and a cell
+    // partition of one line overlap in at most n_sfh + n_age + 1 pairs, so 2 (n_sfh +
+    // n_age + 1) pairs, plus two per bin of zero width (one point inside at most two tents)
+    pc = o;    o += lib.sfh_scheme ? 4 * lib.n_sfh + 2 * lib.n_age + 2 : 0;
+    pidx = o;  o += lib.sfh_scheme ? lib.n_sfh + 1 : 0;     // int: each bin's first node, pair offsets
     total = o;
   }
 };
@@ -316,6 +322,8 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   double *s_Q = smem + L.Q, *s_edges = smem + L.edges, *s_mr = smem + L.mr, *s_zt = smem + L.zt;
   const double *s_ages = smem + L.ages;
   double *s_lr = smem + L.lr;
+  double *s_pc = smem + L.pc;
+  int *s_plo = (int *)(smem + L.pidx), *s_poff = s_plo + n_sfh;
   double *s_wq = smem + L.wq;
   int *s_zj = (int *)(smem + L.zj);
   const int16_t *s_ke = (const int16_t *)(smem + L.ke);
@@ -528,12 +536,12 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       if (!LINEAR) {
         s_mr[i] = s_th[TH_NSCALAR + i] / (s_edges[i + 1] - s_edges[i]);
       } else {
-        // linear scheme: the factor that rescales bin i's clipped tent masses to its
-        // trapezoid mass (p_i + p_{i+1}) (T_{i+1} - T_i) / 2, the last SFR repeated
+        // linear scheme: the nodes whose tents [t_{ag-1}, t_{ag+1}] meet the bin, in
+        // increasing order: from the first whose tent ends above T0 (bisection) while the
+        // tent starts below T1; their count, and the bin's trapezoid mass (p_i + p_{i+1})
+        // (T_{i+1} - T_i) / 2 (the last SFR repeated), which the tent masses are rescaled to
         const double p0 = s_th[TH_NSCALAR + i], p1 = s_th[TH_NSCALAR + min(i + 1, n_sfh - 1)];
         const double T0 = s_edges[i], T1 = s_edges[i + 1];
-        // the nodes whose tents [t_{ag-1}, t_{ag+1}] meet the bin, in increasing order: from
-        // the first whose tent ends above T0 (bisection) while the tent starts below T1
         int ag = 0;
         {
           int l = 0, h = na - 1;
@@ -543,11 +551,11 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
           }
           ag = l;
         }
-        double sum = 0.0;
-        for (; ag < na && (ag == 0 ? 0.0 : s_ages[ag - 1]) < T1; ++ag)
-          sum += fmax(tent_mass(s_ages, s_lr, na, ag, T0, T1, p0, p1), 0.0);
-        const double m = 0.5 * (p0 + p1) * (T1 - T0);
-        s_mr[i] = sum > 0.0 ? m / sum : 1.0;
+        s_plo[i] = ag;
+        int cnt = 0;
+        for (; ag < na && (ag == 0 ? 0.0 : s_ages[ag - 1]) < T1; ++ag) ++cnt;
+        s_poff[i + 1] = cnt;
+        s_mr[i] = 0.5 * (p0 + p1) * (T1 - T0);
       }
     }
   }
@@ -628,6 +636,45 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
   }
   __syncthreads();
 
+  if (LINEAR) {
+    // the (bin, node) pairs: offsets by an exclusive scan of the bins' counts (wave 0, 64
+    // bins at a time), every pair's clipped tent mass once (all threads), then each bin's
+    // rescaling factor from its pairs in node order
+    if (wv == 0) {
+      int carry = 0;
+      for (int i0 = 0; i0 < n_sfh; i0 += 64) {
+        const int i = i0 + lane;
+        int incl = i < n_sfh ? s_poff[i + 1] : 0;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int v = __shfl_up(incl, o, 64);
+          if (lane >= o) incl += v;
+        }
+        if (i < n_sfh) s_poff[i + 1] = carry + incl;
+        carry += __shfl(incl, 63, 64);
+      }
+      if (lane == 0) s_poff[0] = 0;
+    }
+    __syncthreads();
+    const int n_pairs = s_poff[n_sfh];
+    for (int p = tid; p < n_pairs; p += 256) {
+      int l = 0, h = n_sfh - 1;   // the pair's bin: the last i with s_poff[i] <= p
+      while (l < h) {
+        const int mid = (l + h + 1) >> 1;
+        if (s_poff[mid] <= p) l = mid; else h = mid - 1;
+      }
+      const int i = l, ag = s_plo[i] + (p - s_poff[i]);
+      const double p0 = s_th[TH_NSCALAR + i], p1 = s_th[TH_NSCALAR + min(i + 1, n_sfh - 1)];
+      s_pc[p] = fmax(tent_mass(s_ages, s_lr, na, ag, s_edges[i], s_edges[i + 1], p0, p1), 0.0);
+    }
+    __syncthreads();
+    for (int i = tid; i < n_sfh; i += 256) {
+      double sum = 0.0;
+      for (int p = s_poff[i]; p < s_poff[i + 1]; ++p) sum += s_pc[p];
+      s_mr[i] = sum > 0.0 ? s_mr[i] / sum : 1.0;
+    }
+    __syncthreads();
+  }
+
   // ---- B: overlap of SFH bin i with the linear-time cell of age ag (App. B)
   int ja = 0;
   double ta = 0.0;
@@ -646,8 +693,7 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
       i = l;
     }
     for (; i < n_sfh && s_edges[i] < hi; ++i) {
-      const double p0 = s_th[TH_NSCALAR + i], p1 = s_th[TH_NSCALAR + min(i + 1, n_sfh - 1)];
-      const double c = fmax(tent_mass(s_ages, s_lr, na, ag, s_edges[i], s_edges[i + 1], p0, p1), 0.0);
+      const double c = s_pc[s_poff[i] + (ag - s_plo[i])];   // the pair's clipped tent mass
       if (c == 0.0) continue;
       const double w = c * s_mr[i];
       const int j = s_zj[i];

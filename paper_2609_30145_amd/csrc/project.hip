@@ -76,7 +76,7 @@ __device__ __forceinline__ void spec_line_terms(const DevLib &lib, const DevObs 
 }
 
 template <typename T, bool IGM>
-__global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
+__global__ void __launch_bounds__(256, IGM ? 3 : 4) k_project(DevLib lib, ProjArgs<T> a) {
   __shared__ double red[256];
   // LDS: per-line tables (spectra) and, on the FP32 path, a segment of the model row
   // (photometry: the pixels under the filters; spectra: the pixels under the LSF rows);
@@ -359,17 +359,13 @@ __global__ void __launch_bounds__(256, 4) k_project(DevLib lib, ProjArgs<T> a) {
           const int k = k0 + 256 * q;
           v[q] = k < seg_n ? (float)Fr[seg0 + k] * (float)lib.lam2_d[seg0 + k] : 0.f;
         }
-        if (IGM) {   // the IGM transmission at lambda (1 + z), blueward of Ly alpha (FP64)
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int k = k0 + 256 * q;
-            if (k < seg_n) v[q] *= (float)igm_at<IGM>(lib, th, z, lib.wave_d[seg0 + k] * opz);
-          }
-        }
 #pragma unroll
         for (int q = 0; q < 8; ++q)
           if (k0 + 256 * q < seg_n) seg[k0 + 256 * q] = v[q];
       }
+      if (IGM)   // the IGM transmission at lambda (1 + z), blueward of Ly alpha (FP64), on the
+                 // entries this thread staged
+        for (int k = tid; k < seg_n; k += 256) seg[k] *= (float)igm_at<IGM>(lib, th, z, lib.wave_d[seg0 + k] * opz);
       __syncthreads();
       const double dln = 1.0 / lib.inv_dlnw;
       int lwin = 0;   // start of the line window: pixels rise with i, so it only moves up

@@ -55,7 +55,7 @@ class Layout(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "P", "n_scalar", "sfh", "n_sfh", "zh", "n_zh", "logmass", "zred", "tau_bc", "alpha_bc", "tau_diff",
         "delta", "logzsol", "gas_logz", "gas_logu", "afe", "log_err_scale", "log_f_calib", "log_f_data",
-        "log_jitter", "frac_obrun", "igm_factor", "sigma_gal")]
+        "log_jitter", "frac_obrun", "igm_factor", "sigma_gal", "x_hi", "log_nhi", "z_dla")]
 
 
 class ObsDesc(C.Structure):
@@ -141,13 +141,14 @@ class Library:
 
     def __init__(self, lib_arrays: dict, n_sfh: int, T1: float, n_zh: int, cosmo=(70.0, 0.3),
                  dust: dict | None = None, lines: dict | None = None, precisions=("fp32",), device: int = 0,
-                 cont: dict | None = None, escape: str = "none", sfh_scheme: str = "step", igm: bool = False,
+                 cont: dict | None = None, escape: str = "none", sfh_scheme: str = "step", igm: int = 0,
                  sigma_gal_max: float = 0.0):
         """``device=-1`` loads a host-only library (layout and observation operators; used by
         the mock server executor).  ``lines`` may carry ``line_tau`` (the table's own age axis);
         ``cont`` is a nebular continuum cube (cont_table [tau][zg][u][wave], tau_nodes,
         zg_nodes, u_nodes); ``escape`` is "none", "runaway_bc" or "picket"; ``sfh_scheme`` is
-        "step" or "linear"; ``igm`` switches the Madau IGM transmission on; ``sigma_gal_max`` > 0
+        "step" or "linear"; ``igm`` the IGM transmission: True or 1 (Madau), 3 (+ damping wing), 5
+        (+ damped absorber) or 7 (both); ``sigma_gal_max`` > 0
         adds a free stellar velocity dispersion column (km/s, Fourier stage)."""
         L = lib()
         keep = []
@@ -188,7 +189,7 @@ class Library:
             d.cont_tau, d.cont_zg, d.cont_u, d.cont_table = _ptr(ct), _ptr(cz), _ptr(cu), _ptr(cc)
         d.escape = ESCAPE[escape]
         d.sfh_scheme = SFH_SCHEMES[sfh_scheme]
-        d.igm = 1 if igm else 0
+        d.igm = int(igm)
         d.sigma_gal_max = float(sigma_gal_max)
         mask = 0
         for p in precisions:

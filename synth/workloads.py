@@ -43,10 +43,12 @@ THETA_SCALARS = (
 N_SCALARS = len(THETA_SCALARS)
 
 
-def theta_columns(n_sfh: int, n_zh: int, escape: bool = False, igm: bool = False, vdisp: bool = False) -> dict:
+def theta_columns(n_sfh: int, n_zh: int, escape: bool = False, igm: int = 0, vdisp: bool = False) -> dict:
     """Column offsets of the theta layout (scalars, then sfh[n_sfh], then zh[n_zh], then,
     for a library with an ionising-photon escape geometry, frac_obrun, then, with IGM
-    transmission, igm_factor, then, with a free stellar velocity dispersion, sigma_gal)."""
+    transmission (igm: bit mask, 1 Madau, 2 damping wing, 4 damped absorber), igm_factor,
+    x_HI, logN_HI and z_dla as present, then, with a free stellar velocity dispersion,
+    sigma_gal)."""
     cols = {name: i for i, name in enumerate(THETA_SCALARS)}
     cols["sfh"] = N_SCALARS
     cols["zh"] = N_SCALARS + n_sfh
@@ -54,9 +56,17 @@ def theta_columns(n_sfh: int, n_zh: int, escape: bool = False, igm: bool = False
     if escape:
         cols["frac_obrun"] = cols["P"]
         cols["P"] += 1
-    if igm:
+    igm = int(igm)
+    if igm & 1:
         cols["igm_factor"] = cols["P"]
         cols["P"] += 1
+    if igm & 2:
+        cols["x_hi"] = cols["P"]
+        cols["P"] += 1
+    if igm & 4:
+        cols["log_nhi"] = cols["P"]
+        cols["z_dla"] = cols["P"] + 1
+        cols["P"] += 2
     if vdisp:
         cols["sigma_gal"] = cols["P"]
         cols["P"] += 1
@@ -337,8 +347,10 @@ def make_theta(cfg: Config, B: int | None = None, seed: int = 2, escape: bool = 
     one solar mass (the continuity-prior shape of Sec. 4.2, applied to masses).
     Enrichment history: zeta_0 ~ U(-2.2, 0.3) plus a clipped Student-t random
     walk with sigma 0.2, clamped to the grid.  With ``escape``, a column frac_obrun ~
-    U(0, 1) and with ``igm`` a column igm_factor ~ U(0.5, 1.5), each from a stream of its
-    own (the other columns are unchanged); with ``vdisp`` > 0 a column sigma_gal ~
+    U(0, 1) and with ``igm`` a column igm_factor ~ U(0.5, 1.5) (with the damping wing x_HI ~
+    U(0, 1); with the damped absorber logN_HI ~ U(20, 22) and z_dla = z - U(0, 0.5),
+    floored at 0), each from a stream of its own (the other columns are unchanged); with
+    ``vdisp`` > 0 a column sigma_gal ~
     U(0, vdisp) km/s.  Under the linear SFH scheme the SFH values are node SFRs: the bin
     masses divided by 1e10 / n_sfh years.
     """
@@ -350,11 +362,18 @@ def make_theta(cfg: Config, B: int | None = None, seed: int = 2, escape: bool = 
         th[:, cols["sigma_gal"]] = np.random.default_rng(seed + 15485863).uniform(0.0, vdisp, B)
     if escape:
         th[:, cols["frac_obrun"]] = np.random.default_rng(seed + 7919).uniform(0.0, 1.0, B)
-    if igm:
+    igm = int(igm)
+    if igm & 1:
         th[:, cols["igm_factor"]] = np.random.default_rng(seed + 104729).uniform(0.5, 1.5, B)
+    if igm & 2:
+        th[:, cols["x_hi"]] = np.random.default_rng(seed + 1299709).uniform(0.0, 1.0, B)
     zlo, zhi = cfg.z_range
     th[:, cols["logmass"]] = rng.uniform(8.0, 11.0, B)
     th[:, cols["zred"]] = rng.uniform(zlo, zhi, B)
+    if igm & 4:
+        r4 = np.random.default_rng(seed + 15485867)
+        th[:, cols["log_nhi"]] = r4.uniform(20.0, 22.0, B)
+        th[:, cols["z_dla"]] = np.maximum(th[:, cols["zred"]] - r4.uniform(0.0, 0.5, B), 0.0)
     th[:, cols["gas_logz"]] = -0.5
     th[:, cols["gas_logu"]] = -2.5
     th[:, cols["alpha_bc"]] = -0.7

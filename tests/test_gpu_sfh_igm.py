@@ -6,6 +6,10 @@ inputs, through the C ABI:
     on an [alpha/Fe] library (photometry);
   - the IGM on photometry (redshifts 0.5-12, so that the bluest bands cross the Lyman
     alpha forest and the Lyman limit) and on a spectrum with lines;
+  - the Madau IGM with the damping wing of a partly neutral IGM and a damped Lyman-alpha
+    absorber (Sec. 2.6), on photometry and on a spectrum, with sources on both sides of
+    z = 6, x_HI of 0 and 1, absorbers at the source, far in front of it, of negligible and
+    of saturating column;
   - everything at once: linear SFH, IGM, nebular continuum and the runaway_bc escape;
   - a batch over several M tiles with a ragged tail at FP64, FP32, FP16 hi + residual
     (three passes) and, on photometry, FP16 hi + weight residual;
@@ -78,8 +82,16 @@ def check(tag, case, L, O, theta, spec):
 
 def theta_of(case, seed=91):
     th = np.concatenate([case["theta"][:B - 24], near_truth(case["cfg"], case["theta_true"], 24, seed)])
+    cols = om.lib_columns(case["olib"])
     if case["igm"]:
-        th[:4, -1] = [0.0, 1.0, 2.0, 0.3]   # igm_factor: off, nominal, doubled, weak
+        th[:4, cols["igm_factor"]] = [0.0, 1.0, 2.0, 0.3]   # off, nominal, doubled, weak
+    if "x_hi" in cols:   # the damping wing: sources on both sides of z = 6, fully neutral, none
+        th[4:12, 1] = [5.9, 6.0, 6.05, 6.5, 7.5, 9.0, 11.0, 11.9]
+        th[4:8, cols["x_hi"]] = [1.0, 0.0, 1.0, 0.5]
+    if "log_nhi" in cols:   # the absorber: at the source, far in front, negligible, saturated
+        th[12:16, 1] = [3.0, 7.0, 9.5, 11.0]
+        th[12:16, cols["z_dla"]] = [3.0, 5.0, 9.4, 10.999]
+        th[12:16, cols["log_nhi"]] = [22.0, 20.3, 0.0, 21.7]
     return th
 
 
@@ -88,6 +100,8 @@ CASES = {
     "linear_alpha": (CFG_ALPHA, "phot", dict(sfh_scheme="linear")),
     "igm_phot": (CFG_PHOT, "phot", dict(igm=True)),
     "igm_spec": (CFG_SPEC, "spec", dict(igm=True)),
+    "igm_wing_dla_phot": (CFG_PHOT, "phot", dict(igm=7)),
+    "igm_wing_dla_spec": (CFG_SPEC, "spec", dict(igm=7)),
     "all_phot": (CFG_PHOT, "phot", dict(sfh_scheme="linear", igm=True, cont=True, escape="runaway_bc")),
     "all_spec": (CFG_SPEC, "spec", dict(sfh_scheme="linear", igm=True, cont=True, escape="runaway_bc")),
 }
@@ -110,7 +124,8 @@ def test_layout_and_gradient_refusal(case):
     name, c, L, O = case
     cols = om.lib_columns(c["olib"])
     assert L.layout["P"] == cols["P"]
-    assert L.layout["igm_factor"] == cols.get("igm_factor", -1)
+    for k in ("igm_factor", "x_hi", "log_nhi", "z_dla", "sigma_gal"):
+        assert L.layout[k] == cols.get(k, -1)
     th = torch.tensor(theta_of(c)[:8], dtype=torch.float64, device="cuda")
     with pytest.raises(sps.SpsError) as ei:
         sps.logl_grad(L, O, th, "fp32")

@@ -8,6 +8,14 @@ not pinned by anything outside the formula (parity unpinned); the pins fix its s
 identity redward of Lyman alpha and at zero scaling, the power law in the optical-depth
 scaling, the Lyman alpha forest's lambda^3.46 law, continuity at the Lyman limit, and that
 photometric bands redward of Lyman alpha are untouched.
+
+The two optional additions are pinned from outside their formulas: the damping wing's
+closed form against direct quadrature of the optical depth it integrates (the Lorentzian
+wing of Lyman alpha through a neutral, matter-dominated IGM whose density is fixed by the
+Gunn-Peterson depth), Tepper-Garcia's Voigt approximation against the Faddeeva function
+(scipy) within the approximation's accuracy, the absorber's far wings against the pure
+Lorentzian and its line centre against the Doppler core; and both vanish in their limits
+(x_HI = 0, a source below the neutral region, a negligible column).
 """
 import numpy as np
 import pytest
@@ -169,3 +177,96 @@ def test_model_bands_redward_of_lyman_alpha_are_untouched_by_the_igm():
     th[:, 1] = 9.0                                   # now the bluest bands see the forest
     m0, m1 = om.predict(L0, obs, th[:, :-1]), om.predict(L1, obs, th)
     assert np.all(m1 <= m0) and np.any(m1 < 0.9 * m0)
+
+
+# the damping wing and the damped absorber (Sec. 2.6): constants of Lyman alpha in cgs
+_K_LYA = np.pi * igm.E_ESU ** 2 / (igm.ME_G * igm.C_CMS) * igm.LYA_F     # integrated cross-section [cm^2 Hz]
+_NU_A = igm.C_CMS / igm.LYA_CM
+
+
+def test_damping_wing_is_the_lorentzian_wing_integrated_through_the_neutral_igm():
+    from scipy.integrate import quad
+    z, x_hi = 8.3, 0.7
+    for lam in (1215.67 * (1 + z) * np.array([1.0005, 1.003, 1.02, 1.1, 1.5])):
+        # optical depth from z_l = 6 to the source: n_HI sigma c dt, with n_HI / H(z) fixed by
+        # tau_GP(z) = K lambda_alpha n_HI(z) / H(z) and dt = dz / ((1 + z) H(z)); the wing of
+        # the cross-section, K Gamma / (4 pi^2 (nu - nu_alpha)^2) with the Rayleigh factor
+        # (nu / nu_alpha)^4 of the scattering wing, at nu = c (1 + z') / lambda_obs
+        def dtau(zp):
+            nu = igm.C_CMS * (1.0 + zp) / (lam * 1e-8)
+            return (x_hi * float(igm.tau_gp(zp)) / (_K_LYA * igm.LYA_CM) * _K_LYA * igm.LYA_GAMMA
+                    * (nu / _NU_A) ** 4 / (4.0 * np.pi ** 2 * (nu - _NU_A) ** 2) * igm.C_CMS / (1.0 + zp))
+        direct = quad(dtau, igm.Z_NEUTRAL_END, z, epsabs=0.0, epsrel=1e-12, limit=200)[0]
+        assert float(igm.damping_wing_tau(np.array([lam]), z, x_hi)[0]) == pytest.approx(direct, rel=1e-9, abs=0.0)
+
+
+def test_damping_wing_limits_and_the_trough():
+    lam = np.geomspace(7000.0, 30000.0, 400)
+    assert np.all(igm.damping_wing_tau(lam, 5.5, 0.8) == 0.0)          # source below the neutral region
+    assert np.all(igm.damping_wing_tau(lam, 9.0, 0.0) == 0.0)
+    tau = igm.damping_wing_tau(lam, 9.0, 0.5)
+    red = lam > 1215.67 * 10.0
+    assert np.all(np.diff(tau[red]) < 0.0) and tau[red][-1] < 1e-2       # the wing decays redward
+    trough = (lam > 1215.67 * 7.0) & (lam < 1215.67 * 10.0)
+    assert np.all(tau[trough] > 1e4)                                       # Gunn-Peterson: no flux
+    assert np.all(tau[lam < 1215.67 * 7.0] == 0.0)
+    np.testing.assert_allclose(igm.damping_wing_tau(lam, 9.0, 0.25), 0.5 * tau, rtol=1e-14, atol=0.0)
+
+
+def test_voigt_approximation_against_the_faddeeva_function():
+    from scipy.special import wofz
+    dnu_d = igm.DLA_B_KMS * 1e5 / igm.LYA_CM
+    a = igm.LYA_GAMMA / (4.0 * np.pi * dnu_d)
+    x = np.concatenate([[0.0, 1e-4, 9e-3, 1.1e-2], np.linspace(0.02, 12.0, 3000), np.geomspace(12.0, 1e5, 300)])
+    exact = wofz(x + 1j * a).real
+    got = igm.voigt_tepper_garcia(a, x)
+    # the approximation's own accuracy at this damping parameter: a few per cent where the
+    # Doppler core gives way to the wings, far better in the core and the wings
+    assert np.max(np.abs(got - exact) / exact) < 0.035
+    core, near, wing = x < 1.0, x > 6.0, x > 12.0
+    assert np.max(np.abs(got - exact)[core] / exact[core]) < 1e-3
+    assert np.max(np.abs(got - exact)[near] / exact[near]) < 5e-3
+    assert np.max(np.abs(got - exact)[wing] / exact[wing]) < 1e-3
+
+
+def test_damped_absorber_wing_centre_and_column():
+    z_dla, lnh = 6.2, 21.3
+    N = 10.0 ** lnh
+    dnu_d = igm.DLA_B_KMS * 1e5 / igm.LYA_CM
+    a = igm.LYA_GAMMA / (4.0 * np.pi * dnu_d)
+    # line centre: the Doppler core, H(a, 0) = 1 - 2 a / sqrt(pi) to first order in a
+    lam_c = 1215.67 * (1 + z_dla)
+    t0 = float(igm.dla_tau(np.array([lam_c]), z_dla, lnh)[0])
+    assert t0 == pytest.approx(N * _K_LYA / (np.sqrt(np.pi) * dnu_d) * (1.0 - 2.0 * a / np.sqrt(np.pi)),
+                               rel=1e-6, abs=0.0)
+    # far wings: the Lorentzian N K Gamma / (4 pi^2 (nu - nu_alpha)^2)
+    lam = lam_c * np.array([0.97, 0.99, 1.01, 1.05])
+    nu = igm.C_CMS * (1 + z_dla) / (lam * 1e-8)
+    lor = N * _K_LYA * igm.LYA_GAMMA / (4.0 * np.pi ** 2 * (nu - _NU_A) ** 2)
+    np.testing.assert_allclose(igm.dla_tau(lam, z_dla, lnh), lor, rtol=2e-3, atol=0.0)
+    # linear in the column
+    np.testing.assert_allclose(igm.dla_tau(lam, z_dla, lnh - 1.0), 0.1 * igm.dla_tau(lam, z_dla, lnh), rtol=1e-13)
+
+
+def test_model_with_negligible_additions_is_the_madau_model():
+    cfg = wl.reduced(wl.CONFIGS["c1"], n_age=40, logz=(-2.0, -1.0, 0.0), n_wave=1500, n_sfh=10, n_zh=0, n_lines=0)
+    lib = wl.make_library(cfg, 0)
+    dust = wl.make_dust_tables(cfg, lib["wave"])
+    L1 = om.build_library(cfg, lib, None, dust, igm=om.IGM_MADAU)
+    L7 = om.build_library(cfg, lib, None, dust, igm=om.IGM_MADAU | om.IGM_DAMPING | om.IGM_DLA)
+    c1, c7 = om.lib_columns(L1), om.lib_columns(L7)
+    assert c7["P"] == c1["P"] + 3 and c7["x_hi"] == c1["igm_factor"] + 1 and c7["z_dla"] == c7["log_nhi"] + 1
+    obs = om.Photometry(filters=wl.make_filters("gauss20"))
+    th1 = wl.make_theta(cfg, 6, seed=8, igm=1)
+    th1[:, 1] = [6.5, 7.5, 8.5, 9.5, 10.5, 11.5]
+    th7 = np.concatenate([th1, np.zeros((6, 3))], axis=1)
+    th7[:, c7["x_hi"]] = 0.0
+    th7[:, c7["log_nhi"]] = -30.0
+    th7[:, c7["z_dla"]] = th1[:, 1] - 0.2
+    np.testing.assert_allclose(om.predict(L7, obs, th7), om.predict(L1, obs, th1), rtol=1e-14, atol=0.0)
+    th7[:, c7["x_hi"]] = 0.9
+    th7[:, c7["log_nhi"]] = 21.5
+    m1, m7 = om.predict(L1, obs, th1), om.predict(L7, obs, th7)
+    assert np.all(m7 <= m1 * (1 + 1e-14)) and np.any(m7 < 0.95 * m1)
+    with pytest.raises(ValueError):
+        om.build_library(cfg, lib, None, dust, igm=om.IGM_DAMPING)
