@@ -706,12 +706,16 @@ __global__ void __launch_bounds__(64) k_calib_solve(CalibLaunch a) {
 __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) {
   constexpr int NM = kLineMargMax;
   static_assert(NM <= 256, "the factorisation takes one row per thread");
-  __shared__ double sP[NM][NM + 1];
-  __shared__ double s_b[NM], s_F[NM], s_lnl[NM], s_isl[NM], s_L[NM];
+  // the normal matrix's lower triangle, packed by rows (72 KB of LDS in all: two workgroups
+  // per CU); before it is formed the same words hold the library lines' terms
+  __shared__ double sPk[NM * (NM + 1) / 2];
+  static_assert(NM * (NM + 1) / 2 >= 3 * 512 + 128, "the line terms fit where P goes");
+  __shared__ double s_b[NM], s_F[NM], s_lnl[NM], s_isl[NM];
   __shared__ int s_p0[NM], s_p1[NM], s_aoff[NM], s_poff[NM + 1], s_atab;
   __shared__ unsigned char s_flat[NM];
-  __shared__ double t_F[512], t_lnl[512], t_sl[512];
-  __shared__ unsigned char t_fit[512], t_flat[512];
+  double *t_F = sPk, *t_lnl = sPk + 512, *t_sl = sPk + 1024;
+  unsigned char *t_fit = (unsigned char *)(sPk + 1536), *t_flat = t_fit + 512;
+  auto P = [&](int i, int k) -> double & { return sPk[i * (i + 1) / 2 + k]; };   // k <= i
   __shared__ double red[4], s_lnsg;
   __shared__ int s_n, s_nflat;
   const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -792,8 +796,9 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
       const double v = ns * ns * sg * sg + fc * fc * m * m + fd * fd * d * d + jt * jt;
       w = 1.0 / v;
       rr = d - m;
-      for (int j = 0; j < n; ++j)
-        if (s_flat[j] && i >= s_p0[j] && i < s_p1[j]) rr += s_F[j] * A(j, i);
+      if (s_nflat > 0)
+        for (int j = 0; j < n; ++j)
+          if (s_flat[j] && i >= s_p0[j] && i < s_p1[j]) rr += s_F[j] * A(j, i);
       lsum += -0.5 * rr * rr * w - 0.5 * log(2.0 * kPi * v);
     }
     sr[i] = rr;
@@ -804,25 +809,45 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
   __syncthreads();
   const double lnl_diag = (red[0] + red[1]) + (red[2] + red[3]);
   // ---- 3. b and the normal matrix P.  The profiles are tabulated once into the row's
-  // scratch (after r and W) when they fit, line j's window at s_aoff[j]; the pairs that
-  // overlap, (j, k) with k from j up to the last line whose window starts before line j's
-  // ends (windows start in line order), are enumerated and dealt over the waves; the other
-  // entries are 0.
+  // scratch (after r and W) when they fit, line j's window at s_aoff[j].  The pairs (j, k),
+  // k >= j, whose windows overlap (and every (j, j), which carries the prior) are counted per
+  // line (thread j tests every k), numbered
+  // by a scan and computed one per thread, each a serial sum over the overlap in pixel
+  // order; the other entries are 0.
   double *abuf = sw + np;
-  if (tid == 0) {
-    int off = 0, npair = 0;
-    for (int j = 0; j < n; ++j) {
-      s_aoff[j] = off;
-      off += s_p1[j] - s_p0[j];
-      int k = j;
-      while (k + 1 < n && s_p0[k + 1] < s_p1[j]) ++k;
-      s_poff[j] = npair;
-      npair += k - j + 1;
-    }
-    s_poff[n] = npair;
-    s_atab = off <= a.ld_scr - 2 * np ? 1 : 0;
+  auto overlap = [&](int j, int k) { return k == j || (s_p0[k] < s_p1[j] && s_p0[j] < s_p1[k]); };
+  for (int j = tid; j < n; j += 256) {
+    int c = 0;
+    for (int k = j; k < n; ++k) c += overlap(j, k) ? 1 : 0;
+    s_aoff[j] = s_p1[j] - s_p0[j];   // window widths and pair counts, scanned below
+    s_poff[j] = c;
   }
-  for (int q = tid; q < n * n; q += 256) sP[q / n][q % n] = 0.0;
+  for (int q = tid; q < n * (n + 1) / 2; q += 256) sPk[q] = 0.0;
+  __syncthreads();
+  if (wv == 0) {   // exclusive scans, 64 lines at a time
+    int ca = 0, cp = 0;
+    for (int j0 = 0; j0 < n; j0 += 64) {
+      const int j = j0 + lane;
+      int va = j < n ? s_aoff[j] : 0, vp = j < n ? s_poff[j] : 0;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int ua = __shfl_up(va, o, 64), up = __shfl_up(vp, o, 64);
+        if (lane >= o) {
+          va += ua;
+          vp += up;
+        }
+      }
+      if (j < n) {
+        s_aoff[j] = ca + va - s_aoff[j];
+        s_poff[j] = cp + vp - s_poff[j];
+      }
+      ca += __shfl(va, 63, 64);
+      cp += __shfl(vp, 63, 64);
+    }
+    if (lane == 0) {
+      s_poff[n] = cp;
+      s_atab = ca <= a.ld_scr - 2 * np ? 1 : 0;
+    }
+  }
   __syncthreads();
   const bool atab = s_atab != 0;
   if (atab) {
@@ -838,54 +863,73 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
     __syncthreads();
   }
   auto Ag = [&](int j, int i) { return atab ? abuf[s_aoff[j] + (i - s_p0[j])] : A(j, i); };
-  for (int j = wv; j < n; j += 4) {
+  // serial sums in pixel order, eight pixels' loads in flight at a time
+  for (int j = tid; j < n; j += 256) {
     double acc = 0.0;
-    for (int i = s_p0[j] + lane; i < s_p1[j]; i += 64) acc += Ag(j, i) * sw[i] * sr[i];
-    acc = wave_reduce_sum(acc);
-    if (lane == 0) s_b[j] = acc;
+    int i = s_p0[j];
+    const int up = s_p1[j];
+    for (; i + 8 <= up; i += 8) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = Ag(j, i + u) * sw[i + u] * sr[i + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += x[u];
+    }
+    for (; i < up; ++i) acc += Ag(j, i) * sw[i] * sr[i];
+    s_b[j] = acc;
   }
   const int npair = s_poff[n];
-  for (int q = wv; q < npair; q += 4) {
-    int j = 0, hi = n - 1;   // the pair's first line
+  for (int q = tid; q < npair; q += 256) {
+    int j = 0, hi = n - 1;   // the pair's first line: the last j with s_poff[j] <= q
     while (j < hi) {
       const int mid = (j + hi + 1) >> 1;
       if (s_poff[mid] <= q) j = mid; else hi = mid - 1;
     }
-    const int k = j + (q - s_poff[j]);
+    int k = j, m = q - s_poff[j];   // its m-th overlapping partner from j on
+    while (true) {
+      if (overlap(j, k)) {
+        if (m == 0) break;
+        --m;
+      }
+      ++k;
+    }
     const int lo = max(s_p0[j], s_p0[k]), up = min(s_p1[j], s_p1[k]);
     double acc = 0.0;
-    for (int i = lo + lane; i < up; i += 64) acc += Ag(j, i) * Ag(k, i) * sw[i];
-    acc = wave_reduce_sum(acc);
-    if (lane == 0) {
-      if (j == k && !s_flat[j]) {
-        const double sj = ob.lm_frac * s_F[j];
-        acc += 1.0 / (sj * sj);
-      }
-      sP[j][k] = acc;
-      sP[k][j] = acc;
+    int i = lo;
+    for (; i + 8 <= up; i += 8) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = Ag(j, i + u) * Ag(k, i + u) * sw[i + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += x[u];
     }
+    for (; i < up; ++i) acc += Ag(j, i) * Ag(k, i) * sw[i];
+    if (j == k && !s_flat[j]) {
+      const double sj = ob.lm_frac * s_F[j];
+      acc += 1.0 / (sj * sj);
+    }
+    P(k, j) = acc;
   }
   __syncthreads();
-  // ---- 4. Cholesky with the forward solve carried along: for column j every thread forms
-  // L_jj and y_j, thread i > j its L_ij (into s_L); then thread i updates its row of the
-  // trailing matrix and b_i (rows with L_ij = 0, outside the band of overlapping lines, skip)
+  // ---- 4. Cholesky with the forward solve carried along, one barrier per column: column j
+  // (rows below the diagonal) and b_j are final when step j starts, and step j writes only
+  // columns > j and b_i, i > j.  Every thread forms L_jj and y_j; thread i > j updates its row
+  // of the lower triangle, P_ik -= L_ij L_kj for j < k <= i with L_kj = P_kj / L_jj, and b_i
+  // (rows with L_ij = 0, outside the band of overlapping lines, skip)
   double sum_ln = 0.0, ssq = 0.0;   // thread 0
   for (int j = 0; j < n; ++j) {
-    const double ljj = sqrt(sP[j][j]), yj = s_b[j] / ljj;
+    const double ljj = sqrt(P(j, j)), yj = s_b[j] / ljj, inv = 1.0 / ljj;
     if (tid == 0) {
       sum_ln += log(ljj);
       ssq += yj * yj;
     }
     const int i = j + 1 + tid;   // n <= 128 < 256: one row per thread
-    double lij = 0.0;
     if (i < n) {
-      lij = sP[i][j] / ljj;
-      s_L[i] = lij;
-    }
-    __syncthreads();
-    if (i < n && lij != 0.0) {
-      for (int k = j + 1; k <= i; ++k) sP[i][k] -= lij * s_L[k];
-      s_b[i] -= lij * yj;
+      const double lij = P(i, j) * inv;
+      if (lij != 0.0) {
+        for (int k = j + 1; k <= i; ++k) P(i, k) -= lij * (P(k, j) * inv);
+        s_b[i] -= lij * yj;
+      }
     }
     __syncthreads();
   }
