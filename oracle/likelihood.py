@@ -130,3 +130,55 @@ def line_marginal_lnlike(data, model, sigma, mask, A, alpha_bar, prior_sd, flat,
     lnz = base + 0.5 * b @ x - 0.5 * logdet - np.sum(np.log(prior_sd[~flat])) \
         + 0.5 * np.count_nonzero(flat) * np.log(2.0 * np.pi)
     return (lnz, alpha0 + x) if return_mean else lnz
+
+
+def joint_line_marginal_lnlike(spec, cat, alpha_bar, prior_sd, flat, return_mean=False):
+    """Eq. app_line_marg over two observations that see the same fitted lines: a spectrum
+    ``spec`` = dict(data, model, sigma, mask, A, s, f_calib, f_data, jitter) (A[i, j] the
+    unit-flux profile of line j on pixel i, noise floor as in eq. G1) and a line catalogue
+    ``cat`` = dict(data, model, sigma, mask, upper, A) (A[e, j] = 1 where fitted line j is in
+    entry e's blend).  Each model is the full one at the grid fluxes; lnL_diag of the
+    catalogue is its own -chi^2 / 2 (no normalisation term, App. I.2).  Reading: upper-limit
+    entries are not Gaussian in the fluxes and keep their one-sided chi^2 at the grid model;
+    only detections enter the sums.  With r_k = d_k - mu_k - A_k alpha_0, b = sum_k A_k^T W_k
+    r_k and P = sum_k A_k^T W_k A_k + diag(s^-2) over the Gaussian lines,
+
+      ln Z = sum_k lnL_diag,k(r_k) + b^T P^-1 b / 2 - ln|P| / 2 - sum_G ln s_j + (m_flat / 2) ln 2 pi."""
+    flat = np.asarray(flat, dtype=bool)
+    alpha_bar = np.asarray(alpha_bar, dtype=np.float64)
+    prior_sd = np.asarray(prior_sd, dtype=np.float64)
+    alpha0 = np.where(flat, 0.0, alpha_bar)
+    shift = np.where(flat, alpha_bar, 0.0)          # the grid flux of flat lines leaves mu + A alpha_0
+    As = np.asarray(spec["A"], dtype=np.float64)
+    ms = spec["mask"]
+    d = np.where(ms, spec["data"], 0.0)
+    sg = np.where(ms, spec["sigma"], 1.0)
+    v = effective_variance(sg, spec["model"], d, spec.get("s", 1.0), spec.get("f_calib"), spec.get("f_data"),
+                           spec.get("jitter"))
+    iv = np.where(ms, 1.0 / v, 0.0)
+    r = np.where(ms, d - (spec["model"] - As @ shift), 0.0)
+    base = float(np.sum(np.where(ms, -0.5 * r * r * iv - 0.5 * np.log(2.0 * np.pi * np.where(ms, v, 1.0)), 0.0)))
+    b = As.T @ (iv * r)
+    P = As.T @ (iv[:, None] * As)
+    if cat is not None:
+        Ac = np.asarray(cat["A"], dtype=np.float64)
+        mc = cat["mask"]
+        up = np.asarray(cat["upper"], dtype=bool)
+        det = mc & ~up
+        dc = np.where(mc, cat["data"], 0.0)
+        sc = np.where(mc, cat["sigma"], 1.0)
+        rc = np.where(det, dc - (cat["model"] - Ac @ shift), 0.0)
+        wc = np.where(det, 1.0 / sc ** 2, 0.0)
+        base += float(-0.5 * np.sum(wc * rc * rc))
+        ul = mc & up & (cat["model"] > dc)
+        base += float(-0.5 * np.sum(np.where(ul, ((dc - cat["model"]) / sc) ** 2, 0.0)))
+        b = b + Ac.T @ (wc * rc)
+        P = P + Ac.T @ (wc[:, None] * Ac)
+    P = P + np.diag(np.where(flat, 0.0, 1.0 / np.where(flat, 1.0, prior_sd) ** 2))
+    if len(flat) == 0:
+        return (base, alpha0) if return_mean else base
+    x = np.linalg.solve(P, b)
+    _, logdet = np.linalg.slogdet(P)
+    lnz = base + 0.5 * b @ x - 0.5 * logdet - np.sum(np.log(prior_sd[~flat])) \
+        + 0.5 * np.count_nonzero(flat) * np.log(2.0 * np.pi)
+    return (lnz, alpha0 + x) if return_mean else lnz

@@ -444,6 +444,55 @@ def line_marg_terms(L: Library, obs, th, cols, Lline_row):
     return dict(idx=sel, A=A, alpha_bar=Fl[sel], prior_sd=obs.line_prior_frac * Fl[sel], flat=flat[sel])
 
 
+def joint_line_terms(L: Library, spec, cat, th, cols, Lline_row):
+    """The lines fitted jointly by a spectrum (with its line_marg settings) and a line
+    catalogue of the same object (Sec. 4.1, App. I.3): the spectrum's lines (observed
+    wavelength within its pixel range) and the lines of the catalogue's detected, included
+    entries, less the Gaussian-prior lines with no grid flux; their unit-flux profiles on
+    the spectrum's pixels (zero where a line's profile misses them), the 0/1 blend matrix of
+    every catalogue entry, grid fluxes, prior widths and flat flags."""
+    _, dl = observer_scale(L, th, cols)
+    Fl, lobs, s_l = spectrum_line_terms(L, spec, th, cols, Lline_row, dl)
+    n_l = len(Fl)
+    flat = np.ones(n_l, dtype=bool) if spec.line_marg == "flat" else (
+        np.zeros(n_l, dtype=bool) if spec.line_flat is None else np.asarray(spec.line_flat, dtype=bool))
+    inwin = (lobs >= spec.pix_wave[0]) & (lobs <= spec.pix_wave[-1])
+    mask = likelihood.inclusion_mask(cat.data, cat.sigma, cat.mask)
+    up = np.zeros(len(cat.blends), dtype=bool) if cat.upper is None else np.asarray(cat.upper, dtype=bool)
+    in_cat = np.zeros(n_l, dtype=bool)
+    for e, bl in enumerate(cat.blends):
+        if mask[e] and not up[e]:
+            in_cat[list(bl)] = True
+    sel = np.flatnonzero((inwin | in_cat) & (flat | (Fl > 0.0)))
+    A = np.stack([projection.line_profile_pixels(spec.pix_wave, np.array([1.0]), lobs[[j]], s_l[[j]]) / FNU_AB
+                  for j in sel], axis=1) if len(sel) else np.zeros((len(spec.pix_wave), 0))
+    Ac = np.array([[1.0 if j in set(bl) else 0.0 for j in sel] for bl in cat.blends]).reshape(len(cat.blends), len(sel))
+    return dict(idx=sel, A=A, Ac=Ac, alpha_bar=Fl[sel], prior_sd=spec.line_prior_frac * Fl[sel], flat=flat[sel])
+
+
+def logl_lines_joint(L: Library, spec, cat, theta):
+    """logL[B] of a spectrum and a line catalogue of one object with the line fluxes
+    marginalised jointly (eq. app_line_marg summed over both observations)."""
+    theta = np.atleast_2d(theta)
+    cols = lib_columns(L)
+    ms = predict(L, spec, theta)
+    mc = predict(L, cat, theta)
+    rf = rest_frame(L, theta, lines_on_grid=False)
+    mask_s = likelihood.inclusion_mask(spec.data, spec.sigma, spec.mask)
+    mask_c = likelihood.inclusion_mask(cat.data, cat.sigma, cat.mask)
+    up = np.zeros(len(cat.blends), dtype=bool) if cat.upper is None else np.asarray(cat.upper, dtype=bool)
+    out = np.empty(theta.shape[0])
+    for b in range(theta.shape[0]):
+        s, fc, fd, j = noise_terms(spec, theta[b], cols)
+        t = joint_line_terms(L, spec, cat, theta[b], cols, rf["Lline"][b])
+        out[b] = likelihood.joint_line_marginal_lnlike(
+            dict(data=spec.data, model=ms[b], sigma=spec.sigma, mask=mask_s, A=t["A"], s=s, f_calib=fc, f_data=fd,
+                 jitter=j),
+            dict(data=cat.data, model=mc[b], sigma=cat.sigma, mask=mask_c, upper=up, A=t["Ac"]),
+            t["alpha_bar"], t["prior_sd"], t["flat"])
+    return out
+
+
 def fourier_stage_plan(L: Library, obs, sig_k=None):
     """Window rule and transform length of an observation's Fourier stage (Sec. 2.5,
     App. F): the observed range it covers (the pixels, or every filter node) and the

@@ -5,7 +5,7 @@ package holds its build script and a thin ctypes binding.  Importing the
 binding does not require a GPU; calling it does.
 """
 from .sps import (PRECISIONS, Library, Observation, Server, SpsError, forward, lib, logl,  # noqa: F401
-                  logl_grad, logl_static)
+                  logl_grad, logl_lines_joint, logl_static)
 
-__all__ = ["Library", "Observation", "Server", "SpsError", "forward", "logl", "logl_grad", "logl_static", "lib",
-           "PRECISIONS"]
+__all__ = ["Library", "Observation", "Server", "SpsError", "forward", "logl", "logl_grad", "logl_lines_joint",
+           "logl_static", "lib", "PRECISIONS"]

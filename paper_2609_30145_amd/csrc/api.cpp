@@ -841,6 +841,7 @@ sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsH
       if (most > kLineMargMax)
         return fail(SPS_E_SHAPE, "up to %d library lines fall within the pixel range; the marginalisation fits at "
                     "most %d", most, kLineMargMax);
+      h.lm_most = most;
     }
   } else if (d->kind == SPS_OBS_LINES) {
     // emission-line catalogue (Sec. 3.3, App. I): blends of the library's lines
@@ -856,6 +857,8 @@ sps_status build_obs_operators(const sps_library *L, const sps_obs_desc *d, ObsH
       for (int j = 0; j < n; ++j) {
         const int l = d->line_index[h.loff.back() + j];
         if (l < 0 || l >= L->n_line) return fail(SPS_E_INVAL, "catalogue entry %d: line index %d", k, l);
+        for (int q = h.loff.back(); q < (int)h.lidx.size(); ++q)
+          if (h.lidx[q] == l) return fail(SPS_E_INVAL, "catalogue entry %d: line %d listed twice", k, l);
         h.lidx.push_back(l);
       }
       h.loff.push_back(h.loff.back() + n);
@@ -977,7 +980,8 @@ bool precision_built(const sps_library *L, int p) { return p >= 0 && p <= 9 && (
 
 sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_table, const int *point_obs,
                           const double *theta, int B, int prec, double *logl, double *model, int ld_model,
-                          bool grad, int ld_g, const ObsHost *one, sps_obs *timing_obs, hipStream_t s) {
+                          bool grad, int ld_g, const ObsHost *one, sps_obs *timing_obs, hipStream_t s,
+                          bool keep_sorted_model, const LineMargLaunch *joint) {
   if (B < 1 || B > w.max_batch) return fail(SPS_E_SHAPE, "B=%d outside [1, max_batch=%d]", B, w.max_batch);
   if (!precision_built(L, prec)) return fail(SPS_E_INVAL, "precision %d not built into this library", prec);
   const DevLib &g = L->dev;
@@ -1089,7 +1093,7 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   pj.logl = logl;
   pj.gvec = grad ? w.gvec : nullptr;
   pj.gnoise = grad ? w.gnoise : nullptr;
-  pj.msorted = grad || calib || lmarg ? w.mbuf : nullptr;
+  pj.msorted = grad || calib || lmarg || keep_sorted_model ? w.mbuf : nullptr;
   pj.ld_model = ld_model;
   pj.ld_g = ld_g;
   if (e == hipSuccess) e = launch_project(g, pj, s);
@@ -1118,6 +1122,9 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
     lm.ld_scr = w.ld_scr;
     lm.B_pad = B_pad;
     lm.logl = logl;
+    lm.cat = joint ? joint->cat : nullptr;
+    lm.cat_model = joint ? joint->cat_model : nullptr;
+    lm.cat_ld = joint ? joint->cat_ld : 0;
     e = launch_linemarg(g, lm, s);
   }
   if (e != hipSuccess) return fail(SPS_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
@@ -1161,6 +1168,35 @@ extern "C" sps_status sps_logl_grad(const sps_library *L, sps_obs *o, const doub
   sps_status st = run_forward(L, o, theta, B, prec, logl, nullptr, true, (hipStream_t)stream);
   if (st != SPS_OK) return st;
   return run_adjoint(L, o, theta, B, prec, grad, (hipStream_t)stream);
+}
+
+extern "C" sps_status sps_logl_lines_joint(const sps_library *L, sps_obs *spec, sps_obs *cat, const double *theta,
+                                           int32_t B, int32_t prec, double *logl, void *stream) {
+  if (!L || !spec || !cat || !theta || !logl) return fail(SPS_E_INVAL, "NULL argument");
+  if (spec->lib != L || cat->lib != L) return fail(SPS_E_INVAL, "observation belongs to another library");
+  if (spec->host.kind != SPS_OBS_SPEC || spec->host.lm_mode == SPS_LINEMARG_NONE || cat->host.kind != SPS_OBS_LINES)
+    return fail(SPS_E_INVAL, "a joint marginalisation takes a spectrum with line_marg set and a line catalogue");
+  if (cat->host.n_data > kLineCatMaxHost)
+    return fail(SPS_E_SHAPE, "a jointly marginalised catalogue holds at most %d entries", kLineCatMaxHost);
+  std::vector<uint8_t> seen(L->n_line, 0);
+  int n_cat = 0;
+  for (int l : cat->host.lidx) n_cat += seen[l] ? 0 : (seen[l] = 1);
+  if (spec->host.lm_most + n_cat > kLineMargMax)
+    return fail(SPS_E_SHAPE, "up to %d lines would be fitted jointly; at most %d", spec->host.lm_most + n_cat,
+                kLineMargMax);
+  if (L->dev.vdisp && (spec->host.vd_nfft <= 0)) return fail(SPS_E_STATE, "spectrum without its Fourier plan");
+  hipStream_t s = (hipStream_t)stream;
+  // the catalogue first (its logL lands in logl and is replaced), its model kept at the
+  // sorted rows; the spectrum's rows come in the same order (same points, same keys)
+  sps_status st = launch_forward(L, cat->ws, cat->dev_obs, nullptr, theta, B, prec, logl, nullptr, cat->host.n_data,
+                                 false, cat->host.n_data, &cat->host, nullptr, s, true, nullptr);
+  if (st != SPS_OK) return st;
+  LineMargLaunch j{};
+  j.cat = cat->dev_obs;
+  j.cat_model = cat->ws.mbuf;
+  j.cat_ld = cat->host.n_data;
+  return launch_forward(L, spec->ws, spec->dev_obs, nullptr, theta, B, prec, logl, nullptr, spec->host.n_data, false,
+                        spec->host.n_data, &spec->host, spec, s, false, &j);
 }
 
 extern "C" sps_status sps_obs_enable_timing(sps_obs *o, int32_t enable) {

@@ -88,6 +88,11 @@ struct LineMargLaunch {
   double *scr;               // [B_pad][ld_scr] per-row scratch: residuals, weights (ld_scr >= 2 n_pix), then the profiles
   int ld_scr, B_pad;
   double *logl;              // [B] or NULL: overwritten with the marginal likelihood
+  // joint marginalisation with a line catalogue of the same points (its rows in the same
+  // sorted order): its observation (device) and its model at the sorted rows, or NULL
+  const DevObs *cat;
+  const double *cat_model;
+  int cat_ld;
 };
 hipError_t launch_linemarg(const DevLib &lib, const LineMargLaunch &lm, hipStream_t s);
 

@@ -7,6 +7,7 @@
 namespace sps {
 
 constexpr int kLineCut = 10;   // analytic line profiles evaluated within 10 sigma
+constexpr int kLineCatMax = 256;   // entries of a catalogue marginalised jointly with a spectrum
 
 template <typename T>
 struct ProjArgs {
@@ -709,12 +710,15 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
   // the normal matrix's lower triangle, packed by rows (72 KB of LDS in all: two workgroups
   // per CU); before it is formed the same words hold the library lines' terms
   __shared__ double sPk[NM * (NM + 1) / 2];
-  static_assert(NM * (NM + 1) / 2 >= 3 * 512 + 128, "the line terms fit where P goes");
+  static_assert(NM * (NM + 1) / 2 >= 3 * 512 + 192, "the line terms fit where P goes");
   __shared__ double s_b[NM], s_F[NM], s_lnl[NM], s_isl[NM];
   __shared__ int s_p0[NM], s_p1[NM], s_aoff[NM], s_poff[NM + 1], s_atab;
   __shared__ unsigned char s_flat[NM];
+  __shared__ short s_fidx[512];                  // library line -> fitted index, or -1
+  __shared__ double s_cr[kLineCatMax], s_cw[kLineCatMax];   // joint: catalogue residuals, weights
+  __shared__ double s_cl;                        // joint: the catalogue's -chi^2 / 2
   double *t_F = sPk, *t_lnl = sPk + 512, *t_sl = sPk + 1024;
-  unsigned char *t_fit = (unsigned char *)(sPk + 1536), *t_flat = t_fit + 512;
+  unsigned char *t_fit = (unsigned char *)(sPk + 1536), *t_flat = t_fit + 512, *t_cat = t_fit + 1024;
   auto P = [&](int i, int k) -> double & { return sPk[i * (i + 1) / 2 + k]; };   // k <= i
   __shared__ double red[4], s_lnsg;
   __shared__ int s_n, s_nflat;
@@ -726,7 +730,18 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
   const double *th = a.theta + (size_t)pr.b * lib.P;
   const int nl = lib.n_line, np = ob.n_data;
   const double pix_lo = ob.pix[0], pix_hi = ob.pix[np - 1];
-  // ---- 1. the library lines, then the fitted ones in order
+  // ---- 0. joint with a catalogue: the lines of its detected, included entries
+  const DevObs *cat = a.cat;
+  if (cat) {
+    for (int l = tid; l < nl; l += 256) t_cat[l] = 0;
+    __syncthreads();
+    for (int e = tid; e < cat->n_data; e += 256)
+      if (cat->mask[e] && !cat->upper[e])
+        for (int q = cat->loff[e]; q < cat->loff[e + 1]; ++q) t_cat[cat->lidx[q]] = 1;
+    __syncthreads();
+  }
+  // ---- 1. the library lines, then the fitted ones in order (the spectrum's, with a
+  // catalogue also those of its detections)
   for (int l = tid; l < nl; l += 256) {
     double Fl, lobs, sl;
     spec_line_terms<true>(lib, ob, pr, th, a.Lline[(size_t)r * nl + l], l, Fl, lobs, sl);
@@ -735,7 +750,9 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
     t_lnl[l] = log(lobs);
     t_sl[l] = sl;
     t_flat[l] = flat ? 1 : 0;
-    t_fit[l] = (lobs >= pix_lo && lobs <= pix_hi && (flat || Fl > 0.0)) ? 1 : 0;
+    const bool seen = (lobs >= pix_lo && lobs <= pix_hi) || (cat && t_cat[l]);
+    t_fit[l] = (seen && (flat || Fl > 0.0)) ? 1 : 0;
+    s_fidx[l] = -1;
   }
   __syncthreads();
   if (wv == 0) {
@@ -747,6 +764,7 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
       const unsigned long long m = __ballot(f);
       const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
       if (f && pos < NM) {
+        s_fidx[l] = (short)pos;
         s_F[pos] = t_F[l];
         s_lnl[pos] = t_lnl[l];
         s_isl[pos] = 1.0 / t_sl[l];
@@ -773,7 +791,37 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
   }
   __syncthreads();
   const int n = s_n;
-  if (n == 0) {   // no line to fit: the grid model's likelihood stands
+  // joint: each catalogue entry's residual at mu + A alpha_0 (the grid model, plus the grid
+  // flux of its fitted flat lines) and weight; detections sum to the catalogue's -chi^2 / 2,
+  // upper limits keep their one-sided form at the grid model (thread 0, entry order)
+  if (cat && tid == 0) {
+    double cl = 0.0;
+    for (int e = 0; e < cat->n_data; ++e) {
+      double rr = 0.0, w = 0.0;
+      if (cat->mask[e]) {
+        const double m = a.cat_model[(size_t)r * a.cat_ld + e], d = cat->data[e], sg = cat->sigma[e];
+        if (cat->upper[e]) {
+          if (m > d) cl -= 0.5 * ((d - m) / sg) * ((d - m) / sg);
+        } else {
+          rr = d - m;
+          for (int q = cat->loff[e]; q < cat->loff[e + 1]; ++q) {
+            const int j = s_fidx[cat->lidx[q]];
+            if (j >= 0 && s_flat[j]) rr += s_F[j];
+          }
+          w = 1.0 / (sg * sg);
+          cl -= 0.5 * rr * rr * w;
+        }
+      }
+      s_cr[e] = rr;
+      s_cw[e] = w;
+    }
+    s_cl = cl;
+  }
+  if (n == 0) {   // no line to fit: the grid model's likelihood stands (and the catalogue's)
+    if (cat) {
+      __syncthreads();
+      if (tid == 0 && a.logl) a.logl[pr.b] += s_cl;
+    }
     return;
   }
   // unit-flux profile of fitted line j at pixel i (maggies per erg/s/cm^2)
@@ -911,6 +959,22 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
     P(k, j) = acc;
   }
   __syncthreads();
+  if (cat && tid == 0) {   // the catalogue's detections: b_j += w r, P_jk += w for the fitted lines of a blend
+    for (int e = 0; e < cat->n_data; ++e) {
+      const double w = s_cw[e];
+      if (w == 0.0) continue;
+      for (int q = cat->loff[e]; q < cat->loff[e + 1]; ++q) {
+        const int j = s_fidx[cat->lidx[q]];
+        if (j < 0) continue;
+        s_b[j] += w * s_cr[e];
+        for (int q2 = cat->loff[e]; q2 < cat->loff[e + 1]; ++q2) {
+          const int k = s_fidx[cat->lidx[q2]];
+          if (k >= 0 && k <= j) P(j, k) += w;
+        }
+      }
+    }
+  }
+  if (cat) __syncthreads();
   // ---- 4. Cholesky with the forward solve carried along, one barrier per column: column j
   // (rows below the diagonal) and b_j are final when step j starts, and step j writes only
   // columns > j and b_i, i > j.  Every thread forms L_jj and y_j; thread i > j updates its row
@@ -934,7 +998,7 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
     __syncthreads();
   }
   if (tid == 0 && a.logl)
-    a.logl[pr.b] = lnl_diag + 0.5 * ssq - sum_ln - s_lnsg + 0.5 * (double)s_nflat * log(2.0 * kPi);
+    a.logl[pr.b] = lnl_diag + (cat ? s_cl : 0.0) + 0.5 * ssq - sum_ln - s_lnsg + 0.5 * (double)s_nflat * log(2.0 * kPi);
 }
 
 hipError_t launch_linemarg(const DevLib &lib, const LineMargLaunch &lm, hipStream_t s) {

@@ -88,6 +88,7 @@ struct ObsHost {
   double vd_lnlo = 0, vd_lnhi = 0, vd_dlnl = 0;
   std::vector<double> vd_tw;
   int lm_mode = 0;                   // line-flux marginalisation (spectra)
+  int lm_most = 0;                   //   most library lines in a rest interval as wide as the pixels
   double lm_frac = 0;
   std::vector<uint8_t> lm_flat;
 };
@@ -142,9 +143,14 @@ sps_status run_adjoint(const sps_library *L, sps_obs *o, const double *theta, in
 // (point_obs: observation slot per point, NULL = slot 0).  `one` is the host side of the
 // observation when every point has the same one (NULL on the serving path, which mixes
 // observations): line catalogues, calibration polynomials and a free sigma_gal need it.
+// keep_sorted_model: the model at the sorted rows stays in w.mbuf; joint: the catalogue of
+// a joint line marginalisation (its cat, cat_model, cat_ld fields), or NULL.
+struct LineMargLaunch;
+constexpr int kLineCatMaxHost = 256;   // catalogue entries of a joint marginalisation
 sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_table, const int *point_obs,
                           const double *theta, int B, int prec, double *logl, double *model, int ld_model,
-                          bool grad, int ld_g, const ObsHost *one, sps_obs *timing_obs, hipStream_t s);
+                          bool grad, int ld_g, const ObsHost *one, sps_obs *timing_obs, hipStream_t s,
+                          bool keep_sorted_model = false, const LineMargLaunch *joint = nullptr);
 bool precision_built(const sps_library *L, int p);
 // Device address of the allocation-free entry point's static scratch on `device`, looked
 // up once per device (called by sps_library_load).

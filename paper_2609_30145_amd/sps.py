@@ -103,6 +103,7 @@ def lib():
         L.sps_logl.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
         L.sps_logl_grad.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
         L.sps_logl_static.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
+        L.sps_logl_lines_joint.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, vp, vp]
         L.sps_obs_enable_timing.argtypes = [vp, C.c_int32]
         L.sps_obs_contract_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                               C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -110,7 +111,7 @@ def lib():
         L.sps_version.restype = C.c_char_p
         for name in ("sps_library_load", "sps_library_info_get", "sps_theta_layout", "sps_obs_create",
                      "sps_obs_set_data", "sps_obs_n_data", "sps_forward", "sps_logl", "sps_logl_grad", "sps_logl_static",
-                     "sps_obs_enable_timing", "sps_obs_contract_timing"):
+                     "sps_logl_lines_joint", "sps_obs_enable_timing", "sps_obs_contract_timing"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -370,6 +371,18 @@ def logl_static(library, obs, theta, precision="fp32", stream=None, return_model
                                 PRECISIONS[precision], C.c_void_p(out.data_ptr()),
                                 C.c_void_p(model.data_ptr()) if model is not None else None, _stream_ptr(stream)))
     return (out, model) if return_model else out
+
+
+def logl_lines_joint(library, spec, cat, theta, precision="fp32", stream=None):
+    """logL [B] (float64) of a spectrum and a line catalogue with the line fluxes
+    marginalised jointly — sps_logl_lines_joint."""
+    import torch
+    _check_theta(library, theta)
+    out = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
+    check(lib().sps_logl_lines_joint(library.handle, spec.handle, cat.handle, C.c_void_p(theta.data_ptr()),
+                                     theta.shape[0], PRECISIONS[precision], C.c_void_p(out.data_ptr()),
+                                     _stream_ptr(stream)))
+    return out
 
 
 def logl_grad(library, obs, theta, precision="fp32", stream=None):

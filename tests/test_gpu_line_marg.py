@@ -8,7 +8,12 @@ C ABI:
     terms, at redshifts that move lines in and out of the pixel range;
   - a batch over several M tiles with a ragged tail at FP64, FP32 and FP16 (three passes);
   - the gradient, the allocation-free call and a calibration polynomial at the same time
-    are refused; more than 128 lines within the pixel range is SPS_E_SHAPE.
+    are refused; more than 128 lines within the pixel range is SPS_E_SHAPE;
+  - the joint marginalisation over the spectrum and a line catalogue of the same object
+    (sps_logl_lines_joint): single lines and blends, lines inside and outside the pixel
+    range (fitted through the catalogue alone), two upper limits and a masked entry, with
+    Gaussian priors (two lines flat) and with every line flat (single-line entries: a flat
+    line seen only in a blend is not identified and its marginal diverges).
 
 Tolerances: logL FP64 1e-10, FP32 and FP16 1e-4, relative to the larger of the marginal
 and the grid-model likelihood (the marginal likelihood is a difference of terms of that
@@ -140,3 +145,59 @@ def test_refusals_and_size_limit(case):
     assert ei.value.code == -2
     sps.Observation(L2, "spec", 8, pix_wave=np.geomspace(10000.0, 53000.0, 300), lsf_mode="R_fwhm",
                     lsf_value=100.0, line_marg="flat")
+
+
+# catalogue entries over the 24 library lines: single lines, blends, lines that the
+# spectrum's pixel range holds at some redshifts and not at others
+JOINT_BLENDS = [[0], [3], [5, 6], [8], [10, 11, 12], [14], [17], [19, 20], [22], [23]]
+# with every line flat, lines that only a blend sees are not identified one by one (the
+# marginal likelihood of a flat prior diverges): single lines only
+JOINT_SINGLES = [[0], [3], [5], [8], [10], [14], [17], [19], [22], [23]]
+
+
+def cat_obs(case, blends, seed=29):
+    olib = case["olib"]
+    upper = np.zeros(len(blends), dtype=bool)
+    upper[[3, 8]] = True
+    lobs = om.Lines(blends=blends, upper=upper)
+    f_true = om.predict(olib, lobs, case["theta_true"])[0]
+    rng = np.random.default_rng(seed)
+    lobs.sigma = 0.1 * f_true + 1e-25
+    lobs.data = f_true * rng.uniform(0.6, 1.5, f_true.size) + lobs.sigma * rng.normal(size=f_true.size)
+    lobs.data[upper] = 2.0 * lobs.sigma[upper]
+    lobs.mask = np.ones(len(blends), dtype=bool)
+    lobs.mask[6] = False
+    return lobs
+
+
+@pytest.mark.parametrize("mode,frac,some_flat", [("gauss", 0.3, True), ("flat", 0.0, False)])
+def test_joint_with_a_line_catalogue(case, mode, frac, some_flat):
+    c, L, theta = case
+    obs = c["obs"]
+    blends = JOINT_BLENDS if mode == "gauss" else JOINT_SINGLES
+    lobs = cat_obs(c, blends)
+    flat = np.zeros(CFG.n_lines, dtype=bool)
+    if some_flat:
+        flat[[5, 17]] = True
+    sobs = dataclasses.replace(obs, noise={}, line_marg=mode, line_prior_frac=frac,
+                               line_flat=flat if some_flat else None)
+    ref = om.logl_lines_joint(c["olib"], sobs, lobs, theta)
+    alone = om.logl(c["olib"], sobs, theta) + om.logl(c["olib"], lobs, theta)
+    assert np.all(np.isfinite(ref)) and np.max(np.abs(ref - alone)) > 1.0
+    O = spec_obs(L, obs, 256, line_marg=mode, line_prior_frac=frac, line_flat=flat if some_flat else None)
+    Oc = sps.Observation(L, "lines", 256, blends=blends, upper=lobs.upper, data=lobs.data, sigma=lobs.sigma,
+                         mask=lobs.mask)
+    tt = torch.tensor(theta, dtype=torch.float64, device="cuda")
+    scale = np.maximum(1.0, np.maximum(np.abs(ref), np.abs(alone)))
+    for prec in PRECS:
+        say(f"  joint {mode} flat {some_flat} {prec}")
+        ll = sps.logl_lines_joint(L, O, Oc, tt, prec)
+        torch.cuda.synchronize()
+        ll = ll.cpu().numpy()
+        lle = np.abs(ll - ref) / scale
+        say(f"    logL rel err {lle.max():.3e}")
+        assert np.all(np.isfinite(ll))
+        assert lle.max() < LOGL_TOL[prec]
+    with pytest.raises(sps.SpsError) as ei:   # the catalogue first: the wrong kinds
+        sps.logl_lines_joint(L, Oc, O, tt, "fp32")
+    assert ei.value.code == -1

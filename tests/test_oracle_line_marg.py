@@ -8,6 +8,12 @@ is the likelihood at the grid fluxes; the posterior mean of flat lines is the le
 flux (it recovers known fluxes from noise-free data); and on the whole model, lines outside
 the pixel range do not enter, and the posterior mean recovers the fluxes a spectrum was made
 with.
+
+The joint marginalisation over a spectrum and a line catalogue of one object is checked
+against the closed-form Gaussian convolution of a catalogue-only line, against direct
+numerical integration over two amplitudes seen by both observations (a blend and an
+upper limit among the entries), and reduces to the spectrum's own marginal when the
+catalogue has no detection.
 """
 import math
 
@@ -148,3 +154,72 @@ def test_model_marginal_likelihood_limits_and_recovery(spec_case):
     obs.line_marg = None
     plain = om.logl(L, obs, th, model=m)
     np.testing.assert_allclose(narrow, plain, rtol=1e-9, atol=1e-6)
+
+
+def _spec(d, mu_model, sigma, mask, A):
+    return dict(data=d, model=mu_model, sigma=sigma, mask=mask, A=A)
+
+
+def test_joint_catalogue_only_line_is_the_gaussian_convolution():
+    x, mu, prof, sigma, mask, rng = _toy(seed=4)
+    d = mu + sigma * rng.normal(size=x.size)
+    F, sd, dc, sc = 0.8, 0.25, 1.1, 0.3
+    spec = _spec(d, mu, sigma, mask, np.zeros((x.size, 1)))      # the line misses the spectrum
+    cat = dict(data=np.array([dc]), model=np.array([F]), sigma=np.array([sc]), mask=np.array([True]),
+               upper=np.array([False]), A=np.ones((1, 1)))
+    got = lk.joint_line_marginal_lnlike(spec, cat, np.array([F]), np.array([sd]), np.array([False]))
+    # integral of exp(-(d - a)^2 / 2 sc^2) N(a; F, sd^2) da
+    want = lk.lnlike(d, mu, sigma, mask) + math.log(sc / math.sqrt(sc ** 2 + sd ** 2)) \
+        - 0.5 * (dc - F) ** 2 / (sc ** 2 + sd ** 2)
+    assert got == pytest.approx(want, rel=0.0, abs=1e-10)
+
+
+def test_joint_matches_direct_integration_over_two_lines():
+    x, mu, prof, sigma, mask, rng = _toy(seed=5)
+    a_true, a_bar = np.array([0.5, 0.9]), np.array([0.6, 0.8])
+    sd = np.array([0.15, 0.3])
+    flat = np.array([False, True])
+    d = mu + prof @ a_true + sigma * rng.normal(size=x.size)
+    model = mu + prof @ a_bar
+    # catalogue: line 0, the blend of both, and an upper limit on line 1 the grid model exceeds
+    Ac = np.array([[1.0, 0.0], [1.0, 1.0], [0.0, 1.0]])
+    dc = np.array([0.55, 1.35, 0.6])
+    sc = np.array([0.05, 0.1, 0.2])
+    up = np.array([False, False, True])
+    mc = Ac @ a_bar
+    spec = _spec(d, model, sigma, mask, prof)
+    cat = dict(data=dc, model=mc, sigma=sc, mask=np.ones(3, dtype=bool), upper=up, A=Ac)
+    closed = lk.joint_line_marginal_lnlike(spec, cat, a_bar, sd, flat)
+    g0 = np.linspace(0.25, 0.85, 601)
+    g1 = np.linspace(0.5, 1.25, 601)
+    A0, A1 = np.meshgrid(g0, g1, indexing="ij")
+    v = np.where(mask, sigma, 1.0) ** 2
+    ul = -0.5 * ((dc[2] - mc[2]) / sc[2]) ** 2 if mc[2] > dc[2] else 0.0
+    vals = np.empty(A0.shape)
+    for i in range(A0.shape[0]):
+        for j in range(A0.shape[1]):
+            a = np.array([A0[i, j], A1[i, j]])
+            r = np.where(mask, d - mu - prof @ a, 0.0)
+            ll = np.sum(np.where(mask, -0.5 * r * r / v - 0.5 * np.log(2 * np.pi * v), 0.0))
+            rc = dc[:2] - Ac[:2] @ a
+            ll += -0.5 * np.sum((rc / sc[:2]) ** 2) + ul
+            ll += -0.5 * ((a[0] - a_bar[0]) / sd[0]) ** 2 - 0.5 * math.log(2 * math.pi * sd[0] ** 2)
+            vals[i, j] = ll
+    direct = logsumexp(vals) + math.log((g0[1] - g0[0]) * (g1[1] - g1[0]))
+    assert closed == pytest.approx(direct, rel=0.0, abs=1e-5)
+
+
+def test_joint_without_catalogue_detections_is_the_spectrum_marginal():
+    x, mu, prof, sigma, mask, rng = _toy(seed=6)
+    a_bar = np.array([0.6, 0.8])
+    d = mu + prof @ np.array([0.5, 0.9]) + sigma * rng.normal(size=x.size)
+    model = mu + prof @ a_bar
+    sd = np.array([0.2, 0.1])
+    flat = np.array([True, False])
+    spec = _spec(d, model, sigma, mask, prof)
+    # one masked detection and an upper limit above the grid model: neither contributes
+    cat = dict(data=np.array([np.nan, 5.0]), model=np.array([0.6, 1.4]), sigma=np.array([0.1, 0.1]),
+               mask=np.array([False, True]), upper=np.array([False, True]), A=np.array([[1.0, 0.0], [1.0, 1.0]]))
+    got = lk.joint_line_marginal_lnlike(spec, cat, a_bar, sd, flat)
+    want = lk.line_marginal_lnlike(d, model, sigma, mask, prof, a_bar, sd, flat)
+    assert got == pytest.approx(want, rel=1e-14, abs=1e-10)
