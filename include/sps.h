@@ -315,22 +315,29 @@ sps_status sps_logl(const sps_library *lib, sps_obs *obs, const double *theta_de
  * with marginalised line fluxes: SPS_E_INVAL). */
 sps_status sps_logl_grad(const sps_library *lib, sps_obs *obs, const double *theta_dev, int32_t B,
                          int32_t precision, double *logl_dev, double *grad_dev, void *hip_stream);
-/* Joint analytic marginalisation of the line fluxes over a spectrum and a line catalogue
- * of the same object (Sec. 4.1, App. I.3: eq. app_line_marg summed over both
- * observations).  spec: a spectrum created with line_marg set (its prior mode, fraction and
- * flat flags apply); cat: an SPS_OBS_LINES catalogue of the same library.  The fitted lines
- * are the spectrum's (observed wavelength within its pixel range) and the lines of the
- * catalogue's detected, included entries, less Gaussian-prior lines with no grid flux; a
+/* Joint analytic marginalisation of the line fluxes over a spectrum, a line catalogue and
+ * a photometric observation of the same object (Sec. 4.1, App. I.3: eq. app_line_marg
+ * summed over the observations).  spec: a spectrum created with line_marg set (its prior
+ * mode, fraction and flat flags apply); cat: an SPS_OBS_LINES catalogue, or NULL; phot: an
+ * SPS_OBS_PHOT observation, or NULL; all of the same library.  The fitted lines are the
+ * spectrum's (observed wavelength within its pixel range) and the lines of the catalogue's
+ * detected, included entries, less Gaussian-prior lines with no grid flux.  A catalogue
  * detection is linear in the fitted lines of its blend and enters b and P with weight
  * sigma^-2 and lnL_diag as -chi^2 / 2; an upper limit keeps its one-sided chi-squared at the
- * grid model (it is not Gaussian in the fluxes).  logl_dev [B] FP64 receives the joint logL
- * of both observations.  Stream, ownership and allocation as sps_logl (each observation's
- * workspace is used).  Errors: SPS_E_INVAL (NULL, kinds, another library), SPS_E_SHAPE (a
- * catalogue of more than 256 entries; more than 128 lines fitted jointly, bounded by the
- * spectrum's window count plus the catalogue's distinct lines; B beyond either
- * workspace), SPS_E_HIP. */
-sps_status sps_logl_lines_joint(const sps_library *lib, sps_obs *spec, sps_obs *cat, const double *theta_dev,
-                                int32_t B, int32_t precision, double *logl_dev, void *hip_stream);
+ * grid model (it is not Gaussian in the fluxes).  A band is linear in every fitted line
+ * through the line's band response (its profile on the model grid through the dust, the
+ * observer frame, the IGM and the filter, per unit of its observed flux), with the weight
+ * and the normalised Gaussian term of eq. 6 with the noise floor at its grid model; the
+ * lines not fitted stay at their grid fluxes.  logl_dev [B] FP64 receives the joint logL of
+ * all the observations given.  Stream, ownership and allocation as sps_logl (each
+ * observation's workspace is used).  Errors: SPS_E_INVAL (NULL spec or theta, kinds, another
+ * library, photometry with a free sigma_gal), SPS_E_SHAPE (a catalogue of more than 256
+ * entries; more than 128 lines fitted jointly, bounded by the spectrum's window count plus
+ * the catalogue's distinct lines; a photometric observation with fewer than about 43
+ * filter nodes per band; B beyond a workspace), SPS_E_HIP. */
+sps_status sps_logl_lines_joint(const sps_library *lib, sps_obs *spec, sps_obs *cat, sps_obs *phot,
+                                const double *theta_dev, int32_t B, int32_t precision, double *logl_dev,
+                                void *hip_stream);
 
 /* Allocation-free variant of sps_logl, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).

@@ -132,7 +132,7 @@ def line_marginal_lnlike(data, model, sigma, mask, A, alpha_bar, prior_sd, flat,
     return (lnz, alpha0 + x) if return_mean else lnz
 
 
-def joint_line_marginal_lnlike(spec, cat, alpha_bar, prior_sd, flat, return_mean=False):
+def joint_line_marginal_lnlike(spec, cat, alpha_bar, prior_sd, flat, return_mean=False, phot=None):
     """Eq. app_line_marg over two observations that see the same fitted lines: a spectrum
     ``spec`` = dict(data, model, sigma, mask, A, s, f_calib, f_data, jitter) (A[i, j] the
     unit-flux profile of line j on pixel i, noise floor as in eq. G1) and a line catalogue
@@ -140,7 +140,10 @@ def joint_line_marginal_lnlike(spec, cat, alpha_bar, prior_sd, flat, return_mean
     entry e's blend).  Each model is the full one at the grid fluxes; lnL_diag of the
     catalogue is its own -chi^2 / 2 (no normalisation term, App. I.2).  Reading: upper-limit
     entries are not Gaussian in the fluxes and keep their one-sided chi^2 at the grid model;
-    only detections enter the sums.  With r_k = d_k - mu_k - A_k alpha_0, b = sum_k A_k^T W_k
+    only detections enter the sums.  ``phot`` (or None) = dict(data, model, sigma, mask, A,
+    s, f_calib, f_data, jitter): photometry, A[b, j] the band response of fitted line j per
+    unit flux, its lnL_diag the normalised Gaussian of eq. 6 with the noise floor of eq. G1
+    at its model.  With r_k = d_k - mu_k - A_k alpha_0, b = sum_k A_k^T W_k
     r_k and P = sum_k A_k^T W_k A_k + diag(s^-2) over the Gaussian lines,
 
       ln Z = sum_k lnL_diag,k(r_k) + b^T P^-1 b / 2 - ln|P| / 2 - sum_G ln s_j + (m_flat / 2) ln 2 pi."""
@@ -174,6 +177,19 @@ def joint_line_marginal_lnlike(spec, cat, alpha_bar, prior_sd, flat, return_mean
         base += float(-0.5 * np.sum(np.where(ul, ((dc - cat["model"]) / sc) ** 2, 0.0)))
         b = b + Ac.T @ (wc * rc)
         P = P + Ac.T @ (wc[:, None] * Ac)
+    if phot is not None:
+        Ap = np.asarray(phot["A"], dtype=np.float64)
+        mp = phot["mask"]
+        dp = np.where(mp, phot["data"], 0.0)
+        sgp = np.where(mp, phot["sigma"], 1.0)
+        vp = effective_variance(sgp, phot["model"], dp, phot.get("s", 1.0), phot.get("f_calib"), phot.get("f_data"),
+                                phot.get("jitter"))
+        ivp = np.where(mp, 1.0 / vp, 0.0)
+        rp = np.where(mp, dp - (phot["model"] - Ap @ shift), 0.0)
+        base += float(np.sum(np.where(mp, -0.5 * rp * rp * ivp - 0.5 * np.log(2.0 * np.pi * np.where(mp, vp, 1.0)),
+                                      0.0)))
+        b = b + Ap.T @ (ivp * rp)
+        P = P + Ap.T @ (ivp[:, None] * Ap)
     P = P + np.diag(np.where(flat, 0.0, 1.0 / np.where(flat, 1.0, prior_sd) ** 2))
     if len(flat) == 0:
         return (base, alpha0) if return_mean else base

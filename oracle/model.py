@@ -470,26 +470,62 @@ def joint_line_terms(L: Library, spec, cat, th, cols, Lline_row):
     return dict(idx=sel, A=A, Ac=Ac, alpha_bar=Fl[sel], prior_sd=spec.line_prior_frac * Fl[sel], flat=flat[sel])
 
 
-def logl_lines_joint(L: Library, spec, cat, theta):
-    """logL[B] of a spectrum and a line catalogue of one object with the line fluxes
-    marginalised jointly (eq. app_line_marg summed over both observations)."""
+def line_band_response(L: Library, phot, th, cols, Lline_row, idx):
+    """A[b, j]: the photometric model of library line idx[j] alone (its profile on the model
+    grid through the birth cloud with the escape geometry's factors, the diffuse screen,
+    the observer frame, the IGM and the filters: eq. E1), per unit of its observed flux
+    F_l (App. I.1), so that a fitted flux alpha_j adds A[b, j] alpha_j to band b."""
+    scale, dl = observer_scale(L, th, cols)
+    z = th[cols["zred"]]
+    wave = L.wave
+    pf, qf, sf = young_factors(L, escape_fraction(L, th, cols))
+    T_bc = np.exp(-dust.birth_cloud_tau(wave, th[cols["tau_bc"]], th[cols["alpha_bc"]]))
+    T_d = np.exp(-dust.diffuse_tau(wave, th[cols["tau_diff"]], th[cols["delta"]], L.dust_a, L.dust_d))
+    igm_t = igm_transmission(L, th, cols, wave * (1.0 + z))
+    Fl = line_fluxes(L, th, cols, Lline_row, dl)
+    A = np.zeros((len(phot.filters), len(idx)))
+    for c, l in enumerate(idx):
+        F_rest = T_d * (pf * T_bc + qf) * sf * (Lline_row[l] / LSUN) * L.G[l]
+        fnu = fnu_observed(L, F_rest, scale) * igm_t
+        A[:, c] = projection.band_maggies(wave, fnu, z, phot.filters) / Fl[l]
+    return A
+
+
+def logl_lines_joint(L: Library, spec, cat, theta, phot=None):
+    """logL[B] of a spectrum, a line catalogue (or None) and a photometric observation (or
+    None) of one object with the line fluxes marginalised jointly (eq. app_line_marg summed
+    over the observations).  The fitted lines are the spectrum's and the catalogue's
+    detections' (joint_line_terms); the photometry sees every line on the model grid, the
+    fitted ones through line_band_response, the others at their grid fluxes.  Reading: a
+    free sigma_gal (which broadens the photometric lines) is not combined with it."""
     theta = np.atleast_2d(theta)
     cols = lib_columns(L)
+    if phot is not None and L.sigma_gal_max > 0.0:
+        raise ValueError("joint marginalisation with photometry and a free sigma_gal is not supported")
     ms = predict(L, spec, theta)
-    mc = predict(L, cat, theta)
+    cat_in = cat if cat is not None else Lines(blends=[], data=np.zeros(0), sigma=np.zeros(0))
+    mc = predict(L, cat, theta) if cat is not None else np.zeros((theta.shape[0], 0))
+    mp = predict(L, phot, theta) if phot is not None else None
     rf = rest_frame(L, theta, lines_on_grid=False)
     mask_s = likelihood.inclusion_mask(spec.data, spec.sigma, spec.mask)
-    mask_c = likelihood.inclusion_mask(cat.data, cat.sigma, cat.mask)
-    up = np.zeros(len(cat.blends), dtype=bool) if cat.upper is None else np.asarray(cat.upper, dtype=bool)
+    mask_c = likelihood.inclusion_mask(cat_in.data, cat_in.sigma, cat_in.mask)
+    up = np.zeros(len(cat_in.blends), dtype=bool) if cat_in.upper is None else np.asarray(cat_in.upper, dtype=bool)
+    mask_p = likelihood.inclusion_mask(phot.data, phot.sigma, phot.mask) if phot is not None else None
     out = np.empty(theta.shape[0])
     for b in range(theta.shape[0]):
         s, fc, fd, j = noise_terms(spec, theta[b], cols)
-        t = joint_line_terms(L, spec, cat, theta[b], cols, rf["Lline"][b])
+        t = joint_line_terms(L, spec, cat_in, theta[b], cols, rf["Lline"][b])
+        pdict = None
+        if phot is not None:
+            sp_, fcp, fdp, jp = noise_terms(phot, theta[b], cols)
+            pdict = dict(data=phot.data, model=mp[b], sigma=phot.sigma, mask=mask_p,
+                         A=line_band_response(L, phot, theta[b], cols, rf["Lline"][b], t["idx"]),
+                         s=sp_, f_calib=fcp, f_data=fdp, jitter=jp)
         out[b] = likelihood.joint_line_marginal_lnlike(
             dict(data=spec.data, model=ms[b], sigma=spec.sigma, mask=mask_s, A=t["A"], s=s, f_calib=fc, f_data=fd,
                  jitter=j),
-            dict(data=cat.data, model=mc[b], sigma=cat.sigma, mask=mask_c, upper=up, A=t["Ac"]),
-            t["alpha_bar"], t["prior_sd"], t["flat"])
+            dict(data=cat_in.data, model=mc[b], sigma=cat_in.sigma, mask=mask_c, upper=up, A=t["Ac"]),
+            t["alpha_bar"], t["prior_sd"], t["flat"], phot=pdict)
     return out
 
 

@@ -468,6 +468,26 @@ extern "C" sps_status sps_library_load(const sps_library_desc *d, sps_library **
   g.lam2_d = (const double *)up(lam2.data(), Np * 8);
   g.gl_u = (const double *)up(glu.data(), glu.size() * 8);
   g.gl_w = (const double *)up(glw.data(), glw.size() * 8);
+  if (nl > 0) {   // the line profiles' nonzero nodes, compactly (joint marginalisation with photometry)
+    std::vector<int> k0(nl, 0), len(nl, 0);
+    int wmax = 1;
+    for (int l = 0; l < nl; ++l) {
+      const double *row = lineprof.data() + (size_t)l * N;
+      int a = 0, b = N - 1;
+      while (a < N && row[a] == 0.0) ++a;
+      while (b > a && row[b] == 0.0) --b;
+      k0[l] = a < N ? a : 0;
+      len[l] = a < N ? b - a + 1 : 0;
+      wmax = std::max(wmax, len[l]);
+    }
+    std::vector<double> prof((size_t)nl * wmax, 0.0);
+    for (int l = 0; l < nl; ++l)
+      for (int q = 0; q < len[l]; ++q) prof[(size_t)l * wmax + q] = lineprof[(size_t)l * N + k0[l] + q];
+    L->lprof_w = wmax;
+    L->lprof_d = (const double *)up(prof.data(), prof.size() * 8);
+    L->lprof_k0_d = (const int *)up(k0.data(), nl * 4);
+    L->lprof_len_d = (const int *)up(len.data(), nl * 4);
+  }
   L->kpos_d = (int *)up(kpos.data(), kpos.size() * 4);
   int *ksrc_d = (int *)up(ksrc.data(), ksrc.size() * 4);
   // the weight builder's node tables in one block, in its LDS order (DevLib::prep_tab);
@@ -1125,6 +1145,15 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
     lm.cat = joint ? joint->cat : nullptr;
     lm.cat_model = joint ? joint->cat_model : nullptr;
     lm.cat_ld = joint ? joint->cat_ld : 0;
+    lm.phot = joint ? joint->phot : nullptr;
+    lm.phot_model = joint ? joint->phot_model : nullptr;
+    lm.phot_ld = joint ? joint->phot_ld : 0;
+    lm.phot_scr = joint ? joint->phot_scr : nullptr;
+    lm.phot_ld_scr = joint ? joint->phot_ld_scr : 0;
+    lm.lprof = joint ? joint->lprof : nullptr;
+    lm.lprof_k0 = joint ? joint->lprof_k0 : nullptr;
+    lm.lprof_len = joint ? joint->lprof_len : nullptr;
+    lm.lprof_w = joint ? joint->lprof_w : 0;
     e = launch_linemarg(g, lm, s);
   }
   if (e != hipSuccess) return fail(SPS_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
@@ -1170,31 +1199,58 @@ extern "C" sps_status sps_logl_grad(const sps_library *L, sps_obs *o, const doub
   return run_adjoint(L, o, theta, B, prec, grad, (hipStream_t)stream);
 }
 
-extern "C" sps_status sps_logl_lines_joint(const sps_library *L, sps_obs *spec, sps_obs *cat, const double *theta,
-                                           int32_t B, int32_t prec, double *logl, void *stream) {
-  if (!L || !spec || !cat || !theta || !logl) return fail(SPS_E_INVAL, "NULL argument");
-  if (spec->lib != L || cat->lib != L) return fail(SPS_E_INVAL, "observation belongs to another library");
-  if (spec->host.kind != SPS_OBS_SPEC || spec->host.lm_mode == SPS_LINEMARG_NONE || cat->host.kind != SPS_OBS_LINES)
-    return fail(SPS_E_INVAL, "a joint marginalisation takes a spectrum with line_marg set and a line catalogue");
-  if (cat->host.n_data > kLineCatMaxHost)
-    return fail(SPS_E_SHAPE, "a jointly marginalised catalogue holds at most %d entries", kLineCatMaxHost);
-  std::vector<uint8_t> seen(L->n_line, 0);
+extern "C" sps_status sps_logl_lines_joint(const sps_library *L, sps_obs *spec, sps_obs *cat, sps_obs *phot,
+                                           const double *theta, int32_t B, int32_t prec, double *logl, void *stream) {
+  if (!L || !spec || !theta || !logl) return fail(SPS_E_INVAL, "NULL argument");
+  if (spec->lib != L || (cat && cat->lib != L) || (phot && phot->lib != L))
+    return fail(SPS_E_INVAL, "observation belongs to another library");
+  if (spec->host.kind != SPS_OBS_SPEC || spec->host.lm_mode == SPS_LINEMARG_NONE ||
+      (cat && cat->host.kind != SPS_OBS_LINES) || (phot && phot->host.kind != SPS_OBS_PHOT))
+    return fail(SPS_E_INVAL, "a joint marginalisation takes a spectrum with line_marg set, a line catalogue and a "
+                "photometric observation (each of the last two may be NULL)");
   int n_cat = 0;
-  for (int l : cat->host.lidx) n_cat += seen[l] ? 0 : (seen[l] = 1);
+  if (cat) {
+    if (cat->host.n_data > kLineCatMaxHost)
+      return fail(SPS_E_SHAPE, "a jointly marginalised catalogue holds at most %d entries", kLineCatMaxHost);
+    std::vector<uint8_t> seen(L->n_line, 0);
+    for (int l : cat->host.lidx) n_cat += seen[l] ? 0 : (seen[l] = 1);
+  }
   if (spec->host.lm_most + n_cat > kLineMargMax)
     return fail(SPS_E_SHAPE, "up to %d lines would be fitted jointly; at most %d", spec->host.lm_most + n_cat,
                 kLineMargMax);
+  if (phot) {
+    if (L->dev.vdisp)
+      return fail(SPS_E_INVAL, "a joint marginalisation with photometry takes a library without a free sigma_gal");
+    if (!L->lprof_d || (size_t)phot->ws.ld_scr < (size_t)phot->host.n_data * (kLineMargMax + 2))
+      return fail(SPS_E_SHAPE, "the photometric observation's scratch holds no band responses (%d bands)",
+                  phot->host.n_data);
+  }
   if (L->dev.vdisp && (spec->host.vd_nfft <= 0)) return fail(SPS_E_STATE, "spectrum without its Fourier plan");
   hipStream_t s = (hipStream_t)stream;
-  // the catalogue first (its logL lands in logl and is replaced), its model kept at the
-  // sorted rows; the spectrum's rows come in the same order (same points, same keys)
-  sps_status st = launch_forward(L, cat->ws, cat->dev_obs, nullptr, theta, B, prec, logl, nullptr, cat->host.n_data,
-                                 false, cat->host.n_data, &cat->host, nullptr, s, true, nullptr);
+  // the catalogue and the photometry first (their logL land in logl and are replaced),
+  // their models kept at the sorted rows; the spectrum's rows come in the same order
+  // (same points, same keys)
+  sps_status st = SPS_OK;
+  if (cat)
+    st = launch_forward(L, cat->ws, cat->dev_obs, nullptr, theta, B, prec, logl, nullptr, cat->host.n_data, false,
+                        cat->host.n_data, &cat->host, nullptr, s, true, nullptr);
+  if (st == SPS_OK && phot)
+    st = launch_forward(L, phot->ws, phot->dev_obs, nullptr, theta, B, prec, logl, nullptr, phot->host.n_data,
+                        false, phot->host.n_data, &phot->host, nullptr, s, true, nullptr);
   if (st != SPS_OK) return st;
   LineMargLaunch j{};
-  j.cat = cat->dev_obs;
-  j.cat_model = cat->ws.mbuf;
-  j.cat_ld = cat->host.n_data;
+  j.cat = cat ? cat->dev_obs : nullptr;
+  j.cat_model = cat ? cat->ws.mbuf : nullptr;
+  j.cat_ld = cat ? cat->host.n_data : 0;
+  j.phot = phot ? phot->dev_obs : nullptr;
+  j.phot_model = phot ? phot->ws.mbuf : nullptr;
+  j.phot_ld = phot ? phot->host.n_data : 0;
+  j.phot_scr = phot ? phot->ws.scr : nullptr;
+  j.phot_ld_scr = phot ? phot->ws.ld_scr : 0;
+  j.lprof = L->lprof_d;
+  j.lprof_k0 = L->lprof_k0_d;
+  j.lprof_len = L->lprof_len_d;
+  j.lprof_w = L->lprof_w;
   return launch_forward(L, spec->ws, spec->dev_obs, nullptr, theta, B, prec, logl, nullptr, spec->host.n_data, false,
                         spec->host.n_data, &spec->host, spec, s, false, &j);
 }

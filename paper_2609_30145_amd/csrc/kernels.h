@@ -93,6 +93,17 @@ struct LineMargLaunch {
   const DevObs *cat;
   const double *cat_model;
   int cat_ld;
+  // and with a photometric observation of the same points: its observation, its model at
+  // the sorted rows, a per-row scratch [B_pad][phot_ld_scr] (band responses, residuals,
+  // weights: >= n_band (NM + 2) doubles) and the library's compact FP64 line profiles
+  const DevObs *phot;
+  const double *phot_model;
+  int phot_ld;
+  double *phot_scr;
+  int phot_ld_scr;
+  const double *lprof;
+  const int *lprof_k0, *lprof_len;
+  int lprof_w;
 };
 hipError_t launch_linemarg(const DevLib &lib, const LineMargLaunch &lm, hipStream_t s);
 

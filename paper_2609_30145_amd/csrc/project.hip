@@ -715,6 +715,8 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
   __shared__ int s_p0[NM], s_p1[NM], s_aoff[NM], s_poff[NM + 1], s_atab;
   __shared__ unsigned char s_flat[NM];
   __shared__ short s_fidx[512];                  // library line -> fitted index, or -1
+  __shared__ short s_lidx[NM];                   // fitted index -> library line
+  __shared__ double s_pl;                        // joint with photometry: its lnL_diag
   __shared__ double s_cr[kLineCatMax], s_cw[kLineCatMax];   // joint: catalogue residuals, weights
   __shared__ double s_cl;                        // joint: the catalogue's -chi^2 / 2
   double *t_F = sPk, *t_lnl = sPk + 512, *t_sl = sPk + 1024;
@@ -765,6 +767,7 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
       const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
       if (f && pos < NM) {
         s_fidx[l] = (short)pos;
+        s_lidx[pos] = (short)l;
         s_F[pos] = t_F[l];
         s_lnl[pos] = t_lnl[l];
         s_isl[pos] = 1.0 / t_sl[l];
@@ -817,10 +820,87 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
     }
     s_cl = cl;
   }
-  if (n == 0) {   // no line to fit: the grid model's likelihood stands (and the catalogue's)
-    if (cat) {
+  // joint with photometry: per band b and fitted line j the band response A_bj, the model
+  // of line j alone per unit of its observed flux (its FP64 profile on the model grid
+  // through the birth cloud with the escape factors, the diffuse screen, the IGM, the
+  // observer frame and the filter nodes, as the projection forms the bands), in the row of
+  // the photometric scratch; then each band's residual at mu + A alpha_0, weight and the
+  // normalised Gaussian term of eq. 6 with the noise floor of eq. G1
+  const DevObs *ph = a.phot;
+  if (ph) {
+    const int nb = ph->n_band, N = lib.N;
+    double *pA = a.phot_scr + (size_t)r * a.phot_ld_scr, *pR = pA + (size_t)nb * NM, *pW = pR + nb;
+    const double z = pr.z, opz = 1.0 + z, lnopz = log1p(z);
+    const double fac = kC_cms * pr.scale_fnu / (opz * opz * kAng_cm * kAng_cm);
+    const double Eb = 0.85 - 1.9 * pr.delta;
+    const double wlo = lib.wave_d[0], whi = lib.wave_d[N - 1];
+    for (int q = tid; q < nb * n; q += 256) {
+      const int b = q / n, j = q - b * n, l = s_lidx[j];
+      const int k0 = a.lprof_k0[l], kl = a.lprof_len[l];
+      const double *prof = a.lprof + (size_t)l * a.lprof_w;
+      const double Ll = a.Lline[(size_t)r * nl + l] / kLsun;
+      auto Fline = [&](int k) {   // line l's rest-frame contribution at node k
+        if (k < k0 || k >= k0 + kl) return 0.0;
+        const double lv = lib.lnlv_d[k];
+        const double td = exp(-pr.tau_diff * exp(pr.delta * lv) * (lib.dust_a_d[k] + Eb * lib.dust_d_d[k]));
+        const double tb = pr.bc_p * exp(-pr.tau_bc * exp(pr.alpha_bc * lv)) + pr.bc_q;
+        return td * tb * Ll * prof[k - k0] * igm_T(lib, th, z, lib.wave_d[k] * opz);
+      };
+      // the band's nodes whose bracketing interval touches the profile's nodes
+      const double lo = lib.wave_d[max(k0 - 1, 0)] * opz, hi = lib.wave_d[min(k0 + kl, N - 1)] * opz;
+      int n0 = ph->band_off[b], n1 = ph->band_off[b + 1];
+      {
+        int lo_i = n0, hi_i = n1;
+        while (lo_i < hi_i) {
+          const int mid = (lo_i + hi_i) >> 1;
+          if (ph->fw[mid] < lo) lo_i = mid + 1; else hi_i = mid;
+        }
+        n0 = lo_i;
+      }
+      double sum = 0.0;
+      for (int nn = n0; nn < n1 && ph->fw[nn] <= hi; ++nn) {
+        const double lr = ph->fw[nn] / opz;
+        if (!(lr >= wlo && lr <= whi)) continue;
+        int k;
+        if (lib.log_uniform) k = min(max((int)floor((ph->fwln[nn] - lnopz - lib.lnw0) * lib.inv_dlnw), 0), N - 2);
+        else k = bracket(lib.wave_d, N, lr);
+        const double w0 = lib.wave_d[k], w1 = lib.wave_d[k + 1];
+        const double f0 = Fline(k), f1 = Fline(k + 1);
+        const double t = (lr - w0) / (w1 - w0);
+        sum += ph->fr_d[nn] * (f0 + t * (f1 - f0));
+      }
+      pA[(size_t)b * NM + j] = fac * sum / s_F[j];
+    }
+    __syncthreads();
+    const double ns = (ph->noise_flags & 1) ? exp(th[TH_LOG_ERR_SCALE]) : 1.0;
+    const double fcp = (ph->noise_flags & 2) ? exp(th[TH_LOG_F_CALIB]) : 0.0;
+    const double fdp = (ph->noise_flags & 4) ? exp(th[TH_LOG_F_DATA]) : 0.0;
+    const double jtp = (ph->noise_flags & 8) ? exp(th[TH_LOG_JITTER]) : 0.0;
+    double lp = 0.0;
+    for (int b = tid; b < nb; b += 256) {
+      double rr = 0.0, w = 0.0;
+      if (ph->mask[b]) {
+        const double m = a.phot_model[(size_t)r * a.phot_ld + b], d = ph->data[b], sg = ph->sigma[b];
+        const double v = ns * ns * sg * sg + fcp * fcp * m * m + fdp * fdp * d * d + jtp * jtp;
+        w = 1.0 / v;
+        rr = d - m;
+        for (int j = 0; j < n; ++j)
+          if (s_flat[j]) rr += s_F[j] * pA[(size_t)b * NM + j];
+        lp += -0.5 * rr * rr * w - 0.5 * log(2.0 * kPi * v);
+      }
+      pR[b] = rr;
+      pW[b] = w;
+    }
+    lp = wave_reduce_sum(lp);
+    if (lane == 0) red[wv] = lp;
+    __syncthreads();
+    if (tid == 0) s_pl = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+  }
+  if (n == 0) {   // no line to fit: the grid model's likelihood stands (and the others')
+    if (cat || ph) {
       __syncthreads();
-      if (tid == 0 && a.logl) a.logl[pr.b] += s_cl;
+      if (tid == 0 && a.logl) a.logl[pr.b] += (cat ? s_cl : 0.0) + (ph ? s_pl : 0.0);
     }
     return;
   }
@@ -975,6 +1055,25 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
     }
   }
   if (cat) __syncthreads();
+  if (ph) {   // the photometry: b_j += sum_b w r A_bj, P_kj += sum_b w A_bj A_bk (bands in order)
+    const int nb = ph->n_band;
+    const double *pA = a.phot_scr + (size_t)r * a.phot_ld_scr, *pR = pA + (size_t)nb * NM, *pW = pR + nb;
+    for (int j = tid; j < n; j += 256) {
+      double acc = 0.0;
+      for (int b = 0; b < nb; ++b) acc += pW[b] * pR[b] * pA[(size_t)b * NM + j];
+      s_b[j] += acc;
+    }
+    for (int q = tid; q < n * (n + 1) / 2; q += 256) {   // q = k (k + 1) / 2 + j, j <= k
+      int k = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+      while (k * (k + 1) / 2 > q) --k;
+      while ((k + 1) * (k + 2) / 2 <= q) ++k;
+      const int j = q - k * (k + 1) / 2;
+      double acc = 0.0;
+      for (int b = 0; b < nb; ++b) acc += pW[b] * pA[(size_t)b * NM + j] * pA[(size_t)b * NM + k];
+      sPk[q] += acc;
+    }
+    __syncthreads();
+  }
   // ---- 4. Cholesky with the forward solve carried along, one barrier per column: column j
   // (rows below the diagonal) and b_j are final when step j starts, and step j writes only
   // columns > j and b_i, i > j.  Every thread forms L_jj and y_j; thread i > j updates its row
@@ -998,7 +1097,8 @@ __global__ void __launch_bounds__(256) k_linemarg(DevLib lib, LineMargLaunch a) 
     __syncthreads();
   }
   if (tid == 0 && a.logl)
-    a.logl[pr.b] = lnl_diag + (cat ? s_cl : 0.0) + 0.5 * ssq - sum_ln - s_lnsg + 0.5 * (double)s_nflat * log(2.0 * kPi);
+    a.logl[pr.b] = lnl_diag + (cat ? s_cl : 0.0) + (ph ? s_pl : 0.0) + 0.5 * ssq - sum_ln - s_lnsg +
+                   0.5 * (double)s_nflat * log(2.0 * kPi);
 }
 
 hipError_t launch_linemarg(const DevLib &lib, const LineMargLaunch &lm, hipStream_t s) {

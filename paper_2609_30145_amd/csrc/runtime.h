@@ -109,6 +109,11 @@ struct sps_library {
   uint32_t precisions = 0;
   sps::DevLib dev;
   int *kpos_d = nullptr;
+  // the line profiles on the model grid in FP64, compactly: line l's nonzero nodes start at
+  // lprof_k0[l], lprof_len[l] <= lprof_w of them (joint line marginalisation with photometry)
+  const double *lprof_d = nullptr;
+  const int *lprof_k0_d = nullptr, *lprof_len_d = nullptr;
+  int lprof_w = 0;
   sps::DeviceBuffers mem;
   void host_wave(std::vector<double> &w) const;   // copies wave[N] from the device
 };

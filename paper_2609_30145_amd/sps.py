@@ -103,7 +103,7 @@ def lib():
         L.sps_logl.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
         L.sps_logl_grad.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
         L.sps_logl_static.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
-        L.sps_logl_lines_joint.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, vp, vp]
+        L.sps_logl_lines_joint.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_int32, vp, vp]
         L.sps_obs_enable_timing.argtypes = [vp, C.c_int32]
         L.sps_obs_contract_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                               C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -373,13 +373,15 @@ def logl_static(library, obs, theta, precision="fp32", stream=None, return_model
     return (out, model) if return_model else out
 
 
-def logl_lines_joint(library, spec, cat, theta, precision="fp32", stream=None):
-    """logL [B] (float64) of a spectrum and a line catalogue with the line fluxes
-    marginalised jointly — sps_logl_lines_joint."""
+def logl_lines_joint(library, spec, theta, cat=None, phot=None, precision="fp32", stream=None):
+    """logL [B] (float64) of a spectrum with a line catalogue and/or a photometric
+    observation of the same object, the line fluxes marginalised jointly —
+    sps_logl_lines_joint."""
     import torch
     _check_theta(library, theta)
     out = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
-    check(lib().sps_logl_lines_joint(library.handle, spec.handle, cat.handle, C.c_void_p(theta.data_ptr()),
+    check(lib().sps_logl_lines_joint(library.handle, spec.handle, cat.handle if cat is not None else None,
+                                     phot.handle if phot is not None else None, C.c_void_p(theta.data_ptr()),
                                      theta.shape[0], PRECISIONS[precision], C.c_void_p(out.data_ptr()),
                                      _stream_ptr(stream)))
     return out

@@ -9,11 +9,12 @@ C ABI:
   - a batch over several M tiles with a ragged tail at FP64, FP32 and FP16 (three passes);
   - the gradient, the allocation-free call and a calibration polynomial at the same time
     are refused; more than 128 lines within the pixel range is SPS_E_SHAPE;
-  - the joint marginalisation over the spectrum and a line catalogue of the same object
-    (sps_logl_lines_joint): single lines and blends, lines inside and outside the pixel
-    range (fitted through the catalogue alone), two upper limits and a masked entry, with
-    Gaussian priors (two lines flat) and with every line flat (single-line entries: a flat
-    line seen only in a blend is not identified and its marginal diverges).
+  - the joint marginalisation over the spectrum, a line catalogue and 20-band photometry of
+    the same object (sps_logl_lines_joint): single lines and blends, lines inside and
+    outside the pixel range (fitted through the catalogue alone), two upper limits and a
+    masked entry, a masked band, with Gaussian priors (two lines flat) and with every line
+    flat (single-line entries: a flat line seen only in a blend is not identified and its
+    marginal diverges); spectrum + catalogue, spectrum + photometry, and all three.
 
 Tolerances: logL FP64 1e-10, FP32 and FP16 1e-4, relative to the larger of the marginal
 and the grid-model likelihood (the marginal likelihood is a difference of terms of that
@@ -170,34 +171,52 @@ def cat_obs(case, blends, seed=29):
     return lobs
 
 
-@pytest.mark.parametrize("mode,frac,some_flat", [("gauss", 0.3, True), ("flat", 0.0, False)])
-def test_joint_with_a_line_catalogue(case, mode, frac, some_flat):
+def phot_obs(case, seed=31):
+    pobs = om.Photometry(filters=wl.make_filters("gauss20"))
+    m_true = om.predict(case["olib"], pobs, case["theta_true"])[0]
+    pobs.data, pobs.sigma = wl.noisy_photometry(m_true, seed)
+    pobs.mask = np.ones(m_true.size, dtype=bool)
+    pobs.mask[4] = False
+    return pobs
+
+
+@pytest.mark.parametrize("mode,frac,some_flat,with_cat,with_phot", [
+    ("gauss", 0.3, True, True, False), ("flat", 0.0, False, True, False),
+    ("gauss", 0.3, True, True, True), ("gauss", 0.3, False, False, True), ("flat", 0.0, False, True, True)])
+def test_joint_with_a_line_catalogue(case, mode, frac, some_flat, with_cat, with_phot):
     c, L, theta = case
     obs = c["obs"]
     blends = JOINT_BLENDS if mode == "gauss" else JOINT_SINGLES
-    lobs = cat_obs(c, blends)
+    lobs = cat_obs(c, blends) if with_cat else None
+    pobs = phot_obs(c) if with_phot else None
     flat = np.zeros(CFG.n_lines, dtype=bool)
     if some_flat:
         flat[[5, 17]] = True
     sobs = dataclasses.replace(obs, noise={}, line_marg=mode, line_prior_frac=frac,
                                line_flat=flat if some_flat else None)
-    ref = om.logl_lines_joint(c["olib"], sobs, lobs, theta)
-    alone = om.logl(c["olib"], sobs, theta) + om.logl(c["olib"], lobs, theta)
+    ref = om.logl_lines_joint(c["olib"], sobs, lobs, theta, phot=pobs)
+    alone = om.logl(c["olib"], sobs, theta)
+    if lobs is not None:
+        alone = alone + om.logl(c["olib"], lobs, theta)
+    if pobs is not None:
+        alone = alone + om.logl(c["olib"], pobs, theta)
     assert np.all(np.isfinite(ref)) and np.max(np.abs(ref - alone)) > 1.0
     O = spec_obs(L, obs, 256, line_marg=mode, line_prior_frac=frac, line_flat=flat if some_flat else None)
     Oc = sps.Observation(L, "lines", 256, blends=blends, upper=lobs.upper, data=lobs.data, sigma=lobs.sigma,
-                         mask=lobs.mask)
+                         mask=lobs.mask) if lobs is not None else None
+    Op = sps.Observation(L, "phot", 256, filters=pobs.filters, data=pobs.data, sigma=pobs.sigma,
+                         mask=pobs.mask) if pobs is not None else None
     tt = torch.tensor(theta, dtype=torch.float64, device="cuda")
     scale = np.maximum(1.0, np.maximum(np.abs(ref), np.abs(alone)))
     for prec in PRECS:
-        say(f"  joint {mode} flat {some_flat} {prec}")
-        ll = sps.logl_lines_joint(L, O, Oc, tt, prec)
+        say(f"  joint {mode} flat {some_flat} catalogue {with_cat} photometry {with_phot} {prec}")
+        ll = sps.logl_lines_joint(L, O, tt, cat=Oc, phot=Op, precision=prec)
         torch.cuda.synchronize()
         ll = ll.cpu().numpy()
         lle = np.abs(ll - ref) / scale
         say(f"    logL rel err {lle.max():.3e}")
         assert np.all(np.isfinite(ll))
         assert lle.max() < LOGL_TOL[prec]
-    with pytest.raises(sps.SpsError) as ei:   # the catalogue first: the wrong kinds
-        sps.logl_lines_joint(L, Oc, O, tt, "fp32")
+    with pytest.raises(sps.SpsError) as ei:   # the observations in the wrong places
+        sps.logl_lines_joint(L, Oc if Oc is not None else Op, tt, cat=O, precision="fp32")
     assert ei.value.code == -1

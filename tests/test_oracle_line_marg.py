@@ -13,7 +13,10 @@ The joint marginalisation over a spectrum and a line catalogue of one object is 
 against the closed-form Gaussian convolution of a catalogue-only line, against direct
 numerical integration over two amplitudes seen by both observations (a blend and an
 upper limit among the entries), and reduces to the spectrum's own marginal when the
-catalogue has no detection.
+catalogue has no detection.  With photometry as well: the band responses of all the
+library's lines times their grid fluxes are exactly the model's line contribution to each
+band (the model with and without its lines on the grid), and the three-observation closed
+form matches direct integration.
 """
 import math
 
@@ -223,3 +226,60 @@ def test_joint_without_catalogue_detections_is_the_spectrum_marginal():
     got = lk.joint_line_marginal_lnlike(spec, cat, a_bar, sd, flat)
     want = lk.line_marginal_lnlike(d, model, sigma, mask, prof, a_bar, sd, flat)
     assert got == pytest.approx(want, rel=1e-14, abs=1e-10)
+
+
+def test_band_responses_times_fluxes_are_the_models_line_contribution():
+    cfg = wl.reduced(wl.CONFIGS["c1"], n_age=40, logz=tuple(np.linspace(-2.5, 0.5, 6)), n_wave=1500, n_sfh=12,
+                     n_zh=4, n_lines=24)
+    lib = wl.make_library(cfg, 0)
+    lines = wl.make_lines(cfg, lib, 1)
+    dust = wl.make_dust_tables(cfg, lib["wave"])
+    for kw in (dict(), dict(escape="runaway_bc", igm=True)):
+        L = om.build_library(cfg, lib, lines, dust, **kw)
+        cols = om.lib_columns(L)
+        phot = om.Photometry(filters=wl.make_filters("gauss20"))
+        th = wl.make_theta(cfg, 3, seed=9, escape=bool(kw), igm=bool(kw))
+        th[:, 1] = [0.7, 2.5, 6.0]
+        with_lines = om.predict(L, phot, th)
+        no_lines = om.predict(L, phot, th, rf=om.rest_frame(L, th, lines_on_grid=False))
+        rf = om.rest_frame(L, th, lines_on_grid=False)
+        idx = np.arange(cfg.n_lines)
+        for b in range(th.shape[0]):
+            A = om.line_band_response(L, phot, th[b], cols, rf["Lline"][b], idx)
+            _, dl = om.observer_scale(L, th[b], cols)
+            Fl = om.line_fluxes(L, th[b], cols, rf["Lline"][b], dl)
+            np.testing.assert_allclose(A @ Fl, with_lines[b] - no_lines[b], rtol=1e-10,
+                                       atol=1e-12 * np.max(np.abs(with_lines[b])))
+
+
+def test_joint_with_photometry_matches_direct_integration():
+    x, mu, prof, sigma, mask, rng = _toy(seed=7)
+    a_true, a_bar = np.array([0.5, 0.9]), np.array([0.6, 0.8])
+    sd = np.array([0.15, 0.3])
+    flat = np.array([False, True])
+    d = mu + prof @ a_true + sigma * rng.normal(size=x.size)
+    model = mu + prof @ a_bar
+    # three bands that see the lines with different responses, one masked
+    Ap = np.array([[0.8, 0.1], [0.3, 0.6], [0.5, 0.5]])
+    mp0 = np.array([2.0, 1.5, 1.0])
+    dp = mp0 + Ap @ a_true + np.array([0.02, -0.03, 0.0])
+    sp = np.array([0.05, 0.04, 0.05])
+    mkp = np.array([True, True, False])
+    spec = _spec(d, model, sigma, mask, prof)
+    phot = dict(data=dp, model=mp0 + Ap @ a_bar, sigma=sp, mask=mkp, A=Ap)
+    closed = lk.joint_line_marginal_lnlike(spec, None, a_bar, sd, flat, phot=phot)
+    g0 = np.linspace(0.3, 0.75, 451)
+    g1 = np.linspace(0.6, 1.2, 451)
+    v = np.where(mask, sigma, 1.0) ** 2
+    vals = np.empty((g0.size, g1.size))
+    for i, a0 in enumerate(g0):
+        for j, a1 in enumerate(g1):
+            a = np.array([a0, a1])
+            r = np.where(mask, d - mu - prof @ a, 0.0)
+            ll = np.sum(np.where(mask, -0.5 * r * r / v - 0.5 * np.log(2 * np.pi * v), 0.0))
+            rp = (dp - mp0 - Ap @ a)[mkp]
+            ll += np.sum(-0.5 * (rp / sp[mkp]) ** 2 - 0.5 * np.log(2 * np.pi * sp[mkp] ** 2))
+            ll += -0.5 * ((a0 - a_bar[0]) / sd[0]) ** 2 - 0.5 * math.log(2 * math.pi * sd[0] ** 2)
+            vals[i, j] = ll
+    direct = logsumexp(vals) + math.log((g0[1] - g0[0]) * (g1[1] - g1[0]))
+    assert closed == pytest.approx(direct, rel=0.0, abs=1e-5)
