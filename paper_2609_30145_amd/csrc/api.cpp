@@ -1011,7 +1011,7 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   // call; clear it so that only this call's own launches are checked below
   (void)hipGetLastError();
   const int mode = prec == 0 ? 0 : prec == 1 ? 1 : (prec == 2 || prec == 4 || prec == 6 || prec == 8) ? 2 : 3;
-  const int MT = contract_mtile(prec);
+  const int MT = contract_mtile(prec, B_pad);
   const int tf = contract_ktile_factor(prec);
   int *ranks = B >= kRankKernelMinB ? w.ranks : nullptr;
   hipError_t e = launch_keys(g, theta, g.P, B, w.keys, ranks, s);

@@ -514,7 +514,7 @@ hipError_t launch_tile_list(const PointRow *rows, int B_pad, int MT, int n_nt, b
   return hipGetLastError();
 }
 
-int contract_mtile(int precision) { return precision <= 1 ? 64 : 128; }
+int contract_mtile(int precision, int B_pad) { return precision <= 1 || B_pad <= kSmallMtBatch ? 64 : 128; }
 int contract_ktile_factor(int precision) { return precision >= 2 ? 2 : 1; }
 
 hipError_t launch_contract16_impl(const DevLib &lib, const ContractLaunch &cl, int n_mt, hipStream_t s);
@@ -545,7 +545,7 @@ hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStrea
   a.ion_nlim = lib.ion_nlim;
   a.skip_lo = escape_skip(lib, cl.pass, false);
   a.skip_hi = escape_skip(lib, cl.pass, true);
-  const int MT = contract_mtile(cl.precision);
+  const int MT = contract_mtile(cl.precision, cl.B_pad);
   const int n_mt = cl.B_pad / MT;
   if (cl.precision == 0) {
     a.LTa = lib.LT64;

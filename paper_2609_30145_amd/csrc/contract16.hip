@@ -57,8 +57,9 @@ __device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[8], 
 }
 
 // PASSES: 1 = W_h H; 2 = W_h H + W_h R; 3 = W_h H + W_h R + W_l H; 4 = W_h H + W_l H.
-// Block tile 128 (points) x 64 (wavelengths), K tile 64; four waves stacked along M,
-// each 32 x 64 (two 32x32x16 MFMA accumulators).  Each wave reads its own weight
+// Block tile MT (points: 128, or 64 for small batches) x 64 (wavelengths), K tile 64;
+// MT / 32 waves stacked along M, each 32 x 64 (two 32x32x16 MFMA accumulators).  A row's
+// sums do not depend on MT: the K tiles its M tile adds beyond its own are zero rows.  Each wave reads its own weight
 // fragments straight from global memory into registers (the weight planes are stored
 // fragment-tiled, so one wave load is two contiguous 512-byte runs) with two register
 // sets, the next K tile in flight while the current one is multiplied.  The library
@@ -68,11 +69,11 @@ __device__ __forceinline__ void bc16(v16f (&acc)[BM][BN], const float (*sp)[8], 
 // the 8 rows of one parity among 16 consecutive rows, on distinct banks.
 // SPAN: the block's tile comes from the compacted list of pairs that meet the rows' spans
 // (blocks past the list return at once); otherwise every pair of the grid.
-template <bool BF, int PASSES, bool SPAN>
-__global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
-  constexpr int MT = 128, NT = 64, KT = 64, NCH = KT / 8, WTM = 32, BM = 1, BN = 2;
+template <bool BF, int PASSES, bool SPAN, int MT>
+__global__ void __launch_bounds__(2 * MT, MT == 64 && (PASSES == 2 || PASSES == 3) ? 2 : 3) k_contract_16(ContractArgs16 a) {
+  constexpr int NT = 64, KT = 64, NCH = KT / 8, WTM = 32, BM = 1, BN = 2, NTH = 2 * MT;
   constexpr bool USE_WL = PASSES >= 3, USE_R = PASSES == 2 || PASSES == 3;
-  constexpr int B8 = NT * KT / 8 / 256;   // 16-byte library chunks per thread and K tile
+  constexpr int B8 = NT * KT / 8 / NTH;   // 16-byte library chunks per thread and K tile
   __shared__ __attribute__((aligned(16))) uint16_t Bh[2][NT * KT];
   __shared__ __attribute__((aligned(16))) uint16_t Br[2][USE_R ? NT * KT : 8];
   __shared__ float sp[MT][8];
@@ -90,7 +91,7 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
   const int li = lane & 31, lh = lane >> 5;
   const int K_pad = a.K_pad, n_kt = K_pad / KT;
 
-  for (int r = tid; r < MT; r += 256) {
+  for (int r = tid; r < MT; r += NTH) {
     const PointRow &pr = a.rows[m0 + r];
     sp[r][0] = (float)pr.tau_bc;
     sp[r][1] = (float)pr.alpha_bc;
@@ -121,7 +122,7 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
   int offB[B8];
 #pragma unroll
   for (int q = 0; q < B8; ++q) {
-    const int idx = tid + 256 * q;
+    const int idx = tid + NTH * q;
     offB[q] = (n0 + idx / NCH) * K_pad + (idx % NCH) * 8;
   }
   u32x4 ah0[4], al0[USE_WL ? 4 : 1], ah1[4], al1[USE_WL ? 4 : 1], rbh[B8], rbr[USE_R ? B8 : 1];
@@ -144,7 +145,7 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
 #define SPS_STOREB(buf_)                                                           \
   {                                                                                \
     _Pragma("unroll") for (int q = 0; q < B8; ++q) {                               \
-      const int idx = tid + 256 * q, row = idx / NCH, c = idx % NCH;               \
+      const int idx = tid + NTH * q, row = idx / NCH, c = idx % NCH;               \
       *(u32x4 *)(&Bh[buf_][SPS_SW(row, c)]) = rbh[q];                              \
       if constexpr (USE_R) *(u32x4 *)(&Br[buf_][SPS_SW(row, c)]) = rbr[q];         \
     }                                                                              \
@@ -237,10 +238,16 @@ __global__ void __launch_bounds__(256, 3) k_contract_16(ContractArgs16 a) {
 
 
 template <bool BF, int PASSES>
-static void launch16(const ContractArgs16 &a, int n_mt, int N_pad, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+static void launch16(const ContractArgs16 &a, int n_mt, int MT, int N_pad, hipStream_t s, hipEvent_t e0,
+                     hipEvent_t e1) {
   const dim3 grid(n_mt * (N_pad / 64));
-  if (a.list) hipExtLaunchKernelGGL((k_contract_16<BF, PASSES, true>), grid, dim3(256), 0, s, e0, e1, 0, a);
-  else hipExtLaunchKernelGGL((k_contract_16<BF, PASSES, false>), grid, dim3(256), 0, s, e0, e1, 0, a);
+  if (MT == 64) {
+    if (a.list) hipExtLaunchKernelGGL((k_contract_16<BF, PASSES, true, 64>), grid, dim3(128), 0, s, e0, e1, 0, a);
+    else hipExtLaunchKernelGGL((k_contract_16<BF, PASSES, false, 64>), grid, dim3(128), 0, s, e0, e1, 0, a);
+  } else {
+    if (a.list) hipExtLaunchKernelGGL((k_contract_16<BF, PASSES, true, 128>), grid, dim3(256), 0, s, e0, e1, 0, a);
+    else hipExtLaunchKernelGGL((k_contract_16<BF, PASSES, false, 128>), grid, dim3(256), 0, s, e0, e1, 0, a);
+  }
 }
 
 hipError_t launch_contract16_impl(const DevLib &lib, const ContractLaunch &cl, int n_mt, hipStream_t s) {
@@ -272,14 +279,14 @@ hipError_t launch_contract16_impl(const DevLib &lib, const ContractLaunch &cl, i
   // the gradient pass (which needs the young part) runs on the FP32 / FP64 paths only
   if (!a.H || !a.R || Yatt) return hipErrorInvalidValue;
   switch (precision) {
-    case 2: launch16<true, 3>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
-    case 3: launch16<false, 3>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
-    case 4: launch16<true, 1>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
-    case 5: launch16<false, 1>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
-    case 6: launch16<true, 2>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
-    case 7: launch16<false, 2>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
-    case 8: launch16<true, 4>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
-    case 9: launch16<false, 4>(a, n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 2: launch16<true, 3>(a, n_mt, cl.B_pad / n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 3: launch16<false, 3>(a, n_mt, cl.B_pad / n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 4: launch16<true, 1>(a, n_mt, cl.B_pad / n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 5: launch16<false, 1>(a, n_mt, cl.B_pad / n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 6: launch16<true, 2>(a, n_mt, cl.B_pad / n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 7: launch16<false, 2>(a, n_mt, cl.B_pad / n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 8: launch16<true, 4>(a, n_mt, cl.B_pad / n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
+    case 9: launch16<false, 4>(a, n_mt, cl.B_pad / n_mt, lib.N_pad, s, cl.ev_start, cl.ev_stop); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

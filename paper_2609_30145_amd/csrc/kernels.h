@@ -26,6 +26,7 @@ size_t prep_smem_bytes(const DevLib &lib, int mode);   // mode as PrepLaunch::mo
 // batch-ordering keys (the weight builder ranks the points by them)
 // batch-ordering keys and, when ranks is not NULL, each point's rank among them (ties by
 // index; the weight builder ranks its own point otherwise)
+constexpr int kSmallMtBatch = 256;     // 16-bit contraction: 64-row M tiles up to this padded batch
 constexpr int kRankKernelMinB = 2048;   // batches from this size rank in a kernel of their own
 hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, int *ranks,
                        hipStream_t s);
@@ -52,7 +53,9 @@ struct ContractLaunch {
 hipError_t launch_tile_list(const PointRow *rows, int B_pad, int MT, int n_nt, bool nt_major, int *list,
                             hipStream_t s);
 // M tile used by the contraction of a precision (the occupancy list granularity)
-int contract_mtile(int precision);
+// (16-bit: 64 rows for batches of at most kSmallMtBatch padded rows, where 128-row tiles
+// would leave CUs idle and load the padding rows' weights; 128 otherwise)
+int contract_mtile(int precision, int B_pad);
 int contract_ktile_factor(int precision);   // K tile in units of kKTile
 hipError_t launch_contract(const DevLib &lib, const ContractLaunch &cl, hipStream_t s);
 
