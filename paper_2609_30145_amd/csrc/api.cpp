@@ -1020,7 +1020,7 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   pl.P = g.P;
   pl.B = B;
   pl.B_pad = B_pad;
-  pl.keys = w.keys;
+  pl.keys = B <= kSelfKeyMaxB ? nullptr : w.keys;   // NULL: the weight builder forms the keys
   pl.ranks = ranks;
   pl.obs_table = obs_table;
   pl.point_obs = point_obs;

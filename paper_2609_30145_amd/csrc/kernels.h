@@ -27,6 +27,7 @@ size_t prep_smem_bytes(const DevLib &lib, int mode);   // mode as PrepLaunch::mo
 // batch-ordering keys and, when ranks is not NULL, each point's rank among them (ties by
 // index; the weight builder ranks its own point otherwise)
 constexpr int kSmallMtBatch = 256;     // 16-bit contraction: 64-row M tiles up to this padded batch
+constexpr int kSelfKeyMaxB = 512;      // batches up to this size: each weight-builder workgroup forms the keys
 constexpr int kRankKernelMinB = 2048;   // batches from this size rank in a kernel of their own
 hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, int *ranks,
                        hipStream_t s);

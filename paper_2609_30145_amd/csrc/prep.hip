@@ -141,7 +141,7 @@ enum WMode { W_F64 = 0, W_F32 = 1, W_BF16 = 2, W_F16 = 3 };
 struct PrepArgs {
   const double *theta;
   int P, B, B_pad;
-  const double *keys;       // [B] batch-ordering keys (k_keys)
+  const double *keys;       // [B] batch-ordering keys (k_keys), or NULL: formed here (B <= kSelfKeyMaxB)
   const int *ranks;         // [B] each point's row in the key order (k_rank), or NULL: ranked here
   const DevObs *obs_table;
   const int *point_obs;     // [B] observation slot per point, NULL = slot 0
@@ -382,10 +382,17 @@ __global__ void __launch_bounds__(256) k_prep(DevLib lib, PrepArgs a) {
     for (int u = 0; u < UK; ++u) vk[u] = ke4[min(tid + 256 * u, nk8 - 1)];
   }
   double kq[UQ], my = 0.0;
-  if (!a.ranks) {   // small batches rank themselves (no k_rank launch)
+  if (!a.ranks && a.keys) {   // small batches rank themselves (no k_rank launch)
 #pragma unroll
     for (int u = 0; u < UQ; ++u) kq[u] = a.keys[min(tid + 256 * u, a.B - 1)];
     my = a.keys[b];
+  } else if (!a.ranks) {      // the smallest ones also form the keys here (no k_keys launch)
+#pragma unroll
+    for (int u = 0; u < UQ; ++u) {
+      const int j = tid + 256 * u;
+      kq[u] = j < a.B ? sort_key(lib, a.theta + (size_t)j * a.P) : 0.0;
+    }
+    my = sort_key(lib, th);
   }
 
   // cosmology (Sec. 2.6): D_C by composite Gauss-Legendre in u = (1+z')^-1/2, where
@@ -948,6 +955,7 @@ size_t prep_smem_bytes(const DevLib &lib, int mode) {
 
 hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, int *ranks,
                        hipStream_t s) {
+  if (!ranks && B <= kSelfKeyMaxB) return hipSuccess;   // the weight builder forms the keys itself
   hipLaunchKernelGGL(k_keys, dim3((B + 255) / 256), dim3(256), 0, s, lib, theta, P, B, keys);
   if (ranks) hipLaunchKernelGGL(k_rank, dim3((B + 63) / 64), dim3(256), 0, s, keys, B, ranks);
   return hipGetLastError();

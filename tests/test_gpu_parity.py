@@ -131,17 +131,19 @@ def test_batch_edges_single_point_and_composition(c1s):
 @pytest.mark.parametrize("prec", ["fp32", "fp16"])
 def test_large_batch_ranking_path_is_bitwise_the_small_one(c1s, prec):
     # batches from 2048 points rank in a kernel of their own and reduce the M tiles' spans
-    # in another; the row results must not depend on which path ordered the batch.  The
-    # 200 vectors repeated make a 2200-point batch with every key tied ten-fold or more.
+    # in another; up to 512 points each weight-builder workgroup forms the sort keys itself,
+    # in between a key kernel runs first; up to 256 padded rows the 16-bit contraction uses
+    # 64-row M tiles.  The row results must not depend on which path ordered the batch.  The
+    # 200 vectors repeated make batches of 400, 600 and 2200 points with every key tied.
     case, L, _, _, _ = c1s
-    say(f"c1-reduced {prec} B=2200 (rank kernel) against B=200 (in-builder rank)")
+    say(f"c1-reduced {prec} B=400, 600, 2200 against B=200")
     Ob = gpu_observation(L, case, max_batch=2304)
-    big = np.tile(case["theta"], (11, 1))
-    ll_b, m_b = gpu_run(L, Ob, big, prec)
     ll_s, m_s = gpu_run(L, Ob, case["theta"], prec)
-    for k in range(11):
-        assert np.array_equal(m_b[200 * k:200 * (k + 1)], m_s)
-        assert np.array_equal(ll_b[200 * k:200 * (k + 1)], ll_s)
+    for reps in (2, 3, 11):
+        ll_b, m_b = gpu_run(L, Ob, np.tile(case["theta"], (reps, 1)), prec)
+        for k in range(reps):
+            assert np.array_equal(m_b[200 * k:200 * (k + 1)], m_s)
+            assert np.array_equal(ll_b[200 * k:200 * (k + 1)], ll_s)
 
 
 def test_batch_larger_than_workspace_is_rejected(c1s):
