@@ -1048,7 +1048,8 @@ sps_status launch_forward(const sps_library *L, Workspace &w, const DevObs *obs_
   if ((calib || lmarg) && (grad || !w.mbuf || !w.scr || w.ld_scr < std::max(24, 2 * one->n_data)))
     return fail(SPS_E_INVAL, "calibration polynomial / line marginalisation: no gradient, and a full workspace");
   const int n_nt = g.N_pad / 64;
-  const bool span = g.log_uniform && prec != SPS_FP64 && w.tiles && B_pad / MT <= kTileListMaxM;
+  const bool dense_small = !grad && B_pad <= kDenseMaxBpad && (B_pad / MT) * n_nt <= kDenseMaxBlocks;
+  const bool span = g.log_uniform && prec != SPS_FP64 && w.tiles && B_pad / MT <= kTileListMaxM && !dense_small;
   w.f_spans = span && !lines_only;
   ContractLaunch cl;
   cl.list = span ? w.tiles : nullptr;

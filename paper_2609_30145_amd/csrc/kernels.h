@@ -27,6 +27,10 @@ size_t prep_smem_bytes(const DevLib &lib, int mode);   // mode as PrepLaunch::mo
 // batch-ordering keys and, when ranks is not NULL, each point's rank among them (ties by
 // index; the weight builder ranks its own point otherwise)
 constexpr int kSmallMtBatch = 256;     // 16-bit contraction: 64-row M tiles up to this padded batch
+// forward launches of at most kDenseMaxBpad padded rows whose whole grid fits kDenseMaxBlocks
+// blocks (one per CU) skip the tile list: the extra tiles run on otherwise idle CUs, and
+// the list kernel's serial latency is saved
+constexpr int kDenseMaxBpad = 128, kDenseMaxBlocks = 256;
 constexpr int kSelfKeyMaxB = 512;      // batches up to this size: each weight-builder workgroup forms the keys
 constexpr int kRankKernelMinB = 2048;   // batches from this size rank in a kernel of their own
 hipError_t launch_keys(const DevLib &lib, const double *theta, int P, int B, double *keys, int *ranks,
